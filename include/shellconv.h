@@ -1,0 +1,106 @@
+/* libshellconv: Jacobian-vector product of the implicit-Coriolis IMEX step for Boussinesq
+ * convection in a rotating spherical shell, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (Gonzalez Sembla, Rambert, Feudel, Tuckerman, Mathematics 13, 2113 (2025),
+ * arXiv 2508.16635):
+ *   - unknowns: toroidal and poloidal velocity potentials e, f and temperature T (Sec. 3.1),
+ *     expanded in spherical harmonics Y_l^m (normalization N_l^m of Sec. 3.2) and sampled at
+ *     the N Chebyshev-Gauss-Lobatto nodes in radius;
+ *   - the IMEX Euler step B = (M - dt K)^{-1} (M + dt N) of Sec. 3.3 (eq:discrete) with the
+ *     Coriolis force in K (Sec. 3.2, eq:impcor_e_final / eq:impcor_f_final), the drift term
+ *     C i m M of a rotating wave (Sec. 3.4), boundary rows replaced (Sec. 3.1);
+ *   - the Newton residual R = B_C(X) - X (Sec. 3.3, eq:finalrhs) and its Jacobian action
+ *     (Sec. 3.3, eq:precond and the linearization rules; Sec. 3.4, the phase slot J that
+ *     carries the drift-speed increment c).
+ *
+ * Packed state (real float64, Re/Im interleaved, the caller's layout everywhere):
+ *     for field in (e, f, T); for k in 0..K (m = k*m0, K = min(M,L)/m0); for l in m..L;
+ *     for j in 0..N-1 (x_j = cos(pi j/(N-1)), j = 0 at the outer sphere): (Re, Im)
+ *   n_real = 6 * N * S,  S = sum_k (L - k*m0 + 1).
+ *   The slots e, f at l = 0 and the Im parts at m = 0 carry no physical content: they are
+ *   ignored on input and the step map sets them to 0 (so R = -X and jvp y = -v there).
+ *
+ * Ownership: every state/vector pointer is device memory owned by the caller, contiguous
+ * in the packed layout (leading dimensions in elements).  The plan owns its tables, factors,
+ * base-field caches and workspaces; they are allocated by sc_plan_create, never by sc_jvp.
+ * Every call is asynchronous on the given stream (a hipStream_t; NULL = default stream),
+ * except sc_layout and the host scalar of sc_newton_residual (documented synchronization).
+ * A plan is not re-entrant across concurrent streams.
+ *
+ * Errors: every function returns 0 on success or one of SC_ERR_*; sc_last_error() gives a
+ * thread-local message for the last nonzero return.  No C++ exception crosses the ABI.
+ */
+#ifndef SHELLCONV_H
+#define SHELLCONV_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sc_plan sc_plan;
+
+enum {
+  SC_OK = 0,
+  SC_ERR_ARG = 1,        /* bad size, leading dimension, phase slot or precision        */
+  SC_ERR_STATE = 2,      /* jvp before factor/set_base, or a stale factor              */
+  SC_ERR_NONFINITE = 3,  /* NaN/Inf in a residual norm                                  */
+  SC_ERR_NOMEM = 4,      /* device allocation failed                                    */
+  SC_ERR_HIP = 5,        /* HIP runtime error (message carries hipGetErrorString)       */
+  SC_ERR_INTERNAL = 6
+};
+
+typedef enum { SC_FP64 = 0, SC_MIXED = 1 } sc_precision;
+
+typedef struct {
+  int L, M, m0, N;        /* truncations: l <= L, m in {0, m0, .., K m0}, N radial nodes (N >= 6) */
+  double radius_ratio;    /* r_i / r_o (0.35 in Sec. 2.1); the gap r_o - r_i is 1            */
+  double Ek, Ra, Pr, dt;  /* Ekman, Rayleigh (rotational), Prandtl (Sec. 2.1); step dt (Sec. 3.3) */
+  int nr_phys, ntheta, nphi; /* 0 = dealiasing defaults: ceil(3N/2); smallest even >= (3L+1)/2;
+                                smallest 2^a 3^b 5^c >= 3K+1 (Sec. 3.1)                      */
+  int device;             /* HIP device ordinal                                              */
+  int nvec_max;           /* largest batch passed to sc_jvp (0 = 16); sizes the workspaces   */
+  int refine_fp64;        /* FP64 refinement passes of the implicit solve (< 0: default 1)   */
+  int refine_mixed;       /* refinement passes of the FP32 solve (< 0: default 2)            */
+} sc_params;
+
+typedef struct {
+  long long n_real;       /* length of one packed state                                      */
+  int L, M, m0, N, K, S;  /* truncations, number of m, number of (l, m) pairs                */
+  int Np, ntheta, nphi;   /* physical grid: radial dealiasing nodes, Gauss-Legendre, sector  */
+  int nvec_max;
+} sc_layout_info;
+
+/* Plan: grids, Legendre/radial tables and workspaces on params->device.  Sec. 3.1. */
+int sc_plan_create(sc_plan** out, const sc_params* params);
+int sc_plan_destroy(sc_plan* plan);
+/* Sizes of the packed layout and of the physical grid (host only, no synchronization). */
+int sc_layout(const sc_plan* plan, sc_layout_info* out);
+/* Change Ra, Ek, dt.  A change of Ek or dt invalidates the factorization (SC_ERR_STATE from
+ * step/jvp until sc_factor runs again); Ra enters only the explicit buoyancy (Sec. 3.2). */
+int sc_set_params(sc_plan* plan, double Ra, double Ek, double dt);
+/* Factor the implicit operator M - dt K (Sec. 3.2): per m, two block-tridiagonal chains in l
+ * (odd-l e with even-l f, and the complement) with N x N complex blocks, plus one real block
+ * per l for T.  Ruiz-equilibrated block LU in FP64 on the host, uploaded in FP64 and FP32.
+ * Synchronizes the stream. */
+int sc_factor(sc_plan* plan, void* stream);
+/* One IMEX step x_next = B_C(x) with drift speed C (Sec. 3.3, eq:discrete; Sec. 3.4).
+ * FP64 throughout, FP64 refinement of the implicit solve. */
+int sc_step(sc_plan* plan, const double* x, double C, double* x_next, void* stream);
+/* r = B_C(x) - x (Sec. 3.3, eq:finalrhs).  If rnorm_host is non-NULL the stream is
+ * synchronized and ||r||_2 is stored there; SC_ERR_NONFINITE if it is not finite. */
+int sc_newton_residual(sc_plan* plan, const double* x, double C, double* r, double* rnorm_host, void* stream);
+/* Base state of the Jacobian: caches the physical U, omega, grad T of x (FP64 and FP32) and
+ * M x.  J is the phase slot (index of an Im entry with m > 0) or -1 for no drift unknown. */
+int sc_set_base(sc_plan* plan, const double* x, double C, long long J, void* stream);
+/* Jacobian action y_i = (B_X - I)(u_i, c_i) on nvec vectors (Sec. 3.3 eq:precond, Sec. 3.4):
+ * c_i = v_i[J], u_i = v_i with slot J zeroed; homogeneous boundary rows.
+ * SC_FP64: every stage in FP64.  SC_MIXED: transforms and back-substitution in FP32 with
+ * FP32 accumulation, FP64 radial operators, right-hand side, residual and refinement. */
+int sc_jvp(sc_plan* plan, int nvec, const double* v, long long ldv, double* y, long long ldy,
+           sc_precision prec, void* stream);
+const char* sc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,156 @@
+"""Python binding of libshellconv (argument marshalling only).
+
+Every computation runs in the HIP library; PyTorch only provides device memory and the
+current stream.  The entry points mirror the C-ABI of include/shellconv.h:
+plan create/destroy, layout, set_params, factor, step, newton_residual, set_base, jvp.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libshellconv.so")
+
+SC_FP64 = 0
+SC_MIXED = 1
+_ERRORS = {1: "SC_ERR_ARG", 2: "SC_ERR_STATE", 3: "SC_ERR_NONFINITE", 4: "SC_ERR_NOMEM",
+           5: "SC_ERR_HIP", 6: "SC_ERR_INTERNAL"}
+
+
+class ShellConvError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int), ("M", ctypes.c_int), ("m0", ctypes.c_int), ("N", ctypes.c_int),
+                ("radius_ratio", ctypes.c_double), ("Ek", ctypes.c_double), ("Ra", ctypes.c_double),
+                ("Pr", ctypes.c_double), ("dt", ctypes.c_double),
+                ("nr_phys", ctypes.c_int), ("ntheta", ctypes.c_int), ("nphi", ctypes.c_int),
+                ("device", ctypes.c_int), ("nvec_max", ctypes.c_int),
+                ("refine_fp64", ctypes.c_int), ("refine_mixed", ctypes.c_int)]
+
+
+class _Layout(ctypes.Structure):
+    _fields_ = [("n_real", ctypes.c_longlong), ("L", ctypes.c_int), ("M", ctypes.c_int), ("m0", ctypes.c_int),
+                ("N", ctypes.c_int), ("K", ctypes.c_int), ("S", ctypes.c_int), ("Np", ctypes.c_int),
+                ("ntheta", ctypes.c_int), ("nphi", ctypes.c_int), ("nvec_max", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library; fails loudly if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2508_16635_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i, d, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+    sig = {
+        "sc_plan_create": [ctypes.POINTER(vp), ctypes.POINTER(_Params)],
+        "sc_plan_destroy": [vp],
+        "sc_layout": [vp, ctypes.POINTER(_Layout)],
+        "sc_set_params": [vp, d, d, d],
+        "sc_factor": [vp, vp],
+        "sc_step": [vp, vp, d, vp, vp],
+        "sc_newton_residual": [vp, vp, d, vp, ctypes.POINTER(d), vp],
+        "sc_set_base": [vp, vp, d, ll, vp],
+        "sc_jvp": [vp, i, vp, ll, vp, ll, i, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.sc_last_error.argtypes = []
+    lib.sc_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return ["sc_plan_create", "sc_plan_destroy", "sc_layout", "sc_set_params", "sc_factor", "sc_step",
+            "sc_newton_residual", "sc_set_base", "sc_jvp", "sc_last_error"]
+
+
+def _check(rc):
+    if rc != 0:
+        raise ShellConvError(rc, _lib.sc_last_error().decode(errors="replace"))
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, n_min):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("expected a float64 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if t.numel() < n_min:
+        raise ValueError("tensor too small for the packed layout")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """One shell discretization with its tables, factors and workspaces on one GPU."""
+
+    def __init__(self, L, M, m0, N, Ek, Ra, Pr=1.0, dt=200.0, radius_ratio=0.35, device=0, nvec_max=16,
+                 refine_fp64=-1, refine_mixed=-1, nr_phys=0, ntheta=0, nphi=0):
+        lib = load_library()
+        p = _Params(L, M, m0, N, radius_ratio, Ek, Ra, Pr, dt, nr_phys, ntheta, nphi, device, nvec_max,
+                    refine_fp64, refine_mixed)
+        h = ctypes.c_void_p()
+        _check(lib.sc_plan_create(ctypes.byref(h), ctypes.byref(p)))
+        self._h = h
+        lay = _Layout()
+        _check(lib.sc_layout(h, ctypes.byref(lay)))
+        self.layout = {f: getattr(lay, f) for f, _ in _Layout._fields_}
+        self.n_real = lay.n_real
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.sc_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, Ra, Ek, dt):
+        _check(_lib.sc_set_params(self._h, Ra, Ek, dt))
+
+    def factor(self, stream=None):
+        _check(_lib.sc_factor(self._h, _stream(stream)))
+
+    def step(self, x, C, out, stream=None):
+        _check(_lib.sc_step(self._h, _ptr(x, self.n_real), C, _ptr(out, self.n_real), _stream(stream)))
+        return out
+
+    def newton_residual(self, x, C, out, stream=None, norm=True):
+        rn = ctypes.c_double(0.0)
+        _check(_lib.sc_newton_residual(self._h, _ptr(x, self.n_real), C, _ptr(out, self.n_real),
+                                       ctypes.byref(rn) if norm else None, _stream(stream)))
+        return rn.value if norm else None
+
+    def set_base(self, x, C=0.0, J=-1, stream=None):
+        _check(_lib.sc_set_base(self._h, _ptr(x, self.n_real), C, int(J), _stream(stream)))
+
+    def jvp(self, v, out, prec=SC_MIXED, stream=None):
+        """v, out: [nvec, n_real] (or [n_real]) float64 CUDA tensors."""
+        nvec = 1 if v.dim() == 1 else v.shape[0]
+        ld = self.n_real if v.dim() == 1 else v.stride(0)
+        ldy = self.n_real if out.dim() == 1 else out.stride(0)
+        _check(_lib.sc_jvp(self._h, nvec, _ptr(v, self.n_real * nvec), ld, _ptr(out, self.n_real * nvec), ldy,
+                           int(prec), _stream(stream)))
+        return out

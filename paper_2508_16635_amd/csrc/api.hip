@@ -1,0 +1,667 @@
+// C-ABI of libshellconv: plan creation, factorization, IMEX step, Newton residual and the
+// batched Jacobian action on one GPU.  See include/shellconv.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/shellconv.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Fail {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      throw Fail{_e == hipErrorOutOfMemory ? SC_ERR_NOMEM : SC_ERR_HIP,                   \
+                 std::string(#expr) + ": " + hipGetErrorString(_e)};                      \
+  } while (0)
+
+// Device allocation that frees itself.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  void alloc(size_t n) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = n;
+    if (n) HIPCHK(hipMalloc(&p, n));
+  }
+  template <class T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+template <class T>
+void upload(DevBuf& b, const std::vector<T>& h) {
+  b.alloc(h.size() * sizeof(T));
+  if (!h.empty()) HIPCHK(hipMemcpy(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// Workspace offsets (elements) of one precision.
+struct WsLayout {
+  long long Gs, Gv, Cs, Cv, Fs, Fv, As, Av, total;
+};
+
+struct TabLayout {
+  std::vector<long long> synS, synV, anaS, anaV;
+  long long twc, tws, total;
+};
+
+}  // namespace
+
+struct sc_plan {
+  sc_params prm{};
+  sc::HostGrid hg;
+  int vcap = 16;
+  int refine64 = 1, refine32 = 2;
+  long long n_real = 0;
+  bool factored = false, have_base = false;
+  double baseC = 0.0;
+  long long baseJ = -1;
+  // grid / radial data
+  DevBuf d_lmk, d_lml, d_lmbase, d_r, d_rp, d_E, d_ED, d_ED2, d_P, d_Dp, d_D, d_D2, d_D4;
+  // tables and workspaces per precision
+  TabLayout tl;
+  WsLayout wl;
+  DevBuf tab64, tab32, ws64, ws32;
+  DevBuf probs_syn, probs_ana;
+  int nprob_syn = 0, nprob_ana = 0;
+  std::vector<sc::GemmProb> h_syn, h_ana;
+  // canonical FP64 vectors
+  DevBuf bbuf, xbuf, rbuf, dbuf, norms;
+  // base state
+  DevBuf base64, base32, MX;
+  // factors
+  DevBuf chains, blk_field, blk_lm;
+  int nchains = 0, nblocks = 0;
+  DevBuf Sinv64, Lo64, H64, sr64, sc64, Rg64, Cg64;
+  DevBuf Sinv32, Lo32, H32, sr32, sc32, Rg32, Cg32;
+  DevBuf Tinv64, tr64, tc64, Tinv32, tr32, tc32;
+
+  sc::DevGrid dg() const {
+    sc::DevGrid g;
+    g.L = hg.L;
+    g.m0 = hg.m0;
+    g.N = hg.N;
+    g.Np = hg.Np;
+    g.nth = hg.nth;
+    g.nphi = hg.nphi;
+    g.K = hg.K;
+    g.S = hg.S;
+    g.vcap = vcap;
+    g.lm_k = d_lmk.as<int>();
+    g.lm_l = d_lml.as<int>();
+    g.lmbase = d_lmbase.as<int>();
+    g.r = d_r.as<double>();
+    g.rp = d_rp.as<double>();
+    g.E = d_E.as<double>();
+    g.ED = d_ED.as<double>();
+    g.ED2 = d_ED2.as<double>();
+    g.P = d_P.as<double>();
+    g.Dp = d_Dp.as<double>();
+    g.D = d_D.as<double>();
+    g.D2 = d_D2.as<double>();
+    g.D4 = d_D4.as<double>();
+    return g;
+  }
+  sc::PhysParams pp() const {
+    sc::PhysParams p;
+    p.Ek = prm.Ek;
+    p.Ra = prm.Ra;
+    p.Pr = prm.Pr;
+    p.dt = prm.dt;
+    p.ro = hg.ro;
+    return p;
+  }
+};
+
+namespace {
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    f();
+    return SC_OK;
+  } catch (const Fail& e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(SC_ERR_NOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(SC_ERR_INTERNAL, e.what());
+  }
+}
+
+inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void build_tables(sc_plan* P) {
+  const sc::HostGrid& g = P->hg;
+  TabLayout& t = P->tl;
+  const int K1 = g.K + 1, nth = g.nth;
+  t.synS.resize(K1);
+  t.synV.resize(K1);
+  t.anaS.resize(K1);
+  t.anaV.resize(K1);
+  long long off = 0;
+  for (int k = 0; k < K1; ++k) {
+    long long nl = g.nl[k];
+    t.synS[k] = off; off += nth * nl;
+    t.synV[k] = off; off += 2LL * nth * nl;
+    t.anaS[k] = off; off += nth * nl;
+    t.anaV[k] = off; off += 2LL * nth * nl;
+  }
+  t.twc = off; off += (long long)K1 * g.nphi;
+  t.tws = off; off += (long long)K1 * g.nphi;
+  t.total = off;
+  std::vector<double> h(off, 0.0);
+  for (int k = 0; k < K1; ++k) {
+    int m = g.ms[k], nl = g.nl[k];
+    double dm = (m == 0) ? 1.0 : 2.0;
+    for (int il = 0; il < nl; ++il) {
+      int l = m + il;
+      double lam = (double)l * (l + 1);
+      for (int j = 0; j < nth; ++j) {
+        double Pb = g.Pb[k][(size_t)il * nth + j], dP = g.dPb[k][(size_t)il * nth + j],
+               mP = g.mPs[k][(size_t)il * nth + j];
+        h[t.synS[k] + (long long)j * nl + il] = Pb;
+        h[t.synV[k] + (long long)j * nl + il] = dP;
+        h[t.synV[k] + (long long)(nth + j) * nl + il] = mP;
+        double w = g.wt[j];
+        h[t.anaS[k] + (long long)il * nth + j] = w * Pb / (2.0 * dm);
+        double wv = (l > 0) ? w / (2.0 * dm * lam) : 0.0;
+        h[t.anaV[k] + (long long)il * 2 * nth + j] = wv * dP;
+        h[t.anaV[k] + (long long)il * 2 * nth + nth + j] = wv * mP;
+      }
+    }
+  }
+  const double twopi = 6.283185307179586476925286766559;
+  for (int k = 0; k < K1; ++k)
+    for (int p = 0; p < g.nphi; ++p) {
+      // reduce k p mod nphi exactly before the trigonometric evaluation
+      long long kp = ((long long)k * p) % g.nphi;
+      h[t.twc + (long long)k * g.nphi + p] = std::cos(twopi * (double)kp / g.nphi);
+      h[t.tws + (long long)k * g.nphi + p] = std::sin(twopi * (double)kp / g.nphi);
+    }
+  upload(P->tab64, h);
+  std::vector<float> hf(h.begin(), h.end());
+  upload(P->tab32, hf);
+}
+
+void build_workspaces(sc_plan* P) {
+  const sc::HostGrid& g = P->hg;
+  WsLayout& w = P->wl;
+  const long long V = P->vcap, Np = g.Np, S = g.S, K1 = g.K + 1, nth = g.nth;
+  long long off = 0;
+  w.Gs = off; off += 6 * Np * V * S;
+  w.Gv = off; off += 10 * Np * V * S;
+  w.Cs = off; off += K1 * 6 * Np * V * nth;
+  w.Cv = off; off += K1 * 10 * Np * V * 2 * nth;
+  w.Fs = off; off += K1 * 4 * Np * V * nth;
+  w.Fv = off; off += K1 * 4 * Np * V * 2 * nth;
+  w.As = off; off += 4 * Np * V * S;
+  w.Av = off; off += 4 * Np * V * S;
+  w.total = off;
+  P->ws64.alloc(off * sizeof(double));
+  P->ws32.alloc(off * sizeof(float));
+  // contraction problems (offsets are in elements, so they serve both precisions)
+  P->h_syn.clear();
+  P->h_ana.clear();
+  const TabLayout& t = P->tl;
+  for (int k = 0; k < K1; ++k) {
+    int nl = g.nl[k];
+    long long lb = g.lmbase[k];
+    sc::GemmProb a{w.Gs + 6 * Np * V * lb, t.synS[k], w.Cs + k * 6 * Np * V * nth, (int)(6 * Np), (int)nth, nl, nl, nl, (int)nth};
+    sc::GemmProb b{w.Gv + 10 * Np * V * lb, t.synV[k], w.Cv + k * 10 * Np * V * 2 * nth, (int)(10 * Np), (int)(2 * nth), nl, nl, nl, (int)(2 * nth)};
+    P->h_syn.push_back(a);
+    P->h_syn.push_back(b);
+    sc::GemmProb c{w.Fs + k * 4 * Np * V * nth, t.anaS[k], w.As + 4 * Np * V * lb, (int)(4 * Np), nl, (int)nth, (int)nth, (int)nth, nl};
+    sc::GemmProb d{w.Fv + k * 4 * Np * V * 2 * nth, t.anaV[k], w.Av + 4 * Np * V * lb, (int)(4 * Np), nl, (int)(2 * nth), (int)(2 * nth), (int)(2 * nth), nl};
+    P->h_ana.push_back(c);
+    P->h_ana.push_back(d);
+  }
+  upload(P->probs_syn, P->h_syn);
+  upload(P->probs_ana, P->h_ana);
+  P->nprob_syn = (int)P->h_syn.size();
+  P->nprob_ana = (int)P->h_ana.size();
+  const long long nr = P->n_real;
+  P->bbuf.alloc(V * nr * sizeof(double));
+  P->xbuf.alloc(V * nr * sizeof(double));
+  P->rbuf.alloc(V * nr * sizeof(double));
+  P->dbuf.alloc(V * nr * sizeof(double));
+  P->norms.alloc(V * sizeof(double));
+  long long nbase = 9LL * Np * g.nphi * nth;
+  P->base64.alloc(nbase * sizeof(double));
+  P->base32.alloc(nbase * sizeof(float));
+  P->MX.alloc(nr * sizeof(double));
+}
+
+long long gemm_tiles(const std::vector<sc::GemmProb>& pr, int nvec) {
+  long long t = 0;
+  for (const auto& p : pr) t += (long long)((p.Mper * nvec + 63) / 64) * ((p.N + 63) / 64);
+  return t;
+}
+
+// ---- pipeline stages ---------------------------------------------------------------------
+template <class T>
+T* ws_ptr(sc_plan* P);
+template <>
+double* ws_ptr<double>(sc_plan* P) { return P->ws64.as<double>(); }
+template <>
+float* ws_ptr<float>(sc_plan* P) { return P->ws32.as<float>(); }
+template <class T>
+const T* tab_ptr(sc_plan* P);
+template <>
+const double* tab_ptr<double>(sc_plan* P) { return P->tab64.as<double>(); }
+template <>
+const float* tab_ptr<float>(sc_plan* P) { return P->tab32.as<float>(); }
+
+constexpr int kRT = 16;
+
+template <class T>
+size_t ring_smem(const sc::HostGrid& g) {
+  int K1 = g.K + 1;
+  return sizeof(T) * ((size_t)2 * 9 * K1 * kRT + (size_t)4 * g.nphi * kRT + (size_t)2 * K1 * g.nphi);
+}
+
+// Spectral state -> analysed forces (As, Av) in precision T.  mode: linear/nonlinear/synth.
+template <class T>
+void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, long long J, hipStream_t s) {
+  const sc::HostGrid& g = P->hg;
+  sc::DevGrid dg = P->dg();
+  T* ws = ws_ptr<T>(P);
+  const T* tab = tab_ptr<T>(P);
+  const WsLayout& w = P->wl;
+  long long n1 = (long long)nvec * g.Np * g.S;
+  hipLaunchKernelGGL(sc::k_radial_prep<T>, dim3(nblk(n1, 256)), dim3(256), 0, s, dg, v, ldv, J, nvec, ws + w.Gs, ws + w.Gv);
+  HIPCHK(hipGetLastError());
+  long long nt = gemm_tiles(P->h_syn, nvec);
+  hipLaunchKernelGGL(sc::k_gemm_batched<T>, dim3((unsigned)nt), dim3(256), 0, s, P->probs_syn.as<sc::GemmProb>(),
+                     P->nprob_syn, nvec, (const T*)ws, tab, ws);
+  HIPCHK(hipGetLastError());
+  int ntile = (g.nth + kRT - 1) / kRT;
+  dim3 grid((unsigned)((long long)nvec * g.Np * ntile));
+  size_t smem = ring_smem<T>(g);
+  const T* base = std::is_same<T, double>::value ? (const T*)P->base64.p : (const T*)P->base32.p;
+  T Ek = (T)P->prm.Ek;
+  if (mode == sc::RING_LINEAR) {
+    hipLaunchKernelGGL((sc::k_ring<T, sc::RING_LINEAR, kRT>), grid, dim3(256), smem, s, dg, nvec, ws + w.Cs, ws + w.Cv, base,
+                       tab + P->tl.twc, tab + P->tl.tws, Ek, ws + w.Fs, ws + w.Fv, (double*)nullptr, (float*)nullptr);
+  } else if (mode == sc::RING_NONLINEAR) {
+    hipLaunchKernelGGL((sc::k_ring<T, sc::RING_NONLINEAR, kRT>), grid, dim3(256), smem, s, dg, nvec, ws + w.Cs, ws + w.Cv,
+                       base, tab + P->tl.twc, tab + P->tl.tws, Ek, ws + w.Fs, ws + w.Fv, (double*)nullptr, (float*)nullptr);
+  } else {
+    hipLaunchKernelGGL((sc::k_ring<T, sc::RING_SYNTH, kRT>), grid, dim3(256), smem, s, dg, nvec, ws + w.Cs, ws + w.Cv, base,
+                       tab + P->tl.twc, tab + P->tl.tws, Ek, ws + w.Fs, ws + w.Fv, P->base64.as<double>(),
+                       P->base32.as<float>());
+    HIPCHK(hipGetLastError());
+    return;
+  }
+  HIPCHK(hipGetLastError());
+  nt = gemm_tiles(P->h_ana, nvec);
+  hipLaunchKernelGGL(sc::k_gemm_batched<T>, dim3((unsigned)nt), dim3(256), 0, s, P->probs_ana.as<sc::GemmProb>(),
+                     P->nprob_ana, nvec, (const T*)ws, tab, ws);
+  HIPCHK(hipGetLastError());
+}
+
+// Implicit solve x = A^{-1} b with factors in precision F (all vectors in canonical FP64).
+template <class F>
+void implicit_solve(sc_plan* P, int nvec, const double* b, double* x, hipStream_t s) {
+  sc::DevGrid dg = P->dg();
+  constexpr int VG = 16;
+  dim3 grid(P->nchains, (nvec + VG - 1) / VG);
+  bool d = std::is_same<F, double>::value;
+  const F* Sinv = (const F*)(d ? P->Sinv64.p : P->Sinv32.p);
+  const F* Lo = (const F*)(d ? P->Lo64.p : P->Lo32.p);
+  const F* H = (const F*)(d ? P->H64.p : P->H32.p);
+  const F* sr = (const F*)(d ? P->sr64.p : P->sr32.p);
+  const F* scl = (const F*)(d ? P->sc64.p : P->sc32.p);
+  const F* Rg = (const F*)(d ? P->Rg64.p : P->Rg32.p);
+  const F* Cg = (const F*)(d ? P->Cg64.p : P->Cg32.p);
+  hipLaunchKernelGGL((sc::k_chain_solve<F, VG>), grid, dim3(256), 0, s, dg, nvec, P->chains.as<sc::ChainMeta>(),
+                     P->blk_field.as<int>(), P->blk_lm.as<int>(), Sinv, Lo, H, sr, scl, Rg, Cg, b, x);
+  HIPCHK(hipGetLastError());
+  const F* Ti = (const F*)(d ? P->Tinv64.p : P->Tinv32.p);
+  const F* tr = (const F*)(d ? P->tr64.p : P->tr32.p);
+  const F* tc = (const F*)(d ? P->tc64.p : P->tc32.p);
+  long long nT = (long long)nvec * P->hg.S * P->hg.N;
+  hipLaunchKernelGGL(sc::k_T_solve<F>, dim3(nblk(nT, 256)), dim3(256), 0, s, dg, nvec, Ti, tr, tc, b, x);
+  HIPCHK(hipGetLastError());
+}
+
+// x = A^{-1} b with `passes` FP64 refinement passes; factors in precision F.
+template <class F>
+void refined_solve(sc_plan* P, int nvec, const double* b, double* x, int passes, hipStream_t s) {
+  implicit_solve<F>(P, nvec, b, x, s);
+  sc::DevGrid dg = P->dg();
+  long long n = (long long)nvec * P->n_real;
+  long long nres = (long long)nvec * 3 * P->hg.S * P->hg.N;
+  for (int it = 0; it < passes; ++it) {
+    hipLaunchKernelGGL(sc::k_residual64, dim3(nblk(nres, 256)), dim3(256), 0, s, dg, P->pp(), nvec, b, x,
+                       P->rbuf.as<double>());
+    HIPCHK(hipGetLastError());
+    implicit_solve<F>(P, nvec, P->rbuf.as<double>(), P->dbuf.as<double>(), s);
+    hipLaunchKernelGGL(sc::k_axpy1, dim3(nblk(n, 256)), dim3(256), 0, s, n, P->dbuf.as<const double>(), x);
+    HIPCHK(hipGetLastError());
+  }
+}
+
+// Nonlinear step: P->xbuf <- B_C(x) (uncleaned solve output).
+void step_into_xbuf(sc_plan* P, const double* x, double C, hipStream_t s) {
+  transforms<double>(P, sc::RING_NONLINEAR, 1, x, P->n_real, -1, s);
+  sc::DevGrid dg = P->dg();
+  hipLaunchKernelGGL((sc::k_project_rhs<double, true>), dim3(P->hg.S), dim3(128), 0, s, dg, P->pp(), 1,
+                     (const double*)(P->ws64.as<double>() + P->wl.As), (const double*)(P->ws64.as<double>() + P->wl.Av),
+                     x, P->n_real, (long long)-1, C, (const double*)nullptr, P->bbuf.as<double>());
+  HIPCHK(hipGetLastError());
+  refined_solve<double>(P, 1, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine64, s);
+}
+
+void check_plan(sc_plan* P) {
+  if (!P) throw Fail{SC_ERR_ARG, "null plan"};
+  HIPCHK(hipSetDevice(P->prm.device));
+}
+
+}  // namespace
+
+// ==========================================================================================
+extern "C" {
+
+const char* sc_last_error(void) { return g_last_error.c_str(); }
+
+int sc_plan_create(sc_plan** out, const sc_params* params) {
+  if (!out || !params) return fail(SC_ERR_ARG, "null argument");
+  *out = nullptr;
+  return guarded([&] {
+    std::unique_ptr<sc_plan> P(new sc_plan());
+    P->prm = *params;
+    const sc_params& p = *params;
+    if (p.L < 1 || p.m0 < 1 || p.M < 0 || p.N < 6 || p.N > 64) throw Fail{SC_ERR_ARG, "need L >= 1, m0 >= 1, M >= 0, 6 <= N <= 64"};
+    if (!(p.radius_ratio > 0 && p.radius_ratio < 1)) throw Fail{SC_ERR_ARG, "radius_ratio must lie in (0, 1)"};
+    if (!(p.Ek > 0) || !(p.Pr > 0) || !(p.dt > 0) || !std::isfinite(p.Ra)) throw Fail{SC_ERR_ARG, "need Ek, Pr, dt > 0 and finite Ra"};
+    P->vcap = p.nvec_max > 0 ? p.nvec_max : 16;
+    P->refine64 = p.refine_fp64 >= 0 ? p.refine_fp64 : 1;
+    P->refine32 = p.refine_mixed >= 0 ? p.refine_mixed : 2;
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (p.device < 0 || p.device >= ndev) throw Fail{SC_ERR_ARG, "bad device ordinal"};
+    HIPCHK(hipSetDevice(p.device));
+    try {
+      sc::build_grid(P->hg, p.L, p.M, p.m0, p.N, p.radius_ratio, p.nr_phys, p.ntheta, p.nphi);
+    } catch (const std::runtime_error& e) {
+      throw Fail{SC_ERR_ARG, e.what()};
+    }
+    const sc::HostGrid& g = P->hg;
+    if (g.Np > 128) throw Fail{SC_ERR_ARG, "N_p > 128 unsupported"};
+    P->n_real = 6LL * g.N * g.S;
+    upload(P->d_lmk, g.lm_k);
+    upload(P->d_lml, g.lm_l);
+    upload(P->d_lmbase, g.lmbase);
+    upload(P->d_r, g.r);
+    upload(P->d_rp, g.rp);
+    upload(P->d_E, g.E);
+    upload(P->d_ED, g.ED);
+    upload(P->d_ED2, g.ED2);
+    upload(P->d_P, g.P);
+    upload(P->d_Dp, g.Dp);
+    upload(P->d_D, g.D);
+    upload(P->d_D2, g.D2);
+    upload(P->d_D4, g.D4);
+    build_tables(P.get());
+    build_workspaces(P.get());
+    const size_t smem64 = ring_smem<double>(g), smem32 = ring_smem<float>(g);
+    if (smem64 > 160 * 1024) throw Fail{SC_ERR_ARG, "azimuthal grid too large for the ring kernel"};
+    if (smem64 > 64 * 1024) {
+      HIPCHK(hipFuncSetAttribute((const void*)sc::k_ring<double, sc::RING_LINEAR, kRT>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem64));
+      HIPCHK(hipFuncSetAttribute((const void*)sc::k_ring<double, sc::RING_NONLINEAR, kRT>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem64));
+      HIPCHK(hipFuncSetAttribute((const void*)sc::k_ring<double, sc::RING_SYNTH, kRT>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem64));
+    }
+    if (smem32 > 64 * 1024)
+      HIPCHK(hipFuncSetAttribute((const void*)sc::k_ring<float, sc::RING_LINEAR, kRT>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem32));
+    // deterministic contents for slots the solves never write (e, f at l = 0)
+    HIPCHK(hipMemset(P->xbuf.p, 0, P->xbuf.bytes));
+    HIPCHK(hipMemset(P->dbuf.p, 0, P->dbuf.bytes));
+    HIPCHK(hipMemset(P->rbuf.p, 0, P->rbuf.bytes));
+    HIPCHK(hipDeviceSynchronize());
+    *out = P.release();
+  });
+}
+
+int sc_plan_destroy(sc_plan* plan) {
+  if (!plan) return SC_OK;
+  (void)hipSetDevice(plan->prm.device);
+  (void)hipDeviceSynchronize();
+  delete plan;
+  return SC_OK;
+}
+
+int sc_layout(const sc_plan* P, sc_layout_info* out) {
+  if (!P || !out) return fail(SC_ERR_ARG, "null argument");
+  const sc::HostGrid& g = P->hg;
+  out->n_real = P->n_real;
+  out->L = g.L;
+  out->M = g.M;
+  out->m0 = g.m0;
+  out->N = g.N;
+  out->K = g.K;
+  out->S = g.S;
+  out->Np = g.Np;
+  out->ntheta = g.nth;
+  out->nphi = g.nphi;
+  out->nvec_max = P->vcap;
+  return SC_OK;
+}
+
+int sc_set_params(sc_plan* P, double Ra, double Ek, double dt) {
+  if (!P) return fail(SC_ERR_ARG, "null plan");
+  if (!(Ek > 0) || !(dt > 0) || !std::isfinite(Ra)) return fail(SC_ERR_ARG, "need Ek, dt > 0 and finite Ra");
+  if (Ek != P->prm.Ek || dt != P->prm.dt) P->factored = false;
+  P->prm.Ra = Ra;
+  P->prm.Ek = Ek;
+  P->prm.dt = dt;
+  return SC_OK;
+}
+
+int sc_factor(sc_plan* P, void* stream) {
+  return guarded([&] {
+    check_plan(P);
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipStreamSynchronize(s));
+    const sc::HostGrid& g = P->hg;
+    std::vector<sc::ChainFactor> ch;
+    std::vector<sc::TFactor> tf;
+    sc::OpParams op{P->prm.Ek, P->prm.Pr, P->prm.dt};
+    int nth = (int)std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    sc::factor_all(g, op, ch, tf, nth);
+    const int N = g.N;
+    std::vector<sc::ChainMeta> meta;
+    std::vector<int> bf, blm;
+    long long nb = 0;
+    for (auto& c : ch) nb += c.n;
+    std::vector<double> Sinv(2 * nb * N * N), Lo(2 * nb * N * N), H(2 * nb * N * N);
+    std::vector<double> sr(nb * N), scv(nb * N), Rg(nb * N), Cg(nb * N);
+    long long b = 0;
+    for (auto& c : ch) {
+      meta.push_back(sc::ChainMeta{(int)b, c.n, c.k, 0});
+      for (int i = 0; i < c.n; ++i, ++b) {
+        bf.push_back(c.field[i]);
+        blm.push_back(g.lmbase[c.k] + (c.l[i] - c.m));
+        for (long long q = 0; q < (long long)N * N; ++q) {
+          Sinv[2 * (b * N * N + q)] = c.Sinv[(size_t)i * N * N + q].real();
+          Sinv[2 * (b * N * N + q) + 1] = c.Sinv[(size_t)i * N * N + q].imag();
+          Lo[2 * (b * N * N + q)] = c.Lo[(size_t)i * N * N + q].real();
+          Lo[2 * (b * N * N + q) + 1] = c.Lo[(size_t)i * N * N + q].imag();
+          H[2 * (b * N * N + q)] = c.H[(size_t)i * N * N + q].real();
+          H[2 * (b * N * N + q) + 1] = c.H[(size_t)i * N * N + q].imag();
+        }
+        for (int j = 0; j < N; ++j) {
+          sr[b * N + j] = c.sr[(size_t)i * N + j];
+          scv[b * N + j] = c.sc[(size_t)i * N + j];
+          Rg[b * N + j] = c.Rg[(size_t)i * N + j];
+          Cg[b * N + j] = c.Cg[(size_t)i * N + j];
+        }
+      }
+    }
+    std::vector<double> Tinv((size_t)(g.L + 1) * N * N), tr((size_t)(g.L + 1) * N), tc((size_t)(g.L + 1) * N);
+    for (int l = 0; l <= g.L; ++l) {
+      std::copy(tf[l].Tinv.begin(), tf[l].Tinv.end(), Tinv.begin() + (size_t)l * N * N);
+      std::copy(tf[l].tr.begin(), tf[l].tr.end(), tr.begin() + (size_t)l * N);
+      std::copy(tf[l].tc.begin(), tf[l].tc.end(), tc.begin() + (size_t)l * N);
+    }
+    auto up2 = [](DevBuf& d64, DevBuf& d32, const std::vector<double>& h) {
+      upload(d64, h);
+      std::vector<float> f(h.begin(), h.end());
+      upload(d32, f);
+    };
+    upload(P->chains, meta);
+    upload(P->blk_field, bf);
+    upload(P->blk_lm, blm);
+    up2(P->Sinv64, P->Sinv32, Sinv);
+    up2(P->Lo64, P->Lo32, Lo);
+    up2(P->H64, P->H32, H);
+    up2(P->sr64, P->sr32, sr);
+    up2(P->sc64, P->sc32, scv);
+    up2(P->Rg64, P->Rg32, Rg);
+    up2(P->Cg64, P->Cg32, Cg);
+    up2(P->Tinv64, P->Tinv32, Tinv);
+    up2(P->tr64, P->tr32, tr);
+    up2(P->tc64, P->tc32, tc);
+    P->nchains = (int)meta.size();
+    P->nblocks = (int)nb;
+    P->factored = true;
+    P->have_base = false;  // the cached M X depends on Ek
+  });
+}
+
+int sc_step(sc_plan* P, const double* x, double C, double* x_next, void* stream) {
+  return guarded([&] {
+    check_plan(P);
+    if (!x || !x_next) throw Fail{SC_ERR_ARG, "null vector"};
+    if (!P->factored) throw Fail{SC_ERR_STATE, "sc_factor has not run for the current (Ek, dt)"};
+    hipStream_t s = (hipStream_t)stream;
+    step_into_xbuf(P, x, C, s);
+    long long n = P->n_real;
+    hipLaunchKernelGGL(sc::k_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, P->dg(), 1, P->xbuf.as<const double>(), x, n,
+                       (long long)-1, x_next, n, 0);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int sc_newton_residual(sc_plan* P, const double* x, double C, double* r, double* rnorm_host, void* stream) {
+  return guarded([&] {
+    check_plan(P);
+    if (!x || !r) throw Fail{SC_ERR_ARG, "null vector"};
+    if (!P->factored) throw Fail{SC_ERR_STATE, "sc_factor has not run for the current (Ek, dt)"};
+    hipStream_t s = (hipStream_t)stream;
+    step_into_xbuf(P, x, C, s);
+    long long n = P->n_real;
+    hipLaunchKernelGGL(sc::k_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, P->dg(), 1, P->xbuf.as<const double>(), x, n,
+                       (long long)-1, r, n, 1);
+    HIPCHK(hipGetLastError());
+    if (rnorm_host) {
+      hipLaunchKernelGGL(sc::k_sumsq, dim3(1), dim3(256), 0, s, n, (const double*)r, n, P->norms.as<double>());
+      HIPCHK(hipGetLastError());
+      double ss = 0.0;
+      HIPCHK(hipMemcpyAsync(&ss, P->norms.p, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      *rnorm_host = std::sqrt(ss);
+      if (!std::isfinite(*rnorm_host)) throw Fail{SC_ERR_NONFINITE, "residual norm is not finite"};
+    }
+  });
+}
+
+int sc_set_base(sc_plan* P, const double* x, double C, long long J, void* stream) {
+  return guarded([&] {
+    check_plan(P);
+    if (!x) throw Fail{SC_ERR_ARG, "null vector"};
+    if (!P->factored) throw Fail{SC_ERR_STATE, "sc_factor has not run for the current (Ek, dt)"};
+    const sc::HostGrid& g = P->hg;
+    if (J >= 0) {
+      // must be an Im slot with m > 0
+      if (J >= P->n_real || (J % 2) == 0) throw Fail{SC_ERR_ARG, "phase slot must be an Im entry"};
+      long long node = J / 2;
+      int lm = (int)((node / g.N) % g.S);
+      if (g.lm_k[lm] == 0) throw Fail{SC_ERR_ARG, "phase slot must have m > 0"};
+    } else {
+      J = -1;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    transforms<double>(P, sc::RING_SYNTH, 1, x, P->n_real, -1, s);
+    long long n3 = 3LL * g.S * g.N;
+    hipLaunchKernelGGL(sc::k_apply_M, dim3(nblk(n3, 256)), dim3(256), 0, s, P->dg(), P->pp(), x, P->MX.as<double>());
+    HIPCHK(hipGetLastError());
+    P->baseC = C;
+    P->baseJ = J;
+    P->have_base = true;
+  });
+}
+
+int sc_jvp(sc_plan* P, int nvec, const double* v, long long ldv, double* y, long long ldy, sc_precision prec,
+           void* stream) {
+  return guarded([&] {
+    check_plan(P);
+    if (nvec < 0 || nvec > P->vcap) throw Fail{SC_ERR_ARG, "nvec exceeds nvec_max of the plan"};
+    if (nvec == 0) return;
+    if (!v || !y) throw Fail{SC_ERR_ARG, "null vector"};
+    if (ldv < P->n_real || ldy < P->n_real) throw Fail{SC_ERR_ARG, "leading dimension smaller than n_real"};
+    if (prec != SC_FP64 && prec != SC_MIXED) throw Fail{SC_ERR_ARG, "unknown precision"};
+    if (!P->factored || !P->have_base) throw Fail{SC_ERR_STATE, "call sc_factor and sc_set_base before sc_jvp"};
+    hipStream_t s = (hipStream_t)stream;
+    const long long J = P->baseJ;
+    sc::DevGrid dg = P->dg();
+    if (prec == SC_FP64) {
+      transforms<double>(P, sc::RING_LINEAR, nvec, v, ldv, J, s);
+      hipLaunchKernelGGL((sc::k_project_rhs<double, false>), dim3((unsigned)((long long)nvec * P->hg.S)), dim3(128), 0, s,
+                         dg, P->pp(), nvec, (const double*)(P->ws64.as<double>() + P->wl.As),
+                         (const double*)(P->ws64.as<double>() + P->wl.Av), v, ldv, J, P->baseC,
+                         P->MX.as<const double>(), P->bbuf.as<double>());
+      HIPCHK(hipGetLastError());
+      refined_solve<double>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine64, s);
+    } else {
+      transforms<float>(P, sc::RING_LINEAR, nvec, v, ldv, J, s);
+      hipLaunchKernelGGL((sc::k_project_rhs<float, false>), dim3((unsigned)((long long)nvec * P->hg.S)), dim3(128), 0, s,
+                         dg, P->pp(), nvec, (const float*)(P->ws32.as<float>() + P->wl.As),
+                         (const float*)(P->ws32.as<float>() + P->wl.Av), v, ldv, J, P->baseC,
+                         P->MX.as<const double>(), P->bbuf.as<double>());
+      HIPCHK(hipGetLastError());
+      refined_solve<float>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine32, s);
+    }
+    long long n = (long long)nvec * P->n_real;
+    hipLaunchKernelGGL(sc::k_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, dg, nvec, P->xbuf.as<const double>(), v, ldv,
+                       J, y, ldy, 1);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+}  // extern "C"

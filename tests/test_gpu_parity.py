@@ -1,0 +1,102 @@
+"""GPU parity of libshellconv against the FP64 oracle (run on an MI355X)."""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle.solver import Problem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SMALL = [  # (L, M, m0, N, Ek, Ra, dt)
+    (16, 16, 1, 16, 1e-3, 78.0, 200.0),
+    (12, 12, 4, 14, 1e-3, 78.0, 200.0),
+]
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2508_16635_amd as sc
+    sc.load_library()
+    return sc
+
+
+def _setup(sc, cfg, nvec=4):
+    L, M, m0, N, Ek, Ra, dt = cfg
+    plan = sc.Plan(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=dt, nvec_max=nvec)
+    plan.factor()
+    ora = Problem(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=dt)
+    lay = si.Layout(L, M, m0, N)
+    assert plan.n_real == lay.n_real == ora.n_real
+    return plan, ora, lay
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("cfg", SMALL)
+def test_step_and_residual_fp64(lib, cfg):
+    plan, ora, lay = _setup(lib, cfg)
+    X = si.random_state(lay, 101, amp=(1e-2, 1e-2, 1e-2), p=2) + ora.conductive_state()
+    C = 0.3
+    xd = _dev(X)
+    out = torch.empty_like(xd)
+    plan.step(xd, C, out)
+    ref = ora.step(X, C)
+    e1 = _rel(_host(out), ref)
+    rn = plan.newton_residual(xd, C, out)
+    R = ora.residual(X, C)
+    e2 = _rel(_host(out), R)
+    print(f"cfg={cfg} step rel err {e1:.2e} residual rel err {e2:.2e} |R| {rn:.6e} vs {np.linalg.norm(R):.6e}", flush=True)
+    assert e1 < 1e-12
+    assert e2 < 1e-10
+    assert abs(rn - np.linalg.norm(R)) <= 1e-10 * np.linalg.norm(R)
+
+
+def test_conductive_fixed_point(lib):
+    plan, ora, lay = _setup(lib, SMALL[0])
+    Xc = ora.conductive_state()
+    r = torch.empty(plan.n_real, dtype=torch.float64, device="cuda")
+    rn = plan.newton_residual(_dev(Xc), 0.0, r)
+    print("conductive |R|", rn, flush=True)
+    assert rn <= 1e-12 * np.linalg.norm(Xc)
+
+
+@pytest.mark.parametrize("cfg", SMALL)
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 1e-6)])
+def test_jvp(lib, cfg, prec, tol):
+    plan, ora, lay = _setup(lib, cfg)
+    X = si.random_state(lay, 101, amp=(1e-2, 1e-2, 1e-2), p=2) + ora.conductive_state()
+    J = si.default_phase_slot(lay, X)
+    C = 0.3
+    plan.set_base(_dev(X), C, J)
+    ora.set_base(X, C, J)
+    V = si.random_vectors(lay, [1001, 1002, 1003, 1004])
+    vd = _dev(V)
+    yd = torch.empty_like(vd)
+    plan.jvp(vd, yd, prec)
+    Y = _host(yd)
+    errs = [_rel(Y[i], ora.jvp(V[i])) for i in range(len(V))]
+    print(f"cfg={cfg} prec={prec} jvp rel errs", ["%.2e" % e for e in errs], flush=True)
+    assert max(errs) < tol
+
+
+def test_state_errors(lib):
+    plan, ora, lay = _setup(lib, SMALL[1])
+    v = torch.zeros((1, plan.n_real), dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.ShellConvError) as ei:
+        plan.jvp(v, v.clone(), 0)
+    assert ei.value.code == 2
+    with pytest.raises(lib.ShellConvError) as ei:
+        plan.set_base(v[0], 0.0, 2)   # an Re slot
+    assert ei.value.code == 1
