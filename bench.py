@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark: batched Jacobian-vector products of the implicit-Coriolis IMEX step on one MI355X.
+
+Workload (the metric's shell): L = M = 128, m0 = 10, N = 48, Ek = 1e-5, Pr = 1,
+Ra = 1.2 * 6.5 Ek^(-1/3) = 362.0, dt = 200; a seeded synthetic base state (kinetic-energy
+density ~25, coefficients decaying as l^-3, conductive temperature profile added) and 200
+seeded unit Krylov-like vectors (decay l^-1).  One step = one sc_jvp call on a batch of
+nvec vectors (the whole hot path: transforms, products, projections, implicit solve and
+refinement).  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  `value` is mixed-precision jvp/s; the FP64 path is timed the same
+way and reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+WORKLOAD = dict(L=128, M=128, m0=10, N=48, Ek=1e-5, Pr=1.0, Ra=362.0, dt=200.0)
+BASE_AMP = (8.0, 8.0, 0.1)   # e, f amplitudes give kinetic-energy density ~25 at this shell
+PEAK = {"hbm": 8000.0, "fp32": 157.3, "fp64": 78.6}   # GB/s, TFLOP/s (MI355X published)
+
+
+def stage_work(lay, nvec, prec_bytes, factor_bytes, nblocks, refine):
+    """Algorithmic flops and bytes per launch of each stage (measurement)."""
+    L, N, Np, nth, nphi, K1, S = (lay["L"], lay["N"], lay["Np"], lay["ntheta"], lay["nphi"],
+                                  lay["K"] + 1, lay["S"])
+    m0 = lay["m0"]
+    nl = [L - k * m0 + 1 for k in range(K1)]
+    w = {}
+    # Legendre synthesis: per m, (6 Np nvec x nl) . (nl x nth) and (10 Np nvec x nl) . (nl x 2 nth)
+    fl = sum(2.0 * Np * nvec * n * (6 * nth + 10 * 2 * nth) for n in nl)
+    by = prec_bytes * (Np * nvec * 16 * S + (K1 * Np * nvec * (6 * nth + 20 * nth)) + 3 * nth * S)
+    w["legendre_synth"] = (fl, by)
+    fl = sum(2.0 * Np * nvec * n * (4 * nth + 4 * 2 * nth) for n in nl)
+    by = prec_bytes * (K1 * Np * nvec * (4 * nth + 8 * nth) + Np * nvec * 8 * S + 3 * nth * S)
+    w["legendre_anal"] = (fl, by)
+    rings = Np * nth * nvec
+    w["ring"] = (rings * (2.0 * 13 * K1 * nphi * 2 + 60 * nphi),
+                 prec_bytes * (rings * (26 + 12) * K1 + Np * nth * 9 * nphi))
+    nreal = 6 * N * S
+    w["radial_prep"] = (nvec * Np * S * 7 * N * 4.0, 8.0 * nvec * nreal + prec_bytes * nvec * Np * 16 * S)
+    w["project_rhs"] = (nvec * S * 2 * (Np * Np + 3 * N * Np + N * N) * 2.0,
+                        prec_bytes * nvec * Np * 8 * S + 8.0 * nvec * nreal * 3)
+    solves = 1 + refine
+    nvg = (nvec + 15) // 16
+    w["chain_solve"] = (solves * nvec * nblocks * 3 * N * N * 8.0,
+                        solves * (nvg * factor_bytes + 8.0 * nvec * nreal * 4 / 3 * 2))
+    w["T_solve"] = (solves * nvec * S * N * N * 4.0, solves * 8.0 * nvec * nreal / 3 * 2)
+    w["residual64"] = (refine * nvec * 3 * S * N * N * 2 * 10.0, refine * 8.0 * nvec * nreal * 3)
+    return w
+
+
+def run(args):
+    import torch
+    import paper_2508_16635_amd as sc
+    import seeded_inputs as si
+
+    dev = torch.device("cuda:0")
+    W = WORKLOAD
+    nvec = args.nvec
+    plan = sc.Plan(W["L"], W["M"], W["m0"], W["N"], Ek=W["Ek"], Ra=W["Ra"], Pr=W["Pr"], dt=W["dt"],
+                   nvec_max=nvec)
+    lay_d = plan.layout
+    lay = si.Layout(W["L"], W["M"], W["m0"], W["N"])
+    assert lay.n_real == plan.n_real
+    t0 = time.time()
+    plan.factor()
+    t_factor = time.time() - t0
+
+    ri, ro = 0.35 / 0.65, 1.0 / 0.65
+    X = si.random_state(lay, 301, amp=BASE_AMP, p=3.0, t_offset=lambda x: ro * ri / ((x + ri + ro) / 2) - ri)
+    J = si.default_phase_slot(lay, X)
+    C = 0.5
+    Xd = torch.from_numpy(X).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    plan.set_base(Xd, C, J)
+    torch.cuda.synchronize()
+    t_base = time.time() - t0
+    nv_total = max(args.nvectors, nvec)
+    V = torch.from_numpy(si.random_vectors(lay, range(3001, 3001 + nv_total))).to(dev)
+    Y = torch.empty((nvec, plan.n_real), dtype=torch.float64, device=dev)
+    nb = nv_total // nvec
+
+    def batch(i):
+        b = i % nb
+        return V[b * nvec:(b + 1) * nvec]
+
+    results = {}
+    for name, prec in (("mixed", sc.SC_MIXED), ("fp64", sc.SC_FP64)):
+        for i in range(args.warmup):
+            plan.jvp(batch(i), Y, prec)
+        torch.cuda.synchronize()
+        plan.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            plan.jvp(batch(i), Y, prec)
+        torch.cuda.synchronize()
+        dt_ = time.perf_counter() - t0
+        prof = plan.profile_read()
+        plan.profile(False)
+        results[name] = dict(seconds=dt_, jvps=args.steps * nvec, prof=prof)
+
+    # mixed vs FP64 on the same batch (GPU vs GPU, a consistency figure)
+    Y64 = torch.empty_like(Y)
+    plan.jvp(batch(0), Y, sc.SC_MIXED)
+    plan.jvp(batch(0), Y64, sc.SC_FP64)
+    torch.cuda.synchronize()
+    mixed_vs_fp64 = float(((Y - Y64).norm(dim=1) / Y64.norm(dim=1)).max())
+
+    mixed = results["mixed"]
+    fp64 = results["fp64"]
+    value = mixed["jvps"] / mixed["seconds"]
+    # roofline of the dominant stage of the mixed path
+    N = W["N"]
+    nblocks = sum(W["L"] - max(k * W["m0"], 1) + 1 for k in range(lay_d["K"] + 1)) * 2
+    fbytes32 = 3 * nblocks * N * N * 8
+    work = stage_work(lay_d, nvec, 4, fbytes32, nblocks, refine=2)
+    prof = mixed["prof"]
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms, cnt = prof[dom]
+    avg_s = ms / 1e3 / max(cnt, 1)
+    # launches per jvp call differ per stage; the work table is per call
+    per_call = cnt / max(args.steps, 1)
+    fl, by = work.get(dom, (0.0, 0.0))
+    fl /= max(per_call, 1)
+    by /= max(per_call, 1)
+    if dom in ("legendre_synth", "legendre_anal"):
+        roof = {"bound": "alu", "achieved": fl / avg_s / 1e12, "peak": PEAK["fp32"], "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": by / avg_s / 1e9, "peak": PEAK["hbm"], "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_launch_us"] = avg_s * 1e6
+    stages = {k: {"ms_per_step": v[0] / max(args.steps, 1), "launches_per_step": v[1] / max(args.steps, 1)}
+              for k, v in prof.items() if v[1]}
+    out = {
+        "metric": "Jacobian-vector products/s at L=128,N=48; mixed vs FP64 at 1e-10 residual",
+        "value": value,
+        "unit": "jvp/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["seconds"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "rotating-shell jvp L=M=128 m0=10 N=48 Ek=1e-5 Ra=362 dt=200",
+                   "nvec": nvec, "N_p": lay_d["Np"], "N_theta": lay_d["ntheta"], "N_phi": lay_d["nphi"],
+                   "n_real": plan.n_real},
+        "fp64_jvp_per_s": fp64["jvps"] / fp64["seconds"],
+        "mixed_vs_fp64_max_rel": mixed_vs_fp64,
+        "factor_s": t_factor,
+        "set_base_s": t_base,
+        "roofline": roof,
+        "stages_mixed": stages,
+        "stages_fp64": {k: {"ms_per_step": v[0] / max(args.steps, 1)} for k, v in fp64["prof"].items() if v[1]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, X, C, J, lay)
+    return out
+
+
+def cpu_baseline(args, X, C, J, lay):
+    """The FP64 oracle timed on the host cores on a bounded sample of the same workload."""
+    import seeded_inputs as si
+    from oracle.solver import Problem
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    W = WORKLOAD
+    p = Problem(W["L"], W["M"], W["m0"], W["N"], Ek=W["Ek"], Ra=W["Ra"], Pr=W["Pr"], dt=W["dt"])
+    p.factor()
+    p.set_base(X, C, J)
+    V = si.random_vectors(lay, range(3001, 3001 + args.cpu_sample))
+    p.jvp(V[0])   # warm-up
+    t0 = time.perf_counter()
+    for i in range(args.cpu_sample):
+        p.jvp(V[i])
+    dt_ = time.perf_counter() - t0
+    return {"value": args.cpu_sample / dt_, "unit": "jvp/s", "cores": cores, "kind": "oracle",
+            "sample": f"{args.cpu_sample} single-vector jvps of the same shell and base state "
+                      f"(oracle factor and base setup excluded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--nvec", type=int, default=16)
+    ap.add_argument("--nvectors", type=int, default=200)
+    ap.add_argument("--cpu-sample", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    out = run(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    main()

@@ -98,6 +98,25 @@ int sc_set_base(sc_plan* plan, const double* x, double C, long long J, void* str
  * FP32 accumulation, FP64 radial operators, right-hand side, residual and refinement. */
 int sc_jvp(sc_plan* plan, int nvec, const double* v, long long ldv, double* y, long long ldy,
            sc_precision prec, void* stream);
+/* Stage profiler (tracing).  While enabled, every launch of the plan is bracketed by HIP
+ * events on its stream; sc_profile_read synchronizes, returns per-stage total milliseconds
+ * and launch counts (arrays of nstages entries indexed by SC_STAGE_*) and clears the record.
+ * Events are created by the first enabling call, never inside step/jvp. */
+enum {
+  SC_STAGE_RADIAL_PREP = 0,     /* spectral profiles at the dealiasing nodes               */
+  SC_STAGE_LEGENDRE_SYNTH = 1,  /* Legendre synthesis contractions                          */
+  SC_STAGE_RING = 2,            /* azimuthal transforms and pointwise products             */
+  SC_STAGE_LEGENDRE_ANAL = 3,   /* Legendre analysis contractions                          */
+  SC_STAGE_PROJECT_RHS = 4,     /* curl projections and right-hand side                    */
+  SC_STAGE_CHAIN_SOLVE = 5,     /* block-tridiagonal e/f solves                            */
+  SC_STAGE_T_SOLVE = 6,         /* temperature solves                                      */
+  SC_STAGE_RESIDUAL = 7,        /* FP64 residual of the implicit operator                  */
+  SC_STAGE_AXPY = 8,            /* refinement update                                       */
+  SC_STAGE_FINALIZE = 9,        /* output assembly                                         */
+  SC_NSTAGES = 10
+};
+int sc_profile(sc_plan* plan, int enable);
+int sc_profile_read(sc_plan* plan, double* ms_total, long long* count, int nstages);
 const char* sc_last_error(void);
 
 #ifdef __cplusplus

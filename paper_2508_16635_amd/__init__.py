@@ -61,6 +61,8 @@ def load_library(path: str = LIB_PATH):
         "sc_newton_residual": [vp, vp, d, vp, ctypes.POINTER(d), vp],
         "sc_set_base": [vp, vp, d, ll, vp],
         "sc_jvp": [vp, i, vp, ll, vp, ll, i, vp],
+        "sc_profile": [vp, i],
+        "sc_profile_read": [vp, ctypes.POINTER(d), ctypes.POINTER(ll), i],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -72,9 +74,13 @@ def load_library(path: str = LIB_PATH):
     return lib
 
 
+STAGES = ["radial_prep", "legendre_synth", "ring", "legendre_anal", "project_rhs", "chain_solve",
+          "T_solve", "residual64", "axpy", "finalize"]
+
+
 def exported_symbols():
     return ["sc_plan_create", "sc_plan_destroy", "sc_layout", "sc_set_params", "sc_factor", "sc_step",
-            "sc_newton_residual", "sc_set_base", "sc_jvp", "sc_last_error"]
+            "sc_newton_residual", "sc_set_base", "sc_jvp", "sc_profile", "sc_profile_read", "sc_last_error"]
 
 
 def _check(rc):
@@ -154,3 +160,14 @@ class Plan:
         _check(_lib.sc_jvp(self._h, nvec, _ptr(v, self.n_real * nvec), ld, _ptr(out, self.n_real * nvec), ldy,
                            int(prec), _stream(stream)))
         return out
+
+    def profile(self, enable=True):
+        _check(_lib.sc_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{stage: (total ms, launches)} recorded since the last read; synchronizes."""
+        n = len(STAGES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_longlong * n)()
+        _check(_lib.sc_profile_read(self._h, ms, cnt, n))
+        return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}

@@ -96,11 +96,21 @@ struct sc_plan {
   // base state
   DevBuf base64, base32, MX;
   // factors
-  DevBuf chains, blk_field, blk_lm;
-  int nchains = 0, nblocks = 0;
-  DevBuf Sinv64, Lo64, H64, sr64, sc64, Rg64, Cg64;
-  DevBuf Sinv32, Lo32, H32, sr32, sc32, Rg32, Cg32;
+  DevBuf chains, segs, blk_field, blk_lm, blk_next;
+  int nchains = 0, nblocks = 0, nsegs = 0;
+  DevBuf Sinv64, Lo64, H64, Phi64, Psi64, sr64, sc64, Rg64, Cg64;
+  DevBuf Sinv32, Lo32, H32, Phi32, Psi32, sr32, sc32, Rg32, Cg32;
+  DevBuf wscan;  // scan work vectors, capacity vcap x nblocks x N complex doubles
   DevBuf Tinv64, tr64, tc64, Tinv32, tr32, tc32;
+  // stage profiler: pairs of events recorded around launches while enabled
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev;           // 2 * capacity
+  std::vector<int> ev_stage;            // stage of each recorded pair
+  int ev_used = 0;
+
+  ~sc_plan() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
 
   sc::DevGrid dg() const {
     sc::DevGrid g;
@@ -161,6 +171,22 @@ int guarded(F&& f) {
 }
 
 inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Stage profiler: brackets one launch with events on its stream (no effect when disabled).
+struct Prof {
+  sc_plan* P;
+  int pair = -1;
+  hipStream_t s;
+  Prof(sc_plan* p, int stage, hipStream_t st) : P(p), s(st) {
+    if (!P->prof_on || P->ev_used * 2 >= (int)P->ev.size()) return;
+    pair = P->ev_used++;
+    P->ev_stage[pair] = stage;
+    HIPCHK(hipEventRecord(P->ev[2 * pair], s));
+  }
+  ~Prof() noexcept(false) {
+    if (pair >= 0) HIPCHK(hipEventRecord(P->ev[2 * pair + 1], s));
+  }
+};
 
 void build_tables(sc_plan* P) {
   const sc::HostGrid& g = P->hg;
@@ -300,11 +326,17 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
   const T* tab = tab_ptr<T>(P);
   const WsLayout& w = P->wl;
   long long n1 = (long long)nvec * g.Np * g.S;
-  hipLaunchKernelGGL(sc::k_radial_prep<T>, dim3(nblk(n1, 256)), dim3(256), 0, s, dg, v, ldv, J, nvec, ws + w.Gs, ws + w.Gv);
+  {
+    Prof _p(P, SC_STAGE_RADIAL_PREP, s);
+    hipLaunchKernelGGL(sc::k_radial_prep<T>, dim3(nblk(n1, 256)), dim3(256), 0, s, dg, v, ldv, J, nvec, ws + w.Gs, ws + w.Gv);
+  }
   HIPCHK(hipGetLastError());
   long long nt = gemm_tiles(P->h_syn, nvec);
-  hipLaunchKernelGGL(sc::k_gemm_batched<T>, dim3((unsigned)nt), dim3(256), 0, s, P->probs_syn.as<sc::GemmProb>(),
-                     P->nprob_syn, nvec, (const T*)ws, tab, ws);
+  {
+    Prof _p(P, SC_STAGE_LEGENDRE_SYNTH, s);
+    hipLaunchKernelGGL(sc::k_gemm_batched<T>, dim3((unsigned)nt), dim3(256), 0, s, P->probs_syn.as<sc::GemmProb>(),
+                       P->nprob_syn, nvec, (const T*)ws, tab, ws);
+  }
   HIPCHK(hipGetLastError());
   int ntile = (g.nth + kRT - 1) / kRT;
   dim3 grid((unsigned)((long long)nvec * g.Np * ntile));
@@ -312,48 +344,89 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
   const T* base = std::is_same<T, double>::value ? (const T*)P->base64.p : (const T*)P->base32.p;
   T Ek = (T)P->prm.Ek;
   if (mode == sc::RING_LINEAR) {
-    hipLaunchKernelGGL((sc::k_ring<T, sc::RING_LINEAR, kRT>), grid, dim3(256), smem, s, dg, nvec, ws + w.Cs, ws + w.Cv, base,
-                       tab + P->tl.twc, tab + P->tl.tws, Ek, ws + w.Fs, ws + w.Fv, (double*)nullptr, (float*)nullptr);
+    {
+      Prof _p(P, SC_STAGE_RING, s);
+      hipLaunchKernelGGL((sc::k_ring<T, sc::RING_LINEAR, kRT>), grid, dim3(256), smem, s, dg, nvec, ws + w.Cs, ws + w.Cv, base,
+                         tab + P->tl.twc, tab + P->tl.tws, Ek, ws + w.Fs, ws + w.Fv, (double*)nullptr, (float*)nullptr);
+    }
   } else if (mode == sc::RING_NONLINEAR) {
-    hipLaunchKernelGGL((sc::k_ring<T, sc::RING_NONLINEAR, kRT>), grid, dim3(256), smem, s, dg, nvec, ws + w.Cs, ws + w.Cv,
-                       base, tab + P->tl.twc, tab + P->tl.tws, Ek, ws + w.Fs, ws + w.Fv, (double*)nullptr, (float*)nullptr);
+    {
+      Prof _p(P, SC_STAGE_RING, s);
+      hipLaunchKernelGGL((sc::k_ring<T, sc::RING_NONLINEAR, kRT>), grid, dim3(256), smem, s, dg, nvec, ws + w.Cs, ws + w.Cv,
+                         base, tab + P->tl.twc, tab + P->tl.tws, Ek, ws + w.Fs, ws + w.Fv, (double*)nullptr, (float*)nullptr);
+    }
   } else {
-    hipLaunchKernelGGL((sc::k_ring<T, sc::RING_SYNTH, kRT>), grid, dim3(256), smem, s, dg, nvec, ws + w.Cs, ws + w.Cv, base,
-                       tab + P->tl.twc, tab + P->tl.tws, Ek, ws + w.Fs, ws + w.Fv, P->base64.as<double>(),
-                       P->base32.as<float>());
+    {
+      Prof _p(P, SC_STAGE_RING, s);
+      hipLaunchKernelGGL((sc::k_ring<T, sc::RING_SYNTH, kRT>), grid, dim3(256), smem, s, dg, nvec, ws + w.Cs, ws + w.Cv, base,
+                         tab + P->tl.twc, tab + P->tl.tws, Ek, ws + w.Fs, ws + w.Fv, P->base64.as<double>(),
+                         P->base32.as<float>());
+    }
     HIPCHK(hipGetLastError());
     return;
   }
   HIPCHK(hipGetLastError());
   nt = gemm_tiles(P->h_ana, nvec);
-  hipLaunchKernelGGL(sc::k_gemm_batched<T>, dim3((unsigned)nt), dim3(256), 0, s, P->probs_ana.as<sc::GemmProb>(),
-                     P->nprob_ana, nvec, (const T*)ws, tab, ws);
+  {
+    Prof _p(P, SC_STAGE_LEGENDRE_ANAL, s);
+    hipLaunchKernelGGL(sc::k_gemm_batched<T>, dim3((unsigned)nt), dim3(256), 0, s, P->probs_ana.as<sc::GemmProb>(),
+                       P->nprob_ana, nvec, (const T*)ws, tab, ws);
+  }
   HIPCHK(hipGetLastError());
+}
+
+constexpr int kSeg = 8;   // blocks per scan segment
+constexpr int kVG = 16;   // vectors per workgroup in the chain solves
+
+template <class F>
+size_t scan_smem(int N) {
+  return sizeof(F) * 2 * ((size_t)N * N + 3 * (size_t)N * kVG);
 }
 
 // Implicit solve x = A^{-1} b with factors in precision F (all vectors in canonical FP64).
 template <class F>
 void implicit_solve(sc_plan* P, int nvec, const double* b, double* x, hipStream_t s) {
   sc::DevGrid dg = P->dg();
-  constexpr int VG = 16;
-  dim3 grid(P->nchains, (nvec + VG - 1) / VG);
+  const int VG = kVG;
+  const int nvg = (nvec + VG - 1) / VG;
   bool d = std::is_same<F, double>::value;
   const F* Sinv = (const F*)(d ? P->Sinv64.p : P->Sinv32.p);
   const F* Lo = (const F*)(d ? P->Lo64.p : P->Lo32.p);
   const F* H = (const F*)(d ? P->H64.p : P->H32.p);
+  const F* Phi = (const F*)(d ? P->Phi64.p : P->Phi32.p);
+  const F* Psi = (const F*)(d ? P->Psi64.p : P->Psi32.p);
   const F* sr = (const F*)(d ? P->sr64.p : P->sr32.p);
   const F* scl = (const F*)(d ? P->sc64.p : P->sc32.p);
   const F* Rg = (const F*)(d ? P->Rg64.p : P->Rg32.p);
   const F* Cg = (const F*)(d ? P->Cg64.p : P->Cg32.p);
-  hipLaunchKernelGGL((sc::k_chain_solve<F, VG>), grid, dim3(256), 0, s, dg, nvec, P->chains.as<sc::ChainMeta>(),
-                     P->blk_field.as<int>(), P->blk_lm.as<int>(), Sinv, Lo, H, sr, scl, Rg, Cg, b, x);
-  HIPCHK(hipGetLastError());
+  F* W = (F*)P->wscan.p;
+  const size_t smem = scan_smem<F>(P->hg.N);
+  const sc::ChainMeta* ch = P->chains.as<sc::ChainMeta>();
+  const sc::SegMeta* sg = P->segs.as<sc::SegMeta>();
+  {
+    Prof _p(P, SC_STAGE_CHAIN_SOLVE, s);
+    hipLaunchKernelGGL((sc::k_scan_fwd_local<F, kVG>), dim3(P->nsegs, nvg), dim3(256), smem, s, dg, nvec, sg,
+                       P->blk_field.as<int>(), P->blk_lm.as<int>(), Sinv, Lo, sr, scl, Rg, b, W);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL((sc::k_scan_fwd_bound<F, kVG>), dim3(P->nchains, nvg), dim3(256), smem, s, dg, nvec, ch, sg, Phi, W);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL((sc::k_scan_bwd_local<F, kVG>), dim3(P->nsegs, nvg), dim3(256), smem, s, dg, nvec, ch, sg, Phi, H, W);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL((sc::k_scan_bwd_bound<F, kVG>), dim3(P->nchains, nvg), dim3(256), smem, s, dg, nvec, ch, sg, Psi, W);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL((sc::k_scan_out<F, kVG>), dim3(P->nblocks, nvg), dim3(256), smem, s, dg, nvec,
+                       P->blk_field.as<int>(), P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const F*)W, x);
+    HIPCHK(hipGetLastError());
+  }
   const F* Ti = (const F*)(d ? P->Tinv64.p : P->Tinv32.p);
   const F* tr = (const F*)(d ? P->tr64.p : P->tr32.p);
   const F* tc = (const F*)(d ? P->tc64.p : P->tc32.p);
   long long nT = (long long)nvec * P->hg.S * P->hg.N;
-  hipLaunchKernelGGL(sc::k_T_solve<F>, dim3(nblk(nT, 256)), dim3(256), 0, s, dg, nvec, Ti, tr, tc, b, x);
-  HIPCHK(hipGetLastError());
+  {
+    Prof _p(P, SC_STAGE_T_SOLVE, s);
+    hipLaunchKernelGGL(sc::k_T_solve<F>, dim3(nblk(nT, 256)), dim3(256), 0, s, dg, nvec, Ti, tr, tc, b, x);
+    HIPCHK(hipGetLastError());
+  }
 }
 
 // x = A^{-1} b with `passes` FP64 refinement passes; factors in precision F.
@@ -364,11 +437,17 @@ void refined_solve(sc_plan* P, int nvec, const double* b, double* x, int passes,
   long long n = (long long)nvec * P->n_real;
   long long nres = (long long)nvec * 3 * P->hg.S * P->hg.N;
   for (int it = 0; it < passes; ++it) {
-    hipLaunchKernelGGL(sc::k_residual64, dim3(nblk(nres, 256)), dim3(256), 0, s, dg, P->pp(), nvec, b, x,
-                       P->rbuf.as<double>());
+    {
+      Prof _p(P, SC_STAGE_RESIDUAL, s);
+      hipLaunchKernelGGL(sc::k_residual64, dim3(nblk(nres, 256)), dim3(256), 0, s, dg, P->pp(), nvec, b, x,
+                         P->rbuf.as<double>());
+    }
     HIPCHK(hipGetLastError());
     implicit_solve<F>(P, nvec, P->rbuf.as<double>(), P->dbuf.as<double>(), s);
-    hipLaunchKernelGGL(sc::k_axpy1, dim3(nblk(n, 256)), dim3(256), 0, s, n, P->dbuf.as<const double>(), x);
+    {
+      Prof _p(P, SC_STAGE_AXPY, s);
+      hipLaunchKernelGGL(sc::k_axpy1, dim3(nblk(n, 256)), dim3(256), 0, s, n, P->dbuf.as<const double>(), x);
+    }
     HIPCHK(hipGetLastError());
   }
 }
@@ -377,9 +456,12 @@ void refined_solve(sc_plan* P, int nvec, const double* b, double* x, int passes,
 void step_into_xbuf(sc_plan* P, const double* x, double C, hipStream_t s) {
   transforms<double>(P, sc::RING_NONLINEAR, 1, x, P->n_real, -1, s);
   sc::DevGrid dg = P->dg();
-  hipLaunchKernelGGL((sc::k_project_rhs<double, true>), dim3(P->hg.S), dim3(128), 0, s, dg, P->pp(), 1,
-                     (const double*)(P->ws64.as<double>() + P->wl.As), (const double*)(P->ws64.as<double>() + P->wl.Av),
-                     x, P->n_real, (long long)-1, C, (const double*)nullptr, P->bbuf.as<double>());
+  {
+    Prof _p(P, SC_STAGE_PROJECT_RHS, s);
+    hipLaunchKernelGGL((sc::k_project_rhs<double, true>), dim3(P->hg.S), dim3(128), 0, s, dg, P->pp(), 1,
+                       (const double*)(P->ws64.as<double>() + P->wl.As), (const double*)(P->ws64.as<double>() + P->wl.Av),
+                       x, P->n_real, (long long)-1, C, (const double*)nullptr, P->bbuf.as<double>());
+  }
   HIPCHK(hipGetLastError());
   refined_solve<double>(P, 1, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine64, s);
 }
@@ -449,6 +531,24 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     if (smem32 > 64 * 1024)
       HIPCHK(hipFuncSetAttribute((const void*)sc::k_ring<float, sc::RING_LINEAR, kRT>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem32));
+    {
+      const size_t s64 = scan_smem<double>(g.N), s32 = scan_smem<float>(g.N);
+      if (s64 > 160 * 1024) throw Fail{SC_ERR_ARG, "N too large for the chain solve"};
+      if (s64 > 64 * 1024) {
+        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_fwd_local<double, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s64));
+        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_fwd_bound<double, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s64));
+        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_bwd_local<double, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s64));
+        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_bwd_bound<double, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s64));
+        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_out<double, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s64));
+      }
+      if (s32 > 64 * 1024) {
+        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_fwd_local<float, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s32));
+        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_fwd_bound<float, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s32));
+        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_bwd_local<float, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s32));
+        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_bwd_bound<float, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s32));
+        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_out<float, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s32));
+      }
+    }
     // deterministic contents for slots the solves never write (e, f at l = 0)
     HIPCHK(hipMemset(P->xbuf.p, 0, P->xbuf.bytes));
     HIPCHK(hipMemset(P->dbuf.p, 0, P->dbuf.bytes));
@@ -503,28 +603,39 @@ int sc_factor(sc_plan* P, void* stream) {
     std::vector<sc::TFactor> tf;
     sc::OpParams op{P->prm.Ek, P->prm.Pr, P->prm.dt};
     int nth = (int)std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
-    sc::factor_all(g, op, ch, tf, nth);
+    sc::factor_all(g, op, ch, tf, nth, kSeg);
     const int N = g.N;
     std::vector<sc::ChainMeta> meta;
-    std::vector<int> bf, blm;
+    std::vector<sc::SegMeta> segv;
+    std::vector<int> bf, blm, bnext;
     long long nb = 0;
     for (auto& c : ch) nb += c.n;
-    std::vector<double> Sinv(2 * nb * N * N), Lo(2 * nb * N * N), H(2 * nb * N * N);
+    const long long NN = (long long)N * N;
+    std::vector<double> Sinv(2 * nb * NN), Lo(2 * nb * NN), H(2 * nb * NN), Phi(2 * nb * NN), Psi(2 * nb * NN);
     std::vector<double> sr(nb * N), scv(nb * N), Rg(nb * N), Cg(nb * N);
     long long b = 0;
-    for (auto& c : ch) {
-      meta.push_back(sc::ChainMeta{(int)b, c.n, c.k, 0});
+    auto put = [&](std::vector<double>& dst, const std::vector<sc::cplx>& src, long long bb, int i) {
+      for (long long q = 0; q < NN; ++q) {
+        dst[2 * (bb * NN + q)] = src[(size_t)i * NN + q].real();
+        dst[2 * (bb * NN + q) + 1] = src[(size_t)i * NN + q].imag();
+      }
+    };
+    for (int ci = 0; ci < (int)ch.size(); ++ci) {
+      auto& c = ch[ci];
+      int nseg = (c.n + kSeg - 1) / kSeg;
+      meta.push_back(sc::ChainMeta{(int)b, c.n, c.k, (int)segv.size(), nseg, 0, 0, 0});
+      for (int p = 0; p < nseg; ++p) segv.push_back(sc::SegMeta{(int)b + p * kSeg, std::min(kSeg, c.n - p * kSeg), ci, p});
       for (int i = 0; i < c.n; ++i, ++b) {
         bf.push_back(c.field[i]);
         blm.push_back(g.lmbase[c.k] + (c.l[i] - c.m));
-        for (long long q = 0; q < (long long)N * N; ++q) {
-          Sinv[2 * (b * N * N + q)] = c.Sinv[(size_t)i * N * N + q].real();
-          Sinv[2 * (b * N * N + q) + 1] = c.Sinv[(size_t)i * N * N + q].imag();
-          Lo[2 * (b * N * N + q)] = c.Lo[(size_t)i * N * N + q].real();
-          Lo[2 * (b * N * N + q) + 1] = c.Lo[(size_t)i * N * N + q].imag();
-          H[2 * (b * N * N + q)] = c.H[(size_t)i * N * N + q].real();
-          H[2 * (b * N * N + q) + 1] = c.H[(size_t)i * N * N + q].imag();
-        }
+        int p = i / kSeg;
+        bool fixup = (p < nseg - 1) && (i % kSeg != 0);
+        bnext.push_back(fixup ? (int)(meta.back().start + (p + 1) * kSeg) : -1);
+        put(Sinv, c.Sinv, b, i);
+        put(Lo, c.Lo, b, i);
+        put(H, c.H, b, i);
+        put(Phi, c.Phi, b, i);
+        put(Psi, c.Psi, b, i);
         for (int j = 0; j < N; ++j) {
           sr[b * N + j] = c.sr[(size_t)i * N + j];
           scv[b * N + j] = c.sc[(size_t)i * N + j];
@@ -545,11 +656,16 @@ int sc_factor(sc_plan* P, void* stream) {
       upload(d32, f);
     };
     upload(P->chains, meta);
+    upload(P->segs, segv);
     upload(P->blk_field, bf);
     upload(P->blk_lm, blm);
+    upload(P->blk_next, bnext);
     up2(P->Sinv64, P->Sinv32, Sinv);
     up2(P->Lo64, P->Lo32, Lo);
     up2(P->H64, P->H32, H);
+    up2(P->Phi64, P->Phi32, Phi);
+    up2(P->Psi64, P->Psi32, Psi);
+    P->wscan.alloc((size_t)P->vcap * nb * N * 2 * sizeof(double));
     up2(P->sr64, P->sr32, sr);
     up2(P->sc64, P->sc32, scv);
     up2(P->Rg64, P->Rg32, Rg);
@@ -559,6 +675,7 @@ int sc_factor(sc_plan* P, void* stream) {
     up2(P->tc64, P->tc32, tc);
     P->nchains = (int)meta.size();
     P->nblocks = (int)nb;
+    P->nsegs = (int)segv.size();
     P->factored = true;
     P->have_base = false;  // the cached M X depends on Ek
   });
@@ -572,8 +689,11 @@ int sc_step(sc_plan* P, const double* x, double C, double* x_next, void* stream)
     hipStream_t s = (hipStream_t)stream;
     step_into_xbuf(P, x, C, s);
     long long n = P->n_real;
-    hipLaunchKernelGGL(sc::k_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, P->dg(), 1, P->xbuf.as<const double>(), x, n,
-                       (long long)-1, x_next, n, 0);
+    {
+      Prof _p(P, SC_STAGE_FINALIZE, s);
+      hipLaunchKernelGGL(sc::k_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, P->dg(), 1, P->xbuf.as<const double>(), x, n,
+                         (long long)-1, x_next, n, 0);
+    }
     HIPCHK(hipGetLastError());
   });
 }
@@ -586,8 +706,11 @@ int sc_newton_residual(sc_plan* P, const double* x, double C, double* r, double*
     hipStream_t s = (hipStream_t)stream;
     step_into_xbuf(P, x, C, s);
     long long n = P->n_real;
-    hipLaunchKernelGGL(sc::k_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, P->dg(), 1, P->xbuf.as<const double>(), x, n,
-                       (long long)-1, r, n, 1);
+    {
+      Prof _p(P, SC_STAGE_FINALIZE, s);
+      hipLaunchKernelGGL(sc::k_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, P->dg(), 1, P->xbuf.as<const double>(), x, n,
+                         (long long)-1, r, n, 1);
+    }
     HIPCHK(hipGetLastError());
     if (rnorm_host) {
       hipLaunchKernelGGL(sc::k_sumsq, dim3(1), dim3(256), 0, s, n, (const double*)r, n, P->norms.as<double>());
@@ -627,6 +750,43 @@ int sc_set_base(sc_plan* P, const double* x, double C, long long J, void* stream
   });
 }
 
+int sc_profile(sc_plan* P, int enable) {
+  return guarded([&] {
+    check_plan(P);
+    HIPCHK(hipDeviceSynchronize());
+    if (enable && P->ev.empty()) {
+      const int cap = 16384;
+      P->ev.resize(2 * cap);
+      P->ev_stage.assign(cap, -1);
+      for (auto& e : P->ev) HIPCHK(hipEventCreate(&e));
+    }
+    P->ev_used = 0;
+    P->prof_on = enable != 0;
+  });
+}
+
+int sc_profile_read(sc_plan* P, double* ms_total, long long* count, int nstages) {
+  return guarded([&] {
+    check_plan(P);
+    if (!ms_total || !count || nstages < 0) throw Fail{SC_ERR_ARG, "null output"};
+    for (int i = 0; i < nstages; ++i) {
+      ms_total[i] = 0.0;
+      count[i] = 0;
+    }
+    for (int q = 0; q < P->ev_used; ++q) {
+      HIPCHK(hipEventSynchronize(P->ev[2 * q + 1]));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, P->ev[2 * q], P->ev[2 * q + 1]));
+      int st = P->ev_stage[q];
+      if (st >= 0 && st < nstages) {
+        ms_total[st] += ms;
+        count[st] += 1;
+      }
+    }
+    P->ev_used = 0;
+  });
+}
+
 int sc_jvp(sc_plan* P, int nvec, const double* v, long long ldv, double* y, long long ldy, sc_precision prec,
            void* stream) {
   return guarded([&] {
@@ -642,24 +802,33 @@ int sc_jvp(sc_plan* P, int nvec, const double* v, long long ldv, double* y, long
     sc::DevGrid dg = P->dg();
     if (prec == SC_FP64) {
       transforms<double>(P, sc::RING_LINEAR, nvec, v, ldv, J, s);
-      hipLaunchKernelGGL((sc::k_project_rhs<double, false>), dim3((unsigned)((long long)nvec * P->hg.S)), dim3(128), 0, s,
-                         dg, P->pp(), nvec, (const double*)(P->ws64.as<double>() + P->wl.As),
-                         (const double*)(P->ws64.as<double>() + P->wl.Av), v, ldv, J, P->baseC,
-                         P->MX.as<const double>(), P->bbuf.as<double>());
+      {
+        Prof _p(P, SC_STAGE_PROJECT_RHS, s);
+        hipLaunchKernelGGL((sc::k_project_rhs<double, false>), dim3((unsigned)((long long)nvec * P->hg.S)), dim3(128), 0, s,
+                           dg, P->pp(), nvec, (const double*)(P->ws64.as<double>() + P->wl.As),
+                           (const double*)(P->ws64.as<double>() + P->wl.Av), v, ldv, J, P->baseC,
+                           P->MX.as<const double>(), P->bbuf.as<double>());
+      }
       HIPCHK(hipGetLastError());
       refined_solve<double>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine64, s);
     } else {
       transforms<float>(P, sc::RING_LINEAR, nvec, v, ldv, J, s);
-      hipLaunchKernelGGL((sc::k_project_rhs<float, false>), dim3((unsigned)((long long)nvec * P->hg.S)), dim3(128), 0, s,
-                         dg, P->pp(), nvec, (const float*)(P->ws32.as<float>() + P->wl.As),
-                         (const float*)(P->ws32.as<float>() + P->wl.Av), v, ldv, J, P->baseC,
-                         P->MX.as<const double>(), P->bbuf.as<double>());
+      {
+        Prof _p(P, SC_STAGE_PROJECT_RHS, s);
+        hipLaunchKernelGGL((sc::k_project_rhs<float, false>), dim3((unsigned)((long long)nvec * P->hg.S)), dim3(128), 0, s,
+                           dg, P->pp(), nvec, (const float*)(P->ws32.as<float>() + P->wl.As),
+                           (const float*)(P->ws32.as<float>() + P->wl.Av), v, ldv, J, P->baseC,
+                           P->MX.as<const double>(), P->bbuf.as<double>());
+      }
       HIPCHK(hipGetLastError());
       refined_solve<float>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine32, s);
     }
     long long n = (long long)nvec * P->n_real;
-    hipLaunchKernelGGL(sc::k_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, dg, nvec, P->xbuf.as<const double>(), v, ldv,
-                       J, y, ldy, 1);
+    {
+      Prof _p(P, SC_STAGE_FINALIZE, s);
+      hipLaunchKernelGGL(sc::k_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, dg, nvec, P->xbuf.as<const double>(), v, ldv,
+                         J, y, ldy, 1);
+    }
     HIPCHK(hipGetLastError());
   });
 }

@@ -526,115 +526,250 @@ __global__ void k_apply_M(DevGrid g, PhysParams ph, const double* __restrict__ X
 }
 
 // ------------------------------------------------------------------------------------------
-// K8: block-tridiagonal solve along each (m, class) chain with the equilibrated block LU:
-//   b~ = Rg b;  z_i = sc_i Shat_i^{-1} sr_i (b~_i - Lo_i z_{i-1});  x~_i = z_i - H_i x~_{i+1};
-//   x = Cg x~.  One block per (chain, group of VG vectors).  Factors in precision F.
+// K8: block-tridiagonal solve along each (m, class) chain with the equilibrated block LU,
+// organised as a segmented scan so that the sequential part is short:
+//   forward  z_i = D_i (t_i - Lo_i z_{i-1}),  t = Rg b,  D_i = diag(sc_i) Shat_i^{-1} diag(sr_i)
+//   backward x_i = z_i - H_i x_{i+1},         result Cg x
+// Inside a segment [a, e]: z_i = zeta_i + Phi_i z_{a-1}, x_i = xi_i + Psi_i x_{e+1}, where zeta
+// and xi are the local recurrences started from zero.  Five launches: local forward (per
+// segment), forward boundary pass (per chain), local backward with the forward fix-up (per
+// segment), backward boundary pass (per chain), final fix-up and output (per block).
+// Work vectors live in W[(block*N + j)*vcap + vec] (complex, precision F, scaled space).
 struct ChainMeta {
-  int start, n, k, pad;
+  int start, n, k, first_seg, nseg, pad0, pad1, pad2;
+};
+struct SegMeta {
+  int first_block, len, chain, pidx;
 };
 
+template <class F>
+struct cpx {
+  F re, im;
+};
+
+// Stage an N x N complex block (row-major, interleaved) into LDS with coalesced loads.
+template <class F>
+__device__ inline void stage_block(const F* __restrict__ gmat, cpx<F>* sm, int N) {
+  const cpx<F>* src = reinterpret_cast<const cpx<F>*>(gmat);
+  for (int i = threadIdx.x; i < N * N; i += blockDim.x) sm[i] = src[i];
+}
+
+// acc(j, vv) += sign * sum_q M[j][q] v[q][vv] for the thread's own (j, vv) entries.
 template <class F, int VG>
-__global__ void __launch_bounds__(256) k_chain_solve(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
-                                                     const int* __restrict__ blk_field, const int* __restrict__ blk_lm,
-                                                     const F* __restrict__ Sinv, const F* __restrict__ Lo,
-                                                     const F* __restrict__ H, const F* __restrict__ sr,
-                                                     const F* __restrict__ scl, const F* __restrict__ Rg,
-                                                     const F* __restrict__ Cg, const double* __restrict__ bvec,
-                                                     double* __restrict__ xvec) {
-  __shared__ F zr[64][VG], zi[64][VG], tr_[64][VG], ti_[64][VG];
-  const ChainMeta ch = chains[blockIdx.x];
-  const int v0 = blockIdx.y * VG;
-  const int nv = min(VG, nvec - v0);
+__device__ inline void mv_acc(const cpx<F>* M, const cpx<F>* v, cpx<F>* acc, int N, int nv, F sign) {
+  for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) {
+    int vv = idx % VG, j = idx / VG;
+    if (vv >= nv) continue;
+    F ar = 0, ai = 0;
+    const cpx<F>* Mr = M + j * N;
+    for (int q = 0; q < N; ++q) {
+      cpx<F> m = Mr[q], x = v[q * VG + vv];
+      ar += m.re * x.re - m.im * x.im;
+      ai += m.re * x.im + m.im * x.re;
+    }
+    acc[j * VG + vv].re += sign * ar;
+    acc[j * VG + vv].im += sign * ai;
+  }
+}
+
+template <class F, int VG>
+__device__ inline void load_w(const F* __restrict__ W, int vcap, int b, int v0, cpx<F>* dst, int N, int nv) {
+  const cpx<F>* src = reinterpret_cast<const cpx<F>*>(W);
+  for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) {
+    int vv = idx % VG, j = idx / VG;
+    if (vv < nv) dst[idx] = src[((long long)b * N + j) * vcap + v0 + vv];
+  }
+}
+
+template <class F, int VG>
+__device__ inline void store_w(F* __restrict__ W, int vcap, int b, int v0, const cpx<F>* srcv, int N, int nv) {
+  cpx<F>* dst = reinterpret_cast<cpx<F>*>(W);
+  for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) {
+    int vv = idx % VG, j = idx / VG;
+    if (vv < nv) dst[((long long)b * N + j) * vcap + v0 + vv] = srcv[idx];
+  }
+}
+
+template <class F, int VG>
+__global__ void __launch_bounds__(256) k_scan_fwd_local(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
+                                                        const int* __restrict__ blk_field, const int* __restrict__ blk_lm,
+                                                        const F* __restrict__ Sinv, const F* __restrict__ Lo,
+                                                        const F* __restrict__ sr, const F* __restrict__ scl,
+                                                        const F* __restrict__ Rg, const double* __restrict__ bvec,
+                                                        F* __restrict__ W) {
+  extern __shared__ unsigned char smem_raw[];
   const int N = g.N;
-  const int tid = threadIdx.x;
-  const long long NN = (long long)N * N;
-  const long long ld = 6LL * N * g.S;  // canonical vector length
-  if (ch.n <= 0 || nv <= 0) return;
-  // forward sweep
-  for (int i = 0; i < ch.n; ++i) {
-    int b = ch.start + i;
-    long long o = 2LL * ((long long)N * ((long long)blk_field[b] * g.S + blk_lm[b]));
-    const F* Lb = Lo + 2 * NN * b;
-    for (int idx = tid; idx < N * nv; idx += blockDim.x) {
-      int j = idx % N, vv = idx / N;
+  cpx<F>* Ms = reinterpret_cast<cpx<F>*>(smem_raw);
+  cpx<F>* prev = Ms + N * N;
+  cpx<F>* tmp = prev + N * VG;
+  const SegMeta sg = segs[blockIdx.x];
+  const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
+  const long long NN2 = 2LL * N * N, ld = 6LL * N * g.S;
+  for (int i = 0; i < sg.len; ++i) {
+    const int b = sg.first_block + i;
+    const long long o = 2LL * ((long long)N * ((long long)blk_field[b] * g.S + blk_lm[b]));
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) {
+      int vv = idx % VG, j = idx / VG;
+      if (vv >= nv) continue;
       const double* bp = bvec + (long long)(v0 + vv) * ld + o + 2 * j;
-      F rr = (F)(Rg[(long long)b * N + j] * bp[0]);
-      F ri = (F)(Rg[(long long)b * N + j] * bp[1]);
-      if (i > 0) {
-        const F* Lr = Lb + 2LL * j * N;
-        for (int q = 0; q < N; ++q) {
-          F lr = Lr[2 * q], li = Lr[2 * q + 1];
-          F zq = zr[q][vv], zqi = zi[q][vv];
-          rr -= lr * zq - li * zqi;
-          ri -= lr * zqi + li * zq;
-        }
-      }
+      F rg = Rg[(long long)b * N + j];
+      tmp[idx].re = rg * (F)bp[0];
+      tmp[idx].im = rg * (F)bp[1];
+    }
+    if (i > 0) {
+      stage_block(Lo + NN2 * b, Ms, N);
+      __syncthreads();
+      mv_acc<F, VG>(Ms, prev, tmp, N, nv, (F)-1);
+    }
+    for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) {
+      int j = idx / VG;
       F s = sr[(long long)b * N + j];
-      tr_[j][vv] = s * rr;
-      ti_[j][vv] = s * ri;
+      tmp[idx].re *= s;
+      tmp[idx].im *= s;
     }
     __syncthreads();
-    const F* Sb = Sinv + 2 * NN * b;
-    for (int idx = tid; idx < N * nv; idx += blockDim.x) {
-      int j = idx % N, vv = idx / N;
-      const F* Sr = Sb + 2LL * j * N;
-      F ar = 0, ai = 0;
-      for (int q = 0; q < N; ++q) {
-        F sr_ = Sr[2 * q], si_ = Sr[2 * q + 1];
-        ar += sr_ * tr_[q][vv] - si_ * ti_[q][vv];
-        ai += sr_ * ti_[q][vv] + si_ * tr_[q][vv];
-      }
+    stage_block(Sinv + NN2 * b, Ms, N);
+    for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) prev[idx].re = prev[idx].im = 0;
+    __syncthreads();
+    mv_acc<F, VG>(Ms, tmp, prev, N, nv, (F)1);
+    for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) {
+      int j = idx / VG;
       F c = scl[(long long)b * N + j];
-      ar *= c;
-      ai *= c;
-      zr[j][vv] = ar;
-      zi[j][vv] = ai;
-      double* xp = xvec + (long long)(v0 + vv) * ld + o + 2 * j;
-      xp[0] = (double)ar;  // scaled intermediate z_i, finalized in the backward sweep
-      xp[1] = (double)ai;
+      prev[idx].re *= c;
+      prev[idx].im *= c;
     }
     __syncthreads();
+    store_w<F, VG>(W, g.vcap, b, v0, prev, N, nv);
   }
-  // backward sweep: zr/zi hold z_{n-1} = x~_{n-1}
-  {
-    int b = ch.start + ch.n - 1;
-    long long o = 2LL * ((long long)N * ((long long)blk_field[b] * g.S + blk_lm[b]));
-    for (int idx = tid; idx < N * nv; idx += blockDim.x) {
-      int j = idx % N, vv = idx / N;
-      double* xp = xvec + (long long)(v0 + vv) * ld + o + 2 * j;
-      double c = (double)Cg[(long long)b * N + j];
-      xp[0] = c * (double)zr[j][vv];
-      xp[1] = c * (double)zi[j][vv];
-    }
+}
+
+// z at the end of each segment: z_e(p) = zeta_e(p) + Phi_e(p) z_e(p-1), sequential over p.
+template <class F, int VG>
+__global__ void __launch_bounds__(256) k_scan_fwd_bound(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
+                                                        const SegMeta* __restrict__ segs, const F* __restrict__ Phi,
+                                                        F* __restrict__ W) {
+  extern __shared__ unsigned char smem_raw[];
+  const int N = g.N;
+  cpx<F>* Ms = reinterpret_cast<cpx<F>*>(smem_raw);
+  cpx<F>* zb = Ms + N * N;
+  cpx<F>* tmp = zb + N * VG;
+  const ChainMeta ch = chains[blockIdx.x];
+  const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
+  if (ch.nseg <= 1) return;
+  const long long NN2 = 2LL * N * N;
+  SegMeta s0 = segs[ch.first_seg];
+  load_w<F, VG>(W, g.vcap, s0.first_block + s0.len - 1, v0, zb, N, nv);
+  for (int p = 1; p < ch.nseg; ++p) {
+    SegMeta sp = segs[ch.first_seg + p];
+    int e = sp.first_block + sp.len - 1;
+    __syncthreads();
+    load_w<F, VG>(W, g.vcap, e, v0, tmp, N, nv);
+    stage_block(Phi + NN2 * e, Ms, N);
+    __syncthreads();
+    mv_acc<F, VG>(Ms, zb, tmp, N, nv, (F)1);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) zb[idx] = tmp[idx];
+    store_w<F, VG>(W, g.vcap, e, v0, tmp, N, nv);
   }
-  for (int i = ch.n - 2; i >= 0; --i) {
-    int b = ch.start + i;
-    long long o = 2LL * ((long long)N * ((long long)blk_field[b] * g.S + blk_lm[b]));
-    const F* Hb = H + 2 * NN * b;
-    for (int idx = tid; idx < N * nv; idx += blockDim.x) {
-      int j = idx % N, vv = idx / N;
-      double* xp = xvec + (long long)(v0 + vv) * ld + o + 2 * j;
-      F ar = (F)xp[0], ai = (F)xp[1];
-      const F* Hr = Hb + 2LL * j * N;
-      for (int q = 0; q < N; ++q) {
-        F hr = Hr[2 * q], hi = Hr[2 * q + 1];
-        ar -= hr * zr[q][vv] - hi * zi[q][vv];
-        ai -= hr * zi[q][vv] + hi * zr[q][vv];
-      }
-      tr_[j][vv] = ar;
-      ti_[j][vv] = ai;
-    }
+}
+
+// Per segment, top-down: z_i = zeta_i + Phi_i z_{a-1} (segments after the first), then the
+// local backward recurrence xi_i = z_i - H_i xi_{i+1} started from xi_e = z_e.
+template <class F, int VG>
+__global__ void __launch_bounds__(256) k_scan_bwd_local(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
+                                                        const SegMeta* __restrict__ segs, const F* __restrict__ Phi,
+                                                        const F* __restrict__ H, F* __restrict__ W) {
+  extern __shared__ unsigned char smem_raw[];
+  const int N = g.N;
+  cpx<F>* Ms = reinterpret_cast<cpx<F>*>(smem_raw);
+  cpx<F>* prev = Ms + N * N;
+  cpx<F>* tmp = prev + N * VG;
+  cpx<F>* zin = tmp + N * VG;
+  const SegMeta sg = segs[blockIdx.x];
+  const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
+  const long long NN2 = 2LL * N * N;
+  const int e = sg.first_block + sg.len - 1;
+  const bool fix = sg.pidx > 0;
+  if (fix) load_w<F, VG>(W, g.vcap, sg.first_block - 1, v0, zin, N, nv);  // z_{a-1}: end of previous segment
+  load_w<F, VG>(W, g.vcap, e, v0, prev, N, nv);                               // xi_e = z_e
+  for (int b = e - 1; b >= sg.first_block; --b) {
     __syncthreads();
-    for (int idx = tid; idx < N * nv; idx += blockDim.x) {
-      int j = idx % N, vv = idx / N;
-      zr[j][vv] = tr_[j][vv];
-      zi[j][vv] = ti_[j][vv];
-      double* xp = xvec + (long long)(v0 + vv) * ld + o + 2 * j;
-      double c = (double)Cg[(long long)b * N + j];
-      xp[0] = c * (double)tr_[j][vv];
-      xp[1] = c * (double)ti_[j][vv];
+    load_w<F, VG>(W, g.vcap, b, v0, tmp, N, nv);
+    if (fix) {
+      stage_block(Phi + NN2 * b, Ms, N);
+      __syncthreads();
+      mv_acc<F, VG>(Ms, zin, tmp, N, nv, (F)1);
+      __syncthreads();
     }
+    stage_block(H + NN2 * b, Ms, N);
     __syncthreads();
+    mv_acc<F, VG>(Ms, prev, tmp, N, nv, (F)-1);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) prev[idx] = tmp[idx];
+    store_w<F, VG>(W, g.vcap, b, v0, tmp, N, nv);
+  }
+}
+
+// x at the start of each segment: x_a(p) = xi_a(p) + Psi_a(p) x_a(p+1), sequential from the end.
+template <class F, int VG>
+__global__ void __launch_bounds__(256) k_scan_bwd_bound(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
+                                                        const SegMeta* __restrict__ segs, const F* __restrict__ Psi,
+                                                        F* __restrict__ W) {
+  extern __shared__ unsigned char smem_raw[];
+  const int N = g.N;
+  cpx<F>* Ms = reinterpret_cast<cpx<F>*>(smem_raw);
+  cpx<F>* xb = Ms + N * N;
+  cpx<F>* tmp = xb + N * VG;
+  const ChainMeta ch = chains[blockIdx.x];
+  const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
+  if (ch.nseg <= 1) return;
+  const long long NN2 = 2LL * N * N;
+  load_w<F, VG>(W, g.vcap, segs[ch.first_seg + ch.nseg - 1].first_block, v0, xb, N, nv);
+  for (int p = ch.nseg - 2; p >= 0; --p) {
+    int a = segs[ch.first_seg + p].first_block;
+    __syncthreads();
+    load_w<F, VG>(W, g.vcap, a, v0, tmp, N, nv);
+    stage_block(Psi + NN2 * a, Ms, N);
+    __syncthreads();
+    mv_acc<F, VG>(Ms, xb, tmp, N, nv, (F)1);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) xb[idx] = tmp[idx];
+    store_w<F, VG>(W, g.vcap, a, v0, tmp, N, nv);
+  }
+}
+
+// x_i = xi_i + Psi_i x_{a(p+1)} for the blocks not yet final, then x = Cg x~ into the
+// canonical output.  One workgroup per (block, vector group).
+template <class F, int VG>
+__global__ void __launch_bounds__(256) k_scan_out(DevGrid g, int nvec, const int* __restrict__ blk_field,
+                                                  const int* __restrict__ blk_lm, const int* __restrict__ blk_next,
+                                                  const F* __restrict__ Psi, const F* __restrict__ Cg,
+                                                  const F* __restrict__ W, double* __restrict__ xvec) {
+  extern __shared__ unsigned char smem_raw[];
+  const int N = g.N;
+  cpx<F>* Ms = reinterpret_cast<cpx<F>*>(smem_raw);
+  cpx<F>* xn = Ms + N * N;
+  cpx<F>* acc = xn + N * VG;
+  const int b = blockIdx.x;
+  const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
+  const long long NN2 = 2LL * N * N, ld = 6LL * N * g.S;
+  const int nx = blk_next[b];
+  load_w<F, VG>(W, g.vcap, b, v0, acc, N, nv);
+  if (nx >= 0) {
+    load_w<F, VG>(W, g.vcap, nx, v0, xn, N, nv);
+    stage_block(Psi + NN2 * b, Ms, N);
+    __syncthreads();
+    mv_acc<F, VG>(Ms, xn, acc, N, nv, (F)1);
+  }
+  const long long o = 2LL * ((long long)N * ((long long)blk_field[b] * g.S + blk_lm[b]));
+  for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) {
+    int vv = idx % VG, j = idx / VG;
+    if (vv >= nv) continue;
+    double c = (double)Cg[(long long)b * N + j];
+    double* xp = xvec + (long long)(v0 + vv) * ld + o + 2 * j;
+    xp[0] = c * (double)acc[idx].re;
+    xp[1] = c * (double)acc[idx].im;
   }
 }
 

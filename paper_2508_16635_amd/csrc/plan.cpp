@@ -474,6 +474,60 @@ void factor_chain(const Blocks& B, const HostGrid& g, int k, int cls, ChainFacto
   }
 }
 
+// Propagators of the segmented scan (see ChainFactor).
+void build_scan(ChainFactor& cf, int N, int seg) {
+  const int n = cf.n;
+  const size_t NN = (size_t)N * N;
+  cf.Phi.assign((size_t)n * NN, 0.0);
+  cf.Psi.assign((size_t)n * NN, 0.0);
+  std::vector<cplx> D(NN), G(NN), T(NN);
+  for (int a = seg; a < n; a += seg) {
+    int e = std::min(a + seg, n) - 1;
+    for (int i = a; i <= e; ++i) {
+      // D = S_i^{-1} = diag(sc) Shat^{-1} diag(sr);  G = -D Lo_i
+      const cplx* Si = &cf.Sinv[(size_t)i * NN];
+      for (int r = 0; r < N; ++r)
+        for (int c = 0; c < N; ++c) D[(size_t)r * N + c] = cf.sc[(size_t)i * N + r] * Si[(size_t)r * N + c] * cf.sr[(size_t)i * N + c];
+      const cplx* Li = &cf.Lo[(size_t)i * NN];
+      std::fill(G.begin(), G.end(), cplx(0.0));
+      for (int r = 0; r < N; ++r)
+        for (int q = 0; q < N; ++q) {
+          cplx d = D[(size_t)r * N + q];
+          for (int c = 0; c < N; ++c) G[(size_t)r * N + c] -= d * Li[(size_t)q * N + c];
+        }
+      cplx* Pi = &cf.Phi[(size_t)i * NN];
+      if (i == a) {
+        std::copy(G.begin(), G.end(), Pi);
+      } else {
+        const cplx* Pp = &cf.Phi[(size_t)(i - 1) * NN];
+        for (int r = 0; r < N; ++r)
+          for (int q = 0; q < N; ++q) {
+            cplx gv = G[(size_t)r * N + q];
+            for (int c = 0; c < N; ++c) Pi[(size_t)r * N + c] += gv * Pp[(size_t)q * N + c];
+          }
+      }
+    }
+  }
+  for (int a = 0; a < n; a += seg) {
+    int e = std::min(a + seg, n) - 1;
+    if (e == n - 1) break;
+    for (int i = e; i >= a; --i) {
+      const cplx* Hi = &cf.H[(size_t)i * NN];
+      cplx* Pi = &cf.Psi[(size_t)i * NN];
+      if (i == e) {
+        for (size_t q = 0; q < NN; ++q) Pi[q] = -Hi[q];
+      } else {
+        const cplx* Pn = &cf.Psi[(size_t)(i + 1) * NN];
+        for (int r = 0; r < N; ++r)
+          for (int q = 0; q < N; ++q) {
+            cplx hv = -Hi[(size_t)r * N + q];
+            for (int c = 0; c < N; ++c) Pi[(size_t)r * N + c] += hv * Pn[(size_t)q * N + c];
+          }
+      }
+    }
+  }
+}
+
 void factor_T(const HostGrid& g, const OpParams& op, int l, TFactor& tf) {
   const int N = g.N;
   std::vector<double> A((size_t)N * N, 0.0);
@@ -499,7 +553,7 @@ void factor_T(const HostGrid& g, const OpParams& op, int l, TFactor& tf) {
 }  // namespace
 
 void factor_all(const HostGrid& g, const OpParams& op, std::vector<ChainFactor>& chains,
-                std::vector<TFactor>& tf, int nthreads) {
+                std::vector<TFactor>& tf, int nthreads, int seg) {
   Blocks B{g.N, &g, op};
   int nch = 2 * (g.K + 1);
   chains.assign(nch, ChainFactor());
@@ -509,8 +563,10 @@ void factor_all(const HostGrid& g, const OpParams& op, std::vector<ChainFactor>&
   auto work = [&](int tid) {
     try {
       for (int t = tid; t < ntask; t += nthreads) {
-        if (t < nch)
+        if (t < nch) {
           factor_chain(B, g, t / 2, t % 2, chains[t]);
+          build_scan(chains[t], g.N, seg);
+        }
         else
           factor_T(g, op, t - nch, tf[t - nch]);
       }

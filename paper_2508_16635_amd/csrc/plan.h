@@ -34,12 +34,17 @@ void build_grid(HostGrid& g, int L, int M, int m0, int N, double eta, int Np, in
 //   global scalings Rg, Cg (A~ = diag(Rg) A diag(Cg)),
 //   per block: Sinv = inverse of the Ruiz-equilibrated Schur complement diag(sr) S diag(sc),
 //              Lo = A~_{i,i-1},  H = S_i^{-1} A~_{i,i+1}.
+//   segmented scan (segments of `seg` blocks): with z_i the forward unknowns and x_i the
+//   backward ones, z_i = zeta_i + Phi_i z_{a-1} inside a segment starting at a, and
+//   x_i = xi_i + Psi_i x_{e+1} inside a segment ending at e; Phi_i = -S_i^{-1} Lo_i Phi_{i-1},
+//   Psi_i = -H_i Psi_{i+1} (zero in the first / last segment where they are not used).
 struct ChainFactor {
   int k = 0, m = 0, cls = 0, n = 0, l0 = 0;
   std::vector<int> field, l;                  // per block: 0 = e, 1 = f
   std::vector<double> Rg, Cg;                 // n*N
   std::vector<double> sr, sc;                 // n*N
   std::vector<cplx> Sinv, Lo, H;              // n*N*N each (row-major blocks)
+  std::vector<cplx> Phi, Psi;                 // n*N*N each
 };
 
 struct TFactor {                              // temperature block per l (real)
@@ -52,6 +57,6 @@ struct OpParams {
 
 // Builds and factors every chain and temperature block; nthreads host threads.
 void factor_all(const HostGrid& g, const OpParams& op, std::vector<ChainFactor>& chains,
-                std::vector<TFactor>& tf, int nthreads);
+                std::vector<TFactor>& tf, int nthreads, int seg);
 
 }  // namespace sc

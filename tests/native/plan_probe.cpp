@@ -25,7 +25,7 @@ int main(int argc, char** argv) {
   build_grid(g, L, M, m0, N, 0.35, 0, 0, 0);
   std::vector<ChainFactor> ch;
   std::vector<TFactor> tf;
-  factor_all(g, OpParams{Ek, Pr, dt}, ch, tf, 4);
+  factor_all(g, OpParams{Ek, Pr, dt}, ch, tf, 4, 8);
   // read rhs
   long long nreal = 6LL * N * g.S;
   std::vector<double> b(nreal), x(nreal, 0.0);
