@@ -84,6 +84,8 @@ struct sc_plan {
   long long baseJ = -1;
   // grid / radial data
   DevBuf d_lmk, d_lml, d_lmbase, d_r, d_rp, d_E, d_ED, d_ED2, d_P, d_Dp, d_D, d_D2, d_D4;
+  DevBuf d_ET, d_EDT, d_ED2T, d_DT, d_D2T, d_D4T, d_rtiles;
+  int nrtiles = 0;
   // tables and workspaces per precision
   TabLayout tl;
   WsLayout wl;
@@ -96,10 +98,10 @@ struct sc_plan {
   // base state
   DevBuf base64, base32, MX;
   // factors
-  DevBuf chains, segs, blk_field, blk_lm, blk_next;
+  DevBuf chains, segs, blk_field, blk_lm, blk_next, blk_fsrc;
   int nchains = 0, nblocks = 0, nsegs = 0;
-  DevBuf Sinv64, Lo64, H64, Phi64, Psi64, sr64, sc64, Rg64, Cg64;
-  DevBuf Sinv32, Lo32, H32, Phi32, Psi32, sr32, sc32, Rg32, Cg32;
+  DevBuf Sinv64, G64, H64, Phi64, Psi64, sr64, sc64, Rg64, Cg64;
+  DevBuf Sinv32, G32, H32, Phi32, Psi32, sr32, sc32, Rg32, Cg32;
   DevBuf wscan;  // scan work vectors, capacity vcap x nblocks x N complex doubles
   DevBuf Tinv64, tr64, tc64, Tinv32, tr32, tc32;
   // stage profiler: pairs of events recorded around launches while enabled
@@ -136,6 +138,14 @@ struct sc_plan {
     g.D = d_D.as<double>();
     g.D2 = d_D2.as<double>();
     g.D4 = d_D4.as<double>();
+    g.ET = d_ET.as<double>();
+    g.EDT = d_EDT.as<double>();
+    g.ED2T = d_ED2T.as<double>();
+    g.DT = d_DT.as<double>();
+    g.D2T = d_D2T.as<double>();
+    g.D4T = d_D4T.as<double>();
+    g.rtiles = d_rtiles.as<int2>();
+    g.nrtiles = nrtiles;
     return g;
   }
   sc::PhysParams pp() const {
@@ -325,10 +335,9 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
   T* ws = ws_ptr<T>(P);
   const T* tab = tab_ptr<T>(P);
   const WsLayout& w = P->wl;
-  long long n1 = (long long)nvec * g.Np * g.S;
   {
     Prof _p(P, SC_STAGE_RADIAL_PREP, s);
-    hipLaunchKernelGGL(sc::k_radial_prep<T>, dim3(nblk(n1, 256)), dim3(256), 0, s, dg, v, ldv, J, nvec, ws + w.Gs, ws + w.Gv);
+    hipLaunchKernelGGL(sc::k_radial_prep<T>, dim3(P->nrtiles, nvec), dim3(256), 0, s, dg, v, ldv, J, nvec, ws + w.Gs, ws + w.Gv);
   }
   HIPCHK(hipGetLastError());
   long long nt = gemm_tiles(P->h_syn, nvec);
@@ -379,19 +388,23 @@ constexpr int kSeg = 8;   // blocks per scan segment
 constexpr int kVG = 16;   // vectors per workgroup in the chain solves
 
 template <class F>
+size_t tsolve_smem(const sc::HostGrid& g) {
+  return sizeof(F) * ((size_t)g.N * g.N + (size_t)sc::kTV * (g.K + 1) * 2 * g.N);
+}
+
+template <class F>
 size_t scan_smem(int N) {
-  return sizeof(F) * 2 * ((size_t)N * N + 3 * (size_t)N * kVG);
+  return sizeof(F) * 2 * ((size_t)N * (N + 1) + 3 * (size_t)N * kVG);
 }
 
 // Implicit solve x = A^{-1} b with factors in precision F (all vectors in canonical FP64).
 template <class F>
 void implicit_solve(sc_plan* P, int nvec, const double* b, double* x, hipStream_t s) {
   sc::DevGrid dg = P->dg();
-  const int VG = kVG;
-  const int nvg = (nvec + VG - 1) / VG;
+  const int nvg = (nvec + kVG - 1) / kVG;
   bool d = std::is_same<F, double>::value;
   const F* Sinv = (const F*)(d ? P->Sinv64.p : P->Sinv32.p);
-  const F* Lo = (const F*)(d ? P->Lo64.p : P->Lo32.p);
+  const F* Gm = (const F*)(d ? P->G64.p : P->G32.p);
   const F* H = (const F*)(d ? P->H64.p : P->H32.p);
   const F* Phi = (const F*)(d ? P->Phi64.p : P->Phi32.p);
   const F* Psi = (const F*)(d ? P->Psi64.p : P->Psi32.p);
@@ -403,28 +416,34 @@ void implicit_solve(sc_plan* P, int nvec, const double* b, double* x, hipStream_
   const size_t smem = scan_smem<F>(P->hg.N);
   const sc::ChainMeta* ch = P->chains.as<sc::ChainMeta>();
   const sc::SegMeta* sg = P->segs.as<sc::SegMeta>();
+  const dim3 blk(sc::kSolveThreads);
   {
     Prof _p(P, SC_STAGE_CHAIN_SOLVE, s);
-    hipLaunchKernelGGL((sc::k_scan_fwd_local<F, kVG>), dim3(P->nsegs, nvg), dim3(256), smem, s, dg, nvec, sg,
-                       P->blk_field.as<int>(), P->blk_lm.as<int>(), Sinv, Lo, sr, scl, Rg, b, W);
+    hipLaunchKernelGGL((sc::k_cs_rhs<F, kVG>), dim3(P->nblocks, nvg), blk, smem, s, dg, nvec, P->blk_field.as<int>(),
+                       P->blk_lm.as<int>(), Sinv, sr, scl, Rg, b, W);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_scan_fwd_bound<F, kVG>), dim3(P->nchains, nvg), dim3(256), smem, s, dg, nvec, ch, sg, Phi, W);
+    hipLaunchKernelGGL((sc::k_cs_fwd_local<F, kVG>), dim3(P->nsegs, nvg), blk, smem, s, dg, nvec, sg, Gm, W);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_scan_bwd_local<F, kVG>), dim3(P->nsegs, nvg), dim3(256), smem, s, dg, nvec, ch, sg, Phi, H, W);
+    hipLaunchKernelGGL((sc::k_cs_fwd_bound<F, kVG>), dim3(P->nchains, nvg), blk, smem, s, dg, nvec, ch, sg, Phi, W);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_scan_bwd_bound<F, kVG>), dim3(P->nchains, nvg), dim3(256), smem, s, dg, nvec, ch, sg, Psi, W);
+    hipLaunchKernelGGL((sc::k_cs_fwd_fix<F, kVG>), dim3(P->nblocks, nvg), blk, smem, s, dg, nvec,
+                       P->blk_fsrc.as<int>(), Phi, W);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_scan_out<F, kVG>), dim3(P->nblocks, nvg), dim3(256), smem, s, dg, nvec,
-                       P->blk_field.as<int>(), P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const F*)W, x);
+    hipLaunchKernelGGL((sc::k_cs_bwd_local<F, kVG>), dim3(P->nsegs, nvg), blk, smem, s, dg, nvec, sg, H, W);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL((sc::k_cs_bwd_bound<F, kVG>), dim3(P->nchains, nvg), blk, smem, s, dg, nvec, ch, sg, Psi, W);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL((sc::k_cs_out<F, kVG>), dim3(P->nblocks, nvg), blk, smem, s, dg, nvec, P->blk_field.as<int>(),
+                       P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const F*)W, x);
     HIPCHK(hipGetLastError());
   }
   const F* Ti = (const F*)(d ? P->Tinv64.p : P->Tinv32.p);
   const F* tr = (const F*)(d ? P->tr64.p : P->tr32.p);
   const F* tc = (const F*)(d ? P->tc64.p : P->tc32.p);
-  long long nT = (long long)nvec * P->hg.S * P->hg.N;
   {
     Prof _p(P, SC_STAGE_T_SOLVE, s);
-    hipLaunchKernelGGL(sc::k_T_solve<F>, dim3(nblk(nT, 256)), dim3(256), 0, s, dg, nvec, Ti, tr, tc, b, x);
+    hipLaunchKernelGGL(sc::k_T_solve<F>, dim3(P->hg.L + 1, (nvec + sc::kTV - 1) / sc::kTV), dim3(256), tsolve_smem<F>(P->hg), s,
+                       dg, nvec, Ti, tr, tc, b, x);
     HIPCHK(hipGetLastError());
   }
 }
@@ -435,11 +454,10 @@ void refined_solve(sc_plan* P, int nvec, const double* b, double* x, int passes,
   implicit_solve<F>(P, nvec, b, x, s);
   sc::DevGrid dg = P->dg();
   long long n = (long long)nvec * P->n_real;
-  long long nres = (long long)nvec * 3 * P->hg.S * P->hg.N;
   for (int it = 0; it < passes; ++it) {
     {
       Prof _p(P, SC_STAGE_RESIDUAL, s);
-      hipLaunchKernelGGL(sc::k_residual64, dim3(nblk(nres, 256)), dim3(256), 0, s, dg, P->pp(), nvec, b, x,
+      hipLaunchKernelGGL(sc::k_residual64, dim3(P->hg.S, nvec), dim3(64), 0, s, dg, P->pp(), nvec, b, x,
                          P->rbuf.as<double>());
     }
     HIPCHK(hipGetLastError());
@@ -516,6 +534,25 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     upload(P->d_D, g.D);
     upload(P->d_D2, g.D2);
     upload(P->d_D4, g.D4);
+    auto transpose = [](const std::vector<double>& A, int rows, int cols) {
+      std::vector<double> T((size_t)rows * cols);
+      for (int i = 0; i < rows; ++i)
+        for (int j = 0; j < cols; ++j) T[(size_t)j * rows + i] = A[(size_t)i * cols + j];
+      return T;
+    };
+    upload(P->d_ET, transpose(g.E, g.Np, g.N));
+    upload(P->d_EDT, transpose(g.ED, g.Np, g.N));
+    upload(P->d_ED2T, transpose(g.ED2, g.Np, g.N));
+    upload(P->d_DT, transpose(g.D, g.N, g.N));
+    upload(P->d_D2T, transpose(g.D2, g.N, g.N));
+    upload(P->d_D4T, transpose(g.D4, g.N, g.N));
+    {
+      std::vector<int2> tiles;
+      for (int k = 0; k <= g.K; ++k)
+        for (int il = 0; il < g.nl[k]; il += sc::kRPT) tiles.push_back(make_int2(k, il));
+      upload(P->d_rtiles, tiles);
+      P->nrtiles = (int)tiles.size();
+    }
     build_tables(P.get());
     build_workspaces(P.get());
     const size_t smem64 = ring_smem<double>(g), smem32 = ring_smem<float>(g);
@@ -534,20 +571,31 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     {
       const size_t s64 = scan_smem<double>(g.N), s32 = scan_smem<float>(g.N);
       if (s64 > 160 * 1024) throw Fail{SC_ERR_ARG, "N too large for the chain solve"};
-      if (s64 > 64 * 1024) {
-        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_fwd_local<double, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s64));
-        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_fwd_bound<double, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s64));
-        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_bwd_local<double, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s64));
-        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_bwd_bound<double, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s64));
-        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_out<double, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s64));
-      }
-      if (s32 > 64 * 1024) {
-        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_fwd_local<float, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s32));
-        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_fwd_bound<float, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s32));
-        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_bwd_local<float, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s32));
-        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_bwd_bound<float, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s32));
-        HIPCHK(hipFuncSetAttribute((const void*)sc::k_scan_out<float, kVG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s32));
-      }
+      auto attr = [](const void* fn, size_t bytes) {
+        if (bytes > 64 * 1024) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+      };
+      attr((const void*)sc::k_cs_rhs<double, kVG>, s64);
+      attr((const void*)sc::k_cs_fwd_local<double, kVG>, s64);
+      attr((const void*)sc::k_cs_fwd_bound<double, kVG>, s64);
+      attr((const void*)sc::k_cs_fwd_fix<double, kVG>, s64);
+      attr((const void*)sc::k_cs_bwd_local<double, kVG>, s64);
+      attr((const void*)sc::k_cs_bwd_bound<double, kVG>, s64);
+      attr((const void*)sc::k_cs_out<double, kVG>, s64);
+      attr((const void*)sc::k_cs_rhs<float, kVG>, s32);
+      attr((const void*)sc::k_cs_fwd_local<float, kVG>, s32);
+      attr((const void*)sc::k_cs_fwd_bound<float, kVG>, s32);
+      attr((const void*)sc::k_cs_fwd_fix<float, kVG>, s32);
+      attr((const void*)sc::k_cs_bwd_local<float, kVG>, s32);
+      attr((const void*)sc::k_cs_bwd_bound<float, kVG>, s32);
+      attr((const void*)sc::k_cs_out<float, kVG>, s32);
+    }
+    {
+      const size_t t64 = tsolve_smem<double>(g), t32 = tsolve_smem<float>(g);
+      if (t64 > 160 * 1024) throw Fail{SC_ERR_ARG, "too many m for the temperature solve"};
+      if (t64 > 64 * 1024)
+        HIPCHK(hipFuncSetAttribute((const void*)sc::k_T_solve<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t64));
+      if (t32 > 64 * 1024)
+        HIPCHK(hipFuncSetAttribute((const void*)sc::k_T_solve<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t32));
     }
     // deterministic contents for slots the solves never write (e, f at l = 0)
     HIPCHK(hipMemset(P->xbuf.p, 0, P->xbuf.bytes));
@@ -611,7 +659,8 @@ int sc_factor(sc_plan* P, void* stream) {
     long long nb = 0;
     for (auto& c : ch) nb += c.n;
     const long long NN = (long long)N * N;
-    std::vector<double> Sinv(2 * nb * NN), Lo(2 * nb * NN), H(2 * nb * NN), Phi(2 * nb * NN), Psi(2 * nb * NN);
+    std::vector<double> Sinv(2 * nb * NN), Gm(2 * nb * NN), H(2 * nb * NN), Phi(2 * nb * NN), Psi(2 * nb * NN);
+    std::vector<int> bfsrc;
     std::vector<double> sr(nb * N), scv(nb * N), Rg(nb * N), Cg(nb * N);
     long long b = 0;
     auto put = [&](std::vector<double>& dst, const std::vector<sc::cplx>& src, long long bb, int i) {
@@ -631,8 +680,10 @@ int sc_factor(sc_plan* P, void* stream) {
         int p = i / kSeg;
         bool fixup = (p < nseg - 1) && (i % kSeg != 0);
         bnext.push_back(fixup ? (int)(meta.back().start + (p + 1) * kSeg) : -1);
+        bool ffix = (p > 0) && (i != std::min((p + 1) * kSeg, c.n) - 1);
+        bfsrc.push_back(ffix ? (int)(meta.back().start + p * kSeg - 1) : -1);
         put(Sinv, c.Sinv, b, i);
-        put(Lo, c.Lo, b, i);
+        put(Gm, c.G, b, i);
         put(H, c.H, b, i);
         put(Phi, c.Phi, b, i);
         put(Psi, c.Psi, b, i);
@@ -660,8 +711,9 @@ int sc_factor(sc_plan* P, void* stream) {
     upload(P->blk_field, bf);
     upload(P->blk_lm, blm);
     upload(P->blk_next, bnext);
+    upload(P->blk_fsrc, bfsrc);
     up2(P->Sinv64, P->Sinv32, Sinv);
-    up2(P->Lo64, P->Lo32, Lo);
+    up2(P->G64, P->G32, Gm);
     up2(P->H64, P->H32, H);
     up2(P->Phi64, P->Phi32, Phi);
     up2(P->Psi64, P->Psi32, Psi);

@@ -36,10 +36,40 @@ struct DevGrid {
   const double* D;    // [N][N]
   const double* D2;
   const double* D4;
+  // transposed copies ([column][row]) for coalesced row-parallel products
+  const double* ET;   // [N][Np]: E^T
+  const double* EDT;
+  const double* ED2T;
+  const double* DT;   // [N][N]
+  const double* D2T;
+  const double* D4T;
+  const int2* rtiles; // radial-prep tiles: (k, first l-m)
+  int nrtiles;
 };
 
 struct PhysParams {
   double Ek, Ra, Pr, dt, ro;
+};
+
+// Matrix-core (MFMA) 16x16x4 tile per wavefront: D[16][16] += A[16][4] B[4][16].
+// Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; element q of its 4-vector holds
+// D[out_row(l, q)][l % 16], with out_row = 4 (l / 16) + q for FP32 and l / 16 + 4 q for FP64
+// (both checked on gfx950 with a probe kernel).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef f32x4 acc_t;
+  static __device__ inline acc_t step(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ inline int out_row(int lane, int q) { return 4 * (lane >> 4) + q; }
+};
+template <>
+struct Mfma<double> {
+  typedef f64x4 acc_t;
+  static __device__ inline acc_t step(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ inline int out_row(int lane, int q) { return (lane >> 4) + 4 * q; }
 };
 
 // ------------------------------------------------------------------------------------------
@@ -48,83 +78,85 @@ struct PhysParams {
 //   Su = f'/r, Tu = e/r, Sw = e'/r, Tw = -(f'' - lam f/r^2)/r, ST = T/r  (vector synthesis)
 // evaluated at the N_p nodes as diag(r^-k) E D^j u, in FP64, stored in precision T.
 // Input cleaning: Im at m = 0, e/f at l = 0 and the phase slot J are read as 0.
+// One workgroup per (tile of up to 16 consecutive l at one m, vector); the tile's e, f, T
+// profiles are staged in LDS with coalesced loads.
+constexpr int kRPT = 16;  // l per radial-prep tile
+
 template <class T>
-__global__ void k_radial_prep(DevGrid g, const double* __restrict__ v, long long ldv, long long J,
-                              int nvec, T* __restrict__ Gs, T* __restrict__ Gv) {
-  long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long total = (long long)nvec * g.Np * g.S;
-  if (tid >= total) return;
-  int lm = (int)(tid % g.S);
-  long long t2 = tid / g.S;
-  int rp = (int)(t2 % g.Np);
-  int vec = (int)(t2 / g.Np);
-  int k = g.lm_k[lm], l = g.lm_l[lm];
-  int m = k * g.m0;
-  const int N = g.N;
+__global__ void __launch_bounds__(256) k_radial_prep(DevGrid g, const double* __restrict__ v, long long ldv,
+                                                     long long J, int nvec, T* __restrict__ Gs, T* __restrict__ Gv) {
+  const int N = g.N, Np = g.Np;
+  const int XS = 2 * N + 2;  // padded row of one profile (Re/Im interleaved)
+  __shared__ double xs[3 * kRPT * (2 * 64 + 2)];
+  const int2 tl = g.rtiles[blockIdx.x];
+  const int vec = blockIdx.y;
+  const int k = tl.x, il0 = tl.y;
+  const int m = k * g.m0, nl = g.L - m + 1;
+  const int nt = min(kRPT, nl - il0);
+  const int lm0 = g.lmbase[k] + il0;
   const double* vb = v + (long long)vec * ldv;
-  double acc[7][2];
-#pragma unroll
-  for (int a = 0; a < 7; ++a) acc[a][0] = acc[a][1] = 0.0;
-  const double* Er = g.E + (long long)rp * N;
-  const double* EDr = g.ED + (long long)rp * N;
-  const double* ED2r = g.ED2 + (long long)rp * N;
-  long long base_e = 2LL * ((long long)N * (0LL * g.S + lm));
-  long long base_f = 2LL * ((long long)N * (1LL * g.S + lm));
-  long long base_t = 2LL * ((long long)N * (2LL * g.S + lm));
-  bool ef_ok = (l > 0);
-  for (int j = 0; j < N; ++j) {
-    double e0 = 0, e1 = 0, f0 = 0, f1 = 0, t0, t1;
-    long long ie = base_e + 2 * j, jf = base_f + 2 * j, it = base_t + 2 * j;
-    if (ef_ok) {
-      e0 = (ie == J) ? 0.0 : vb[ie];
-      e1 = (k == 0 || ie + 1 == J) ? 0.0 : vb[ie + 1];
-      f0 = (jf == J) ? 0.0 : vb[jf];
-      f1 = (k == 0 || jf + 1 == J) ? 0.0 : vb[jf + 1];
-    }
-    t0 = (it == J) ? 0.0 : vb[it];
-    t1 = (k == 0 || it + 1 == J) ? 0.0 : vb[it + 1];
-    double E0 = Er[j], E1 = EDr[j], E2 = ED2r[j];
-    acc[0][0] += E0 * f0; acc[0][1] += E0 * f1;   // E f
-    acc[1][0] += E1 * f0; acc[1][1] += E1 * f1;   // E D f
-    acc[2][0] += E2 * f0; acc[2][1] += E2 * f1;   // E D^2 f
-    acc[3][0] += E0 * e0; acc[3][1] += E0 * e1;   // E e
-    acc[4][0] += E1 * e0; acc[4][1] += E1 * e1;   // E D e
-    acc[5][0] += E0 * t0; acc[5][1] += E0 * t1;   // E T
-    acc[6][0] += E1 * t0; acc[6][1] += E1 * t1;   // E D T
+  for (int idx = threadIdx.x; idx < 3 * nt * 2 * N; idx += blockDim.x) {
+    int c = idx % (2 * N);
+    int t = (idx / (2 * N)) % nt;
+    int f = idx / (2 * N * nt);
+    long long o = 2LL * (long long)N * ((long long)f * g.S + lm0 + t) + c;
+    int l = m + il0 + t;
+    double val = vb[o];
+    if (o == J || ((c & 1) && k == 0) || (f < 2 && l == 0)) val = 0.0;
+    xs[(f * kRPT + t) * XS + c] = val;
   }
-  double lam = (double)l * (l + 1);
-  double ri = 1.0 / g.rp[rp];
-  double ri2 = ri * ri;
-  int nl = g.L - m + 1;
-  int il = l - m;
-  long long rowS = ((long long)vec * g.Np + rp) * 6;
-  long long rowV = ((long long)vec * g.Np + rp) * 10;
-  long long offS = 6LL * g.Np * g.vcap * g.lmbase[k];  // block k of Gs (rows x nl)
-  long long offV = 10LL * g.Np * g.vcap * g.lmbase[k];
-  T* gs = Gs + offS + rowS * nl + il;
-  T* gv = Gv + offV + rowV * nl + il;
-  for (int c = 0; c < 2; ++c) {
-    gs[(0 + c) * nl] = (T)(lam * ri2 * acc[0][c]);                 // ur
-    gs[(2 + c) * nl] = (T)(lam * ri2 * acc[3][c]);                 // wr
-    gs[(4 + c) * nl] = (T)(acc[6][c]);                             // dT
-    gv[(0 + c) * nl] = (T)(acc[1][c] * ri);                        // Su
-    gv[(2 + c) * nl] = (T)(acc[3][c] * ri);                        // Tu
-    gv[(4 + c) * nl] = (T)(acc[4][c] * ri);                        // Sw
-    gv[(6 + c) * nl] = (T)(-acc[2][c] * ri + lam * ri2 * ri * acc[0][c]);  // Tw
-    gv[(8 + c) * nl] = (T)(acc[5][c] * ri);                        // ST
+  __syncthreads();
+  const long long offS = 6LL * Np * g.vcap * g.lmbase[k];
+  const long long offV = 10LL * Np * g.vcap * g.lmbase[k];
+  for (int idx = threadIdx.x; idx < Np * kRPT * 2; idx += blockDim.x) {
+    int t = idx % kRPT;
+    int ri = (idx / kRPT) & 1;
+    int rp = idx / (2 * kRPT);
+    if (t >= nt) continue;
+    double acc[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) acc[a] = 0.0;
+    const double* xe = xs + (0 * kRPT + t) * XS + ri;
+    const double* xf = xs + (1 * kRPT + t) * XS + ri;
+    const double* xt = xs + (2 * kRPT + t) * XS + ri;
+    for (int jj = 0; jj < N; ++jj) {
+      double E0 = g.ET[(long long)jj * Np + rp], E1 = g.EDT[(long long)jj * Np + rp], E2 = g.ED2T[(long long)jj * Np + rp];
+      double e = xe[2 * jj], f = xf[2 * jj], tt = xt[2 * jj];
+      acc[0] += E0 * f;
+      acc[1] += E1 * f;
+      acc[2] += E2 * f;
+      acc[3] += E0 * e;
+      acc[4] += E1 * e;
+      acc[5] += E0 * tt;
+      acc[6] += E1 * tt;
+    }
+    const int il = il0 + t, l = m + il;
+    const double lam = (double)l * (l + 1);
+    const double ri1 = 1.0 / g.rp[rp], ri2 = ri1 * ri1;
+    T* gs = Gs + offS + (((long long)vec * Np + rp) * 6 + ri) * nl + il;
+    T* gv = Gv + offV + (((long long)vec * Np + rp) * 10 + ri) * nl + il;
+    gs[0 * nl] = (T)(lam * ri2 * acc[0]);                        // ur
+    gs[2 * nl] = (T)(lam * ri2 * acc[3]);                        // wr
+    gs[4 * nl] = (T)(acc[6]);                                    // dT
+    gv[0 * nl] = (T)(acc[1] * ri1);                              // Su
+    gv[2 * nl] = (T)(acc[3] * ri1);                              // Tu
+    gv[4 * nl] = (T)(acc[4] * ri1);                              // Sw
+    gv[6 * nl] = (T)(-acc[2] * ri1 + lam * ri2 * ri1 * acc[0]);  // Tw
+    gv[8 * nl] = (T)(acc[5] * ri1);                              // ST
   }
 }
 
 // ------------------------------------------------------------------------------------------
-// K2/K6: batched contractions C[i][j] = sum_k A[i][k] B[j][k], 64x64 tiles, LDS-staged.
+// K2/K6: batched contractions C[i][j] = sum_k A[i][k] B[j][k] on the matrix cores.
+// 64 x 64 output tile per workgroup (4 wavefronts, 32 x 32 each as 2 x 2 MFMA tiles),
+// k staged through LDS 16 at a time.  Problems of one launch are enumerated tile by tile.
 template <class T>
 __global__ void __launch_bounds__(256) k_gemm_batched(const GemmProb* __restrict__ probs, int nprob, int nvec,
                                                       const T* __restrict__ ws_in, const T* __restrict__ tab,
                                                       T* __restrict__ ws_out) {
-  constexpr int BM = 64, BN = 64, BK = 16;
-  __shared__ T As[BK][BM + 1];
-  __shared__ T Bs[BK][BN + 1];
-  // locate this tile's problem
+  constexpr int BM = 64, BN = 64, BK = 16, LDK = BK + 1;
+  __shared__ T As[BM * LDK];
+  __shared__ T Bs[BN * LDK];
   int tile = blockIdx.x;
   int p = 0;
   GemmProb pr;
@@ -146,57 +178,53 @@ __global__ void __launch_bounds__(256) k_gemm_batched(const GemmProb* __restrict
   const T* A = ws_in + pr.a_off;
   const T* B = tab + pr.b_off;
   T* C = ws_out + pr.c_off;
-  const int tid = threadIdx.x;
-  const int tx = tid % 16, ty = tid / 16;  // 16 x 16 threads, 4 x 4 outputs each
-  T acc[4][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;  // wavefront's 32 x 32 sub-tile
+  typename Mfma<T>::acc_t acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[x][y][q] = (T)0;
   const int i0 = tm * BM, j0 = tn * BN;
+  const int lr = tid / 4, lk = (tid % 4) * 4;  // loader: row, first k
   for (int k0 = 0; k0 < K; k0 += BK) {
-    // load A tile: 64 rows x 16 k; thread -> row tid/4, k (tid%4)*4 .. +3
     {
-      int r = tid / 4, kk = (tid % 4) * 4;
-      int gi = i0 + r;
+      const int gi = i0 + lr, gj = j0 + lr;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        int gk = k0 + kk + q;
-        As[kk + q][r] = (gi < M && gk < K) ? A[(long long)gi * pr.lda + gk] : (T)0;
-      }
-      int gj = j0 + r;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        int gk = k0 + kk + q;
-        Bs[kk + q][r] = (gj < N && gk < K) ? B[(long long)gj * pr.ldb + gk] : (T)0;
+        const int gk = k0 + lk + q;
+        As[lr * LDK + lk + q] = (gi < M && gk < K) ? A[(long long)gi * pr.lda + gk] : (T)0;
+        Bs[lr * LDK + lk + q] = (gj < N && gk < K) ? B[(long long)gj * pr.ldb + gk] : (T)0;
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      T a[4], b[4];
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      T a[2], b[2];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = As[kk][ty + 16 * q];
-        b[q] = Bs[kk][tx + 16 * q];
-      }
+      for (int x = 0; x < 2; ++x) a[x] = As[(wm + x * 16 + (lane & 15)) * LDK + kk];
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int y = 0; y < 2; ++y) b[y] = Bs[(wn + y * 16 + (lane & 15)) * LDK + kk];
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<T>::step(a[x], b[y], acc[x][y]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    int gi = i0 + ty + 16 * x;
-    if (gi >= M) continue;
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      int gj = j0 + tx + 16 * y;
-      if (gj < N) C[(long long)gi * pr.ldc + gj] = acc[x][y];
-    }
-  }
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gi = i0 + wm + x * 16 + Mfma<T>::out_row(lane, q);
+        const int gj = j0 + wn + y * 16 + (lane & 15);
+        if (gi < M && gj < N) C[(long long)gi * pr.ldc + gj] = acc[x][y][q];
+      }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -527,13 +555,16 @@ __global__ void k_apply_M(DevGrid g, PhysParams ph, const double* __restrict__ X
 
 // ------------------------------------------------------------------------------------------
 // K8: block-tridiagonal solve along each (m, class) chain with the equilibrated block LU,
-// organised as a segmented scan so that the sequential part is short:
-//   forward  z_i = D_i (t_i - Lo_i z_{i-1}),  t = Rg b,  D_i = diag(sc_i) Shat_i^{-1} diag(sr_i)
-//   backward x_i = z_i - H_i x_{i+1},         result Cg x
-// Inside a segment [a, e]: z_i = zeta_i + Phi_i z_{a-1}, x_i = xi_i + Psi_i x_{e+1}, where zeta
-// and xi are the local recurrences started from zero.  Five launches: local forward (per
-// segment), forward boundary pass (per chain), local backward with the forward fix-up (per
-// segment), backward boundary pass (per chain), final fix-up and output (per block).
+// organised as a segmented scan so that the sequential part is short.  In scaled space
+// (t = Rg b, result x = Cg x~), with D_i = S_i^{-1} = diag(sc_i) Shat_i^{-1} diag(sr_i):
+//   forward  z_i = c_i - G_i z_{i-1},   c_i = D_i t_i,  G_i = D_i Lo_i
+//   backward x_i = z_i - H_i x_{i+1}
+// Inside a segment [a, e]: z_i = zeta_i + Phi_i z_{a-1}, x_i = xi_i + Psi_i x_{e+1}, with zeta
+// and xi the local recurrences started from zero.  Launches: c (all blocks), local forward
+// (per segment), forward boundary pass (per chain), forward fix-up (all blocks), local
+// backward (per segment), backward boundary pass (per chain), backward fix-up and output
+// (all blocks).  The sequential loops prefetch the next block into registers while the
+// current one is applied from LDS.
 // Work vectors live in W[(block*N + j)*vcap + vec] (complex, precision F, scaled space).
 struct ChainMeta {
   int start, n, k, first_seg, nseg, pad0, pad1, pad2;
@@ -547,257 +578,412 @@ struct cpx {
   F re, im;
 };
 
-// Stage an N x N complex block (row-major, interleaved) into LDS with coalesced loads.
-template <class F>
-__device__ inline void stage_block(const F* __restrict__ gmat, cpx<F>* sm, int N) {
-  const cpx<F>* src = reinterpret_cast<const cpx<F>*>(gmat);
-  for (int i = threadIdx.x; i < N * N; i += blockDim.x) sm[i] = src[i];
-}
+constexpr int kSolveThreads = 256;
+constexpr int kPF = 16;   // complex block entries per thread: ceil(64 * 64 / 256)
+constexpr int kVPF = 4;   // complex vector entries per thread: ceil(64 * 16 / 256)
 
-// acc(j, vv) += sign * sum_q M[j][q] v[q][vv] for the thread's own (j, vv) entries.
+// One N x N complex block in registers (coalesced load), then into LDS with padded rows.
+// Re and Im are kept in separate arrays so the compiler keeps them in registers.
+template <class F>
+struct BlkRegs {
+  F re[kPF], im[kPF];
+  int off[kPF];  // LDS slot of each register entry (row * (N+1) + col), -1 if unused
+  __device__ inline void init(int N) {
+#pragma unroll
+    for (int u = 0; u < kPF; ++u) {
+      int i = threadIdx.x + u * kSolveThreads;
+      off[u] = (i < N * N) ? (i / N) * (N + 1) + (i % N) : -1;
+    }
+  }
+  __device__ inline void load(const F* __restrict__ gmat, int N) {
+#pragma unroll
+    for (int u = 0; u < kPF; ++u) {
+      int i = threadIdx.x + u * kSolveThreads;
+      if (i < N * N) {
+        re[u] = gmat[2 * i];
+        im[u] = gmat[2 * i + 1];
+      }
+    }
+  }
+  __device__ inline void to_lds(cpx<F>* sm, int N) const {
+#pragma unroll
+    for (int u = 0; u < kPF; ++u)
+      if (off[u] >= 0) {
+        sm[off[u]].re = re[u];
+        sm[off[u]].im = im[u];
+      }
+  }
+};
+
+// One work vector group W[b][j][v0 .. v0+nv) in registers.
+template <class F, int VG>
+struct VecRegs {
+  F re[kVPF], im[kVPF];
+  __device__ inline void load(const F* __restrict__ W, int vcap, int b, int v0, int N, int nv) {
+#pragma unroll
+    for (int u = 0; u < kVPF; ++u) {
+      int idx = threadIdx.x + u * kSolveThreads;
+      int vv = idx % VG, j = idx / VG;
+      if (j < N && vv < nv) {
+        long long o = 2 * (((long long)b * N + j) * vcap + v0 + vv);
+        re[u] = W[o];
+        im[u] = W[o + 1];
+      }
+    }
+  }
+  __device__ inline void to_lds(cpx<F>* dst, int N) const {
+#pragma unroll
+    for (int u = 0; u < kVPF; ++u) {
+      int idx = threadIdx.x + u * kSolveThreads;
+      if (idx < N * VG) {
+        dst[idx].re = re[u];
+        dst[idx].im = im[u];
+      }
+    }
+  }
+};
+
+// acc(j, vv) += sign * sum_q M[j][q] v[q][vv] (M in LDS with row stride N+1) for the
+// thread's own entries idx = j * VG + vv, idx = threadIdx.x + 256 u.
 template <class F, int VG>
 __device__ inline void mv_acc(const cpx<F>* M, const cpx<F>* v, cpx<F>* acc, int N, int nv, F sign) {
-  for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) {
-    int vv = idx % VG, j = idx / VG;
+  for (int idx = threadIdx.x; idx < N * VG; idx += kSolveThreads) {
+    const int vv = idx % VG, j = idx / VG;
     if (vv >= nv) continue;
     F ar = 0, ai = 0;
-    const cpx<F>* Mr = M + j * N;
+    const cpx<F>* Mr = M + j * (N + 1);
+#pragma unroll 4
     for (int q = 0; q < N; ++q) {
-      cpx<F> m = Mr[q], x = v[q * VG + vv];
+      const cpx<F> m = Mr[q], x = v[q * VG + vv];
       ar += m.re * x.re - m.im * x.im;
       ai += m.re * x.im + m.im * x.re;
     }
-    acc[j * VG + vv].re += sign * ar;
-    acc[j * VG + vv].im += sign * ai;
-  }
-}
-
-template <class F, int VG>
-__device__ inline void load_w(const F* __restrict__ W, int vcap, int b, int v0, cpx<F>* dst, int N, int nv) {
-  const cpx<F>* src = reinterpret_cast<const cpx<F>*>(W);
-  for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) {
-    int vv = idx % VG, j = idx / VG;
-    if (vv < nv) dst[idx] = src[((long long)b * N + j) * vcap + v0 + vv];
+    acc[idx].re += sign * ar;
+    acc[idx].im += sign * ai;
   }
 }
 
 template <class F, int VG>
 __device__ inline void store_w(F* __restrict__ W, int vcap, int b, int v0, const cpx<F>* srcv, int N, int nv) {
   cpx<F>* dst = reinterpret_cast<cpx<F>*>(W);
-  for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < N * VG; idx += kSolveThreads) {
     int vv = idx % VG, j = idx / VG;
     if (vv < nv) dst[((long long)b * N + j) * vcap + v0 + vv] = srcv[idx];
   }
 }
 
 template <class F, int VG>
-__global__ void __launch_bounds__(256) k_scan_fwd_local(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
-                                                        const int* __restrict__ blk_field, const int* __restrict__ blk_lm,
-                                                        const F* __restrict__ Sinv, const F* __restrict__ Lo,
-                                                        const F* __restrict__ sr, const F* __restrict__ scl,
-                                                        const F* __restrict__ Rg, const double* __restrict__ bvec,
-                                                        F* __restrict__ W) {
+__device__ inline void load_w(const F* __restrict__ W, int vcap, int b, int v0, cpx<F>* dst, int N, int nv) {
+  const cpx<F>* src = reinterpret_cast<const cpx<F>*>(W);
+  for (int idx = threadIdx.x; idx < N * VG; idx += kSolveThreads) {
+    int vv = idx % VG, j = idx / VG;
+    if (vv < nv) dst[idx] = src[((long long)b * N + j) * vcap + v0 + vv];
+  }
+}
+
+// LDS carve-up shared by the solve kernels: one padded block and three vector groups.
+template <class F, int VG>
+struct SolveLds {
+  cpx<F>* M;
+  cpx<F>* a;
+  cpx<F>* b;
+  cpx<F>* c;
+  __device__ SolveLds(unsigned char* raw, int N) {
+    M = reinterpret_cast<cpx<F>*>(raw);
+    a = M + N * (N + 1);
+    b = a + N * VG;
+    c = b + N * VG;
+  }
+};
+
+// c_i = D_i t_i for every block (parallel over blocks).
+template <class F, int VG>
+__global__ void __launch_bounds__(256, 1) k_cs_rhs(DevGrid g, int nvec, const int* __restrict__ blk_field,
+                                                const int* __restrict__ blk_lm, const F* __restrict__ Sinv,
+                                                const F* __restrict__ sr, const F* __restrict__ scl,
+                                                const F* __restrict__ Rg, const double* __restrict__ bvec,
+                                                F* __restrict__ W) {
   extern __shared__ unsigned char smem_raw[];
   const int N = g.N;
-  cpx<F>* Ms = reinterpret_cast<cpx<F>*>(smem_raw);
-  cpx<F>* prev = Ms + N * N;
-  cpx<F>* tmp = prev + N * VG;
+  SolveLds<F, VG> L(smem_raw, N);
+  const int blk = blockIdx.x, v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
+  const long long ld = 6LL * N * g.S;
+  const long long o = 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + blk_lm[blk]));
+  BlkRegs<F> R;
+  R.init(N);
+  R.load(Sinv + 2LL * N * N * blk, N);
+  for (int idx = threadIdx.x; idx < N * VG; idx += kSolveThreads) {
+    int vv = idx % VG, j = idx / VG;
+    L.b[idx].re = L.b[idx].im = 0;
+    if (vv >= nv) continue;
+    const double* bp = bvec + (long long)(v0 + vv) * ld + o + 2 * j;
+    F s = Rg[(long long)blk * N + j] * sr[(long long)blk * N + j];
+    L.a[idx].re = s * (F)bp[0];
+    L.a[idx].im = s * (F)bp[1];
+  }
+  R.to_lds(L.M, N);
+  __syncthreads();
+  mv_acc<F, VG>(L.M, L.a, L.b, N, nv, (F)1);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < N * VG; idx += kSolveThreads) {
+    F c = scl[(long long)blk * N + idx / VG];
+    L.b[idx].re *= c;
+    L.b[idx].im *= c;
+  }
+  store_w<F, VG>(W, g.vcap, blk, v0, L.b, N, nv);
+}
+
+// Local forward recurrence per segment: zeta_a = c_a, zeta_i = c_i - G_i zeta_{i-1}.
+template <class F, int VG>
+__global__ void __launch_bounds__(256, 1) k_cs_fwd_local(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
+                                                      const F* __restrict__ Gm, F* __restrict__ W) {
+  extern __shared__ unsigned char smem_raw[];
+  const int N = g.N;
+  SolveLds<F, VG> L(smem_raw, N);
   const SegMeta sg = segs[blockIdx.x];
   const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
-  const long long NN2 = 2LL * N * N, ld = 6LL * N * g.S;
-  for (int i = 0; i < sg.len; ++i) {
+  const long long NN2 = 2LL * N * N;
+  if (sg.len <= 1) return;
+  cpx<F>* prev = L.a;
+  cpx<F>* cur = L.b;
+  load_w<F, VG>(W, g.vcap, sg.first_block, v0, prev, N, nv);
+  BlkRegs<F> R;
+  R.init(N);
+  VecRegs<F, VG> V;
+  R.load(Gm + NN2 * (sg.first_block + 1), N);
+  V.load(W, g.vcap, sg.first_block + 1, v0, N, nv);
+  for (int i = 1; i < sg.len; ++i) {
     const int b = sg.first_block + i;
-    const long long o = 2LL * ((long long)N * ((long long)blk_field[b] * g.S + blk_lm[b]));
+    R.to_lds(L.M, N);
+    V.to_lds(cur, N);
     __syncthreads();
-    for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) {
-      int vv = idx % VG, j = idx / VG;
-      if (vv >= nv) continue;
-      const double* bp = bvec + (long long)(v0 + vv) * ld + o + 2 * j;
-      F rg = Rg[(long long)b * N + j];
-      tmp[idx].re = rg * (F)bp[0];
-      tmp[idx].im = rg * (F)bp[1];
+    if (i + 1 < sg.len) {
+      R.load(Gm + NN2 * (b + 1), N);
+      V.load(W, g.vcap, b + 1, v0, N, nv);
     }
-    if (i > 0) {
-      stage_block(Lo + NN2 * b, Ms, N);
-      __syncthreads();
-      mv_acc<F, VG>(Ms, prev, tmp, N, nv, (F)-1);
-    }
-    for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) {
-      int j = idx / VG;
-      F s = sr[(long long)b * N + j];
-      tmp[idx].re *= s;
-      tmp[idx].im *= s;
-    }
+    mv_acc<F, VG>(L.M, prev, cur, N, nv, (F)-1);
     __syncthreads();
-    stage_block(Sinv + NN2 * b, Ms, N);
-    for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) prev[idx].re = prev[idx].im = 0;
-    __syncthreads();
-    mv_acc<F, VG>(Ms, tmp, prev, N, nv, (F)1);
-    for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) {
-      int j = idx / VG;
-      F c = scl[(long long)b * N + j];
-      prev[idx].re *= c;
-      prev[idx].im *= c;
-    }
-    __syncthreads();
-    store_w<F, VG>(W, g.vcap, b, v0, prev, N, nv);
+    store_w<F, VG>(W, g.vcap, b, v0, cur, N, nv);
+    cpx<F>* t = prev;
+    prev = cur;
+    cur = t;
   }
 }
 
-// z at the end of each segment: z_e(p) = zeta_e(p) + Phi_e(p) z_e(p-1), sequential over p.
+// Boundary pass of the forward recurrence: z_e(p) = zeta_e(p) + Phi_e(p) z_e(p-1).
 template <class F, int VG>
-__global__ void __launch_bounds__(256) k_scan_fwd_bound(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
-                                                        const SegMeta* __restrict__ segs, const F* __restrict__ Phi,
-                                                        F* __restrict__ W) {
+__global__ void __launch_bounds__(256, 1) k_cs_fwd_bound(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
+                                                      const SegMeta* __restrict__ segs, const F* __restrict__ Phi,
+                                                      F* __restrict__ W) {
   extern __shared__ unsigned char smem_raw[];
   const int N = g.N;
-  cpx<F>* Ms = reinterpret_cast<cpx<F>*>(smem_raw);
-  cpx<F>* zb = Ms + N * N;
-  cpx<F>* tmp = zb + N * VG;
+  SolveLds<F, VG> L(smem_raw, N);
   const ChainMeta ch = chains[blockIdx.x];
   const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
   if (ch.nseg <= 1) return;
   const long long NN2 = 2LL * N * N;
-  SegMeta s0 = segs[ch.first_seg];
-  load_w<F, VG>(W, g.vcap, s0.first_block + s0.len - 1, v0, zb, N, nv);
+  auto seg_end = [&](int p) {
+    SegMeta s_ = segs[ch.first_seg + p];
+    return s_.first_block + s_.len - 1;
+  };
+  cpx<F>* prev = L.a;
+  cpx<F>* cur = L.b;
+  load_w<F, VG>(W, g.vcap, seg_end(0), v0, prev, N, nv);
+  BlkRegs<F> R;
+  R.init(N);
+  VecRegs<F, VG> V;
+  R.load(Phi + NN2 * seg_end(1), N);
+  V.load(W, g.vcap, seg_end(1), v0, N, nv);
   for (int p = 1; p < ch.nseg; ++p) {
-    SegMeta sp = segs[ch.first_seg + p];
-    int e = sp.first_block + sp.len - 1;
+    const int e = seg_end(p);
+    R.to_lds(L.M, N);
+    V.to_lds(cur, N);
     __syncthreads();
-    load_w<F, VG>(W, g.vcap, e, v0, tmp, N, nv);
-    stage_block(Phi + NN2 * e, Ms, N);
+    if (p + 1 < ch.nseg) {
+      R.load(Phi + NN2 * seg_end(p + 1), N);
+      V.load(W, g.vcap, seg_end(p + 1), v0, N, nv);
+    }
+    mv_acc<F, VG>(L.M, prev, cur, N, nv, (F)1);
     __syncthreads();
-    mv_acc<F, VG>(Ms, zb, tmp, N, nv, (F)1);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) zb[idx] = tmp[idx];
-    store_w<F, VG>(W, g.vcap, e, v0, tmp, N, nv);
+    store_w<F, VG>(W, g.vcap, e, v0, cur, N, nv);
+    cpx<F>* t = prev;
+    prev = cur;
+    cur = t;
   }
 }
 
-// Per segment, top-down: z_i = zeta_i + Phi_i z_{a-1} (segments after the first), then the
-// local backward recurrence xi_i = z_i - H_i xi_{i+1} started from xi_e = z_e.
+// Forward fix-up inside segments after the first: z_i = zeta_i + Phi_i z_{a-1} (per block;
+// src[b] = a-1, or -1 when block b needs no fix-up).
 template <class F, int VG>
-__global__ void __launch_bounds__(256) k_scan_bwd_local(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
-                                                        const SegMeta* __restrict__ segs, const F* __restrict__ Phi,
-                                                        const F* __restrict__ H, F* __restrict__ W) {
+__global__ void __launch_bounds__(256, 1) k_cs_fwd_fix(DevGrid g, int nvec, const int* __restrict__ src,
+                                                    const F* __restrict__ Phi, F* __restrict__ W) {
   extern __shared__ unsigned char smem_raw[];
   const int N = g.N;
-  cpx<F>* Ms = reinterpret_cast<cpx<F>*>(smem_raw);
-  cpx<F>* prev = Ms + N * N;
-  cpx<F>* tmp = prev + N * VG;
-  cpx<F>* zin = tmp + N * VG;
+  const int blk = blockIdx.x;
+  const int sb = src[blk];
+  if (sb < 0) return;
+  SolveLds<F, VG> L(smem_raw, N);
+  const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
+  BlkRegs<F> R;
+  R.init(N);
+  R.load(Phi + 2LL * N * N * blk, N);
+  load_w<F, VG>(W, g.vcap, sb, v0, L.a, N, nv);
+  load_w<F, VG>(W, g.vcap, blk, v0, L.b, N, nv);
+  R.to_lds(L.M, N);
+  __syncthreads();
+  mv_acc<F, VG>(L.M, L.a, L.b, N, nv, (F)1);
+  __syncthreads();
+  store_w<F, VG>(W, g.vcap, blk, v0, L.b, N, nv);
+}
+
+// Local backward recurrence per segment: xi_e = z_e, xi_i = z_i - H_i xi_{i+1}.
+template <class F, int VG>
+__global__ void __launch_bounds__(256, 1) k_cs_bwd_local(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
+                                                      const F* __restrict__ H, F* __restrict__ W) {
+  extern __shared__ unsigned char smem_raw[];
+  const int N = g.N;
+  SolveLds<F, VG> L(smem_raw, N);
   const SegMeta sg = segs[blockIdx.x];
   const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
   const long long NN2 = 2LL * N * N;
+  if (sg.len <= 1) return;
   const int e = sg.first_block + sg.len - 1;
-  const bool fix = sg.pidx > 0;
-  if (fix) load_w<F, VG>(W, g.vcap, sg.first_block - 1, v0, zin, N, nv);  // z_{a-1}: end of previous segment
-  load_w<F, VG>(W, g.vcap, e, v0, prev, N, nv);                               // xi_e = z_e
+  cpx<F>* prev = L.a;
+  cpx<F>* cur = L.b;
+  load_w<F, VG>(W, g.vcap, e, v0, prev, N, nv);
+  BlkRegs<F> R;
+  R.init(N);
+  VecRegs<F, VG> V;
+  R.load(H + NN2 * (e - 1), N);
+  V.load(W, g.vcap, e - 1, v0, N, nv);
   for (int b = e - 1; b >= sg.first_block; --b) {
+    R.to_lds(L.M, N);
+    V.to_lds(cur, N);
     __syncthreads();
-    load_w<F, VG>(W, g.vcap, b, v0, tmp, N, nv);
-    if (fix) {
-      stage_block(Phi + NN2 * b, Ms, N);
-      __syncthreads();
-      mv_acc<F, VG>(Ms, zin, tmp, N, nv, (F)1);
-      __syncthreads();
+    if (b - 1 >= sg.first_block) {
+      R.load(H + NN2 * (b - 1), N);
+      V.load(W, g.vcap, b - 1, v0, N, nv);
     }
-    stage_block(H + NN2 * b, Ms, N);
+    mv_acc<F, VG>(L.M, prev, cur, N, nv, (F)-1);
     __syncthreads();
-    mv_acc<F, VG>(Ms, prev, tmp, N, nv, (F)-1);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) prev[idx] = tmp[idx];
-    store_w<F, VG>(W, g.vcap, b, v0, tmp, N, nv);
+    store_w<F, VG>(W, g.vcap, b, v0, cur, N, nv);
+    cpx<F>* t = prev;
+    prev = cur;
+    cur = t;
   }
 }
 
-// x at the start of each segment: x_a(p) = xi_a(p) + Psi_a(p) x_a(p+1), sequential from the end.
+// Boundary pass of the backward recurrence: x_a(p) = xi_a(p) + Psi_a(p) x_a(p+1).
 template <class F, int VG>
-__global__ void __launch_bounds__(256) k_scan_bwd_bound(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
-                                                        const SegMeta* __restrict__ segs, const F* __restrict__ Psi,
-                                                        F* __restrict__ W) {
+__global__ void __launch_bounds__(256, 1) k_cs_bwd_bound(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
+                                                      const SegMeta* __restrict__ segs, const F* __restrict__ Psi,
+                                                      F* __restrict__ W) {
   extern __shared__ unsigned char smem_raw[];
   const int N = g.N;
-  cpx<F>* Ms = reinterpret_cast<cpx<F>*>(smem_raw);
-  cpx<F>* xb = Ms + N * N;
-  cpx<F>* tmp = xb + N * VG;
+  SolveLds<F, VG> L(smem_raw, N);
   const ChainMeta ch = chains[blockIdx.x];
   const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
   if (ch.nseg <= 1) return;
   const long long NN2 = 2LL * N * N;
-  load_w<F, VG>(W, g.vcap, segs[ch.first_seg + ch.nseg - 1].first_block, v0, xb, N, nv);
+  auto seg_start = [&](int p) { return segs[ch.first_seg + p].first_block; };
+  cpx<F>* prev = L.a;
+  cpx<F>* cur = L.b;
+  load_w<F, VG>(W, g.vcap, seg_start(ch.nseg - 1), v0, prev, N, nv);
+  BlkRegs<F> R;
+  R.init(N);
+  VecRegs<F, VG> V;
+  R.load(Psi + NN2 * seg_start(ch.nseg - 2), N);
+  V.load(W, g.vcap, seg_start(ch.nseg - 2), v0, N, nv);
   for (int p = ch.nseg - 2; p >= 0; --p) {
-    int a = segs[ch.first_seg + p].first_block;
+    const int a = seg_start(p);
+    R.to_lds(L.M, N);
+    V.to_lds(cur, N);
     __syncthreads();
-    load_w<F, VG>(W, g.vcap, a, v0, tmp, N, nv);
-    stage_block(Psi + NN2 * a, Ms, N);
+    if (p - 1 >= 0) {
+      R.load(Psi + NN2 * seg_start(p - 1), N);
+      V.load(W, g.vcap, seg_start(p - 1), v0, N, nv);
+    }
+    mv_acc<F, VG>(L.M, prev, cur, N, nv, (F)1);
     __syncthreads();
-    mv_acc<F, VG>(Ms, xb, tmp, N, nv, (F)1);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) xb[idx] = tmp[idx];
-    store_w<F, VG>(W, g.vcap, a, v0, tmp, N, nv);
+    store_w<F, VG>(W, g.vcap, a, v0, cur, N, nv);
+    cpx<F>* t = prev;
+    prev = cur;
+    cur = t;
   }
 }
 
 // x_i = xi_i + Psi_i x_{a(p+1)} for the blocks not yet final, then x = Cg x~ into the
 // canonical output.  One workgroup per (block, vector group).
 template <class F, int VG>
-__global__ void __launch_bounds__(256) k_scan_out(DevGrid g, int nvec, const int* __restrict__ blk_field,
-                                                  const int* __restrict__ blk_lm, const int* __restrict__ blk_next,
-                                                  const F* __restrict__ Psi, const F* __restrict__ Cg,
-                                                  const F* __restrict__ W, double* __restrict__ xvec) {
+__global__ void __launch_bounds__(256, 1) k_cs_out(DevGrid g, int nvec, const int* __restrict__ blk_field,
+                                                const int* __restrict__ blk_lm, const int* __restrict__ blk_next,
+                                                const F* __restrict__ Psi, const F* __restrict__ Cg,
+                                                const F* __restrict__ W, double* __restrict__ xvec) {
   extern __shared__ unsigned char smem_raw[];
   const int N = g.N;
-  cpx<F>* Ms = reinterpret_cast<cpx<F>*>(smem_raw);
-  cpx<F>* xn = Ms + N * N;
-  cpx<F>* acc = xn + N * VG;
-  const int b = blockIdx.x;
+  SolveLds<F, VG> L(smem_raw, N);
+  const int blk = blockIdx.x;
   const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
-  const long long NN2 = 2LL * N * N, ld = 6LL * N * g.S;
-  const int nx = blk_next[b];
-  load_w<F, VG>(W, g.vcap, b, v0, acc, N, nv);
+  const long long ld = 6LL * N * g.S;
+  const int nx = blk_next[blk];
+  load_w<F, VG>(W, g.vcap, blk, v0, L.b, N, nv);
   if (nx >= 0) {
-    load_w<F, VG>(W, g.vcap, nx, v0, xn, N, nv);
-    stage_block(Psi + NN2 * b, Ms, N);
+    BlkRegs<F> R;
+  R.init(N);
+    R.load(Psi + 2LL * N * N * blk, N);
+    load_w<F, VG>(W, g.vcap, nx, v0, L.a, N, nv);
+    R.to_lds(L.M, N);
     __syncthreads();
-    mv_acc<F, VG>(Ms, xn, acc, N, nv, (F)1);
+    mv_acc<F, VG>(L.M, L.a, L.b, N, nv, (F)1);
   }
-  const long long o = 2LL * ((long long)N * ((long long)blk_field[b] * g.S + blk_lm[b]));
-  for (int idx = threadIdx.x; idx < N * VG; idx += blockDim.x) {
+  __syncthreads();
+  const long long o = 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + blk_lm[blk]));
+  for (int idx = threadIdx.x; idx < N * VG; idx += kSolveThreads) {
     int vv = idx % VG, j = idx / VG;
     if (vv >= nv) continue;
-    double c = (double)Cg[(long long)b * N + j];
+    double c = (double)Cg[(long long)blk * N + j];
     double* xp = xvec + (long long)(v0 + vv) * ld + o + 2 * j;
-    xp[0] = c * (double)acc[idx].re;
-    xp[1] = c * (double)acc[idx].im;
+    xp[0] = c * (double)L.b[idx].re;
+    xp[1] = c * (double)L.b[idx].im;
   }
 }
 
 // Temperature blocks: x = tc * Tinv (tr * b) per l, for every (vec, k, l), both Re and Im.
+// One workgroup per (l, group of kTV vectors): Tinv_l staged in LDS, columns (vec, k, Re/Im).
+constexpr int kTV = 4;
+
 template <class F>
-__global__ void k_T_solve(DevGrid g, int nvec, const F* __restrict__ Tinv, const F* __restrict__ tr,
-                          const F* __restrict__ tc, const double* __restrict__ bvec, double* __restrict__ xvec) {
-  long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_T_solve(DevGrid g, int nvec, const F* __restrict__ Tinv,
+                                                 const F* __restrict__ tr, const F* __restrict__ tc,
+                                                 const double* __restrict__ bvec, double* __restrict__ xvec) {
+  extern __shared__ unsigned char smem_raw[];
   const int N = g.N;
-  long long total = (long long)nvec * g.S * N;
-  if (tid >= total) return;
-  int j = (int)(tid % N);
-  int lm = (int)((tid / N) % g.S);
-  int vec = (int)(tid / ((long long)N * g.S));
-  int l = g.lm_l[lm];
-  long long ld = 6LL * N * g.S;
-  long long o = (long long)vec * ld + 2LL * ((long long)N * (2LL * g.S + lm));
-  const F* Ti = Tinv + (long long)l * N * N + (long long)j * N;
-  const F* trl = tr + (long long)l * N;
-  F ar = 0, ai = 0;
-  for (int i = 0; i < N; ++i) {
-    F w = Ti[i] * trl[i];
-    ar += w * (F)bvec[o + 2 * i];
-    ai += w * (F)bvec[o + 2 * i + 1];
+  F* Ts = reinterpret_cast<F*>(smem_raw);         // [N][N] transposed: Ts[i * N + j] = Tinv[j][i]
+  F* bs = Ts + N * N;                             // [ncol][N]
+  const int l = blockIdx.x;
+  const int v0 = blockIdx.y * kTV, nv = min(kTV, nvec - v0);
+  const int nk = min(g.K, l / g.m0) + 1;          // m = k m0 <= l
+  const int ncol = nv * nk * 2;
+  const long long ld = 6LL * N * g.S;
+  for (int i = threadIdx.x; i < N * N; i += blockDim.x) Ts[(i % N) * N + i / N] = Tinv[(long long)l * N * N + i];
+  for (int idx = threadIdx.x; idx < ncol * N; idx += blockDim.x) {
+    int jj = idx % N, col = idx / N;
+    int ri = col & 1, kk = (col >> 1) % nk, vv = (col >> 1) / nk;
+    int lm = g.lmbase[kk] + l - kk * g.m0;
+    long long o = (long long)(v0 + vv) * ld + 2LL * ((long long)N * (2LL * g.S + lm) + jj) + ri;
+    bs[col * N + jj] = tr[(long long)l * N + jj] * (F)bvec[o];
   }
-  F c = tc[(long long)l * N + j];
-  xvec[o + 2 * j] = (double)(c * ar);
-  xvec[o + 2 * j + 1] = (double)(c * ai);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < ncol * N; idx += blockDim.x) {
+    int jj = idx % N, col = idx / N;
+    int ri = col & 1, kk = (col >> 1) % nk, vv = (col >> 1) / nk;
+    F a = 0;
+    const F* bc = bs + col * N;
+    for (int i = 0; i < N; ++i) a += Ts[i * N + jj] * bc[i];
+    int lm = g.lmbase[kk] + l - kk * g.m0;
+    long long o = (long long)(v0 + vv) * ld + 2LL * ((long long)N * (2LL * g.S + lm) + jj) + ri;
+    xvec[o] = (double)(tc[(long long)l * N + jj] * a);
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -809,125 +995,129 @@ __device__ inline double kappa_dev(int l, int m) {
   return (ll * ll - 1.0) * sqrt((ll * ll - (double)m * m) / (4.0 * ll * ll - 1.0));
 }
 
-__global__ void k_residual64(DevGrid g, PhysParams ph, int nvec, const double* __restrict__ bvec,
-                             const double* __restrict__ xvec, double* __restrict__ rvec) {
-  long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// One workgroup per (vec, lm), one thread per node j; the e, f, T profiles of lm and the
+// e/f neighbours at l +- 1 are staged in LDS; matrices are read transposed (coalesced).
+__global__ void __launch_bounds__(64) k_residual64(DevGrid g, PhysParams ph, int nvec, const double* __restrict__ bvec,
+                                                   const double* __restrict__ xvec, double* __restrict__ rvec) {
+  __shared__ double xs[7][2 * 64];   // e, f, T at lm; e(l-1), f(l-1), e(l+1), f(l+1)
+  __shared__ double xq[2 * 64];      // f / r^2
   const int N = g.N;
-  long long total = (long long)nvec * 3 * g.S * N;
-  if (tid >= total) return;
-  int j = (int)(tid % N);
-  long long t2 = tid / N;
-  int lm = (int)(t2 % g.S);
-  long long t3 = t2 / g.S;
-  int f = (int)(t3 % 3);
-  int vec = (int)(t3 / 3);
-  int k = g.lm_k[lm], l = g.lm_l[lm];
-  int m = k * g.m0;
-  long long ld = 6LL * N * g.S;
+  const int lm = blockIdx.x, vec = blockIdx.y;
+  const int k = g.lm_k[lm], l = g.lm_l[lm];
+  const int m = k * g.m0;
+  const long long ld = 6LL * N * g.S;
   const double* x = xvec + (long long)vec * ld;
-  long long o = 2LL * ((long long)N * ((long long)f * g.S + lm));
-  double br = bvec[(long long)vec * ld + o + 2 * j], bi = bvec[(long long)vec * ld + o + 2 * j + 1];
-  double* rr = rvec + (long long)vec * ld + o + 2 * j;
-  if (f < 2 && l == 0) {
-    rr[0] = 0.0;
-    rr[1] = 0.0;
-    return;
+  const bool has_lo = (l - 1 >= max(m, 1)), has_hi = (l + 1 <= g.L);
+  for (int idx = threadIdx.x; idx < 7 * 2 * N; idx += blockDim.x) {
+    int c = idx % (2 * N), a = idx / (2 * N);
+    int f = (a < 3) ? a : ((a - 3) & 1);
+    int dl = (a < 3) ? 0 : (a < 5 ? -1 : 1);
+    bool ok = (a < 3) || (dl < 0 ? has_lo : has_hi);
+    xs[a][c] = ok ? x[2LL * ((long long)N * ((long long)f * g.S + lm + dl)) + c] : 0.0;
   }
-  const double* xs = x + o;
-  double r = g.r[j], r2 = r * r;
-  double lam = (double)l * (l + 1);
-  const double* Dr = g.D + (long long)j * N;
-  const double* D2r = g.D2 + (long long)j * N;
-  double ar, ai;
-  if (f == 2) {
-    if (j == 0 || j == N - 1) {
-      ar = xs[2 * j];
-      ai = xs[2 * j + 1];
-    } else {
-      double d1r = 0, d1i = 0, d2r = 0, d2i = 0;
-      for (int i = 0; i < N; ++i) {
-        d1r += Dr[i] * xs[2 * i];
-        d1i += Dr[i] * xs[2 * i + 1];
-        d2r += D2r[i] * xs[2 * i];
-        d2i += D2r[i] * xs[2 * i + 1];
+  __syncthreads();
+  for (int c = threadIdx.x; c < 2 * N; c += blockDim.x) {
+    double r = g.r[c >> 1];
+    xq[c] = xs[1][c] / (r * r);
+  }
+  __syncthreads();
+  const int j = threadIdx.x;
+  const bool active = j < N;
+  const double r = active ? g.r[j] : 1.0, r2 = r * r;
+  const double lam = (double)l * (l + 1);
+  // products with the transposed matrices: column j of M^T gives row j of M
+  double De[2] = {0, 0}, D2e[2] = {0, 0}, Df[2] = {0, 0}, D2f[2] = {0, 0}, D4f[2] = {0, 0}, D2q[2] = {0, 0};
+  double DT_[2] = {0, 0}, D2T_[2] = {0, 0}, Dn[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  if (active) {
+    for (int i = 0; i < N; ++i) {
+      double d1 = g.DT[(long long)i * N + j], d2 = g.D2T[(long long)i * N + j], d4 = g.D4T[(long long)i * N + j];
+      for (int c = 0; c < 2; ++c) {
+        double e = xs[0][2 * i + c], f = xs[1][2 * i + c], t = xs[2][2 * i + c];
+        De[c] += d1 * e;
+        D2e[c] += d2 * e;
+        Df[c] += d1 * f;
+        D2f[c] += d2 * f;
+        D4f[c] += d4 * f;
+        D2q[c] += d2 * xq[2 * i + c];
+        DT_[c] += d1 * t;
+        D2T_[c] += d2 * t;
+        for (int a = 0; a < 4; ++a) Dn[a][c] += d1 * xs[3 + a][2 * i + c];
       }
-      double Kr = (d2r + 2.0 / r * d1r - lam / r2 * xs[2 * j]) / ph.Pr;
-      double Ki = (d2i + 2.0 / r * d1i - lam / r2 * xs[2 * j + 1]) / ph.Pr;
-      ar = xs[2 * j] - ph.dt * Kr;
-      ai = xs[2 * j + 1] - ph.dt * Ki;
     }
-  } else {
-    bool bc = (f == 0) ? (j == 0 || j == N - 1) : (j == 0 || j == 1 || j == N - 2 || j == N - 1);
-    if (bc) {
+  }
+  // boundary-row derivatives: (D f)_0 and (D f)_{N-1} for rows 1 and N-2
+  __shared__ double dfb[2][2];
+  if (j == 0 || j == N - 1) {
+    dfb[j == 0 ? 0 : 1][0] = Df[0];
+    dfb[j == 0 ? 0 : 1][1] = Df[1];
+  }
+  __syncthreads();
+  if (!active) return;
+  const double* b = bvec + (long long)vec * ld;
+  double* rr = rvec + (long long)vec * ld;
+  for (int f = 0; f < 3; ++f) {
+    long long o = 2LL * ((long long)N * ((long long)f * g.S + lm) + j);
+    double ar, ai;
+    if (f < 2 && l == 0) {
+      rr[o] = 0.0;
+      rr[o + 1] = 0.0;
+      continue;
+    }
+    const double* xsf = xs[f];
+    if (f == 2) {
       if (j == 0 || j == N - 1) {
-        ar = xs[2 * j];
-        ai = xs[2 * j + 1];
+        ar = xsf[2 * j];
+        ai = xsf[2 * j + 1];
       } else {
-        const double* Db = g.D + (long long)((j == 1) ? 0 : N - 1) * N;
-        ar = ai = 0.0;
-        for (int i = 0; i < N; ++i) {
-          ar += Db[i] * xs[2 * i];
-          ai += Db[i] * xs[2 * i + 1];
-        }
+        double Kr = (D2T_[0] + 2.0 / r * DT_[0] - lam / r2 * xsf[2 * j]) / ph.Pr;
+        double Ki = (D2T_[1] + 2.0 / r * DT_[1] - lam / r2 * xsf[2 * j + 1]) / ph.Pr;
+        ar = xsf[2 * j] - ph.dt * Kr;
+        ai = xsf[2 * j + 1] - ph.dt * Ki;
       }
     } else {
-      double a = ph.Ek * lam / r2;
-      double cr, ci;  // self part
-      if (f == 0) {
-        double d2r = 0, d2i = 0;
-        for (int i = 0; i < N; ++i) {
-          d2r += D2r[i] * xs[2 * i];
-          d2i += D2r[i] * xs[2 * i + 1];
+      bool bc = (f == 0) ? (j == 0 || j == N - 1) : (j == 0 || j == 1 || j == N - 2 || j == N - 1);
+      if (bc) {
+        if (j == 0 || j == N - 1) {
+          ar = xsf[2 * j];
+          ai = xsf[2 * j + 1];
+        } else {
+          ar = dfb[j == 1 ? 0 : 1][0];
+          ai = dfb[j == 1 ? 0 : 1][1];
         }
-        double Lr = d2r - lam / r2 * xs[2 * j], Li = d2i - lam / r2 * xs[2 * j + 1];
-        // a e - dt (a L e + (2 i m / r^2) e)
-        cr = a * xs[2 * j] - ph.dt * (a * Lr - 2.0 * m / r2 * xs[2 * j + 1]);
-        ci = a * xs[2 * j + 1] - ph.dt * (a * Li + 2.0 * m / r2 * xs[2 * j]);
       } else {
-        const double* D4r = g.D4 + (long long)j * N;
-        double d2r = 0, d2i = 0, d4r = 0, d4i = 0, q2r = 0, q2i = 0;
-        for (int i = 0; i < N; ++i) {
-          double xr = xs[2 * i], xi = xs[2 * i + 1];
-          double ir2 = 1.0 / (g.r[i] * g.r[i]);
-          d2r += D2r[i] * xr;
-          d2i += D2r[i] * xi;
-          d4r += D4r[i] * xr;
-          d4i += D4r[i] * xi;
-          q2r += D2r[i] * xr * ir2;
-          q2i += D2r[i] * xi * ir2;
+        const double a = ph.Ek * lam / r2;
+        double xr = xsf[2 * j], xi = xsf[2 * j + 1];
+        double cr, ci;
+        if (f == 0) {
+          double Lr = D2e[0] - lam / r2 * xr, Li = D2e[1] - lam / r2 * xi;
+          cr = a * xr - ph.dt * (a * Lr - 2.0 * m / r2 * xi);
+          ci = a * xi - ph.dt * (a * Li + 2.0 * m / r2 * xr);
+        } else {
+          double Lr = D2f[0] - lam / r2 * xr, Li = D2f[1] - lam / r2 * xi;
+          double L2r = D4f[0] - lam * D2q[0] - lam / r2 * D2f[0] + lam * lam / (r2 * r2) * xr;
+          double L2i = D4f[1] - lam * D2q[1] - lam / r2 * D2f[1] + lam * lam / (r2 * r2) * xi;
+          cr = -a * Lr + ph.dt * (a * L2r - 2.0 * m / r2 * Li);
+          ci = -a * Li + ph.dt * (a * L2i + 2.0 * m / r2 * Lr);
         }
-        double xr = xs[2 * j], xi = xs[2 * j + 1];
-        double Lr = d2r - lam / r2 * xr, Li = d2i - lam / r2 * xi;
-        double L2r = d4r - lam * q2r - lam / r2 * d2r + lam * lam / (r2 * r2) * xr;
-        double L2i = d4i - lam * q2i - lam / r2 * d2i + lam * lam / (r2 * r2) * xi;
-        // -a L f - dt(-a L^2 f - (2 i m/r^2) L f)
-        cr = -a * Lr + ph.dt * (a * L2r - 2.0 * m / r2 * Li);
-        ci = -a * Li + ph.dt * (a * L2i + 2.0 * m / r2 * Lr);
-      }
-      // Coriolis coupling to the other potential at l-1 and l+1 (same m)
-      int fo = 1 - f;
-      for (int nb = -1; nb <= 1; nb += 2) {
-        int ln = l + nb;
-        if (ln < max(m, 1) || ln > g.L) continue;
-        double kap = (nb < 0) ? kappa_dev(l, m) : kappa_dev(l + 1, m);
-        if (kap == 0.0) continue;
-        double c = (nb < 0) ? (double)l : -(l + 1.0);
-        const double* xn = x + 2LL * ((long long)N * ((long long)fo * g.S + lm + nb));
-        double dr = 0, di = 0;
-        for (int i = 0; i < N; ++i) {
-          dr += Dr[i] * xn[2 * i];
-          di += Dr[i] * xn[2 * i + 1];
+        // Coriolis coupling to the other potential at l-1 and l+1
+        for (int nb = -1; nb <= 1; nb += 2) {
+          if (nb < 0 ? !has_lo : !has_hi) continue;
+          double kap = (nb < 0) ? kappa_dev(l, m) : kappa_dev(l + 1, m);
+          if (kap == 0.0) continue;
+          double cc = (nb < 0) ? (double)l : -(l + 1.0);
+          int a_ = 3 + (nb < 0 ? 0 : 2) + (1 - f);   // other potential: f-row uses e, e-row uses f
+          const double* xn = xs[a_];
+          double pre = ph.dt * 2.0 / r2 * kap;
+          cr += pre * (cc / r * xn[2 * j] - Dn[a_ - 3][0]);
+          ci += pre * (cc / r * xn[2 * j + 1] - Dn[a_ - 3][1]);
         }
-        double pre = ph.dt * 2.0 / r2 * kap;
-        cr += pre * (c / r * xn[2 * j] - dr);
-        ci += pre * (c / r * xn[2 * j + 1] - di);
+        ar = cr;
+        ai = ci;
       }
-      ar = cr;
-      ai = ci;
     }
+    rr[o] = b[o] - ar;
+    rr[o + 1] = b[o + 1] - ai;
   }
-  rr[0] = br - ar;
-  rr[1] = bi - ai;
 }
 
 // x += d (FP64), over n elements

@@ -480,29 +480,34 @@ void build_scan(ChainFactor& cf, int N, int seg) {
   const size_t NN = (size_t)N * N;
   cf.Phi.assign((size_t)n * NN, 0.0);
   cf.Psi.assign((size_t)n * NN, 0.0);
-  std::vector<cplx> D(NN), G(NN), T(NN);
+  cf.G.assign((size_t)n * NN, 0.0);
+  std::vector<cplx> D(NN);
+  for (int i = 1; i < n; ++i) {
+    // D = S_i^{-1} = diag(sc) Shat^{-1} diag(sr);  G_i = D Lo_i
+    const cplx* Si = &cf.Sinv[(size_t)i * NN];
+    for (int r = 0; r < N; ++r)
+      for (int c = 0; c < N; ++c) D[(size_t)r * N + c] = cf.sc[(size_t)i * N + r] * Si[(size_t)r * N + c] * cf.sr[(size_t)i * N + c];
+    const cplx* Li = &cf.Lo[(size_t)i * NN];
+    cplx* Gi = &cf.G[(size_t)i * NN];
+    for (int r = 0; r < N; ++r)
+      for (int q = 0; q < N; ++q) {
+        cplx d = D[(size_t)r * N + q];
+        for (int c = 0; c < N; ++c) Gi[(size_t)r * N + c] += d * Li[(size_t)q * N + c];
+      }
+  }
   for (int a = seg; a < n; a += seg) {
     int e = std::min(a + seg, n) - 1;
     for (int i = a; i <= e; ++i) {
-      // D = S_i^{-1} = diag(sc) Shat^{-1} diag(sr);  G = -D Lo_i
-      const cplx* Si = &cf.Sinv[(size_t)i * NN];
-      for (int r = 0; r < N; ++r)
-        for (int c = 0; c < N; ++c) D[(size_t)r * N + c] = cf.sc[(size_t)i * N + r] * Si[(size_t)r * N + c] * cf.sr[(size_t)i * N + c];
-      const cplx* Li = &cf.Lo[(size_t)i * NN];
-      std::fill(G.begin(), G.end(), cplx(0.0));
-      for (int r = 0; r < N; ++r)
-        for (int q = 0; q < N; ++q) {
-          cplx d = D[(size_t)r * N + q];
-          for (int c = 0; c < N; ++c) G[(size_t)r * N + c] -= d * Li[(size_t)q * N + c];
-        }
+      // Phi_a = -G_a, Phi_i = -G_i Phi_{i-1}
+      const cplx* Gi = &cf.G[(size_t)i * NN];
       cplx* Pi = &cf.Phi[(size_t)i * NN];
       if (i == a) {
-        std::copy(G.begin(), G.end(), Pi);
+        for (size_t q = 0; q < NN; ++q) Pi[q] = -Gi[q];
       } else {
         const cplx* Pp = &cf.Phi[(size_t)(i - 1) * NN];
         for (int r = 0; r < N; ++r)
           for (int q = 0; q < N; ++q) {
-            cplx gv = G[(size_t)r * N + q];
+            cplx gv = -Gi[(size_t)r * N + q];
             for (int c = 0; c < N; ++c) Pi[(size_t)r * N + c] += gv * Pp[(size_t)q * N + c];
           }
       }

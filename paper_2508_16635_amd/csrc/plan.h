@@ -45,6 +45,7 @@ struct ChainFactor {
   std::vector<double> sr, sc;                 // n*N
   std::vector<cplx> Sinv, Lo, H;              // n*N*N each (row-major blocks)
   std::vector<cplx> Phi, Psi;                 // n*N*N each
+  std::vector<cplx> G;                        // n*N*N: S_i^{-1} Lo_i (forward recurrence matrix)
 };
 
 struct TFactor {                              // temperature block per l (real)
