@@ -65,7 +65,7 @@ def run(args):
     W = WORKLOAD
     nvec = args.nvec
     plan = sc.Plan(W["L"], W["M"], W["m0"], W["N"], Ek=W["Ek"], Ra=W["Ra"], Pr=W["Pr"], dt=W["dt"],
-                   nvec_max=nvec)
+                   nvec_max=nvec, refine_mixed=args.refine_mixed)
     lay_d = plan.layout
     lay = si.Layout(W["L"], W["M"], W["m0"], W["N"])
     assert lay.n_real == plan.n_real
@@ -122,7 +122,7 @@ def run(args):
     N = W["N"]
     nblocks = sum(W["L"] - max(k * W["m0"], 1) + 1 for k in range(lay_d["K"] + 1)) * 2
     fbytes32 = 3 * nblocks * N * N * 8
-    work = stage_work(lay_d, nvec, 4, fbytes32, nblocks, refine=2)
+    work = stage_work(lay_d, nvec, 4, fbytes32, nblocks, refine=args.refine_mixed)
     prof = mixed["prof"]
     dom = max(prof, key=lambda k: prof[k][0])
     ms, cnt = prof[dom]
@@ -156,7 +156,7 @@ def run(args):
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "rotating-shell jvp L=M=128 m0=10 N=48 Ek=1e-5 Ra=362 dt=200",
-                   "nvec": nvec, "N_p": lay_d["Np"], "N_theta": lay_d["ntheta"], "N_phi": lay_d["nphi"],
+                   "nvec": nvec, "refine_mixed": args.refine_mixed, "N_p": lay_d["Np"], "N_theta": lay_d["ntheta"], "N_phi": lay_d["nphi"],
                    "n_real": plan.n_real},
         "fp64_jvp_per_s": fp64["jvps"] / fp64["seconds"],
         "mixed_vs_fp64_max_rel": mixed_vs_fp64,
@@ -166,9 +166,43 @@ def run(args):
         "stages_mixed": stages,
         "stages_fp64": {k: {"ms_per_step": v[0] / max(args.steps, 1)} for k, v in fp64["prof"].items() if v[1]},
     }
+    if not args.no_newton:
+        out["newton"] = newton_runs(args, plan, X, C, J, lay)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, X, C, J, lay)
     return out
+
+
+def newton_runs(args, plan, X, C, J, lay):
+    """Manufactured Newton problem at the same shell: X* = the base state, forcing F* = -R(X*),
+    start X* + 1e-3 |X*| d (seeded d, phase slot kept), C* + 1e-3; both Jacobian precisions must
+    drive ||R_F|| to 1e-10.  Reports steps, Jacobian actions, final residual and wall time."""
+    import torch
+    import paper_2508_16635_amd as sc
+    import seeded_inputs as si
+    dev = torch.device("cuda:0")
+    Xs = torch.from_numpy(X).to(dev)
+    F = torch.empty_like(Xs)
+    plan.newton_residual(Xs, C, F)
+    F.neg_()
+    d = si.random_state(lay, 3999, p=2.0)
+    d[lay.nonphysical_mask()] = 0.0
+    d[J] = 0.0
+    d *= 1e-3 * np.linalg.norm(X) / np.linalg.norm(d)
+    res = {}
+    for name, prec, gtol in (("mixed", sc.SC_MIXED, 1e-6), ("fp64", sc.SC_FP64, 1e-10)):
+        x = torch.from_numpy(X + d).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Cf, rep = plan.newton(x, C + 1e-3, J, tol=1e-10, gmres_tol=gtol, restart=args.restart,
+                              max_newton=8, max_matvec=args.max_matvec, prec=prec, forcing=F)
+        torch.cuda.synchronize()
+        dt_ = time.perf_counter() - t0
+        err = float((x - Xs).norm() / Xs.norm())
+        res[name] = {"converged": rep["converged"], "newton_steps": rep["newton_steps"], "matvecs": rep["matvecs"],
+                     "rnorm_final": rep["rnorm"][-1], "rnorm_history": rep["rnorm"], "seconds": dt_,
+                     "rel_err_vs_root": err, "C_err": abs(Cf - C), "gmres_tol": gtol}
+    return res
 
 
 def cpu_baseline(args, X, C, J, lay):
@@ -204,6 +238,10 @@ def main():
     ap.add_argument("--nvectors", type=int, default=200)
     ap.add_argument("--cpu-sample", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--refine-mixed", type=int, default=2, help="FP64 refinement passes of the mixed solve")
+    ap.add_argument("--no-newton", action="store_true")
+    ap.add_argument("--restart", type=int, default=80)
+    ap.add_argument("--max-matvec", type=int, default=400)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no multi-GPU path.",

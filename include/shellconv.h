@@ -98,6 +98,32 @@ int sc_set_base(sc_plan* plan, const double* x, double C, long long J, void* str
  * FP32 accumulation, FP64 radial operators, right-hand side, residual and refinement. */
 int sc_jvp(sc_plan* plan, int nvec, const double* v, long long ldv, double* y, long long ldy,
            sc_precision prec, void* stream);
+/* Newton-GMRES on R_C(X) = B_C(X) - X (+ forcing), Sec. 3.3 and 3.4: each Newton step solves
+ * (B_X - I)(u, c) = R with restarted GMRES (Saad-Schultz, classical Gram-Schmidt applied twice,
+ * dot products and updates on the device, Hessenberg and Givens rotations on the host) using
+ * sc_jvp in the chosen precision, then X <- X - u, C <- C - c with c carried in slot J.
+ * x: device state, updated in place; C: host drift speed, updated in place.  Synchronizes the
+ * stream once per Krylov step.  The Krylov basis is allocated by the first call (or a call
+ * with a longer restart) and kept by the plan. */
+typedef struct {
+  double tol;             /* stop when ||R||_2 <= tol (absolute)                         */
+  double gmres_tol;       /* relative tolerance of each GMRES solve                      */
+  int restart;            /* GMRES restart length, 1..128                                */
+  int max_newton;         /* Newton steps                                                */
+  int max_matvec;         /* Jacobian actions per Newton step                            */
+  int prec;               /* sc_precision of the Jacobian action                         */
+  long long J;            /* phase slot (Im entry with m > 0), or -1: C stays fixed      */
+  const double* forcing;  /* device vector added to the residual, or NULL                */
+} sc_newton_opts;
+typedef struct {
+  int newton_steps, matvecs, converged;
+  double rnorm[65];       /* ||R|| before each Newton step and at the end                 */
+  int step_matvecs[64];   /* Jacobian actions per Newton step                            */
+  double C;               /* final drift speed                                           */
+} sc_newton_report;
+int sc_newton(sc_plan* plan, double* x, double* C, const sc_newton_opts* opts, sc_newton_report* report,
+              void* stream);
+
 /* Stage profiler (tracing).  While enabled, every launch of the plan is bracketed by HIP
  * events on its stream; sc_profile_read synchronizes, returns per-stage total milliseconds
  * and launch counts (arrays of nstages entries indexed by SC_STAGE_*) and clears the record.

@@ -39,6 +39,17 @@ class _Layout(ctypes.Structure):
                 ("ntheta", ctypes.c_int), ("nphi", ctypes.c_int), ("nvec_max", ctypes.c_int)]
 
 
+class _NewtonOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("gmres_tol", ctypes.c_double), ("restart", ctypes.c_int),
+                ("max_newton", ctypes.c_int), ("max_matvec", ctypes.c_int), ("prec", ctypes.c_int),
+                ("J", ctypes.c_longlong), ("forcing", ctypes.c_void_p)]
+
+
+class _NewtonReport(ctypes.Structure):
+    _fields_ = [("newton_steps", ctypes.c_int), ("matvecs", ctypes.c_int), ("converged", ctypes.c_int),
+                ("rnorm", ctypes.c_double * 65), ("step_matvecs", ctypes.c_int * 64), ("C", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -61,6 +72,7 @@ def load_library(path: str = LIB_PATH):
         "sc_newton_residual": [vp, vp, d, vp, ctypes.POINTER(d), vp],
         "sc_set_base": [vp, vp, d, ll, vp],
         "sc_jvp": [vp, i, vp, ll, vp, ll, i, vp],
+        "sc_newton": [vp, vp, ctypes.POINTER(d), ctypes.POINTER(_NewtonOpts), ctypes.POINTER(_NewtonReport), vp],
         "sc_profile": [vp, i],
         "sc_profile_read": [vp, ctypes.POINTER(d), ctypes.POINTER(ll), i],
     }
@@ -80,7 +92,8 @@ STAGES = ["radial_prep", "legendre_synth", "ring", "legendre_anal", "project_rhs
 
 def exported_symbols():
     return ["sc_plan_create", "sc_plan_destroy", "sc_layout", "sc_set_params", "sc_factor", "sc_step",
-            "sc_newton_residual", "sc_set_base", "sc_jvp", "sc_profile", "sc_profile_read", "sc_last_error"]
+            "sc_newton_residual", "sc_set_base", "sc_jvp", "sc_newton", "sc_profile", "sc_profile_read",
+            "sc_last_error"]
 
 
 def _check(rc):
@@ -171,3 +184,17 @@ class Plan:
         cnt = (ctypes.c_longlong * n)()
         _check(_lib.sc_profile_read(self._h, ms, cnt, n))
         return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+    def newton(self, x, C=0.0, J=-1, tol=1e-10, gmres_tol=1e-10, restart=40, max_newton=20, max_matvec=400,
+               prec=SC_FP64, forcing=None, stream=None):
+        """Newton-GMRES in place on x (device); returns (C, report dict)."""
+        o = _NewtonOpts(tol, gmres_tol, restart, max_newton, max_matvec, int(prec), int(J),
+                        None if forcing is None else _ptr(forcing, self.n_real).value)
+        rep = _NewtonReport()
+        c = ctypes.c_double(C)
+        _check(_lib.sc_newton(self._h, _ptr(x, self.n_real), ctypes.byref(c), ctypes.byref(o), ctypes.byref(rep),
+                              _stream(stream)))
+        k = rep.newton_steps
+        return c.value, {"newton_steps": k, "matvecs": rep.matvecs, "converged": bool(rep.converged),
+                         "rnorm": [rep.rnorm[i] for i in range(k + 1)],
+                         "step_matvecs": [rep.step_matvecs[i] for i in range(k)]}

@@ -84,8 +84,8 @@ struct sc_plan {
   long long baseJ = -1;
   // grid / radial data
   DevBuf d_lmk, d_lml, d_lmbase, d_r, d_rp, d_E, d_ED, d_ED2, d_P, d_Dp, d_D, d_D2, d_D4;
-  DevBuf d_ET, d_EDT, d_ED2T, d_DT, d_D2T, d_D4T, d_rtiles;
-  int nrtiles = 0;
+  DevBuf d_ET, d_EDT, d_ED2T, d_DT, d_D2T, d_D4T, d_rtiles, d_PT, d_DpT, d_ptiles;
+  int nrtiles = 0, nptiles = 0;
   // tables and workspaces per precision
   TabLayout tl;
   WsLayout wl;
@@ -104,6 +104,9 @@ struct sc_plan {
   DevBuf Sinv32, G32, H32, Phi32, Psi32, sr32, sc32, Rg32, Cg32;
   DevBuf wscan;  // scan work vectors, capacity vcap x nblocks x N complex doubles
   DevBuf Tinv64, tr64, tc64, Tinv32, tr32, tc32;
+  // Newton-GMRES workspace (allocated by the first sc_newton call)
+  DevBuf kV, kW, kR, kDu, kPart, kH;
+  int krylov_cap = 0;
   // stage profiler: pairs of events recorded around launches while enabled
   bool prof_on = false;
   std::vector<hipEvent_t> ev;           // 2 * capacity
@@ -146,6 +149,10 @@ struct sc_plan {
     g.D4T = d_D4T.as<double>();
     g.rtiles = d_rtiles.as<int2>();
     g.nrtiles = nrtiles;
+    g.PT = d_PT.as<double>();
+    g.DpT = d_DpT.as<double>();
+    g.ptiles = d_ptiles.as<int2>();
+    g.nptiles = nptiles;
     return g;
   }
   sc::PhysParams pp() const {
@@ -299,9 +306,11 @@ void build_workspaces(sc_plan* P) {
   P->MX.alloc(nr * sizeof(double));
 }
 
+template <class T>
 long long gemm_tiles(const std::vector<sc::GemmProb>& pr, int nvec) {
+  const int BM = sc::GemmCfg<T>::BM, BN = sc::GemmCfg<T>::BN;
   long long t = 0;
-  for (const auto& p : pr) t += (long long)((p.Mper * nvec + 63) / 64) * ((p.N + 63) / 64);
+  for (const auto& p : pr) t += (long long)((p.Mper * nvec + BM - 1) / BM) * ((p.N + BN - 1) / BN);
   return t;
 }
 
@@ -340,7 +349,7 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
     hipLaunchKernelGGL(sc::k_radial_prep<T>, dim3(P->nrtiles, nvec), dim3(256), 0, s, dg, v, ldv, J, nvec, ws + w.Gs, ws + w.Gv);
   }
   HIPCHK(hipGetLastError());
-  long long nt = gemm_tiles(P->h_syn, nvec);
+  long long nt = gemm_tiles<T>(P->h_syn, nvec);
   {
     Prof _p(P, SC_STAGE_LEGENDRE_SYNTH, s);
     hipLaunchKernelGGL(sc::k_gemm_batched<T>, dim3((unsigned)nt), dim3(256), 0, s, P->probs_syn.as<sc::GemmProb>(),
@@ -375,7 +384,7 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
     return;
   }
   HIPCHK(hipGetLastError());
-  nt = gemm_tiles(P->h_ana, nvec);
+  nt = gemm_tiles<T>(P->h_ana, nvec);
   {
     Prof _p(P, SC_STAGE_LEGENDRE_ANAL, s);
     hipLaunchKernelGGL(sc::k_gemm_batched<T>, dim3((unsigned)nt), dim3(256), 0, s, P->probs_ana.as<sc::GemmProb>(),
@@ -386,6 +395,10 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
 
 constexpr int kSeg = 8;   // blocks per scan segment
 constexpr int kVG = 16;   // vectors per workgroup in the chain solves
+
+size_t project_smem(const sc::HostGrid& g) {
+  return sizeof(double) * ((size_t)5 * sc::kPT * 2 * g.Np + (size_t)3 * sc::kPT * 2 * g.N);
+}
 
 template <class F>
 size_t tsolve_smem(const sc::HostGrid& g) {
@@ -476,7 +489,7 @@ void step_into_xbuf(sc_plan* P, const double* x, double C, hipStream_t s) {
   sc::DevGrid dg = P->dg();
   {
     Prof _p(P, SC_STAGE_PROJECT_RHS, s);
-    hipLaunchKernelGGL((sc::k_project_rhs<double, true>), dim3(P->hg.S), dim3(128), 0, s, dg, P->pp(), 1,
+    hipLaunchKernelGGL((sc::k_project_rhs<double, true>), dim3(P->nptiles, 1), dim3(256), project_smem(P->hg), s, dg, P->pp(), 1,
                        (const double*)(P->ws64.as<double>() + P->wl.As), (const double*)(P->ws64.as<double>() + P->wl.Av),
                        x, P->n_real, (long long)-1, C, (const double*)nullptr, P->bbuf.as<double>());
   }
@@ -487,6 +500,229 @@ void step_into_xbuf(sc_plan* P, const double* x, double C, hipStream_t s) {
 void check_plan(sc_plan* P) {
   if (!P) throw Fail{SC_ERR_ARG, "null plan"};
   HIPCHK(hipSetDevice(P->prm.device));
+}
+
+
+long long check_slot(sc_plan* P, long long J) {
+  if (J < 0) return -1;
+  const sc::HostGrid& g = P->hg;
+  if (J >= P->n_real || (J % 2) == 0) throw Fail{SC_ERR_ARG, "phase slot must be an Im entry"};
+  long long node = J / 2;
+  int lm = (int)((node / g.N) % g.S);
+  if (g.lm_k[lm] == 0) throw Fail{SC_ERR_ARG, "phase slot must have m > 0"};
+  return J;
+}
+
+void set_base_impl(sc_plan* P, const double* x, double C, long long J, hipStream_t s) {
+  const sc::HostGrid& g = P->hg;
+  transforms<double>(P, sc::RING_SYNTH, 1, x, P->n_real, -1, s);
+  long long n3 = 3LL * g.S * g.N;
+  hipLaunchKernelGGL(sc::k_apply_M, dim3(nblk(n3, 256)), dim3(256), 0, s, P->dg(), P->pp(), x, P->MX.as<double>());
+  HIPCHK(hipGetLastError());
+  P->baseC = C;
+  P->baseJ = J;
+  P->have_base = true;
+}
+
+void jvp_impl(sc_plan* P, int nvec, const double* v, long long ldv, double* y, long long ldy, int prec, hipStream_t s) {
+  const long long J = P->baseJ;
+  sc::DevGrid dg = P->dg();
+  if (prec == SC_FP64) {
+    transforms<double>(P, sc::RING_LINEAR, nvec, v, ldv, J, s);
+    {
+      Prof _p(P, SC_STAGE_PROJECT_RHS, s);
+      hipLaunchKernelGGL((sc::k_project_rhs<double, false>), dim3(P->nptiles, nvec), dim3(256), project_smem(P->hg), s,
+                         dg, P->pp(), nvec, (const double*)(P->ws64.as<double>() + P->wl.As),
+                         (const double*)(P->ws64.as<double>() + P->wl.Av), v, ldv, J, P->baseC,
+                         P->MX.as<const double>(), P->bbuf.as<double>());
+      HIPCHK(hipGetLastError());
+    }
+    refined_solve<double>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine64, s);
+  } else {
+    transforms<float>(P, sc::RING_LINEAR, nvec, v, ldv, J, s);
+    {
+      Prof _p(P, SC_STAGE_PROJECT_RHS, s);
+      hipLaunchKernelGGL((sc::k_project_rhs<float, false>), dim3(P->nptiles, nvec), dim3(256), project_smem(P->hg), s,
+                         dg, P->pp(), nvec, (const float*)(P->ws32.as<float>() + P->wl.As),
+                         (const float*)(P->ws32.as<float>() + P->wl.Av), v, ldv, J, P->baseC,
+                         P->MX.as<const double>(), P->bbuf.as<double>());
+      HIPCHK(hipGetLastError());
+    }
+    refined_solve<float>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine32, s);
+  }
+  long long n = (long long)nvec * P->n_real;
+  {
+    Prof _p(P, SC_STAGE_FINALIZE, s);
+    hipLaunchKernelGGL(sc::k_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, dg, nvec, P->xbuf.as<const double>(), v, ldv, J,
+                       y, ldy, 1);
+    HIPCHK(hipGetLastError());
+  }
+}
+
+// ---- Krylov / Newton (host control, device vectors) ----------------------------------------
+constexpr int kDotChunks = 64;
+
+void ensure_krylov(sc_plan* P, int restart) {
+  if (P->krylov_cap >= restart) return;
+  const long long n = P->n_real;
+  P->kV.alloc((size_t)(restart + 1) * n * sizeof(double));
+  P->kW.alloc(n * sizeof(double));
+  P->kR.alloc(n * sizeof(double));
+  P->kDu.alloc(n * sizeof(double));
+  P->kPart.alloc((size_t)(restart + 1) * kDotChunks * sizeof(double));
+  P->kH.alloc((size_t)(restart + 1) * sizeof(double));
+  P->krylov_cap = restart;
+}
+
+// h[i] = <V_i, w> for i < k (device vectors, fixed-order host summation of fixed chunks)
+void dots(sc_plan* P, const double* V, long long ldv, int k, const double* w, std::vector<double>& h, hipStream_t s) {
+  const long long n = P->n_real;
+  hipLaunchKernelGGL(sc::k_dots_partial, dim3(kDotChunks, k), dim3(256), 0, s, V, ldv, k, w, n, kDotChunks,
+                     P->kPart.as<double>());
+  HIPCHK(hipGetLastError());
+  std::vector<double> part((size_t)k * kDotChunks);
+  HIPCHK(hipMemcpyAsync(part.data(), P->kPart.p, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  h.assign(k, 0.0);
+  for (int i = 0; i < k; ++i)
+    for (int c = 0; c < kDotChunks; ++c) h[i] += part[(size_t)i * kDotChunks + c];
+}
+
+double norm2(sc_plan* P, const double* w, hipStream_t s) {
+  std::vector<double> h;
+  dots(P, w, P->n_real, 1, w, h, s);
+  return std::sqrt(h[0]);
+}
+
+// w = alpha w - sum_{i<k} h_i V_i
+void combine(sc_plan* P, double* w, double alpha, const double* V, long long ldv, int k, const std::vector<double>& h,
+             hipStream_t s) {
+  const long long n = P->n_real;
+  if (k > 0) HIPCHK(hipMemcpyAsync(P->kH.p, h.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(sc::k_combine, dim3(nblk(n, 256)), dim3(256), 0, s, w, alpha, V, ldv, k, P->kH.as<const double>(), n);
+  HIPCHK(hipGetLastError());
+}
+
+// Restarted GMRES for (B_X - I) du = b with the current base; returns the number of jvps.
+int gmres(sc_plan* P, const double* b, double* du, double rtol, int restart, int maxmv, int prec, hipStream_t s) {
+  const long long n = P->n_real;
+  double* V = P->kV.as<double>();
+  double* w = P->kW.as<double>();
+  const double bn = norm2(P, b, s);
+  hipLaunchKernelGGL(sc::k_scale, dim3(nblk(n, 256)), dim3(256), 0, s, du, b, 0.0, n);
+  HIPCHK(hipGetLastError());
+  if (bn == 0.0) return 0;
+  // r = b (x0 = 0) kept in V_0 before normalization
+  hipLaunchKernelGGL(sc::k_scale, dim3(nblk(n, 256)), dim3(256), 0, s, V, b, 1.0, n);
+  HIPCHK(hipGetLastError());
+  int mv = 0;
+  double beta = bn;
+  std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), h, h2;
+  while (true) {
+    if (beta <= rtol * bn || mv >= maxmv) break;
+    hipLaunchKernelGGL(sc::k_scale, dim3(nblk(n, 256)), dim3(256), 0, s, V, V, 1.0 / beta, n);
+    HIPCHK(hipGetLastError());
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jend = 0;
+    bool done = false;
+    for (int j = 0; j < restart; ++j) {
+      jvp_impl(P, 1, V + (long long)j * n, n, w, n, prec, s);
+      ++mv;
+      dots(P, V, n, j + 1, w, h, s);
+      combine(P, w, 1.0, V, n, j + 1, h, s);
+      dots(P, V, n, j + 1, w, h2, s);
+      combine(P, w, 1.0, V, n, j + 1, h2, s);
+      for (int i = 0; i <= j; ++i) h[i] += h2[i];
+      double hn = norm2(P, w, s);
+      for (int i = 0; i <= j; ++i) H[(size_t)i * restart + j] = h[i];
+      H[(size_t)(j + 1) * restart + j] = hn;
+      if (hn > 0.0) {
+        hipLaunchKernelGGL(sc::k_scale, dim3(nblk(n, 256)), dim3(256), 0, s, V + (long long)(j + 1) * n, w, 1.0 / hn, n);
+        HIPCHK(hipGetLastError());
+      }
+      for (int i = 0; i < j; ++i) {
+        double a = H[(size_t)i * restart + j], c = H[(size_t)(i + 1) * restart + j];
+        H[(size_t)i * restart + j] = cs[i] * a + sn[i] * c;
+        H[(size_t)(i + 1) * restart + j] = -sn[i] * a + cs[i] * c;
+      }
+      double a = H[(size_t)j * restart + j], c = H[(size_t)(j + 1) * restart + j];
+      double den = std::hypot(a, c);
+      cs[j] = den > 0 ? a / den : 1.0;
+      sn[j] = den > 0 ? c / den : 0.0;
+      H[(size_t)j * restart + j] = den;
+      H[(size_t)(j + 1) * restart + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      jend = j + 1;
+      if (std::fabs(g[j + 1]) <= rtol * bn || mv >= maxmv || hn == 0.0) {
+        done = true;
+        break;
+      }
+    }
+    // y = R^{-1} g, du += V y
+    std::vector<double> y(jend, 0.0);
+    for (int i = jend - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int q = i + 1; q < jend; ++q) acc -= H[(size_t)i * restart + q] * y[q];
+      y[i] = acc / H[(size_t)i * restart + i];
+    }
+    for (auto& v : y) v = -v;
+    combine(P, du, 1.0, V, n, jend, y, s);
+    if (done || mv >= maxmv) break;
+    // restart: r = b - J du, stored in V_0
+    jvp_impl(P, 1, du, n, w, n, prec, s);
+    ++mv;
+    hipLaunchKernelGGL(sc::k_scale, dim3(nblk(n, 256)), dim3(256), 0, s, V, b, 1.0, n);
+    HIPCHK(hipGetLastError());
+    std::vector<double> one{1.0};
+    combine(P, V, 1.0, w, n, 1, one, s);
+    beta = norm2(P, V, s);
+  }
+  return mv;
+}
+
+void newton_impl(sc_plan* P, double* x, double* C, const sc_newton_opts& o, long long J, sc_newton_report* rep,
+                 hipStream_t s) {
+  ensure_krylov(P, o.restart);
+  const long long n = P->n_real;
+  std::memset(rep, 0, sizeof(*rep));
+  double* R = P->kR.as<double>();
+  double* du = P->kDu.as<double>();
+  for (int it = 0;; ++it) {
+    step_into_xbuf(P, x, *C, s);
+    hipLaunchKernelGGL(sc::k_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, P->dg(), 1, P->xbuf.as<const double>(), x, n,
+                       (long long)-1, R, n, 1);
+    HIPCHK(hipGetLastError());
+    if (o.forcing) {
+      hipLaunchKernelGGL(sc::k_axpy1, dim3(nblk(n, 256)), dim3(256), 0, s, n, o.forcing, R);
+      HIPCHK(hipGetLastError());
+    }
+    const double rn = norm2(P, R, s);
+    rep->rnorm[it] = rn;
+    rep->newton_steps = it;
+    rep->C = *C;
+    if (!std::isfinite(rn)) throw Fail{SC_ERR_NONFINITE, "Newton residual is not finite"};
+    if (rn <= o.tol) {
+      rep->converged = 1;
+      return;
+    }
+    if (it >= o.max_newton) return;
+    set_base_impl(P, x, *C, J, s);
+    const int mv = gmres(P, R, du, o.gmres_tol, o.restart, o.max_matvec, o.prec, s);
+    rep->step_matvecs[it] = mv;
+    rep->matvecs += mv;
+    if (J >= 0) {
+      double c = 0.0, zero = 0.0;
+      HIPCHK(hipMemcpyAsync(&c, du + J, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(hipMemcpyAsync(du + J, &zero, sizeof(double), hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+      *C -= c;
+    }
+    std::vector<double> one{1.0};
+    combine(P, x, 1.0, du, n, 1, one, s);
+  }
 }
 
 }  // namespace
@@ -546,6 +782,15 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     upload(P->d_DT, transpose(g.D, g.N, g.N));
     upload(P->d_D2T, transpose(g.D2, g.N, g.N));
     upload(P->d_D4T, transpose(g.D4, g.N, g.N));
+    upload(P->d_PT, transpose(g.P, g.N, g.Np));
+    upload(P->d_DpT, transpose(g.Dp, g.Np, g.Np));
+    {
+      std::vector<int2> tiles;
+      for (int k = 0; k <= g.K; ++k)
+        for (int il = 0; il < g.nl[k]; il += sc::kPT) tiles.push_back(make_int2(k, il));
+      upload(P->d_ptiles, tiles);
+      P->nptiles = (int)tiles.size();
+    }
     {
       std::vector<int2> tiles;
       for (int k = 0; k <= g.K; ++k)
@@ -781,24 +1026,7 @@ int sc_set_base(sc_plan* P, const double* x, double C, long long J, void* stream
     check_plan(P);
     if (!x) throw Fail{SC_ERR_ARG, "null vector"};
     if (!P->factored) throw Fail{SC_ERR_STATE, "sc_factor has not run for the current (Ek, dt)"};
-    const sc::HostGrid& g = P->hg;
-    if (J >= 0) {
-      // must be an Im slot with m > 0
-      if (J >= P->n_real || (J % 2) == 0) throw Fail{SC_ERR_ARG, "phase slot must be an Im entry"};
-      long long node = J / 2;
-      int lm = (int)((node / g.N) % g.S);
-      if (g.lm_k[lm] == 0) throw Fail{SC_ERR_ARG, "phase slot must have m > 0"};
-    } else {
-      J = -1;
-    }
-    hipStream_t s = (hipStream_t)stream;
-    transforms<double>(P, sc::RING_SYNTH, 1, x, P->n_real, -1, s);
-    long long n3 = 3LL * g.S * g.N;
-    hipLaunchKernelGGL(sc::k_apply_M, dim3(nblk(n3, 256)), dim3(256), 0, s, P->dg(), P->pp(), x, P->MX.as<double>());
-    HIPCHK(hipGetLastError());
-    P->baseC = C;
-    P->baseJ = J;
-    P->have_base = true;
+    set_base_impl(P, x, C, check_slot(P, J), (hipStream_t)stream);
   });
 }
 
@@ -849,39 +1077,20 @@ int sc_jvp(sc_plan* P, int nvec, const double* v, long long ldv, double* y, long
     if (ldv < P->n_real || ldy < P->n_real) throw Fail{SC_ERR_ARG, "leading dimension smaller than n_real"};
     if (prec != SC_FP64 && prec != SC_MIXED) throw Fail{SC_ERR_ARG, "unknown precision"};
     if (!P->factored || !P->have_base) throw Fail{SC_ERR_STATE, "call sc_factor and sc_set_base before sc_jvp"};
-    hipStream_t s = (hipStream_t)stream;
-    const long long J = P->baseJ;
-    sc::DevGrid dg = P->dg();
-    if (prec == SC_FP64) {
-      transforms<double>(P, sc::RING_LINEAR, nvec, v, ldv, J, s);
-      {
-        Prof _p(P, SC_STAGE_PROJECT_RHS, s);
-        hipLaunchKernelGGL((sc::k_project_rhs<double, false>), dim3((unsigned)((long long)nvec * P->hg.S)), dim3(128), 0, s,
-                           dg, P->pp(), nvec, (const double*)(P->ws64.as<double>() + P->wl.As),
-                           (const double*)(P->ws64.as<double>() + P->wl.Av), v, ldv, J, P->baseC,
-                           P->MX.as<const double>(), P->bbuf.as<double>());
-      }
-      HIPCHK(hipGetLastError());
-      refined_solve<double>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine64, s);
-    } else {
-      transforms<float>(P, sc::RING_LINEAR, nvec, v, ldv, J, s);
-      {
-        Prof _p(P, SC_STAGE_PROJECT_RHS, s);
-        hipLaunchKernelGGL((sc::k_project_rhs<float, false>), dim3((unsigned)((long long)nvec * P->hg.S)), dim3(128), 0, s,
-                           dg, P->pp(), nvec, (const float*)(P->ws32.as<float>() + P->wl.As),
-                           (const float*)(P->ws32.as<float>() + P->wl.Av), v, ldv, J, P->baseC,
-                           P->MX.as<const double>(), P->bbuf.as<double>());
-      }
-      HIPCHK(hipGetLastError());
-      refined_solve<float>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine32, s);
-    }
-    long long n = (long long)nvec * P->n_real;
-    {
-      Prof _p(P, SC_STAGE_FINALIZE, s);
-      hipLaunchKernelGGL(sc::k_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, dg, nvec, P->xbuf.as<const double>(), v, ldv,
-                         J, y, ldy, 1);
-    }
-    HIPCHK(hipGetLastError());
+    jvp_impl(P, nvec, v, ldv, y, ldy, prec, (hipStream_t)stream);
+  });
+}
+
+int sc_newton(sc_plan* P, double* x, double* C, const sc_newton_opts* o, sc_newton_report* rep, void* stream) {
+  return guarded([&] {
+    check_plan(P);
+    if (!x || !C || !o || !rep) throw Fail{SC_ERR_ARG, "null argument"};
+    if (o->restart < 1 || o->restart > 128) throw Fail{SC_ERR_ARG, "restart must lie in 1..128"};
+    if (o->max_newton < 0 || o->max_newton > 64 || o->max_matvec < 1) throw Fail{SC_ERR_ARG, "bad iteration caps"};
+    if (o->prec != SC_FP64 && o->prec != SC_MIXED) throw Fail{SC_ERR_ARG, "unknown precision"};
+    if (!P->factored) throw Fail{SC_ERR_STATE, "sc_factor has not run for the current (Ek, dt)"};
+    const long long J = check_slot(P, o->J);
+    newton_impl(P, x, C, *o, J, rep, (hipStream_t)stream);
   });
 }
 

@@ -43,8 +43,12 @@ struct DevGrid {
   const double* DT;   // [N][N]
   const double* D2T;
   const double* D4T;
-  const int2* rtiles; // radial-prep tiles: (k, first l-m)
+  const int2* rtiles; // radial-prep tiles: (k, first l-m), up to 16 l
   int nrtiles;
+  const double* PT;   // [Np][N]: P^T
+  const double* DpT;  // [Np][Np]: Dp^T
+  const int2* ptiles; // projection / residual tiles: (k, first l-m), up to 8 l
+  int nptiles;
 };
 
 struct PhysParams {
@@ -148,15 +152,26 @@ __global__ void __launch_bounds__(256) k_radial_prep(DevGrid g, const double* __
 
 // ------------------------------------------------------------------------------------------
 // K2/K6: batched contractions C[i][j] = sum_k A[i][k] B[j][k] on the matrix cores.
-// 64 x 64 output tile per workgroup (4 wavefronts, 32 x 32 each as 2 x 2 MFMA tiles),
-// k staged through LDS 16 at a time.  Problems of one launch are enumerated tile by tile.
+// Output tile BM x 64 per workgroup (BM = 128 in FP32, 64 in FP64); the four wavefronts
+// form a 2 x 2 grid, each owning (BM/2) x 32 as (BM/32) x 2 MFMA 16x16 tiles.  k is staged
+// through LDS 32 at a time, and the next k-slice is fetched into registers while the current
+// one is multiplied.  Problems of one launch are enumerated tile by tile.
+template <class T>
+struct GemmCfg {
+  static constexpr int BM = (sizeof(T) == 4) ? 128 : 64;
+  static constexpr int BN = 64, BK = 32, LDK = BK + 1;
+  static constexpr int TM = BM / 32;                 // MFMA row tiles per wavefront
+  static constexpr int AL = BM * BK / 256;           // A elements loaded per thread
+  static constexpr int BL = BN * BK / 256;           // B elements loaded per thread
+};
+
 template <class T>
 __global__ void __launch_bounds__(256) k_gemm_batched(const GemmProb* __restrict__ probs, int nprob, int nvec,
                                                       const T* __restrict__ ws_in, const T* __restrict__ tab,
                                                       T* __restrict__ ws_out) {
-  constexpr int BM = 64, BN = 64, BK = 16, LDK = BK + 1;
-  __shared__ T As[BM * LDK];
-  __shared__ T Bs[BN * LDK];
+  typedef GemmCfg<T> G;
+  __shared__ T As[G::BM * G::LDK];
+  __shared__ T Bs[G::BN * G::LDK];
   int tile = blockIdx.x;
   int p = 0;
   GemmProb pr;
@@ -164,7 +179,7 @@ __global__ void __launch_bounds__(256) k_gemm_batched(const GemmProb* __restrict
   for (p = 0; p < nprob; ++p) {
     pr = probs[p];
     int M = pr.Mper * nvec;
-    int nt_m = (M + BM - 1) / BM, nt_n = (pr.N + BN - 1) / BN;
+    int nt_m = (M + G::BM - 1) / G::BM, nt_n = (pr.N + G::BN - 1) / G::BN;
     int nt = nt_m * nt_n;
     if (tile < nt) {
       tm = tile / nt_n;
@@ -179,44 +194,60 @@ __global__ void __launch_bounds__(256) k_gemm_batched(const GemmProb* __restrict
   const T* B = tab + pr.b_off;
   T* C = ws_out + pr.c_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;  // wavefront's 32 x 32 sub-tile
-  typename Mfma<T>::acc_t acc[2][2];
+  const int wm = (wave >> 1) * (G::BM / 2), wn = (wave & 1) * 32;
+  typename Mfma<T>::acc_t acc[G::TM][2];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < G::TM; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[x][y][q] = (T)0;
-  const int i0 = tm * BM, j0 = tn * BN;
-  const int lr = tid / 4, lk = (tid % 4) * 4;  // loader: row, first k
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    {
-      const int gi = i0 + lr, gj = j0 + lr;
+  const int i0 = tm * G::BM, j0 = tn * G::BN;
+  // loader mapping: element e = tid + 256 u of the tile, row = e / BK, k = e % BK
+  T ra[G::AL], rb[G::BL];
+  auto fetch = [&](int k0) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int gk = k0 + lk + q;
-        As[lr * LDK + lk + q] = (gi < M && gk < K) ? A[(long long)gi * pr.lda + gk] : (T)0;
-        Bs[lr * LDK + lk + q] = (gj < N && gk < K) ? B[(long long)gj * pr.ldb + gk] : (T)0;
-      }
+    for (int u = 0; u < G::AL; ++u) {
+      const int e = tid + 256 * u, r = e / G::BK, kk = k0 + e % G::BK, gi = i0 + r;
+      ra[u] = (gi < M && kk < K) ? A[(long long)gi * pr.lda + kk] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < G::BL; ++u) {
+      const int e = tid + 256 * u, r = e / G::BK, kk = k0 + e % G::BK, gj = j0 + r;
+      rb[u] = (gj < N && kk < K) ? B[(long long)gj * pr.ldb + kk] : (T)0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += G::BK) {
+#pragma unroll
+    for (int u = 0; u < G::AL; ++u) {
+      const int e = tid + 256 * u;
+      As[(e / G::BK) * G::LDK + e % G::BK] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < G::BL; ++u) {
+      const int e = tid + 256 * u;
+      Bs[(e / G::BK) * G::LDK + e % G::BK] = rb[u];
     }
     __syncthreads();
+    if (k0 + G::BK < K) fetch(k0 + G::BK);
 #pragma unroll
-    for (int ks = 0; ks < BK / 4; ++ks) {
+    for (int ks = 0; ks < G::BK / 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
-      T a[2], b[2];
+      T a[G::TM], b[2];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) a[x] = As[(wm + x * 16 + (lane & 15)) * LDK + kk];
+      for (int x = 0; x < G::TM; ++x) a[x] = As[(wm + x * 16 + (lane & 15)) * G::LDK + kk];
 #pragma unroll
-      for (int y = 0; y < 2; ++y) b[y] = Bs[(wn + y * 16 + (lane & 15)) * LDK + kk];
+      for (int y = 0; y < 2; ++y) b[y] = Bs[(wn + y * 16 + (lane & 15)) * G::LDK + kk];
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int x = 0; x < G::TM; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<T>::step(a[x], b[y], acc[x][y]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < G::TM; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
@@ -405,93 +436,101 @@ __global__ void __launch_bounds__(256) k_ring(DevGrid g, int nvec, const T* __re
 // K7: curl projections back to the N nodes and assembly of the right-hand side
 //   b = M u + dt (N(u) + Ra lam T/(r r_o) [f only] + C i m M u + c i m M X)
 // with M_e = Ek lam/r^2, M_f = -Ek lam/r^2 (D^2 - lam/r^2), M_T = 1, and boundary rows.
-// MODE_STEP: inhomogeneous T_00 rows, no c-term.  One block per (vec, lm).
+// STEP: inhomogeneous T_00 rows, no c-term.  One workgroup per (tile of up to 8 consecutive l
+// at one m, vector); all radial matrices are read transposed so that consecutive threads
+// touch consecutive entries.
+constexpr int kPT = 4;  // l per projection tile
+
 template <class T, bool STEP>
-__global__ void __launch_bounds__(128) k_project_rhs(DevGrid g, PhysParams ph, int nvec, const T* __restrict__ As,
+__global__ void __launch_bounds__(256) k_project_rhs(DevGrid g, PhysParams ph, int nvec, const T* __restrict__ As,
                                                      const T* __restrict__ Av, const double* __restrict__ v,
                                                      long long ldv, long long J, double C,
                                                      const double* __restrict__ MX, double* __restrict__ b) {
-  __shared__ double sWr[2][128], sQ[2][128], sS[2][128], sTor[2][128], sTf[2][128];
-  __shared__ double su[3][2][64];
-  int blk = blockIdx.x;
-  int lm = blk % g.S, vec = blk / g.S;
-  int k = g.lm_k[lm], l = g.lm_l[lm];
-  int m = k * g.m0;
-  int nl = g.L - m + 1, il = l - m;
+  // [t][c][rp] arrays on the N_p nodes, c = Re/Im; u as [f][t][c][j]; sized exactly (dynamic)
+  extern __shared__ unsigned char smem_raw[];
   const int N = g.N, Np = g.Np;
-  const int tid = threadIdx.x;
-  double lam = (double)l * (l + 1);
-  const long long Ma = (long long)4 * Np * g.vcap;
-  const double* vb = v + (long long)vec * ldv;
-  double* bb = b + (long long)vec * 6LL * N * g.S;
-  // phase-slot value c
-  double cval = 0.0;
-  if (!STEP && J >= 0) cval = v[(long long)vec * ldv + J];
+  double* base_ = reinterpret_cast<double*>(smem_raw);
+  auto A2 = [&](int which, int t, int c) { return base_ + ((which * kPT + t) * 2 + c) * Np; };
+  auto U2 = [&](int f, int t, int c) { return base_ + 5 * kPT * 2 * Np + ((f * kPT + t) * 2 + c) * N; };
+  const int2 tl = g.ptiles[blockIdx.x];
+  const int vec = blockIdx.y;
+  const int k = tl.x, il0 = tl.y;
+  const int m = k * g.m0, nl = g.L - m + 1;
+  const int nt = min(kPT, nl - il0);
+  const int lm0 = g.lmbase[k] + il0;
+  const long long Ma = 4LL * Np * g.vcap;
   const T* as = As + Ma * g.lmbase[k];
   const T* av = Av + Ma * g.lmbase[k];
-  for (int rp = tid; rp < Np; rp += blockDim.x) {
-    long long row = ((long long)vec * Np + rp) * 4;
-    for (int c = 0; c < 2; ++c) {
-      sWr[c][rp] = (double)as[(row + 0 + c) * nl + il];
-      sQ[c][rp] = (double)as[(row + 2 + c) * nl + il];
-      sS[c][rp] = (double)av[(row + 0 + c) * nl + il] * g.rp[rp];  // r S
-      sTor[c][rp] = (double)av[(row + 2 + c) * nl + il];
-    }
+  const double* vb = v + (long long)vec * ldv;
+  double* bb = b + (long long)vec * 6LL * N * g.S;
+  double cval = 0.0;
+  if (!STEP && J >= 0) cval = v[(long long)vec * ldv + J];
+  // analysis outputs: rows (vec, rp, q, c), l contiguous
+  for (int idx = threadIdx.x; idx < nt * 8 * Np; idx += blockDim.x) {
+    int t = idx % nt, qc = (idx / nt) % 8, rp = idx / (8 * nt);
+    int q = qc >> 1, c = qc & 1;
+    long long row = ((long long)vec * Np + rp) * 4 + (q & 1) * 2 + c;
+    double val = (q < 2) ? (double)as[row * nl + il0 + t] : (double)av[row * nl + il0 + t];
+    if (q == 2) val *= g.rp[rp];   // r S
+    A2(q, t, c)[rp] = val;          // 0 W_r, 1 Q, 2 r S, 3 Tor
   }
   // cleaned state u at the N nodes
-  for (int j = tid; j < N; j += blockDim.x) {
-    for (int f = 0; f < 3; ++f) {
-      long long o = 2LL * ((long long)N * ((long long)f * g.S + lm) + j);
-      double re = (o == J) ? 0.0 : vb[o];
-      double im = (k == 0 || o + 1 == J) ? 0.0 : vb[o + 1];
-      if (f < 2 && l == 0) re = im = 0.0;
-      su[f][0][j] = re;
-      su[f][1][j] = im;
-    }
+  for (int idx = threadIdx.x; idx < 3 * nt * 2 * N; idx += blockDim.x) {
+    int cj = idx % (2 * N), t = (idx / (2 * N)) % nt, f = idx / (2 * N * nt);
+    int jj = cj >> 1, c = cj & 1;
+    long long o = 2LL * ((long long)N * ((long long)f * g.S + lm0 + t)) + cj;
+    int l = m + il0 + t;
+    double val = vb[o];
+    if (o == J || (c == 1 && k == 0) || (f < 2 && l == 0)) val = 0.0;
+    U2(f, t, c)[jj] = val;
   }
   __syncthreads();
-  for (int rp = tid; rp < Np; rp += blockDim.x) {
-    double r = g.rp[rp];
+  // f-row force on the N_p nodes: (lam/r^2)(W_r - d_r(r S)) -> slot 4; e-row: (lam/r) Tor
+  for (int idx = threadIdx.x; idx < nt * 2 * Np; idx += blockDim.x) {
+    int rp = idx % Np, c = (idx / Np) & 1, t = idx / (2 * Np);
+    int l = m + il0 + t;
+    double lam = (double)l * (l + 1), r = g.rp[rp];
+    const double* rS = A2(2, t, c);
+    double d = 0.0;
+    for (int q = 0; q < Np; ++q) d += g.DpT[(long long)q * Np + rp] * rS[q];
+    A2(4, t, c)[rp] = lam / (r * r) * (A2(0, t, c)[rp] - d);
+    A2(3, t, c)[rp] *= lam / r;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nt * N; idx += blockDim.x) {
+    int jj = idx % N, t = idx / N;
+    int l = m + il0 + t;
+    double lam = (double)l * (l + 1);
+    double ne[2] = {0, 0}, nf[2] = {0, 0}, nq[2] = {0, 0};
     for (int c = 0; c < 2; ++c) {
-      double d = 0.0;
-      for (int q = 0; q < Np; ++q) d += g.Dp[(long long)rp * Np + q] * sS[c][q];
-      sTf[c][rp] = lam / (r * r) * (sWr[c][rp] - d);
-      sTor[c][rp] = lam / r * sTor[c][rp];
-    }
-  }
-  __syncthreads();
-  for (int j = tid; j < N; j += blockDim.x) {
-    double ne[2] = {0, 0}, nf[2] = {0, 0}, nt[2] = {0, 0};
-    const double* Pr = g.P + (long long)j * Np;
-    for (int q = 0; q < Np; ++q) {
-      double pw = Pr[q];
-      for (int c = 0; c < 2; ++c) {
-        ne[c] += pw * sTor[c][q];
-        nf[c] += pw * sTf[c][q];
-        nt[c] += pw * sQ[c][q];
+      const double* to = A2(3, t, c);
+      const double* tf = A2(4, t, c);
+      const double* qq = A2(1, t, c);
+      for (int q = 0; q < Np; ++q) {
+        double pw = g.PT[(long long)q * N + jj];
+        ne[c] += pw * to[q];
+        nf[c] += pw * tf[q];
+        nq[c] += pw * qq[q];
       }
     }
-    double r = g.r[j];
-    double a = ph.Ek * lam / (r * r);
     double d2f[2] = {0, 0};
-    const double* D2r = g.D2 + (long long)j * N;
-    for (int i = 0; i < N; ++i) {
-      d2f[0] += D2r[i] * su[1][0][i];
-      d2f[1] += D2r[i] * su[1][1][i];
+    for (int c = 0; c < 2; ++c) {
+      const double* uf = U2(1, t, c);
+      for (int i = 0; i < N; ++i) d2f[c] += g.D2T[(long long)i * N + jj] * uf[i];
     }
+    double r = g.r[jj];
+    double a = ph.Ek * lam / (r * r);
     double Mu[3][2];
     for (int c = 0; c < 2; ++c) {
-      Mu[0][c] = a * su[0][c][j];
-      Mu[1][c] = -a * (d2f[c] - lam / (r * r) * su[1][c][j]);
-      Mu[2][c] = su[2][c][j];
+      Mu[0][c] = a * U2(0, t, c)[jj];
+      Mu[1][c] = -a * (d2f[c] - lam / (r * r) * U2(1, t, c)[jj]);
+      Mu[2][c] = U2(2, t, c)[jj];
     }
-    double nn[3][2] = {{ne[0], ne[1]}, {nf[0], nf[1]}, {nt[0], nt[1]}};
-    // buoyancy on the f-equation
-    nn[1][0] += ph.Ra * lam * su[2][0][j] / (r * ph.ro);
-    nn[1][1] += ph.Ra * lam * su[2][1][j] / (r * ph.ro);
+    double nn[3][2] = {{ne[0], ne[1]}, {nf[0], nf[1]}, {nq[0], nq[1]}};
+    nn[1][0] += ph.Ra * lam * U2(2, t, 0)[jj] / (r * ph.ro);
+    nn[1][1] += ph.Ra * lam * U2(2, t, 1)[jj] / (r * ph.ro);
     for (int f = 0; f < 3; ++f) {
-      long long o = 2LL * ((long long)N * ((long long)f * g.S + lm) + j);
-      // i m C M u  +  i m c M X
+      long long o = 2LL * ((long long)N * ((long long)f * g.S + lm0 + t) + jj);
       double tr = -m * C * Mu[f][1], ti = m * C * Mu[f][0];
       if (!STEP) {
         tr += -m * cval * MX[o + 1];
@@ -499,13 +538,11 @@ __global__ void __launch_bounds__(128) k_project_rhs(DevGrid g, PhysParams ph, i
       }
       double br = Mu[f][0] + ph.dt * (nn[f][0] + tr);
       double bi = Mu[f][1] + ph.dt * (nn[f][1] + ti);
-      bool bc;
-      if (f == 1) bc = (j == 0 || j == 1 || j == N - 2 || j == N - 1);
-      else bc = (j == 0 || j == N - 1);
+      bool bc = (f == 1) ? (jj == 0 || jj == 1 || jj == N - 2 || jj == N - 1) : (jj == 0 || jj == N - 1);
       if (bc) {
         br = 0.0;
         bi = 0.0;
-        if (STEP && f == 2 && lm == 0 && j == N - 1) br = 1.0;  // T_00(r_i) = 1
+        if (STEP && f == 2 && l == 0 && jj == N - 1) br = 1.0;  // T_00(r_i) = 1
       }
       if (f < 2 && l == 0) br = bi = 0.0;
       bb[o] = br;
@@ -1145,6 +1182,44 @@ __global__ void k_finalize(DevGrid g, int nvec, const double* __restrict__ x, co
   double u = 0.0;
   if (subtract) u = (i == J) ? 0.0 : v[(long long)vec * ldv + i];
   y[(long long)vec * ldy + i] = xv - u;
+}
+
+// ------------------------------------------------------------------------------------------
+// K13: Krylov helpers (FP64).  Partial dot products part[i * nchunk + chunk] of V_i with w over
+// fixed chunks (summed on the host in a fixed order, so results are reproducible).
+__global__ void __launch_bounds__(256) k_dots_partial(const double* __restrict__ V, long long ldv, int k,
+                                                      const double* __restrict__ w, long long n, int nchunk,
+                                                      double* __restrict__ part) {
+  __shared__ double red[256];
+  const int chunk = blockIdx.x, i = blockIdx.y;
+  const long long len = (n + nchunk - 1) / nchunk;
+  const long long a = (long long)chunk * len, b = min(n, a + len);
+  const double* v = V + (long long)i * ldv;
+  double s = 0.0;
+  for (long long t = a + threadIdx.x; t < b; t += blockDim.x) s += v[t] * w[t];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long long)i * nchunk + chunk] = red[0];
+}
+
+// w = alpha * w - sum_i h_i V_i   (alpha = 1: Gram-Schmidt update; the sum runs over i < k)
+__global__ void k_combine(double* __restrict__ w, double alpha, const double* __restrict__ V, long long ldv, int k,
+                          const double* __restrict__ h, long long n) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double acc = alpha * w[t];
+  for (int i = 0; i < k; ++i) acc -= h[i] * V[(long long)i * ldv + t];
+  w[t] = acc;
+}
+
+// dst = alpha * src
+__global__ void k_scale(double* __restrict__ dst, const double* __restrict__ src, double alpha, long long n) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) dst[t] = alpha * src[t];
 }
 
 // Sum of squares per vector into out[vec] (deterministic: one block per vector).

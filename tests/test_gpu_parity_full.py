@@ -122,3 +122,4 @@ def test_jvp_batch_limits(sc):
     with pytest.raises(sc.ShellConvError) as ei:
         plan.jvp(V[:1], V[:1].clone(), sc.SC_FP64)
     assert ei.value.code == 2
+
