@@ -68,7 +68,7 @@ struct WsLayout {
 
 struct TabLayout {
   std::vector<long long> synS, synV, anaS, anaV;
-  long long twc, tws, total;
+  long long fw, total;
 };
 
 }  // namespace
@@ -78,6 +78,7 @@ struct sc_plan {
   sc::HostGrid hg;
   int vcap = 16;
   int refine64 = 1, refine32 = 2;
+  int fft_nr = 0, fft_r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   long long n_real = 0;
   bool factored = false, have_base = false;
   double baseC = 0.0;
@@ -125,6 +126,8 @@ struct sc_plan {
     g.Np = hg.Np;
     g.nth = hg.nth;
     g.nphi = hg.nphi;
+    g.fft_nr = fft_nr;
+    for (int i = 0; i < 8; ++i) g.fft_r[i] = fft_r[i];
     g.K = hg.K;
     g.S = hg.S;
     g.vcap = vcap;
@@ -221,8 +224,7 @@ void build_tables(sc_plan* P) {
     t.anaS[k] = off; off += nth * nl;
     t.anaV[k] = off; off += 2LL * nth * nl;
   }
-  t.twc = off; off += (long long)K1 * g.nphi;
-  t.tws = off; off += (long long)K1 * g.nphi;
+  t.fw = off; off += 2LL * g.nphi;
   t.total = off;
   std::vector<double> h(off, 0.0);
   for (int k = 0; k < K1; ++k) {
@@ -246,13 +248,10 @@ void build_tables(sc_plan* P) {
     }
   }
   const double twopi = 6.283185307179586476925286766559;
-  for (int k = 0; k < K1; ++k)
-    for (int p = 0; p < g.nphi; ++p) {
-      // reduce k p mod nphi exactly before the trigonometric evaluation
-      long long kp = ((long long)k * p) % g.nphi;
-      h[t.twc + (long long)k * g.nphi + p] = std::cos(twopi * (double)kp / g.nphi);
-      h[t.tws + (long long)k * g.nphi + p] = std::sin(twopi * (double)kp / g.nphi);
-    }
+  for (int q = 0; q < g.nphi; ++q) {  // FFT twiddles exp(-2 pi i q / nphi)
+    h[t.fw + 2LL * q] = std::cos(twopi * (double)q / g.nphi);
+    h[t.fw + 2LL * q + 1] = -std::sin(twopi * (double)q / g.nphi);
+  }
   upload(P->tab64, h);
   std::vector<float> hf(h.begin(), h.end());
   upload(P->tab32, hf);
@@ -328,12 +327,13 @@ const double* tab_ptr<double>(sc_plan* P) { return P->tab64.as<double>(); }
 template <>
 const float* tab_ptr<float>(sc_plan* P) { return P->tab32.as<float>(); }
 
-constexpr int kRT = 16;
-
+// Rings per k_ring workgroup: the largest power of two up to 16 whose 5 spectra fit the
+// register staging bound of the in-place FFT passes (-1 if even one ring does not).
 template <class T>
-size_t ring_smem(const sc::HostGrid& g) {
-  int K1 = g.K + 1;
-  return sizeof(T) * ((size_t)2 * 9 * K1 * kRT + (size_t)4 * g.nphi * kRT + (size_t)2 * K1 * g.nphi);
+int ring_rt_log2(const sc::HostGrid& g) {
+  int lg = 4;
+  while (lg >= 0 && 5LL * g.nphi * (1LL << lg) > sc::ring_cap<T>()) --lg;
+  return lg;
 }
 
 // Spectral state -> analysed forces (As, Av) in precision T.  mode: linear/nonlinear/synth.
@@ -356,30 +356,26 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
                        P->nprob_syn, nvec, (const T*)ws, tab, ws);
   }
   HIPCHK(hipGetLastError());
-  int ntile = (g.nth + kRT - 1) / kRT;
+  const int rtl = ring_rt_log2<T>(g);
+  const int ntile = (g.nth + (1 << rtl) - 1) >> rtl;
   dim3 grid((unsigned)((long long)nvec * g.Np * ntile));
-  size_t smem = ring_smem<T>(g);
+  size_t smem = sc::ring_lds_bytes<T>(g.nphi, rtl);
   const T* base = std::is_same<T, double>::value ? (const T*)P->base64.p : (const T*)P->base32.p;
+  const T* fw = tab + P->tl.fw;
   T Ek = (T)P->prm.Ek;
-  if (mode == sc::RING_LINEAR) {
-    {
-      Prof _p(P, SC_STAGE_RING, s);
-      hipLaunchKernelGGL((sc::k_ring<T, sc::RING_LINEAR, kRT>), grid, dim3(256), smem, s, dg, nvec, ws + w.Cs, ws + w.Cv, base,
-                         tab + P->tl.twc, tab + P->tl.tws, Ek, ws + w.Fs, ws + w.Fv, (double*)nullptr, (float*)nullptr);
-    }
-  } else if (mode == sc::RING_NONLINEAR) {
-    {
-      Prof _p(P, SC_STAGE_RING, s);
-      hipLaunchKernelGGL((sc::k_ring<T, sc::RING_NONLINEAR, kRT>), grid, dim3(256), smem, s, dg, nvec, ws + w.Cs, ws + w.Cv,
-                         base, tab + P->tl.twc, tab + P->tl.tws, Ek, ws + w.Fs, ws + w.Fv, (double*)nullptr, (float*)nullptr);
-    }
-  } else {
-    {
-      Prof _p(P, SC_STAGE_RING, s);
-      hipLaunchKernelGGL((sc::k_ring<T, sc::RING_SYNTH, kRT>), grid, dim3(256), smem, s, dg, nvec, ws + w.Cs, ws + w.Cv, base,
-                         tab + P->tl.twc, tab + P->tl.tws, Ek, ws + w.Fs, ws + w.Fv, P->base64.as<double>(),
-                         P->base32.as<float>());
-    }
+  {
+    Prof _p(P, SC_STAGE_RING, s);
+    if (mode == sc::RING_LINEAR)
+      hipLaunchKernelGGL((sc::k_ring<T, sc::RING_LINEAR>), grid, dim3(256), smem, s, dg, nvec, rtl, ws + w.Cs, ws + w.Cv,
+                         base, fw, Ek, ws + w.Fs, ws + w.Fv, (double*)nullptr, (float*)nullptr);
+    else if (mode == sc::RING_NONLINEAR)
+      hipLaunchKernelGGL((sc::k_ring<T, sc::RING_NONLINEAR>), grid, dim3(256), smem, s, dg, nvec, rtl, ws + w.Cs,
+                         ws + w.Cv, base, fw, Ek, ws + w.Fs, ws + w.Fv, (double*)nullptr, (float*)nullptr);
+    else
+      hipLaunchKernelGGL((sc::k_ring<T, sc::RING_SYNTH>), grid, dim3(256), smem, s, dg, nvec, rtl, ws + w.Cs, ws + w.Cv,
+                         base, fw, Ek, ws + w.Fs, ws + w.Fv, P->base64.as<double>(), P->base32.as<float>());
+  }
+  if (mode == sc::RING_SYNTH) {
     HIPCHK(hipGetLastError());
     return;
   }
@@ -800,19 +796,24 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     }
     build_tables(P.get());
     build_workspaces(P.get());
-    const size_t smem64 = ring_smem<double>(g), smem32 = ring_smem<float>(g);
-    if (smem64 > 160 * 1024) throw Fail{SC_ERR_ARG, "azimuthal grid too large for the ring kernel"};
-    if (smem64 > 64 * 1024) {
-      HIPCHK(hipFuncSetAttribute((const void*)sc::k_ring<double, sc::RING_LINEAR, kRT>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem64));
-      HIPCHK(hipFuncSetAttribute((const void*)sc::k_ring<double, sc::RING_NONLINEAR, kRT>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem64));
-      HIPCHK(hipFuncSetAttribute((const void*)sc::k_ring<double, sc::RING_SYNTH, kRT>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem64));
+    {
+      // azimuthal FFT plan: radices 4, then 2, 3, 5
+      int n = g.nphi, nr = 0;
+      P->fft_nr = 0;
+      for (int R : {4, 2, 3, 5})
+        while (n % R == 0) {
+          if (nr == 8) throw Fail{SC_ERR_ARG, "nphi needs more than 8 FFT passes"};
+          P->fft_r[nr++] = R;
+          n /= R;
+        }
+      if (n != 1) throw Fail{SC_ERR_ARG, "nphi must be a product of powers of 2, 3 and 5"};
+      P->fft_nr = nr;
+      if (ring_rt_log2<double>(g) < 0 || ring_rt_log2<float>(g) < 0)
+        throw Fail{SC_ERR_ARG, "nphi too large for the ring kernel"};
+      const size_t smem64 = sc::ring_lds_bytes<double>(g.nphi, ring_rt_log2<double>(g));
+      const size_t smem32 = sc::ring_lds_bytes<float>(g.nphi, ring_rt_log2<float>(g));
+      if (smem64 > 64 * 1024 || smem32 > 64 * 1024) throw Fail{SC_ERR_INTERNAL, "ring LDS above 64 KB"};
     }
-    if (smem32 > 64 * 1024)
-      HIPCHK(hipFuncSetAttribute((const void*)sc::k_ring<float, sc::RING_LINEAR, kRT>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem32));
     {
       const size_t s64 = scan_smem<double>(g.N), s32 = scan_smem<float>(g.N);
       if (s64 > 160 * 1024) throw Fail{SC_ERR_ARG, "N too large for the chain solve"};

@@ -47,8 +47,10 @@ struct DevGrid {
   int nrtiles;
   const double* PT;   // [Np][N]: P^T
   const double* DpT;  // [Np][Np]: Dp^T
-  const int2* ptiles; // projection / residual tiles: (k, first l-m), up to 8 l
+  const int2* ptiles; // projection tiles: (k, first l-m)
   int nptiles;
+  int fft_nr;         // azimuthal FFT: number of passes and their radices (each 2, 3, 4 or 5)
+  int fft_r[8];
 };
 
 struct PhysParams {
@@ -260,98 +262,246 @@ __global__ void __launch_bounds__(256) k_gemm_batched(const GemmProb* __restrict
 
 // ------------------------------------------------------------------------------------------
 // K3/K4/K5: per ring (vec, r_p, theta): combine the synthesized Legendre sums into the
-// Fourier coefficients of the 9 physical fields (U, omega, grad T), inverse DFT along phi,
-// pointwise products, forward DFT of (W_r, W_theta, W_phi, Q), and write the analysis inputs.
+// Fourier coefficients of the 9 physical fields (U, omega, grad T), inverse real FFT along
+// phi, pointwise products, forward real FFT of (W_r, W_theta, W_phi, Q), and write the
+// analysis inputs.  The FFTs are mixed-radix Stockham passes (radix 4, 2, 3, 5) between two
+// LDS buffers; two real signals travel as the real and imaginary parts of one complex
+// transform, so a ring needs 5 inverse and 2 forward complex transforms of length N_phi.
+// A workgroup holds 2^rt_log2 rings of one (vec, r_p).
 // MODE 0: linearized products about the cached base fields,
 // MODE 1: nonlinear products of the fields themselves,
 // MODE 2: synthesis only, the 9 fields are written to base (and base32 if non-null).
 enum { RING_LINEAR = 0, RING_NONLINEAR = 1, RING_SYNTH = 2 };
 
-template <class T, int MODE, int RT>
-__global__ void __launch_bounds__(256) k_ring(DevGrid g, int nvec, const T* __restrict__ Cs, const T* __restrict__ Cv,
-                                              const T* __restrict__ base, const T* __restrict__ twc,
-                                              const T* __restrict__ tws, T Ek, T* __restrict__ Fs,
-                                              T* __restrict__ Fv, double* __restrict__ base_out64,
-                                              float* __restrict__ base_out32) {
-  extern __shared__ unsigned char smem_raw[];
-  T* sm = reinterpret_cast<T*>(smem_raw);
-  const int K1 = g.K + 1, nphi = g.nphi, nth = g.nth;
-  T* coef = sm;                                  // [9][K1][RT] complex -> 2 arrays
-  T* coefr = coef;                               // [(f*K1 + k)*RT + tt]
-  T* coefi = coef + 9 * K1 * RT;
-  T* vals = coefi + 9 * K1 * RT;                 // [4][nphi][RT]
-  T* tc = vals + 4 * nphi * RT;                  // [K1][nphi]
-  T* ts = tc + K1 * nphi;
-  const int ntile = (nth + RT - 1) / RT;
-  int blk = blockIdx.x;
-  int tile = blk % ntile;
-  int vr = blk / ntile;  // vec * Np + rp
-  int rp = vr % g.Np;
-  const int th0 = tile * RT;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < K1 * nphi; i += blockDim.x) {
-    tc[i] = twc[i];
-    ts[i] = tws[i];
+template <class T>
+struct cz {
+  T re, im;
+};
+
+// In-place R-point DFT X_k = sum_n v_n exp(sgn 2 pi i n k / R), sgn = +-1.
+template <class T, int R>
+__device__ inline void small_dft(cz<T>* v, T sgn) {
+  if (R == 2) {
+    const cz<T> a = v[0], b = v[1];
+    v[0] = {a.re + b.re, a.im + b.im};
+    v[1] = {a.re - b.re, a.im - b.im};
+  } else if (R == 4) {
+    const cz<T> a = v[0], b = v[1], c = v[2], d = v[3];
+    const cz<T> s0 = {a.re + c.re, a.im + c.im}, s1 = {a.re - c.re, a.im - c.im};
+    const cz<T> s2 = {b.re + d.re, b.im + d.im}, s3 = {b.re - d.re, b.im - d.im};
+    const cz<T> is3 = {-sgn * s3.im, sgn * s3.re};  // sgn i s3
+    v[0] = {s0.re + s2.re, s0.im + s2.im};
+    v[2] = {s0.re - s2.re, s0.im - s2.im};
+    v[1] = {s1.re + is3.re, s1.im + is3.im};
+    v[3] = {s1.re - is3.re, s1.im - is3.im};
+  } else if (R == 3) {
+    const T h = (T)0.86602540378443864676;  // sin(2 pi / 3)
+    const cz<T> a = v[0], t = {v[1].re + v[2].re, v[1].im + v[2].im}, u = {v[1].re - v[2].re, v[1].im - v[2].im};
+    const cz<T> m = {a.re - (T)0.5 * t.re, a.im - (T)0.5 * t.im};
+    const cz<T> iu = {-sgn * h * u.im, sgn * h * u.re};
+    v[0] = {a.re + t.re, a.im + t.im};
+    v[1] = {m.re + iu.re, m.im + iu.im};
+    v[2] = {m.re - iu.re, m.im - iu.im};
+  } else {  // R == 5
+    const T c1 = (T)0.30901699437494742410, s1 = (T)0.95105651629515357212;   // cos, sin(2 pi/5)
+    const T c2 = (T)-0.80901699437494742410, s2 = (T)0.58778525229247312917;  // cos, sin(4 pi/5)
+    const cz<T> a = v[0];
+    const cz<T> t1 = {v[1].re + v[4].re, v[1].im + v[4].im}, u1 = {v[1].re - v[4].re, v[1].im - v[4].im};
+    const cz<T> t2 = {v[2].re + v[3].re, v[2].im + v[3].im}, u2 = {v[2].re - v[3].re, v[2].im - v[3].im};
+    const cz<T> p1 = {a.re + c1 * t1.re + c2 * t2.re, a.im + c1 * t1.im + c2 * t2.im};
+    const cz<T> p2 = {a.re + c2 * t1.re + c1 * t2.re, a.im + c2 * t1.im + c1 * t2.im};
+    const cz<T> q1 = {s1 * u1.re + s2 * u2.re, s1 * u1.im + s2 * u2.im};
+    const cz<T> q2 = {s2 * u1.re - s1 * u2.re, s2 * u1.im - s1 * u2.im};
+    const cz<T> iq1 = {-sgn * q1.im, sgn * q1.re}, iq2 = {-sgn * q2.im, sgn * q2.re};
+    v[0] = {a.re + t1.re + t2.re, a.im + t1.im + t2.im};
+    v[1] = {p1.re + iq1.re, p1.im + iq1.im};
+    v[4] = {p1.re - iq1.re, p1.im - iq1.im};
+    v[2] = {p2.re + iq2.re, p2.im + iq2.im};
+    v[3] = {p2.re - iq2.re, p2.im - iq2.im};
   }
-  // step A: gather coefficients
-  const long long Ms = (long long)6 * g.Np * g.vcap, Mv = (long long)10 * g.Np * g.vcap;
-  for (int idx = tid; idx < K1 * RT; idx += blockDim.x) {
-    int tt = idx % RT, k = idx / RT;
-    int th = th0 + tt;
-    T c[26];
-    if (th < nth) {
-      const T* cs = Cs + (long long)k * Ms * nth + ((long long)vr * 6) * nth + th;
+}
+
+// Layout of the transforms of a workgroup in LDS: transform t lives at
+// (t / per) * stride + (t % per) * N (per transforms of each ring, consecutive).
+struct FftSet {
+  int ntr, per, stride;
+};
+
+constexpr int kRingThreads = 256;
+
+// Most complex values a k_ring workgroup transforms at once (5 spectra of 2^rt_log2 rings of
+// N_phi points); bounds the butterflies each thread holds in registers during a pass.
+template <class T>
+__host__ __device__ constexpr int ring_cap() {
+  return sizeof(T) == 4 ? 4096 : 2048;
+}
+
+// One radix-R Stockham pass (Ns = product of the radices of the earlier passes), in place:
+// every thread first reads and transforms its butterflies into registers, then, after a
+// barrier, all of them write.  w[m] = exp(-2 pi i m / N); the inverse (sgn = +1) uses its
+// conjugate.  Requires fs.ntr * N <= ring_cap<T>().  Kept out of line so that the register
+// staging of the four radices is not allocated side by side in the caller.
+template <class T, int R>
+__device__ __attribute__((noinline)) void stockham_pass(cz<T>* buf, int N, int Ns, FftSet fs, const cz<T>* __restrict__ w, T sgn) {
+  constexpr int MAXB = (ring_cap<T>() + R * kRingThreads - 1) / (R * kRingThreads);
+  const int nb = N / R, step = N / (Ns * R), total = fs.ntr * nb;
+  cz<T> v[MAXB][R];
+  int dst[MAXB];
 #pragma unroll
-      for (int q = 0; q < 6; ++q) c[q] = cs[(long long)q * nth];
-      const T* cv = Cv + (long long)k * Mv * 2 * nth + ((long long)vr * 10) * 2 * nth + th;
+  for (int b = 0; b < MAXB; ++b) {
+    const int idx = threadIdx.x + b * kRingThreads;
+    dst[b] = -1;
+    if (idx < total) {
+      const int t = idx / nb, j = idx - t * nb;
+      const int o = (t / fs.per) * fs.stride + (t % fs.per) * N;
+      const int k = j % Ns;
 #pragma unroll
-      for (int q = 0; q < 10; ++q) {
-        c[6 + q] = cv[(long long)q * 2 * nth];         // dP part
-        c[16 + q] = cv[(long long)q * 2 * nth + nth];  // mPs part
+      for (int r = 0; r < R; ++r) {
+        cz<T> a = buf[o + j + r * nb];
+        if (r > 0) {
+          const cz<T> tw = w[k * r * step];
+          const T twi = (sgn < 0) ? tw.im : -tw.im;
+          a = {a.re * tw.re - a.im * twi, a.re * twi + a.im * tw.re};
+        }
+        v[b][r] = a;
       }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 26; ++q) c[q] = (T)0;
+      small_dft<T, R>(v[b], sgn);
+      dst[b] = o + (j - k) * R + k;
     }
-    // scalar parts: ur(0,1) wr(2,3) dT(4,5); vector parts q: Su 0, Tu 1, Sw 2, Tw 3, ST 4
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b)
+    if (dst[b] >= 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[dst[b] + r * Ns] = v[b][r];
+    }
+  __syncthreads();
+}
+
+// All passes of the plan's radices over the set, in place.
+template <class T>
+__device__ inline void fft_run(const DevGrid& g, cz<T>* buf, FftSet fs, const cz<T>* w, T sgn) {
+  int Ns = 1;
+  for (int s = 0; s < g.fft_nr; ++s) {
+    const int R = g.fft_r[s];
+    if (R == 4) stockham_pass<T, 4>(buf, g.nphi, Ns, fs, w, sgn);
+    else if (R == 2) stockham_pass<T, 2>(buf, g.nphi, Ns, fs, w, sgn);
+    else if (R == 3) stockham_pass<T, 3>(buf, g.nphi, Ns, fs, w, sgn);
+    else stockham_pass<T, 5>(buf, g.nphi, Ns, fs, w, sgn);
+    Ns *= R;
+  }
+}
+
+// LDS bytes of k_ring for 2^rt_log2 rings per workgroup.
+template <class T>
+__host__ __device__ inline size_t ring_lds_bytes(int nphi, int rt_log2) {
+  return sizeof(cz<T>) * ((size_t)nphi + (size_t)5 * nphi * ((size_t)1 << rt_log2));
+}
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(kRingThreads) k_ring(DevGrid g, int nvec, int rt_log2, const T* __restrict__ Cs,
+                                              const T* __restrict__ Cv, const T* __restrict__ base,
+                                              const T* __restrict__ fw, T Ek, T* __restrict__ Fs, T* __restrict__ Fv,
+                                              double* __restrict__ base_out64, float* __restrict__ base_out32) {
+  extern __shared__ unsigned char smem_raw[];
+  const int K1 = g.K + 1, N = g.nphi, nth = g.nth;
+  const int RT = 1 << rt_log2, rmask = RT - 1;
+  cz<T>* w = reinterpret_cast<cz<T>*>(smem_raw);  // [N] twiddles exp(-2 pi i m / N)
+  cz<T>* X = w + N;                                // [RT][5][N]
+  const int ntile = (nth + RT - 1) >> rt_log2;
+  const int tile = blockIdx.x % ntile;
+  const int vr = blockIdx.x / ntile;  // vec * Np + rp
+  const int rp = vr % g.Np;
+  const int th0 = tile << rt_log2;
+  const int tid = threadIdx.x;
+  // the linearized products read the base fields at the points this thread owns in step C:
+  // issue those loads first so that they overlap the gathers and transforms
+  constexpr int NPT = (ring_cap<T>() / 5 + kRingThreads - 1) / kRingThreads;
+  T bpre[NPT][9];
+  if (MODE == RING_LINEAR) {
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      const int idx = tid + u * kRingThreads;
+      const int tt = idx & rmask, p = idx >> rt_log2;
+      const int th = th0 + tt;
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+        bpre[u][q] = (idx < N * RT && th < nth) ? base[(((long long)rp * 9 + q) * N + p) * nth + th] : (T)0;
+    }
+  }
+  for (int i = tid; i < N; i += kRingThreads) w[i] = {fw[2 * i], fw[2 * i + 1]};
+  // spectra entries K < k < N - K stay zero
+  for (int i = tid; i < RT * 5 * N; i += kRingThreads) X[i] = {(T)0, (T)0};
+  __syncthreads();
+  // step A: gather the Legendre sums and form the Fourier coefficients of the 9 fields,
+  // packing fields (2q, 2q+1) into spectrum q: Z_k = (A_k + i B_k)/2, Z_{N-k} = conj(A_k)/2 +
+  // i conj(B_k)/2 for k >= 1 and Z_0 = Re A_0 + i Re B_0.
+  const long long Ms = (long long)6 * g.Np * g.vcap, Mv = (long long)10 * g.Np * g.vcap;
+  for (int idx = tid; idx < K1 * RT; idx += kRingThreads) {
+    const int tt = idx & rmask, k = idx >> rt_log2;
+    const int th = th0 + tt;
+    if (th >= nth) continue;
+    T c[26];
+    const T* cs = Cs + (long long)k * Ms * nth + ((long long)vr * 6) * nth + th;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) c[q] = cs[(long long)q * nth];
+    const T* cv = Cv + (long long)k * Mv * 2 * nth + ((long long)vr * 10) * 2 * nth + th;
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      c[6 + q] = cv[(long long)q * 2 * nth];         // dP part
+      c[16 + q] = cv[(long long)q * 2 * nth + nth];  // mPs part
+    }
+    // scalar sums: U_r (0,1), w_r (2,3), dT/dr (4,5); vector sums q: S_u 0, T_u 1, S_w 2, T_w 3, T 4
     auto dPr = [&](int q) { return c[6 + 2 * q]; };
     auto dPi = [&](int q) { return c[7 + 2 * q]; };
     auto mPr = [&](int q) { return c[16 + 2 * q]; };
     auto mPi = [&](int q) { return c[17 + 2 * q]; };
-    T fr[9], fi[9];
-    fr[0] = c[0]; fi[0] = c[1];                                   // U_r
-    fr[1] = dPr(0) - mPi(1); fi[1] = dPi(0) + mPr(1);              // U_th = dP Su + i mPs Tu
-    fr[2] = -mPi(0) - dPr(1); fi[2] = mPr(0) - dPi(1);             // U_ph = i mPs Su - dP Tu
-    fr[3] = c[2]; fi[3] = c[3];                                   // w_r
-    fr[4] = dPr(2) - mPi(3); fi[4] = dPi(2) + mPr(3);              // w_th
-    fr[5] = -mPi(2) - dPr(3); fi[5] = mPr(2) - dPi(3);             // w_ph
-    fr[6] = c[4]; fi[6] = c[5];                                   // G_r
-    fr[7] = dPr(4); fi[7] = dPi(4);                               // G_th = dP ST
-    fr[8] = -mPi(4); fi[8] = mPr(4);                              // G_ph = i mPs ST
+    T fr[10], fi[10];
+    fr[0] = c[0]; fi[0] = c[1];                          // U_r
+    fr[1] = dPr(0) - mPi(1); fi[1] = dPi(0) + mPr(1);    // U_th = dP S + i mPs T
+    fr[2] = -mPi(0) - dPr(1); fi[2] = mPr(0) - dPi(1);   // U_ph = i mPs S - dP T
+    fr[3] = c[2]; fi[3] = c[3];                          // w_r
+    fr[4] = dPr(2) - mPi(3); fi[4] = dPi(2) + mPr(3);    // w_th
+    fr[5] = -mPi(2) - dPr(3); fi[5] = mPr(2) - dPi(3);   // w_ph
+    fr[6] = c[4]; fi[6] = c[5];                          // dT/dr
+    fr[7] = dPr(4); fi[7] = dPi(4);                      // (1/r) dT/dth
+    fr[8] = -mPi(4); fi[8] = mPr(4);                     // (1/(r sin)) dT/dph
+    fr[9] = 0; fi[9] = 0;
+    cz<T>* Z = X + tt * 5 * N;
 #pragma unroll
-    for (int f = 0; f < 9; ++f) {
-      coefr[(f * K1 + k) * RT + tt] = fr[f];
-      coefi[(f * K1 + k) * RT + tt] = fi[f];
+    for (int q = 0; q < 5; ++q) {
+      const T ar = fr[2 * q], ai = fi[2 * q], br = fr[2 * q + 1], bi = fi[2 * q + 1];
+      if (k == 0) {
+        Z[q * N] = {ar, br};
+      } else {
+        Z[q * N + k] = {(T)0.5 * (ar - bi), (T)0.5 * (ai + br)};
+        Z[q * N + N - k] = {(T)0.5 * (ar + bi), (T)0.5 * (br - ai)};
+      }
     }
   }
   __syncthreads();
-  // step B: inverse DFT and pointwise products
-  for (int idx = tid; idx < nphi * RT; idx += blockDim.x) {
-    int tt = idx % RT, p = idx / RT;
-    int th = th0 + tt;
-    T f[9];
+  // step B: inverse transforms; spectrum q of a ring becomes field 2q + i field 2q+1
+  fft_run<T>(g, X, FftSet{5 * RT, 5, 5 * N}, w, (T)1);
+  // step C: pointwise products, written in place as slot 0 = W_r + i Q, slot 1 = W_th + i W_ph
 #pragma unroll
-    for (int q = 0; q < 9; ++q) f[q] = (T)0;
-    for (int k = 0; k < K1; ++k) {
-      T cr = tc[k * nphi + p], si = ts[k * nphi + p];
+  for (int u = 0; u < NPT; ++u) {
+    const int idx = tid + u * kRingThreads;
+    if (idx >= N * RT) continue;
+    const int tt = idx & rmask, p = idx >> rt_log2;
+    const int th = th0 + tt;
+    cz<T>* Zr = X + tt * 5 * N;
+    T f[10];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) f[q] += coefr[(q * K1 + k) * RT + tt] * cr - coefi[(q * K1 + k) * RT + tt] * si;
+    for (int q = 0; q < 5; ++q) {
+      f[2 * q] = Zr[q * N + p].re;
+      f[2 * q + 1] = Zr[q * N + p].im;
     }
     if (MODE == RING_SYNTH) {
       if (th < nth) {
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-          long long o = (((long long)rp * 9 + q) * nphi + p) * nth + th;
+          const long long o = (((long long)rp * 9 + q) * N + p) * nth + th;
           base_out64[o] = (double)f[q];
           if (base_out32) base_out32[o] = (float)f[q];
         }
@@ -366,60 +516,49 @@ __global__ void __launch_bounds__(256) k_ring(DevGrid g, int nvec, const T* __re
       W2 = Ek * (f[0] * f[4] - f[1] * f[3]);
       Q = -(f[0] * f[6] + f[1] * f[7] + f[2] * f[8]);
     } else {
-      T b[9];
-      if (th < nth) {
-#pragma unroll
-        for (int q = 0; q < 9; ++q) b[q] = base[(((long long)rp * 9 + q) * nphi + p) * nth + th];
-      } else {
-#pragma unroll
-        for (int q = 0; q < 9; ++q) b[q] = (T)0;
-      }
+      const T* b = bpre[u];
       // W' = Ek (U x w_u + u x Omega), Q' = -(U . grad tau + u . grad T)
       W0 = Ek * ((b[1] * f[5] - b[2] * f[4]) + (f[1] * b[5] - f[2] * b[4]));
       W1 = Ek * ((b[2] * f[3] - b[0] * f[5]) + (f[2] * b[3] - f[0] * b[5]));
       W2 = Ek * ((b[0] * f[4] - b[1] * f[3]) + (f[0] * b[4] - f[1] * b[3]));
       Q = -((b[0] * f[6] + b[1] * f[7] + b[2] * f[8]) + (f[0] * b[6] + f[1] * b[7] + f[2] * b[8]));
     }
-    vals[(0 * nphi + p) * RT + tt] = W0;
-    vals[(1 * nphi + p) * RT + tt] = W1;
-    vals[(2 * nphi + p) * RT + tt] = W2;
-    vals[(3 * nphi + p) * RT + tt] = Q;
+    Zr[p] = {W0, Q};
+    Zr[N + p] = {W1, W2};
   }
   if (MODE == RING_SYNTH) return;
   __syncthreads();
-  // step C: forward DFT, scale (2 - d_k0)/nphi, write analysis inputs
+  // step D: forward transforms of slots 0 and 1 of every ring
+  fft_run<T>(g, X, FftSet{2 * RT, 2, 5 * N}, w, (T)-1);
+  // step E: split the packed pair, scale by (2 - delta_k0)/N_phi, write analysis inputs
   const long long Ma = (long long)4 * g.Np * g.vcap;
-  for (int idx = tid; idx < 3 * K1 * RT; idx += blockDim.x) {
-    int tt = idx % RT;
-    int o = (idx / RT) % 3;
-    int k = idx / (3 * RT);
-    int th = th0 + tt;
+  for (int idx = tid; idx < 2 * K1 * RT; idx += kRingThreads) {
+    const int tt = idx & rmask;
+    const int o = (idx >> rt_log2) & 1;
+    const int k = idx >> (rt_log2 + 1);
+    const int th = th0 + tt;
     if (th >= nth) continue;
-    T sc = (k == 0 ? (T)1 : (T)2) / (T)nphi;
-    if (o < 2) {
-      int src = (o == 0) ? 0 : 3;  // W_r or Q
-      T ar = 0, ai = 0;
-      for (int p = 0; p < nphi; ++p) {
-        T x = vals[(src * nphi + p) * RT + tt];
-        ar += x * tc[k * nphi + p];
-        ai -= x * ts[k * nphi + p];
-      }
-      T* out = Fs + (long long)k * Ma * nth + ((long long)vr * 4 + 2 * o) * nth + th;
-      out[0] = ar * sc;
-      out[nth] = ai * sc;
+    const cz<T>* Z = X + tt * 5 * N + o * N;
+    const T sc = (k == 0 ? (T)1 : (T)2) / (T)N;
+    T ar, ai, br, bi;
+    if (k == 0) {
+      ar = Z[0].re; ai = 0; br = Z[0].im; bi = 0;
     } else {
-      T ar = 0, ai = 0, br = 0, bi = 0;  // W_th, W_ph
-      for (int p = 0; p < nphi; ++p) {
-        T x = vals[(1 * nphi + p) * RT + tt], y = vals[(2 * nphi + p) * RT + tt];
-        T cc = tc[k * nphi + p], ss = ts[k * nphi + p];
-        ar += x * cc;
-        ai -= x * ss;
-        br += y * cc;
-        bi -= y * ss;
-      }
-      ar *= sc; ai *= sc; br *= sc; bi *= sc;
+      const cz<T> zk = Z[k], zm = Z[N - k];
+      ar = (T)0.5 * (zk.re + zm.re);
+      ai = (T)0.5 * (zk.im - zm.im);
+      br = (T)0.5 * (zk.im + zm.im);
+      bi = (T)0.5 * (zm.re - zk.re);
+    }
+    ar *= sc; ai *= sc; br *= sc; bi *= sc;
+    if (o == 0) {  // (W_r, Q)
+      T* out = Fs + (long long)k * Ma * nth + ((long long)vr * 4) * nth + th;
+      out[0 * nth] = ar;
+      out[1 * nth] = ai;
+      out[2 * nth] = br;
+      out[3 * nth] = bi;
+    } else {       // (W_th, W_ph): dP rows (W_th, -W_ph); mPs rows (-i W_ph, -i W_th)
       T* out = Fv + (long long)k * Ma * 2 * nth + ((long long)vr * 4) * 2 * nth + th;
-      // dP rows: (W_th, -W_ph); mPs rows: (-i W_ph, -i W_th)
       out[0 * 2 * nth] = ar;
       out[1 * 2 * nth] = ai;
       out[2 * 2 * nth] = -br;
