@@ -76,7 +76,7 @@ struct TabLayout {
 struct sc_plan {
   sc_params prm{};
   sc::HostGrid hg;
-  int vcap = 16;
+  int vcap = 16, wcap = 16;
   int refine64 = 1, refine32 = 2;
   int fft_nr = 0, fft_r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   long long n_real = 0;
@@ -131,6 +131,7 @@ struct sc_plan {
     g.K = hg.K;
     g.S = hg.S;
     g.vcap = vcap;
+    g.wcap = wcap;
     g.lm_k = d_lmk.as<int>();
     g.lm_l = d_lml.as<int>();
     g.lmbase = d_lmbase.as<int>();
@@ -390,7 +391,7 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
 }
 
 constexpr int kSeg = 8;   // blocks per scan segment
-constexpr int kVG = 16;   // vectors per workgroup in the chain solves
+using sc::kVG;            // vectors per workgroup in the chain solves
 
 size_t project_smem(const sc::HostGrid& g) {
   return sizeof(double) * ((size_t)5 * sc::kPT * 2 * g.Np + (size_t)3 * sc::kPT * 2 * g.N);
@@ -401,50 +402,57 @@ size_t tsolve_smem(const sc::HostGrid& g) {
   return sizeof(F) * ((size_t)g.N * g.N + (size_t)sc::kTV * (g.K + 1) * 2 * g.N);
 }
 
-template <class F>
-size_t scan_smem(int N) {
-  return sizeof(F) * 2 * ((size_t)N * (N + 1) + 3 * (size_t)N * kVG);
+// The seven chain-solve launches for RT = ceil(N/16) row tiles.
+template <class F, int RT>
+void chain_solve_rt(sc_plan* P, int nvec, const double* b, double* x, hipStream_t s) {
+  sc::DevGrid dg = P->dg();
+  const int nvg = (nvec + kVG - 1) / kVG;
+  const bool d = std::is_same<F, double>::value;
+  typedef sc::cpx<F> C;
+  const C* Sinv = (const C*)(d ? P->Sinv64.p : P->Sinv32.p);
+  const C* Gm = (const C*)(d ? P->G64.p : P->G32.p);
+  const C* H = (const C*)(d ? P->H64.p : P->H32.p);
+  const C* Phi = (const C*)(d ? P->Phi64.p : P->Phi32.p);
+  const C* Psi = (const C*)(d ? P->Psi64.p : P->Psi32.p);
+  const F* sr = (const F*)(d ? P->sr64.p : P->sr32.p);
+  const F* scl = (const F*)(d ? P->sc64.p : P->sc32.p);
+  const F* Rg = (const F*)(d ? P->Rg64.p : P->Rg32.p);
+  const F* Cg = (const F*)(d ? P->Cg64.p : P->Cg32.p);
+  C* W = (C*)P->wscan.p;
+  const sc::ChainMeta* ch = P->chains.as<sc::ChainMeta>();
+  const sc::SegMeta* sg = P->segs.as<sc::SegMeta>();
+  const dim3 blk(sc::kSolveThreads);
+  hipLaunchKernelGGL((sc::k_cs_rhs<F, RT>), dim3(P->nblocks, nvg), blk, 0, s, dg, nvec, P->blk_field.as<int>(),
+                     P->blk_lm.as<int>(), Sinv, sr, scl, Rg, b, W);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL((sc::k_cs_fwd_local<F, RT>), dim3(P->nsegs, nvg), blk, 0, s, dg, nvec, sg, Gm, W);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL((sc::k_cs_fwd_bound<F, RT>), dim3(P->nchains, nvg), blk, 0, s, dg, nvec, ch, kSeg, Phi, W);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL((sc::k_cs_fix<F, RT>), dim3(P->nblocks, nvg), blk, 0, s, dg, nvec, P->blk_fsrc.as<int>(), Phi, W);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL((sc::k_cs_bwd_local<F, RT>), dim3(P->nsegs, nvg), blk, 0, s, dg, nvec, sg, H, W);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL((sc::k_cs_bwd_bound<F, RT>), dim3(P->nchains, nvg), blk, 0, s, dg, nvec, ch, kSeg, Psi, W);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL((sc::k_cs_out<F, RT>), dim3(P->nblocks, nvg), blk, 0, s, dg, nvec, P->blk_field.as<int>(),
+                     P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const C*)W, x);
+  HIPCHK(hipGetLastError());
 }
 
 // Implicit solve x = A^{-1} b with factors in precision F (all vectors in canonical FP64).
 template <class F>
 void implicit_solve(sc_plan* P, int nvec, const double* b, double* x, hipStream_t s) {
   sc::DevGrid dg = P->dg();
-  const int nvg = (nvec + kVG - 1) / kVG;
-  bool d = std::is_same<F, double>::value;
-  const F* Sinv = (const F*)(d ? P->Sinv64.p : P->Sinv32.p);
-  const F* Gm = (const F*)(d ? P->G64.p : P->G32.p);
-  const F* H = (const F*)(d ? P->H64.p : P->H32.p);
-  const F* Phi = (const F*)(d ? P->Phi64.p : P->Phi32.p);
-  const F* Psi = (const F*)(d ? P->Psi64.p : P->Psi32.p);
-  const F* sr = (const F*)(d ? P->sr64.p : P->sr32.p);
-  const F* scl = (const F*)(d ? P->sc64.p : P->sc32.p);
-  const F* Rg = (const F*)(d ? P->Rg64.p : P->Rg32.p);
-  const F* Cg = (const F*)(d ? P->Cg64.p : P->Cg32.p);
-  F* W = (F*)P->wscan.p;
-  const size_t smem = scan_smem<F>(P->hg.N);
-  const sc::ChainMeta* ch = P->chains.as<sc::ChainMeta>();
-  const sc::SegMeta* sg = P->segs.as<sc::SegMeta>();
-  const dim3 blk(sc::kSolveThreads);
+  const bool d = std::is_same<F, double>::value;
   {
     Prof _p(P, SC_STAGE_CHAIN_SOLVE, s);
-    hipLaunchKernelGGL((sc::k_cs_rhs<F, kVG>), dim3(P->nblocks, nvg), blk, smem, s, dg, nvec, P->blk_field.as<int>(),
-                       P->blk_lm.as<int>(), Sinv, sr, scl, Rg, b, W);
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_cs_fwd_local<F, kVG>), dim3(P->nsegs, nvg), blk, smem, s, dg, nvec, sg, Gm, W);
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_cs_fwd_bound<F, kVG>), dim3(P->nchains, nvg), blk, smem, s, dg, nvec, ch, sg, Phi, W);
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_cs_fwd_fix<F, kVG>), dim3(P->nblocks, nvg), blk, smem, s, dg, nvec,
-                       P->blk_fsrc.as<int>(), Phi, W);
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_cs_bwd_local<F, kVG>), dim3(P->nsegs, nvg), blk, smem, s, dg, nvec, sg, H, W);
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_cs_bwd_bound<F, kVG>), dim3(P->nchains, nvg), blk, smem, s, dg, nvec, ch, sg, Psi, W);
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_cs_out<F, kVG>), dim3(P->nblocks, nvg), blk, smem, s, dg, nvec, P->blk_field.as<int>(),
-                       P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const F*)W, x);
-    HIPCHK(hipGetLastError());
+    switch ((P->hg.N + 15) / 16) {
+      case 1: chain_solve_rt<F, 1>(P, nvec, b, x, s); break;
+      case 2: chain_solve_rt<F, 2>(P, nvec, b, x, s); break;
+      case 3: chain_solve_rt<F, 3>(P, nvec, b, x, s); break;
+      default: chain_solve_rt<F, 4>(P, nvec, b, x, s); break;
+    }
   }
   const F* Ti = (const F*)(d ? P->Tinv64.p : P->Tinv32.p);
   const F* tr = (const F*)(d ? P->tr64.p : P->tr32.p);
@@ -739,6 +747,7 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     if (!(p.radius_ratio > 0 && p.radius_ratio < 1)) throw Fail{SC_ERR_ARG, "radius_ratio must lie in (0, 1)"};
     if (!(p.Ek > 0) || !(p.Pr > 0) || !(p.dt > 0) || !std::isfinite(p.Ra)) throw Fail{SC_ERR_ARG, "need Ek, Pr, dt > 0 and finite Ra"};
     P->vcap = p.nvec_max > 0 ? p.nvec_max : 16;
+    P->wcap = (P->vcap + kVG - 1) / kVG * kVG;
     P->refine64 = p.refine_fp64 >= 0 ? p.refine_fp64 : 1;
     P->refine32 = p.refine_mixed >= 0 ? p.refine_mixed : 2;
     int ndev = 0;
@@ -815,27 +824,6 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
       if (smem64 > 64 * 1024 || smem32 > 64 * 1024) throw Fail{SC_ERR_INTERNAL, "ring LDS above 64 KB"};
     }
     {
-      const size_t s64 = scan_smem<double>(g.N), s32 = scan_smem<float>(g.N);
-      if (s64 > 160 * 1024) throw Fail{SC_ERR_ARG, "N too large for the chain solve"};
-      auto attr = [](const void* fn, size_t bytes) {
-        if (bytes > 64 * 1024) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-      };
-      attr((const void*)sc::k_cs_rhs<double, kVG>, s64);
-      attr((const void*)sc::k_cs_fwd_local<double, kVG>, s64);
-      attr((const void*)sc::k_cs_fwd_bound<double, kVG>, s64);
-      attr((const void*)sc::k_cs_fwd_fix<double, kVG>, s64);
-      attr((const void*)sc::k_cs_bwd_local<double, kVG>, s64);
-      attr((const void*)sc::k_cs_bwd_bound<double, kVG>, s64);
-      attr((const void*)sc::k_cs_out<double, kVG>, s64);
-      attr((const void*)sc::k_cs_rhs<float, kVG>, s32);
-      attr((const void*)sc::k_cs_fwd_local<float, kVG>, s32);
-      attr((const void*)sc::k_cs_fwd_bound<float, kVG>, s32);
-      attr((const void*)sc::k_cs_fwd_fix<float, kVG>, s32);
-      attr((const void*)sc::k_cs_bwd_local<float, kVG>, s32);
-      attr((const void*)sc::k_cs_bwd_bound<float, kVG>, s32);
-      attr((const void*)sc::k_cs_out<float, kVG>, s32);
-    }
-    {
       const size_t t64 = tsolve_smem<double>(g), t32 = tsolve_smem<float>(g);
       if (t64 > 160 * 1024) throw Fail{SC_ERR_ARG, "too many m for the temperature solve"};
       if (t64 > 64 * 1024)
@@ -905,15 +893,26 @@ int sc_factor(sc_plan* P, void* stream) {
     long long nb = 0;
     for (auto& c : ch) nb += c.n;
     const long long NN = (long long)N * N;
-    std::vector<double> Sinv(2 * nb * NN), Gm(2 * nb * NN), H(2 * nb * NN), Phi(2 * nb * NN), Psi(2 * nb * NN);
+    // blocks in MFMA operand order (see the chain-solve kernels): RT row tiles, 4 RT k-steps,
+    // lane l of (t, s) holds M[16 t + l % 16][4 s + l / 16], zero outside N x N
+    const int RT = (N + 15) / 16, KS = 4 * RT;
+    const long long FB = sc::frag_block_size(RT);
+    std::vector<double> Sinv(2 * nb * FB, 0.0), Gm(2 * nb * FB, 0.0), H(2 * nb * FB, 0.0), Phi(2 * nb * FB, 0.0),
+        Psi(2 * nb * FB, 0.0);
     std::vector<int> bfsrc;
     std::vector<double> sr(nb * N), scv(nb * N), Rg(nb * N), Cg(nb * N);
     long long b = 0;
     auto put = [&](std::vector<double>& dst, const std::vector<sc::cplx>& src, long long bb, int i) {
-      for (long long q = 0; q < NN; ++q) {
-        dst[2 * (bb * NN + q)] = src[(size_t)i * NN + q].real();
-        dst[2 * (bb * NN + q) + 1] = src[(size_t)i * NN + q].imag();
-      }
+      for (int t = 0; t < RT; ++t)
+        for (int ks = 0; ks < KS; ++ks)
+          for (int l = 0; l < 64; ++l) {
+            const int row = 16 * t + l % 16, col = 4 * ks + l / 16;
+            if (row >= N || col >= N) continue;
+            const long long o = bb * FB + ((long long)t * KS + ks) * 64 + l;
+            const sc::cplx v = src[(size_t)i * NN + (size_t)row * N + col];
+            dst[2 * o] = v.real();
+            dst[2 * o + 1] = v.imag();
+          }
     };
     for (int ci = 0; ci < (int)ch.size(); ++ci) {
       auto& c = ch[ci];
@@ -963,7 +962,8 @@ int sc_factor(sc_plan* P, void* stream) {
     up2(P->H64, P->H32, H);
     up2(P->Phi64, P->Phi32, Phi);
     up2(P->Psi64, P->Psi32, Psi);
-    P->wscan.alloc((size_t)P->vcap * nb * N * 2 * sizeof(double));
+    P->wscan.alloc((size_t)P->wcap * nb * N * 2 * sizeof(double));
+    HIPCHK(hipMemset(P->wscan.p, 0, (size_t)P->wcap * nb * N * 2 * sizeof(double)));
     up2(P->sr64, P->sr32, sr);
     up2(P->sc64, P->sc32, scv);
     up2(P->Rg64, P->Rg32, Rg);

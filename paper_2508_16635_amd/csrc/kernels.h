@@ -23,6 +23,7 @@ struct GemmProb {
 struct DevGrid {
   int L, m0, N, Np, nth, nphi, K, S;
   int vcap;           // vector capacity of the workspaces (block strides use it)
+  int wcap;           // column stride of the chain-solve work vectors (vcap rounded up to 16)
   const int* lm_k;    // [S]
   const int* lm_l;    // [S]
   const int* lmbase;  // [K+1]
@@ -739,9 +740,16 @@ __global__ void k_apply_M(DevGrid g, PhysParams ph, const double* __restrict__ X
 // and xi the local recurrences started from zero.  Launches: c (all blocks), local forward
 // (per segment), forward boundary pass (per chain), forward fix-up (all blocks), local
 // backward (per segment), backward boundary pass (per chain), backward fix-up and output
-// (all blocks).  The sequential loops prefetch the next block into registers while the
-// current one is applied from LDS.
-// Work vectors live in W[(block*N + j)*vcap + vec] (complex, precision F, scaled space).
+// (all blocks).
+//
+// Every step is y = w + sign M x for one complex N x N block M and 16 right-hand sides, done
+// as four real 16x16x4 MFMA products per k-step (Re/Im split).  The blocks are stored in the
+// MFMA operand order: with RT = ceil(N/16) row tiles and 4 RT k-steps, lane l of
+// (row tile t, k-step s) holds M[16t + l%16][4s + l/16] (zero outside N x N), so wave t of
+// the workgroup streams its operands with fully coalesced loads straight into registers,
+// one step ahead of their use.  x sits in LDS (64 rows x 16 columns, rows >= N zero).
+// Work vectors live in W[(block*N + j)*wcap + vec] (complex, precision F, scaled space);
+// wcap is a multiple of 16 and the columns beyond nvec carry zeros.
 struct ChainMeta {
   int start, n, k, first_seg, nseg, pad0, pad1, pad2;
 };
@@ -755,372 +763,285 @@ struct cpx {
 };
 
 constexpr int kSolveThreads = 256;
-constexpr int kPF = 16;   // complex block entries per thread: ceil(64 * 64 / 256)
-constexpr int kVPF = 4;   // complex vector entries per thread: ceil(64 * 16 / 256)
+constexpr int kVG = 16;  // right-hand sides per workgroup (the MFMA column count)
 
-// One N x N complex block in registers (coalesced load), then into LDS with padded rows.
-// Re and Im are kept in separate arrays so the compiler keeps them in registers.
+// complex entries of one block in MFMA operand order
+__host__ __device__ constexpr int frag_block_size(int rt) { return 256 * rt * rt; }
+
+template <class F, int RT>
+struct ChainOps {
+  static constexpr int KS = 4 * RT;
+  static constexpr int FB = 256 * RT * RT;
+  typedef typename Mfma<F>::acc_t acc_t;
+
+  // registers of one step: operand fragments of this wave's row tile and its w rows
+  struct Set {
+    F ar[KS], ai[KS];
+    cpx<F> w[4];
+  };
+
+  int N, wcap, w, l, col;
+  int rowc[4];  // output rows of this lane, clamped into [0, N)
+
+  __device__ ChainOps(int N_, int wcap_) : N(N_), wcap(wcap_) {
+    w = threadIdx.x >> 6;
+    l = threadIdx.x & 63;
+    col = l & 15;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = 16 * w + Mfma<F>::out_row(l, q);
+      rowc[q] = row < N ? row : N - 1;
+    }
+  }
+  __device__ inline bool active() const { return w < RT; }
+  __device__ inline int row(int q) const { return 16 * w + Mfma<F>::out_row(l, q); }
+
+  __device__ inline void load_frag(const cpx<F>* __restrict__ frags, long long blk, Set& S) const {
+    const cpx<F>* p = frags + blk * FB + (long long)w * KS * 64 + l;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const cpx<F> v = p[ks * 64];
+      S.ar[ks] = v.re;
+      S.ai[ks] = v.im;
+    }
+  }
+  __device__ inline void load_w(const cpx<F>* __restrict__ W, long long blk, int v0, Set& S) const {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) S.w[q] = W[(blk * N + rowc[q]) * wcap + v0 + col];
+  }
+  // acc = M x for this wave's row tile; x = 64 x 16 complex in LDS
+  __device__ inline void apply(const Set& S, const cpx<F>* x, acc_t& yr, acc_t& yi) const {
+    acc_t r0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0}, i0 = {0, 0, 0, 0}, i1 = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const cpx<F> xv = x[(4 * ks + (l >> 4)) * kVG + col];
+      r0 = Mfma<F>::step(S.ar[ks], xv.re, r0);
+      r1 = Mfma<F>::step(-S.ai[ks], xv.im, r1);
+      i0 = Mfma<F>::step(S.ar[ks], xv.im, i0);
+      i1 = Mfma<F>::step(S.ai[ks], xv.re, i1);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      yr[q] = r0[q] + r1[q];
+      yi[q] = i0[q] + i1[q];
+    }
+  }
+};
+
+// x block of W (or zero) into a 64 x 16 LDS buffer; the second buffer (if any) is zeroed.
 template <class F>
-struct BlkRegs {
-  F re[kPF], im[kPF];
-  int off[kPF];  // LDS slot of each register entry (row * (N+1) + col), -1 if unused
-  __device__ inline void init(int N) {
-#pragma unroll
-    for (int u = 0; u < kPF; ++u) {
-      int i = threadIdx.x + u * kSolveThreads;
-      off[u] = (i < N * N) ? (i / N) * (N + 1) + (i % N) : -1;
-    }
-  }
-  __device__ inline void load(const F* __restrict__ gmat, int N) {
-#pragma unroll
-    for (int u = 0; u < kPF; ++u) {
-      int i = threadIdx.x + u * kSolveThreads;
-      if (i < N * N) {
-        re[u] = gmat[2 * i];
-        im[u] = gmat[2 * i + 1];
-      }
-    }
-  }
-  __device__ inline void to_lds(cpx<F>* sm, int N) const {
-#pragma unroll
-    for (int u = 0; u < kPF; ++u)
-      if (off[u] >= 0) {
-        sm[off[u]].re = re[u];
-        sm[off[u]].im = im[u];
-      }
-  }
-};
-
-// One work vector group W[b][j][v0 .. v0+nv) in registers.
-template <class F, int VG>
-struct VecRegs {
-  F re[kVPF], im[kVPF];
-  __device__ inline void load(const F* __restrict__ W, int vcap, int b, int v0, int N, int nv) {
-#pragma unroll
-    for (int u = 0; u < kVPF; ++u) {
-      int idx = threadIdx.x + u * kSolveThreads;
-      int vv = idx % VG, j = idx / VG;
-      if (j < N && vv < nv) {
-        long long o = 2 * (((long long)b * N + j) * vcap + v0 + vv);
-        re[u] = W[o];
-        im[u] = W[o + 1];
-      }
-    }
-  }
-  __device__ inline void to_lds(cpx<F>* dst, int N) const {
-#pragma unroll
-    for (int u = 0; u < kVPF; ++u) {
-      int idx = threadIdx.x + u * kSolveThreads;
-      if (idx < N * VG) {
-        dst[idx].re = re[u];
-        dst[idx].im = im[u];
-      }
-    }
-  }
-};
-
-// acc(j, vv) += sign * sum_q M[j][q] v[q][vv] (M in LDS with row stride N+1) for the
-// thread's own entries idx = j * VG + vv, idx = threadIdx.x + 256 u.
-template <class F, int VG>
-__device__ inline void mv_acc(const cpx<F>* M, const cpx<F>* v, cpx<F>* acc, int N, int nv, F sign) {
-  for (int idx = threadIdx.x; idx < N * VG; idx += kSolveThreads) {
-    const int vv = idx % VG, j = idx / VG;
-    if (vv >= nv) continue;
-    F ar = 0, ai = 0;
-    const cpx<F>* Mr = M + j * (N + 1);
-#pragma unroll 4
-    for (int q = 0; q < N; ++q) {
-      const cpx<F> m = Mr[q], x = v[q * VG + vv];
-      ar += m.re * x.re - m.im * x.im;
-      ai += m.re * x.im + m.im * x.re;
-    }
-    acc[idx].re += sign * ar;
-    acc[idx].im += sign * ai;
+__device__ inline void stage_x(const cpx<F>* __restrict__ W, int N, int wcap, long long blk, int v0, cpx<F>* xa,
+                               cpx<F>* xb_zero) {
+  for (int idx = threadIdx.x; idx < 64 * kVG; idx += kSolveThreads) {
+    const int r = idx / kVG, c = idx % kVG;
+    xa[idx] = (r < N && blk >= 0) ? W[(blk * N + r) * wcap + v0 + c] : cpx<F>{0, 0};
+    if (xb_zero) xb_zero[idx] = cpx<F>{0, 0};
   }
 }
 
-template <class F, int VG>
-__device__ inline void store_w(F* __restrict__ W, int vcap, int b, int v0, const cpx<F>* srcv, int N, int nv) {
-  cpx<F>* dst = reinterpret_cast<cpx<F>*>(W);
-  for (int idx = threadIdx.x; idx < N * VG; idx += kSolveThreads) {
-    int vv = idx % VG, j = idx / VG;
-    if (vv < nv) dst[((long long)b * N + j) * vcap + v0 + vv] = srcv[idx];
+// Sequential walk: x_0 = W[blk(0)], then for t = 1..nsteps: W[blk(t)] = W[blk(t)] +
+// sign M_{blk(t)} x_{t-1}, x_t = that result.  Two register sets alternate so that the operands
+// of step t+1 load while step t computes.
+template <class F, int RT, class BlockOf>
+__device__ inline void chain_walk(int N, int wcap, const cpx<F>* __restrict__ frags, cpx<F>* __restrict__ W, int v0,
+                                  int nsteps, BlockOf blk_of, F sign, cpx<F>* xbuf) {
+  typedef ChainOps<F, RT> Ops;
+  Ops op(N, wcap);
+  typename Ops::Set S0, S1;
+  stage_x<F>(W, N, wcap, blk_of(0), v0, xbuf, xbuf + 64 * kVG);
+  auto load = [&](int t, typename Ops::Set& S) {
+    const long long b = blk_of(t < nsteps ? t : nsteps);
+    op.load_frag(frags, b, S);
+    op.load_w(W, b, v0, S);
+  };
+  if (op.active()) load(1, S0);
+  __syncthreads();
+  auto body = [&](int t, typename Ops::Set& cur, typename Ops::Set& nxt, int pb) {
+    if (op.active()) {
+      load(t + 1, nxt);
+      __builtin_amdgcn_sched_barrier(0);
+      typename Ops::acc_t yr, yi;
+      op.apply(cur, xbuf + pb * 64 * kVG, yr, yi);
+      cpx<F>* xo = xbuf + (pb ^ 1) * 64 * kVG;
+      const long long b = blk_of(t);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = op.row(q);
+        if (r < N) {
+          const cpx<F> y = {cur.w[q].re + sign * yr[q], cur.w[q].im + sign * yi[q]};
+          xo[r * kVG + op.col] = y;
+          W[(b * N + r) * wcap + v0 + op.col] = y;
+        }
+      }
+    }
+    __syncthreads();
+  };
+  int pb = 0;
+  for (int t = 1; t <= nsteps; t += 2) {
+    body(t, S0, S1, pb);
+    pb ^= 1;
+    if (t + 1 <= nsteps) {
+      body(t + 1, S1, S0, pb);
+      pb ^= 1;
+    }
   }
 }
 
-template <class F, int VG>
-__device__ inline void load_w(const F* __restrict__ W, int vcap, int b, int v0, cpx<F>* dst, int N, int nv) {
-  const cpx<F>* src = reinterpret_cast<const cpx<F>*>(W);
-  for (int idx = threadIdx.x; idx < N * VG; idx += kSolveThreads) {
-    int vv = idx % VG, j = idx / VG;
-    if (vv < nv) dst[idx] = src[((long long)b * N + j) * vcap + v0 + vv];
-  }
-}
-
-// LDS carve-up shared by the solve kernels: one padded block and three vector groups.
-template <class F, int VG>
-struct SolveLds {
-  cpx<F>* M;
-  cpx<F>* a;
-  cpx<F>* b;
-  cpx<F>* c;
-  __device__ SolveLds(unsigned char* raw, int N) {
-    M = reinterpret_cast<cpx<F>*>(raw);
-    a = M + N * (N + 1);
-    b = a + N * VG;
-    c = b + N * VG;
-  }
-};
-
-// c_i = D_i t_i for every block (parallel over blocks).
-template <class F, int VG>
-__global__ void __launch_bounds__(256, 1) k_cs_rhs(DevGrid g, int nvec, const int* __restrict__ blk_field,
-                                                const int* __restrict__ blk_lm, const F* __restrict__ Sinv,
-                                                const F* __restrict__ sr, const F* __restrict__ scl,
-                                                const F* __restrict__ Rg, const double* __restrict__ bvec,
-                                                F* __restrict__ W) {
-  extern __shared__ unsigned char smem_raw[];
+// c_i = diag(sc_i) Shat_i^{-1} diag(Rg_i sr_i) b_i for every block; zero columns beyond nvec.
+template <class F, int RT>
+__global__ void __launch_bounds__(kSolveThreads) k_cs_rhs(DevGrid g, int nvec, const int* __restrict__ blk_field,
+                                                         const int* __restrict__ blk_lm, const cpx<F>* __restrict__ Sinv,
+                                                         const F* __restrict__ sr, const F* __restrict__ scl,
+                                                         const F* __restrict__ Rg, const double* __restrict__ bvec,
+                                                         cpx<F>* __restrict__ W) {
+  __shared__ cpx<F> xs[64 * kVG];
+  typedef ChainOps<F, RT> Ops;
   const int N = g.N;
-  SolveLds<F, VG> L(smem_raw, N);
-  const int blk = blockIdx.x, v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
+  Ops op(N, g.wcap);
+  const int blk = blockIdx.x, v0 = blockIdx.y * kVG, nv = min(kVG, nvec - v0);
+  typename Ops::Set S;
+  if (op.active()) op.load_frag(Sinv, blk, S);
   const long long ld = 6LL * N * g.S;
   const long long o = 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + blk_lm[blk]));
-  BlkRegs<F> R;
-  R.init(N);
-  R.load(Sinv + 2LL * N * N * blk, N);
-  for (int idx = threadIdx.x; idx < N * VG; idx += kSolveThreads) {
-    int vv = idx % VG, j = idx / VG;
-    L.b[idx].re = L.b[idx].im = 0;
-    if (vv >= nv) continue;
-    const double* bp = bvec + (long long)(v0 + vv) * ld + o + 2 * j;
-    F s = Rg[(long long)blk * N + j] * sr[(long long)blk * N + j];
-    L.a[idx].re = s * (F)bp[0];
-    L.a[idx].im = s * (F)bp[1];
+  for (int idx = threadIdx.x; idx < 64 * kVG; idx += kSolveThreads) {
+    const int r = idx / kVG, c = idx % kVG;
+    cpx<F> v = {0, 0};
+    if (r < N && c < nv) {
+      const double* bp = bvec + (long long)(v0 + c) * ld + o + 2 * r;
+      const F sc = Rg[(long long)blk * N + r] * sr[(long long)blk * N + r];
+      v = {sc * (F)bp[0], sc * (F)bp[1]};
+    }
+    xs[idx] = v;
   }
-  R.to_lds(L.M, N);
   __syncthreads();
-  mv_acc<F, VG>(L.M, L.a, L.b, N, nv, (F)1);
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < N * VG; idx += kSolveThreads) {
-    F c = scl[(long long)blk * N + idx / VG];
-    L.b[idx].re *= c;
-    L.b[idx].im *= c;
+  if (op.active()) {
+    typename Ops::acc_t yr, yi;
+    op.apply(S, xs, yr, yi);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = op.row(q);
+      if (r < N) {
+        const F c = scl[(long long)blk * N + r];
+        W[((long long)blk * N + r) * g.wcap + v0 + op.col] = cpx<F>{c * yr[q], c * yi[q]};
+      }
+    }
   }
-  store_w<F, VG>(W, g.vcap, blk, v0, L.b, N, nv);
 }
 
 // Local forward recurrence per segment: zeta_a = c_a, zeta_i = c_i - G_i zeta_{i-1}.
-template <class F, int VG>
-__global__ void __launch_bounds__(256, 1) k_cs_fwd_local(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
-                                                      const F* __restrict__ Gm, F* __restrict__ W) {
-  extern __shared__ unsigned char smem_raw[];
-  const int N = g.N;
-  SolveLds<F, VG> L(smem_raw, N);
+template <class F, int RT>
+__global__ void __launch_bounds__(kSolveThreads, 1) k_cs_fwd_local(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
+                                                                  const cpx<F>* __restrict__ Gm, cpx<F>* __restrict__ W) {
+  __shared__ cpx<F> xb[2 * 64 * kVG];
   const SegMeta sg = segs[blockIdx.x];
-  const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
-  const long long NN2 = 2LL * N * N;
   if (sg.len <= 1) return;
-  cpx<F>* prev = L.a;
-  cpx<F>* cur = L.b;
-  load_w<F, VG>(W, g.vcap, sg.first_block, v0, prev, N, nv);
-  BlkRegs<F> R;
-  R.init(N);
-  VecRegs<F, VG> V;
-  R.load(Gm + NN2 * (sg.first_block + 1), N);
-  V.load(W, g.vcap, sg.first_block + 1, v0, N, nv);
-  for (int i = 1; i < sg.len; ++i) {
-    const int b = sg.first_block + i;
-    R.to_lds(L.M, N);
-    V.to_lds(cur, N);
-    __syncthreads();
-    if (i + 1 < sg.len) {
-      R.load(Gm + NN2 * (b + 1), N);
-      V.load(W, g.vcap, b + 1, v0, N, nv);
-    }
-    mv_acc<F, VG>(L.M, prev, cur, N, nv, (F)-1);
-    __syncthreads();
-    store_w<F, VG>(W, g.vcap, b, v0, cur, N, nv);
-    cpx<F>* t = prev;
-    prev = cur;
-    cur = t;
-  }
+  const int a = sg.first_block;
+  chain_walk<F, RT>(g.N, g.wcap, Gm, W, blockIdx.y * kVG, sg.len - 1, [&](int t) { return (long long)(a + t); },
+                    (F)-1, xb);
 }
 
 // Boundary pass of the forward recurrence: z_e(p) = zeta_e(p) + Phi_e(p) z_e(p-1).
-template <class F, int VG>
-__global__ void __launch_bounds__(256, 1) k_cs_fwd_bound(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
-                                                      const SegMeta* __restrict__ segs, const F* __restrict__ Phi,
-                                                      F* __restrict__ W) {
-  extern __shared__ unsigned char smem_raw[];
-  const int N = g.N;
-  SolveLds<F, VG> L(smem_raw, N);
+template <class F, int RT>
+__global__ void __launch_bounds__(kSolveThreads, 1) k_cs_fwd_bound(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
+                                                                  int seg, const cpx<F>* __restrict__ Phi,
+                                                                  cpx<F>* __restrict__ W) {
+  __shared__ cpx<F> xb[2 * 64 * kVG];
   const ChainMeta ch = chains[blockIdx.x];
-  const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
   if (ch.nseg <= 1) return;
-  const long long NN2 = 2LL * N * N;
-  auto seg_end = [&](int p) {
-    SegMeta s_ = segs[ch.first_seg + p];
-    return s_.first_block + s_.len - 1;
-  };
-  cpx<F>* prev = L.a;
-  cpx<F>* cur = L.b;
-  load_w<F, VG>(W, g.vcap, seg_end(0), v0, prev, N, nv);
-  BlkRegs<F> R;
-  R.init(N);
-  VecRegs<F, VG> V;
-  R.load(Phi + NN2 * seg_end(1), N);
-  V.load(W, g.vcap, seg_end(1), v0, N, nv);
-  for (int p = 1; p < ch.nseg; ++p) {
-    const int e = seg_end(p);
-    R.to_lds(L.M, N);
-    V.to_lds(cur, N);
-    __syncthreads();
-    if (p + 1 < ch.nseg) {
-      R.load(Phi + NN2 * seg_end(p + 1), N);
-      V.load(W, g.vcap, seg_end(p + 1), v0, N, nv);
-    }
-    mv_acc<F, VG>(L.M, prev, cur, N, nv, (F)1);
-    __syncthreads();
-    store_w<F, VG>(W, g.vcap, e, v0, cur, N, nv);
-    cpx<F>* t = prev;
-    prev = cur;
-    cur = t;
-  }
-}
-
-// Forward fix-up inside segments after the first: z_i = zeta_i + Phi_i z_{a-1} (per block;
-// src[b] = a-1, or -1 when block b needs no fix-up).
-template <class F, int VG>
-__global__ void __launch_bounds__(256, 1) k_cs_fwd_fix(DevGrid g, int nvec, const int* __restrict__ src,
-                                                    const F* __restrict__ Phi, F* __restrict__ W) {
-  extern __shared__ unsigned char smem_raw[];
-  const int N = g.N;
-  const int blk = blockIdx.x;
-  const int sb = src[blk];
-  if (sb < 0) return;
-  SolveLds<F, VG> L(smem_raw, N);
-  const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
-  BlkRegs<F> R;
-  R.init(N);
-  R.load(Phi + 2LL * N * N * blk, N);
-  load_w<F, VG>(W, g.vcap, sb, v0, L.a, N, nv);
-  load_w<F, VG>(W, g.vcap, blk, v0, L.b, N, nv);
-  R.to_lds(L.M, N);
-  __syncthreads();
-  mv_acc<F, VG>(L.M, L.a, L.b, N, nv, (F)1);
-  __syncthreads();
-  store_w<F, VG>(W, g.vcap, blk, v0, L.b, N, nv);
+  const int st = ch.start, n = ch.n;
+  chain_walk<F, RT>(g.N, g.wcap, Phi, W, blockIdx.y * kVG, ch.nseg - 1,
+                    [&](int p) { return (long long)(st + min((p + 1) * seg, n) - 1); }, (F)1, xb);
 }
 
 // Local backward recurrence per segment: xi_e = z_e, xi_i = z_i - H_i xi_{i+1}.
-template <class F, int VG>
-__global__ void __launch_bounds__(256, 1) k_cs_bwd_local(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
-                                                      const F* __restrict__ H, F* __restrict__ W) {
-  extern __shared__ unsigned char smem_raw[];
-  const int N = g.N;
-  SolveLds<F, VG> L(smem_raw, N);
+template <class F, int RT>
+__global__ void __launch_bounds__(kSolveThreads, 1) k_cs_bwd_local(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
+                                                                  const cpx<F>* __restrict__ H, cpx<F>* __restrict__ W) {
+  __shared__ cpx<F> xb[2 * 64 * kVG];
   const SegMeta sg = segs[blockIdx.x];
-  const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
-  const long long NN2 = 2LL * N * N;
   if (sg.len <= 1) return;
   const int e = sg.first_block + sg.len - 1;
-  cpx<F>* prev = L.a;
-  cpx<F>* cur = L.b;
-  load_w<F, VG>(W, g.vcap, e, v0, prev, N, nv);
-  BlkRegs<F> R;
-  R.init(N);
-  VecRegs<F, VG> V;
-  R.load(H + NN2 * (e - 1), N);
-  V.load(W, g.vcap, e - 1, v0, N, nv);
-  for (int b = e - 1; b >= sg.first_block; --b) {
-    R.to_lds(L.M, N);
-    V.to_lds(cur, N);
-    __syncthreads();
-    if (b - 1 >= sg.first_block) {
-      R.load(H + NN2 * (b - 1), N);
-      V.load(W, g.vcap, b - 1, v0, N, nv);
-    }
-    mv_acc<F, VG>(L.M, prev, cur, N, nv, (F)-1);
-    __syncthreads();
-    store_w<F, VG>(W, g.vcap, b, v0, cur, N, nv);
-    cpx<F>* t = prev;
-    prev = cur;
-    cur = t;
-  }
+  chain_walk<F, RT>(g.N, g.wcap, H, W, blockIdx.y * kVG, sg.len - 1, [&](int t) { return (long long)(e - t); },
+                    (F)-1, xb);
 }
 
 // Boundary pass of the backward recurrence: x_a(p) = xi_a(p) + Psi_a(p) x_a(p+1).
-template <class F, int VG>
-__global__ void __launch_bounds__(256, 1) k_cs_bwd_bound(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
-                                                      const SegMeta* __restrict__ segs, const F* __restrict__ Psi,
-                                                      F* __restrict__ W) {
-  extern __shared__ unsigned char smem_raw[];
-  const int N = g.N;
-  SolveLds<F, VG> L(smem_raw, N);
+template <class F, int RT>
+__global__ void __launch_bounds__(kSolveThreads, 1) k_cs_bwd_bound(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
+                                                                  int seg, const cpx<F>* __restrict__ Psi,
+                                                                  cpx<F>* __restrict__ W) {
+  __shared__ cpx<F> xb[2 * 64 * kVG];
   const ChainMeta ch = chains[blockIdx.x];
-  const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
   if (ch.nseg <= 1) return;
-  const long long NN2 = 2LL * N * N;
-  auto seg_start = [&](int p) { return segs[ch.first_seg + p].first_block; };
-  cpx<F>* prev = L.a;
-  cpx<F>* cur = L.b;
-  load_w<F, VG>(W, g.vcap, seg_start(ch.nseg - 1), v0, prev, N, nv);
-  BlkRegs<F> R;
-  R.init(N);
-  VecRegs<F, VG> V;
-  R.load(Psi + NN2 * seg_start(ch.nseg - 2), N);
-  V.load(W, g.vcap, seg_start(ch.nseg - 2), v0, N, nv);
-  for (int p = ch.nseg - 2; p >= 0; --p) {
-    const int a = seg_start(p);
-    R.to_lds(L.M, N);
-    V.to_lds(cur, N);
-    __syncthreads();
-    if (p - 1 >= 0) {
-      R.load(Psi + NN2 * seg_start(p - 1), N);
-      V.load(W, g.vcap, seg_start(p - 1), v0, N, nv);
+  const int st = ch.start, last = ch.nseg - 1;
+  chain_walk<F, RT>(g.N, g.wcap, Psi, W, blockIdx.y * kVG, ch.nseg - 1,
+                    [&](int t) { return (long long)(st + (last - t) * seg); }, (F)1, xb);
+}
+
+// One fix-up step for every block with src[b] >= 0: W[b] = W[b] + M_b W[src[b]].
+template <class F, int RT>
+__global__ void __launch_bounds__(kSolveThreads) k_cs_fix(DevGrid g, int nvec, const int* __restrict__ src,
+                                                         const cpx<F>* __restrict__ M, cpx<F>* __restrict__ W) {
+  __shared__ cpx<F> xs[64 * kVG];
+  typedef ChainOps<F, RT> Ops;
+  const int blk = blockIdx.x;
+  const int sb = src[blk];
+  if (sb < 0) return;
+  const int N = g.N, v0 = blockIdx.y * kVG;
+  Ops op(N, g.wcap);
+  typename Ops::Set S;
+  if (op.active()) {
+    op.load_frag(M, blk, S);
+    op.load_w(W, blk, v0, S);
+  }
+  stage_x<F>(W, N, g.wcap, sb, v0, xs, nullptr);
+  __syncthreads();
+  if (op.active()) {
+    typename Ops::acc_t yr, yi;
+    op.apply(S, xs, yr, yi);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = op.row(q);
+      if (r < N) W[((long long)blk * N + r) * g.wcap + v0 + op.col] = cpx<F>{S.w[q].re + yr[q], S.w[q].im + yi[q]};
     }
-    mv_acc<F, VG>(L.M, prev, cur, N, nv, (F)1);
-    __syncthreads();
-    store_w<F, VG>(W, g.vcap, a, v0, cur, N, nv);
-    cpx<F>* t = prev;
-    prev = cur;
-    cur = t;
   }
 }
 
 // x_i = xi_i + Psi_i x_{a(p+1)} for the blocks not yet final, then x = Cg x~ into the
-// canonical output.  One workgroup per (block, vector group).
-template <class F, int VG>
-__global__ void __launch_bounds__(256, 1) k_cs_out(DevGrid g, int nvec, const int* __restrict__ blk_field,
-                                                const int* __restrict__ blk_lm, const int* __restrict__ blk_next,
-                                                const F* __restrict__ Psi, const F* __restrict__ Cg,
-                                                const F* __restrict__ W, double* __restrict__ xvec) {
-  extern __shared__ unsigned char smem_raw[];
+// canonical FP64 output.  One workgroup per (block, vector group).
+template <class F, int RT>
+__global__ void __launch_bounds__(kSolveThreads) k_cs_out(DevGrid g, int nvec, const int* __restrict__ blk_field,
+                                                         const int* __restrict__ blk_lm, const int* __restrict__ blk_next,
+                                                         const cpx<F>* __restrict__ Psi, const F* __restrict__ Cg,
+                                                         const cpx<F>* __restrict__ W, double* __restrict__ xvec) {
+  __shared__ cpx<F> xs[64 * kVG];
+  typedef ChainOps<F, RT> Ops;
   const int N = g.N;
-  SolveLds<F, VG> L(smem_raw, N);
-  const int blk = blockIdx.x;
-  const int v0 = blockIdx.y * VG, nv = min(VG, nvec - v0);
-  const long long ld = 6LL * N * g.S;
+  Ops op(N, g.wcap);
+  const int blk = blockIdx.x, v0 = blockIdx.y * kVG, nv = min(kVG, nvec - v0);
   const int nx = blk_next[blk];
-  load_w<F, VG>(W, g.vcap, blk, v0, L.b, N, nv);
-  if (nx >= 0) {
-    BlkRegs<F> R;
-  R.init(N);
-    R.load(Psi + 2LL * N * N * blk, N);
-    load_w<F, VG>(W, g.vcap, nx, v0, L.a, N, nv);
-    R.to_lds(L.M, N);
-    __syncthreads();
-    mv_acc<F, VG>(L.M, L.a, L.b, N, nv, (F)1);
+  typename Ops::Set S;
+  if (op.active()) {
+    if (nx >= 0) op.load_frag(Psi, blk, S);
+    op.load_w(W, blk, v0, S);
   }
+  if (nx >= 0) stage_x<F>(W, N, g.wcap, nx, v0, xs, nullptr);
   __syncthreads();
-  const long long o = 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + blk_lm[blk]));
-  for (int idx = threadIdx.x; idx < N * VG; idx += kSolveThreads) {
-    int vv = idx % VG, j = idx / VG;
-    if (vv >= nv) continue;
-    double c = (double)Cg[(long long)blk * N + j];
-    double* xp = xvec + (long long)(v0 + vv) * ld + o + 2 * j;
-    xp[0] = c * (double)L.b[idx].re;
-    xp[1] = c * (double)L.b[idx].im;
+  if (op.active()) {
+    typename Ops::acc_t yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
+    if (nx >= 0) op.apply(S, xs, yr, yi);
+    const long long ld = 6LL * N * g.S;
+    const long long o = 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + blk_lm[blk]));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = op.row(q);
+      if (r < N && op.col < nv) {
+        const double c = (double)Cg[(long long)blk * N + r];
+        double* xp = xvec + (long long)(v0 + op.col) * ld + o + 2 * r;
+        xp[0] = c * (double)(S.w[q].re + yr[q]);
+        xp[1] = c * (double)(S.w[q].im + yi[q]);
+      }
+    }
   }
 }
 
