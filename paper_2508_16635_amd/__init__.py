@@ -60,6 +60,9 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2508_16635_amd.build`")
+    # torch's HIP runtime must be the one in the process: loading the library first would bind
+    # its libamdhip64 dependency to another copy and leave torch without a device
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i, d, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
     sig = {

@@ -86,6 +86,7 @@ struct sc_plan {
   // grid / radial data
   DevBuf d_lmk, d_lml, d_lmbase, d_r, d_rp, d_E, d_ED, d_ED2, d_P, d_Dp, d_D, d_D2, d_D4;
   DevBuf d_ET, d_EDT, d_ED2T, d_DT, d_D2T, d_D4T, d_rtiles, d_PT, d_DpT, d_ptiles;
+  DevBuf d_EF;
   int nrtiles = 0, nptiles = 0;
   // tables and workspaces per precision
   TabLayout tl;
@@ -146,6 +147,7 @@ struct sc_plan {
     g.D2 = d_D2.as<double>();
     g.D4 = d_D4.as<double>();
     g.ET = d_ET.as<double>();
+    g.EF = d_EF.as<double>();
     g.EDT = d_EDT.as<double>();
     g.ED2T = d_ED2T.as<double>();
     g.DT = d_DT.as<double>();
@@ -347,7 +349,13 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
   const WsLayout& w = P->wl;
   {
     Prof _p(P, SC_STAGE_RADIAL_PREP, s);
-    hipLaunchKernelGGL(sc::k_radial_prep<T>, dim3(P->nrtiles, nvec), dim3(256), 0, s, dg, v, ldv, J, nvec, ws + w.Gs, ws + w.Gv);
+    const dim3 grid(P->nrtiles, nvec);
+    switch ((g.N + 15) / 16) {
+      case 1: hipLaunchKernelGGL((sc::k_radial_prep<T, 1>), grid, dim3(256), 0, s, dg, v, ldv, J, nvec, ws + w.Gs, ws + w.Gv); break;
+      case 2: hipLaunchKernelGGL((sc::k_radial_prep<T, 2>), grid, dim3(256), 0, s, dg, v, ldv, J, nvec, ws + w.Gs, ws + w.Gv); break;
+      case 3: hipLaunchKernelGGL((sc::k_radial_prep<T, 3>), grid, dim3(256), 0, s, dg, v, ldv, J, nvec, ws + w.Gs, ws + w.Gv); break;
+      default: hipLaunchKernelGGL((sc::k_radial_prep<T, 4>), grid, dim3(256), 0, s, dg, v, ldv, J, nvec, ws + w.Gs, ws + w.Gv); break;
+    }
   }
   HIPCHK(hipGetLastError());
   long long nt = gemm_tiles<T>(P->h_syn, nvec);
@@ -781,6 +789,21 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
         for (int j = 0; j < cols; ++j) T[(size_t)j * rows + i] = A[(size_t)i * cols + j];
       return T;
     };
+    {
+      // E, ED, ED2 in MFMA operand order, k (the N nodes) padded to 16 ceil(N/16)
+      const int rtp = (g.Np + 15) / 16, ks = 4 * ((g.N + 15) / 16);
+      const size_t ms = (size_t)rtp * ks * 64;
+      std::vector<double> F(3 * ms, 0.0);
+      const std::vector<double>* mats[3] = {&g.E, &g.ED, &g.ED2};
+      for (int a = 0; a < 3; ++a)
+        for (int t = 0; t < rtp; ++t)
+          for (int sk = 0; sk < ks; ++sk)
+            for (int l = 0; l < 64; ++l) {
+              const int row = 16 * t + l % 16, col = 4 * sk + l / 16;
+              if (row < g.Np && col < g.N) F[a * ms + ((size_t)t * ks + sk) * 64 + l] = (*mats[a])[(size_t)row * g.N + col];
+            }
+      upload(P->d_EF, F);
+    }
     upload(P->d_ET, transpose(g.E, g.Np, g.N));
     upload(P->d_EDT, transpose(g.ED, g.Np, g.N));
     upload(P->d_ED2T, transpose(g.ED2, g.Np, g.N));

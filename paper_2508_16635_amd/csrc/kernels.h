@@ -50,6 +50,7 @@ struct DevGrid {
   const double* DpT;  // [Np][Np]: Dp^T
   const int2* ptiles; // projection tiles: (k, first l-m)
   int nptiles;
+  const double* EF;   // E, ED, ED2 (N_p x N each) in 16x16x4 MFMA operand order, k padded to 16 ceil(N/16)
   int fft_nr;         // azimuthal FFT: number of passes and their radices (each 2, 3, 4 or 5)
   int fft_r[8];
 };
@@ -57,6 +58,15 @@ struct DevGrid {
 struct PhysParams {
   double Ek, Ra, Pr, dt, ro;
 };
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on XCD b % 8), each
+// with its own L2.  This maps blockIdx.x to a linear id such that every XCD receives one
+// contiguous range of ids (a bijection on [0, gridDim.x)).
+__device__ inline int xcd_linear_id() {
+  const int b = blockIdx.x, G = gridDim.x;
+  const int x = b & 7, q = G >> 3, r = G & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
 
 // Matrix-core (MFMA) 16x16x4 tile per wavefront: D[16][16] += A[16][4] B[4][16].
 // Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; element q of its 4-vector holds
@@ -80,21 +90,31 @@ struct Mfma<double> {
 };
 
 // ------------------------------------------------------------------------------------------
+// Real matrices in 16x16x4 MFMA operand order: for R row tiles and KS k-steps, lane l of
+// (row tile t, k-step s) holds M[16t + l%16][4s + l/16] (zero outside the matrix), at
+// ((t KS + s) 64 + l).  A wavefront then loads its A operands with unit-stride loads.
+
+// ------------------------------------------------------------------------------------------
 // K1: radial preparation.  For each (vec, r_p, lm): the eight spectral profiles
 //   ur = lam f/r^2, wr = lam e/r^2, dT = T'   (scalar synthesis with Pbar)
 //   Su = f'/r, Tu = e/r, Sw = e'/r, Tw = -(f'' - lam f/r^2)/r, ST = T/r  (vector synthesis)
 // evaluated at the N_p nodes as diag(r^-k) E D^j u, in FP64, stored in precision T.
 // Input cleaning: Im at m = 0, e/f at l = 0 and the phase slot J are read as 0.
-// One workgroup per (tile of up to 16 consecutive l at one m, vector); the tile's e, f, T
-// profiles are staged in LDS with coalesced loads.
+// One workgroup per (tile of up to 16 consecutive l at one m, vector).  The tile's profiles
+// form the columns (field, Re/Im, l) of X (N x 96, staged in LDS); the products E X, ED X and
+// (f columns only) ED2 X run on the FP64 matrix cores, one (16 r_p x 16 column) tile per
+// wavefront at a time, and every output is formed from one column's products in registers.
 constexpr int kRPT = 16;  // l per radial-prep tile
 
-template <class T>
+template <class T, int RTN>
 __global__ void __launch_bounds__(256) k_radial_prep(DevGrid g, const double* __restrict__ v, long long ldv,
                                                      long long J, int nvec, T* __restrict__ Gs, T* __restrict__ Gv) {
+  constexpr int KS = 4 * RTN;           // k-steps over the N nodes (rows of X padded to 16 RTN)
+  constexpr int NC = 6 * kRPT;          // columns (field, c, t)
+  constexpr int XST = NC + 16;          // LDS row stride: consecutive k rows 32 banks apart
+  __shared__ double xs[16 * RTN * XST];
   const int N = g.N, Np = g.Np;
-  const int XS = 2 * N + 2;  // padded row of one profile (Re/Im interleaved)
-  __shared__ double xs[3 * kRPT * (2 * 64 + 2)];
+  const int RTP = (Np + 15) / 16;
   const int2 tl = g.rtiles[blockIdx.x];
   const int vec = blockIdx.y;
   const int k = tl.x, il0 = tl.y;
@@ -102,54 +122,65 @@ __global__ void __launch_bounds__(256) k_radial_prep(DevGrid g, const double* __
   const int nt = min(kRPT, nl - il0);
   const int lm0 = g.lmbase[k] + il0;
   const double* vb = v + (long long)vec * ldv;
-  for (int idx = threadIdx.x; idx < 3 * nt * 2 * N; idx += blockDim.x) {
-    int c = idx % (2 * N);
-    int t = (idx / (2 * N)) % nt;
-    int f = idx / (2 * N * nt);
-    long long o = 2LL * (long long)N * ((long long)f * g.S + lm0 + t) + c;
-    int l = m + il0 + t;
-    double val = vb[o];
-    if (o == J || ((c & 1) && k == 0) || (f < 2 && l == 0)) val = 0.0;
-    xs[(f * kRPT + t) * XS + c] = val;
+  for (int idx = threadIdx.x; idx < 16 * RTN * NC; idx += blockDim.x) {
+    const int col = idx % NC, j = idx / NC;
+    const int t = col % kRPT, c = (col / kRPT) & 1, f = col / (2 * kRPT);
+    double val = 0.0;
+    if (j < N && t < nt) {
+      const long long o = 2LL * ((long long)N * ((long long)f * g.S + lm0 + t) + j) + c;
+      const int l = m + il0 + t;
+      val = vb[o];
+      if (o == J || (c == 1 && k == 0) || (f < 2 && l == 0)) val = 0.0;
+    }
+    xs[j * XST + col] = val;
   }
   __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const long long mstride = (long long)RTP * KS * 64;
   const long long offS = 6LL * Np * g.vcap * g.lmbase[k];
   const long long offV = 10LL * Np * g.vcap * g.lmbase[k];
-  for (int idx = threadIdx.x; idx < Np * kRPT * 2; idx += blockDim.x) {
-    int t = idx % kRPT;
-    int ri = (idx / kRPT) & 1;
-    int rp = idx / (2 * kRPT);
-    if (t >= nt) continue;
-    double acc[7];
+  const int t = l & 15;
+  const int il = il0 + t, lw = m + il;
+  const double lam = (double)lw * (lw + 1);
+  for (int p = w; p < RTP * 6; p += 4) {
+    const int rt = p / 6, ct = p % 6, f = ct >> 1, c = ct & 1;
+    const double* F0 = g.EF + (long long)rt * KS * 64 + l;
+    double a0[KS], a1[KS], a2[KS];
 #pragma unroll
-    for (int a = 0; a < 7; ++a) acc[a] = 0.0;
-    const double* xe = xs + (0 * kRPT + t) * XS + ri;
-    const double* xf = xs + (1 * kRPT + t) * XS + ri;
-    const double* xt = xs + (2 * kRPT + t) * XS + ri;
-    for (int jj = 0; jj < N; ++jj) {
-      double E0 = g.ET[(long long)jj * Np + rp], E1 = g.EDT[(long long)jj * Np + rp], E2 = g.ED2T[(long long)jj * Np + rp];
-      double e = xe[2 * jj], f = xf[2 * jj], tt = xt[2 * jj];
-      acc[0] += E0 * f;
-      acc[1] += E1 * f;
-      acc[2] += E2 * f;
-      acc[3] += E0 * e;
-      acc[4] += E1 * e;
-      acc[5] += E0 * tt;
-      acc[6] += E1 * tt;
+    for (int sidx = 0; sidx < KS; ++sidx) {
+      a0[sidx] = F0[sidx * 64];
+      a1[sidx] = F0[mstride + sidx * 64];
+      a2[sidx] = (f == 1) ? F0[2 * mstride + sidx * 64] : 0.0;
     }
-    const int il = il0 + t, l = m + il;
-    const double lam = (double)l * (l + 1);
-    const double ri1 = 1.0 / g.rp[rp], ri2 = ri1 * ri1;
-    T* gs = Gs + offS + (((long long)vec * Np + rp) * 6 + ri) * nl + il;
-    T* gv = Gv + offV + (((long long)vec * Np + rp) * 10 + ri) * nl + il;
-    gs[0 * nl] = (T)(lam * ri2 * acc[0]);                        // ur
-    gs[2 * nl] = (T)(lam * ri2 * acc[3]);                        // wr
-    gs[4 * nl] = (T)(acc[6]);                                    // dT
-    gv[0 * nl] = (T)(acc[1] * ri1);                              // Su
-    gv[2 * nl] = (T)(acc[3] * ri1);                              // Tu
-    gv[4 * nl] = (T)(acc[4] * ri1);                              // Sw
-    gv[6 * nl] = (T)(-acc[2] * ri1 + lam * ri2 * ri1 * acc[0]);  // Tw
-    gv[8 * nl] = (T)(acc[5] * ri1);                              // ST
+    f64x4 y0 = {0, 0, 0, 0}, y1 = {0, 0, 0, 0}, y2 = {0, 0, 0, 0};
+#pragma unroll
+    for (int sidx = 0; sidx < KS; ++sidx) {
+      const double b = xs[(4 * sidx + (l >> 4)) * XST + ct * 16 + t];
+      y0 = Mfma<double>::step(a0[sidx], b, y0);
+      y1 = Mfma<double>::step(a1[sidx], b, y1);
+      if (f == 1) y2 = Mfma<double>::step(a2[sidx], b, y2);
+    }
+    if (t >= nt) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int rp = 16 * rt + Mfma<double>::out_row(l, q);
+      if (rp >= Np) continue;
+      const double ri1 = 1.0 / g.rp[rp], ri2 = ri1 * ri1;
+      T* gs = Gs + offS + (((long long)vec * Np + rp) * 6 + c) * nl + il;
+      T* gv = Gv + offV + (((long long)vec * Np + rp) * 10 + c) * nl + il;
+      if (f == 0) {          // e
+        gs[2 * nl] = (T)(lam * ri2 * y0[q]);                          // wr
+        gv[2 * nl] = (T)(y0[q] * ri1);                                // Tu
+        gv[4 * nl] = (T)(y1[q] * ri1);                                // Sw
+      } else if (f == 1) {   // f
+        gs[0 * nl] = (T)(lam * ri2 * y0[q]);                          // ur
+        gv[0 * nl] = (T)(y1[q] * ri1);                                // Su
+        gv[6 * nl] = (T)(-y2[q] * ri1 + lam * ri2 * ri1 * y0[q]);     // Tw
+      } else {               // T
+        gs[4 * nl] = (T)(y1[q]);                                      // dT
+        gv[8 * nl] = (T)(y0[q] * ri1);                                // ST
+      }
+    }
   }
 }
 
@@ -411,9 +442,13 @@ __global__ void __launch_bounds__(kRingThreads) k_ring(DevGrid g, int nvec, int 
   cz<T>* w = reinterpret_cast<cz<T>*>(smem_raw);  // [N] twiddles exp(-2 pi i m / N)
   cz<T>* X = w + N;                                // [RT][5][N]
   const int ntile = (nth + RT - 1) >> rt_log2;
-  const int tile = blockIdx.x % ntile;
-  const int vr = blockIdx.x / ntile;  // vec * Np + rp
-  const int rp = vr % g.Np;
+  // logical order (r_p, vec, tile) in contiguous runs per XCD, so that the tiles of one ring
+  // row and the vectors sharing one base radius reuse the same L2
+  const int lid = xcd_linear_id();
+  const int tile = lid % ntile;
+  const int rv = lid / ntile;  // rp * nvec + vec
+  const int rp = rv / nvec;
+  const int vr = (rv - rp * nvec) * g.Np + rp;  // vec * Np + rp: row index of the sums
   const int th0 = tile << rt_log2;
   const int tid = threadIdx.x;
   // the linearized products read the base fields at the points this thread owns in step C:
