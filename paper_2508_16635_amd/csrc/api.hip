@@ -86,7 +86,7 @@ struct sc_plan {
   // grid / radial data
   DevBuf d_lmk, d_lml, d_lmbase, d_r, d_rp, d_E, d_ED, d_ED2, d_P, d_Dp, d_D, d_D2, d_D4;
   DevBuf d_ET, d_EDT, d_ED2T, d_DT, d_D2T, d_D4T, d_rtiles, d_PT, d_DpT, d_ptiles;
-  DevBuf d_EF;
+  DevBuf d_EF, d_PF, d_D2F;
   int nrtiles = 0, nptiles = 0;
   // tables and workspaces per precision
   TabLayout tl;
@@ -148,6 +148,8 @@ struct sc_plan {
     g.D4 = d_D4.as<double>();
     g.ET = d_ET.as<double>();
     g.EF = d_EF.as<double>();
+    g.PF = d_PF.as<double>();
+    g.D2F = d_D2F.as<double>();
     g.EDT = d_EDT.as<double>();
     g.ED2T = d_ED2T.as<double>();
     g.DT = d_DT.as<double>();
@@ -401,8 +403,27 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
 constexpr int kSeg = 8;   // blocks per scan segment
 using sc::kVG;            // vectors per workgroup in the chain solves
 
-size_t project_smem(const sc::HostGrid& g) {
-  return sizeof(double) * ((size_t)5 * sc::kPT * 2 * g.Np + (size_t)3 * sc::kPT * 2 * g.N);
+// Projection launch for RT = ceil(N/16) output row tiles.
+template <class T, bool STEP>
+void launch_project(sc_plan* P, int nvec, const T* As, const T* Av, const double* v, long long ldv, long long J, double C,
+                    const double* MX, double* b, hipStream_t s) {
+  const sc::HostGrid& g = P->hg;
+  const dim3 grid(P->nptiles, nvec);
+  const size_t smem = sc::project_lds_bytes<T>(g.Np, g.N);
+  sc::DevGrid dg = P->dg();
+  switch ((g.N + 15) / 16) {
+    case 1: hipLaunchKernelGGL((sc::k_project_rhs<T, STEP, 1>), grid, dim3(256), smem, s, dg, P->pp(), nvec, As, Av, v, ldv, J, C, MX, b); break;
+    case 2: hipLaunchKernelGGL((sc::k_project_rhs<T, STEP, 2>), grid, dim3(256), smem, s, dg, P->pp(), nvec, As, Av, v, ldv, J, C, MX, b); break;
+    case 3: hipLaunchKernelGGL((sc::k_project_rhs<T, STEP, 3>), grid, dim3(256), smem, s, dg, P->pp(), nvec, As, Av, v, ldv, J, C, MX, b); break;
+    default: hipLaunchKernelGGL((sc::k_project_rhs<T, STEP, 4>), grid, dim3(256), smem, s, dg, P->pp(), nvec, As, Av, v, ldv, J, C, MX, b); break;
+  }
+  HIPCHK(hipGetLastError());
+}
+
+template <class T, bool STEP, int RT>
+void project_attr() {
+  HIPCHK(hipFuncSetAttribute((const void*)sc::k_project_rhs<T, STEP, RT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)sc::project_lds_bytes<double>(128, 64)));
 }
 
 template <class F>
@@ -501,11 +522,10 @@ void step_into_xbuf(sc_plan* P, const double* x, double C, hipStream_t s) {
   sc::DevGrid dg = P->dg();
   {
     Prof _p(P, SC_STAGE_PROJECT_RHS, s);
-    hipLaunchKernelGGL((sc::k_project_rhs<double, true>), dim3(P->nptiles, 1), dim3(256), project_smem(P->hg), s, dg, P->pp(), 1,
-                       (const double*)(P->ws64.as<double>() + P->wl.As), (const double*)(P->ws64.as<double>() + P->wl.Av),
-                       x, P->n_real, (long long)-1, C, (const double*)nullptr, P->bbuf.as<double>());
+    launch_project<double, true>(P, 1, (const double*)(P->ws64.as<double>() + P->wl.As),
+                                 (const double*)(P->ws64.as<double>() + P->wl.Av), x, P->n_real, (long long)-1, C,
+                                 (const double*)nullptr, P->bbuf.as<double>(), s);
   }
-  HIPCHK(hipGetLastError());
   refined_solve<double>(P, 1, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine64, s);
 }
 
@@ -543,22 +563,18 @@ void jvp_impl(sc_plan* P, int nvec, const double* v, long long ldv, double* y, l
     transforms<double>(P, sc::RING_LINEAR, nvec, v, ldv, J, s);
     {
       Prof _p(P, SC_STAGE_PROJECT_RHS, s);
-      hipLaunchKernelGGL((sc::k_project_rhs<double, false>), dim3(P->nptiles, nvec), dim3(256), project_smem(P->hg), s,
-                         dg, P->pp(), nvec, (const double*)(P->ws64.as<double>() + P->wl.As),
-                         (const double*)(P->ws64.as<double>() + P->wl.Av), v, ldv, J, P->baseC,
-                         P->MX.as<const double>(), P->bbuf.as<double>());
-      HIPCHK(hipGetLastError());
+      launch_project<double, false>(P, nvec, (const double*)(P->ws64.as<double>() + P->wl.As),
+                                    (const double*)(P->ws64.as<double>() + P->wl.Av), v, ldv, J, P->baseC,
+                                    P->MX.as<const double>(), P->bbuf.as<double>(), s);
     }
     refined_solve<double>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine64, s);
   } else {
     transforms<float>(P, sc::RING_LINEAR, nvec, v, ldv, J, s);
     {
       Prof _p(P, SC_STAGE_PROJECT_RHS, s);
-      hipLaunchKernelGGL((sc::k_project_rhs<float, false>), dim3(P->nptiles, nvec), dim3(256), project_smem(P->hg), s,
-                         dg, P->pp(), nvec, (const float*)(P->ws32.as<float>() + P->wl.As),
-                         (const float*)(P->ws32.as<float>() + P->wl.Av), v, ldv, J, P->baseC,
-                         P->MX.as<const double>(), P->bbuf.as<double>());
-      HIPCHK(hipGetLastError());
+      launch_project<float, false>(P, nvec, (const float*)(P->ws32.as<float>() + P->wl.As),
+                                   (const float*)(P->ws32.as<float>() + P->wl.Av), v, ldv, J, P->baseC,
+                                   P->MX.as<const double>(), P->bbuf.as<double>(), s);
     }
     refined_solve<float>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine32, s);
   }
@@ -804,6 +820,41 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
             }
       upload(P->d_EF, F);
     }
+    {
+      // projection matrices (N x N_p) and D^2 (N x N) in MFMA operand order
+      const int rtn = (g.N + 15) / 16, ksp = 4 * ((g.Np + 15) / 16), ksn = 4 * rtn;
+      auto frag = [](const std::vector<double>& M, int rows, int cols, int rt, int ks, double* out) {
+        for (int t = 0; t < rt; ++t)
+          for (int sk = 0; sk < ks; ++sk)
+            for (int l = 0; l < 64; ++l) {
+              const int row = 16 * t + l % 16, col = 4 * sk + l / 16;
+              out[((size_t)t * ks + sk) * 64 + l] = (row < rows && col < cols) ? M[(size_t)row * cols + col] : 0.0;
+            }
+      };
+      const int N = g.N, Np = g.Np;
+      std::vector<double> P1((size_t)N * Np), P2((size_t)N * Np), PDr((size_t)N * Np, 0.0);
+      for (int j = 0; j < N; ++j)
+        for (int q = 0; q < Np; ++q) {
+          const double pr = g.P[(size_t)j * Np + q], r = g.rp[q];
+          P1[(size_t)j * Np + q] = pr / r;
+          P2[(size_t)j * Np + q] = pr / (r * r);
+        }
+      for (int j = 0; j < N; ++j)          // P diag(1/r^2) Dp diag(r)
+        for (int i = 0; i < Np; ++i) {
+          const double a = P2[(size_t)j * Np + i];
+          for (int q = 0; q < Np; ++q) PDr[(size_t)j * Np + q] += a * g.Dp[(size_t)i * Np + q] * g.rp[q];
+        }
+      const size_t ms = (size_t)rtn * ksp * 64;
+      std::vector<double> F(4 * ms);
+      frag(P1, N, Np, rtn, ksp, F.data());
+      frag(P2, N, Np, rtn, ksp, F.data() + ms);
+      frag(PDr, N, Np, rtn, ksp, F.data() + 2 * ms);
+      frag(g.P, N, Np, rtn, ksp, F.data() + 3 * ms);
+      upload(P->d_PF, F);
+      std::vector<double> F2((size_t)rtn * ksn * 64);
+      frag(g.D2, N, N, rtn, ksn, F2.data());
+      upload(P->d_D2F, F2);
+    }
     upload(P->d_ET, transpose(g.E, g.Np, g.N));
     upload(P->d_EDT, transpose(g.ED, g.Np, g.N));
     upload(P->d_ED2T, transpose(g.ED2, g.Np, g.N));
@@ -845,6 +896,11 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
       const size_t smem64 = sc::ring_lds_bytes<double>(g.nphi, ring_rt_log2<double>(g));
       const size_t smem32 = sc::ring_lds_bytes<float>(g.nphi, ring_rt_log2<float>(g));
       if (smem64 > 64 * 1024 || smem32 > 64 * 1024) throw Fail{SC_ERR_INTERNAL, "ring LDS above 64 KB"};
+    }
+    if (sc::project_lds_bytes<double>(g.Np, g.N) > 64 * 1024) {
+      project_attr<double, true, 1>(); project_attr<double, true, 2>(); project_attr<double, true, 3>(); project_attr<double, true, 4>();
+      project_attr<double, false, 1>(); project_attr<double, false, 2>(); project_attr<double, false, 3>(); project_attr<double, false, 4>();
+      project_attr<float, false, 1>(); project_attr<float, false, 2>(); project_attr<float, false, 3>(); project_attr<float, false, 4>();
     }
     {
       const size_t t64 = tsolve_smem<double>(g), t32 = tsolve_smem<float>(g);

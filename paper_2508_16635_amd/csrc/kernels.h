@@ -51,6 +51,8 @@ struct DevGrid {
   const int2* ptiles; // projection tiles: (k, first l-m)
   int nptiles;
   const double* EF;   // E, ED, ED2 (N_p x N each) in 16x16x4 MFMA operand order, k padded to 16 ceil(N/16)
+  const double* PF;   // P diag(1/r), P diag(1/r^2), P diag(1/r^2) Dp diag(r), P (N x N_p each), operand order
+  const double* D2F;  // D^2 (N x N), operand order
   int fft_nr;         // azimuthal FFT: number of passes and their radices (each 2, 3, 4 or 5)
   int fft_r[8];
 };
@@ -93,6 +95,42 @@ struct Mfma<double> {
 // Real matrices in 16x16x4 MFMA operand order: for R row tiles and KS k-steps, lane l of
 // (row tile t, k-step s) holds M[16t + l%16][4s + l/16] (zero outside the matrix), at
 // ((t KS + s) 64 + l).  A wavefront then loads its A operands with unit-stride loads.
+
+// acc[p] += M_p X_p over k < 16 KB for NPR independent products on one 16-row tile: Mp[p] is
+// this lane's element of k-step 0 of the tile (k-step stride 64), Xp[p] the LDS column of X_p
+// (row k at Xp[p][k ldx]).  The operands of the next 16-wide k block load while the current
+// block multiplies.
+template <int NPR, class TX>
+__device__ inline void mfma_f64_products(const double* const (&Mp)[NPR], const TX* const (&Xp)[NPR], int ldx, int KB,
+                                         int l, f64x4 (&acc)[NPR]) {
+  double a0[NPR][4], a1[NPR][4];
+  auto load = [&](int kb, double (&a)[NPR][4]) {
+    kb = kb < KB ? kb : KB - 1;
+#pragma unroll
+    for (int p = 0; p < NPR; ++p)
+#pragma unroll
+      for (int st = 0; st < 4; ++st) a[p][st] = Mp[p][(4 * kb + st) * 64];
+  };
+  auto run = [&](int kb, const double (&a)[NPR][4]) {
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int row = 16 * kb + 4 * st + (l >> 4);
+#pragma unroll
+      for (int p = 0; p < NPR; ++p) acc[p] = Mfma<double>::step(a[p][st], (double)Xp[p][row * ldx], acc[p]);
+    }
+  };
+  load(0, a0);
+  for (int kb = 0; kb < KB; kb += 2) {
+    load(kb + 1, a1);
+    __builtin_amdgcn_sched_barrier(0);
+    run(kb, a0);
+    if (kb + 1 < KB) {
+      load(kb + 2, a0);
+      __builtin_amdgcn_sched_barrier(0);
+      run(kb + 1, a1);
+    }
+  }
+}
 
 // ------------------------------------------------------------------------------------------
 // K1: radial preparation.  For each (vec, r_p, lm): the eight spectral profiles
@@ -611,22 +649,31 @@ __global__ void __launch_bounds__(kRingThreads) k_ring(DevGrid g, int nvec, int 
 // K7: curl projections back to the N nodes and assembly of the right-hand side
 //   b = M u + dt (N(u) + Ra lam T/(r r_o) [f only] + C i m M u + c i m M X)
 // with M_e = Ek lam/r^2, M_f = -Ek lam/r^2 (D^2 - lam/r^2), M_T = 1, and boundary rows.
+// The e-row force P((lam/r) Tor), the f-row force P((lam/r^2)(W_r - d_r(r S))) and the T-row
+// force P(Q) are products with fixed N x N_p matrices (P diag(1/r), P diag(1/r^2),
+// P diag(1/r^2) Dp diag(r), P), so every output of the tile comes from five FP64 MFMA
+// products (the fifth is D^2 on f) and a pointwise epilogue in registers.
 // STEP: inhomogeneous T_00 rows, no c-term.  One workgroup per (tile of up to 8 consecutive l
-// at one m, vector); all radial matrices are read transposed so that consecutive threads
-// touch consecutive entries.
-constexpr int kPT = 4;  // l per projection tile
+// at one m, vector); columns (Re/Im, l); wavefront w owns output rows 16w..16w+15.
+constexpr int kPT = 8;  // l per projection tile
 
-template <class T, bool STEP>
+template <class T>
+__host__ __device__ inline size_t project_lds_bytes(int Np, int N) {
+  const int rp = 16 * ((Np + 15) / 16), rn = 16 * ((N + 15) / 16);
+  return (size_t)4 * rp * 16 * sizeof(T) + (size_t)3 * rn * 16 * sizeof(double);
+}
+
+template <class T, bool STEP, int RTN>
 __global__ void __launch_bounds__(256) k_project_rhs(DevGrid g, PhysParams ph, int nvec, const T* __restrict__ As,
                                                      const T* __restrict__ Av, const double* __restrict__ v,
                                                      long long ldv, long long J, double C,
                                                      const double* __restrict__ MX, double* __restrict__ b) {
-  // [t][c][rp] arrays on the N_p nodes, c = Re/Im; u as [f][t][c][j]; sized exactly (dynamic)
   extern __shared__ unsigned char smem_raw[];
   const int N = g.N, Np = g.Np;
-  double* base_ = reinterpret_cast<double*>(smem_raw);
-  auto A2 = [&](int which, int t, int c) { return base_ + ((which * kPT + t) * 2 + c) * Np; };
-  auto U2 = [&](int f, int t, int c) { return base_ + 5 * kPT * 2 * Np + ((f * kPT + t) * 2 + c) * N; };
+  const int KBP = (Np + 15) / 16, rowsP = 16 * KBP;
+  constexpr int rowsN = 16 * RTN;
+  T* Xa = reinterpret_cast<T*>(smem_raw);                                             // [4][rowsP][16]: Tor, W_r, S, Q
+  double* Xu = reinterpret_cast<double*>(smem_raw + (size_t)4 * rowsP * 16 * sizeof(T));  // [3][rowsN][16]: e, f, T
   const int2 tl = g.ptiles[blockIdx.x];
   const int vec = blockIdx.y;
   const int k = tl.x, il0 = tl.y;
@@ -640,88 +687,80 @@ __global__ void __launch_bounds__(256) k_project_rhs(DevGrid g, PhysParams ph, i
   double* bb = b + (long long)vec * 6LL * N * g.S;
   double cval = 0.0;
   if (!STEP && J >= 0) cval = v[(long long)vec * ldv + J];
-  // analysis outputs: rows (vec, rp, q, c), l contiguous
-  for (int idx = threadIdx.x; idx < nt * 8 * Np; idx += blockDim.x) {
-    int t = idx % nt, qc = (idx / nt) % 8, rp = idx / (8 * nt);
-    int q = qc >> 1, c = qc & 1;
-    long long row = ((long long)vec * Np + rp) * 4 + (q & 1) * 2 + c;
-    double val = (q < 2) ? (double)as[row * nl + il0 + t] : (double)av[row * nl + il0 + t];
-    if (q == 2) val *= g.rp[rp];   // r S
-    A2(q, t, c)[rp] = val;          // 0 W_r, 1 Q, 2 r S, 3 Tor
+  // analysis outputs on the N_p nodes: column (c, t) = c * 8 + t
+  for (int idx = threadIdx.x; idx < 4 * rowsP * 16; idx += blockDim.x) {
+    const int col = idx & 15, rp = (idx >> 4) % rowsP, which = idx / (16 * rowsP);
+    const int c = col >> 3, t = col & 7;
+    T val = (T)0;
+    if (rp < Np && t < nt) {
+      // which: 0 Tor (vector slot 2), 1 W_r (scalar slot 0), 2 S (vector slot 0), 3 Q (scalar slot 2)
+      const T* src = (which == 1 || which == 3) ? as : av;
+      const int slot = (which == 0 || which == 3) ? 2 : 0;
+      const long long row = ((long long)vec * Np + rp) * 4 + slot + c;
+      val = src[row * nl + il0 + t];
+    }
+    Xa[idx] = val;
   }
-  // cleaned state u at the N nodes
-  for (int idx = threadIdx.x; idx < 3 * nt * 2 * N; idx += blockDim.x) {
-    int cj = idx % (2 * N), t = (idx / (2 * N)) % nt, f = idx / (2 * N * nt);
-    int jj = cj >> 1, c = cj & 1;
-    long long o = 2LL * ((long long)N * ((long long)f * g.S + lm0 + t)) + cj;
-    int l = m + il0 + t;
-    double val = vb[o];
-    if (o == J || (c == 1 && k == 0) || (f < 2 && l == 0)) val = 0.0;
-    U2(f, t, c)[jj] = val;
-  }
-  __syncthreads();
-  // f-row force on the N_p nodes: (lam/r^2)(W_r - d_r(r S)) -> slot 4; e-row: (lam/r) Tor
-  for (int idx = threadIdx.x; idx < nt * 2 * Np; idx += blockDim.x) {
-    int rp = idx % Np, c = (idx / Np) & 1, t = idx / (2 * Np);
-    int l = m + il0 + t;
-    double lam = (double)l * (l + 1), r = g.rp[rp];
-    const double* rS = A2(2, t, c);
-    double d = 0.0;
-    for (int q = 0; q < Np; ++q) d += g.DpT[(long long)q * Np + rp] * rS[q];
-    A2(4, t, c)[rp] = lam / (r * r) * (A2(0, t, c)[rp] - d);
-    A2(3, t, c)[rp] *= lam / r;
+  // cleaned state u at the N nodes (coalesced over (j, c) of one profile)
+  for (int idx = threadIdx.x; idx < 3 * kPT * 2 * rowsN; idx += blockDim.x) {
+    const int cj = idx % (2 * rowsN), t = (idx / (2 * rowsN)) % kPT, f = idx / (2 * rowsN * kPT);
+    const int jj = cj >> 1, c = cj & 1;
+    double val = 0.0;
+    if (jj < N && t < nt) {
+      const long long o = 2LL * ((long long)N * ((long long)f * g.S + lm0 + t) + jj) + c;
+      const int l = m + il0 + t;
+      val = vb[o];
+      if (o == J || (c == 1 && k == 0) || (f < 2 && l == 0)) val = 0.0;
+    }
+    Xu[(f * rowsN + jj) * 16 + c * 8 + t] = val;
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < nt * N; idx += blockDim.x) {
-    int jj = idx % N, t = idx / N;
-    int l = m + il0 + t;
-    double lam = (double)l * (l + 1);
-    double ne[2] = {0, 0}, nf[2] = {0, 0}, nq[2] = {0, 0};
-    for (int c = 0; c < 2; ++c) {
-      const double* to = A2(3, t, c);
-      const double* tf = A2(4, t, c);
-      const double* qq = A2(1, t, c);
-      for (int q = 0; q < Np; ++q) {
-        double pw = g.PT[(long long)q * N + jj];
-        ne[c] += pw * to[q];
-        nf[c] += pw * tf[q];
-        nq[c] += pw * qq[q];
-      }
-    }
-    double d2f[2] = {0, 0};
-    for (int c = 0; c < 2; ++c) {
-      const double* uf = U2(1, t, c);
-      for (int i = 0; i < N; ++i) d2f[c] += g.D2T[(long long)i * N + jj] * uf[i];
-    }
-    double r = g.r[jj];
-    double a = ph.Ek * lam / (r * r);
-    double Mu[3][2];
-    for (int c = 0; c < 2; ++c) {
-      Mu[0][c] = a * U2(0, t, c)[jj];
-      Mu[1][c] = -a * (d2f[c] - lam / (r * r) * U2(1, t, c)[jj]);
-      Mu[2][c] = U2(2, t, c)[jj];
-    }
-    double nn[3][2] = {{ne[0], ne[1]}, {nf[0], nf[1]}, {nq[0], nq[1]}};
-    nn[1][0] += ph.Ra * lam * U2(2, t, 0)[jj] / (r * ph.ro);
-    nn[1][1] += ph.Ra * lam * U2(2, t, 1)[jj] / (r * ph.ro);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (w >= RTN) return;
+  const int col = l & 15, c = col >> 3, t = col & 7;
+  // the four N x N_p products
+  f64x4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  {
+    const long long ms = (long long)RTN * 4 * KBP * 64;
+    const double* base = g.PF + (long long)w * 4 * KBP * 64 + l;
+    const double* const Mp[4] = {base, base + ms, base + 2 * ms, base + 3 * ms};
+    const T* const Xp[4] = {Xa + col, Xa + rowsP * 16 + col, Xa + 2 * rowsP * 16 + col, Xa + 3 * rowsP * 16 + col};
+    mfma_f64_products<4, T>(Mp, Xp, 16, KBP, l, acc);
+  }
+  f64x4 dacc[1] = {{0, 0, 0, 0}};
+  {
+    const double* const Mp[1] = {g.D2F + (long long)w * 4 * RTN * 64 + l};
+    const double* const Xp[1] = {Xu + rowsN * 16 + col};
+    mfma_f64_products<1, double>(Mp, Xp, 16, RTN, l, dacc);
+  }
+  const int il = il0 + t, lw = m + il;
+  const double lam = (double)lw * (lw + 1);
+  const double sgn = (c == 0) ? -1.0 : 1.0;  // i z: Re <- -Im, Im <- +Re
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double d2f = dacc[0][q];
+    const double d2f_o = __shfl_xor(d2f, 8);  // the other component of the same (j, l)
+    const int jj = 16 * w + Mfma<double>::out_row(l, q);
+    if (jj >= N || t >= nt) continue;
+    const double r = g.r[jj], r2 = r * r;
+    const double a = ph.Ek * lam / r2;
+    const double* ue = Xu + jj * 16 + 8 * c + t;
+    const double* uo = Xu + jj * 16 + 8 * (1 - c) + t;
+    const double u_e = ue[0], u_f = ue[rowsN * 16], u_T = ue[2 * rowsN * 16];
+    const double o_e = uo[0], o_f = uo[rowsN * 16], o_T = uo[2 * rowsN * 16];
+    const double Mu[3] = {a * u_e, -a * (d2f - lam / r2 * u_f), u_T};
+    const double Mo[3] = {a * o_e, -a * (d2f_o - lam / r2 * o_f), o_T};
+    const double nn[3] = {lam * acc[0][q], lam * (acc[1][q] - acc[2][q]) + ph.Ra * lam * u_T / (r * ph.ro), acc[3][q]};
+#pragma unroll
     for (int f = 0; f < 3; ++f) {
-      long long o = 2LL * ((long long)N * ((long long)f * g.S + lm0 + t) + jj);
-      double tr = -m * C * Mu[f][1], ti = m * C * Mu[f][0];
-      if (!STEP) {
-        tr += -m * cval * MX[o + 1];
-        ti += m * cval * MX[o];
-      }
-      double br = Mu[f][0] + ph.dt * (nn[f][0] + tr);
-      double bi = Mu[f][1] + ph.dt * (nn[f][1] + ti);
-      bool bc = (f == 1) ? (jj == 0 || jj == 1 || jj == N - 2 || jj == N - 1) : (jj == 0 || jj == N - 1);
-      if (bc) {
-        br = 0.0;
-        bi = 0.0;
-        if (STEP && f == 2 && l == 0 && jj == N - 1) br = 1.0;  // T_00(r_i) = 1
-      }
-      if (f < 2 && l == 0) br = bi = 0.0;
-      bb[o] = br;
-      bb[o + 1] = bi;
+      const long long o = 2LL * ((long long)N * ((long long)f * g.S + lm0 + t) + jj);
+      double tv = sgn * m * C * Mo[f];
+      if (!STEP) tv += sgn * m * cval * MX[o + 1 - c];
+      double bv = Mu[f] + ph.dt * (nn[f] + tv);
+      const bool bc = (f == 1) ? (jj == 0 || jj == 1 || jj == N - 2 || jj == N - 1) : (jj == 0 || jj == N - 1);
+      if (bc) bv = (STEP && f == 2 && lw == 0 && jj == N - 1 && c == 0) ? 1.0 : 0.0;  // T_00(r_i) = 1
+      if (f < 2 && lw == 0) bv = 0.0;
+      bb[o + c] = bv;
     }
   }
 }
