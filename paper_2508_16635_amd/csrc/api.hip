@@ -86,7 +86,8 @@ struct sc_plan {
   // grid / radial data
   DevBuf d_lmk, d_lml, d_lmbase, d_r, d_rp, d_E, d_ED, d_ED2, d_P, d_Dp, d_D, d_D2, d_D4;
   DevBuf d_ET, d_EDT, d_ED2T, d_DT, d_D2T, d_D4T, d_rtiles, d_PT, d_DpT, d_ptiles;
-  DevBuf d_EF, d_PF, d_D2F;
+  DevBuf d_EF, d_PF, d_D2F, d_DF, d_D4F, d_qtiles;
+  int nqtiles = 0;
   int nrtiles = 0, nptiles = 0;
   // tables and workspaces per precision
   TabLayout tl;
@@ -150,6 +151,10 @@ struct sc_plan {
     g.EF = d_EF.as<double>();
     g.PF = d_PF.as<double>();
     g.D2F = d_D2F.as<double>();
+    g.DF = d_DF.as<double>();
+    g.D4F = d_D4F.as<double>();
+    g.qtiles = d_qtiles.as<int2>();
+    g.nqtiles = nqtiles;
     g.EDT = d_EDT.as<double>();
     g.ED2T = d_ED2T.as<double>();
     g.DT = d_DT.as<double>();
@@ -503,8 +508,14 @@ void refined_solve(sc_plan* P, int nvec, const double* b, double* x, int passes,
   for (int it = 0; it < passes; ++it) {
     {
       Prof _p(P, SC_STAGE_RESIDUAL, s);
-      hipLaunchKernelGGL(sc::k_residual64, dim3(P->hg.S, nvec), dim3(64), 0, s, dg, P->pp(), nvec, b, x,
-                         P->rbuf.as<double>());
+      const dim3 grid(P->nqtiles, nvec);
+      double* r = P->rbuf.as<double>();
+      switch ((P->hg.N + 15) / 16) {
+        case 1: hipLaunchKernelGGL((sc::k_residual64<1>), grid, dim3(256), 0, s, dg, P->pp(), nvec, b, x, r); break;
+        case 2: hipLaunchKernelGGL((sc::k_residual64<2>), grid, dim3(256), 0, s, dg, P->pp(), nvec, b, x, r); break;
+        case 3: hipLaunchKernelGGL((sc::k_residual64<3>), grid, dim3(256), 0, s, dg, P->pp(), nvec, b, x, r); break;
+        default: hipLaunchKernelGGL((sc::k_residual64<4>), grid, dim3(256), 0, s, dg, P->pp(), nvec, b, x, r); break;
+      }
     }
     HIPCHK(hipGetLastError());
     implicit_solve<F>(P, nvec, P->rbuf.as<double>(), P->dbuf.as<double>(), s);
@@ -854,6 +865,15 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
       std::vector<double> F2((size_t)rtn * ksn * 64);
       frag(g.D2, N, N, rtn, ksn, F2.data());
       upload(P->d_D2F, F2);
+      frag(g.D, N, N, rtn, ksn, F2.data());
+      upload(P->d_DF, F2);
+      frag(g.D4, N, N, rtn, ksn, F2.data());
+      upload(P->d_D4F, F2);
+      std::vector<int2> tiles;
+      for (int k = 0; k <= g.K; ++k)
+        for (int il = 0; il < g.nl[k]; il += sc::kRLT) tiles.push_back(make_int2(k, il));
+      upload(P->d_qtiles, tiles);
+      P->nqtiles = (int)tiles.size();
     }
     upload(P->d_ET, transpose(g.E, g.Np, g.N));
     upload(P->d_EDT, transpose(g.ED, g.Np, g.N));

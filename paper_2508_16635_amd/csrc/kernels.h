@@ -50,6 +50,10 @@ struct DevGrid {
   const double* DpT;  // [Np][Np]: Dp^T
   const int2* ptiles; // projection tiles: (k, first l-m)
   int nptiles;
+  const int2* qtiles; // residual tiles: (k, first l-m)
+  int nqtiles;
+  const double* DF;   // D (N x N), operand order
+  const double* D4F;  // D^4 (N x N), operand order
   const double* EF;   // E, ED, ED2 (N_p x N each) in 16x16x4 MFMA operand order, k padded to 16 ceil(N/16)
   const double* PF;   // P diag(1/r), P diag(1/r^2), P diag(1/r^2) Dp diag(r), P (N x N_p each), operand order
   const double* D2F;  // D^2 (N x N), operand order
@@ -1166,128 +1170,137 @@ __device__ inline double kappa_dev(int l, int m) {
   return (ll * ll - 1.0) * sqrt((ll * ll - (double)m * m) / (4.0 * ll * ll - 1.0));
 }
 
-// One workgroup per (vec, lm), one thread per node j; the e, f, T profiles of lm and the
-// e/f neighbours at l +- 1 are staged in LDS; matrices are read transposed (coalesced).
-__global__ void __launch_bounds__(64) k_residual64(DevGrid g, PhysParams ph, int nvec, const double* __restrict__ bvec,
-                                                   const double* __restrict__ xvec, double* __restrict__ rvec) {
-  __shared__ double xs[7][2 * 64];   // e, f, T at lm; e(l-1), f(l-1), e(l+1), f(l+1)
-  __shared__ double xq[2 * 64];      // f / r^2
+// One workgroup per (tile of up to 6 consecutive l at one m, vector).  The columns
+// (Re/Im, t = 0..7) hold l0-1 .. l0+6: the outer two only feed the Coriolis coupling of their
+// neighbours.  The products D e, D^2 e, D f, D^2 f, D^4 f, D^2 (f/r^2), D T, D^2 T run on the FP64
+// matrix cores (wavefront w owns rows 16w..16w+15); the coupling reads its neighbours'
+// products from the adjacent lanes and the other Re/Im component from lane ^ 8.
+constexpr int kRLT = 6;  // own l per residual tile
+
+template <int RTN>
+__global__ void __launch_bounds__(256) k_residual64(DevGrid g, PhysParams ph, int nvec, const double* __restrict__ bvec,
+                                                    const double* __restrict__ xvec, double* __restrict__ rvec) {
+  constexpr int rowsN = 16 * RTN;
+  __shared__ double xs[4][rowsN][16];   // e, f, q = f/r^2, T; column c*8 + t
+  __shared__ double dfb[2][16];         // (D f) at rows 0 and N-1 per column
   const int N = g.N;
-  const int lm = blockIdx.x, vec = blockIdx.y;
-  const int k = g.lm_k[lm], l = g.lm_l[lm];
-  const int m = k * g.m0;
+  const int2 tl = g.qtiles[blockIdx.x];
+  const int vec = blockIdx.y;
+  const int k = tl.x, il0 = tl.y;
+  const int m = k * g.m0, nl = g.L - m + 1;
+  const int nown = min(kRLT, nl - il0);
+  const int lmb = g.lmbase[k];
   const long long ld = 6LL * N * g.S;
   const double* x = xvec + (long long)vec * ld;
-  const bool has_lo = (l - 1 >= max(m, 1)), has_hi = (l + 1 <= g.L);
-  for (int idx = threadIdx.x; idx < 7 * 2 * N; idx += blockDim.x) {
-    int c = idx % (2 * N), a = idx / (2 * N);
-    int f = (a < 3) ? a : ((a - 3) & 1);
-    int dl = (a < 3) ? 0 : (a < 5 ? -1 : 1);
-    bool ok = (a < 3) || (dl < 0 ? has_lo : has_hi);
-    xs[a][c] = ok ? x[2LL * ((long long)N * ((long long)f * g.S + lm + dl)) + c] : 0.0;
-  }
-  __syncthreads();
-  for (int c = threadIdx.x; c < 2 * N; c += blockDim.x) {
-    double r = g.r[c >> 1];
-    xq[c] = xs[1][c] / (r * r);
-  }
-  __syncthreads();
-  const int j = threadIdx.x;
-  const bool active = j < N;
-  const double r = active ? g.r[j] : 1.0, r2 = r * r;
-  const double lam = (double)l * (l + 1);
-  // products with the transposed matrices: column j of M^T gives row j of M
-  double De[2] = {0, 0}, D2e[2] = {0, 0}, Df[2] = {0, 0}, D2f[2] = {0, 0}, D4f[2] = {0, 0}, D2q[2] = {0, 0};
-  double DT_[2] = {0, 0}, D2T_[2] = {0, 0}, Dn[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-  if (active) {
-    for (int i = 0; i < N; ++i) {
-      double d1 = g.DT[(long long)i * N + j], d2 = g.D2T[(long long)i * N + j], d4 = g.D4T[(long long)i * N + j];
-      for (int c = 0; c < 2; ++c) {
-        double e = xs[0][2 * i + c], f = xs[1][2 * i + c], t = xs[2][2 * i + c];
-        De[c] += d1 * e;
-        D2e[c] += d2 * e;
-        Df[c] += d1 * f;
-        D2f[c] += d2 * f;
-        D4f[c] += d4 * f;
-        D2q[c] += d2 * xq[2 * i + c];
-        DT_[c] += d1 * t;
-        D2T_[c] += d2 * t;
-        for (int a = 0; a < 4; ++a) Dn[a][c] += d1 * xs[3 + a][2 * i + c];
-      }
+  for (int idx = threadIdx.x; idx < 3 * 8 * 2 * rowsN; idx += blockDim.x) {
+    const int cj = idx % (2 * rowsN), t = (idx / (2 * rowsN)) % 8, f = idx / (2 * rowsN * 8);
+    const int jj = cj >> 1, c = cj & 1;
+    const int il = il0 - 1 + t;
+    double val = 0.0;
+    if (jj < N && il >= 0 && il < nl)
+      val = x[2LL * ((long long)N * ((long long)f * g.S + lmb + il) + jj) + c];
+    const int fs = (f == 2) ? 3 : f;
+    xs[fs][jj][c * 8 + t] = val;
+    if (f == 1) {
+      const double r = (jj < N) ? g.r[jj] : 1.0;
+      xs[2][jj][c * 8 + t] = val / (r * r);
     }
   }
-  // boundary-row derivatives: (D f)_0 and (D f)_{N-1} for rows 1 and N-2
-  __shared__ double dfb[2][2];
-  if (j == 0 || j == N - 1) {
-    dfb[j == 0 ? 0 : 1][0] = Df[0];
-    dfb[j == 0 ? 0 : 1][1] = Df[1];
+  __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int col = l & 15, c = col >> 3, t = col & 7;
+  // products: 0 De, 1 D2e, 2 Df, 3 D2f, 4 D4f, 5 D2q, 6 DT, 7 D2T
+  f64x4 y[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) y[p] = f64x4{0, 0, 0, 0};
+  if (w < RTN) {
+    const double* A0 = g.DF + (long long)w * 4 * RTN * 64 + l;
+    const double* A1 = g.D2F + (long long)w * 4 * RTN * 64 + l;
+    const double* A2 = g.D4F + (long long)w * 4 * RTN * 64 + l;
+#pragma unroll
+    for (int st = 0; st < 4 * RTN; ++st) {
+      const double d1 = A0[st * 64], d2 = A1[st * 64], d4 = A2[st * 64];
+      const int row = 4 * st + (l >> 4);
+      const double xe = xs[0][row][col], xf = xs[1][row][col], xq = xs[2][row][col], xt = xs[3][row][col];
+      y[0] = Mfma<double>::step(d1, xe, y[0]);
+      y[1] = Mfma<double>::step(d2, xe, y[1]);
+      y[2] = Mfma<double>::step(d1, xf, y[2]);
+      y[3] = Mfma<double>::step(d2, xf, y[3]);
+      y[4] = Mfma<double>::step(d4, xf, y[4]);
+      y[5] = Mfma<double>::step(d2, xq, y[5]);
+      y[6] = Mfma<double>::step(d1, xt, y[6]);
+      y[7] = Mfma<double>::step(d2, xt, y[7]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jj = 16 * w + Mfma<double>::out_row(l, q);
+      if (jj == 0) dfb[0][col] = y[2][q];
+      if (jj == N - 1) dfb[1][col] = y[2][q];
+    }
   }
   __syncthreads();
-  if (!active) return;
+  if (w >= RTN) return;
+  const int il = il0 - 1 + t, lw = m + il;
+  const bool own = (t >= 1 && t <= nown);
+  const bool has_lo = (lw - 1 >= max(m, 1)), has_hi = (lw + 1 <= g.L);
+  const double lam = (double)lw * (lw + 1);
+  const double sg = (c == 0) ? -1.0 : 1.0;
   const double* b = bvec + (long long)vec * ld;
   double* rr = rvec + (long long)vec * ld;
-  for (int f = 0; f < 3; ++f) {
-    long long o = 2LL * ((long long)N * ((long long)f * g.S + lm) + j);
-    double ar, ai;
-    if (f < 2 && l == 0) {
-      rr[o] = 0.0;
-      rr[o + 1] = 0.0;
-      continue;
-    }
-    const double* xsf = xs[f];
-    if (f == 2) {
-      if (j == 0 || j == N - 1) {
-        ar = xsf[2 * j];
-        ai = xsf[2 * j + 1];
-      } else {
-        double Kr = (D2T_[0] + 2.0 / r * DT_[0] - lam / r2 * xsf[2 * j]) / ph.Pr;
-        double Ki = (D2T_[1] + 2.0 / r * DT_[1] - lam / r2 * xsf[2 * j + 1]) / ph.Pr;
-        ar = xsf[2 * j] - ph.dt * Kr;
-        ai = xsf[2 * j + 1] - ph.dt * Ki;
+  const double kap_lo = kappa_dev(lw, m), kap_hi = kappa_dev(lw + 1, m);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    // values from other lanes first (every lane takes part)
+    const double De_lo = __shfl(y[0][q], l - 1), De_hi = __shfl(y[0][q], l + 1);
+    const double Df_lo = __shfl(y[2][q], l - 1), Df_hi = __shfl(y[2][q], l + 1);
+    const double D2f_o = __shfl_xor(y[3][q], 8);
+    const int jj = 16 * w + Mfma<double>::out_row(l, q);
+    if (!own || jj >= N) continue;
+    const double r = g.r[jj], r2 = r * r;
+    const double a = ph.Ek * lam / r2;
+    const int co = col ^ 8;
+    for (int f = 0; f < 3; ++f) {
+      const long long o = 2LL * ((long long)N * ((long long)f * g.S + lmb + il) + jj) + c;
+      if (f < 2 && lw == 0) {
+        rr[o] = 0.0;
+        continue;
       }
-    } else {
-      bool bc = (f == 0) ? (j == 0 || j == N - 1) : (j == 0 || j == 1 || j == N - 2 || j == N - 1);
-      if (bc) {
-        if (j == 0 || j == N - 1) {
-          ar = xsf[2 * j];
-          ai = xsf[2 * j + 1];
-        } else {
-          ar = dfb[j == 1 ? 0 : 1][0];
-          ai = dfb[j == 1 ? 0 : 1][1];
-        }
+      double av;
+      if (f == 2) {
+        const double xt = xs[3][jj][col];
+        if (jj == 0 || jj == N - 1) av = xt;
+        else av = xt - ph.dt * (y[7][q] + 2.0 / r * y[6][q] - lam / r2 * xt) / ph.Pr;
       } else {
-        const double a = ph.Ek * lam / r2;
-        double xr = xsf[2 * j], xi = xsf[2 * j + 1];
-        double cr, ci;
-        if (f == 0) {
-          double Lr = D2e[0] - lam / r2 * xr, Li = D2e[1] - lam / r2 * xi;
-          cr = a * xr - ph.dt * (a * Lr - 2.0 * m / r2 * xi);
-          ci = a * xi - ph.dt * (a * Li + 2.0 * m / r2 * xr);
+        const double xv = xs[f][jj][col], xo = xs[f][jj][co];
+        const bool bc = (f == 0) ? (jj == 0 || jj == N - 1) : (jj == 0 || jj == 1 || jj == N - 2 || jj == N - 1);
+        if (bc) {
+          if (jj == 0 || jj == N - 1) av = xv;
+          else av = dfb[jj == 1 ? 0 : 1][col];
         } else {
-          double Lr = D2f[0] - lam / r2 * xr, Li = D2f[1] - lam / r2 * xi;
-          double L2r = D4f[0] - lam * D2q[0] - lam / r2 * D2f[0] + lam * lam / (r2 * r2) * xr;
-          double L2i = D4f[1] - lam * D2q[1] - lam / r2 * D2f[1] + lam * lam / (r2 * r2) * xi;
-          cr = -a * Lr + ph.dt * (a * L2r - 2.0 * m / r2 * Li);
-          ci = -a * Li + ph.dt * (a * L2i + 2.0 * m / r2 * Lr);
+          double cv;
+          if (f == 0) {
+            const double L_ = y[1][q] - lam / r2 * xv;
+            cv = a * xv - ph.dt * (a * L_ + sg * 2.0 * m / r2 * xo);
+          } else {
+            const double L_ = y[3][q] - lam / r2 * xv, Lo = D2f_o - lam / r2 * xo;
+            const double L2 = y[4][q] - lam * y[5][q] - lam / r2 * y[3][q] + lam * lam / (r2 * r2) * xv;
+            cv = -a * L_ + ph.dt * (a * L2 + sg * 2.0 * m / r2 * Lo);
+          }
+          // Coriolis coupling to the other potential at l-1 and l+1
+          const int fo = 1 - f;
+          if (has_lo && kap_lo != 0.0) {
+            const double xn = xs[fo][jj][col - 1], Dn = (f == 0) ? Df_lo : De_lo;
+            cv += ph.dt * 2.0 / r2 * kap_lo * ((double)lw / r * xn - Dn);
+          }
+          if (has_hi && kap_hi != 0.0) {
+            const double xn = xs[fo][jj][col + 1], Dn = (f == 0) ? Df_hi : De_hi;
+            cv += ph.dt * 2.0 / r2 * kap_hi * (-(lw + 1.0) / r * xn - Dn);
+          }
+          av = cv;
         }
-        // Coriolis coupling to the other potential at l-1 and l+1
-        for (int nb = -1; nb <= 1; nb += 2) {
-          if (nb < 0 ? !has_lo : !has_hi) continue;
-          double kap = (nb < 0) ? kappa_dev(l, m) : kappa_dev(l + 1, m);
-          if (kap == 0.0) continue;
-          double cc = (nb < 0) ? (double)l : -(l + 1.0);
-          int a_ = 3 + (nb < 0 ? 0 : 2) + (1 - f);   // other potential: f-row uses e, e-row uses f
-          const double* xn = xs[a_];
-          double pre = ph.dt * 2.0 / r2 * kap;
-          cr += pre * (cc / r * xn[2 * j] - Dn[a_ - 3][0]);
-          ci += pre * (cc / r * xn[2 * j + 1] - Dn[a_ - 3][1]);
-        }
-        ar = cr;
-        ai = ci;
       }
+      rr[o] = b[o] - av;
     }
-    rr[o] = b[o] - ar;
-    rr[o + 1] = b[o + 1] - ai;
   }
 }
 
