@@ -248,7 +248,8 @@ def main():
     ap.add_argument("--nvectors", type=int, default=200)
     ap.add_argument("--cpu-sample", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--refine-mixed", type=int, default=2, help="FP64 refinement passes of the mixed solve")
+    ap.add_argument("--refine-mixed", type=int, default=1,
+                    help="FP64 refinement passes (FP64 residual + FP64 correction) after the FP32 solve")
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--restart", type=int, default=100)
     ap.add_argument("--max-matvec", type=int, default=300)

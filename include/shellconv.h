@@ -59,8 +59,9 @@ typedef struct {
                                 smallest 2^a 3^b 5^c >= 3K+1 (Sec. 3.1)                      */
   int device;             /* HIP device ordinal                                              */
   int nvec_max;           /* largest batch passed to sc_jvp (0 = 16); sizes the workspaces   */
-  int refine_fp64;        /* FP64 refinement passes of the implicit solve (< 0: default 1)   */
-  int refine_mixed;       /* refinement passes of the FP32 solve (< 0: default 2)            */
+  int refine_fp64;        /* FP64 refinement passes after the FP64 solve (< 0: default 1)    */
+  int refine_mixed;       /* FP64 refinement passes after the FP32 solve (< 0: default 1);
+                             a pass is an FP64 residual and an FP64 correction solve          */
 } sc_params;
 
 typedef struct {
@@ -94,8 +95,9 @@ int sc_newton_residual(sc_plan* plan, const double* x, double C, double* r, doub
 int sc_set_base(sc_plan* plan, const double* x, double C, long long J, void* stream);
 /* Jacobian action y_i = (B_X - I)(u_i, c_i) on nvec vectors (Sec. 3.3 eq:precond, Sec. 3.4):
  * c_i = v_i[J], u_i = v_i with slot J zeroed; homogeneous boundary rows.
- * SC_FP64: every stage in FP64.  SC_MIXED: transforms and back-substitution in FP32 with
- * FP32 accumulation, FP64 radial operators, right-hand side, residual and refinement. */
+ * SC_FP64: every stage in FP64.  SC_MIXED: transforms and the first block back-substitution
+ * in FP32 with FP32 accumulation; FP64 radial operators, right-hand side, residual and the
+ * refinement passes (refine_mixed). */
 int sc_jvp(sc_plan* plan, int nvec, const double* v, long long ldv, double* y, long long ldy,
            sc_precision prec, void* stream);
 /* Newton-GMRES on R_C(X) = B_C(X) - X (+ forcing), Sec. 3.3 and 3.4: each Newton step solves
@@ -137,7 +139,7 @@ enum {
   SC_STAGE_CHAIN_SOLVE = 5,     /* block-tridiagonal e/f solves                            */
   SC_STAGE_T_SOLVE = 6,         /* temperature solves                                      */
   SC_STAGE_RESIDUAL = 7,        /* FP64 residual of the implicit operator                  */
-  SC_STAGE_AXPY = 8,            /* refinement update                                       */
+  SC_STAGE_AXPY = 8,            /* refinement update (now folded into the correction solve) */
   SC_STAGE_FINALIZE = 9,        /* output assembly                                         */
   SC_NSTAGES = 10
 };

@@ -77,7 +77,7 @@ struct sc_plan {
   sc_params prm{};
   sc::HostGrid hg;
   int vcap = 16, wcap = 16;
-  int refine64 = 1, refine32 = 2;
+  int refine64 = 1, refine32 = 1;
   int fft_nr = 0, fft_r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   long long n_real = 0;
   bool factored = false, have_base = false;
@@ -437,7 +437,7 @@ size_t tsolve_smem(const sc::HostGrid& g) {
 }
 
 // The seven chain-solve launches for RT = ceil(N/16) row tiles.
-template <class F, int RT>
+template <class F, int RT, bool ACC>
 void chain_solve_rt(sc_plan* P, int nvec, const double* b, double* x, hipStream_t s) {
   sc::DevGrid dg = P->dg();
   const int nvg = (nvec + kVG - 1) / kVG;
@@ -469,23 +469,24 @@ void chain_solve_rt(sc_plan* P, int nvec, const double* b, double* x, hipStream_
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL((sc::k_cs_bwd_bound<F, RT>), dim3(P->nchains, nvg), blk, 0, s, dg, nvec, ch, kSeg, Psi, W);
   HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL((sc::k_cs_out<F, RT>), dim3(P->nblocks, nvg), blk, 0, s, dg, nvec, P->blk_field.as<int>(),
+  hipLaunchKernelGGL((sc::k_cs_out<F, RT, ACC>), dim3(P->nblocks, nvg), blk, 0, s, dg, nvec, P->blk_field.as<int>(),
                      P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const C*)W, x);
   HIPCHK(hipGetLastError());
 }
 
-// Implicit solve x = A^{-1} b with factors in precision F (all vectors in canonical FP64).
-template <class F>
+// Implicit solve x = A^{-1} b (ACC: x += A^{-1} b) with factors in precision F (all vectors
+// in canonical FP64).
+template <class F, bool ACC>
 void implicit_solve(sc_plan* P, int nvec, const double* b, double* x, hipStream_t s) {
   sc::DevGrid dg = P->dg();
   const bool d = std::is_same<F, double>::value;
   {
     Prof _p(P, SC_STAGE_CHAIN_SOLVE, s);
     switch ((P->hg.N + 15) / 16) {
-      case 1: chain_solve_rt<F, 1>(P, nvec, b, x, s); break;
-      case 2: chain_solve_rt<F, 2>(P, nvec, b, x, s); break;
-      case 3: chain_solve_rt<F, 3>(P, nvec, b, x, s); break;
-      default: chain_solve_rt<F, 4>(P, nvec, b, x, s); break;
+      case 1: chain_solve_rt<F, 1, ACC>(P, nvec, b, x, s); break;
+      case 2: chain_solve_rt<F, 2, ACC>(P, nvec, b, x, s); break;
+      case 3: chain_solve_rt<F, 3, ACC>(P, nvec, b, x, s); break;
+      default: chain_solve_rt<F, 4, ACC>(P, nvec, b, x, s); break;
     }
   }
   const F* Ti = (const F*)(d ? P->Tinv64.p : P->Tinv32.p);
@@ -493,18 +494,18 @@ void implicit_solve(sc_plan* P, int nvec, const double* b, double* x, hipStream_
   const F* tc = (const F*)(d ? P->tc64.p : P->tc32.p);
   {
     Prof _p(P, SC_STAGE_T_SOLVE, s);
-    hipLaunchKernelGGL(sc::k_T_solve<F>, dim3(P->hg.L + 1, (nvec + sc::kTV - 1) / sc::kTV), dim3(256), tsolve_smem<F>(P->hg), s,
+    hipLaunchKernelGGL((sc::k_T_solve<F, ACC>), dim3(P->hg.L + 1, (nvec + sc::kTV - 1) / sc::kTV), dim3(256), tsolve_smem<F>(P->hg), s,
                        dg, nvec, Ti, tr, tc, b, x);
     HIPCHK(hipGetLastError());
   }
 }
 
-// x = A^{-1} b with `passes` FP64 refinement passes; factors in precision F.
+// x = A^{-1} b: a solve with the factors in precision F, then `passes` FP64 refinement passes
+// (FP64 residual r = b - A x, FP64 correction solve added to x).
 template <class F>
 void refined_solve(sc_plan* P, int nvec, const double* b, double* x, int passes, hipStream_t s) {
-  implicit_solve<F>(P, nvec, b, x, s);
+  implicit_solve<F, false>(P, nvec, b, x, s);
   sc::DevGrid dg = P->dg();
-  long long n = (long long)nvec * P->n_real;
   for (int it = 0; it < passes; ++it) {
     {
       Prof _p(P, SC_STAGE_RESIDUAL, s);
@@ -518,12 +519,7 @@ void refined_solve(sc_plan* P, int nvec, const double* b, double* x, int passes,
       }
     }
     HIPCHK(hipGetLastError());
-    implicit_solve<F>(P, nvec, P->rbuf.as<double>(), P->dbuf.as<double>(), s);
-    {
-      Prof _p(P, SC_STAGE_AXPY, s);
-      hipLaunchKernelGGL(sc::k_axpy1, dim3(nblk(n, 256)), dim3(256), 0, s, n, P->dbuf.as<const double>(), x);
-    }
-    HIPCHK(hipGetLastError());
+    implicit_solve<double, true>(P, nvec, P->rbuf.as<double>(), x, s);
   }
 }
 
@@ -784,7 +780,7 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     P->vcap = p.nvec_max > 0 ? p.nvec_max : 16;
     P->wcap = (P->vcap + kVG - 1) / kVG * kVG;
     P->refine64 = p.refine_fp64 >= 0 ? p.refine_fp64 : 1;
-    P->refine32 = p.refine_mixed >= 0 ? p.refine_mixed : 2;
+    P->refine32 = p.refine_mixed >= 0 ? p.refine_mixed : 1;
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
     if (p.device < 0 || p.device >= ndev) throw Fail{SC_ERR_ARG, "bad device ordinal"};
@@ -925,10 +921,12 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     {
       const size_t t64 = tsolve_smem<double>(g), t32 = tsolve_smem<float>(g);
       if (t64 > 160 * 1024) throw Fail{SC_ERR_ARG, "too many m for the temperature solve"};
-      if (t64 > 64 * 1024)
-        HIPCHK(hipFuncSetAttribute((const void*)sc::k_T_solve<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t64));
+      if (t64 > 64 * 1024) {
+        HIPCHK(hipFuncSetAttribute((const void*)sc::k_T_solve<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t64));
+        HIPCHK(hipFuncSetAttribute((const void*)sc::k_T_solve<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t64));
+      }
       if (t32 > 64 * 1024)
-        HIPCHK(hipFuncSetAttribute((const void*)sc::k_T_solve<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t32));
+        HIPCHK(hipFuncSetAttribute((const void*)sc::k_T_solve<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t32));
     }
     // deterministic contents for slots the solves never write (e, f at l = 0)
     HIPCHK(hipMemset(P->xbuf.p, 0, P->xbuf.bytes));

@@ -1086,8 +1086,9 @@ __global__ void __launch_bounds__(kSolveThreads) k_cs_fix(DevGrid g, int nvec, c
 }
 
 // x_i = xi_i + Psi_i x_{a(p+1)} for the blocks not yet final, then x = Cg x~ into the
-// canonical FP64 output.  One workgroup per (block, vector group).
-template <class F, int RT>
+// canonical FP64 output (ACC: added to it, the update of a refinement pass).  One workgroup
+// per (block, vector group).
+template <class F, int RT, bool ACC>
 __global__ void __launch_bounds__(kSolveThreads) k_cs_out(DevGrid g, int nvec, const int* __restrict__ blk_field,
                                                          const int* __restrict__ blk_lm, const int* __restrict__ blk_next,
                                                          const cpx<F>* __restrict__ Psi, const F* __restrict__ Cg,
@@ -1116,18 +1117,25 @@ __global__ void __launch_bounds__(kSolveThreads) k_cs_out(DevGrid g, int nvec, c
       if (r < N && op.col < nv) {
         const double c = (double)Cg[(long long)blk * N + r];
         double* xp = xvec + (long long)(v0 + op.col) * ld + o + 2 * r;
-        xp[0] = c * (double)(S.w[q].re + yr[q]);
-        xp[1] = c * (double)(S.w[q].im + yi[q]);
+        const double x0 = c * (double)(S.w[q].re + yr[q]), x1 = c * (double)(S.w[q].im + yi[q]);
+        if (ACC) {
+          xp[0] += x0;
+          xp[1] += x1;
+        } else {
+          xp[0] = x0;
+          xp[1] = x1;
+        }
       }
     }
   }
 }
 
-// Temperature blocks: x = tc * Tinv (tr * b) per l, for every (vec, k, l), both Re and Im.
-// One workgroup per (l, group of kTV vectors): Tinv_l staged in LDS, columns (vec, k, Re/Im).
+// Temperature blocks: x = tc * Tinv (tr * b) per l, for every (vec, k, l), both Re and Im
+// (ACC: added to x).  One workgroup per (l, group of kTV vectors): Tinv_l staged in LDS,
+// columns (vec, k, Re/Im).
 constexpr int kTV = 4;
 
-template <class F>
+template <class F, bool ACC>
 __global__ void __launch_bounds__(256) k_T_solve(DevGrid g, int nvec, const F* __restrict__ Tinv,
                                                  const F* __restrict__ tr, const F* __restrict__ tc,
                                                  const double* __restrict__ bvec, double* __restrict__ xvec) {
@@ -1157,7 +1165,9 @@ __global__ void __launch_bounds__(256) k_T_solve(DevGrid g, int nvec, const F* _
     for (int i = 0; i < N; ++i) a += Ts[i * N + jj] * bc[i];
     int lm = g.lmbase[kk] + l - kk * g.m0;
     long long o = (long long)(v0 + vv) * ld + 2LL * ((long long)N * (2LL * g.S + lm) + jj) + ri;
-    xvec[o] = (double)(tc[(long long)l * N + jj] * a);
+    const double xv = (double)(tc[(long long)l * N + jj] * a);
+    if (ACC) xvec[o] += xv;
+    else xvec[o] = xv;
   }
 }
 
