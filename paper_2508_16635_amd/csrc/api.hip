@@ -896,10 +896,10 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     build_tables(P.get());
     build_workspaces(P.get());
     {
-      // azimuthal FFT plan: radices 4, then 2, 3, 5
+      // azimuthal FFT plan: radices 8, then 4, 2, 3, 5
       int n = g.nphi, nr = 0;
       P->fft_nr = 0;
-      for (int R : {4, 2, 3, 5})
+      for (int R : {8, 4, 2, 3, 5})
         while (n % R == 0) {
           if (nr == 8) throw Fail{SC_ERR_ARG, "nphi needs more than 8 FFT passes"};
           P->fft_r[nr++] = R;

@@ -368,6 +368,21 @@ __device__ inline void small_dft(cz<T>* v, T sgn) {
     v[2] = {s0.re - s2.re, s0.im - s2.im};
     v[1] = {s1.re + is3.re, s1.im + is3.im};
     v[3] = {s1.re - is3.re, s1.im - is3.im};
+  } else if (R == 8) {
+    // two radix-4 transforms of the even and odd samples, combined with w^k, w = exp(sgn 2 pi i/8)
+    const T c8 = (T)0.70710678118654752440;
+    cz<T> e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    small_dft<T, 4>(e, sgn);
+    small_dft<T, 4>(o, sgn);
+    const cz<T> t1 = {c8 * (o[1].re - sgn * o[1].im), c8 * (o[1].im + sgn * o[1].re)};
+    const cz<T> t2 = {-sgn * o[2].im, sgn * o[2].re};
+    const cz<T> t3 = {c8 * (-o[3].re - sgn * o[3].im), c8 * (-o[3].im + sgn * o[3].re)};
+    const cz<T> tw[4] = {o[0], t1, t2, t3};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = {e[k].re + tw[k].re, e[k].im + tw[k].im};
+      v[k + 4] = {e[k].re - tw[k].re, e[k].im - tw[k].im};
+    }
   } else if (R == 3) {
     const T h = (T)0.86602540378443864676;  // sin(2 pi / 3)
     const cz<T> a = v[0], t = {v[1].re + v[2].re, v[1].im + v[2].im}, u = {v[1].re - v[2].re, v[1].im - v[2].im};
@@ -395,10 +410,14 @@ __device__ inline void small_dft(cz<T>* v, T sgn) {
   }
 }
 
+// LDS slot of complex entry i of the ring buffer: one pad entry after every 16 breaks the
+// power-of-two strides of the butterflies and of the (ring, point) accesses across banks.
+__device__ inline int lp(int i) { return i + (i >> 4); }
+
 // Layout of the transforms of a workgroup in LDS: transform t lives at
-// (t / per) * stride + (t % per) * N (per transforms of each ring, consecutive).
+// (t / PER) * stride + (t % PER) * N (PER transforms of each ring, consecutive).
 struct FftSet {
-  int ntr, per, stride;
+  int ntr, stride;
 };
 
 constexpr int kRingThreads = 256;
@@ -410,15 +429,22 @@ __host__ __device__ constexpr int ring_cap() {
   return sizeof(T) == 4 ? 4096 : 2048;
 }
 
+// Exact quotient a / b for 0 <= a < 2^13 and 1 <= b < 2^12 through a single-precision
+// reciprocal (rcp_b = 1/b rounded): the error of (a + 1/2) rcp_b stays far below the 1/(2b)
+// margin to the next integer, so no integer division is issued.
+__device__ inline int fdiv_small(int a, float rcp_b) { return (int)(((float)a + 0.5f) * rcp_b); }
+
 // One radix-R Stockham pass (Ns = product of the radices of the earlier passes), in place:
 // every thread first reads and transforms its butterflies into registers, then, after a
 // barrier, all of them write.  w[m] = exp(-2 pi i m / N); the inverse (sgn = +1) uses its
 // conjugate.  Requires fs.ntr * N <= ring_cap<T>().  Kept out of line so that the register
 // staging of the four radices is not allocated side by side in the caller.
-template <class T, int R>
-__device__ __attribute__((noinline)) void stockham_pass(cz<T>* buf, int N, int Ns, FftSet fs, const cz<T>* __restrict__ w, T sgn) {
+template <class T, int R, int PER>
+__device__ __attribute__((noinline)) void stockham_pass(cz<T>* buf, int N, int Ns, FftSet fs, const cz<T>* __restrict__ w,
+                                                        T sgn) {
   constexpr int MAXB = (ring_cap<T>() + R * kRingThreads - 1) / (R * kRingThreads);
   const int nb = N / R, step = N / (Ns * R), total = fs.ntr * nb;
+  const float rnb = 1.0f / (float)nb, rNs = 1.0f / (float)Ns;
   cz<T> v[MAXB][R];
   int dst[MAXB];
 #pragma unroll
@@ -426,12 +452,12 @@ __device__ __attribute__((noinline)) void stockham_pass(cz<T>* buf, int N, int N
     const int idx = threadIdx.x + b * kRingThreads;
     dst[b] = -1;
     if (idx < total) {
-      const int t = idx / nb, j = idx - t * nb;
-      const int o = (t / fs.per) * fs.stride + (t % fs.per) * N;
-      const int k = j % Ns;
+      const int t = fdiv_small(idx, rnb), j = idx - t * nb;
+      const int o = (t / PER) * fs.stride + (t % PER) * N;
+      const int qq = fdiv_small(j, rNs), k = j - qq * Ns;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        cz<T> a = buf[o + j + r * nb];
+        cz<T> a = buf[lp(o + j + r * nb)];
         if (r > 0) {
           const cz<T> tw = w[k * r * step];
           const T twi = (sgn < 0) ? tw.im : -tw.im;
@@ -440,7 +466,7 @@ __device__ __attribute__((noinline)) void stockham_pass(cz<T>* buf, int N, int N
         v[b][r] = a;
       }
       small_dft<T, R>(v[b], sgn);
-      dst[b] = o + (j - k) * R + k;
+      dst[b] = o + qq * Ns * R + k;
     }
   }
   __syncthreads();
@@ -448,21 +474,22 @@ __device__ __attribute__((noinline)) void stockham_pass(cz<T>* buf, int N, int N
   for (int b = 0; b < MAXB; ++b)
     if (dst[b] >= 0) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[dst[b] + r * Ns] = v[b][r];
+      for (int r = 0; r < R; ++r) buf[lp(dst[b] + r * Ns)] = v[b][r];
     }
   __syncthreads();
 }
 
 // All passes of the plan's radices over the set, in place.
-template <class T>
+template <class T, int PER>
 __device__ inline void fft_run(const DevGrid& g, cz<T>* buf, FftSet fs, const cz<T>* w, T sgn) {
   int Ns = 1;
   for (int s = 0; s < g.fft_nr; ++s) {
     const int R = g.fft_r[s];
-    if (R == 4) stockham_pass<T, 4>(buf, g.nphi, Ns, fs, w, sgn);
-    else if (R == 2) stockham_pass<T, 2>(buf, g.nphi, Ns, fs, w, sgn);
-    else if (R == 3) stockham_pass<T, 3>(buf, g.nphi, Ns, fs, w, sgn);
-    else stockham_pass<T, 5>(buf, g.nphi, Ns, fs, w, sgn);
+    if (R == 8) stockham_pass<T, 8, PER>(buf, g.nphi, Ns, fs, w, sgn);
+    else if (R == 4) stockham_pass<T, 4, PER>(buf, g.nphi, Ns, fs, w, sgn);
+    else if (R == 2) stockham_pass<T, 2, PER>(buf, g.nphi, Ns, fs, w, sgn);
+    else if (R == 3) stockham_pass<T, 3, PER>(buf, g.nphi, Ns, fs, w, sgn);
+    else stockham_pass<T, 5, PER>(buf, g.nphi, Ns, fs, w, sgn);
     Ns *= R;
   }
 }
@@ -470,7 +497,8 @@ __device__ inline void fft_run(const DevGrid& g, cz<T>* buf, FftSet fs, const cz
 // LDS bytes of k_ring for 2^rt_log2 rings per workgroup.
 template <class T>
 __host__ __device__ inline size_t ring_lds_bytes(int nphi, int rt_log2) {
-  return sizeof(cz<T>) * ((size_t)nphi + (size_t)5 * nphi * ((size_t)1 << rt_log2));
+  const size_t n = (size_t)5 * nphi * ((size_t)1 << rt_log2);
+  return sizeof(cz<T>) * ((size_t)nphi + n + n / 16 + 1);
 }
 
 template <class T, int MODE>
@@ -510,7 +538,7 @@ __global__ void __launch_bounds__(kRingThreads) k_ring(DevGrid g, int nvec, int 
   }
   for (int i = tid; i < N; i += kRingThreads) w[i] = {fw[2 * i], fw[2 * i + 1]};
   // spectra entries K < k < N - K stay zero
-  for (int i = tid; i < RT * 5 * N; i += kRingThreads) X[i] = {(T)0, (T)0};
+  for (int i = tid; i < lp(RT * 5 * N); i += kRingThreads) X[i] = {(T)0, (T)0};
   __syncthreads();
   // step A: gather the Legendre sums and form the Fourier coefficients of the 9 fields,
   // packing fields (2q, 2q+1) into spectrum q: Z_k = (A_k + i B_k)/2, Z_{N-k} = conj(A_k)/2 +
@@ -546,21 +574,21 @@ __global__ void __launch_bounds__(kRingThreads) k_ring(DevGrid g, int nvec, int 
     fr[7] = dPr(4); fi[7] = dPi(4);                      // (1/r) dT/dth
     fr[8] = -mPi(4); fi[8] = mPr(4);                     // (1/(r sin)) dT/dph
     fr[9] = 0; fi[9] = 0;
-    cz<T>* Z = X + tt * 5 * N;
+    const int zb = tt * 5 * N;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       const T ar = fr[2 * q], ai = fi[2 * q], br = fr[2 * q + 1], bi = fi[2 * q + 1];
       if (k == 0) {
-        Z[q * N] = {ar, br};
+        X[lp(zb + q * N)] = {ar, br};
       } else {
-        Z[q * N + k] = {(T)0.5 * (ar - bi), (T)0.5 * (ai + br)};
-        Z[q * N + N - k] = {(T)0.5 * (ar + bi), (T)0.5 * (br - ai)};
+        X[lp(zb + q * N + k)] = {(T)0.5 * (ar - bi), (T)0.5 * (ai + br)};
+        X[lp(zb + q * N + N - k)] = {(T)0.5 * (ar + bi), (T)0.5 * (br - ai)};
       }
     }
   }
   __syncthreads();
   // step B: inverse transforms; spectrum q of a ring becomes field 2q + i field 2q+1
-  fft_run<T>(g, X, FftSet{5 * RT, 5, 5 * N}, w, (T)1);
+  fft_run<T, 5>(g, X, FftSet{5 * RT, 5 * N}, w, (T)1);
   // step C: pointwise products, written in place as slot 0 = W_r + i Q, slot 1 = W_th + i W_ph
 #pragma unroll
   for (int u = 0; u < NPT; ++u) {
@@ -568,12 +596,13 @@ __global__ void __launch_bounds__(kRingThreads) k_ring(DevGrid g, int nvec, int 
     if (idx >= N * RT) continue;
     const int tt = idx & rmask, p = idx >> rt_log2;
     const int th = th0 + tt;
-    cz<T>* Zr = X + tt * 5 * N;
+    const int zb = tt * 5 * N;
     T f[10];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      f[2 * q] = Zr[q * N + p].re;
-      f[2 * q + 1] = Zr[q * N + p].im;
+      const cz<T> zq = X[lp(zb + q * N + p)];
+      f[2 * q] = zq.re;
+      f[2 * q + 1] = zq.im;
     }
     if (MODE == RING_SYNTH) {
       if (th < nth) {
@@ -601,13 +630,13 @@ __global__ void __launch_bounds__(kRingThreads) k_ring(DevGrid g, int nvec, int 
       W2 = Ek * ((b[0] * f[4] - b[1] * f[3]) + (f[0] * b[4] - f[1] * b[3]));
       Q = -((b[0] * f[6] + b[1] * f[7] + b[2] * f[8]) + (f[0] * b[6] + f[1] * b[7] + f[2] * b[8]));
     }
-    Zr[p] = {W0, Q};
-    Zr[N + p] = {W1, W2};
+    X[lp(zb + p)] = {W0, Q};
+    X[lp(zb + N + p)] = {W1, W2};
   }
   if (MODE == RING_SYNTH) return;
   __syncthreads();
   // step D: forward transforms of slots 0 and 1 of every ring
-  fft_run<T>(g, X, FftSet{2 * RT, 2, 5 * N}, w, (T)-1);
+  fft_run<T, 2>(g, X, FftSet{2 * RT, 5 * N}, w, (T)-1);
   // step E: split the packed pair, scale by (2 - delta_k0)/N_phi, write analysis inputs
   const long long Ma = (long long)4 * g.Np * g.vcap;
   for (int idx = tid; idx < 2 * K1 * RT; idx += kRingThreads) {
@@ -616,13 +645,14 @@ __global__ void __launch_bounds__(kRingThreads) k_ring(DevGrid g, int nvec, int 
     const int k = idx >> (rt_log2 + 1);
     const int th = th0 + tt;
     if (th >= nth) continue;
-    const cz<T>* Z = X + tt * 5 * N + o * N;
+    const int zb = tt * 5 * N + o * N;
     const T sc = (k == 0 ? (T)1 : (T)2) / (T)N;
     T ar, ai, br, bi;
     if (k == 0) {
-      ar = Z[0].re; ai = 0; br = Z[0].im; bi = 0;
+      const cz<T> z0 = X[lp(zb)];
+      ar = z0.re; ai = 0; br = z0.im; bi = 0;
     } else {
-      const cz<T> zk = Z[k], zm = Z[N - k];
+      const cz<T> zk = X[lp(zb + k)], zm = X[lp(zb + N - k)];
       ar = (T)0.5 * (zk.re + zm.re);
       ai = (T)0.5 * (zk.im - zm.im);
       br = (T)0.5 * (zk.im + zm.im);
