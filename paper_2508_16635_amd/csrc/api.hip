@@ -116,8 +116,15 @@ struct sc_plan {
   std::vector<int> ev_stage;            // stage of each recorded pair
   int ev_used = 0;
 
+  // side stream (default priority) for the temperature solve, which runs beside the chains
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
   ~sc_plan() {
     for (auto e : ev) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
   }
 
   sc::DevGrid dg() const {
@@ -480,6 +487,18 @@ template <class F, bool ACC>
 void implicit_solve(sc_plan* P, int nvec, const double* b, double* x, hipStream_t s) {
   sc::DevGrid dg = P->dg();
   const bool d = std::is_same<F, double>::value;
+  // the temperature blocks are independent of the chains: solve them on the side stream
+  HIPCHK(hipEventRecord(P->ev_fork, s));
+  HIPCHK(hipStreamWaitEvent(P->side, P->ev_fork, 0));
+  {
+    const F* Ti = (const F*)(d ? P->Tinv64.p : P->Tinv32.p);
+    const F* tr = (const F*)(d ? P->tr64.p : P->tr32.p);
+    const F* tc = (const F*)(d ? P->tc64.p : P->tc32.p);
+    Prof _p(P, SC_STAGE_T_SOLVE, P->side);
+    hipLaunchKernelGGL((sc::k_T_solve<F, ACC>), dim3(P->hg.L + 1, (nvec + sc::kTV - 1) / sc::kTV), dim3(256),
+                       tsolve_smem<F>(P->hg), P->side, dg, nvec, Ti, tr, tc, b, x);
+    HIPCHK(hipGetLastError());
+  }
   {
     Prof _p(P, SC_STAGE_CHAIN_SOLVE, s);
     switch ((P->hg.N + 15) / 16) {
@@ -489,15 +508,8 @@ void implicit_solve(sc_plan* P, int nvec, const double* b, double* x, hipStream_
       default: chain_solve_rt<F, 4, ACC>(P, nvec, b, x, s); break;
     }
   }
-  const F* Ti = (const F*)(d ? P->Tinv64.p : P->Tinv32.p);
-  const F* tr = (const F*)(d ? P->tr64.p : P->tr32.p);
-  const F* tc = (const F*)(d ? P->tc64.p : P->tc32.p);
-  {
-    Prof _p(P, SC_STAGE_T_SOLVE, s);
-    hipLaunchKernelGGL((sc::k_T_solve<F, ACC>), dim3(P->hg.L + 1, (nvec + sc::kTV - 1) / sc::kTV), dim3(256), tsolve_smem<F>(P->hg), s,
-                       dg, nvec, Ti, tr, tc, b, x);
-    HIPCHK(hipGetLastError());
-  }
+  HIPCHK(hipEventRecord(P->ev_join, P->side));
+  HIPCHK(hipStreamWaitEvent(s, P->ev_join, 0));
 }
 
 // x = A^{-1} b: a solve with the factors in precision F, then `passes` FP64 refinement passes
@@ -785,6 +797,9 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     HIPCHK(hipGetDeviceCount(&ndev));
     if (p.device < 0 || p.device >= ndev) throw Fail{SC_ERR_ARG, "bad device ordinal"};
     HIPCHK(hipSetDevice(p.device));
+    HIPCHK(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
     try {
       sc::build_grid(P->hg, p.L, p.M, p.m0, p.N, p.radius_ratio, p.nr_phys, p.ntheta, p.nphi);
     } catch (const std::runtime_error& e) {
