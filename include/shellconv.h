@@ -147,6 +147,22 @@ int sc_profile(sc_plan* plan, int enable);
 int sc_profile_read(sc_plan* plan, double* ms_total, long long* count, int nstages);
 const char* sc_last_error(void);
 
+/* Ragged batches of problems (plans of different L, M, m0, N, Ek, Ra, ...) on one device, e.g.
+ * the points of a continuation in (Ra, Ek) (Sec. 4).  sc_batch_jvp applies the Jacobian of every
+ * plan to its own vectors, each plan on a stream branch of its own forked from `stream` and
+ * joined back into it, so that problems of uneven size share the device.
+ *   plans: nplans >= 1 distinct plans on one device; the batch keeps the pointers, does not
+ *          own the plans, and must be destroyed before them.
+ *   nvec[i] (0..nvec_max of plan i), v[i], y[i]: vectors of plan i, leading dimension n_real.
+ * Errors: SC_ERR_ARG (bad sizes, plans on different devices, a plan listed twice),
+ * SC_ERR_STATE (a plan without factor or base, or with the stage profiler on).  Calls that
+ * overlap on one batch, or that share a plan, race. */
+typedef struct sc_batch sc_batch;
+int sc_batch_create(sc_batch** out, sc_plan* const* plans, int nplans);
+int sc_batch_destroy(sc_batch* batch);
+int sc_batch_jvp(sc_batch* batch, const int* nvec, const double* const* v, double* const* y, sc_precision prec,
+                 void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,6 +78,9 @@ def load_library(path: str = LIB_PATH):
         "sc_newton": [vp, vp, ctypes.POINTER(d), ctypes.POINTER(_NewtonOpts), ctypes.POINTER(_NewtonReport), vp],
         "sc_profile": [vp, i],
         "sc_profile_read": [vp, ctypes.POINTER(d), ctypes.POINTER(ll), i],
+        "sc_batch_create": [ctypes.POINTER(vp), ctypes.POINTER(vp), i],
+        "sc_batch_destroy": [vp],
+        "sc_batch_jvp": [vp, ctypes.POINTER(i), ctypes.POINTER(vp), ctypes.POINTER(vp), i, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -96,7 +99,7 @@ STAGES = ["radial_prep", "legendre_synth", "ring", "legendre_anal", "project_rhs
 def exported_symbols():
     return ["sc_plan_create", "sc_plan_destroy", "sc_layout", "sc_set_params", "sc_factor", "sc_step",
             "sc_newton_residual", "sc_set_base", "sc_jvp", "sc_newton", "sc_profile", "sc_profile_read",
-            "sc_last_error"]
+            "sc_last_error", "sc_batch_create", "sc_batch_destroy", "sc_batch_jvp"]
 
 
 def _check(rc):
@@ -201,3 +204,47 @@ class Plan:
         return c.value, {"newton_steps": k, "matvecs": rep.matvecs, "converged": bool(rep.converged),
                          "rnorm": [rep.rnorm[i] for i in range(k + 1)],
                          "step_matvecs": [rep.step_matvecs[i] for i in range(k)]}
+
+
+class Batch:
+    """A ragged batch of plans whose Jacobian actions run on concurrent stream branches.
+
+    The batch keeps references to its plans; destroy it (close()) before them."""
+
+    def __init__(self, plans):
+        lib = load_library()
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib.sc_batch_create(ctypes.byref(h), arr, len(self.plans)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.sc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def jvp(self, vs, ys, prec=SC_MIXED, stream=None):
+        """vs[i], ys[i]: [nvec_i, n_real_i] float64 CUDA tensors of plan i (or None for nvec_i = 0)."""
+        n = len(self.plans)
+        nv = (ctypes.c_int * n)()
+        pv = (ctypes.c_void_p * n)()
+        py = (ctypes.c_void_p * n)()
+        for i, (p, v, y) in enumerate(zip(self.plans, vs, ys)):
+            if v is None:
+                nv[i], pv[i], py[i] = 0, None, None
+                continue
+            k = 1 if v.dim() == 1 else v.shape[0]
+            if y.shape != v.shape:
+                raise ValueError("output shape differs from input shape")
+            nv[i] = k
+            pv[i] = _ptr(v, p.n_real * k).value
+            py[i] = _ptr(y, p.n_real * k).value
+        _check(_lib.sc_batch_jvp(self._h, nv, pv, py, int(prec), _stream(stream)))
+        return ys

@@ -81,6 +81,7 @@ struct sc_plan {
   int fft_nr = 0, fft_r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   long long n_real = 0;
   bool factored = false, have_base = false;
+  unsigned long long gen = 0;  // bumped by every change of factor, base or parameters
   double baseC = 0.0;
   long long baseJ = -1;
   // grid / radial data
@@ -538,7 +539,6 @@ void refined_solve(sc_plan* P, int nvec, const double* b, double* x, int passes,
 // Nonlinear step: P->xbuf <- B_C(x) (uncleaned solve output).
 void step_into_xbuf(sc_plan* P, const double* x, double C, hipStream_t s) {
   transforms<double>(P, sc::RING_NONLINEAR, 1, x, P->n_real, -1, s);
-  sc::DevGrid dg = P->dg();
   {
     Prof _p(P, SC_STAGE_PROJECT_RHS, s);
     launch_project<double, true>(P, 1, (const double*)(P->ws64.as<double>() + P->wl.As),
@@ -573,6 +573,7 @@ void set_base_impl(sc_plan* P, const double* x, double C, long long J, hipStream
   P->baseC = C;
   P->baseJ = J;
   P->have_base = true;
+  ++P->gen;
 }
 
 void jvp_impl(sc_plan* P, int nvec, const double* v, long long ldv, double* y, long long ldy, int prec, hipStream_t s) {
@@ -981,6 +982,7 @@ int sc_set_params(sc_plan* P, double Ra, double Ek, double dt) {
   if (!P) return fail(SC_ERR_ARG, "null plan");
   if (!(Ek > 0) || !(dt > 0) || !std::isfinite(Ra)) return fail(SC_ERR_ARG, "need Ek, dt > 0 and finite Ra");
   if (Ek != P->prm.Ek || dt != P->prm.dt) P->factored = false;
+  ++P->gen;
   P->prm.Ra = Ra;
   P->prm.Ek = Ek;
   P->prm.dt = dt;
@@ -1088,6 +1090,7 @@ int sc_factor(sc_plan* P, void* stream) {
     P->nsegs = (int)segv.size();
     P->factored = true;
     P->have_base = false;  // the cached M X depends on Ek
+    ++P->gen;
   });
 }
 
@@ -1204,6 +1207,82 @@ int sc_newton(sc_plan* P, double* x, double* C, const sc_newton_opts* o, sc_newt
     if (!P->factored) throw Fail{SC_ERR_STATE, "sc_factor has not run for the current (Ek, dt)"};
     const long long J = check_slot(P, o->J);
     newton_impl(P, x, C, *o, J, rep, (hipStream_t)stream);
+  });
+}
+
+
+// ------------------------------------------------------------------------------------------
+// Ragged batches: one stream branch per plan, forked from and joined into the caller's stream.
+struct sc_batch {
+  std::vector<sc_plan*> plans;
+  int device = 0;
+  std::vector<hipStream_t> br;             // one branch stream per plan
+  hipEvent_t ev_start = nullptr;
+  std::vector<hipEvent_t> ev_done;
+
+  ~sc_batch() {
+    for (auto e : ev_done) (void)hipEventDestroy(e);
+    if (ev_start) (void)hipEventDestroy(ev_start);
+    for (auto st : br) (void)hipStreamDestroy(st);
+  }
+};
+
+int sc_batch_create(sc_batch** out, sc_plan* const* plans, int nplans) {
+  if (!out || !plans || nplans < 1) return fail(SC_ERR_ARG, "need at least one plan");
+  *out = nullptr;
+  return guarded([&] {
+    std::unique_ptr<sc_batch> B(new sc_batch());
+    for (int i = 0; i < nplans; ++i) {
+      if (!plans[i]) throw Fail{SC_ERR_ARG, "null plan"};
+      for (int j = 0; j < i; ++j)
+        if (plans[j] == plans[i]) throw Fail{SC_ERR_ARG, "a plan is listed twice"};
+      if (plans[i]->prm.device != plans[0]->prm.device) throw Fail{SC_ERR_ARG, "plans on different devices"};
+      B->plans.push_back(plans[i]);
+    }
+    B->device = plans[0]->prm.device;
+    HIPCHK(hipSetDevice(B->device));
+    HIPCHK(hipEventCreateWithFlags(&B->ev_start, hipEventDisableTiming));
+    B->br.resize(nplans, nullptr);
+    B->ev_done.resize(nplans, nullptr);
+    for (int i = 0; i < nplans; ++i) {
+      HIPCHK(hipStreamCreateWithFlags(&B->br[i], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&B->ev_done[i], hipEventDisableTiming));
+    }
+    *out = B.release();
+  });
+}
+
+int sc_batch_destroy(sc_batch* b) {
+  if (!b) return SC_OK;
+  (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
+  delete b;
+  return SC_OK;
+}
+
+int sc_batch_jvp(sc_batch* b, const int* nvec, const double* const* v, double* const* y, sc_precision prec,
+                 void* stream) {
+  return guarded([&] {
+    if (!b || !nvec || !v || !y) throw Fail{SC_ERR_ARG, "null argument"};
+    if (prec != SC_FP64 && prec != SC_MIXED) throw Fail{SC_ERR_ARG, "unknown precision"};
+    HIPCHK(hipSetDevice(b->device));
+    const int n = (int)b->plans.size();
+    for (int i = 0; i < n; ++i) {
+      sc_plan* P = b->plans[i];
+      if (nvec[i] < 0 || nvec[i] > P->vcap) throw Fail{SC_ERR_ARG, "nvec exceeds nvec_max of a plan"};
+      if (nvec[i] > 0 && (!v[i] || !y[i])) throw Fail{SC_ERR_ARG, "null vector"};
+      if (!P->factored || !P->have_base) throw Fail{SC_ERR_STATE, "every plan needs sc_factor and sc_set_base"};
+      if (P->prof_on) throw Fail{SC_ERR_STATE, "turn the stage profiler off before a batch call"};
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipEventRecord(b->ev_start, s));
+    for (int i = 0; i < n; ++i) {
+      if (nvec[i] == 0) continue;
+      HIPCHK(hipStreamWaitEvent(b->br[i], b->ev_start, 0));
+      jvp_impl(b->plans[i], nvec[i], v[i], b->plans[i]->n_real, y[i], b->plans[i]->n_real, prec, b->br[i]);
+      HIPCHK(hipEventRecord(b->ev_done[i], b->br[i]));
+      HIPCHK(hipStreamWaitEvent(s, b->ev_done[i], 0));
+    }
   });
 }
 
