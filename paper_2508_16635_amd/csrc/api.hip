@@ -94,9 +94,12 @@ struct sc_plan {
   TabLayout tl;
   WsLayout wl;
   DevBuf tab64, tab32, ws64, ws32;
-  DevBuf probs_syn, probs_ana;
+  DevBuf probs_syn, probs_ana, d_gsoff;
   int nprob_syn = 0, nprob_ana = 0;
-  std::vector<sc::GemmProb> h_syn, h_ana;
+  std::vector<sc::SynProb> h_syn;
+  std::vector<sc::GemmProb> h_ana;
+  std::vector<long long> h_gsoff;         // per m: operand-order offsets of Gs, Gv
+  int rtcS = 0, rtcV = 0;
   // canonical FP64 vectors
   DevBuf bbuf, xbuf, rbuf, dbuf, norms;
   // base state
@@ -157,6 +160,9 @@ struct sc_plan {
     g.D4 = d_D4.as<double>();
     g.ET = d_ET.as<double>();
     g.EF = d_EF.as<double>();
+    g.gsoff = d_gsoff.as<long long>();
+    g.rtcS = rtcS;
+    g.rtcV = rtcV;
     g.PF = d_PF.as<double>();
     g.D2F = d_D2F.as<double>();
     g.DF = d_DF.as<double>();
@@ -234,11 +240,16 @@ void build_tables(sc_plan* P) {
   t.synV.resize(K1);
   t.anaS.resize(K1);
   t.anaV.resize(K1);
+  // synthesis tables on the northern nodes, in MFMA B-operand order: for the even l - m then
+  // the odd ones, [column tile][k-step][lane], lane l of (c, s) holding
+  // B[degree 4s + lane/16 of the part][node 16c' + lane%16], zero outside; vector tables have
+  // the dP/dtheta column tiles first, then the m P/sin ones (c' = c mod cth)
+  const long long cth = (nth / 2 + 15) / 16;
   long long off = 0;
   for (int k = 0; k < K1; ++k) {
-    long long nl = g.nl[k];
-    t.synS[k] = off; off += nth * nl;
-    t.synV[k] = off; off += 2LL * nth * nl;
+    const long long nl = g.nl[k], kse = ((nl + 1) / 2 + 3) / 4, kso = (nl / 2 + 3) / 4;
+    t.synS[k] = off; off += cth * (kse + kso) * 64;
+    t.synV[k] = off; off += 2 * cth * (kse + kso) * 64;
     t.anaS[k] = off; off += nth * nl;
     t.anaV[k] = off; off += 2LL * nth * nl;
   }
@@ -254,9 +265,18 @@ void build_tables(sc_plan* P) {
       for (int j = 0; j < nth; ++j) {
         double Pb = g.Pb[k][(size_t)il * nth + j], dP = g.dPb[k][(size_t)il * nth + j],
                mP = g.mPs[k][(size_t)il * nth + j];
-        h[t.synS[k] + (long long)j * nl + il] = Pb;
-        h[t.synV[k] + (long long)j * nl + il] = dP;
-        h[t.synV[k] + (long long)(nth + j) * nl + il] = mP;
+        if (j < nth / 2) {
+          const long long kse = ((nl + 1) / 2 + 3) / 4, kso = (nl / 2 + 3) / 4;
+          const bool odd = il & 1;
+          const long long kp = odd ? kso : kse, ie = il >> 1;
+          const long long kpos = (ie >> 2) * 64 + (ie & 3) * 16 + (j & 15);
+          // scalar: cth tiles; vector: 2 cth tiles (dP first)
+          const long long sS = t.synS[k] + (odd ? cth * kse * 64 : 0);
+          const long long sV = t.synV[k] + (odd ? 2 * cth * kse * 64 : 0);
+          h[sS + (long long)(j >> 4) * kp * 64 + kpos] = Pb;
+          h[sV + (long long)(j >> 4) * kp * 64 + kpos] = dP;
+          h[sV + (long long)(cth + (j >> 4)) * kp * 64 + kpos] = mP;
+        }
         double w = g.wt[j];
         h[t.anaS[k] + (long long)il * nth + j] = w * Pb / (2.0 * dm);
         double wv = (l > 0) ? w / (2.0 * dm * lam) : 0.0;
@@ -280,8 +300,20 @@ void build_workspaces(sc_plan* P) {
   WsLayout& w = P->wl;
   const long long V = P->vcap, Np = g.Np, S = g.S, K1 = g.K + 1, nth = g.nth;
   long long off = 0;
-  w.Gs = off; off += 6 * Np * V * S;
-  w.Gv = off; off += 10 * Np * V * S;
+  // synthesis inputs in MFMA A-operand order per m: [row tile][k-step][lane]
+  P->rtcS = (int)((6 * Np * V + 15) / 16);
+  P->rtcV = (int)((10 * Np * V + 15) / 16);
+  P->h_gsoff.assign(2 * K1, 0);
+  long long gsz = 0, gvz = 0;
+  for (int k = 0; k < K1; ++k) {
+    const long long ks = ((g.nl[k] + 1) / 2 + 3) / 4 + (g.nl[k] / 2 + 3) / 4;
+    P->h_gsoff[2 * k] = gsz;
+    P->h_gsoff[2 * k + 1] = gvz;
+    gsz += (long long)P->rtcS * ks * 64;
+    gvz += (long long)P->rtcV * ks * 64;
+  }
+  w.Gs = off; off += gsz;   // h_gsoff: relative to Gs and Gv
+  w.Gv = off; off += gvz;
   w.Cs = off; off += K1 * 6 * Np * V * nth;
   w.Cv = off; off += K1 * 10 * Np * V * 2 * nth;
   w.Fs = off; off += K1 * 4 * Np * V * nth;
@@ -291,6 +323,10 @@ void build_workspaces(sc_plan* P) {
   w.total = off;
   P->ws64.alloc(off * sizeof(double));
   P->ws32.alloc(off * sizeof(float));
+  // the operand-order padding (k beyond n_l) is never written and must read as zero
+  HIPCHK(hipMemset(P->ws64.p, 0, off * sizeof(double)));
+  HIPCHK(hipMemset(P->ws32.p, 0, off * sizeof(float)));
+  upload(P->d_gsoff, P->h_gsoff);
   // contraction problems (offsets are in elements, so they serve both precisions)
   P->h_syn.clear();
   P->h_ana.clear();
@@ -298,10 +334,11 @@ void build_workspaces(sc_plan* P) {
   for (int k = 0; k < K1; ++k) {
     int nl = g.nl[k];
     long long lb = g.lmbase[k];
-    sc::GemmProb a{w.Gs + 6 * Np * V * lb, t.synS[k], w.Cs + k * 6 * Np * V * nth, (int)(6 * Np), (int)nth, nl, nl, nl, (int)nth};
-    sc::GemmProb b{w.Gv + 10 * Np * V * lb, t.synV[k], w.Cv + k * 10 * Np * V * 2 * nth, (int)(10 * Np), (int)(2 * nth), nl, nl, nl, (int)(2 * nth)};
-    P->h_syn.push_back(a);
-    P->h_syn.push_back(b);
+    const int kse = ((nl + 1) / 2 + 3) / 4, kso = (nl / 2 + 3) / 4, cth = (int)((nth / 2 + 15) / 16);
+    P->h_syn.push_back(sc::SynProb{w.Gs + P->h_gsoff[2 * k], t.synS[k], w.Cs + k * 6 * Np * V * nth, (int)(6 * Np), kse,
+                                   kso, cth, 1, (int)nth});
+    P->h_syn.push_back(sc::SynProb{w.Gv + P->h_gsoff[2 * k + 1], t.synV[k], w.Cv + k * 10 * Np * V * 2 * nth, (int)(10 * Np),
+                                   kse, kso, cth, 2, (int)nth});
     sc::GemmProb c{w.Fs + k * 4 * Np * V * nth, t.anaS[k], w.As + 4 * Np * V * lb, (int)(4 * Np), nl, (int)nth, (int)nth, (int)nth, nl};
     sc::GemmProb d{w.Fv + k * 4 * Np * V * 2 * nth, t.anaV[k], w.Av + 4 * Np * V * lb, (int)(4 * Np), nl, (int)(2 * nth), (int)(2 * nth), (int)(2 * nth), nl};
     P->h_ana.push_back(c);
@@ -373,10 +410,11 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
     }
   }
   HIPCHK(hipGetLastError());
-  long long nt = gemm_tiles<T>(P->h_syn, nvec);
+  long long nt = 0;
+  for (const auto& pr : P->h_syn) nt += sc::syn_tiles(pr, nvec);
   {
     Prof _p(P, SC_STAGE_LEGENDRE_SYNTH, s);
-    hipLaunchKernelGGL(sc::k_gemm_batched<T>, dim3((unsigned)nt), dim3(256), 0, s, P->probs_syn.as<sc::GemmProb>(),
+    hipLaunchKernelGGL(sc::k_synth<T>, dim3((unsigned)nt), dim3(256), 0, s, P->probs_syn.as<sc::SynProb>(),
                        P->nprob_syn, nvec, (const T*)ws, tab, ws);
   }
   HIPCHK(hipGetLastError());
@@ -808,6 +846,7 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     }
     const sc::HostGrid& g = P->hg;
     if (g.Np > 128) throw Fail{SC_ERR_ARG, "N_p > 128 unsupported"};
+    if (g.nth % 2) throw Fail{SC_ERR_ARG, "ntheta must be even (mirror pairs of Gauss-Legendre nodes)"};
     P->n_real = 6LL * g.N * g.S;
     upload(P->d_lmk, g.lm_k);
     upload(P->d_lml, g.lm_l);

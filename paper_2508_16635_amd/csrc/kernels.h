@@ -54,6 +54,8 @@ struct DevGrid {
   int nqtiles;
   const double* DF;   // D (N x N), operand order
   const double* D4F;  // D^4 (N x N), operand order
+  const long long* gsoff;  // per m: offsets of the synthesis inputs in operand order, from Gs and from Gv
+  int rtcS, rtcV;     // row tiles of the scalar / vector synthesis inputs at vector capacity
   const double* EF;   // E, ED, ED2 (N_p x N each) in 16x16x4 MFMA operand order, k padded to 16 ceil(N/16)
   const double* PF;   // P diag(1/r), P diag(1/r^2), P diag(1/r^2) Dp diag(r), P (N x N_p each), operand order
   const double* D2F;  // D^2 (N x N), operand order
@@ -179,8 +181,10 @@ __global__ void __launch_bounds__(256) k_radial_prep(DevGrid g, const double* __
   __syncthreads();
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const long long mstride = (long long)RTP * KS * 64;
-  const long long offS = 6LL * Np * g.vcap * g.lmbase[k];
-  const long long offV = 10LL * Np * g.vcap * g.lmbase[k];
+  // outputs in operand order: row r of the sums, depth column kc of degree il (even l - m at
+  // il/2, odd ones at 4 KSe + il/2): ((r/16) KS + kc/4) 64 + (kc%4) 16 + r%16
+  const long long offS = g.gsoff[2 * k], offV = g.gsoff[2 * k + 1];
+  const int KSe = ((nl + 1) / 2 + 3) >> 2, KSo = (nl / 2 + 3) >> 2, KSl = KSe + KSo;
   const int t = l & 15;
   const int il = il0 + t, lw = m + il;
   const double lam = (double)lw * (lw + 1);
@@ -208,26 +212,168 @@ __global__ void __launch_bounds__(256) k_radial_prep(DevGrid g, const double* __
       const int rp = 16 * rt + Mfma<double>::out_row(l, q);
       if (rp >= Np) continue;
       const double ri1 = 1.0 / g.rp[rp], ri2 = ri1 * ri1;
-      T* gs = Gs + offS + (((long long)vec * Np + rp) * 6 + c) * nl + il;
-      T* gv = Gv + offV + (((long long)vec * Np + rp) * 10 + c) * nl + il;
+      const long long rs = ((long long)vec * Np + rp) * 6 + c, rv = ((long long)vec * Np + rp) * 10 + c;
+      const int kc = (il & 1) ? 4 * KSe + (il >> 1) : (il >> 1);
+      const long long kofs = (kc >> 2) * 64 + (kc & 3) * 16;
+      auto gs = [&](int slot) -> T& {
+        const long long r = rs + slot;
+        return Gs[offS + ((r >> 4) * KSl) * 64 + kofs + (r & 15)];
+      };
+      auto gv = [&](int slot) -> T& {
+        const long long r = rv + slot;
+        return Gv[offV + ((r >> 4) * KSl) * 64 + kofs + (r & 15)];
+      };
       if (f == 0) {          // e
-        gs[2 * nl] = (T)(lam * ri2 * y0[q]);                          // wr
-        gv[2 * nl] = (T)(y0[q] * ri1);                                // Tu
-        gv[4 * nl] = (T)(y1[q] * ri1);                                // Sw
+        gs(2) = (T)(lam * ri2 * y0[q]);                          // wr
+        gv(2) = (T)(y0[q] * ri1);                                // Tu
+        gv(4) = (T)(y1[q] * ri1);                                // Sw
       } else if (f == 1) {   // f
-        gs[0 * nl] = (T)(lam * ri2 * y0[q]);                          // ur
-        gv[0 * nl] = (T)(y1[q] * ri1);                                // Su
-        gv[6 * nl] = (T)(-y2[q] * ri1 + lam * ri2 * ri1 * y0[q]);     // Tw
+        gs(0) = (T)(lam * ri2 * y0[q]);                          // ur
+        gv(0) = (T)(y1[q] * ri1);                                // Su
+        gv(6) = (T)(-y2[q] * ri1 + lam * ri2 * ri1 * y0[q]);     // Tw
       } else {               // T
-        gs[4 * nl] = (T)(y1[q]);                                      // dT
-        gv[8 * nl] = (T)(y0[q] * ri1);                                // ST
+        gs(4) = (T)(y1[q]);                                      // dT
+        gv(8) = (T)(y0[q] * ri1);                                // ST
       }
     }
   }
 }
 
 // ------------------------------------------------------------------------------------------
-// K2/K6: batched contractions C[i][j] = sum_k A[i][k] B[j][k] on the matrix cores.
+// K2: Legendre synthesis per m with the equatorial symmetry.  Nodes nth-1-j mirror j; P and
+// m P/sin have the parity (-1)^(l-m) under the mirror, dP/dtheta the opposite one.  For the
+// northern nodes the sums over even l - m (S_e) and over odd l - m (S_o) are two products
+// C_e = A_e B_e, C_o = A_o B_o with half the columns and half the depth; the outputs are then
+// S_e + S_o at the node and S_e - S_o (P, m P/sin) or S_o - S_e (dP/dtheta) at its mirror,
+// written in the natural layout C[row][theta] (vector rows: [dP part | m P/sin part]).
+// A (spectral profiles, rows (vec, r_p, q), depth [even l | odd l]) and B (tables, northern
+// columns) are stored in MFMA operand order, so every wavefront streams its operands from L2
+// into registers with unit-stride loads, one k-step ahead, with no LDS.  A workgroup owns
+// kSynTM row tiles and 4 kSynTN column tiles, wavefront w the column tiles w, w+4, ...
+constexpr int kSynTM = 4;
+constexpr int kSynTN = 2;
+
+struct SynProb {
+  long long a_off, b_off, c_off;  // A, C in the workspace; B in the tables (even part, then odd)
+  int rper;                        // rows per vector (6 N_p or 10 N_p)
+  int kse, kso;                    // k-steps of the even and odd parts
+  int cth;                         // column tiles of one part (ceil(nth/2 / 16))
+  int parts;                       // 1 (scalar: P) or 2 (vector: dP, m P/sin)
+  int nth;                         // theta nodes; C rows have parts * nth columns
+};
+
+__host__ __device__ inline int syn_tiles(const SynProb& p, int nvec) {
+  const int rt = (p.rper * nvec + 15) / 16;
+  return ((rt + kSynTM - 1) / kSynTM) * ((p.parts * p.cth + 4 * kSynTN - 1) / (4 * kSynTN));
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_synth(const SynProb* __restrict__ probs, int nprob, int nvec,
+                                               const T* __restrict__ ws_in, const T* __restrict__ tab,
+                                               T* __restrict__ ws_out) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  int tile = blockIdx.x, p = 0;
+  for (; p < nprob; ++p) {
+    const int nt = syn_tiles(probs[p], nvec);
+    if (tile < nt) break;
+    tile -= nt;
+  }
+  if (p >= nprob) return;
+  const SynProb pr = probs[p];
+  const int ct = pr.parts * pr.cth, ks = pr.kse + pr.kso;
+  const int ncg = (ct + 4 * kSynTN - 1) / (4 * kSynTN);
+  const int rg = tile / ncg, cg = tile - rg * ncg;
+  const int rows = pr.rper * nvec, rtu = (rows + 15) / 16;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const T* A[kSynTM];
+  const T* Be[kSynTN];
+  const T* Bo[kSynTN];
+  int rt[kSynTM], ctl[kSynTN];
+#pragma unroll
+  for (int i = 0; i < kSynTM; ++i) {
+    rt[i] = rg * kSynTM + i;
+    A[i] = ws_in + pr.a_off + (long long)min(rt[i], rtu - 1) * ks * 64 + l;
+  }
+  int ncol = 0;
+  const long long bodd = (long long)ct * pr.kse * 64;  // odd tables follow the even ones
+#pragma unroll
+  for (int j = 0; j < kSynTN; ++j) {
+    ctl[j] = cg * 4 * kSynTN + w + 4 * j;
+    if (ctl[j] < ct) ncol = j + 1;
+    const int cc = min(ctl[j], ct - 1);
+    Be[j] = tab + pr.b_off + (long long)cc * pr.kse * 64 + l;
+    Bo[j] = tab + pr.b_off + bodd + (long long)cc * pr.kso * 64 + l;
+  }
+  acc_t ce[kSynTM][kSynTN], co[kSynTM][kSynTN];
+#pragma unroll
+  for (int i = 0; i < kSynTM; ++i)
+#pragma unroll
+    for (int j = 0; j < kSynTN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ce[i][j][q] = (T)0;
+        co[i][j][q] = (T)0;
+      }
+  // one pipelined pass over a part: A k-steps [k0, k0 + n), tables B
+  auto pass = [&](int k0, int n, const T* const* B, acc_t (&acc)[kSynTM][kSynTN]) {
+    if (n <= 0) return;
+    T a0[kSynTM], b0[kSynTN], a1[kSynTM], b1[kSynTN];
+    auto load = [&](int st, T* a, T* b) {
+      st = st < n ? st : n - 1;
+#pragma unroll
+      for (int i = 0; i < kSynTM; ++i) a[i] = A[i][(k0 + st) * 64];
+#pragma unroll
+      for (int j = 0; j < kSynTN; ++j) b[j] = B[j][st * 64];
+    };
+    auto run = [&](const T* a, const T* b) {
+#pragma unroll
+      for (int j = 0; j < kSynTN; ++j)
+        if (j < ncol) {
+#pragma unroll
+          for (int i = 0; i < kSynTM; ++i) acc[i][j] = Mfma<T>::step(a[i], b[j], acc[i][j]);
+        }
+    };
+    load(0, a0, b0);
+    for (int st = 0; st < n; st += 2) {
+      load(st + 1, a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      run(a0, b0);
+      if (st + 1 < n) {
+        load(st + 2, a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        run(a1, b1);
+      }
+    }
+  };
+  pass(0, pr.kse, Be, ce);
+  pass(pr.kse, pr.kso, Bo, co);
+  T* C = ws_out + pr.c_off;
+  const int nh = pr.nth >> 1, ncolC = pr.parts * pr.nth;
+#pragma unroll
+  for (int j = 0; j < kSynTN; ++j) {
+    if (j >= ncol) continue;
+    const int part = ctl[j] / pr.cth;
+    const int tn = (ctl[j] - part * pr.cth) * 16 + (l & 15);  // northern node
+    if (tn >= nh) continue;
+    const int cn = part * pr.nth + tn, cs = part * pr.nth + pr.nth - 1 - tn;
+    const bool dp = (pr.parts == 2 && part == 0);   // mirror value: e - o, or o - e for dP/dtheta
+    const T sge = dp ? (T)-1 : (T)1, sgo = dp ? (T)1 : (T)-1;
+#pragma unroll
+    for (int i = 0; i < kSynTM; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = rt[i] * 16 + Mfma<T>::out_row(l, q);
+        if (row >= rows) continue;
+        const T e = ce[i][j][q], o = co[i][j][q];
+        T* cr = C + (long long)row * ncolC;
+        cr[cn] = e + o;
+        cr[cs] = sge * e + sgo * o;
+      }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// K6: batched contractions C[i][j] = sum_k A[i][k] B[j][k] on the matrix cores.
 // Output tile BM x 64 per workgroup (BM = 128 in FP32, 64 in FP64); the four wavefronts
 // form a 2 x 2 grid, each owning (BM/2) x 32 as (BM/32) x 2 MFMA 16x16 tiles.  k is staged
 // through LDS 32 at a time, and the next k-slice is fetched into registers while the current
