@@ -5,11 +5,12 @@ Workload (the metric's shell): L = M = 128, m0 = 10, N = 48, Ek = 1e-5, Pr = 1,
 Ra = 1.2 * 6.5 Ek^(-1/3) = 362.0, dt = 200; a seeded synthetic base state (kinetic-energy
 density ~25, coefficients decaying as l^-3, conductive temperature profile added) and 200
 seeded unit Krylov-like vectors (decay l^-1).  One step = one sc_jvp call on a batch of
-nvec vectors (the whole hot path: transforms, products, projections, implicit solve and
-refinement).  Inputs are resident in HBM before the timed region.
+nvec vectors (the whole hot path: transforms, products, projections, implicit solve and,
+where the precision asks for it, refinement).  Inputs are resident in HBM before the timed region.
 
-Prints one JSON line.  `value` is mixed-precision jvp/s; the FP64 path is timed the same
-way and reported beside it.
+Prints one JSON line.  `value` is mixed-precision jvp/s (FP32 transforms, one FP64 solve); the
+FP64 path, and the mixed path with an FP32 solve plus FP64 refinement, are timed the same way
+and reported beside it.
 """
 from __future__ import annotations
 
@@ -103,8 +104,9 @@ def run(args):
     dev = torch.device("cuda:0")
     W = WORKLOAD
     nvec = args.nvec
+    mixed_solve = sc.SC_MIXED_SOLVE_FP32 if args.mixed_solve == "fp32" else sc.SC_MIXED_SOLVE_FP64
     plan = sc.Plan(W["L"], W["M"], W["m0"], W["N"], Ek=W["Ek"], Ra=W["Ra"], Pr=W["Pr"], dt=W["dt"],
-                   nvec_max=nvec, refine_mixed=args.refine_mixed)
+                   nvec_max=nvec, refine_mixed=args.refine_mixed, mixed_solve=mixed_solve)
     lay_d = plan.layout
     lay = si.Layout(W["L"], W["M"], W["m0"], W["N"])
     assert lay.n_real == plan.n_real
@@ -131,21 +133,38 @@ def run(args):
         b = i % nb
         return V[b * nvec:(b + 1) * nvec]
 
-    results = {}
-    for name, prec in (("mixed", sc.SC_MIXED), ("fp64", sc.SC_FP64)):
+    def timed(pl, prec):
         for i in range(args.warmup):
-            plan.jvp(batch(i), Y, prec)
+            pl.jvp(batch(i), Y, prec)
         torch.cuda.synchronize()
-        plan.profile(True)
+        pl.profile(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(args.steps):
-            plan.jvp(batch(i), Y, prec)
+            pl.jvp(batch(i), Y, prec)
         torch.cuda.synchronize()
         dt_ = time.perf_counter() - t0
-        prof = plan.profile_read()
-        plan.profile(False)
-        results[name] = dict(seconds=dt_, jvps=args.steps * nvec, prof=prof)
+        prof = pl.profile_read()
+        pl.profile(False)
+        return dict(seconds=dt_, jvps=args.steps * nvec, prof=prof)
+
+    results = {"mixed": timed(plan, sc.SC_MIXED), "fp64": timed(plan, sc.SC_FP64)}
+    # the other implicit solve of the mixed path, on a plan of its own (same shell and base)
+    other = None
+    if not args.no_alt_solve:
+        alt = "fp64" if args.mixed_solve == "fp32" else "fp32"
+        plan2 = sc.Plan(W["L"], W["M"], W["m0"], W["N"], Ek=W["Ek"], Ra=W["Ra"], Pr=W["Pr"], dt=W["dt"], nvec_max=nvec,
+                        refine_mixed=args.refine_mixed,
+                        mixed_solve=sc.SC_MIXED_SOLVE_FP32 if alt == "fp32" else sc.SC_MIXED_SOLVE_FP64)
+        plan2.factor()
+        plan2.set_base(Xd, C, J)
+        r2 = timed(plan2, sc.SC_MIXED)
+        Y2 = torch.empty_like(Y)
+        plan2.jvp(batch(0), Y2, sc.SC_MIXED)
+        plan2.close()
+        other = {"mixed_solve": alt, "refine_mixed": args.refine_mixed if alt == "fp32" else 0,
+                 "jvp_per_s": r2["jvps"] / r2["seconds"],
+                 "stages": {k: v[0] / max(args.steps, 1) for k, v in r2["prof"].items() if v[1]}}
 
     # mixed vs FP64 on the same batch (GPU vs GPU, a consistency figure)
     Y64 = torch.empty_like(Y)
@@ -153,6 +172,8 @@ def run(args):
     plan.jvp(batch(0), Y64, sc.SC_FP64)
     torch.cuda.synchronize()
     mixed_vs_fp64 = float(((Y - Y64).norm(dim=1) / Y64.norm(dim=1)).max())
+    if other is not None:
+        other["mixed_vs_fp64_max_rel"] = float(((Y2 - Y64).norm(dim=1) / Y64.norm(dim=1)).max())
 
     mixed = results["mixed"]
     fp64 = results["fp64"]
@@ -160,8 +181,8 @@ def run(args):
     # roofline of the dominant stage of the mixed path
     N = W["N"]
     nblocks = sum(W["L"] - max(k * W["m0"], 1) + 1 for k in range(lay_d["K"] + 1)) * 2
-    fbytes32 = 3 * nblocks * N * N * 8
-    work = stage_work(lay_d, nvec, 4, fbytes32, nblocks, refine=args.refine_mixed)
+    fbytes = 3 * nblocks * N * N * (8 if args.mixed_solve == "fp32" else 16)
+    work = stage_work(lay_d, nvec, 4, fbytes, nblocks, refine=args.refine_mixed if args.mixed_solve == "fp32" else 0)
     prof = mixed["prof"]
     # the dominant single-kernel stage of the mixed path (the chain solve is seven kernels and
     # the temperature solve runs beside it on a second stream)
@@ -201,10 +222,12 @@ def run(args):
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "rotating-shell jvp L=M=128 m0=10 N=48 Ek=1e-5 Ra=362 dt=200",
-                   "nvec": nvec, "refine_mixed": args.refine_mixed, "N_p": lay_d["Np"], "N_theta": lay_d["ntheta"], "N_phi": lay_d["nphi"],
+                   "nvec": nvec, "mixed_solve": args.mixed_solve,
+                   "refine_mixed": args.refine_mixed if args.mixed_solve == "fp32" else 0, "N_p": lay_d["Np"], "N_theta": lay_d["ntheta"], "N_phi": lay_d["nphi"],
                    "n_real": plan.n_real},
         "fp64_jvp_per_s": fp64["jvps"] / fp64["seconds"],
         "mixed_vs_fp64_max_rel": mixed_vs_fp64,
+        "mixed_other_solve": other,
         "factor_s": t_factor,
         "set_base_s": t_base,
         "roofline": roof,
@@ -292,8 +315,11 @@ def main():
     ap.add_argument("--nvectors", type=int, default=200)
     ap.add_argument("--cpu-sample", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed-solve", choices=("fp64", "fp32"), default="fp64",
+                    help="implicit solve of the mixed path: one FP64 solve, or an FP32 solve plus refinement")
     ap.add_argument("--refine-mixed", type=int, default=1,
-                    help="FP64 refinement passes (FP64 residual + FP64 correction) after the FP32 solve")
+                    help="with --mixed-solve fp32: FP64 refinement passes (FP64 residual + FP64 correction)")
+    ap.add_argument("--no-alt-solve", action="store_true", help="do not time the other mixed-path solve")
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--restart", type=int, default=100)
     ap.add_argument("--max-matvec", type=int, default=300)

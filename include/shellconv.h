@@ -60,9 +60,19 @@ typedef struct {
   int device;             /* HIP device ordinal                                              */
   int nvec_max;           /* largest batch passed to sc_jvp (0 = 16); sizes the workspaces   */
   int refine_fp64;        /* FP64 refinement passes after the FP64 solve (< 0: default 1)    */
-  int refine_mixed;       /* FP64 refinement passes after the FP32 solve (< 0: default 1);
-                             a pass is an FP64 residual and an FP64 correction solve          */
+  int refine_mixed;       /* SC_MIXED_SOLVE_FP32: FP64 refinement passes after the FP32 solve
+                             (< 0: default 1); a pass is an FP64 residual and an FP64 correction
+                             solve                                                             */
+  int mixed_solve;        /* implicit solve of SC_MIXED: SC_MIXED_SOLVE_FP64 (0 = default) or
+                             SC_MIXED_SOLVE_FP32                                               */
 } sc_params;
+
+/* Implicit solve of the mixed path.  SC_MIXED_SOLVE_FP64: one solve with the FP64 factors (its
+ * error, ~1e-11 relative, is far below that of the FP32 transforms).  SC_MIXED_SOLVE_FP32: a
+ * solve with the FP32 factors, then refine_mixed FP64 refinement passes.  With factors resident
+ * the solve streams them once per pass, so one FP64 pass costs less than an FP32 pass plus a
+ * refinement pass. */
+enum { SC_MIXED_SOLVE_FP64 = 1, SC_MIXED_SOLVE_FP32 = 2 };
 
 typedef struct {
   long long n_real;       /* length of one packed state                                      */
@@ -95,9 +105,9 @@ int sc_newton_residual(sc_plan* plan, const double* x, double C, double* r, doub
 int sc_set_base(sc_plan* plan, const double* x, double C, long long J, void* stream);
 /* Jacobian action y_i = (B_X - I)(u_i, c_i) on nvec vectors (Sec. 3.3 eq:precond, Sec. 3.4):
  * c_i = v_i[J], u_i = v_i with slot J zeroed; homogeneous boundary rows.
- * SC_FP64: every stage in FP64.  SC_MIXED: transforms and the first block back-substitution
- * in FP32 with FP32 accumulation; FP64 radial operators, right-hand side, residual and the
- * refinement passes (refine_mixed). */
+ * SC_FP64: every stage in FP64, refine_fp64 refinement passes.  SC_MIXED: Legendre transforms,
+ * azimuthal transforms and products in FP32 with FP32 accumulation; FP64 radial operators and
+ * right-hand side; the implicit solve as chosen by mixed_solve. */
 int sc_jvp(sc_plan* plan, int nvec, const double* v, long long ldv, double* y, long long ldy,
            sc_precision prec, void* stream);
 /* Newton-GMRES on R_C(X) = B_C(X) - X (+ forcing), Sec. 3.3 and 3.4: each Newton step solves

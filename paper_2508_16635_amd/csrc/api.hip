@@ -78,6 +78,7 @@ struct sc_plan {
   sc::HostGrid hg;
   int vcap = 16, wcap = 16;
   int refine64 = 1, refine32 = 1;
+  bool mixed_fp32_solve = false;  // SC_MIXED_SOLVE_FP32
   int fft_nr = 0, fft_r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   long long n_real = 0;
   bool factored = false, have_base = false;
@@ -634,7 +635,10 @@ void jvp_impl(sc_plan* P, int nvec, const double* v, long long ldv, double* y, l
                                    (const float*)(P->ws32.as<float>() + P->wl.Av), v, ldv, J, P->baseC,
                                    P->MX.as<const double>(), P->bbuf.as<double>(), s);
     }
-    refined_solve<float>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine32, s);
+    if (P->mixed_fp32_solve)
+      refined_solve<float>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine32, s);
+    else
+      implicit_solve<double, false>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), s);
   }
   long long n = (long long)nvec * P->n_real;
   {
@@ -832,6 +836,9 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     P->wcap = (P->vcap + kVG - 1) / kVG * kVG;
     P->refine64 = p.refine_fp64 >= 0 ? p.refine_fp64 : 1;
     P->refine32 = p.refine_mixed >= 0 ? p.refine_mixed : 1;
+    if (p.mixed_solve != 0 && p.mixed_solve != SC_MIXED_SOLVE_FP64 && p.mixed_solve != SC_MIXED_SOLVE_FP32)
+      throw Fail{SC_ERR_ARG, "mixed_solve must be 0, SC_MIXED_SOLVE_FP64 or SC_MIXED_SOLVE_FP32"};
+    P->mixed_fp32_solve = (p.mixed_solve == SC_MIXED_SOLVE_FP32);
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
     if (p.device < 0 || p.device >= ndev) throw Fail{SC_ERR_ARG, "bad device ordinal"};

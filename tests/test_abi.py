@@ -57,3 +57,12 @@ def _reload_missing(tmp_path):
         sc.load_library(str(tmp_path / "absent.so"))
     finally:
         sc._lib = saved
+
+
+def test_plan_rejects_bad_mixed_solve():
+    """Argument checks run before any device call, so this runs without a GPU."""
+    if not os.path.exists(sc.LIB_PATH):
+        pytest.skip("libshellconv.so not built")
+    with pytest.raises(sc.ShellConvError) as ei:
+        sc.Plan(8, 8, 2, 10, Ek=1e-3, Ra=50.0, mixed_solve=7)
+    assert ei.value.code == 1

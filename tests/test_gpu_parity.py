@@ -30,9 +30,9 @@ def lib():
     return sc
 
 
-def _setup(sc, cfg, nvec=4):
+def _setup(sc, cfg, nvec=4, mixed_solve=0):
     L, M, m0, N, Ek, Ra, dt = cfg
-    plan = sc.Plan(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=dt, nvec_max=nvec)
+    plan = sc.Plan(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=dt, nvec_max=nvec, mixed_solve=mixed_solve)
     plan.factor()
     ora = Problem(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=dt)
     lay = si.Layout(L, M, m0, N)
@@ -73,9 +73,10 @@ def test_conductive_fixed_point(lib):
 
 
 @pytest.mark.parametrize("cfg", SMALL)
-@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 1e-6)])
-def test_jvp(lib, cfg, prec, tol):
-    plan, ora, lay = _setup(lib, cfg)
+@pytest.mark.parametrize("prec,solve,tol", [(0, 0, 1e-11), (1, 1, 1e-6), (1, 2, 1e-6)],
+                         ids=["fp64", "mixed-fp64solve", "mixed-fp32solve-refined"])
+def test_jvp(lib, cfg, prec, solve, tol):
+    plan, ora, lay = _setup(lib, cfg, mixed_solve=solve)
     X = si.random_state(lay, 101, amp=(1e-2, 1e-2, 1e-2), p=2) + ora.conductive_state()
     J = si.default_phase_slot(lay, X)
     C = 0.3
@@ -87,7 +88,7 @@ def test_jvp(lib, cfg, prec, tol):
     plan.jvp(vd, yd, prec)
     Y = _host(yd)
     errs = [_rel(Y[i], ora.jvp(V[i])) for i in range(len(V))]
-    print(f"cfg={cfg} prec={prec} jvp rel errs", ["%.2e" % e for e in errs], flush=True)
+    print(f"cfg={cfg} prec={prec} solve={solve} jvp rel errs", ["%.2e" % e for e in errs], flush=True)
     assert max(errs) < tol
 
 

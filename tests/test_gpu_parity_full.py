@@ -37,7 +37,9 @@ def _base(lay, ora, seed, amp):
 @pytest.mark.parametrize("shell", [SHELL_C2, SHELL_C3], ids=["L64N32", "L128N48"])
 def test_full_shell_jvp_batched(sc, shell):
     """nvec = 17 (a full group of 16 plus a ragged tail of 1); vectors 0, 15 and 16 are
-    compared with the oracle one by one; every vector's mixed result against its FP64 one."""
+    compared with the oracle one by one; every vector's mixed result against its FP64 one.
+    Both implicit solves of the mixed path: one FP64 solve (default) and the FP32 solve with
+    one FP64 refinement pass (a plan of its own)."""
     L, M, m0, N, Ek, Ra, seed, amp = shell
     nvec = 17
     plan = sc.Plan(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=200.0, nvec_max=nvec)
@@ -55,15 +57,24 @@ def test_full_shell_jvp_batched(sc, shell):
     Y32 = torch.empty_like(Vd)
     plan.jvp(Vd, Y64, sc.SC_FP64)
     plan.jvp(Vd, Y32, sc.SC_MIXED)
+    plan2 = sc.Plan(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=200.0, nvec_max=nvec, mixed_solve=sc.SC_MIXED_SOLVE_FP32,
+                    refine_mixed=1)
+    plan2.factor()
+    plan2.set_base(_dev(X), C, J)
+    Y32r = torch.empty_like(Vd)
+    plan2.jvp(Vd, Y32r, sc.SC_MIXED)
     torch.cuda.synchronize()
-    y64, y32 = Y64.cpu().numpy(), Y32.cpu().numpy()
+    y64, y32, y32r = Y64.cpu().numpy(), Y32.cpu().numpy(), Y32r.cpu().numpy()
+    plan2.close()
     for i in (0, 15, 16):
         ref = ora.jvp(V[i])
-        e64, e32 = _rel(y64[i], ref), _rel(y32[i], ref)
-        print(f"L={L} N={N} vec {i}: fp64 rel err {e64:.2e}  mixed rel err {e32:.2e}", flush=True)
+        e64, e32, e32r = _rel(y64[i], ref), _rel(y32[i], ref), _rel(y32r[i], ref)
+        print(f"L={L} N={N} vec {i}: fp64 rel err {e64:.2e}  mixed rel err {e32:.2e}  "
+              f"mixed (FP32 solve + refinement) {e32r:.2e}", flush=True)
         assert e64 < 1e-11
         assert e32 < 1e-6
-    worst = max(_rel(y32[i], y64[i]) for i in range(nvec))
+        assert e32r < 1e-6
+    worst = max(max(_rel(y32[i], y64[i]), _rel(y32r[i], y64[i])) for i in range(nvec))
     print(f"L={L} N={N} max mixed-vs-fp64 over {nvec} vectors {worst:.2e}", flush=True)
     assert worst < 1e-6
 
