@@ -484,8 +484,8 @@ size_t tsolve_smem(const sc::HostGrid& g) {
 }
 
 // The seven chain-solve launches for RT = ceil(N/16) row tiles.
-template <class F, int RT, bool ACC>
-void chain_solve_rt(sc_plan* P, int nvec, const double* b, double* x, hipStream_t s) {
+template <class F, int RT, bool ACC, bool FIN>
+void chain_solve_rt(sc_plan* P, int nvec, const double* b, double* x, const sc::FinalOut& fo, hipStream_t s) {
   sc::DevGrid dg = P->dg();
   const int nvg = (nvec + kVG - 1) / kVG;
   const bool d = std::is_same<F, double>::value;
@@ -516,15 +516,16 @@ void chain_solve_rt(sc_plan* P, int nvec, const double* b, double* x, hipStream_
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL((sc::k_cs_bwd_bound<F, RT>), dim3(P->nchains, nvg), blk, 0, s, dg, nvec, ch, kSeg, Psi, W);
   HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL((sc::k_cs_out<F, RT, ACC>), dim3(P->nblocks, nvg), blk, 0, s, dg, nvec, P->blk_field.as<int>(),
-                     P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const C*)W, x);
+  hipLaunchKernelGGL((sc::k_cs_out<F, RT, ACC, FIN>), dim3(P->nblocks, nvg), blk, 0, s, dg, nvec,
+                     P->blk_field.as<int>(), P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const C*)W, x, fo);
   HIPCHK(hipGetLastError());
 }
 
 // Implicit solve x = A^{-1} b (ACC: x += A^{-1} b) with factors in precision F (all vectors
-// in canonical FP64).
-template <class F, bool ACC>
-void implicit_solve(sc_plan* P, int nvec, const double* b, double* x, hipStream_t s) {
+// in canonical FP64).  With FIN the result is not stored in x: the output kernels write the
+// Jacobian action fo.y = clean(x) - u instead.
+template <class F, bool ACC, bool FIN>
+void implicit_solve(sc_plan* P, int nvec, const double* b, double* x, const sc::FinalOut& fo, hipStream_t s) {
   sc::DevGrid dg = P->dg();
   const bool d = std::is_same<F, double>::value;
   // the temperature blocks are independent of the chains: solve them on the side stream
@@ -535,17 +536,17 @@ void implicit_solve(sc_plan* P, int nvec, const double* b, double* x, hipStream_
     const F* tr = (const F*)(d ? P->tr64.p : P->tr32.p);
     const F* tc = (const F*)(d ? P->tc64.p : P->tc32.p);
     Prof _p(P, SC_STAGE_T_SOLVE, P->side);
-    hipLaunchKernelGGL((sc::k_T_solve<F, ACC>), dim3(P->hg.L + 1, (nvec + sc::kTV - 1) / sc::kTV), dim3(256),
-                       tsolve_smem<F>(P->hg), P->side, dg, nvec, Ti, tr, tc, b, x);
+    hipLaunchKernelGGL((sc::k_T_solve<F, ACC, FIN>), dim3(P->hg.L + 1, (nvec + sc::kTV - 1) / sc::kTV), dim3(256),
+                       tsolve_smem<F>(P->hg), P->side, dg, nvec, Ti, tr, tc, b, x, fo);
     HIPCHK(hipGetLastError());
   }
   {
     Prof _p(P, SC_STAGE_CHAIN_SOLVE, s);
     switch ((P->hg.N + 15) / 16) {
-      case 1: chain_solve_rt<F, 1, ACC>(P, nvec, b, x, s); break;
-      case 2: chain_solve_rt<F, 2, ACC>(P, nvec, b, x, s); break;
-      case 3: chain_solve_rt<F, 3, ACC>(P, nvec, b, x, s); break;
-      default: chain_solve_rt<F, 4, ACC>(P, nvec, b, x, s); break;
+      case 1: chain_solve_rt<F, 1, ACC, FIN>(P, nvec, b, x, fo, s); break;
+      case 2: chain_solve_rt<F, 2, ACC, FIN>(P, nvec, b, x, fo, s); break;
+      case 3: chain_solve_rt<F, 3, ACC, FIN>(P, nvec, b, x, fo, s); break;
+      default: chain_solve_rt<F, 4, ACC, FIN>(P, nvec, b, x, fo, s); break;
     }
   }
   HIPCHK(hipEventRecord(P->ev_join, P->side));
@@ -553,10 +554,17 @@ void implicit_solve(sc_plan* P, int nvec, const double* b, double* x, hipStream_
 }
 
 // x = A^{-1} b: a solve with the factors in precision F, then `passes` FP64 refinement passes
-// (FP64 residual r = b - A x, FP64 correction solve added to x).
+// (FP64 residual r = b - A x, FP64 correction solve added to x).  With fo the last solve writes
+// the Jacobian action fo->y = clean(x) - u instead of updating x.
 template <class F>
-void refined_solve(sc_plan* P, int nvec, const double* b, double* x, int passes, hipStream_t s) {
-  implicit_solve<F, false>(P, nvec, b, x, s);
+void refined_solve(sc_plan* P, int nvec, const double* b, double* x, int passes, const sc::FinalOut* fo,
+                   hipStream_t s) {
+  const sc::FinalOut none = {nullptr, 0, -1, nullptr, 0};
+  if (fo && passes == 0) {
+    implicit_solve<F, false, true>(P, nvec, b, x, *fo, s);
+    return;
+  }
+  implicit_solve<F, false, false>(P, nvec, b, x, none, s);
   sc::DevGrid dg = P->dg();
   for (int it = 0; it < passes; ++it) {
     {
@@ -571,7 +579,8 @@ void refined_solve(sc_plan* P, int nvec, const double* b, double* x, int passes,
       }
     }
     HIPCHK(hipGetLastError());
-    implicit_solve<double, true>(P, nvec, P->rbuf.as<double>(), x, s);
+    if (fo && it == passes - 1) implicit_solve<double, true, true>(P, nvec, P->rbuf.as<double>(), x, *fo, s);
+    else implicit_solve<double, true, false>(P, nvec, P->rbuf.as<double>(), x, none, s);
   }
 }
 
@@ -584,7 +593,7 @@ void step_into_xbuf(sc_plan* P, const double* x, double C, hipStream_t s) {
                                  (const double*)(P->ws64.as<double>() + P->wl.Av), x, P->n_real, (long long)-1, C,
                                  (const double*)nullptr, P->bbuf.as<double>(), s);
   }
-  refined_solve<double>(P, 1, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine64, s);
+  refined_solve<double>(P, 1, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine64, nullptr, s);
 }
 
 void check_plan(sc_plan* P) {
@@ -617,7 +626,8 @@ void set_base_impl(sc_plan* P, const double* x, double C, long long J, hipStream
 
 void jvp_impl(sc_plan* P, int nvec, const double* v, long long ldv, double* y, long long ldy, int prec, hipStream_t s) {
   const long long J = P->baseJ;
-  sc::DevGrid dg = P->dg();
+  // the last solve writes y = clean(x) - u, u = v with slot J zeroed
+  const sc::FinalOut fo = {v, ldv, J, y, ldy};
   if (prec == SC_FP64) {
     transforms<double>(P, sc::RING_LINEAR, nvec, v, ldv, J, s);
     {
@@ -626,7 +636,7 @@ void jvp_impl(sc_plan* P, int nvec, const double* v, long long ldv, double* y, l
                                     (const double*)(P->ws64.as<double>() + P->wl.Av), v, ldv, J, P->baseC,
                                     P->MX.as<const double>(), P->bbuf.as<double>(), s);
     }
-    refined_solve<double>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine64, s);
+    refined_solve<double>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine64, &fo, s);
   } else {
     transforms<float>(P, sc::RING_LINEAR, nvec, v, ldv, J, s);
     {
@@ -636,16 +646,9 @@ void jvp_impl(sc_plan* P, int nvec, const double* v, long long ldv, double* y, l
                                    P->MX.as<const double>(), P->bbuf.as<double>(), s);
     }
     if (P->mixed_fp32_solve)
-      refined_solve<float>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine32, s);
+      refined_solve<float>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), P->refine32, &fo, s);
     else
-      implicit_solve<double, false>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), s);
-  }
-  long long n = (long long)nvec * P->n_real;
-  {
-    Prof _p(P, SC_STAGE_FINALIZE, s);
-    hipLaunchKernelGGL(sc::k_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, dg, nvec, P->xbuf.as<const double>(), v, ldv, J,
-                       y, ldy, 1);
-    HIPCHK(hipGetLastError());
+      refined_solve<double>(P, nvec, P->bbuf.as<double>(), P->xbuf.as<double>(), 0, &fo, s);
   }
 }
 
@@ -983,12 +986,19 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     {
       const size_t t64 = tsolve_smem<double>(g), t32 = tsolve_smem<float>(g);
       if (t64 > 160 * 1024) throw Fail{SC_ERR_ARG, "too many m for the temperature solve"};
+      auto attr = [](const void* f, size_t b) {
+        HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b));
+      };
       if (t64 > 64 * 1024) {
-        HIPCHK(hipFuncSetAttribute((const void*)sc::k_T_solve<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t64));
-        HIPCHK(hipFuncSetAttribute((const void*)sc::k_T_solve<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t64));
+        attr((const void*)sc::k_T_solve<double, false, false>, t64);
+        attr((const void*)sc::k_T_solve<double, false, true>, t64);
+        attr((const void*)sc::k_T_solve<double, true, false>, t64);
+        attr((const void*)sc::k_T_solve<double, true, true>, t64);
       }
-      if (t32 > 64 * 1024)
-        HIPCHK(hipFuncSetAttribute((const void*)sc::k_T_solve<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)t32));
+      if (t32 > 64 * 1024) {
+        attr((const void*)sc::k_T_solve<float, false, false>, t32);
+        attr((const void*)sc::k_T_solve<float, false, true>, t32);
+      }
     }
     // deterministic contents for slots the solves never write (e, f at l = 0)
     HIPCHK(hipMemset(P->xbuf.p, 0, P->xbuf.bytes));

@@ -67,6 +67,20 @@ struct PhysParams {
   double Ek, Ra, Pr, dt, ro;
 };
 
+// Final output of a Jacobian action, written by the last solve: y = clean(x) - u, where clean
+// zeroes e, f at l = 0 and Im at m = 0, and u = v with the phase slot J read as 0.
+struct FinalOut {
+  const double* v;
+  long long ldv, J;
+  double* y;
+  long long ldy;
+};
+
+__device__ inline double final_value(const FinalOut& fo, int vec, long long o, double x) {
+  const double u = (o == fo.J) ? 0.0 : fo.v[(long long)vec * fo.ldv + o];
+  return x - u;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on XCD b % 8), each
 // with its own L2.  This maps blockIdx.x to a linear id such that every XCD receives one
 // contiguous range of ids (a bijection on [0, gridDim.x)).
@@ -1262,13 +1276,15 @@ __global__ void __launch_bounds__(kSolveThreads) k_cs_fix(DevGrid g, int nvec, c
 }
 
 // x_i = xi_i + Psi_i x_{a(p+1)} for the blocks not yet final, then x = Cg x~ into the
-// canonical FP64 output (ACC: added to it, the update of a refinement pass).  One workgroup
-// per (block, vector group).
-template <class F, int RT, bool ACC>
+// canonical FP64 output (ACC: added to it, the update of a refinement pass; FIN: the sum is
+// not stored but turned into the Jacobian action y = clean(x) - u).  One workgroup per
+// (block, vector group).
+template <class F, int RT, bool ACC, bool FIN>
 __global__ void __launch_bounds__(kSolveThreads) k_cs_out(DevGrid g, int nvec, const int* __restrict__ blk_field,
                                                          const int* __restrict__ blk_lm, const int* __restrict__ blk_next,
                                                          const cpx<F>* __restrict__ Psi, const F* __restrict__ Cg,
-                                                         const cpx<F>* __restrict__ W, double* __restrict__ xvec) {
+                                                         const cpx<F>* __restrict__ W, double* __restrict__ xvec,
+                                                         FinalOut fo) {
   __shared__ cpx<F> xs[64 * kVG];
   typedef ChainOps<F, RT> Ops;
   const int N = g.N;
@@ -1286,17 +1302,25 @@ __global__ void __launch_bounds__(kSolveThreads) k_cs_out(DevGrid g, int nvec, c
     typename Ops::acc_t yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
     if (nx >= 0) op.apply(S, xs, yr, yi);
     const long long ld = 6LL * N * g.S;
-    const long long o = 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + blk_lm[blk]));
+    const int lm = blk_lm[blk];
+    const long long o = 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + lm));
+    const bool mzero = (g.lm_k[lm] == 0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int r = op.row(q);
       if (r < N && op.col < nv) {
         const double c = (double)Cg[(long long)blk * N + r];
         double* xp = xvec + (long long)(v0 + op.col) * ld + o + 2 * r;
-        const double x0 = c * (double)(S.w[q].re + yr[q]), x1 = c * (double)(S.w[q].im + yi[q]);
+        double x0 = c * (double)(S.w[q].re + yr[q]), x1 = c * (double)(S.w[q].im + yi[q]);
         if (ACC) {
-          xp[0] += x0;
-          xp[1] += x1;
+          x0 += xp[0];
+          x1 += xp[1];
+        }
+        if (FIN) {
+          const long long oo = o + 2 * r;
+          double* yp = fo.y + (long long)(v0 + op.col) * fo.ldy + oo;
+          yp[0] = final_value(fo, v0 + op.col, oo, x0);
+          yp[1] = final_value(fo, v0 + op.col, oo + 1, mzero ? 0.0 : x1);
         } else {
           xp[0] = x0;
           xp[1] = x1;
@@ -1307,14 +1331,16 @@ __global__ void __launch_bounds__(kSolveThreads) k_cs_out(DevGrid g, int nvec, c
 }
 
 // Temperature blocks: x = tc * Tinv (tr * b) per l, for every (vec, k, l), both Re and Im
-// (ACC: added to x).  One workgroup per (l, group of kTV vectors): Tinv_l staged in LDS,
-// columns (vec, k, Re/Im).
+// (ACC: added to x; FIN: y = clean(x) - u is written instead of x, and the workgroups of l = 0
+// also write y = -u on the e, f slots at l = 0, which no chain covers).  One workgroup per
+// (l, group of kTV vectors): Tinv_l staged in LDS, columns (vec, k, Re/Im).
 constexpr int kTV = 4;
 
-template <class F, bool ACC>
+template <class F, bool ACC, bool FIN>
 __global__ void __launch_bounds__(256) k_T_solve(DevGrid g, int nvec, const F* __restrict__ Tinv,
                                                  const F* __restrict__ tr, const F* __restrict__ tc,
-                                                 const double* __restrict__ bvec, double* __restrict__ xvec) {
+                                                 const double* __restrict__ bvec, double* __restrict__ xvec,
+                                                 FinalOut fo) {
   extern __shared__ unsigned char smem_raw[];
   const int N = g.N;
   F* Ts = reinterpret_cast<F*>(smem_raw);         // [N][N] transposed: Ts[i * N + j] = Tinv[j][i]
@@ -1341,9 +1367,22 @@ __global__ void __launch_bounds__(256) k_T_solve(DevGrid g, int nvec, const F* _
     for (int i = 0; i < N; ++i) a += Ts[i * N + jj] * bc[i];
     int lm = g.lmbase[kk] + l - kk * g.m0;
     long long o = (long long)(v0 + vv) * ld + 2LL * ((long long)N * (2LL * g.S + lm) + jj) + ri;
-    const double xv = (double)(tc[(long long)l * N + jj] * a);
-    if (ACC) xvec[o] += xv;
-    else xvec[o] = xv;
+    double xv = (double)(tc[(long long)l * N + jj] * a);
+    if (ACC) xv += xvec[o];
+    if (FIN) {
+      const long long oo = 2LL * ((long long)N * (2LL * g.S + lm) + jj) + ri;
+      fo.y[(long long)(v0 + vv) * fo.ldy + oo] = final_value(fo, v0 + vv, oo, (kk == 0 && ri == 1) ? 0.0 : xv);
+    } else {
+      xvec[o] = xv;
+    }
+  }
+  if (FIN && l == 0) {
+    // e, f at (m, l) = (0, 0): lm = 0
+    for (int idx = threadIdx.x; idx < nv * 2 * 2 * N; idx += blockDim.x) {
+      const int ri = idx & 1, jj = (idx >> 1) % N, f = (idx / (2 * N)) & 1, vv = idx / (4 * N);
+      const long long oo = 2LL * ((long long)N * ((long long)f * g.S) + jj) + ri;
+      fo.y[(long long)(v0 + vv) * fo.ldy + oo] = final_value(fo, v0 + vv, oo, 0.0);
+    }
   }
 }
 
