@@ -3,8 +3,8 @@
 //
 // Data layouts (nv = vectors in the batch, q = field component, ri = Re/Im):
 //   canonical state  v[vec][field e,f,T][lm][j][ri]          (FP64; lm packs (m, l))
-//   synthesis input  Gs[k][(vec, rp, q<3, ri)][l-m]  Gv[k][(vec, rp, q<5, ri)][l-m]
-//   synthesis output Cs[k][(vec, rp, q<3, ri)][theta]  Cv[k][(vec, rp, q<5, ri)][2 nth]
+//   synthesis input  Gs[k][(vec, q<3, ri, rp)][l-m]  Gv[k][(vec, q<5, ri, rp)][l-m]  (operand order)
+//   synthesis output Cs[k][(vec, q<3, ri, rp)][theta]  Cv[k][(vec, q<5, ri, rp)][2 nth]
 //   analysis input   Fs[k][(vec, rp, q<2, ri)][theta]  Fv[k][(vec, rp, q<2, ri)][2 nth]
 //   analysis output  As[k][(vec, rp, q<2, ri)][l-m]    Av[k][(vec, rp, q<2, ri)][l-m]
 //   base fields      base[rp][field<9][phi][theta]
@@ -158,99 +158,138 @@ __device__ inline void mfma_f64_products(const double* const (&Mp)[NPR], const T
 //   Su = f'/r, Tu = e/r, Sw = e'/r, Tw = -(f'' - lam f/r^2)/r, ST = T/r  (vector synthesis)
 // evaluated at the N_p nodes as diag(r^-k) E D^j u, in FP64, stored in precision T.
 // Input cleaning: Im at m = 0, e/f at l = 0 and the phase slot J are read as 0.
-// One workgroup per (tile of up to 16 consecutive l at one m, vector).  The tile's profiles
-// form the columns (field, Re/Im, l) of X (N x 96, staged in LDS); the products E X, ED X and
-// (f columns only) ED2 X run on the FP64 matrix cores, one (16 r_p x 16 column) tile per
-// wavefront at a time, and every output is formed from one column's products in registers.
-constexpr int kRPT = 16;  // l per radial-prep tile
+constexpr int kRPT = 16;      // l per radial-prep tile
 
-template <class T, int RTN>
-__global__ void __launch_bounds__(256) k_radial_prep(DevGrid g, const double* __restrict__ v, long long ldv,
-                                                     long long J, int nvec, T* __restrict__ Gs, T* __restrict__ Gv) {
-  constexpr int KS = 4 * RTN;           // k-steps over the N nodes (rows of X padded to 16 RTN)
-  constexpr int NC = 6 * kRPT;          // columns (field, c, t)
-  constexpr int XST = NC + 16;          // LDS row stride: consecutive k rows 32 banks apart
-  __shared__ double xs[16 * RTN * XST];
+// The work of one wavefront: NT column tiles (ct0, ct0 + 4) of one field class, NP products
+// each (E, ED and, for f, ED2).  Kept separate per wave kind so that each holds only its own
+// operands.
+template <class T, int RTN, int NT, int NP>
+__device__ inline void radial_prep_wave(const DevGrid& g, const double* __restrict__ vb, long long J, int vec, int k,
+                                        int il0, int ct0, T* __restrict__ Gs, T* __restrict__ Gv) {
+  constexpr int KS = 4 * RTN;           // k-steps over the N nodes
+  constexpr int QB = KS / 4;            // k-steps per operand block (a quarter row tile)
   const int N = g.N, Np = g.Np;
   const int RTP = (Np + 15) / 16;
-  const int2 tl = g.rtiles[blockIdx.x];
-  const int vec = blockIdx.y;
-  const int k = tl.x, il0 = tl.y;
   const int m = k * g.m0, nl = g.L - m + 1;
   const int nt = min(kRPT, nl - il0);
   const int lm0 = g.lmbase[k] + il0;
-  const double* vb = v + (long long)vec * ldv;
-  for (int idx = threadIdx.x; idx < 16 * RTN * NC; idx += blockDim.x) {
-    const int col = idx % NC, j = idx / NC;
-    const int t = col % kRPT, c = (col / kRPT) & 1, f = col / (2 * kRPT);
-    double val = 0.0;
-    if (j < N && t < nt) {
-      const long long o = 2LL * ((long long)N * ((long long)f * g.S + lm0 + t) + j) + c;
-      const int l = m + il0 + t;
-      val = vb[o];
-      if (o == J || (c == 1 && k == 0) || (f < 2 && l == 0)) val = 0.0;
+  const int l = threadIdx.x & 63, t = l & 15;
+  // X^T operands: lane l of k-step s holds X[4 s + l/16][column t] of its tile
+  double xb[NT][KS];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    const int ct = ct0 + 4 * u, f = ct >> 1, c = ct & 1;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int j = 4 * s + (l >> 4);
+      double val = 0.0;
+      if (j < N && t < nt) {
+        const long long o = 2LL * ((long long)N * ((long long)f * g.S + lm0 + t) + j) + c;
+        val = vb[o];
+        if (o == J || (c == 1 && k == 0) || (f < 2 && m + il0 + t == 0)) val = 0.0;
+      }
+      xb[u][s] = val;
     }
-    xs[j * XST + col] = val;
   }
-  __syncthreads();
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const long long mstride = (long long)RTP * KS * 64;
-  // outputs in operand order: row r of the sums, depth column kc of degree il (even l - m at
-  // il/2, odd ones at 4 KSe + il/2): ((r/16) KS + kc/4) 64 + (kc%4) 16 + r%16
+  // Synthesis operand order: row r = (vec ns + slot) Np + r_p of the sums, depth column kc of
+  // degree il (even l - m at il/2, odd ones at 4 KSe + il/2) at
+  // ((r/16) KSl + kc/4) 64 + (kc%4) 16 + r%16.
   const long long offS = g.gsoff[2 * k], offV = g.gsoff[2 * k + 1];
   const int KSe = ((nl + 1) / 2 + 3) >> 2, KSo = (nl / 2 + 3) >> 2, KSl = KSe + KSo;
-  const int t = l & 15;
-  const int il = il0 + t, lw = m + il;
-  const double lam = (double)lw * (lw + 1);
-  for (int p = w; p < RTP * 6; p += 4) {
-    const int rt = p / 6, ct = p % 6, f = ct >> 1, c = ct & 1;
-    const double* F0 = g.EF + (long long)rt * KS * 64 + l;
-    double a0[KS], a1[KS], a2[KS];
+  // E operands in quarter row tiles, the next block loading while the current one multiplies:
+  // block b = 4 rt + h
+  double ea[NP][QB], eb[NP][QB];
+  auto load_blk = [&](int b, double (&a)[NP][QB]) {
+    b = b < 4 * RTP ? b : 4 * RTP - 1;
+    const double* F = g.EF + (long long)(b >> 2) * KS * 64 + (b & 3) * QB * 64 + l;
 #pragma unroll
-    for (int sidx = 0; sidx < KS; ++sidx) {
-      a0[sidx] = F0[sidx * 64];
-      a1[sidx] = F0[mstride + sidx * 64];
-      a2[sidx] = (f == 1) ? F0[2 * mstride + sidx * 64] : 0.0;
-    }
-    f64x4 y0 = {0, 0, 0, 0}, y1 = {0, 0, 0, 0}, y2 = {0, 0, 0, 0};
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
-    for (int sidx = 0; sidx < KS; ++sidx) {
-      const double b = xs[(4 * sidx + (l >> 4)) * XST + ct * 16 + t];
-      y0 = Mfma<double>::step(a0[sidx], b, y0);
-      y1 = Mfma<double>::step(a1[sidx], b, y1);
-      if (f == 1) y2 = Mfma<double>::step(a2[sidx], b, y2);
+      for (int s = 0; s < QB; ++s) a[p][s] = F[p * mstride + s * 64];
+  };
+  f64x4 acc[NT][NP];
+  auto run_blk = [&](int h, const double (&a)[NP][QB]) {
+#pragma unroll
+    for (int s = 0; s < QB; ++s)
+#pragma unroll
+      for (int u = 0; u < NT; ++u)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) acc[u][p] = Mfma<double>::step(xb[u][h * QB + s], a[p][s], acc[u][p]);
+  };
+  load_blk(0, ea);
+  for (int rt = 0; rt < RTP; ++rt) {
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int p = 0; p < NP; ++p) acc[u][p] = f64x4{0, 0, 0, 0};
+#pragma unroll
+    for (int h = 0; h < 4; h += 2) {
+      load_blk(4 * rt + h + 1, eb);
+      __builtin_amdgcn_sched_barrier(0);
+      run_blk(h, ea);
+      load_blk(4 * rt + h + 2, ea);
+      __builtin_amdgcn_sched_barrier(0);
+      run_blk(h + 1, eb);
     }
-    if (t >= nt) continue;
+    // epilogue: this lane's r_p, four degrees (element q: degree il0 + l/16 + 4 q)
+    const int rp = 16 * rt + t;
+    if (rp >= Np) continue;
+    const double ri1 = 1.0 / g.rp[rp], ri2 = ri1 * ri1;
+    const long long rs = (long long)vec * 6 * Np + rp, rv = (long long)vec * 10 * Np + rp;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int rp = 16 * rt + Mfma<double>::out_row(l, q);
-      if (rp >= Np) continue;
-      const double ri1 = 1.0 / g.rp[rp], ri2 = ri1 * ri1;
-      const long long rs = ((long long)vec * Np + rp) * 6 + c, rv = ((long long)vec * Np + rp) * 10 + c;
+      const int tq = Mfma<double>::out_row(l, q), il = il0 + tq, lw = m + il;
+      if (tq >= nt) continue;
       const int kc = (il & 1) ? 4 * KSe + (il >> 1) : (il >> 1);
       const long long kofs = (kc >> 2) * 64 + (kc & 3) * 16;
-      auto gs = [&](int slot) -> T& {
-        const long long r = rs + slot;
-        return Gs[offS + ((r >> 4) * KSl) * 64 + kofs + (r & 15)];
+      const double lam = (double)lw * (lw + 1);
+      auto gs = [&](int slot, double val) {
+        const long long r = rs + (long long)slot * Np;
+        Gs[offS + (r >> 4) * KSl * 64 + kofs + (r & 15)] = (T)val;
       };
-      auto gv = [&](int slot) -> T& {
-        const long long r = rv + slot;
-        return Gv[offV + ((r >> 4) * KSl) * 64 + kofs + (r & 15)];
+      auto gv = [&](int slot, double val) {
+        const long long r = rv + (long long)slot * Np;
+        Gv[offV + (r >> 4) * KSl * 64 + kofs + (r & 15)] = (T)val;
       };
-      if (f == 0) {          // e
-        gs(2) = (T)(lam * ri2 * y0[q]);                          // wr
-        gv(2) = (T)(y0[q] * ri1);                                // Tu
-        gv(4) = (T)(y1[q] * ri1);                                // Sw
-      } else if (f == 1) {   // f
-        gs(0) = (T)(lam * ri2 * y0[q]);                          // ur
-        gv(0) = (T)(y1[q] * ri1);                                // Su
-        gv(6) = (T)(-y2[q] * ri1 + lam * ri2 * ri1 * y0[q]);     // Tw
-      } else {               // T
-        gs(4) = (T)(y1[q]);                                      // dT
-        gv(8) = (T)(y0[q] * ri1);                                // ST
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const int ct = ct0 + 4 * u, f = ct >> 1, c = ct & 1;
+        const double y0 = acc[u][0][q], y1 = acc[u][1][q], y2 = (NP == 3) ? acc[u][NP - 1][q] : 0.0;
+        if (f == 0) {          // e
+          gs(2 + c, lam * ri2 * y0);                                   // wr
+          gv(2 + c, y0 * ri1);                                         // Tu
+          gv(4 + c, y1 * ri1);                                         // Sw
+        } else if (f == 1) {   // f
+          gs(0 + c, lam * ri2 * y0);                                   // ur
+          gv(0 + c, y1 * ri1);                                         // Su
+          gv(6 + c, -y2 * ri1 + lam * ri2 * ri1 * y0);                 // Tw
+        } else {               // T
+          gs(4 + c, y1);                                               // dT
+          gv(8 + c, y0 * ri1);                                         // ST
+        }
       }
     }
   }
+}
+
+// K1: one workgroup per (tile of up to 16 consecutive l at one m, vector).  The tile's
+// profiles form six 16-column tiles (field, Re/Im) of X; wavefront w owns column tiles w and
+// (w < 2) w + 4 (waves 0, 1: an e and a T tile, products E and ED; waves 2, 3: an f tile,
+// products E, ED, ED2) and holds their X operands in registers (read once from the state).
+// Row tile by row tile it forms (E X)^T = X^T E^T etc. on the FP64 matrix cores, with the E
+// operands streamed from L2 a quarter row tile ahead.  A lane then holds 16 consecutive r_p
+// of one degree, which are consecutive rows of the synthesis operands (rows ordered
+// (vec, slot, r_p)): every store writes runs of 16 contiguous elements.
+template <class T, int RTN>
+__global__ void __launch_bounds__(256) k_radial_prep(DevGrid g, const double* __restrict__ v, long long ldv,
+                                                     long long J, int nvec, T* __restrict__ Gs, T* __restrict__ Gv) {
+  const int2 tl = g.rtiles[blockIdx.x];
+  const int vec = blockIdx.y;
+  const double* vb = v + (long long)vec * ldv;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (w >= 2) radial_prep_wave<T, RTN, 1, 3>(g, vb, J, vec, tl.x, tl.y, w, Gs, Gv);
+  else radial_prep_wave<T, RTN, 2, 2>(g, vb, J, vec, tl.x, tl.y, w, Gs, Gv);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -704,19 +743,21 @@ __global__ void __launch_bounds__(kRingThreads) k_ring(DevGrid g, int nvec, int 
   // packing fields (2q, 2q+1) into spectrum q: Z_k = (A_k + i B_k)/2, Z_{N-k} = conj(A_k)/2 +
   // i conj(B_k)/2 for k >= 1 and Z_0 = Re A_0 + i Re B_0.
   const long long Ms = (long long)6 * g.Np * g.vcap, Mv = (long long)10 * g.Np * g.vcap;
+  const int vq = rv - rp * nvec;  // vector index
   for (int idx = tid; idx < K1 * RT; idx += kRingThreads) {
     const int tt = idx & rmask, k = idx >> rt_log2;
     const int th = th0 + tt;
     if (th >= nth) continue;
     T c[26];
-    const T* cs = Cs + (long long)k * Ms * nth + ((long long)vr * 6) * nth + th;
+    // rows of the sums: (vec, slot, r_p)
+    const T* cs = Cs + (long long)k * Ms * nth + ((long long)vq * 6 * g.Np + rp) * nth + th;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) c[q] = cs[(long long)q * nth];
-    const T* cv = Cv + (long long)k * Mv * 2 * nth + ((long long)vr * 10) * 2 * nth + th;
+    for (int q = 0; q < 6; ++q) c[q] = cs[(long long)q * g.Np * nth];
+    const T* cv = Cv + (long long)k * Mv * 2 * nth + ((long long)vq * 10 * g.Np + rp) * 2 * nth + th;
 #pragma unroll
     for (int q = 0; q < 10; ++q) {
-      c[6 + q] = cv[(long long)q * 2 * nth];         // dP part
-      c[16 + q] = cv[(long long)q * 2 * nth + nth];  // mPs part
+      c[6 + q] = cv[(long long)q * g.Np * 2 * nth];         // dP part
+      c[16 + q] = cv[(long long)q * g.Np * 2 * nth + nth];  // mPs part
     }
     // scalar sums: U_r (0,1), w_r (2,3), dT/dr (4,5); vector sums q: S_u 0, T_u 1, S_w 2, T_w 3, T 4
     auto dPr = [&](int q) { return c[6 + 2 * q]; };
