@@ -79,6 +79,7 @@ struct sc_plan {
   int vcap = 16, wcap = 16;
   int refine64 = 1, refine32 = 1;
   bool mixed_fp32_solve = false;  // SC_MIXED_SOLVE_FP32
+  bool ring_reg32 = true, ring_reg64 = false;  // register-transform ring kernel where N_phi has one
   int fft_nr = 0, fft_r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   long long n_real = 0;
   bool factored = false, have_base = false;
@@ -392,6 +393,29 @@ int ring_rt_log2(const sc::HostGrid& g) {
   return lg;
 }
 
+// Register-transform ring kernel for N_phi = N1 N2, if this N_phi has one and N_phi >= 3K + 1.
+// Returns false if not.
+template <class T, int MODE>
+bool launch_ring_reg(int nphi, dim3 grid, hipStream_t s, const sc::DevGrid& dg, int nvec, const T* Cs, const T* Cv,
+                     const T* base, const T* fw, T Ek, T* Fs, T* Fv, double* b64, float* b32) {
+  // the LDS copy of the sums (26 (K+1) per ring) fits the field buffer (10 (N_phi + 1)) when
+  // N_phi >= 3K + 1
+  if (3 * dg.K + 1 > nphi) return false;
+#define SC_RING_REG(N1, N2)                                                                                   \
+  hipLaunchKernelGGL((sc::k_ring_reg<T, MODE, N1, N2>), grid, dim3(256), 0, s, dg, nvec, Cs, Cv, base, fw, Ek, Fs, \
+                     Fv, b64, b32);                                                                           \
+  return true
+  switch (nphi) {
+    case 10: SC_RING_REG(2, 5);
+    case 15: SC_RING_REG(3, 5);
+    case 20: SC_RING_REG(4, 5);
+    case 32: SC_RING_REG(8, 4);
+    case 40: SC_RING_REG(8, 5);
+    default: return false;
+  }
+#undef SC_RING_REG
+}
+
 // Spectral state -> analysed forces (As, Av) in precision T.  mode: linear/nonlinear/synth.
 template <class T>
 void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, long long J, hipStream_t s) {
@@ -426,9 +450,25 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
   const T* base = std::is_same<T, double>::value ? (const T*)P->base64.p : (const T*)P->base32.p;
   const T* fw = tab + P->tl.fw;
   T Ek = (T)P->prm.Ek;
+  const bool use_reg = std::is_same<T, float>::value ? P->ring_reg32 : P->ring_reg64;
+  const int RRg = sc::ring_reg_rings<T>();
+  const dim3 grid_reg((unsigned)((long long)nvec * g.Np * ((g.nth + RRg - 1) / RRg)));
   {
     Prof _p(P, SC_STAGE_RING, s);
-    if (mode == sc::RING_LINEAR)
+    bool done = false;
+    if (use_reg) {
+      if (mode == sc::RING_LINEAR)
+        done = launch_ring_reg<T, sc::RING_LINEAR>(g.nphi, grid_reg, s, dg, nvec, ws + w.Cs, ws + w.Cv, base, fw, Ek,
+                                                    ws + w.Fs, ws + w.Fv, (double*)nullptr, (float*)nullptr);
+      else if (mode == sc::RING_NONLINEAR)
+        done = launch_ring_reg<T, sc::RING_NONLINEAR>(g.nphi, grid_reg, s, dg, nvec, ws + w.Cs, ws + w.Cv, base, fw, Ek,
+                                                       ws + w.Fs, ws + w.Fv, (double*)nullptr, (float*)nullptr);
+      else
+        done = launch_ring_reg<T, sc::RING_SYNTH>(g.nphi, grid_reg, s, dg, nvec, ws + w.Cs, ws + w.Cv, base, fw, Ek,
+                                                   ws + w.Fs, ws + w.Fv, P->base64.as<double>(), P->base32.as<float>());
+    }
+    if (done) {
+    } else if (mode == sc::RING_LINEAR)
       hipLaunchKernelGGL((sc::k_ring<T, sc::RING_LINEAR>), grid, dim3(256), smem, s, dg, nvec, rtl, ws + w.Cs, ws + w.Cv,
                          base, fw, Ek, ws + w.Fs, ws + w.Fv, (double*)nullptr, (float*)nullptr);
     else if (mode == sc::RING_NONLINEAR)

@@ -881,6 +881,271 @@ __global__ void __launch_bounds__(kRingThreads) k_ring(DevGrid g, int nvec, int 
 }
 
 // ------------------------------------------------------------------------------------------
+// K3/K4/K5 with register-resident transforms, for N_phi = N1 N2 (N1, N2 in {2, 3, 4, 5, 8}).
+// Every thread owns one complex transform of one ring and runs it entirely in registers as a
+// four-step FFT with compile-time indices: N2 DFTs of length N1 over n1 (inputs n = N2 n1 + n2),
+// twiddles w^(n2 k1), N1 DFTs of length N2 over n2.  Both steps work in place, so output k
+// = k1 + N1 k2 ends at position N2 k1 + k2 (fft_pos).  LDS only carries the fields from the
+// inverse transforms to the pointwise products and the products to the forward transforms.
+template <int N1, int N2>
+__host__ __device__ constexpr int fft_pos(int k) {
+  return N2 * (k % N1) + k / N1;
+}
+
+// x: natural order in, x[fft_pos(k)] = sum_n x_n exp(SGN 2 pi i n k / N) out; fw[2e], fw[2e+1]
+// = cos, -sin(2 pi e / N).
+template <class T, int N1, int N2, int SGN>
+__device__ inline void fft_reg(cz<T> (&x)[N1 * N2], const T* __restrict__ fw) {
+  constexpr int N = N1 * N2;
+#pragma unroll
+  for (int n2 = 0; n2 < N2; ++n2) {
+    cz<T> v[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) v[n1] = x[N2 * n1 + n2];
+    small_dft<T, N1>(v, (T)SGN);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+      cz<T> a = v[k1];
+      const int e = (n2 * k1) % N;
+      if (e != 0) {
+        const T c = fw[2 * e], sn = (SGN < 0) ? fw[2 * e + 1] : -fw[2 * e + 1];
+        a = {a.re * c - a.im * sn, a.re * sn + a.im * c};
+      }
+      x[N2 * k1 + n2] = a;
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) {
+    cz<T> u[N2];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) u[n2] = x[N2 * k1 + n2];
+    small_dft<T, N2>(u, (T)SGN);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) x[N2 * k1 + k2] = u[k2];
+  }
+}
+
+// Fourier coefficients (fr, fi) at one k of field F (0..8 as in k_ring; 9 is zero) from the
+// Legendre sums of one ring, read from the LDS copy g[row * rs] with rows 0..5 the scalar sums,
+// 6..15 the dP parts and 16..25 the mP/sin parts of the vector sums.
+template <class T, int F>
+__device__ inline void ring_field_coef(const T* g, int rs, T& fr, T& fi) {
+  auto c = [&](int j, int ri) { return g[(2 * j + ri) * rs]; };
+  auto dP = [&](int j, int ri) { return g[(6 + 2 * j + ri) * rs]; };
+  auto mP = [&](int j, int ri) { return g[(16 + 2 * j + ri) * rs]; };
+  if (F == 0) { fr = c(0, 0); fi = c(0, 1); }                                        // U_r
+  else if (F == 1) { fr = dP(0, 0) - mP(1, 1); fi = dP(0, 1) + mP(1, 0); }           // U_th
+  else if (F == 2) { fr = -mP(0, 1) - dP(1, 0); fi = mP(0, 0) - dP(1, 1); }          // U_ph
+  else if (F == 3) { fr = c(1, 0); fi = c(1, 1); }                                   // w_r
+  else if (F == 4) { fr = dP(2, 0) - mP(3, 1); fi = dP(2, 1) + mP(3, 0); }           // w_th
+  else if (F == 5) { fr = -mP(2, 1) - dP(3, 0); fi = mP(2, 0) - dP(3, 1); }          // w_ph
+  else if (F == 6) { fr = c(2, 0); fi = c(2, 1); }                                   // dT/dr
+  else if (F == 7) { fr = dP(4, 0); fi = dP(4, 1); }                                 // (1/r) dT/dth
+  else if (F == 8) { fr = -mP(4, 1); fi = mP(4, 0); }                                // (1/(r sin)) dT/dph
+  else { fr = 0; fi = 0; }
+}
+
+// Spectrum of transform q = fields (2q, 2q+1) of one ring, packed as in k_ring; g points at
+// the ring's column of the LDS copy, laid out [row][k][ring] (row stride rs, k stride ks).
+template <class T, int N, int QA>
+__device__ inline void ring_spectrum(cz<T> (&z)[N], const T* g, int rs, int ks, int K1) {
+  constexpr int KMAX = (N - 1) / 2;
+#pragma unroll
+  for (int k = 0; k <= KMAX; ++k) {
+    T ar = 0, ai = 0, br = 0, bi = 0;
+    if (k < K1) {
+      ring_field_coef<T, 2 * QA>(g + k * ks, rs, ar, ai);
+      ring_field_coef<T, 2 * QA + 1>(g + k * ks, rs, br, bi);
+    }
+    if (k == 0) {
+      z[0] = {ar, br};
+    } else {
+      z[k] = {(T)0.5 * (ar - bi), (T)0.5 * (ai + br)};
+      z[N - k] = {(T)0.5 * (ar + bi), (T)0.5 * (br - ai)};
+    }
+  }
+}
+
+// Rings per workgroup of k_ring_reg.
+template <class T>
+__host__ __device__ constexpr int ring_reg_rings() {
+  return sizeof(T) == 4 ? 32 : 16;
+}
+
+template <class T, int MODE, int N1, int N2>
+__global__ void __launch_bounds__(256) k_ring_reg(DevGrid g, int nvec, const T* __restrict__ Cs, const T* __restrict__ Cv,
+                                                  const T* __restrict__ base, const T* __restrict__ fw, T Ek,
+                                                  T* __restrict__ Fs, T* __restrict__ Fv, double* __restrict__ base_out64,
+                                                  float* __restrict__ base_out32) {
+  constexpr int N = N1 * N2, RR = ring_reg_rings<T>(), LS = N + 1;  // LS: LDS stride of one (slot, ring)
+  constexpr int KMAX = (N - 1) / 2;
+  constexpr int NPT = (RR * N + 255) / 256;                         // product points per thread
+  // the fields of the transforms; first the copy of the Legendre sums [26 rows][K1][RR rings]
+  __shared__ cz<T> X[5 * RR * LS];
+  T* Gl = reinterpret_cast<T*>(X);
+  const int K1 = g.K + 1, nth = g.nth, Np = g.Np;
+  const int ntile = (nth + RR - 1) / RR;
+  const int lid = xcd_linear_id();
+  const int tile = lid % ntile, rv = lid / ntile, rp = rv / nvec, vq = rv - rp * nvec;
+  const int th0 = tile * RR, tid = threadIdx.x;
+  // base fields of this thread's product points, loaded first so they arrive during the FFTs
+  T bpre[NPT][9];
+  if (MODE == RING_LINEAR) {
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      const int idx = tid + 256 * u, r = idx % RR, pt = idx / RR, th = th0 + r;
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+        bpre[u][q] = (pt < N && th < nth) ? base[(((long long)rp * 9 + q) * N + pt) * nth + th] : (T)0;
+    }
+  }
+  // copy of the sums of this workgroup's rings into LDS, [26 rows][K1][RR rings]: every (row, k)
+  // is a run of RR consecutive theta, read as 8-byte pieces (nth and th0 are even, so a piece
+  // lies wholly inside or wholly beyond the last node).  K1 <= KM = (N - 1)/3 + 1, so the
+  // loop has a compile-time trip count and all loads of a thread are issued together.
+  {
+    constexpr int EPL = 8 / sizeof(T), PPR = RR / EPL, JS = 256 / PPR;   // elements per piece, pieces per run
+    constexpr int KM = (N - 1) / 3 + 1, NIT = (26 * KM + JS - 1) / JS;
+    typedef T pT __attribute__((ext_vector_type(EPL)));
+    const long long kS = (long long)6 * Np * g.vcap * nth, kV = (long long)10 * Np * g.vcap * 2 * nth;
+    const long long sS = (long long)Np * nth, sV = (long long)Np * 2 * nth;
+    const int e = tid % PPR, j0 = tid / PPR, th = th0 + e * EPL;
+    const bool ok = th < nth;
+    const T* cs = Cs + ((long long)vq * 6 * Np + rp) * nth + th;
+    const T* cv = Cv + ((long long)vq * 10 * Np + rp) * 2 * nth + th;
+    pT val[NIT];
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+      const int rk = j0 + i * JS, row = rk / KM, k = rk - row * KM;
+      val[i] = pT{};
+      if (row < 26 && k < K1 && ok) {
+        const T* src = row < 6 ? cs + row * sS + k * kS
+                               : (row < 16 ? cv + (row - 6) * sV + k * kV : cv + (row - 16) * sV + nth + k * kV);
+        val[i] = *reinterpret_cast<const pT*>(src);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+      const int rk = j0 + i * JS, row = rk / KM, k = rk - row * KM;
+      if (row < 26 && k < K1) *reinterpret_cast<pT*>(Gl + (row * K1 + k) * RR + e * EPL) = val[i];
+    }
+  }
+  __syncthreads();
+  // inverse transforms: thread (q, r) owns transform q of ring r
+  {
+    const int q = tid / RR, r = tid % RR;
+    cz<T> z[N];
+#pragma unroll
+    for (int p = 0; p < N; ++p) z[p] = {(T)0, (T)0};
+    if (q < 5) {
+      const T* gr = Gl + r;
+      if (q == 0) ring_spectrum<T, N, 0>(z, gr, K1 * RR, RR, K1);
+      else if (q == 1) ring_spectrum<T, N, 1>(z, gr, K1 * RR, RR, K1);
+      else if (q == 2) ring_spectrum<T, N, 2>(z, gr, K1 * RR, RR, K1);
+      else if (q == 3) ring_spectrum<T, N, 3>(z, gr, K1 * RR, RR, K1);
+      else ring_spectrum<T, N, 4>(z, gr, K1 * RR, RR, K1);
+    }
+    __syncthreads();   // the copy of the sums is dead from here on; X reuses its space
+    if (q < 5) {
+      fft_reg<T, N1, N2, 1>(z, fw);
+      cz<T>* xo = X + (q * RR + r) * LS;
+#pragma unroll
+      for (int p = 0; p < N; ++p) xo[p] = z[fft_pos<N1, N2>(p)];
+    }
+  }
+  __syncthreads();
+  // pointwise products at (ring, point), in place as slot 0 = W_r + i Q, slot 1 = W_th + i W_ph
+#pragma unroll
+  for (int u = 0; u < NPT; ++u) {
+    const int idx = tid + 256 * u, r = idx % RR, pt = idx / RR, th = th0 + r;
+    if (pt >= N) continue;
+    T f[10];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const cz<T> zq = X[(q * RR + r) * LS + pt];
+      f[2 * q] = zq.re;
+      f[2 * q + 1] = zq.im;
+    }
+    if (MODE == RING_SYNTH) {
+      if (th < nth) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          const long long o = (((long long)rp * 9 + q) * N + pt) * nth + th;
+          base_out64[o] = (double)f[q];
+          if (base_out32) base_out32[o] = (float)f[q];
+        }
+      }
+      continue;
+    }
+    T W0, W1, W2, Q;
+    if (MODE == RING_NONLINEAR) {
+      W0 = Ek * (f[1] * f[5] - f[2] * f[4]);
+      W1 = Ek * (f[2] * f[3] - f[0] * f[5]);
+      W2 = Ek * (f[0] * f[4] - f[1] * f[3]);
+      Q = -(f[0] * f[6] + f[1] * f[7] + f[2] * f[8]);
+    } else {
+      const T* b = bpre[u];
+      W0 = Ek * ((b[1] * f[5] - b[2] * f[4]) + (f[1] * b[5] - f[2] * b[4]));
+      W1 = Ek * ((b[2] * f[3] - b[0] * f[5]) + (f[2] * b[3] - f[0] * b[5]));
+      W2 = Ek * ((b[0] * f[4] - b[1] * f[3]) + (f[0] * b[4] - f[1] * b[3]));
+      Q = -((b[0] * f[6] + b[1] * f[7] + b[2] * f[8]) + (f[0] * b[6] + f[1] * b[7] + f[2] * b[8]));
+    }
+    X[(0 * RR + r) * LS + pt] = {W0, Q};
+    X[(1 * RR + r) * LS + pt] = {W1, W2};
+  }
+  if (MODE == RING_SYNTH) return;
+  __syncthreads();
+  // forward transforms of slots 0 and 1: thread (o, r); split the packed pair, scale by
+  // (2 - delta_k0)/N_phi and write the analysis inputs
+  if (tid < 2 * RR) {
+    const int o = tid / RR, r = tid % RR, th = th0 + r;
+    cz<T> z[N];
+    const cz<T>* xi = X + (o * RR + r) * LS;
+#pragma unroll
+    for (int p = 0; p < N; ++p) z[p] = xi[p];
+    fft_reg<T, N1, N2, -1>(z, fw);
+    if (th < nth) {
+      const int vr = vq * Np + rp;  // row (vec, r_p) of the analysis inputs
+      const long long Ma = (long long)4 * Np * g.vcap;
+#pragma unroll
+      for (int k = 0; k <= KMAX; ++k) {
+        if (k >= K1) continue;
+        const T sc = (k == 0 ? (T)1 : (T)2) / (T)N;
+        T ar, ai, br, bi;
+        if (k == 0) {
+          const cz<T> z0 = z[fft_pos<N1, N2>(0)];
+          ar = z0.re; ai = 0; br = z0.im; bi = 0;
+        } else {
+          const cz<T> zk = z[fft_pos<N1, N2>(k)], zm = z[fft_pos<N1, N2>(N - k)];
+          ar = (T)0.5 * (zk.re + zm.re);
+          ai = (T)0.5 * (zk.im - zm.im);
+          br = (T)0.5 * (zk.im + zm.im);
+          bi = (T)0.5 * (zm.re - zk.re);
+        }
+        ar *= sc; ai *= sc; br *= sc; bi *= sc;
+        if (o == 0) {  // (W_r, Q)
+          T* out = Fs + (long long)k * Ma * nth + ((long long)vr * 4) * nth + th;
+          out[0 * nth] = ar;
+          out[1 * nth] = ai;
+          out[2 * nth] = br;
+          out[3 * nth] = bi;
+        } else {       // (W_th, W_ph): dP rows (W_th, -W_ph); mPs rows (-i W_ph, -i W_th)
+          T* out = Fv + (long long)k * Ma * 2 * nth + ((long long)vr * 4) * 2 * nth + th;
+          out[0 * 2 * nth] = ar;
+          out[1 * 2 * nth] = ai;
+          out[2 * 2 * nth] = -br;
+          out[3 * 2 * nth] = -bi;
+          out[0 * 2 * nth + nth] = bi;
+          out[1 * 2 * nth + nth] = -br;
+          out[2 * 2 * nth + nth] = ai;
+          out[3 * 2 * nth + nth] = -ar;
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // K7: curl projections back to the N nodes and assembly of the right-hand side
 //   b = M u + dt (N(u) + Ra lam T/(r r_o) [f only] + C i m M u + c i m M X)
 // with M_e = Ek lam/r^2, M_f = -Ek lam/r^2 (D^2 - lam/r^2), M_T = 1, and boundary rows.
