@@ -67,7 +67,7 @@ struct WsLayout {
 };
 
 struct TabLayout {
-  std::vector<long long> synS, synV, anaS, anaV;
+  std::vector<long long> synS, synV, anaS, anaV, anfS, anfV;
   long long fw, total;
 };
 
@@ -96,8 +96,10 @@ struct sc_plan {
   TabLayout tl;
   WsLayout wl;
   DevBuf tab64, tab32, ws64, ws32;
-  DevBuf probs_syn, probs_ana, d_gsoff;
-  int nprob_syn = 0, nprob_ana = 0;
+  DevBuf probs_syn, probs_ana, probs_anf, d_gsoff;
+  int nprob_syn = 0, nprob_ana = 0, nprob_anf = 0;
+  int ana_ct = 0;                          // column tiles of the folded analysis kernel (0: GEMM path)
+  std::vector<sc::AnaProb> h_anf;
   std::vector<sc::SynProb> h_syn;
   std::vector<sc::GemmProb> h_ana;
   std::vector<long long> h_gsoff;         // per m: operand-order offsets of Gs, Gv
@@ -242,6 +244,8 @@ void build_tables(sc_plan* P) {
   t.synV.resize(K1);
   t.anaS.resize(K1);
   t.anaV.resize(K1);
+  t.anfS.resize(K1);
+  t.anfV.resize(K1);
   // synthesis tables on the northern nodes, in MFMA B-operand order: for the even l - m then
   // the odd ones, [column tile][k-step][lane], lane l of (c, s) holding
   // B[degree 4s + lane/16 of the part][node 16c' + lane%16], zero outside; vector tables have
@@ -254,6 +258,11 @@ void build_tables(sc_plan* P) {
     t.synV[k] = off; off += 2 * cth * (kse + kso) * 64;
     t.anaS[k] = off; off += nth * nl;
     t.anaV[k] = off; off += 2LL * nth * nl;
+    // folded analysis tables in MFMA B-operand order: [part][parity][column tile][k-step][lane],
+    // lane l of (c, s) holding table[degree 2 (16c + l%16) + parity][northern node 4s + l/16]
+    const long long ksa = (nth / 2 + 3) / 4, cte = ((nl + 1) / 2 + 15) / 16, cto = (nl / 2 + 15) / 16;
+    t.anfS[k] = off; off += (cte + cto) * ksa * 64;
+    t.anfV[k] = off; off += 2 * (cte + cto) * ksa * 64;
   }
   t.fw = off; off += 2LL * g.nphi;
   t.total = off;
@@ -284,6 +293,15 @@ void build_tables(sc_plan* P) {
         double wv = (l > 0) ? w / (2.0 * dm * lam) : 0.0;
         h[t.anaV[k] + (long long)il * 2 * nth + j] = wv * dP;
         h[t.anaV[k] + (long long)il * 2 * nth + nth + j] = wv * mP;
+        if (j < nth / 2) {
+          const long long ksa = (nth / 2 + 3) / 4, cte = ((nl + 1) / 2 + 15) / 16, cto = (nl / 2 + 15) / 16;
+          const int par = il & 1, ie = il >> 1;
+          const long long blk = (par ? cte : 0) + ie / 16;          // column tile within the part
+          const long long pos = (blk * ksa + j / 4) * 64 + (j % 4) * 16 + ie % 16;
+          h[t.anfS[k] + pos] = w * Pb / (2.0 * dm);
+          h[t.anfV[k] + pos] = wv * dP;
+          h[t.anfV[k] + (cte + cto) * ksa * 64 + pos] = wv * mP;
+        }
       }
     }
   }
@@ -345,11 +363,29 @@ void build_workspaces(sc_plan* P) {
     sc::GemmProb d{w.Fv + k * 4 * Np * V * 2 * nth, t.anaV[k], w.Av + 4 * Np * V * lb, (int)(4 * Np), nl, (int)(2 * nth), (int)(2 * nth), (int)(2 * nth), nl};
     P->h_ana.push_back(c);
     P->h_ana.push_back(d);
+    const int cte = ((nl + 1) / 2 + 15) / 16, cto = (nl / 2 + 15) / 16;
+    P->h_anf.push_back(sc::AnaProb{w.Fs + k * 4 * Np * V * nth, t.anfS[k], w.As + 4 * Np * V * lb, 1, nl, (int)nth, cte, cto,
+                                   (int)(4 * Np)});
+    P->h_anf.push_back(sc::AnaProb{w.Fv + k * 4 * Np * V * 2 * nth, t.anfV[k], w.Av + 4 * Np * V * lb, 2, nl, (int)(2 * nth),
+                                   cte, cto, (int)(4 * Np)});
   }
   upload(P->probs_syn, P->h_syn);
   upload(P->probs_ana, P->h_ana);
+  upload(P->probs_anf, P->h_anf);
   P->nprob_syn = (int)P->h_syn.size();
   P->nprob_ana = (int)P->h_ana.size();
+  P->nprob_anf = (int)P->h_anf.size();
+  {
+    // the smallest instantiated column-tile count that covers every m (0: keep the GEMM path)
+    int ct = 0;
+    for (const auto& a : P->h_anf) ct = std::max(ct, std::max(a.cte, a.cto));
+    P->ana_ct = 0;
+    for (int c : {1, 2, 3, 5, 8})
+      if (ct <= c) {
+        P->ana_ct = c;
+        break;
+      }
+  }
   const long long nr = P->n_real;
   P->bbuf.alloc(V * nr * sizeof(double));
   P->xbuf.alloc(V * nr * sizeof(double));
@@ -483,8 +519,24 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
     return;
   }
   HIPCHK(hipGetLastError());
-  nt = gemm_tiles<T>(P->h_ana, nvec);
-  {
+  if (P->ana_ct > 0) {
+    long long na = 0;
+    for (const auto& a : P->h_anf) na += sc::ana_tiles(a, nvec);
+    const size_t lds = sc::ana_lds_bytes<T>(g.nth);
+    Prof _p(P, SC_STAGE_LEGENDRE_ANAL, s);
+#define SC_ANAL(CT)                                                                                              \
+  hipLaunchKernelGGL((sc::k_anal<T, CT>), dim3((unsigned)na), dim3(256), lds, s, P->probs_anf.as<sc::AnaProb>(), \
+                     P->nprob_anf, nvec, g.nth, (const T*)ws, tab, ws)
+    switch (P->ana_ct) {
+      case 1: SC_ANAL(1); break;
+      case 2: SC_ANAL(2); break;
+      case 3: SC_ANAL(3); break;
+      case 5: SC_ANAL(5); break;
+      default: SC_ANAL(8); break;
+    }
+#undef SC_ANAL
+  } else {
+    nt = gemm_tiles<T>(P->h_ana, nvec);
     Prof _p(P, SC_STAGE_LEGENDRE_ANAL, s);
     hipLaunchKernelGGL(sc::k_gemm_batched<T>, dim3((unsigned)nt), dim3(256), 0, s, P->probs_ana.as<sc::GemmProb>(),
                        P->nprob_ana, nvec, (const T*)ws, tab, ws);
@@ -1038,6 +1090,20 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
       if (t32 > 64 * 1024) {
         attr((const void*)sc::k_T_solve<float, false, false>, t32);
         attr((const void*)sc::k_T_solve<float, false, true>, t32);
+      }
+      // folded analysis: LDS grows with N_theta; beyond the CU's 160 KiB the GEMM path is used
+      const size_t a64 = sc::ana_lds_bytes<double>(g.nth), a32 = sc::ana_lds_bytes<float>(g.nth);
+      if (a64 > 160 * 1024 || g.nth > 256) P->ana_ct = 0;   // the fold covers nth/2 <= 128 nodes
+      if (P->ana_ct > 0 && a64 > 64 * 1024) {
+        for (const void* f : {(const void*)sc::k_anal<double, 1>, (const void*)sc::k_anal<double, 2>,
+                              (const void*)sc::k_anal<double, 3>, (const void*)sc::k_anal<double, 5>,
+                              (const void*)sc::k_anal<double, 8>})
+          attr(f, a64);
+        if (a32 > 64 * 1024)
+          for (const void* f : {(const void*)sc::k_anal<float, 1>, (const void*)sc::k_anal<float, 2>,
+                                (const void*)sc::k_anal<float, 3>, (const void*)sc::k_anal<float, 5>,
+                                (const void*)sc::k_anal<float, 8>})
+            attr(f, a32);
       }
     }
     // deterministic contents for slots the solves never write (e, f at l = 0)

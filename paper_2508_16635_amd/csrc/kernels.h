@@ -426,6 +426,142 @@ __global__ void __launch_bounds__(256) k_synth(const SynProb* __restrict__ probs
 }
 
 // ------------------------------------------------------------------------------------------
+// K6: Legendre analysis per m with the equatorial symmetry.  The quadrature over the N_theta
+// Gauss-Legendre nodes pairs node j with its mirror nth-1-j (equal weights); Pbar and
+// m Pbar/sin have parity (-1)^(l-m) under the mirror, dPbar/dtheta the opposite one.  So the
+// even-degree outputs contract the folded inputs F(j) + s F(nth-1-j) and the odd-degree ones
+// F(j) - s F(nth-1-j) over the northern nodes only, s = +1 for Pbar and m Pbar/sin, -1 for
+// dPbar/dtheta: half the depth for each half of the degrees.
+// A workgroup owns ROWS rows (vec, r_p, q, Re/Im) of one m and part set (scalar: P; vector:
+// the dP part, then the m P/sin part, accumulated).  It folds each part of its rows into LDS
+// ([parity][row][node], rows padded to an odd stride), then wavefront w multiplies row tile
+// w%2 against all column tiles of parity w/2, the tables streamed from L2 in MFMA operand
+// order one k-step ahead.  Each input row is read once.
+struct AnaProb {
+  long long f_off;   // first input row of this m and part set (Fs or Fv), elements
+  long long t_off;   // tables of this m and part set: [part][parity][column tile][k-step][lane]
+  long long c_off;   // output (As or Av of this m), rows of nl degrees
+  int parts;         // 1 (scalar) or 2 (vector: dP, m P/sin)
+  int nl, ldf;       // degrees; input row length (nth or 2 nth)
+  int cte, cto;      // column tiles of the even and odd degrees
+  int rper;          // rows per vector (4 N_p)
+};
+constexpr int kAnaRows = 32;
+
+__host__ __device__ inline int ana_tiles(const AnaProb& p, int nvec) {
+  return (p.rper * nvec + kAnaRows - 1) / kAnaRows;
+}
+
+template <class T>
+__host__ __device__ inline size_t ana_lds_bytes(int nth) {
+  const int ksa = (nth / 2 + 3) / 4;
+  return sizeof(T) * 2 * kAnaRows * (4 * ksa + 1);
+}
+
+template <class T, int CT>
+__global__ void __launch_bounds__(256) k_anal(const AnaProb* __restrict__ probs, int nprob, int nvec, int nth,
+                                              const T* __restrict__ ws_in, const T* __restrict__ tab,
+                                              T* __restrict__ ws_out) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  extern __shared__ unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  int tile = blockIdx.x, p = 0;
+  for (; p < nprob; ++p) {
+    const int nt = ana_tiles(probs[p], nvec);
+    if (tile < nt) break;
+    tile -= nt;
+  }
+  if (p >= nprob) return;
+  const AnaProb pr = probs[p];
+  const int nh = nth / 2, KSa = (nh + 3) >> 2, pitch = 4 * KSa + 1;
+  const int rows = pr.rper * nvec, r0 = tile * kAnaRows;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+  const int rt = w & 1, par = w >> 1;
+  const int nct = par ? pr.cto : pr.cte;
+  acc_t acc[CT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[c][q] = (T)0;
+  for (int part = 0; part < pr.parts; ++part) {
+    // fold this part of the rows into [parity][row][node]: wave w takes rows w, w + 4, ...,
+    // lane l nodes l and l + 64 (nh <= 128); all loads of a thread are issued before use
+    const T sg = (pr.parts == 2 && part == 0) ? (T)-1 : (T)1;
+    constexpr int NI = kAnaRows / 4;
+    T va[NI][2], vb[NI][2];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int row = r0 + w + 4 * i;
+      const T* fr = ws_in + pr.f_off + (long long)row * pr.ldf + part * nth;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int j = l + 64 * h;
+        va[i][h] = (T)0;
+        vb[i][h] = (T)0;
+        if (row < rows && j < nh) {
+          va[i][h] = fr[j];
+          vb[i][h] = fr[nth - 1 - j];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int rr = w + 4 * i;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int j = l + 64 * h;
+        if (j < 4 * KSa) {
+          lds[rr * pitch + j] = va[i][h] + sg * vb[i][h];
+          lds[(kAnaRows + rr) * pitch + j] = va[i][h] - sg * vb[i][h];
+        }
+      }
+    }
+    __syncthreads();
+    if (nct > 0) {
+      const T* Ab = lds + (par * kAnaRows + 16 * rt + (l & 15)) * pitch + (l >> 4);
+      const T* Bb = tab + pr.t_off + (long long)(part * (pr.cte + pr.cto) + (par ? pr.cte : 0)) * KSa * 64 + l;
+      T a0, a1, b0[CT], b1[CT];
+      auto load = [&](int s, T& a, T (&b)[CT]) {
+        s = s < KSa ? s : KSa - 1;
+        a = Ab[4 * s];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) b[c] = (c < nct) ? Bb[((long long)c * KSa + s) * 64] : (T)0;
+      };
+      auto run = [&](T a, const T (&b)[CT]) {
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+          if (c < nct) acc[c] = Mfma<T>::step(a, b[c], acc[c]);
+      };
+      load(0, a0, b0);
+      for (int s = 0; s < KSa; s += 2) {
+        load(s + 1, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+        run(a0, b0);
+        if (s + 1 < KSa) {
+          load(s + 2, a0, b0);
+          __builtin_amdgcn_sched_barrier(0);
+          run(a1, b1);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // degree il = 2 (16 c + l%16) + parity
+  T* C = ws_out + pr.c_off;
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    if (c >= nct) continue;
+    const int il = 2 * (16 * c + (l & 15)) + par;
+    if (il >= pr.nl) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = r0 + 16 * rt + Mfma<T>::out_row(l, q);
+      if (row < rows) C[(long long)row * pr.nl + il] = acc[c][q];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // K6: batched contractions C[i][j] = sum_k A[i][k] B[j][k] on the matrix cores.
 // Output tile BM x 64 per workgroup (BM = 128 in FP32, 64 in FP64); the four wavefronts
 // form a 2 x 2 grid, each owning (BM/2) x 32 as (BM/32) x 2 MFMA 16x16 tiles.  k is staged
@@ -949,9 +1085,9 @@ __device__ inline void ring_field_coef(const T* g, int rs, T& fr, T& fi) {
 // the ring's column of the LDS copy, laid out [row][k][ring] (row stride rs, k stride ks).
 template <class T, int N, int QA>
 __device__ inline void ring_spectrum(cz<T> (&z)[N], const T* g, int rs, int ks, int K1) {
-  constexpr int KMAX = (N - 1) / 2;
+  constexpr int KM = (N - 1) / 3 + 1;   // K1 <= KM (N_phi >= 3K + 1)
 #pragma unroll
-  for (int k = 0; k <= KMAX; ++k) {
+  for (int k = 0; k < KM; ++k) {
     T ar = 0, ai = 0, br = 0, bi = 0;
     if (k < K1) {
       ring_field_coef<T, 2 * QA>(g + k * ks, rs, ar, ai);
@@ -978,7 +1114,6 @@ __global__ void __launch_bounds__(256) k_ring_reg(DevGrid g, int nvec, const T* 
                                                   T* __restrict__ Fs, T* __restrict__ Fv, double* __restrict__ base_out64,
                                                   float* __restrict__ base_out32) {
   constexpr int N = N1 * N2, RR = ring_reg_rings<T>(), LS = N + 1;  // LS: LDS stride of one (slot, ring)
-  constexpr int KMAX = (N - 1) / 2;
   constexpr int NPT = (RR * N + 255) / 256;                         // product points per thread
   // the fields of the transforms; first the copy of the Legendre sums [26 rows][K1][RR rings]
   __shared__ cz<T> X[5 * RR * LS];
@@ -1108,7 +1243,7 @@ __global__ void __launch_bounds__(256) k_ring_reg(DevGrid g, int nvec, const T* 
       const int vr = vq * Np + rp;  // row (vec, r_p) of the analysis inputs
       const long long Ma = (long long)4 * Np * g.vcap;
 #pragma unroll
-      for (int k = 0; k <= KMAX; ++k) {
+      for (int k = 0; k < (N - 1) / 3 + 1; ++k) {
         if (k >= K1) continue;
         const T sc = (k == 0 ? (T)1 : (T)2) / (T)N;
         T ar, ai, br, bi;
