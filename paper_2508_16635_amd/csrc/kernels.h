@@ -90,6 +90,26 @@ __device__ inline int xcd_linear_id() {
   return x * q + min(x, r) + (b >> 3);
 }
 
+// Cooperative copy into LDS by a 256-thread workgroup: element i (i = tid, tid + 256, ... <
+// total) is ld(i) stored by st(i, value).  The loads of CH consecutive rounds are all issued
+// before the first store, so a thread waits for memory once per CH elements, not per element.
+template <int CH, class V, class LoadF, class StoreF>
+__device__ inline void staged_copy(int total, LoadF ld, StoreF st) {
+  for (int b = threadIdx.x; b < total; b += CH * 256) {
+    V v[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = b + u * 256;
+      v[u] = (i < total) ? ld(i) : V(0);
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = b + u * 256;
+      if (i < total) st(i, v[u]);
+    }
+  }
+}
+
 // Matrix-core (MFMA) 16x16x4 tile per wavefront: D[16][16] += A[16][4] B[4][16].
 // Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; element q of its 4-vector holds
 // D[out_row(l, q)][l % 16], with out_row = 4 (l / 16) + q for FP32 and l / 16 + 4 q for FP64
@@ -520,27 +540,28 @@ __global__ void __launch_bounds__(256) k_anal(const AnaProb* __restrict__ probs,
     if (nct > 0) {
       const T* Ab = lds + (par * kAnaRows + 16 * rt + (l & 15)) * pitch + (l >> 4);
       const T* Bb = tab + pr.t_off + (long long)(part * (pr.cte + pr.cto) + (par ? pr.cte : 0)) * KSa * 64 + l;
-      T a0, a1, b0[CT], b1[CT];
+      // operands of four k-steps in flight: slot u holds k-step s + u while it is multiplied and
+      // is then refilled with k-step s + u + 4
+      constexpr int PD = 4;
+      T aq[PD], bq[PD][CT];
       auto load = [&](int s, T& a, T (&b)[CT]) {
         s = s < KSa ? s : KSa - 1;
         a = Ab[4 * s];
 #pragma unroll
         for (int c = 0; c < CT; ++c) b[c] = (c < nct) ? Bb[((long long)c * KSa + s) * 64] : (T)0;
       };
-      auto run = [&](T a, const T (&b)[CT]) {
 #pragma unroll
-        for (int c = 0; c < CT; ++c)
-          if (c < nct) acc[c] = Mfma<T>::step(a, b[c], acc[c]);
-      };
-      load(0, a0, b0);
-      for (int s = 0; s < KSa; s += 2) {
-        load(s + 1, a1, b1);
-        __builtin_amdgcn_sched_barrier(0);
-        run(a0, b0);
-        if (s + 1 < KSa) {
-          load(s + 2, a0, b0);
+      for (int u = 0; u < PD; ++u) load(u, aq[u], bq[u]);
+      for (int s = 0; s < KSa; s += PD) {
+#pragma unroll
+        for (int u = 0; u < PD; ++u) {
           __builtin_amdgcn_sched_barrier(0);
-          run(a1, b1);
+          if (s + u < KSa) {
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+              if (c < nct) acc[c] = Mfma<T>::step(aq[u], bq[u][c], acc[c]);
+          }
+          load(s + u + PD, aq[u], bq[u]);
         }
       }
     }
@@ -1323,32 +1344,35 @@ __global__ void __launch_bounds__(256) k_project_rhs(DevGrid g, PhysParams ph, i
   double cval = 0.0;
   if (!STEP && J >= 0) cval = v[(long long)vec * ldv + J];
   // analysis outputs on the N_p nodes: column (c, t) = c * 8 + t
-  for (int idx = threadIdx.x; idx < 4 * rowsP * 16; idx += blockDim.x) {
-    const int col = idx & 15, rp = (idx >> 4) % rowsP, which = idx / (16 * rowsP);
-    const int c = col >> 3, t = col & 7;
-    T val = (T)0;
-    if (rp < Np && t < nt) {
-      // which: 0 Tor (vector slot 2), 1 W_r (scalar slot 0), 2 S (vector slot 0), 3 Q (scalar slot 2)
-      const T* src = (which == 1 || which == 3) ? as : av;
-      const int slot = (which == 0 || which == 3) ? 2 : 0;
-      const long long row = ((long long)vec * Np + rp) * 4 + slot + c;
-      val = src[row * nl + il0 + t];
-    }
-    Xa[idx] = val;
-  }
+  staged_copy<10, T>(
+      4 * rowsP * 16,
+      [&](int idx) -> T {
+        const int col = idx & 15, rp = (idx >> 4) % rowsP, which = idx / (16 * rowsP);
+        const int c = col >> 3, t = col & 7;
+        if (rp >= Np || t >= nt) return (T)0;
+        // which: 0 Tor (vector slot 2), 1 W_r (scalar slot 0), 2 S (vector slot 0), 3 Q (scalar slot 2)
+        const T* src = (which == 1 || which == 3) ? as : av;
+        const int slot = (which == 0 || which == 3) ? 2 : 0;
+        const long long row = ((long long)vec * Np + rp) * 4 + slot + c;
+        return src[row * nl + il0 + t];
+      },
+      [&](int idx, T val) { Xa[idx] = val; });
   // cleaned state u at the N nodes (coalesced over (j, c) of one profile)
-  for (int idx = threadIdx.x; idx < 3 * kPT * 2 * rowsN; idx += blockDim.x) {
-    const int cj = idx % (2 * rowsN), t = (idx / (2 * rowsN)) % kPT, f = idx / (2 * rowsN * kPT);
-    const int jj = cj >> 1, c = cj & 1;
-    double val = 0.0;
-    if (jj < N && t < nt) {
-      const long long o = 2LL * ((long long)N * ((long long)f * g.S + lm0 + t) + jj) + c;
-      const int l = m + il0 + t;
-      val = vb[o];
-      if (o == J || (c == 1 && k == 0) || (f < 2 && l == 0)) val = 0.0;
-    }
-    Xu[(f * rowsN + jj) * 16 + c * 8 + t] = val;
-  }
+  staged_copy<10, double>(
+      3 * kPT * 2 * rowsN,
+      [&](int idx) -> double {
+        const int cj = idx % (2 * rowsN), t = (idx / (2 * rowsN)) % kPT, f = idx / (2 * rowsN * kPT);
+        const int jj = cj >> 1, c = cj & 1;
+        if (jj >= N || t >= nt) return 0.0;
+        const long long o = 2LL * ((long long)N * ((long long)f * g.S + lm0 + t) + jj) + c;
+        const int l = m + il0 + t;
+        if (o == J || (c == 1 && k == 0) || (f < 2 && l == 0)) return 0.0;
+        return vb[o];
+      },
+      [&](int idx, double val) {
+        const int cj = idx % (2 * rowsN), t = (idx / (2 * rowsN)) % kPT, f = idx / (2 * rowsN * kPT);
+        Xu[(f * rowsN + (cj >> 1)) * 16 + (cj & 1) * 8 + t] = val;
+      });
   __syncthreads();
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   if (w >= RTN) return;
@@ -1858,20 +1882,25 @@ __global__ void __launch_bounds__(256) k_residual64(DevGrid g, PhysParams ph, in
   const int lmb = g.lmbase[k];
   const long long ld = 6LL * N * g.S;
   const double* x = xvec + (long long)vec * ld;
-  for (int idx = threadIdx.x; idx < 3 * 8 * 2 * rowsN; idx += blockDim.x) {
-    const int cj = idx % (2 * rowsN), t = (idx / (2 * rowsN)) % 8, f = idx / (2 * rowsN * 8);
-    const int jj = cj >> 1, c = cj & 1;
-    const int il = il0 - 1 + t;
-    double val = 0.0;
-    if (jj < N && il >= 0 && il < nl)
-      val = x[2LL * ((long long)N * ((long long)f * g.S + lmb + il) + jj) + c];
-    const int fs = (f == 2) ? 3 : f;
-    xs[fs][jj][c * 8 + t] = val;
-    if (f == 1) {
-      const double r = (jj < N) ? g.r[jj] : 1.0;
-      xs[2][jj][c * 8 + t] = val / (r * r);
-    }
-  }
+  staged_copy<9, double>(
+      3 * 8 * 2 * rowsN,
+      [&](int idx) -> double {
+        const int cj = idx % (2 * rowsN), t = (idx / (2 * rowsN)) % 8, f = idx / (2 * rowsN * 8);
+        const int jj = cj >> 1, c = cj & 1;
+        const int il = il0 - 1 + t;
+        if (jj >= N || il < 0 || il >= nl) return 0.0;
+        return x[2LL * ((long long)N * ((long long)f * g.S + lmb + il) + jj) + c];
+      },
+      [&](int idx, double val) {
+        const int cj = idx % (2 * rowsN), t = (idx / (2 * rowsN)) % 8, f = idx / (2 * rowsN * 8);
+        const int jj = cj >> 1, c = cj & 1;
+        const int fs = (f == 2) ? 3 : f;
+        xs[fs][jj][c * 8 + t] = val;
+        if (f == 1) {
+          const double r = (jj < N) ? g.r[jj] : 1.0;
+          xs[2][jj][c * 8 + t] = val / (r * r);
+        }
+      });
   __syncthreads();
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int col = l & 15, c = col >> 3, t = col & 7;
