@@ -31,13 +31,11 @@ PEAK = {"hbm": 8000.0, "fp32": 157.3, "fp64": 78.6}   # GB/s, TFLOP/s (MI355X pu
 
 # single-kernel stages of the mixed path at this workload and the kernel each one launches
 SINGLE_KERNEL_STAGES = {
-    "ring": "sc::k_ring<float, 0>",
+    "ring": "sc::k_ring_reg<float, 0, 8, 5>",          # N_phi = 40 = 8 x 5
     "legendre_synth": "sc::k_synth<float>",
-    "legendre_anal": "sc::k_gemm_batched<float>",
+    "legendre_anal": "sc::k_anal<float, 5>",           # up to 5 column tiles per degree parity
     "radial_prep": "sc::k_radial_prep<float, 3>",
     "project_rhs": "sc::k_project_rhs<float, false, 3>",
-    "residual64": "sc::k_residual64<3>",
-    "finalize": "sc::k_finalize",
 }
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic_L128_N48_nvec16.json")
 
@@ -77,8 +75,10 @@ def stage_work(lay, nvec, prec_bytes, factor_bytes, nblocks, refine):
     fl = sum(2.0 * Np * nvec * n * (6 * nth + 10 * 2 * nth) for n in nl) / 2
     by = prec_bytes * (Np * nvec * 16 * S + (K1 * Np * nvec * (6 * nth + 20 * nth)) + 3 * nth * S)
     w["legendre_synth"] = (fl, by)
-    fl = sum(2.0 * Np * nvec * n * (4 * nth + 4 * 2 * nth) for n in nl)
-    by = prec_bytes * (K1 * Np * nvec * (4 * nth + 8 * nth) + Np * nvec * 8 * S + 3 * nth * S)
+    # Legendre analysis: (4 Np nvec x nth) . (nth x nl) and (4 Np nvec x 2 nth) . (2 nth x nl) per m,
+    # counted with the mirror folding (each degree parity contracts over the northern half)
+    fl = sum(2.0 * Np * nvec * n * (4 * nth + 4 * 2 * nth) for n in nl) / 2
+    by = prec_bytes * (K1 * Np * nvec * (4 * nth + 8 * nth) + Np * nvec * 8 * S + 3 * nth * S // 2)
     w["legendre_anal"] = (fl, by)
     rings = Np * nth * nvec
     w["ring"] = (rings * (2.0 * 13 * K1 * nphi * 2 + 60 * nphi),
