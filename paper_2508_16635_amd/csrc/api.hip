@@ -438,7 +438,8 @@ bool launch_ring_reg(int nphi, dim3 grid, hipStream_t s, const sc::DevGrid& dg, 
   // N_phi >= 3K + 1
   if (3 * dg.K + 1 > nphi) return false;
 #define SC_RING_REG(N1, N2)                                                                                   \
-  hipLaunchKernelGGL((sc::k_ring_reg<T, MODE, N1, N2>), grid, dim3(256), 0, s, dg, nvec, Cs, Cv, base, fw, Ek, Fs, \
+  hipLaunchKernelGGL((sc::k_ring_reg<T, MODE, N1, N2>), grid, dim3(sc::ring_reg_threads<T>()), 0, s, dg, nvec, Cs, Cv, \
+                     base, fw, Ek, Fs, \
                      Fv, b64, b32);                                                                           \
   return true
   switch (nphi) {

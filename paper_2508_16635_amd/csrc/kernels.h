@@ -542,7 +542,7 @@ __global__ void __launch_bounds__(256) k_anal(const AnaProb* __restrict__ probs,
       const T* Bb = tab + pr.t_off + (long long)(part * (pr.cte + pr.cto) + (par ? pr.cte : 0)) * KSa * 64 + l;
       // operands of four k-steps in flight: slot u holds k-step s + u while it is multiplied and
       // is then refilled with k-step s + u + 4
-      constexpr int PD = 4;
+      constexpr int PD = sizeof(T) == 4 ? 2 : 4;
       T aq[PD], bq[PD][CT];
       auto load = [&](int s, T& a, T (&b)[CT]) {
         s = s < KSa ? s : KSa - 1;
@@ -1123,19 +1123,25 @@ __device__ inline void ring_spectrum(cz<T> (&z)[N], const T* g, int rs, int ks, 
   }
 }
 
-// Rings per workgroup of k_ring_reg.
+// Rings and threads per workgroup of k_ring_reg.
 template <class T>
 __host__ __device__ constexpr int ring_reg_rings() {
   return sizeof(T) == 4 ? 32 : 16;
 }
+template <class T>
+__host__ __device__ constexpr int ring_reg_threads() {
+  return 256;
+}
 
 template <class T, int MODE, int N1, int N2>
-__global__ void __launch_bounds__(256) k_ring_reg(DevGrid g, int nvec, const T* __restrict__ Cs, const T* __restrict__ Cv,
+__global__ void __launch_bounds__(ring_reg_threads<T>()) k_ring_reg(DevGrid g, int nvec, const T* __restrict__ Cs, const T* __restrict__ Cv,
                                                   const T* __restrict__ base, const T* __restrict__ fw, T Ek,
                                                   T* __restrict__ Fs, T* __restrict__ Fv, double* __restrict__ base_out64,
                                                   float* __restrict__ base_out32) {
   constexpr int N = N1 * N2, RR = ring_reg_rings<T>(), LS = N + 1;  // LS: LDS stride of one (slot, ring)
-  constexpr int NPT = (RR * N + 255) / 256;                         // product points per thread
+  constexpr int NT = ring_reg_threads<T>();                         // threads per workgroup
+  static_assert(5 * RR <= NT && NT % 64 == 0, "a thread per inverse transform");
+  constexpr int NPT = (RR * N + NT - 1) / NT;                       // product points per thread
   // the fields of the transforms; first the copy of the Legendre sums [26 rows][K1][RR rings]
   __shared__ cz<T> X[5 * RR * LS];
   T* Gl = reinterpret_cast<T*>(X);
@@ -1149,7 +1155,7 @@ __global__ void __launch_bounds__(256) k_ring_reg(DevGrid g, int nvec, const T* 
   if (MODE == RING_LINEAR) {
 #pragma unroll
     for (int u = 0; u < NPT; ++u) {
-      const int idx = tid + 256 * u, r = idx % RR, pt = idx / RR, th = th0 + r;
+      const int idx = tid + NT * u, r = idx % RR, pt = idx / RR, th = th0 + r;
 #pragma unroll
       for (int q = 0; q < 9; ++q)
         bpre[u][q] = (pt < N && th < nth) ? base[(((long long)rp * 9 + q) * N + pt) * nth + th] : (T)0;
@@ -1160,7 +1166,7 @@ __global__ void __launch_bounds__(256) k_ring_reg(DevGrid g, int nvec, const T* 
   // lies wholly inside or wholly beyond the last node).  K1 <= KM = (N - 1)/3 + 1, so the
   // loop has a compile-time trip count and all loads of a thread are issued together.
   {
-    constexpr int EPL = 8 / sizeof(T), PPR = RR / EPL, JS = 256 / PPR;   // elements per piece, pieces per run
+    constexpr int EPL = 8 / sizeof(T), PPR = RR / EPL, JS = NT / PPR;    // elements per piece, pieces per run
     constexpr int KM = (N - 1) / 3 + 1, NIT = (26 * KM + JS - 1) / JS;
     typedef T pT __attribute__((ext_vector_type(EPL)));
     const long long kS = (long long)6 * Np * g.vcap * nth, kV = (long long)10 * Np * g.vcap * 2 * nth;
@@ -1213,7 +1219,7 @@ __global__ void __launch_bounds__(256) k_ring_reg(DevGrid g, int nvec, const T* 
   // pointwise products at (ring, point), in place as slot 0 = W_r + i Q, slot 1 = W_th + i W_ph
 #pragma unroll
   for (int u = 0; u < NPT; ++u) {
-    const int idx = tid + 256 * u, r = idx % RR, pt = idx / RR, th = th0 + r;
+    const int idx = tid + NT * u, r = idx % RR, pt = idx / RR, th = th0 + r;
     if (pt >= N) continue;
     T f[10];
 #pragma unroll
