@@ -100,7 +100,7 @@ __device__ inline void staged_copy(int total, LoadF ld, StoreF st) {
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
       const int i = b + u * 256;
-      v[u] = (i < total) ? ld(i) : V(0);
+      v[u] = (i < total) ? ld(i) : V{};
     }
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
@@ -1571,11 +1571,16 @@ struct ChainOps {
 template <class F>
 __device__ inline void stage_x(const cpx<F>* __restrict__ W, int N, int wcap, long long blk, int v0, cpx<F>* xa,
                                cpx<F>* xb_zero) {
-  for (int idx = threadIdx.x; idx < 64 * kVG; idx += kSolveThreads) {
-    const int r = idx / kVG, c = idx % kVG;
-    xa[idx] = (r < N && blk >= 0) ? W[(blk * N + r) * wcap + v0 + c] : cpx<F>{0, 0};
-    if (xb_zero) xb_zero[idx] = cpx<F>{0, 0};
-  }
+  staged_copy<64 * kVG / kSolveThreads, cpx<F>>(
+      64 * kVG,
+      [&](int idx) -> cpx<F> {
+        const int r = idx / kVG, c = idx % kVG;
+        return (r < N && blk >= 0) ? W[(blk * N + r) * wcap + v0 + c] : cpx<F>{0, 0};
+      },
+      [&](int idx, cpx<F> v) {
+        xa[idx] = v;
+        if (xb_zero) xb_zero[idx] = cpx<F>{0, 0};
+      });
 }
 
 // Sequential walk: x_0 = W[blk(0)], then for t = 1..nsteps: W[blk(t)] = W[blk(t)] +
@@ -1642,16 +1647,16 @@ __global__ void __launch_bounds__(kSolveThreads) k_cs_rhs(DevGrid g, int nvec, c
   if (op.active()) op.load_frag(Sinv, blk, S);
   const long long ld = 6LL * N * g.S;
   const long long o = 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + blk_lm[blk]));
-  for (int idx = threadIdx.x; idx < 64 * kVG; idx += kSolveThreads) {
-    const int r = idx / kVG, c = idx % kVG;
-    cpx<F> v = {0, 0};
-    if (r < N && c < nv) {
-      const double* bp = bvec + (long long)(v0 + c) * ld + o + 2 * r;
-      const F sc = Rg[(long long)blk * N + r] * sr[(long long)blk * N + r];
-      v = {sc * (F)bp[0], sc * (F)bp[1]};
-    }
-    xs[idx] = v;
-  }
+  staged_copy<64 * kVG / kSolveThreads, cpx<F>>(
+      64 * kVG,
+      [&](int idx) -> cpx<F> {
+        const int r = idx / kVG, c = idx % kVG;
+        if (r >= N || c >= nv) return cpx<F>{0, 0};
+        const double* bp = bvec + (long long)(v0 + c) * ld + o + 2 * r;
+        const F sc = Rg[(long long)blk * N + r] * sr[(long long)blk * N + r];
+        return cpx<F>{sc * (F)bp[0], sc * (F)bp[1]};
+      },
+      [&](int idx, cpx<F> v) { xs[idx] = v; });
   __syncthreads();
   if (op.active()) {
     typename Ops::acc_t yr, yi;
@@ -1768,31 +1773,49 @@ __global__ void __launch_bounds__(kSolveThreads) k_cs_out(DevGrid g, int nvec, c
     op.load_w(W, blk, v0, S);
   }
   if (nx >= 0) stage_x<F>(W, N, g.wcap, nx, v0, xs, nullptr);
+  // the output's other operands (scaling, accumulated x, u) load before the product
+  const long long ld = 6LL * N * g.S;
+  const int lm = blk_lm[blk];
+  const long long o = 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + lm));
+  double cq[4], xa[4][2], ua[4][2];
+  if (op.active()) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = op.row(q);
+      const bool ok = r < N && op.col < nv;
+      const long long oo = o + 2 * r;
+      cq[q] = ok ? (double)Cg[(long long)blk * N + r] : 0.0;
+      xa[q][0] = xa[q][1] = ua[q][0] = ua[q][1] = 0.0;
+      if (ACC && ok) {
+        const double* xp = xvec + (long long)(v0 + op.col) * ld + oo;
+        xa[q][0] = xp[0];
+        xa[q][1] = xp[1];
+      }
+      if (FIN && ok) {
+        const double* vp = fo.v + (long long)(v0 + op.col) * fo.ldv + oo;
+        ua[q][0] = (oo == fo.J) ? 0.0 : vp[0];
+        ua[q][1] = (oo + 1 == fo.J) ? 0.0 : vp[1];
+      }
+    }
+  }
   __syncthreads();
   if (op.active()) {
     typename Ops::acc_t yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
     if (nx >= 0) op.apply(S, xs, yr, yi);
-    const long long ld = 6LL * N * g.S;
-    const int lm = blk_lm[blk];
-    const long long o = 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + lm));
     const bool mzero = (g.lm_k[lm] == 0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int r = op.row(q);
       if (r < N && op.col < nv) {
-        const double c = (double)Cg[(long long)blk * N + r];
-        double* xp = xvec + (long long)(v0 + op.col) * ld + o + 2 * r;
-        double x0 = c * (double)(S.w[q].re + yr[q]), x1 = c * (double)(S.w[q].im + yi[q]);
-        if (ACC) {
-          x0 += xp[0];
-          x1 += xp[1];
-        }
+        const double c = cq[q];
+        const long long oo = o + 2 * r;
+        double x0 = c * (double)(S.w[q].re + yr[q]) + xa[q][0], x1 = c * (double)(S.w[q].im + yi[q]) + xa[q][1];
         if (FIN) {
-          const long long oo = o + 2 * r;
           double* yp = fo.y + (long long)(v0 + op.col) * fo.ldy + oo;
-          yp[0] = final_value(fo, v0 + op.col, oo, x0);
-          yp[1] = final_value(fo, v0 + op.col, oo + 1, mzero ? 0.0 : x1);
+          yp[0] = x0 - ua[q][0];
+          yp[1] = (mzero ? 0.0 : x1) - ua[q][1];
         } else {
+          double* xp = xvec + (long long)(v0 + op.col) * ld + oo;
           xp[0] = x0;
           xp[1] = x1;
         }
