@@ -1102,17 +1102,34 @@ __device__ inline void ring_field_coef(const T* g, int rs, T& fr, T& fi) {
   else { fr = 0; fi = 0; }
 }
 
+// Rows of the LDS copy of the sums that field f combines, F = alpha z1 + beta i z2 (z = Re row,
+// Re row + 1), as in ring_field_coef: {z1 row, alpha, z2 row, beta} for f = 0..9.
+__device__ constexpr int kRingFieldRows[10][2] = {{0, 0}, {6, 18}, {8, 16}, {2, 2}, {10, 22}, {12, 20}, {4, 4}, {14, 14}, {24, 24}, {0, 0}};
+__device__ constexpr float kRingFieldCoef[10][2] = {{1, 0}, {1, 1}, {-1, 1}, {1, 0}, {1, 1}, {-1, 1}, {1, 0}, {1, 0}, {0, 1}, {0, 0}};
+
 // Spectrum of transform q = fields (2q, 2q+1) of one ring, packed as in k_ring; g points at
-// the ring's column of the LDS copy, laid out [row][k][ring] (row stride rs, k stride ks).
-template <class T, int N, int QA>
-__device__ inline void ring_spectrum(cz<T> (&z)[N], const T* g, int rs, int ks, int K1) {
+// the ring's column of the LDS copy, laid out [row][k][ring] (row stride rs, k stride ks).  The
+// same code serves every q (row indices and coefficients per lane), so the lanes of a wave that
+// hold different transforms do not diverge.
+template <class T, int N>
+__device__ inline void ring_spectrum(cz<T> (&z)[N], const T* g, int rs, int ks, int K1, int q) {
   constexpr int KM = (N - 1) / 3 + 1;   // K1 <= KM (N_phi >= 3K + 1)
+  const int fa = 2 * q, fb = 2 * q + 1;
+  const T* a1 = g + kRingFieldRows[fa][0] * rs;
+  const T* a2 = g + kRingFieldRows[fa][1] * rs;
+  const T* b1 = g + kRingFieldRows[fb][0] * rs;
+  const T* b2 = g + kRingFieldRows[fb][1] * rs;
+  const T aal = kRingFieldCoef[fa][0], abe = kRingFieldCoef[fa][1];
+  const T bal = kRingFieldCoef[fb][0], bbe = kRingFieldCoef[fb][1];
 #pragma unroll
   for (int k = 0; k < KM; ++k) {
     T ar = 0, ai = 0, br = 0, bi = 0;
     if (k < K1) {
-      ring_field_coef<T, 2 * QA>(g + k * ks, rs, ar, ai);
-      ring_field_coef<T, 2 * QA + 1>(g + k * ks, rs, br, bi);
+      const int o = k * ks;
+      ar = aal * a1[o] - abe * a2[o + rs];
+      ai = aal * a1[o + rs] + abe * a2[o];
+      br = bal * b1[o] - bbe * b2[o + rs];
+      bi = bal * b1[o + rs] + bbe * b2[o];
     }
     if (k == 0) {
       z[0] = {ar, br};
@@ -1163,33 +1180,37 @@ __global__ void __launch_bounds__(ring_reg_threads<T>()) k_ring_reg(DevGrid g, i
   }
   // copy of the sums of this workgroup's rings into LDS, [26 rows][K1][RR rings]: every (row, k)
   // is a run of RR consecutive theta, read as 8-byte pieces (nth and th0 are even, so a piece
-  // lies wholly inside or wholly beyond the last node).  K1 <= KM = (N - 1)/3 + 1, so the
-  // loop has a compile-time trip count and all loads of a thread are issued together.
+  // lies wholly inside or wholly beyond the last node).  Thread (group, piece) owns rows group,
+  // group + NG, ... and reads them for every k (K1 <= KM = (N - 1)/3 + 1, a compile-time trip
+  // count), all loads issued before the first store.
   {
-    constexpr int EPL = 8 / sizeof(T), PPR = RR / EPL, JS = NT / PPR;    // elements per piece, pieces per run
-    constexpr int KM = (N - 1) / 3 + 1, NIT = (26 * KM + JS - 1) / JS;
+    constexpr int EPL = 8 / sizeof(T), PPR = RR / EPL, NG = NT / PPR;   // elements per piece, pieces per run, groups
+    constexpr int KM = (N - 1) / 3 + 1, NRW = (26 + NG - 1) / NG;      // rows per group
     typedef T pT __attribute__((ext_vector_type(EPL)));
     const long long kS = (long long)6 * Np * g.vcap * nth, kV = (long long)10 * Np * g.vcap * 2 * nth;
     const long long sS = (long long)Np * nth, sV = (long long)Np * 2 * nth;
-    const int e = tid % PPR, j0 = tid / PPR, th = th0 + e * EPL;
+    const int e = tid % PPR, grp = tid / PPR, th = th0 + e * EPL;
     const bool ok = th < nth;
     const T* cs = Cs + ((long long)vq * 6 * Np + rp) * nth + th;
     const T* cv = Cv + ((long long)vq * 10 * Np + rp) * 2 * nth + th;
-    pT val[NIT];
+    pT val[NRW][KM];
 #pragma unroll
-    for (int i = 0; i < NIT; ++i) {
-      const int rk = j0 + i * JS, row = rk / KM, k = rk - row * KM;
-      val[i] = pT{};
-      if (row < 26 && k < K1 && ok) {
-        const T* src = row < 6 ? cs + row * sS + k * kS
-                               : (row < 16 ? cv + (row - 6) * sV + k * kV : cv + (row - 16) * sV + nth + k * kV);
-        val[i] = *reinterpret_cast<const pT*>(src);
+    for (int i = 0; i < NRW; ++i) {
+      const int row = grp + i * NG;
+      const T* src = row < 6 ? cs + row * sS : (row < 16 ? cv + (row - 6) * sV : cv + (row - 16) * sV + nth);
+      const long long kst = row < 6 ? kS : kV;
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        val[i][k] = pT{};
+        if (row < 26 && k < K1 && ok) val[i][k] = *reinterpret_cast<const pT*>(src + k * kst);
       }
     }
 #pragma unroll
-    for (int i = 0; i < NIT; ++i) {
-      const int rk = j0 + i * JS, row = rk / KM, k = rk - row * KM;
-      if (row < 26 && k < K1) *reinterpret_cast<pT*>(Gl + (row * K1 + k) * RR + e * EPL) = val[i];
+    for (int i = 0; i < NRW; ++i) {
+      const int row = grp + i * NG;
+#pragma unroll
+      for (int k = 0; k < KM; ++k)
+        if (row < 26 && k < K1) *reinterpret_cast<pT*>(Gl + (row * K1 + k) * RR + e * EPL) = val[i][k];
     }
   }
   __syncthreads();
@@ -1199,14 +1220,7 @@ __global__ void __launch_bounds__(ring_reg_threads<T>()) k_ring_reg(DevGrid g, i
     cz<T> z[N];
 #pragma unroll
     for (int p = 0; p < N; ++p) z[p] = {(T)0, (T)0};
-    if (q < 5) {
-      const T* gr = Gl + r;
-      if (q == 0) ring_spectrum<T, N, 0>(z, gr, K1 * RR, RR, K1);
-      else if (q == 1) ring_spectrum<T, N, 1>(z, gr, K1 * RR, RR, K1);
-      else if (q == 2) ring_spectrum<T, N, 2>(z, gr, K1 * RR, RR, K1);
-      else if (q == 3) ring_spectrum<T, N, 3>(z, gr, K1 * RR, RR, K1);
-      else ring_spectrum<T, N, 4>(z, gr, K1 * RR, RR, K1);
-    }
+    if (q < 5) ring_spectrum<T, N>(z, Gl + r, K1 * RR, RR, K1, q);
     __syncthreads();   // the copy of the sums is dead from here on; X reuses its space
     if (q < 5) {
       fft_reg<T, N1, N2, 1>(z, fw);
