@@ -12,6 +12,7 @@
 // operands contiguous in k (gemm_batched).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 namespace sc {
 
@@ -88,6 +89,19 @@ __device__ inline int xcd_linear_id() {
   const int b = blockIdx.x, G = gridDim.x;
   const int x = b & 7, q = G >> 3, r = G & 7;
   return x * q + min(x, r) + (b >> 3);
+}
+
+// Calls f(std::integral_constant<int, n>) for the runtime count 1 <= n <= NMAX (wave-uniform), so
+// that loops over n tiles have a compile-time trip count and no per-tile branch.
+template <int NMAX, class Fn>
+__device__ inline void with_count(int n, Fn&& f) {
+  if constexpr (NMAX >= 1) {
+    if (n == NMAX) {
+      f(std::integral_constant<int, NMAX>());
+      return;
+    }
+    with_count<NMAX - 1>(n, f);
+  }
 }
 
 // Cooperative copy into LDS by a 256-thread workgroup: element i (i = tid, tid + 256, ... <
@@ -540,30 +554,32 @@ __global__ void __launch_bounds__(256) k_anal(const AnaProb* __restrict__ probs,
     if (nct > 0) {
       const T* Ab = lds + (par * kAnaRows + 16 * rt + (l & 15)) * pitch + (l >> 4);
       const T* Bb = tab + pr.t_off + (long long)(part * (pr.cte + pr.cto) + (par ? pr.cte : 0)) * KSa * 64 + l;
-      // operands of four k-steps in flight: slot u holds k-step s + u while it is multiplied and
-      // is then refilled with k-step s + u + 4
+      // operands of PD k-steps are in flight: slot u holds k-step s + u while it is multiplied
+      // and is then refilled with k-step s + u + PD
       constexpr int PD = sizeof(T) == 4 ? 2 : 4;
-      T aq[PD], bq[PD][CT];
-      auto load = [&](int s, T& a, T (&b)[CT]) {
-        s = s < KSa ? s : KSa - 1;
-        a = Ab[4 * s];
+      with_count<CT>(nct, [&](auto ncc) {
+        constexpr int NC = decltype(ncc)::value;
+        T aq[PD], bq[PD][NC];
+        auto load = [&](int s, T& a, T (&b)[NC]) {
+          s = s < KSa ? s : KSa - 1;
+          a = Ab[4 * s];
 #pragma unroll
-        for (int c = 0; c < CT; ++c) b[c] = (c < nct) ? Bb[((long long)c * KSa + s) * 64] : (T)0;
-      };
+          for (int c = 0; c < NC; ++c) b[c] = Bb[((long long)c * KSa + s) * 64];
+        };
 #pragma unroll
-      for (int u = 0; u < PD; ++u) load(u, aq[u], bq[u]);
-      for (int s = 0; s < KSa; s += PD) {
+        for (int u = 0; u < PD; ++u) load(u, aq[u], bq[u]);
+        for (int s = 0; s < KSa; s += PD) {
 #pragma unroll
-        for (int u = 0; u < PD; ++u) {
-          __builtin_amdgcn_sched_barrier(0);
-          if (s + u < KSa) {
+          for (int u = 0; u < PD; ++u) {
+            __builtin_amdgcn_sched_barrier(0);
+            if (s + u < KSa) {
 #pragma unroll
-            for (int c = 0; c < CT; ++c)
-              if (c < nct) acc[c] = Mfma<T>::step(aq[u], bq[u][c], acc[c]);
+              for (int c = 0; c < NC; ++c) acc[c] = Mfma<T>::step(aq[u], bq[u][c], acc[c]);
+            }
+            load(s + u + PD, aq[u], bq[u]);
           }
-          load(s + u + PD, aq[u], bq[u]);
         }
-      }
+      });
     }
     __syncthreads();
   }
