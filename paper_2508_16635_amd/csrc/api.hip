@@ -96,7 +96,8 @@ struct sc_plan {
   TabLayout tl;
   WsLayout wl;
   DevBuf tab64, tab32, ws64, ws32;
-  DevBuf probs_syn, probs_ana, probs_anf, d_gsoff;
+  DevBuf probs_syn, probs_ana, probs_anf, d_gsoff, d_lmb8;
+  std::vector<int> h_lmb8;                 // per m: first tile-padded degree slot of the analysis outputs
   int nprob_syn = 0, nprob_ana = 0, nprob_anf = 0;
   int ana_ct = 0;                          // column tiles of the folded analysis kernel (0: GEMM path)
   std::vector<sc::AnaProb> h_anf;
@@ -184,6 +185,8 @@ struct sc_plan {
     g.DpT = d_DpT.as<double>();
     g.ptiles = d_ptiles.as<int2>();
     g.nptiles = nptiles;
+    g.ana_tiled = ana_ct > 0 ? 1 : 0;
+    g.lmbase8 = d_lmb8.as<int>();
     return g;
   }
   sc::PhysParams pp() const {
@@ -338,8 +341,17 @@ void build_workspaces(sc_plan* P) {
   w.Cv = off; off += K1 * 10 * Np * V * 2 * nth;
   w.Fs = off; off += K1 * 4 * Np * V * nth;
   w.Fv = off; off += K1 * 4 * Np * V * 2 * nth;
-  w.As = off; off += 4 * Np * V * S;
-  w.Av = off; off += 4 * Np * V * S;
+  // analysis outputs sized for both layouts: natural (S degrees) and tiled (degrees of every m
+  // padded to a multiple of 8)
+  P->h_lmb8.assign(K1, 0);
+  long long S8 = 0;
+  for (int k = 0; k < K1; ++k) {
+    P->h_lmb8[k] = (int)S8;
+    S8 += (g.nl[k] + 7) / 8 * 8;
+  }
+  upload(P->d_lmb8, P->h_lmb8);
+  w.As = off; off += 4 * Np * V * std::max(S, S8);
+  w.Av = off; off += 4 * Np * V * std::max(S, S8);
   w.total = off;
   P->ws64.alloc(off * sizeof(double));
   P->ws32.alloc(off * sizeof(float));
@@ -364,10 +376,11 @@ void build_workspaces(sc_plan* P) {
     P->h_ana.push_back(c);
     P->h_ana.push_back(d);
     const int cte = ((nl + 1) / 2 + 15) / 16, cto = (nl / 2 + 15) / 16;
-    P->h_anf.push_back(sc::AnaProb{w.Fs + k * 4 * Np * V * nth, t.anfS[k], w.As + 4 * Np * V * lb, 1, nl, (int)nth, cte, cto,
-                                   (int)(4 * Np)});
-    P->h_anf.push_back(sc::AnaProb{w.Fv + k * 4 * Np * V * 2 * nth, t.anfV[k], w.Av + 4 * Np * V * lb, 2, nl, (int)(2 * nth),
-                                   cte, cto, (int)(4 * Np)});
+    const long long lb8 = P->h_lmb8[k];
+    P->h_anf.push_back(sc::AnaProb{w.Fs + k * 4 * Np * V * nth, t.anfS[k], w.As + 4 * Np * V * lb8, 1, nl, (int)nth, cte, cto,
+                                   (int)(4 * Np), (int)(4 * Np * V)});
+    P->h_anf.push_back(sc::AnaProb{w.Fv + k * 4 * Np * V * 2 * nth, t.anfV[k], w.Av + 4 * Np * V * lb8, 2, nl, (int)(2 * nth),
+                                   cte, cto, (int)(4 * Np), (int)(4 * Np * V)});
   }
   upload(P->probs_syn, P->h_syn);
   upload(P->probs_ana, P->h_ana);
@@ -523,7 +536,7 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
   if (P->ana_ct > 0) {
     long long na = 0;
     for (const auto& a : P->h_anf) na += sc::ana_tiles(a, nvec);
-    const size_t lds = sc::ana_lds_bytes<T>(g.nth);
+    const size_t lds = sc::ana_lds_bytes<T>(g.nth, g.L + 1);
     Prof _p(P, SC_STAGE_LEGENDRE_ANAL, s);
 #define SC_ANAL(CT)                                                                                              \
   hipLaunchKernelGGL((sc::k_anal<T, CT>), dim3((unsigned)na), dim3(256), lds, s, P->probs_anf.as<sc::AnaProb>(), \
@@ -1093,7 +1106,7 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
         attr((const void*)sc::k_T_solve<float, false, true>, t32);
       }
       // folded analysis: LDS grows with N_theta; beyond the CU's 160 KiB the GEMM path is used
-      const size_t a64 = sc::ana_lds_bytes<double>(g.nth), a32 = sc::ana_lds_bytes<float>(g.nth);
+      const size_t a64 = sc::ana_lds_bytes<double>(g.nth, g.L + 1), a32 = sc::ana_lds_bytes<float>(g.nth, g.L + 1);
       if (a64 > 160 * 1024 || g.nth > 256) P->ana_ct = 0;   // the fold covers nth/2 <= 128 nodes
       if (P->ana_ct > 0 && a64 > 64 * 1024) {
         for (const void* f : {(const void*)sc::k_anal<double, 1>, (const void*)sc::k_anal<double, 2>,

@@ -6,7 +6,8 @@
 //   synthesis input  Gs[k][(vec, q<3, ri, rp)][l-m]  Gv[k][(vec, q<5, ri, rp)][l-m]  (operand order)
 //   synthesis output Cs[k][(vec, q<3, ri, rp)][theta]  Cv[k][(vec, q<5, ri, rp)][2 nth]
 //   analysis input   Fs[k][(vec, rp, q<2, ri)][theta]  Fv[k][(vec, rp, q<2, ri)][2 nth]
-//   analysis output  As[k][(vec, rp, q<2, ri)][l-m]    Av[k][(vec, rp, q<2, ri)][l-m]
+//   analysis output  As[k][(l-m)/8][(vec, rp, q<2, ri)][(l-m)%8]  (likewise Av; the GEMM
+//                    fallback writes As[k][(vec, rp, q<2, ri)][l-m])
 //   base fields      base[rp][field<9][phi][theta]
 // The Legendre transforms are the contractions C[i][j] = sum_k A[i][k] B[j][k] with both
 // operands contiguous in k (gemm_batched).
@@ -62,6 +63,10 @@ struct DevGrid {
   const double* D2F;  // D^2 (N x N), operand order
   int fft_nr;         // azimuthal FFT: number of passes and their radices (each 2, 3, 4 or 5)
   int fft_r[8];
+  // analysis outputs: tiled ([m][l-m tile of 8][row][8], m blocks at lmbase8) when ana_tiled,
+  // else [m][row][l-m] at lmbase
+  int ana_tiled;
+  const int* lmbase8;
 };
 
 struct PhysParams {
@@ -479,6 +484,7 @@ struct AnaProb {
   int nl, ldf;       // degrees; input row length (nth or 2 nth)
   int cte, cto;      // column tiles of the even and odd degrees
   int rper;          // rows per vector (4 N_p)
+  int rcap;          // rows of an output tile of 8 degrees (4 N_p times the vector capacity)
 };
 constexpr int kAnaRows = 32;
 
@@ -487,9 +493,11 @@ __host__ __device__ inline int ana_tiles(const AnaProb& p, int nvec) {
 }
 
 template <class T>
-__host__ __device__ inline size_t ana_lds_bytes(int nth) {
+__host__ __device__ inline size_t ana_lds_bytes(int nth, int nlmax) {
+  // the folded rows, then (reused) the output block of kAnaRows rows x nlmax degrees padded to 8
   const int ksa = (nth / 2 + 3) / 4;
-  return sizeof(T) * 2 * kAnaRows * (4 * ksa + 1);
+  const size_t fold = (size_t)2 * kAnaRows * (4 * ksa + 1), out = (size_t)kAnaRows * ((nlmax + 7) & ~7);
+  return sizeof(T) * (fold > out ? fold : out);
 }
 
 template <class T, int CT>
@@ -583,18 +591,24 @@ __global__ void __launch_bounds__(256) k_anal(const AnaProb* __restrict__ probs,
     }
     __syncthreads();
   }
-  // degree il = 2 (16 c + l%16) + parity
-  T* C = ws_out + pr.c_off;
+  // degree il = 2 (16 c + l%16) + parity; the block [row][il] is gathered in LDS (the fold
+  // buffer is free) and written in tiles of 8 degrees, [il/8][row][il%8], each tile of the
+  // block one contiguous run
+  const int nlp = (pr.nl + 7) & ~7;
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
     if (c >= nct) continue;
     const int il = 2 * (16 * c + (l & 15)) + par;
     if (il >= pr.nl) continue;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int row = r0 + 16 * rt + Mfma<T>::out_row(l, q);
-      if (row < rows) C[(long long)row * pr.nl + il] = acc[c][q];
-    }
+    for (int q = 0; q < 4; ++q) lds[(16 * rt + Mfma<T>::out_row(l, q)) * nlp + il] = acc[c][q];
+  }
+  __syncthreads();
+  T* C = ws_out + pr.c_off;
+  const int nrow = min(kAnaRows, rows - r0);
+  for (int idx = threadIdx.x; idx < kAnaRows * nlp; idx += 256) {
+    const int it = idx / (8 * kAnaRows), rem = idx - it * 8 * kAnaRows, row = rem >> 3, e = rem & 7;
+    if (row < nrow && it * 8 + e < pr.nl) C[((long long)it * pr.rcap + r0 + row) * 8 + e] = lds[row * nlp + it * 8 + e];
   }
 }
 
@@ -1373,8 +1387,9 @@ __global__ void __launch_bounds__(256) k_project_rhs(DevGrid g, PhysParams ph, i
   const int nt = min(kPT, nl - il0);
   const int lm0 = g.lmbase[k] + il0;
   const long long Ma = 4LL * Np * g.vcap;
-  const T* as = As + Ma * g.lmbase[k];
-  const T* av = Av + Ma * g.lmbase[k];
+  const long long mb = Ma * (g.ana_tiled ? g.lmbase8[k] : g.lmbase[k]);
+  const T* as = As + mb;
+  const T* av = Av + mb;
   const double* vb = v + (long long)vec * ldv;
   double* bb = b + (long long)vec * 6LL * N * g.S;
   double cval = 0.0;
@@ -1390,7 +1405,7 @@ __global__ void __launch_bounds__(256) k_project_rhs(DevGrid g, PhysParams ph, i
         const T* src = (which == 1 || which == 3) ? as : av;
         const int slot = (which == 0 || which == 3) ? 2 : 0;
         const long long row = ((long long)vec * Np + rp) * 4 + slot + c;
-        return src[row * nl + il0 + t];
+        return g.ana_tiled ? src[((il0 >> 3) * Ma + row) * 8 + t] : src[row * nl + il0 + t];
       },
       [&](int idx, T val) { Xa[idx] = val; });
   // cleaned state u at the N nodes (coalesced over (j, c) of one profile)
