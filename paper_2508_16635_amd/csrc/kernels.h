@@ -109,21 +109,22 @@ __device__ inline void with_count(int n, Fn&& f) {
   }
 }
 
-// Cooperative copy into LDS by a 256-thread workgroup: element i (i = tid, tid + 256, ... <
-// total) is ld(i) stored by st(i, value).  The loads of CH consecutive rounds are all issued
-// before the first store, so a thread waits for memory once per CH elements, not per element.
+// Cooperative copy into LDS by the workgroup: element i (i = tid, tid + blockDim, ... < total)
+// is ld(i) stored by st(i, value).  The loads of CH consecutive rounds are all issued before the
+// first store, so a thread waits for memory once per CH elements, not per element.
 template <int CH, class V, class LoadF, class StoreF>
 __device__ inline void staged_copy(int total, LoadF ld, StoreF st) {
-  for (int b = threadIdx.x; b < total; b += CH * 256) {
+  const int nt = blockDim.x;
+  for (int b = threadIdx.x; b < total; b += CH * nt) {
     V v[CH];
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-      const int i = b + u * 256;
+      const int i = b + u * nt;
       v[u] = (i < total) ? ld(i) : V{};
     }
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-      const int i = b + u * 256;
+      const int i = b + u * nt;
       if (i < total) st(i, v[u]);
     }
   }

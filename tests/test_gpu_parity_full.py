@@ -134,3 +134,33 @@ def test_jvp_batch_limits(sc):
         plan.jvp(V[:1], V[:1].clone(), sc.SC_FP64)
     assert ei.value.code == 2
 
+
+
+def test_wide_theta_fallback_paths(sc):
+    """N_theta = 258 > 256: the analysis runs on the GEMM path with the untiled output layout,
+    and N_phi = 8 takes the Stockham ring in both precisions; FP64 and mixed jvp against the
+    oracle."""
+    L, M, m0, N = 171, 171, 80, 10
+    plan = sc.Plan(L, M, m0, N, Ek=1e-3, Ra=60.0, Pr=1.0, dt=5.0, nvec_max=3)
+    plan.factor()
+    assert plan.layout["ntheta"] > 256
+    ora = Problem(L, M, m0, N, Ek=1e-3, Ra=60.0, Pr=1.0, dt=5.0)
+    lay = si.Layout(L, M, m0, N)
+    X = si.random_state(lay, 5, amp=(1e-2, 1e-2, 1e-2), p=2) + ora.conductive_state()
+    J = si.default_phase_slot(lay, X)
+    plan.set_base(_dev(X), 0.2, J)
+    ora.set_base(X, 0.2, J)
+    V = si.random_vectors(lay, [11, 12, 13])
+    Vd = _dev(V)
+    Y64 = torch.empty_like(Vd)
+    Y32 = torch.empty_like(Vd)
+    plan.jvp(Vd, Y64, sc.SC_FP64)
+    plan.jvp(Vd, Y32, sc.SC_MIXED)
+    torch.cuda.synchronize()
+    y64, y32 = Y64.cpu().numpy(), Y32.cpu().numpy()
+    for i in range(3):
+        ref = ora.jvp(V[i])
+        e64, e32 = _rel(y64[i], ref), _rel(y32[i], ref)
+        print(f"L={L} N_theta={plan.layout['ntheta']} vec {i}: fp64 {e64:.2e} mixed {e32:.2e}", flush=True)
+        assert e64 < 1e-11
+        assert e32 < 1e-6
