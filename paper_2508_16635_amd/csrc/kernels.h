@@ -1198,15 +1198,16 @@ __global__ void __launch_bounds__(ring_reg_threads<T>()) k_ring_reg(DevGrid g, i
   const int lid = xcd_linear_id();
   const int tile = lid % ntile, rv = lid / ntile, rp = rv / nvec, vq = rv - rp * nvec;
   const int th0 = tile * RR, tid = threadIdx.x;
-  // base fields of this thread's product points, loaded first so they arrive during the FFTs
+  // base fields of this thread's product points, loaded first so they arrive during the FFTs;
+  // points of rings beyond the last node read that node (their results are never written)
   T bpre[NPT][9];
   if (MODE == RING_LINEAR) {
 #pragma unroll
     for (int u = 0; u < NPT; ++u) {
-      const int idx = tid + NT * u, r = idx % RR, pt = idx / RR, th = th0 + r;
+      const int idx = tid + NT * u, r = idx % RR, pt = min(idx / RR, N - 1), th = min(th0 + r, nth - 1);
+      const T* bp = base + ((long long)rp * 9 * N + pt) * nth + th;
 #pragma unroll
-      for (int q = 0; q < 9; ++q)
-        bpre[u][q] = (pt < N && th < nth) ? base[(((long long)rp * 9 + q) * N + pt) * nth + th] : (T)0;
+      for (int q = 0; q < 9; ++q) bpre[u][q] = bp[(long long)q * N * nth];
     }
   }
   // copy of the sums of this workgroup's rings into LDS, [26 rows][K1][RR rings]: every (row, k)
@@ -1220,21 +1221,20 @@ __global__ void __launch_bounds__(ring_reg_threads<T>()) k_ring_reg(DevGrid g, i
     typedef T pT __attribute__((ext_vector_type(EPL)));
     const long long kS = (long long)6 * Np * g.vcap * nth, kV = (long long)10 * Np * g.vcap * 2 * nth;
     const long long sS = (long long)Np * nth, sV = (long long)Np * 2 * nth;
-    const int e = tid % PPR, grp = tid / PPR, th = th0 + e * EPL;
-    const bool ok = th < nth;
+    // unconditional loads at clamped positions: a piece beyond the last node reads the last
+    // one (that ring's results are never written), rows >= 26 and k >= K1 repeat valid ones
+    // and are not stored
+    const int e = tid % PPR, grp = tid / PPR, th = min(th0 + e * EPL, nth - EPL);
     const T* cs = Cs + ((long long)vq * 6 * Np + rp) * nth + th;
     const T* cv = Cv + ((long long)vq * 10 * Np + rp) * 2 * nth + th;
     pT val[NRW][KM];
 #pragma unroll
     for (int i = 0; i < NRW; ++i) {
-      const int row = grp + i * NG;
+      const int row = min(grp + i * NG, 25);
       const T* src = row < 6 ? cs + row * sS : (row < 16 ? cv + (row - 6) * sV : cv + (row - 16) * sV + nth);
       const long long kst = row < 6 ? kS : kV;
 #pragma unroll
-      for (int k = 0; k < KM; ++k) {
-        val[i][k] = pT{};
-        if (row < 26 && k < K1 && ok) val[i][k] = *reinterpret_cast<const pT*>(src + k * kst);
-      }
+      for (int k = 0; k < KM; ++k) val[i][k] = *reinterpret_cast<const pT*>(src + min(k, K1 - 1) * kst);
     }
 #pragma unroll
     for (int i = 0; i < NRW; ++i) {
@@ -1314,8 +1314,12 @@ __global__ void __launch_bounds__(ring_reg_threads<T>()) k_ring_reg(DevGrid g, i
     if (th < nth) {
       const int vr = vq * Np + rp;  // row (vec, r_p) of the analysis inputs
       const long long Ma = (long long)4 * Np * g.vcap;
+      // output rows of harmonic k: running pointers, advanced by one harmonic block per k
+      T* os = Fs + ((long long)vr * 4) * nth + th;
+      T* ov = Fv + ((long long)vr * 4) * 2 * nth + th;
+      const long long dS = Ma * nth, dV = Ma * 2 * nth;
 #pragma unroll
-      for (int k = 0; k < (N - 1) / 3 + 1; ++k) {
+      for (int k = 0; k < (N - 1) / 3 + 1; ++k, os += dS, ov += dV) {
         if (k >= K1) continue;
         const T sc = (k == 0 ? (T)1 : (T)2) / (T)N;
         T ar, ai, br, bi;
@@ -1331,21 +1335,19 @@ __global__ void __launch_bounds__(ring_reg_threads<T>()) k_ring_reg(DevGrid g, i
         }
         ar *= sc; ai *= sc; br *= sc; bi *= sc;
         if (o == 0) {  // (W_r, Q)
-          T* out = Fs + (long long)k * Ma * nth + ((long long)vr * 4) * nth + th;
-          out[0 * nth] = ar;
-          out[1 * nth] = ai;
-          out[2 * nth] = br;
-          out[3 * nth] = bi;
+          os[0 * nth] = ar;
+          os[1 * nth] = ai;
+          os[2 * nth] = br;
+          os[3 * nth] = bi;
         } else {       // (W_th, W_ph): dP rows (W_th, -W_ph); mPs rows (-i W_ph, -i W_th)
-          T* out = Fv + (long long)k * Ma * 2 * nth + ((long long)vr * 4) * 2 * nth + th;
-          out[0 * 2 * nth] = ar;
-          out[1 * 2 * nth] = ai;
-          out[2 * 2 * nth] = -br;
-          out[3 * 2 * nth] = -bi;
-          out[0 * 2 * nth + nth] = bi;
-          out[1 * 2 * nth + nth] = -br;
-          out[2 * 2 * nth + nth] = ai;
-          out[3 * 2 * nth + nth] = -ar;
+          ov[0 * 2 * nth] = ar;
+          ov[1 * 2 * nth] = ai;
+          ov[2 * 2 * nth] = -br;
+          ov[3 * 2 * nth] = -bi;
+          ov[0 * 2 * nth + nth] = bi;
+          ov[1 * 2 * nth + nth] = -br;
+          ov[2 * 2 * nth + nth] = ai;
+          ov[3 * 2 * nth + nth] = -ar;
         }
       }
     }
