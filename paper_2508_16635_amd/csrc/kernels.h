@@ -1596,21 +1596,22 @@ struct ChainOps {
 #pragma unroll
     for (int q = 0; q < 4; ++q) S.w[q] = W[(blk * N + rowc[q]) * wcap + v0 + col];
   }
-  // acc = M x for this wave's row tile; x = 64 x 16 complex in LDS
+  // acc = M x for this wave's row tile; x = 64 x 16 complex in LDS.  M = A + iB, x = c + id in
+  // three real products (Gauss): P1 = A c, P2 = B d, P3 = (A + B)(c + d); Re = P1 - P2,
+  // Im = P3 - P1 - P2.
   __device__ inline void apply(const Set& S, const cpx<F>* x, acc_t& yr, acc_t& yi) const {
-    acc_t r0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0}, i0 = {0, 0, 0, 0}, i1 = {0, 0, 0, 0};
+    acc_t p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const cpx<F> xv = x[(4 * ks + (l >> 4)) * kVG + col];
-      r0 = Mfma<F>::step(S.ar[ks], xv.re, r0);
-      r1 = Mfma<F>::step(-S.ai[ks], xv.im, r1);
-      i0 = Mfma<F>::step(S.ar[ks], xv.im, i0);
-      i1 = Mfma<F>::step(S.ai[ks], xv.re, i1);
+      p1 = Mfma<F>::step(S.ar[ks], xv.re, p1);
+      p2 = Mfma<F>::step(S.ai[ks], xv.im, p2);
+      p3 = Mfma<F>::step(S.ar[ks] + S.ai[ks], xv.re + xv.im, p3);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      yr[q] = r0[q] + r1[q];
-      yi[q] = i0[q] + i1[q];
+      yr[q] = p1[q] - p2[q];
+      yi[q] = p3[q] - p1[q] - p2[q];
     }
   }
 };
