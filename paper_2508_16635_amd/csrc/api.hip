@@ -187,6 +187,7 @@ struct sc_plan {
     g.nptiles = nptiles;
     g.ana_tiled = ana_ct > 0 ? 1 : 0;
     g.lmbase8 = d_lmb8.as<int>();
+    g.fv_dp_only = g.ana_tiled;   // the folded analysis derives the m P/sin half
     return g;
   }
   sc::PhysParams pp() const {

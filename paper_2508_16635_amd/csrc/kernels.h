@@ -67,6 +67,10 @@ struct DevGrid {
   // else [m][row][l-m] at lmbase
   int ana_tiled;
   const int* lmbase8;
+  // the vector analysis inputs hold only their dP half: the m P/sin half of a row group
+  // (-D3, D2, D1, -D0) is a signed permutation of its dP half (D0..D3), and the folded analysis
+  // takes it from there
+  int fv_dp_only;
 };
 
 struct PhysParams {
@@ -473,10 +477,12 @@ __global__ void __launch_bounds__(256) k_synth(const SynProb* __restrict__ probs
 // F(j) - s F(nth-1-j) over the northern nodes only, s = +1 for Pbar and m Pbar/sin, -1 for
 // dPbar/dtheta: half the depth for each half of the degrees.
 // A workgroup owns ROWS rows (vec, r_p, q, Re/Im) of one m and part set (scalar: P; vector:
-// the dP part, then the m P/sin part, accumulated).  It folds each part of its rows into LDS
-// ([parity][row][node], rows padded to an odd stride), then wavefront w multiplies row tile
-// w%2 against all column tiles of parity w/2, the tables streamed from L2 in MFMA operand
-// order one k-step ahead.  Each input row is read once.
+// the dP part, then the m P/sin part, accumulated).  It folds its rows into LDS ([parity][row]
+// [node], rows padded to an odd stride), then wavefront w multiplies row tile w%2 against all
+// column tiles of parity w/2, the tables streamed from L2 in MFMA operand order one k-step
+// ahead.  Only the dP half of a vector row is stored (the ring kernels skip the other half when
+// this kernel runs): the m P/sin operand is a signed row permutation of the dP fold.  Each
+// input row is read once.
 struct AnaProb {
   long long f_off;   // first input row of this m and part set (Fs or Fv), elements
   long long t_off;   // tables of this m and part set: [part][parity][column tile][k-step][lane]
@@ -527,41 +533,51 @@ __global__ void __launch_bounds__(256) k_anal(const AnaProb* __restrict__ probs,
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[c][q] = (T)0;
   for (int part = 0; part < pr.parts; ++part) {
-    // fold this part of the rows into [parity][row][node]: wave w takes rows w, w + 4, ...,
-    // lane l nodes l and l + 64 (nh <= 128); all loads of a thread are issued before use
-    const T sg = (pr.parts == 2 && part == 0) ? (T)-1 : (T)1;
-    constexpr int NI = kAnaRows / 4;
-    T va[NI][2], vb[NI][2];
+    // the m P/sin part (part 1) of the vector rows is not stored: within a group of four rows
+    // it is (-D3, D2, D1, -D0) of the dP part D, and its fold (sign +1) is the dP fold (sign -1)
+    // with the parities exchanged, so its operand is read from the dP fold at the permuted row
+    // of the other parity, with that sign
+    const bool derived = part == 1;
+    if (!derived) {
+      // fold this part of the rows into [parity][row][node]: wave w takes rows w, w + 4, ...,
+      // lane l nodes l and l + 64 (nh <= 128); all loads of a thread are issued before use
+      const T sg = (pr.parts == 2 && part == 0) ? (T)-1 : (T)1;
+      constexpr int NI = kAnaRows / 4;
+      T va[NI][2], vb[NI][2];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-      const int row = r0 + w + 4 * i;
-      const T* fr = ws_in + pr.f_off + (long long)row * pr.ldf + part * nth;
+      for (int i = 0; i < NI; ++i) {
+        const int row = r0 + w + 4 * i;
+        const T* fr = ws_in + pr.f_off + (long long)row * pr.ldf + part * nth;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int j = l + 64 * h;
-        va[i][h] = (T)0;
-        vb[i][h] = (T)0;
-        if (row < rows && j < nh) {
-          va[i][h] = fr[j];
-          vb[i][h] = fr[nth - 1 - j];
+        for (int h = 0; h < 2; ++h) {
+          const int j = l + 64 * h;
+          va[i][h] = (T)0;
+          vb[i][h] = (T)0;
+          if (row < rows && j < nh) {
+            va[i][h] = fr[j];
+            vb[i][h] = fr[nth - 1 - j];
+          }
         }
       }
-    }
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-      const int rr = w + 4 * i;
+      for (int i = 0; i < NI; ++i) {
+        const int rr = w + 4 * i;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int j = l + 64 * h;
-        if (j < 4 * KSa) {
-          lds[rr * pitch + j] = va[i][h] + sg * vb[i][h];
-          lds[(kAnaRows + rr) * pitch + j] = va[i][h] - sg * vb[i][h];
+        for (int h = 0; h < 2; ++h) {
+          const int j = l + 64 * h;
+          if (j < 4 * KSa) {
+            lds[rr * pitch + j] = va[i][h] + sg * vb[i][h];
+            lds[(kAnaRows + rr) * pitch + j] = va[i][h] - sg * vb[i][h];
+          }
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
     if (nct > 0) {
-      const T* Ab = lds + (par * kAnaRows + 16 * rt + (l & 15)) * pitch + (l >> 4);
+      const int R = 16 * rt + (l & 15), q4 = R & 3;
+      const T* Ab = derived ? lds + ((1 - par) * kAnaRows + (R - q4) + (3 - q4)) * pitch + (l >> 4)
+                            : lds + (par * kAnaRows + R) * pitch + (l >> 4);
+      const T asg = (derived && (q4 == 0 || q4 == 3)) ? (T)-1 : (T)1;
       const T* Bb = tab + pr.t_off + (long long)(part * (pr.cte + pr.cto) + (par ? pr.cte : 0)) * KSa * 64 + l;
       // operands of PD k-steps are in flight: slot u holds k-step s + u while it is multiplied
       // and is then refilled with k-step s + u + PD
@@ -571,7 +587,7 @@ __global__ void __launch_bounds__(256) k_anal(const AnaProb* __restrict__ probs,
         T aq[PD], bq[PD][NC];
         auto load = [&](int s, T& a, T (&b)[NC]) {
           s = s < KSa ? s : KSa - 1;
-          a = Ab[4 * s];
+          a = asg * Ab[4 * s];
 #pragma unroll
           for (int c = 0; c < NC; ++c) b[c] = Bb[((long long)c * KSa + s) * 64];
         };
@@ -590,7 +606,7 @@ __global__ void __launch_bounds__(256) k_anal(const AnaProb* __restrict__ probs,
         }
       });
     }
-    __syncthreads();
+    if (!(part == 0 && pr.parts == 2)) __syncthreads();   // the fold stays for the derived part
   }
   // degree il = 2 (16 c + l%16) + parity; the block [row][il] is gathered in LDS (the fold
   // buffer is free) and written in tiles of 8 degrees, [il/8][row][il%8], each tile of the
@@ -1060,10 +1076,12 @@ __global__ void __launch_bounds__(kRingThreads) k_ring(DevGrid g, int nvec, int 
       out[1 * 2 * nth] = ai;
       out[2 * 2 * nth] = -br;
       out[3 * 2 * nth] = -bi;
-      out[0 * 2 * nth + nth] = bi;
-      out[1 * 2 * nth + nth] = -br;
-      out[2 * 2 * nth + nth] = ai;
-      out[3 * 2 * nth + nth] = -ar;
+      if (!g.fv_dp_only) {
+        out[0 * 2 * nth + nth] = bi;
+        out[1 * 2 * nth + nth] = -br;
+        out[2 * 2 * nth + nth] = ai;
+        out[3 * 2 * nth + nth] = -ar;
+      }
     }
   }
 }
@@ -1344,10 +1362,12 @@ __global__ void __launch_bounds__(ring_reg_threads<T>()) k_ring_reg(DevGrid g, i
           ov[1 * 2 * nth] = ai;
           ov[2 * 2 * nth] = -br;
           ov[3 * 2 * nth] = -bi;
-          ov[0 * 2 * nth + nth] = bi;
-          ov[1 * 2 * nth + nth] = -br;
-          ov[2 * 2 * nth + nth] = ai;
-          ov[3 * 2 * nth + nth] = -ar;
+          if (!g.fv_dp_only) {
+            ov[0 * 2 * nth + nth] = bi;
+            ov[1 * 2 * nth + nth] = -br;
+            ov[2 * 2 * nth + nth] = ai;
+            ov[3 * 2 * nth + nth] = -ar;
+          }
         }
       }
     }
