@@ -326,7 +326,7 @@ void build_workspaces(sc_plan* P) {
   long long off = 0;
   // synthesis inputs in MFMA A-operand order per m: [row tile][k-step][lane]
   P->rtcS = (int)((6 * Np * V + 15) / 16);
-  P->rtcV = (int)((10 * Np * V + 15) / 16);
+  P->rtcV = (int)((12 * Np * V + 15) / 16);   // three groups of four rows per (vec, r_p)
   P->h_gsoff.assign(2 * K1, 0);
   long long gsz = 0, gvz = 0;
   for (int k = 0; k < K1; ++k) {
@@ -339,7 +339,7 @@ void build_workspaces(sc_plan* P) {
   w.Gs = off; off += gsz;   // h_gsoff: relative to Gs and Gv
   w.Gv = off; off += gvz;
   w.Cs = off; off += K1 * 6 * Np * V * nth;
-  w.Cv = off; off += K1 * 10 * Np * V * 2 * nth;
+  w.Cv = off; off += K1 * 12 * Np * V * nth;
   w.Fs = off; off += K1 * 4 * Np * V * nth;
   w.Fv = off; off += K1 * 4 * Np * V * 2 * nth;
   // analysis outputs sized for both layouts: natural (S degrees) and tiled (degrees of every m
@@ -370,7 +370,7 @@ void build_workspaces(sc_plan* P) {
     const int kse = ((nl + 1) / 2 + 3) / 4, kso = (nl / 2 + 3) / 4, cth = (int)((nth / 2 + 15) / 16);
     P->h_syn.push_back(sc::SynProb{w.Gs + P->h_gsoff[2 * k], t.synS[k], w.Cs + k * 6 * Np * V * nth, (int)(6 * Np), kse,
                                    kso, cth, 1, (int)nth});
-    P->h_syn.push_back(sc::SynProb{w.Gv + P->h_gsoff[2 * k + 1], t.synV[k], w.Cv + k * 10 * Np * V * 2 * nth, (int)(10 * Np),
+    P->h_syn.push_back(sc::SynProb{w.Gv + P->h_gsoff[2 * k + 1], t.synV[k], w.Cv + k * 12 * Np * V * nth, (int)(12 * Np),
                                    kse, kso, cth, 2, (int)nth});
     sc::GemmProb c{w.Fs + k * 4 * Np * V * nth, t.anaS[k], w.As + 4 * Np * V * lb, (int)(4 * Np), nl, (int)nth, (int)nth, (int)nth, nl};
     sc::GemmProb d{w.Fv + k * 4 * Np * V * 2 * nth, t.anaV[k], w.Av + 4 * Np * V * lb, (int)(4 * Np), nl, (int)(2 * nth), (int)(2 * nth), (int)(2 * nth), nl};

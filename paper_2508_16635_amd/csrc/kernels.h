@@ -197,6 +197,17 @@ __device__ inline void mfma_f64_products(const double* const (&Mp)[NPR], const T
 }
 
 // ------------------------------------------------------------------------------------------
+// Rows of the vector synthesis operand.  The five complex vector profiles of one (vec, r_p),
+// (S_u, T_u, S_w, T_w, T), form three groups of four real rows: (S_u, T_u), (S_w, T_w) and
+// (T, two zero rows); group G = (3 vec + g) N_p + r_p.  Member q of group G sits in the 16-row
+// tile G/4 at the row where the MFMA output layout places element q of lane group G%4, so
+// that one lane of the synthesis receives all four members of a group and can combine them
+// into the physical fields (U_th, U_ph), (w_th, w_ph) or (dT/dth, dT/dph) in registers.
+template <class T>
+__host__ __device__ inline long long syn_vec_row(long long G, int q) {
+  return 16 * (G >> 2) + (sizeof(T) == 4 ? 4 * (G & 3) + q : (G & 3) + 4 * q);
+}
+
 // K1: radial preparation.  For each (vec, r_p, lm): the eight spectral profiles
 //   ur = lam f/r^2, wr = lam e/r^2, dT = T'   (scalar synthesis with Pbar)
 //   Su = f'/r, Tu = e/r, Sw = e'/r, Tw = -(f'' - lam f/r^2)/r, ST = T/r  (vector synthesis)
@@ -280,7 +291,7 @@ __device__ inline void radial_prep_wave(const DevGrid& g, const double* __restri
     const int rp = 16 * rt + t;
     if (rp >= Np) continue;
     const double ri1 = 1.0 / g.rp[rp], ri2 = ri1 * ri1;
-    const long long rs = (long long)vec * 6 * Np + rp, rv = (long long)vec * 10 * Np + rp;
+    const long long rs = (long long)vec * 6 * Np + rp, gv0 = (long long)vec * 3 * Np + rp;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int tq = Mfma<double>::out_row(l, q), il = il0 + tq, lw = m + il;
@@ -293,7 +304,7 @@ __device__ inline void radial_prep_wave(const DevGrid& g, const double* __restri
         Gs[offS + (r >> 4) * KSl * 64 + kofs + (r & 15)] = (T)val;
       };
       auto gv = [&](int slot, double val) {
-        const long long r = rv + (long long)slot * Np;
+        const long long r = syn_vec_row<T>(gv0 + (long long)(slot >> 2) * Np, slot & 3);
         Gv[offV + (r >> 4) * KSl * 64 + kofs + (r & 15)] = (T)val;
       };
 #pragma unroll
@@ -323,8 +334,9 @@ __device__ inline void radial_prep_wave(const DevGrid& g, const double* __restri
 // products E, ED, ED2) and holds their X operands in registers (read once from the state).
 // Row tile by row tile it forms (E X)^T = X^T E^T etc. on the FP64 matrix cores, with the E
 // operands streamed from L2 a quarter row tile ahead.  A lane then holds 16 consecutive r_p
-// of one degree, which are consecutive rows of the synthesis operands (rows ordered
-// (vec, slot, r_p)): every store writes runs of 16 contiguous elements.
+// of one degree: consecutive rows of the scalar synthesis operand (rows ordered
+// (vec, slot, r_p)), so its stores write runs of 16 contiguous elements; in the vector operand
+// they are consecutive groups (syn_vec_row), four rows of each 16-row run per store.
 template <class T, int RTN>
 __global__ void __launch_bounds__(256) k_radial_prep(DevGrid g, const double* __restrict__ v, long long ldv,
                                                      long long J, int nvec, T* __restrict__ Gs, T* __restrict__ Gv) {
@@ -393,10 +405,14 @@ __global__ void __launch_bounds__(256) k_synth(const SynProb* __restrict__ probs
   }
   int ncol = 0;
   const long long bodd = (long long)ct * pr.kse * 64;  // odd tables follow the even ones
+  // vector problems: the wavefront's two column tiles are the dP and the m P/sin tile of the
+  // same nodes (both parts of a field meet in one lane)
+  const bool vec2 = pr.parts == 2;
+  static_assert(kSynTN == 2, "column tile pairs of the vector problems");
 #pragma unroll
   for (int j = 0; j < kSynTN; ++j) {
-    ctl[j] = cg * 4 * kSynTN + w + 4 * j;
-    if (ctl[j] < ct) ncol = j + 1;
+    ctl[j] = vec2 ? j * pr.cth + cg * 4 + w : cg * 4 * kSynTN + w + 4 * j;
+    if (vec2 ? (cg * 4 + w < pr.cth) : (ctl[j] < ct)) ncol = j + 1;
     const int cc = min(ctl[j], ct - 1);
     Be[j] = tab + pr.b_off + (long long)cc * pr.kse * 64 + l;
     Bo[j] = tab + pr.b_off + bodd + (long long)cc * pr.kso * 64 + l;
@@ -446,6 +462,46 @@ __global__ void __launch_bounds__(256) k_synth(const SynProb* __restrict__ probs
   pass(pr.kse, pr.kso, Bo, co);
   T* C = ws_out + pr.c_off;
   const int nh = pr.nth >> 1, ncolC = pr.parts * pr.nth;
+  if (vec2) {
+    // group G of lane group l/16 in row tile rt: members q = (Re, Im) of the two profiles
+    // (a, b) of the group; with D the dP sums and M the m P/sin sums the fields are
+    // (D a + i M b, i M a - D b), i.e. (U_th, U_ph) from (S_u, T_u) and (w_th, w_ph) from
+    // (S_w, T_w); the third group (T, 0) gives (dT/dth, dT/dph) = (D T, i M T).  Output rows
+    // (vec, field row f = 4 g + 0..3, r_p), nth columns.
+    if (ncol == 0) return;
+    const int tn = (cg * 4 + w) * 16 + (l & 15);  // northern node
+    if (tn >= nh) return;
+    const int ts = pr.nth - 1 - tn, np3 = pr.rper / 4;   // rper = 12 N_p
+    const int Np = np3 / 3;
+#pragma unroll
+    for (int i = 0; i < kSynTM; ++i) {
+      const int G = rt[i] * 4 + (l >> 4);
+      if (G >= np3 * nvec) continue;
+      const int vec = G / np3, rem = G - vec * np3, gg = rem / Np, rp = rem - gg * Np;
+      T* cr = C + ((long long)(vec * 12 + 4 * gg) * Np + rp) * pr.nth;
+      const bool pad = gg == 2;   // members 2, 3 of the third group are zero rows
+      T Dn[4], Ds[4], Mn[4], Ms[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const T de = ce[i][0][q], dd = co[i][0][q], me = ce[i][1][q], mo = co[i][1][q];
+        const bool z = pad && q >= 2;
+        Dn[q] = z ? (T)0 : de + dd;   // dP: north e + o, south o - e
+        Ds[q] = z ? (T)0 : dd - de;
+        Mn[q] = z ? (T)0 : me + mo;   // m P/sin: north e + o, south e - o
+        Ms[q] = z ? (T)0 : me - mo;
+      }
+      const long long fs = (long long)Np * pr.nth;
+      cr[0 * fs + tn] = Dn[0] - Mn[3];
+      cr[1 * fs + tn] = Dn[1] + Mn[2];
+      cr[2 * fs + tn] = -Mn[1] - Dn[2];
+      cr[3 * fs + tn] = Mn[0] - Dn[3];
+      cr[0 * fs + ts] = Ds[0] - Ms[3];
+      cr[1 * fs + ts] = Ds[1] + Ms[2];
+      cr[2 * fs + ts] = -Ms[1] - Ds[2];
+      cr[3 * fs + ts] = Ms[0] - Ds[3];
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < kSynTN; ++j) {
     if (j >= ncol) continue;
@@ -750,6 +806,13 @@ __global__ void __launch_bounds__(256) k_gemm_batched(const GemmProb* __restrict
 // MODE 2: synthesis only, the 9 fields are written to base (and base32 if non-null).
 enum { RING_LINEAR = 0, RING_NONLINEAR = 1, RING_SYNTH = 2 };
 
+// Rows of the Legendre sums a ring reads per harmonic: 0..5 the scalar sums (U_r, w_r, dT/dr;
+// Re, Im), 6..17 the vector fields (U_th, U_ph, w_th, w_ph, (1/r) dT/dth, (1/(r sin)) dT/dph;
+// Re, Im).  Field f = 0..9 of the transforms (U_r, U_th, U_ph, w_r, w_th, w_ph, dT/dr, dT/dth,
+// dT/dph, zero) starts at row kRingFieldRow[f].
+__device__ constexpr int kRingFieldRow[10] = {0, 6, 8, 2, 10, 12, 4, 14, 16, 0};
+constexpr int kRingRows = 18;
+
 template <class T>
 struct cz {
   T re, im;
@@ -946,38 +1009,27 @@ __global__ void __launch_bounds__(kRingThreads) k_ring(DevGrid g, int nvec, int 
   // step A: gather the Legendre sums and form the Fourier coefficients of the 9 fields,
   // packing fields (2q, 2q+1) into spectrum q: Z_k = (A_k + i B_k)/2, Z_{N-k} = conj(A_k)/2 +
   // i conj(B_k)/2 for k >= 1 and Z_0 = Re A_0 + i Re B_0.
-  const long long Ms = (long long)6 * g.Np * g.vcap, Mv = (long long)10 * g.Np * g.vcap;
+  const long long Ms = (long long)6 * g.Np * g.vcap, Mv = (long long)12 * g.Np * g.vcap;
   const int vq = rv - rp * nvec;  // vector index
   for (int idx = tid; idx < K1 * RT; idx += kRingThreads) {
     const int tt = idx & rmask, k = idx >> rt_log2;
     const int th = th0 + tt;
     if (th >= nth) continue;
-    T c[26];
-    // rows of the sums: (vec, slot, r_p)
+    T c[kRingRows];
+    // rows of the sums: (vec, slot, r_p); scalar U_r, w_r, dT/dr, vector fields U_th, U_ph,
+    // w_th, w_ph, (1/r) dT/dth, (1/(r sin)) dT/dph (Re, Im each)
     const T* cs = Cs + (long long)k * Ms * nth + ((long long)vq * 6 * g.Np + rp) * nth + th;
 #pragma unroll
     for (int q = 0; q < 6; ++q) c[q] = cs[(long long)q * g.Np * nth];
-    const T* cv = Cv + (long long)k * Mv * 2 * nth + ((long long)vq * 10 * g.Np + rp) * 2 * nth + th;
+    const T* cv = Cv + (long long)k * Mv * nth + ((long long)vq * 12 * g.Np + rp) * nth + th;
 #pragma unroll
-    for (int q = 0; q < 10; ++q) {
-      c[6 + q] = cv[(long long)q * g.Np * 2 * nth];         // dP part
-      c[16 + q] = cv[(long long)q * g.Np * 2 * nth + nth];  // mPs part
-    }
-    // scalar sums: U_r (0,1), w_r (2,3), dT/dr (4,5); vector sums q: S_u 0, T_u 1, S_w 2, T_w 3, T 4
-    auto dPr = [&](int q) { return c[6 + 2 * q]; };
-    auto dPi = [&](int q) { return c[7 + 2 * q]; };
-    auto mPr = [&](int q) { return c[16 + 2 * q]; };
-    auto mPi = [&](int q) { return c[17 + 2 * q]; };
+    for (int q = 0; q < 12; ++q) c[6 + q] = cv[(long long)q * g.Np * nth];
     T fr[10], fi[10];
-    fr[0] = c[0]; fi[0] = c[1];                          // U_r
-    fr[1] = dPr(0) - mPi(1); fi[1] = dPi(0) + mPr(1);    // U_th = dP S + i mPs T
-    fr[2] = -mPi(0) - dPr(1); fi[2] = mPr(0) - dPi(1);   // U_ph = i mPs S - dP T
-    fr[3] = c[2]; fi[3] = c[3];                          // w_r
-    fr[4] = dPr(2) - mPi(3); fi[4] = dPi(2) + mPr(3);    // w_th
-    fr[5] = -mPi(2) - dPr(3); fi[5] = mPr(2) - dPi(3);   // w_ph
-    fr[6] = c[4]; fi[6] = c[5];                          // dT/dr
-    fr[7] = dPr(4); fi[7] = dPi(4);                      // (1/r) dT/dth
-    fr[8] = -mPi(4); fi[8] = mPr(4);                     // (1/(r sin)) dT/dph
+#pragma unroll
+    for (int f = 0; f < 9; ++f) {
+      fr[f] = c[kRingFieldRow[f]];
+      fi[f] = c[kRingFieldRow[f] + 1];
+    }
     fr[9] = 0; fi[9] = 0;
     const int zb = tt * 5 * N;
 #pragma unroll
@@ -1131,54 +1183,26 @@ __device__ inline void fft_reg(cz<T> (&x)[N1 * N2], const T* __restrict__ fw) {
   }
 }
 
-// Fourier coefficients (fr, fi) at one k of field F (0..8 as in k_ring; 9 is zero) from the
-// Legendre sums of one ring, read from the LDS copy g[row * rs] with rows 0..5 the scalar sums,
-// 6..15 the dP parts and 16..25 the mP/sin parts of the vector sums.
-template <class T, int F>
-__device__ inline void ring_field_coef(const T* g, int rs, T& fr, T& fi) {
-  auto c = [&](int j, int ri) { return g[(2 * j + ri) * rs]; };
-  auto dP = [&](int j, int ri) { return g[(6 + 2 * j + ri) * rs]; };
-  auto mP = [&](int j, int ri) { return g[(16 + 2 * j + ri) * rs]; };
-  if (F == 0) { fr = c(0, 0); fi = c(0, 1); }                                        // U_r
-  else if (F == 1) { fr = dP(0, 0) - mP(1, 1); fi = dP(0, 1) + mP(1, 0); }           // U_th
-  else if (F == 2) { fr = -mP(0, 1) - dP(1, 0); fi = mP(0, 0) - dP(1, 1); }          // U_ph
-  else if (F == 3) { fr = c(1, 0); fi = c(1, 1); }                                   // w_r
-  else if (F == 4) { fr = dP(2, 0) - mP(3, 1); fi = dP(2, 1) + mP(3, 0); }           // w_th
-  else if (F == 5) { fr = -mP(2, 1) - dP(3, 0); fi = mP(2, 0) - dP(3, 1); }          // w_ph
-  else if (F == 6) { fr = c(2, 0); fi = c(2, 1); }                                   // dT/dr
-  else if (F == 7) { fr = dP(4, 0); fi = dP(4, 1); }                                 // (1/r) dT/dth
-  else if (F == 8) { fr = -mP(4, 1); fi = mP(4, 0); }                                // (1/(r sin)) dT/dph
-  else { fr = 0; fi = 0; }
-}
-
-// Rows of the LDS copy of the sums that field f combines, F = alpha z1 + beta i z2 (z = Re row,
-// Re row + 1), as in ring_field_coef: {z1 row, alpha, z2 row, beta} for f = 0..9.
-__device__ constexpr int kRingFieldRows[10][2] = {{0, 0}, {6, 18}, {8, 16}, {2, 2}, {10, 22}, {12, 20}, {4, 4}, {14, 14}, {24, 24}, {0, 0}};
-__device__ constexpr float kRingFieldCoef[10][2] = {{1, 0}, {1, 1}, {-1, 1}, {1, 0}, {1, 1}, {-1, 1}, {1, 0}, {1, 0}, {0, 1}, {0, 0}};
-
 // Spectrum of transform q = fields (2q, 2q+1) of one ring, packed as in k_ring; g points at
 // the ring's column of the LDS copy, laid out [row][k][ring] (row stride rs, k stride ks).  The
-// same code serves every q (row indices and coefficients per lane), so the lanes of a wave that
-// hold different transforms do not diverge.
+// same code serves every q (row indices per lane), so the lanes of a wave that hold different
+// transforms do not diverge.
 template <class T, int N>
 __device__ inline void ring_spectrum(cz<T> (&z)[N], const T* g, int rs, int ks, int K1, int q) {
   constexpr int KM = (N - 1) / 3 + 1;   // K1 <= KM (N_phi >= 3K + 1)
   const int fa = 2 * q, fb = 2 * q + 1;
-  const T* a1 = g + kRingFieldRows[fa][0] * rs;
-  const T* a2 = g + kRingFieldRows[fa][1] * rs;
-  const T* b1 = g + kRingFieldRows[fb][0] * rs;
-  const T* b2 = g + kRingFieldRows[fb][1] * rs;
-  const T aal = kRingFieldCoef[fa][0], abe = kRingFieldCoef[fa][1];
-  const T bal = kRingFieldCoef[fb][0], bbe = kRingFieldCoef[fb][1];
+  const T* a = g + kRingFieldRow[fa] * rs;
+  const T* b = g + kRingFieldRow[fb] * rs;
+  const T bon = fb == 9 ? (T)0 : (T)1;
 #pragma unroll
   for (int k = 0; k < KM; ++k) {
     T ar = 0, ai = 0, br = 0, bi = 0;
     if (k < K1) {
       const int o = k * ks;
-      ar = aal * a1[o] - abe * a2[o + rs];
-      ai = aal * a1[o + rs] + abe * a2[o];
-      br = bal * b1[o] - bbe * b2[o + rs];
-      bi = bal * b1[o + rs] + bbe * b2[o];
+      ar = a[o];
+      ai = a[o + rs];
+      br = bon * b[o];
+      bi = bon * b[o + rs];
     }
     if (k == 0) {
       z[0] = {ar, br};
@@ -1228,28 +1252,29 @@ __global__ void __launch_bounds__(ring_reg_threads<T>()) k_ring_reg(DevGrid g, i
       for (int q = 0; q < 9; ++q) bpre[u][q] = bp[(long long)q * N * nth];
     }
   }
-  // copy of the sums of this workgroup's rings into LDS, [26 rows][K1][RR rings]: every (row, k)
+  // copy of the sums of this workgroup's rings into LDS, [18 rows][K1][RR rings]: every (row, k)
   // is a run of RR consecutive theta, read as 8-byte pieces (nth and th0 are even, so a piece
   // lies wholly inside or wholly beyond the last node).  Thread (group, piece) owns rows group,
   // group + NG, ... and reads them for every k (K1 <= KM = (N - 1)/3 + 1, a compile-time trip
   // count), all loads issued before the first store.
   {
     constexpr int EPL = 8 / sizeof(T), PPR = RR / EPL, NG = NT / PPR;   // elements per piece, pieces per run, groups
-    constexpr int KM = (N - 1) / 3 + 1, NRW = (26 + NG - 1) / NG;      // rows per group
+    constexpr int KM = (N - 1) / 3 + 1, NRW = (kRingRows + NG - 1) / NG; // rows per group
     typedef T pT __attribute__((ext_vector_type(EPL)));
-    const long long kS = (long long)6 * Np * g.vcap * nth, kV = (long long)10 * Np * g.vcap * 2 * nth;
-    const long long sS = (long long)Np * nth, sV = (long long)Np * 2 * nth;
+    const long long kS = (long long)6 * Np * g.vcap * nth, kV = (long long)12 * Np * g.vcap * nth;
+    const long long sR = (long long)Np * nth;
     // unconditional loads at clamped positions: a piece beyond the last node reads the last
-    // one (that ring's results are never written), rows >= 26 and k >= K1 repeat valid ones
-    // and are not stored
+    // one (that ring's results are never written), k >= K1 repeats a valid one and is not
+    // stored; rows beyond the last are skipped (whole wavefronts but one)
     const int e = tid % PPR, grp = tid / PPR, th = min(th0 + e * EPL, nth - EPL);
     const T* cs = Cs + ((long long)vq * 6 * Np + rp) * nth + th;
-    const T* cv = Cv + ((long long)vq * 10 * Np + rp) * 2 * nth + th;
+    const T* cv = Cv + ((long long)vq * 12 * Np + rp) * nth + th;
     pT val[NRW][KM];
 #pragma unroll
     for (int i = 0; i < NRW; ++i) {
-      const int row = min(grp + i * NG, 25);
-      const T* src = row < 6 ? cs + row * sS : (row < 16 ? cv + (row - 6) * sV : cv + (row - 16) * sV + nth);
+      const int row = grp + i * NG;
+      if (i > 0 && row >= kRingRows) continue;
+      const T* src = row < 6 ? cs + row * sR : cv + (row - 6) * sR;
       const long long kst = row < 6 ? kS : kV;
 #pragma unroll
       for (int k = 0; k < KM; ++k) val[i][k] = *reinterpret_cast<const pT*>(src + min(k, K1 - 1) * kst);
@@ -1259,7 +1284,7 @@ __global__ void __launch_bounds__(ring_reg_threads<T>()) k_ring_reg(DevGrid g, i
       const int row = grp + i * NG;
 #pragma unroll
       for (int k = 0; k < KM; ++k)
-        if (row < 26 && k < K1) *reinterpret_cast<pT*>(Gl + (row * K1 + k) * RR + e * EPL) = val[i][k];
+        if (row < kRingRows && k < K1) *reinterpret_cast<pT*>(Gl + (row * K1 + k) * RR + e * EPL) = val[i][k];
     }
   }
   __syncthreads();
