@@ -326,7 +326,7 @@ void build_workspaces(sc_plan* P) {
   long long off = 0;
   // synthesis inputs in MFMA A-operand order per m: [row tile][k-step][lane]
   P->rtcS = (int)((6 * Np * V + 15) / 16);
-  P->rtcV = (int)((12 * Np * V + 15) / 16);   // three groups of four rows per (vec, r_p)
+  P->rtcV = sc::syn_vec_tiles(3 * Np * V);   // three groups of four rows per (vec, r_p)
   P->h_gsoff.assign(2 * K1, 0);
   long long gsz = 0, gvz = 0;
   for (int k = 0; k < K1; ++k) {

@@ -198,15 +198,17 @@ __device__ inline void mfma_f64_products(const double* const (&Mp)[NPR], const T
 
 // ------------------------------------------------------------------------------------------
 // Rows of the vector synthesis operand.  The five complex vector profiles of one (vec, r_p),
-// (S_u, T_u, S_w, T_w, T), form three groups of four real rows: (S_u, T_u), (S_w, T_w) and
-// (T, two zero rows); group G = (3 vec + g) N_p + r_p.  Member q of group G sits in the 16-row
-// tile G/4 at the row where the MFMA output layout places element q of lane group G%4, so
-// that one lane of the synthesis receives all four members of a group and can combine them
-// into the physical fields (U_th, U_ph), (w_th, w_ph) or (dT/dth, dT/dph) in registers.
-template <class T>
+// (S_u, T_u, S_w, T_w, T), form three groups of four real rows (members): (S_u, T_u),
+// (S_w, T_w) and (T, two zero rows); group G = (3 vec + g) N_p + r_p.  Sixteen consecutive
+// groups share four 16-row tiles, member q in tile 4 (G/16) + q at row G % 16: a synthesis
+// workgroup owns such a set of four row tiles, so every lane holds the four members of its
+// groups at the same output position and combines them into the physical fields (U_th, U_ph),
+// (w_th, w_ph) or (dT/dth, dT/dph) in registers; consecutive r_p stay consecutive rows.
 __host__ __device__ inline long long syn_vec_row(long long G, int q) {
-  return 16 * (G >> 2) + (sizeof(T) == 4 ? 4 * (G & 3) + q : (G & 3) + 4 * q);
+  return ((G >> 4) * 4 + q) * 16 + (G & 15);
 }
+// Row tiles of the vector synthesis operand for n groups.
+__host__ __device__ inline int syn_vec_tiles(long long n) { return (int)(4 * ((n + 15) / 16)); }
 
 // K1: radial preparation.  For each (vec, r_p, lm): the eight spectral profiles
 //   ur = lam f/r^2, wr = lam e/r^2, dT = T'   (scalar synthesis with Pbar)
@@ -304,7 +306,7 @@ __device__ inline void radial_prep_wave(const DevGrid& g, const double* __restri
         Gs[offS + (r >> 4) * KSl * 64 + kofs + (r & 15)] = (T)val;
       };
       auto gv = [&](int slot, double val) {
-        const long long r = syn_vec_row<T>(gv0 + (long long)(slot >> 2) * Np, slot & 3);
+        const long long r = syn_vec_row(gv0 + (long long)(slot >> 2) * Np, slot & 3);
         Gv[offV + (r >> 4) * KSl * 64 + kofs + (r & 15)] = (T)val;
       };
 #pragma unroll
@@ -334,9 +336,9 @@ __device__ inline void radial_prep_wave(const DevGrid& g, const double* __restri
 // products E, ED, ED2) and holds their X operands in registers (read once from the state).
 // Row tile by row tile it forms (E X)^T = X^T E^T etc. on the FP64 matrix cores, with the E
 // operands streamed from L2 a quarter row tile ahead.  A lane then holds 16 consecutive r_p
-// of one degree: consecutive rows of the scalar synthesis operand (rows ordered
-// (vec, slot, r_p)), so its stores write runs of 16 contiguous elements; in the vector operand
-// they are consecutive groups (syn_vec_row), four rows of each 16-row run per store.
+// of one degree, which are consecutive rows of the synthesis operands (scalar rows ordered
+// (vec, slot, r_p); vector rows of consecutive groups, syn_vec_row): the stores write runs of
+// 16 contiguous elements (two runs where a vector run crosses a tile).
 template <class T, int RTN>
 __global__ void __launch_bounds__(256) k_radial_prep(DevGrid g, const double* __restrict__ v, long long ldv,
                                                      long long J, int nvec, T* __restrict__ Gs, T* __restrict__ Gv) {
@@ -371,8 +373,12 @@ struct SynProb {
   int nth;                         // theta nodes; C rows have parts * nth columns
 };
 
+__host__ __device__ inline int syn_row_tiles(const SynProb& p, int nvec) {
+  return p.parts == 2 ? syn_vec_tiles((long long)(p.rper / 4) * nvec) : (p.rper * nvec + 15) / 16;
+}
+
 __host__ __device__ inline int syn_tiles(const SynProb& p, int nvec) {
-  const int rt = (p.rper * nvec + 15) / 16;
+  const int rt = syn_row_tiles(p, nvec);
   return ((rt + kSynTM - 1) / kSynTM) * ((p.parts * p.cth + 4 * kSynTN - 1) / (4 * kSynTN));
 }
 
@@ -392,7 +398,7 @@ __global__ void __launch_bounds__(256) k_synth(const SynProb* __restrict__ probs
   const int ct = pr.parts * pr.cth, ks = pr.kse + pr.kso;
   const int ncg = (ct + 4 * kSynTN - 1) / (4 * kSynTN);
   const int rg = tile / ncg, cg = tile - rg * ncg;
-  const int rows = pr.rper * nvec, rtu = (rows + 15) / 16;
+  const int rows = pr.rper * nvec, rtu = syn_row_tiles(pr, nvec);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const T* A[kSynTM];
   const T* Be[kSynTN];
@@ -463,19 +469,21 @@ __global__ void __launch_bounds__(256) k_synth(const SynProb* __restrict__ probs
   T* C = ws_out + pr.c_off;
   const int nh = pr.nth >> 1, ncolC = pr.parts * pr.nth;
   if (vec2) {
-    // group G of lane group l/16 in row tile rt: members q = (Re, Im) of the two profiles
-    // (a, b) of the group; with D the dP sums and M the m P/sin sums the fields are
+    // the four row tiles of this workgroup hold the members q = 0..3 (Re, Im of the two
+    // profiles (a, b) of a group) of sixteen groups; element e of a lane is group
+    // 16 rg + out_row(l, e).  With D the dP sums and M the m P/sin sums the fields are
     // (D a + i M b, i M a - D b), i.e. (U_th, U_ph) from (S_u, T_u) and (w_th, w_ph) from
     // (S_w, T_w); the third group (T, 0) gives (dT/dth, dT/dph) = (D T, i M T).  Output rows
     // (vec, field row f = 4 g + 0..3, r_p), nth columns.
+    static_assert(kSynTM == 4, "one row tile per member");
     if (ncol == 0) return;
     const int tn = (cg * 4 + w) * 16 + (l & 15);  // northern node
     if (tn >= nh) return;
     const int ts = pr.nth - 1 - tn, np3 = pr.rper / 4;   // rper = 12 N_p
     const int Np = np3 / 3;
 #pragma unroll
-    for (int i = 0; i < kSynTM; ++i) {
-      const int G = rt[i] * 4 + (l >> 4);
+    for (int e = 0; e < 4; ++e) {
+      const int G = rg * 16 + Mfma<T>::out_row(l, e);
       if (G >= np3 * nvec) continue;
       const int vec = G / np3, rem = G - vec * np3, gg = rem / Np, rp = rem - gg * Np;
       T* cr = C + ((long long)(vec * 12 + 4 * gg) * Np + rp) * pr.nth;
@@ -483,7 +491,7 @@ __global__ void __launch_bounds__(256) k_synth(const SynProb* __restrict__ probs
       T Dn[4], Ds[4], Mn[4], Ms[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const T de = ce[i][0][q], dd = co[i][0][q], me = ce[i][1][q], mo = co[i][1][q];
+        const T de = ce[q][0][e], dd = co[q][0][e], me = ce[q][1][e], mo = co[q][1][e];
         const bool z = pad && q >= 2;
         Dn[q] = z ? (T)0 : de + dd;   // dP: north e + o, south o - e
         Ds[q] = z ? (T)0 : dd - de;
