@@ -326,7 +326,7 @@ void build_workspaces(sc_plan* P) {
   long long off = 0;
   // synthesis inputs in MFMA A-operand order per m: [row tile][k-step][lane]
   P->rtcS = (int)((6 * Np * V + 15) / 16);
-  P->rtcV = sc::syn_vec_tiles(3 * Np * V);   // three groups of four rows per (vec, r_p)
+  P->rtcV = sc::syn_vec_tiles((long long)sc::syn_vec_groups((int)Np) * V);
   P->h_gsoff.assign(2 * K1, 0);
   long long gsz = 0, gvz = 0;
   for (int k = 0; k < K1; ++k) {
@@ -369,9 +369,9 @@ void build_workspaces(sc_plan* P) {
     long long lb = g.lmbase[k];
     const int kse = ((nl + 1) / 2 + 3) / 4, kso = (nl / 2 + 3) / 4, cth = (int)((nth / 2 + 15) / 16);
     P->h_syn.push_back(sc::SynProb{w.Gs + P->h_gsoff[2 * k], t.synS[k], w.Cs + k * 6 * Np * V * nth, (int)(6 * Np), kse,
-                                   kso, cth, 1, (int)nth});
-    P->h_syn.push_back(sc::SynProb{w.Gv + P->h_gsoff[2 * k + 1], t.synV[k], w.Cv + k * 12 * Np * V * nth, (int)(12 * Np),
-                                   kse, kso, cth, 2, (int)nth});
+                                   kso, cth, 1, (int)nth, (int)Np});
+    P->h_syn.push_back(sc::SynProb{w.Gv + P->h_gsoff[2 * k + 1], t.synV[k], w.Cv + k * 12 * Np * V * nth,
+                                   4 * sc::syn_vec_groups((int)Np), kse, kso, cth, 2, (int)nth, (int)Np});
     sc::GemmProb c{w.Fs + k * 4 * Np * V * nth, t.anaS[k], w.As + 4 * Np * V * lb, (int)(4 * Np), nl, (int)nth, (int)nth, (int)nth, nl};
     sc::GemmProb d{w.Fv + k * 4 * Np * V * 2 * nth, t.anaV[k], w.Av + 4 * Np * V * lb, (int)(4 * Np), nl, (int)(2 * nth), (int)(2 * nth), (int)(2 * nth), nl};
     P->h_ana.push_back(c);

@@ -197,16 +197,19 @@ __device__ inline void mfma_f64_products(const double* const (&Mp)[NPR], const T
 }
 
 // ------------------------------------------------------------------------------------------
-// Rows of the vector synthesis operand.  The five complex vector profiles of one (vec, r_p),
-// (S_u, T_u, S_w, T_w, T), form three groups of four real rows (members): (S_u, T_u),
-// (S_w, T_w) and (T, two zero rows); group G = (3 vec + g) N_p + r_p.  Sixteen consecutive
-// groups share four 16-row tiles, member q in tile 4 (G/16) + q at row G % 16: a synthesis
-// workgroup owns such a set of four row tiles, so every lane holds the four members of its
-// groups at the same output position and combines them into the physical fields (U_th, U_ph),
-// (w_th, w_ph) or (dT/dth, dT/dph) in registers; consecutive r_p stay consecutive rows.
+// Rows of the vector synthesis operand.  The five complex vector profiles (S_u, T_u, S_w, T_w,
+// T) form groups of four real rows (members): per vector, groups [0, N_p) are (S_u, T_u) and
+// [N_p, 2 N_p) are (S_w, T_w) at r_p = G mod N_p, and groups [2 N_p, 2 N_p + ceil(N_p/2)) are
+// (T at r_p = 2 j, T at r_p = 2 j + 1); syn_vec_groups(N_p) groups per vector.  Sixteen
+// consecutive groups share four 16-row tiles, member q in tile 4 (G/16) + q at row G % 16: a
+// synthesis workgroup owns such a set of four row tiles, so every lane holds the four members
+// of its groups at the same output position and combines them into the physical fields
+// (U_th, U_ph), (w_th, w_ph) or (dT/dth, dT/dph) in registers; consecutive r_p stay
+// consecutive rows.
 __host__ __device__ inline long long syn_vec_row(long long G, int q) {
   return ((G >> 4) * 4 + q) * 16 + (G & 15);
 }
+__host__ __device__ inline int syn_vec_groups(int Np) { return 2 * Np + (Np + 1) / 2; }
 // Row tiles of the vector synthesis operand for n groups.
 __host__ __device__ inline int syn_vec_tiles(long long n) { return (int)(4 * ((n + 15) / 16)); }
 
@@ -293,7 +296,7 @@ __device__ inline void radial_prep_wave(const DevGrid& g, const double* __restri
     const int rp = 16 * rt + t;
     if (rp >= Np) continue;
     const double ri1 = 1.0 / g.rp[rp], ri2 = ri1 * ri1;
-    const long long rs = (long long)vec * 6 * Np + rp, gv0 = (long long)vec * 3 * Np + rp;
+    const long long rs = (long long)vec * 6 * Np + rp, gv0 = (long long)vec * syn_vec_groups(Np);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int tq = Mfma<double>::out_row(l, q), il = il0 + tq, lw = m + il;
@@ -306,7 +309,8 @@ __device__ inline void radial_prep_wave(const DevGrid& g, const double* __restri
         Gs[offS + (r >> 4) * KSl * 64 + kofs + (r & 15)] = (T)val;
       };
       auto gv = [&](int slot, double val) {
-        const long long r = syn_vec_row(gv0 + (long long)(slot >> 2) * Np, slot & 3);
+        const long long r = slot < 8 ? syn_vec_row(gv0 + (long long)(slot >> 2) * Np + rp, slot & 3)
+                                     : syn_vec_row(gv0 + 2LL * Np + (rp >> 1), 2 * (rp & 1) + (slot & 1));
         Gv[offV + (r >> 4) * KSl * 64 + kofs + (r & 15)] = (T)val;
       };
 #pragma unroll
@@ -366,15 +370,16 @@ constexpr int kSynTN = 2;
 
 struct SynProb {
   long long a_off, b_off, c_off;  // A, C in the workspace; B in the tables (even part, then odd)
-  int rper;                        // rows per vector (6 N_p or 10 N_p)
+  int rper;                        // rows per vector (6 N_p; vector: 4 syn_vec_groups(N_p))
   int kse, kso;                    // k-steps of the even and odd parts
   int cth;                         // column tiles of one part (ceil(nth/2 / 16))
   int parts;                       // 1 (scalar: P) or 2 (vector: dP, m P/sin)
   int nth;                         // theta nodes; C rows have parts * nth columns
+  int np;                          // N_p
 };
 
 __host__ __device__ inline int syn_row_tiles(const SynProb& p, int nvec) {
-  return p.parts == 2 ? syn_vec_tiles((long long)(p.rper / 4) * nvec) : (p.rper * nvec + 15) / 16;
+  return p.parts == 2 ? syn_vec_tiles((long long)syn_vec_groups(p.np) * nvec) : (p.rper * nvec + 15) / 16;
 }
 
 __host__ __device__ inline int syn_tiles(const SynProb& p, int nvec) {
@@ -469,44 +474,66 @@ __global__ void __launch_bounds__(256) k_synth(const SynProb* __restrict__ probs
   T* C = ws_out + pr.c_off;
   const int nh = pr.nth >> 1, ncolC = pr.parts * pr.nth;
   if (vec2) {
-    // the four row tiles of this workgroup hold the members q = 0..3 (Re, Im of the two
-    // profiles (a, b) of a group) of sixteen groups; element e of a lane is group
-    // 16 rg + out_row(l, e).  With D the dP sums and M the m P/sin sums the fields are
-    // (D a + i M b, i M a - D b), i.e. (U_th, U_ph) from (S_u, T_u) and (w_th, w_ph) from
-    // (S_w, T_w); the third group (T, 0) gives (dT/dth, dT/dph) = (D T, i M T).  Output rows
-    // (vec, field row f = 4 g + 0..3, r_p), nth columns.
+    // the four row tiles of this workgroup hold the members q = 0..3 of sixteen groups; element
+    // e of a lane is group 16 rg + out_row(l, e).  With D the dP sums and M the m P/sin sums:
+    // a group (a, b) of two profiles gives the fields (D a + i M b, i M a - D b), i.e.
+    // (U_th, U_ph) from (S_u, T_u) and (w_th, w_ph) from (S_w, T_w); a group (T, T') of two
+    // nodes gives (dT/dth, dT/dph) = (D T, i M T) at both.  Output rows (vec, field row
+    // 0..11, r_p), nth columns.
     static_assert(kSynTM == 4, "one row tile per member");
     if (ncol == 0) return;
     const int tn = (cg * 4 + w) * 16 + (l & 15);  // northern node
     if (tn >= nh) return;
-    const int ts = pr.nth - 1 - tn, np3 = pr.rper / 4;   // rper = 12 N_p
-    const int Np = np3 / 3;
+    const int ts = pr.nth - 1 - tn, Np = pr.np, GP = syn_vec_groups(Np);
+    const long long fs = (long long)Np * pr.nth;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int G = rg * 16 + Mfma<T>::out_row(l, e);
-      if (G >= np3 * nvec) continue;
-      const int vec = G / np3, rem = G - vec * np3, gg = rem / Np, rp = rem - gg * Np;
-      T* cr = C + ((long long)(vec * 12 + 4 * gg) * Np + rp) * pr.nth;
-      const bool pad = gg == 2;   // members 2, 3 of the third group are zero rows
+      if (G >= GP * nvec) continue;
+      const int vec = G / GP, rem = G - vec * GP;
       T Dn[4], Ds[4], Mn[4], Ms[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const T de = ce[q][0][e], dd = co[q][0][e], me = ce[q][1][e], mo = co[q][1][e];
-        const bool z = pad && q >= 2;
-        Dn[q] = z ? (T)0 : de + dd;   // dP: north e + o, south o - e
-        Ds[q] = z ? (T)0 : dd - de;
-        Mn[q] = z ? (T)0 : me + mo;   // m P/sin: north e + o, south e - o
-        Ms[q] = z ? (T)0 : me - mo;
+        Dn[q] = de + dd;   // dP: north e + o, south o - e
+        Ds[q] = dd - de;
+        Mn[q] = me + mo;   // m P/sin: north e + o, south e - o
+        Ms[q] = me - mo;
       }
-      const long long fs = (long long)Np * pr.nth;
-      cr[0 * fs + tn] = Dn[0] - Mn[3];
-      cr[1 * fs + tn] = Dn[1] + Mn[2];
-      cr[2 * fs + tn] = -Mn[1] - Dn[2];
-      cr[3 * fs + tn] = Mn[0] - Dn[3];
-      cr[0 * fs + ts] = Ds[0] - Ms[3];
-      cr[1 * fs + ts] = Ds[1] + Ms[2];
-      cr[2 * fs + ts] = -Ms[1] - Ds[2];
-      cr[3 * fs + ts] = Ms[0] - Ds[3];
+      if (rem < 2 * Np) {
+        const int gg = rem >= Np ? 1 : 0, rp = rem - gg * Np;
+        T* cr = C + ((long long)(vec * 12 + 4 * gg) * Np + rp) * pr.nth;
+        cr[0 * fs + tn] = Dn[0] - Mn[3];
+        cr[1 * fs + tn] = Dn[1] + Mn[2];
+        cr[2 * fs + tn] = -Mn[1] - Dn[2];
+        cr[3 * fs + tn] = Mn[0] - Dn[3];
+        cr[0 * fs + ts] = Ds[0] - Ms[3];
+        cr[1 * fs + ts] = Ds[1] + Ms[2];
+        cr[2 * fs + ts] = -Ms[1] - Ds[2];
+        cr[3 * fs + ts] = Ms[0] - Ds[3];
+      } else {
+        const int rp = 2 * (rem - 2 * Np);
+        T* cr = C + ((long long)(vec * 12 + 8) * Np + rp) * pr.nth;
+        cr[0 * fs + tn] = Dn[0];
+        cr[1 * fs + tn] = Dn[1];
+        cr[2 * fs + tn] = -Mn[1];
+        cr[3 * fs + tn] = Mn[0];
+        cr[0 * fs + ts] = Ds[0];
+        cr[1 * fs + ts] = Ds[1];
+        cr[2 * fs + ts] = -Ms[1];
+        cr[3 * fs + ts] = Ms[0];
+        if (rp + 1 < Np) {
+          cr += pr.nth;
+          cr[0 * fs + tn] = Dn[2];
+          cr[1 * fs + tn] = Dn[3];
+          cr[2 * fs + tn] = -Mn[3];
+          cr[3 * fs + tn] = Mn[2];
+          cr[0 * fs + ts] = Ds[2];
+          cr[1 * fs + ts] = Ds[3];
+          cr[2 * fs + ts] = -Ms[3];
+          cr[3 * fs + ts] = Ms[2];
+        }
+      }
     }
     return;
   }
