@@ -71,18 +71,22 @@ def stage_work(lay, nvec, prec_bytes, factor_bytes, nblocks, refine):
     nl = [L - k * m0 + 1 for k in range(K1)]
     w = {}
     # Legendre synthesis: per m, (6 Np nvec x nl) . (nl x nth) and (10 Np nvec x nl) . (nl x 2 nth),
-    # counted with the equatorial split (even and odd degrees on half the nodes: half the flops)
+    # counted with the equatorial split (even and odd degrees on half the nodes: half the flops);
+    # it writes 6 scalar and 12 vector-field rows of nth per (vec, r_p, m)
     fl = sum(2.0 * Np * nvec * n * (6 * nth + 10 * 2 * nth) for n in nl) / 2
-    by = prec_bytes * (Np * nvec * 16 * S + (K1 * Np * nvec * (6 * nth + 20 * nth)) + 3 * nth * S)
+    by = prec_bytes * (Np * nvec * 16 * S + (K1 * Np * nvec * (6 * nth + 12 * nth)) + 3 * nth * S)
     w["legendre_synth"] = (fl, by)
     # Legendre analysis: (4 Np nvec x nth) . (nth x nl) and (4 Np nvec x 2 nth) . (2 nth x nl) per m,
-    # counted with the mirror folding (each degree parity contracts over the northern half)
+    # counted with the mirror folding (each degree parity contracts over the northern half); the
+    # vector inputs are read once (their m P/sin half is derived from the dP half)
     fl = sum(2.0 * Np * nvec * n * (4 * nth + 4 * 2 * nth) for n in nl) / 2
-    by = prec_bytes * (K1 * Np * nvec * (4 * nth + 8 * nth) + Np * nvec * 8 * S + 3 * nth * S // 2)
+    by = prec_bytes * (K1 * Np * nvec * (4 * nth + 4 * nth) + Np * nvec * 8 * S + 3 * nth * S // 2)
     w["legendre_anal"] = (fl, by)
     rings = Np * nth * nvec
+    # ring: reads 18 rows (6 scalar sums, 12 vector fields) and writes 8 rows (4 scalar, 4 vector)
+    # per (ring, harmonic), plus the 9 base fields per (r_p, node, point) in the linear mode
     w["ring"] = (rings * (2.0 * 13 * K1 * nphi * 2 + 60 * nphi),
-                 prec_bytes * (rings * (26 + 12) * K1 + Np * nth * 9 * nphi))
+                 prec_bytes * (rings * (18 + 8) * K1 + Np * nth * 9 * nphi))
     nreal = 6 * N * S
     w["radial_prep"] = (nvec * Np * S * 7 * N * 4.0, 8.0 * nvec * nreal + prec_bytes * nvec * Np * 16 * S)
     w["project_rhs"] = (nvec * S * 2 * (Np * Np + 3 * N * Np + N * N) * 2.0,
