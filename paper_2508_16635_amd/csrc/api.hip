@@ -587,7 +587,7 @@ void project_attr() {
 
 template <class F>
 size_t tsolve_smem(const sc::HostGrid& g) {
-  return sizeof(F) * ((size_t)g.N * g.N + (size_t)sc::kTV * (g.K + 1) * 2 * g.N);
+  return sizeof(F) * ((size_t)g.N * (g.N + 1) + (size_t)sc::kTV * (g.K + 1) * 2 * (g.N + 1));
 }
 
 // The seven chain-solve launches for RT = ceil(N/16) row tiles.

@@ -1956,7 +1956,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_cs_out(DevGrid g, int nvec, c
 // Temperature blocks: x = tc * Tinv (tr * b) per l, for every (vec, k, l), both Re and Im
 // (ACC: added to x; FIN: y = clean(x) - u is written instead of x, and the workgroups of l = 0
 // also write y = -u on the e, f slots at l = 0, which no chain covers).  One workgroup per
-// (l, group of kTV vectors): Tinv_l staged in LDS, columns (vec, k, Re/Im).
+// (l, group of kTV vectors): Tinv_l and the columns (vec, k, Re/Im) staged in LDS, the product
+// on the matrix cores.
 constexpr int kTV = 4;
 
 template <class F, bool ACC, bool FIN>
@@ -1964,39 +1965,59 @@ __global__ void __launch_bounds__(256) k_T_solve(DevGrid g, int nvec, const F* _
                                                  const F* __restrict__ tr, const F* __restrict__ tc,
                                                  const double* __restrict__ bvec, double* __restrict__ xvec,
                                                  FinalOut fo) {
+  typedef typename Mfma<F>::acc_t acc_t;
   extern __shared__ unsigned char smem_raw[];
-  const int N = g.N;
-  F* Ts = reinterpret_cast<F*>(smem_raw);         // [N][N] transposed: Ts[i * N + j] = Tinv[j][i]
-  F* bs = Ts + N * N;                             // [ncol][N]
+  const int N = g.N, NP1 = N + 1;                 // padded LDS row stride
+  F* Ts = reinterpret_cast<F*>(smem_raw);         // [N][N + 1]: Ts[r * NP1 + k] = Tinv[r][k]
+  F* bs = Ts + N * NP1;                           // [ncol][N + 1]: right-hand side columns
   const int l = blockIdx.x;
   const int v0 = blockIdx.y * kTV, nv = min(kTV, nvec - v0);
   const int nk = min(g.K, l / g.m0) + 1;          // m = k m0 <= l
   const int ncol = nv * nk * 2;
   const long long ld = 6LL * N * g.S;
-  for (int i = threadIdx.x; i < N * N; i += blockDim.x) Ts[(i % N) * N + i / N] = Tinv[(long long)l * N * N + i];
+  for (int i = threadIdx.x; i < N * N; i += blockDim.x) Ts[(i / N) * NP1 + i % N] = Tinv[(long long)l * N * N + i];
   for (int idx = threadIdx.x; idx < ncol * N; idx += blockDim.x) {
     int jj = idx % N, col = idx / N;
     int ri = col & 1, kk = (col >> 1) % nk, vv = (col >> 1) / nk;
     int lm = g.lmbase[kk] + l - kk * g.m0;
     long long o = (long long)(v0 + vv) * ld + 2LL * ((long long)N * (2LL * g.S + lm) + jj) + ri;
-    bs[col * N + jj] = tr[(long long)l * N + jj] * (F)bvec[o];
+    bs[col * NP1 + jj] = tr[(long long)l * N + jj] * (F)bvec[o];
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < ncol * N; idx += blockDim.x) {
-    int jj = idx % N, col = idx / N;
-    int ri = col & 1, kk = (col >> 1) % nk, vv = (col >> 1) / nk;
-    F a = 0;
-    const F* bc = bs + col * N;
-    for (int i = 0; i < N; ++i) a += Ts[i * N + jj] * bc[i];
-    int lm = g.lmbase[kk] + l - kk * g.m0;
-    long long o = (long long)(v0 + vv) * ld + 2LL * ((long long)N * (2LL * g.S + lm) + jj) + ri;
-    double xv = (double)(tc[(long long)l * N + jj] * a);
-    if (ACC) xv += xvec[o];
-    if (FIN) {
-      const long long oo = 2LL * ((long long)N * (2LL * g.S + lm) + jj) + ri;
-      fo.y[(long long)(v0 + vv) * fo.ldy + oo] = final_value(fo, v0 + vv, oo, (kk == 0 && ri == 1) ? 0.0 : xv);
-    } else {
-      xvec[o] = xv;
+  // Tinv (N x N) times the columns (N x ncol) on the matrix cores: 16 x 16 output tiles,
+  // wavefront w takes tiles w, w + 4, ...; operands read from LDS (zero beyond N and ncol)
+  const int RTt = (N + 15) / 16, KS = (N + 3) / 4, CT = (ncol + 15) / 16;
+  const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  for (int tile = w; tile < RTt * CT; tile += 4) {
+    const int rt = tile % RTt, ct = tile / RTt;
+    const int ar = 16 * rt + (ln & 15), bc = 16 * ct + (ln & 15);
+    acc_t acc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = (F)0;
+    for (int s = 0; s < KS; ++s) {
+      const int k = 4 * s + (ln >> 4);
+      const F a = (ar < N && k < N) ? Ts[ar * NP1 + k] : (F)0;
+      const F b = (bc < ncol && k < N) ? bs[bc * NP1 + k] : (F)0;
+      acc = Mfma<F>::step(a, b, acc);
+    }
+    const int col = bc;
+    if (col >= ncol) continue;
+    const int ri = col & 1, kk = (col >> 1) % nk, vv = (col >> 1) / nk;
+    const int lm = g.lmbase[kk] + l - kk * g.m0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jj = 16 * rt + Mfma<F>::out_row(ln, q);
+      if (jj >= N) continue;
+      const F a = acc[q];
+      long long o = (long long)(v0 + vv) * ld + 2LL * ((long long)N * (2LL * g.S + lm) + jj) + ri;
+      double xv = (double)(tc[(long long)l * N + jj] * a);
+      if (ACC) xv += xvec[o];
+      if (FIN) {
+        const long long oo = 2LL * ((long long)N * (2LL * g.S + lm) + jj) + ri;
+        fo.y[(long long)(v0 + vv) * fo.ldy + oo] = final_value(fo, v0 + vv, oo, (kk == 0 && ri == 1) ? 0.0 : xv);
+      } else {
+        xvec[o] = xv;
+      }
     }
   }
   if (FIN && l == 0) {
