@@ -37,6 +37,17 @@ SINGLE_KERNEL_STAGES = {
     "radial_prep": "sc::k_radial_prep<float, 3>",
     "project_rhs": "sc::k_project_rhs<float, false, 3>",
 }
+
+
+def stage_kernels(tuning):
+    """The kernel of each single-kernel stage under the autotuner's choices (FP32 transforms)."""
+    k = dict(SINGLE_KERNEL_STAGES)
+    if tuning is not None:
+        if tuning["ring_fp32"] >= 0:
+            k["ring"] = "sc::k_ring<float, 0>"
+        if not tuning["anal_folded"]:
+            k["legendre_anal"] = "sc::k_gemm_batched<float>"
+    return k
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "hbm_traffic_L128_N48_nvec16.json")
 
 
@@ -117,6 +128,8 @@ def run(args):
     t0 = time.time()
     plan.factor()
     t_factor = time.time() - t0
+    # kernel choice by measurement at this shell and batch (sc_autotune), before any timing
+    tuning = None if args.no_autotune else plan.autotune(nvec, reps=5)
 
     ri, ro = RI_RO
     X = si.random_state(lay, 301, amp=BASE_AMP, p=3.0, t_offset=lambda x: ro * ri / ((x + ri + ro) / 2) - ri)
@@ -165,6 +178,8 @@ def run(args):
                         refine_mixed=args.refine_mixed,
                         mixed_solve=sc.SC_MIXED_SOLVE_FP32 if alt == "fp32" else sc.SC_MIXED_SOLVE_FP64)
         plan2.factor()
+        if not args.no_autotune:
+            plan2.autotune(nvec, reps=5)
         plan2.set_base(Xd, C, J)
         r2 = timed(plan2, sc.SC_MIXED)
         Y2 = torch.empty_like(Y)
@@ -194,7 +209,8 @@ def run(args):
     prof = mixed["prof"]
     # the dominant single-kernel stage of the mixed path (the chain solve is seven kernels and
     # the temperature solve runs beside it on a second stream)
-    dom = max((k for k in SINGLE_KERNEL_STAGES if k in prof and prof[k][1]), key=lambda k: prof[k][0])
+    kernels = stage_kernels(tuning)
+    dom = max((k for k in kernels if k in prof and prof[k][1]), key=lambda k: prof[k][0])
     ms, cnt = prof[dom]
     avg_s = ms / 1e3 / max(cnt, 1)
     # launches per jvp call differ per stage; the work table is per call
@@ -202,7 +218,7 @@ def run(args):
     fl, by = work.get(dom, (0.0, 0.0))
     fl /= max(per_call, 1)
     by /= max(per_call, 1)
-    kname = SINGLE_KERNEL_STAGES[dom]
+    kname = kernels[dom]
     traffic = measured_traffic(kname)
     if dom in ("legendre_synth", "legendre_anal"):
         roof = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": PEAK["fp32"], "unit": "TFLOP/s"}
@@ -237,6 +253,7 @@ def run(args):
         "mixed_vs_fp64_max_rel": mixed_vs_fp64,
         "mixed_other_solve": other,
         "factor_s": t_factor,
+        "tuning": tuning,
         "set_base_s": t_base,
         "roofline": roof,
         "stages_mixed": stages,
@@ -329,6 +346,7 @@ def main():
                     help="with --mixed-solve fp32: FP64 refinement passes (FP64 residual + FP64 correction)")
     ap.add_argument("--no-alt-solve", action="store_true", help="do not time the other mixed-path solve")
     ap.add_argument("--no-newton", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default kernel choices")
     ap.add_argument("--restart", type=int, default=100)
     ap.add_argument("--max-matvec", type=int, default=300)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",

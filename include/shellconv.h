@@ -157,6 +157,26 @@ int sc_profile(sc_plan* plan, int enable);
 int sc_profile_read(sc_plan* plan, double* ms_total, long long* count, int nstages);
 const char* sc_last_error(void);
 
+/* Kernel choice by measurement (the transforms of Sec. 3.1 at this plan's L, M, m0, N).  Times
+ * one transform pass (spectral prep, Legendre synthesis, azimuthal transforms and products,
+ * Legendre analysis) of nvec zero vectors for every candidate, `reps` timed passes after one
+ * untimed pass each, on `stream`, and keeps the fastest in the plan for later calls:
+ *   ring kernel, per precision: the register-transform kernel (where N_phi = N1 N2 has one and
+ *     N_phi >= 3K + 1) or the LDS kernel with 2^k rings per workgroup, k = 0 .. the LDS limit;
+ *   analysis: the folded matrix-core kernel (where N_theta <= 256) or the plain batched GEMM,
+ *     timed in FP32 and used by both precisions.
+ * Results are unchanged in value (every candidate computes the same sums).  Allocates a
+ * scratch vector block (nvec * n_real doubles) for the call.  nvec: 1 .. nvec_max; reps >= 1.
+ * report (may be NULL): the choices (ring_fp32/ring_fp64: -1 register kernel, k >= 0 LDS kernel
+ * with 2^k rings; anal_folded: 1 or 0), the best times in ms per pass and the number of
+ * candidates timed.  Errors: SC_ERR_ARG (sizes), SC_ERR_STATE (the stage profiler is on).
+ * Calls that overlap with other calls on the plan race. */
+typedef struct {
+  int ring_fp32, ring_fp64, anal_folded, ncand;
+  double ms_fp32, ms_fp64;
+} sc_tune_report;
+int sc_autotune(sc_plan* plan, int nvec, int reps, sc_tune_report* report, void* stream);
+
 /* Ragged batches of problems (plans of different L, M, m0, N, Ek, Ra, ...) on one device, e.g.
  * the points of a continuation in (Ra, Ek) (Sec. 4).  sc_batch_jvp applies the Jacobian of every
  * plan to its own vectors, each plan on a stream branch of its own forked from `stream` and

@@ -47,6 +47,11 @@ class _NewtonOpts(ctypes.Structure):
                 ("J", ctypes.c_longlong), ("forcing", ctypes.c_void_p)]
 
 
+class _TuneReport(ctypes.Structure):
+    _fields_ = [("ring_fp32", ctypes.c_int), ("ring_fp64", ctypes.c_int), ("anal_folded", ctypes.c_int),
+                ("ncand", ctypes.c_int), ("ms_fp32", ctypes.c_double), ("ms_fp64", ctypes.c_double)]
+
+
 class _NewtonReport(ctypes.Structure):
     _fields_ = [("newton_steps", ctypes.c_int), ("matvecs", ctypes.c_int), ("converged", ctypes.c_int),
                 ("rnorm", ctypes.c_double * 65), ("step_matvecs", ctypes.c_int * 64), ("C", ctypes.c_double)]
@@ -80,6 +85,7 @@ def load_library(path: str = LIB_PATH):
         "sc_newton": [vp, vp, ctypes.POINTER(d), ctypes.POINTER(_NewtonOpts), ctypes.POINTER(_NewtonReport), vp],
         "sc_profile": [vp, i],
         "sc_profile_read": [vp, ctypes.POINTER(d), ctypes.POINTER(ll), i],
+        "sc_autotune": [vp, i, i, ctypes.POINTER(_TuneReport), vp],
         "sc_batch_create": [ctypes.POINTER(vp), ctypes.POINTER(vp), i],
         "sc_batch_destroy": [vp],
         "sc_batch_jvp": [vp, ctypes.POINTER(i), ctypes.POINTER(vp), ctypes.POINTER(vp), i, vp],
@@ -101,7 +107,7 @@ STAGES = ["radial_prep", "legendre_synth", "ring", "legendre_anal", "project_rhs
 def exported_symbols():
     return ["sc_plan_create", "sc_plan_destroy", "sc_layout", "sc_set_params", "sc_factor", "sc_step",
             "sc_newton_residual", "sc_set_base", "sc_jvp", "sc_newton", "sc_profile", "sc_profile_read",
-            "sc_last_error", "sc_batch_create", "sc_batch_destroy", "sc_batch_jvp"]
+            "sc_last_error", "sc_batch_create", "sc_batch_destroy", "sc_batch_jvp", "sc_autotune"]
 
 
 def _check(rc):
@@ -192,6 +198,14 @@ class Plan:
         cnt = (ctypes.c_longlong * n)()
         _check(_lib.sc_profile_read(self._h, ms, cnt, n))
         return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+    def autotune(self, nvec=1, reps=5, stream=None):
+        """Times the kernel candidates of the transforms and keeps the fastest (sc_autotune);
+        returns the choices and best times."""
+        r = _TuneReport()
+        _check(_lib.sc_autotune(self._h, int(nvec), int(reps), ctypes.byref(r), _stream(stream)))
+        return {"ring_fp32": r.ring_fp32, "ring_fp64": r.ring_fp64, "anal_folded": r.anal_folded,
+                "candidates": r.ncand, "ms_fp32": r.ms_fp32, "ms_fp64": r.ms_fp64}
 
     def newton(self, x, C=0.0, J=-1, tol=1e-10, gmres_tol=1e-10, restart=40, max_newton=20, max_matvec=400,
                prec=SC_FP64, forcing=None, stream=None):

@@ -80,6 +80,7 @@ struct sc_plan {
   int refine64 = 1, refine32 = 1;
   bool mixed_fp32_solve = false;  // SC_MIXED_SOLVE_FP32
   bool ring_reg32 = true, ring_reg64 = false;  // register-transform ring kernel where N_phi has one
+  int ring_rtl32 = -1, ring_rtl64 = -1;         // LDS ring kernel: log2 rings per workgroup (-1: the LDS limit)
   int fft_nr = 0, fft_r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   long long n_real = 0;
   bool factored = false, have_base = false;
@@ -100,6 +101,7 @@ struct sc_plan {
   std::vector<int> h_lmb8;                 // per m: first tile-padded degree slot of the analysis outputs
   int nprob_syn = 0, nprob_ana = 0, nprob_anf = 0;
   int ana_ct = 0;                          // column tiles of the folded analysis kernel (0: GEMM path)
+  int ana_ct_fold = 0;                     // the folded kernel's column tiles where it can run (0: it cannot)
   std::vector<sc::AnaProb> h_anf;
   std::vector<sc::SynProb> h_syn;
   std::vector<sc::GemmProb> h_ana;
@@ -443,14 +445,23 @@ int ring_rt_log2(const sc::HostGrid& g) {
   return lg;
 }
 
+// Whether the register-transform ring kernel serves this N_phi and K: N_phi = N1 N2 with an
+// instantiation below, and N_phi >= 3K + 1 (the LDS copy of the sums, 26 (K+1) values per ring,
+// fits the field buffer of 10 (N_phi + 1)).
+static bool ring_reg_available(int nphi, int K) {
+  if (3 * K + 1 > nphi) return false;
+  switch (nphi) {
+    case 10: case 15: case 20: case 32: case 40: return true;
+    default: return false;
+  }
+}
+
 // Register-transform ring kernel for N_phi = N1 N2, if this N_phi has one and N_phi >= 3K + 1.
 // Returns false if not.
 template <class T, int MODE>
 bool launch_ring_reg(int nphi, dim3 grid, hipStream_t s, const sc::DevGrid& dg, int nvec, const T* Cs, const T* Cv,
                      const T* base, const T* fw, T Ek, T* Fs, T* Fv, double* b64, float* b32) {
-  // the LDS copy of the sums (26 (K+1) per ring) fits the field buffer (10 (N_phi + 1)) when
-  // N_phi >= 3K + 1
-  if (3 * dg.K + 1 > nphi) return false;
+  if (!ring_reg_available(nphi, dg.K)) return false;
 #define SC_RING_REG(N1, N2)                                                                                   \
   hipLaunchKernelGGL((sc::k_ring_reg<T, MODE, N1, N2>), grid, dim3(sc::ring_reg_threads<T>()), 0, s, dg, nvec, Cs, Cv, \
                      base, fw, Ek, Fs, \
@@ -494,7 +505,8 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
                        P->nprob_syn, nvec, (const T*)ws, tab, ws);
   }
   HIPCHK(hipGetLastError());
-  const int rtl = ring_rt_log2<T>(g);
+  const int rtl_set = std::is_same<T, float>::value ? P->ring_rtl32 : P->ring_rtl64;
+  const int rtl = rtl_set >= 0 ? std::min(rtl_set, ring_rt_log2<T>(g)) : ring_rt_log2<T>(g);
   const int ntile = (g.nth + (1 << rtl) - 1) >> rtl;
   dim3 grid((unsigned)((long long)nvec * g.Np * ntile));
   size_t smem = sc::ring_lds_bytes<T>(g.nphi, rtl);
@@ -1109,6 +1121,7 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
       // folded analysis: LDS grows with N_theta; beyond the CU's 160 KiB the GEMM path is used
       const size_t a64 = sc::ana_lds_bytes<double>(g.nth, g.L + 1), a32 = sc::ana_lds_bytes<float>(g.nth, g.L + 1);
       if (a64 > 160 * 1024 || g.nth > 256) P->ana_ct = 0;   // the fold covers nth/2 <= 128 nodes
+      P->ana_ct_fold = P->ana_ct;
       if (P->ana_ct > 0 && a64 > 64 * 1024) {
         for (const void* f : {(const void*)sc::k_anal<double, 1>, (const void*)sc::k_anal<double, 2>,
                               (const void*)sc::k_anal<double, 3>, (const void*)sc::k_anal<double, 5>,
@@ -1357,6 +1370,100 @@ int sc_profile_read(sc_plan* P, double* ms_total, long long* count, int nstages)
       }
     }
     P->ev_used = 0;
+  });
+}
+
+int sc_autotune(sc_plan* P, int nvec, int reps, sc_tune_report* rep, void* stream) {
+  return guarded([&] {
+    check_plan(P);
+    if (nvec < 1 || nvec > P->vcap || reps < 1) throw Fail{SC_ERR_ARG, "need 1 <= nvec <= nvec_max and reps >= 1"};
+    if (P->prof_on) throw Fail{SC_ERR_STATE, "turn the stage profiler off before sc_autotune"};
+    hipStream_t s = (hipStream_t)stream;
+    const sc::HostGrid& g = P->hg;
+    DevBuf vin;
+    vin.alloc((size_t)nvec * P->n_real * sizeof(double));
+    HIPCHK(hipMemsetAsync(vin.p, 0, vin.bytes, s));
+    struct Events {
+      hipEvent_t a = nullptr, b = nullptr;
+      ~Events() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+      }
+    } ev;
+    HIPCHK(hipEventCreate(&ev.a));
+    HIPCHK(hipEventCreate(&ev.b));
+    int ncand = 0;
+    // ms per transform pass of the current choices
+    auto time_pass = [&](auto tag) -> double {
+      typedef decltype(tag) T;
+      transforms<T>(P, sc::RING_NONLINEAR, nvec, vin.as<double>(), P->n_real, -1, s);
+      HIPCHK(hipEventRecord(ev.a, s));
+      for (int i = 0; i < reps; ++i) transforms<T>(P, sc::RING_NONLINEAR, nvec, vin.as<double>(), P->n_real, -1, s);
+      HIPCHK(hipEventRecord(ev.b, s));
+      HIPCHK(hipEventSynchronize(ev.b));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ev.a, ev.b));
+      ++ncand;
+      return (double)ms / reps;
+    };
+    // ring candidates: -1 register kernel, k >= 0 LDS kernel with 2^k rings
+    auto ring_cands = [&](auto tag) {
+      typedef decltype(tag) T;
+      std::vector<int> c;
+      if (ring_reg_available(g.nphi, g.K)) c.push_back(-1);
+      for (int k = 0; k <= ring_rt_log2<T>(g); ++k) c.push_back(k);
+      return c;
+    };
+    auto set_ring = [&](auto tag, int c) {
+      typedef decltype(tag) T;
+      if (std::is_same<T, float>::value) {
+        P->ring_reg32 = c < 0;
+        P->ring_rtl32 = c;
+      } else {
+        P->ring_reg64 = c < 0;
+        P->ring_rtl64 = c;
+      }
+    };
+    auto tune_ring = [&](auto tag, double& best, int& choice) {
+      best = 1e300;
+      for (int c : ring_cands(tag)) {
+        set_ring(tag, c);
+        const double t = time_pass(tag);
+        if (t < best) {
+          best = t;
+          choice = c;
+        }
+      }
+      set_ring(tag, choice);
+    };
+    // FP32: ring choice for each analysis path; the analysis path serves both precisions
+    double best32 = 1e300, best64 = 1e300;
+    int ring32 = 0, ring64 = 0, folded = 0;
+    std::vector<int> paths;
+    if (P->ana_ct_fold > 0) paths.push_back(1);
+    paths.push_back(0);
+    for (int f : paths) {
+      P->ana_ct = f ? P->ana_ct_fold : 0;
+      double t;
+      int c = 0;
+      tune_ring(0.0f, t, c);
+      if (t < best32) {
+        best32 = t;
+        ring32 = c;
+        folded = f;
+      }
+    }
+    P->ana_ct = folded ? P->ana_ct_fold : 0;
+    set_ring(0.0f, ring32);
+    tune_ring(0.0, best64, ring64);
+    if (rep) {
+      rep->ring_fp32 = ring32;
+      rep->ring_fp64 = ring64;
+      rep->anal_folded = folded;
+      rep->ncand = ncand;
+      rep->ms_fp32 = best32;
+      rep->ms_fp64 = best64;
+    }
   });
 }
 

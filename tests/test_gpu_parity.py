@@ -92,6 +92,33 @@ def test_jvp(lib, cfg, prec, solve, tol):
     assert max(errs) < tol
 
 
+@pytest.mark.parametrize("cfg", SMALL)
+def test_autotune_then_jvp(lib, cfg):
+    """sc_autotune times every ring and analysis candidate of the shell and keeps the fastest;
+    the Jacobian actions with the chosen kernels still match the oracle in both precisions."""
+    plan, ora, lay = _setup(lib, cfg)
+    rep = plan.autotune(nvec=4, reps=2)
+    print(f"cfg={cfg} autotune {rep}", flush=True)
+    assert rep["candidates"] >= 2 and rep["ms_fp32"] > 0 and rep["ms_fp64"] > 0
+    assert rep["ring_fp32"] >= -1 and rep["ring_fp64"] >= -1 and rep["anal_folded"] in (0, 1)
+    X = si.random_state(lay, 101, amp=(1e-2, 1e-2, 1e-2), p=2) + ora.conductive_state()
+    J = si.default_phase_slot(lay, X)
+    plan.set_base(_dev(X), 0.3, J)
+    ora.set_base(X, 0.3, J)
+    V = si.random_vectors(lay, [1001, 1002, 1003, 1004])
+    vd = _dev(V)
+    for prec, tol in ((0, 1e-11), (1, 1e-6)):
+        yd = torch.empty_like(vd)
+        plan.jvp(vd, yd, prec)
+        Y = _host(yd)
+        errs = [_rel(Y[i], ora.jvp(V[i])) for i in range(len(V))]
+        print(f"cfg={cfg} tuned prec={prec} jvp rel errs", ["%.2e" % e for e in errs], flush=True)
+        assert max(errs) < tol
+    with pytest.raises(lib.ShellConvError) as ei:
+        plan.autotune(nvec=0)
+    assert ei.value.code == 1
+
+
 def test_state_errors(lib):
     plan, ora, lay = _setup(lib, SMALL[1])
     v = torch.zeros((1, plan.n_real), dtype=torch.float64, device="cuda")
