@@ -193,6 +193,18 @@ int sc_batch_destroy(sc_batch* batch);
 int sc_batch_jvp(sc_batch* batch, const int* nvec, const double* const* v, double* const* y, sc_precision prec,
                  void* stream);
 
+/* Newton-GMRES (as sc_newton, Sec. 3.3-3.4) on every plan of a batch at once, e.g. the points
+ * of a continuation in (Ra, Ek): plan i runs on its own stream branch, forked from `stream`
+ * and joined back into it, driven by a host thread of its own, so that the problems' Krylov
+ * iterations share the device.  Arrays of nplans entries (the batch's plan order): x[i] (device,
+ * n_real of plan i, updated in place), C[i] (host, in/out), opts[i], reports[i] (host, out).
+ * Each plan needs sc_factor; sc_set_base is done by the solve itself.  Per-plan results are
+ * those of sc_newton on that plan.  Errors: SC_ERR_ARG, SC_ERR_STATE as sc_newton (the first
+ * failing plan's code and message; the other plans still finish), SC_ERR_STATE also for a plan
+ * with the stage profiler on.  Calls that overlap on one batch, or that share a plan, race. */
+int sc_batch_newton(sc_batch* batch, double* const* x, double* C, const sc_newton_opts* opts,
+                    sc_newton_report* reports, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

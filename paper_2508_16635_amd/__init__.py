@@ -89,6 +89,8 @@ def load_library(path: str = LIB_PATH):
         "sc_batch_create": [ctypes.POINTER(vp), ctypes.POINTER(vp), i],
         "sc_batch_destroy": [vp],
         "sc_batch_jvp": [vp, ctypes.POINTER(i), ctypes.POINTER(vp), ctypes.POINTER(vp), i, vp],
+        "sc_batch_newton": [vp, ctypes.POINTER(vp), ctypes.POINTER(d), ctypes.POINTER(_NewtonOpts),
+                            ctypes.POINTER(_NewtonReport), vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -107,7 +109,8 @@ STAGES = ["radial_prep", "legendre_synth", "ring", "legendre_anal", "project_rhs
 def exported_symbols():
     return ["sc_plan_create", "sc_plan_destroy", "sc_layout", "sc_set_params", "sc_factor", "sc_step",
             "sc_newton_residual", "sc_set_base", "sc_jvp", "sc_newton", "sc_profile", "sc_profile_read",
-            "sc_last_error", "sc_batch_create", "sc_batch_destroy", "sc_batch_jvp", "sc_autotune"]
+            "sc_last_error", "sc_batch_create", "sc_batch_destroy", "sc_batch_jvp", "sc_autotune",
+            "sc_batch_newton"]
 
 
 def _check(rc):
@@ -216,10 +219,13 @@ class Plan:
         c = ctypes.c_double(C)
         _check(_lib.sc_newton(self._h, _ptr(x, self.n_real), ctypes.byref(c), ctypes.byref(o), ctypes.byref(rep),
                               _stream(stream)))
-        k = rep.newton_steps
-        return c.value, {"newton_steps": k, "matvecs": rep.matvecs, "converged": bool(rep.converged),
-                         "rnorm": [rep.rnorm[i] for i in range(k + 1)],
-                         "step_matvecs": [rep.step_matvecs[i] for i in range(k)]}
+        return c.value, _report_dict(rep)
+
+
+def _report_dict(rep):
+    k = rep.newton_steps
+    return {"newton_steps": k, "matvecs": rep.matvecs, "converged": bool(rep.converged),
+            "rnorm": [rep.rnorm[i] for i in range(k + 1)], "step_matvecs": [rep.step_matvecs[i] for i in range(k)]}
 
 
 class Batch:
@@ -264,3 +270,19 @@ class Batch:
             py[i] = _ptr(y, p.n_real * k).value
         _check(_lib.sc_batch_jvp(self._h, nv, pv, py, int(prec), _stream(stream)))
         return ys
+
+    def newton(self, xs, Cs, Js, tol=1e-10, gmres_tol=1e-10, restart=40, max_newton=20, max_matvec=400,
+               prec=SC_FP64, forcings=None, stream=None):
+        """Newton-GMRES on every plan at once (sc_batch_newton), in place on xs[i] (device);
+        returns [(C_i, report dict_i)]."""
+        n = len(self.plans)
+        px = (ctypes.c_void_p * n)()
+        cs = (ctypes.c_double * n)(*[float(c) for c in Cs])
+        opts = (_NewtonOpts * n)()
+        reps = (_NewtonReport * n)()
+        for i, (p, x) in enumerate(zip(self.plans, xs)):
+            px[i] = _ptr(x, p.n_real).value
+            f = None if forcings is None or forcings[i] is None else _ptr(forcings[i], p.n_real).value
+            opts[i] = _NewtonOpts(tol, gmres_tol, restart, max_newton, max_matvec, int(prec), int(Js[i]), f)
+        _check(_lib.sc_batch_newton(self._h, px, cs, opts, reps, _stream(stream)))
+        return [(cs[i], _report_dict(reps[i])) for i in range(n)]

@@ -1570,4 +1570,52 @@ int sc_batch_jvp(sc_batch* b, const int* nvec, const double* const* v, double* c
   });
 }
 
+int sc_batch_newton(sc_batch* b, double* const* x, double* C, const sc_newton_opts* opts, sc_newton_report* reps,
+                    void* stream) {
+  return guarded([&] {
+    if (!b || !x || !C || !opts || !reps) throw Fail{SC_ERR_ARG, "null argument"};
+    HIPCHK(hipSetDevice(b->device));
+    const int n = (int)b->plans.size();
+    std::vector<long long> J(n);
+    for (int i = 0; i < n; ++i) {
+      sc_plan* P = b->plans[i];
+      const sc_newton_opts& o = opts[i];
+      if (!x[i]) throw Fail{SC_ERR_ARG, "null state"};
+      if (o.restart < 1 || o.restart > 128) throw Fail{SC_ERR_ARG, "restart must lie in 1..128"};
+      if (o.max_newton < 0 || o.max_newton > 64 || o.max_matvec < 1) throw Fail{SC_ERR_ARG, "bad iteration caps"};
+      if (o.prec != SC_FP64 && o.prec != SC_MIXED) throw Fail{SC_ERR_ARG, "unknown precision"};
+      if (!P->factored) throw Fail{SC_ERR_STATE, "every plan needs sc_factor for its current (Ek, dt)"};
+      if (P->prof_on) throw Fail{SC_ERR_STATE, "turn the stage profiler off before a batch call"};
+      J[i] = check_slot(P, o.J);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipEventRecord(b->ev_start, s));
+    for (int i = 0; i < n; ++i) HIPCHK(hipStreamWaitEvent(b->br[i], b->ev_start, 0));
+    // one host thread per plan: each Newton-GMRES reads its norms back on its own branch
+    std::vector<int> code(n, SC_OK);
+    std::vector<std::string> msg(n);
+    std::vector<std::thread> th;
+    for (int i = 0; i < n; ++i)
+      th.emplace_back([&, i] {
+        try {
+          HIPCHK(hipSetDevice(b->device));
+          newton_impl(b->plans[i], x[i], &C[i], opts[i], J[i], &reps[i], b->br[i]);
+        } catch (const Fail& f) {
+          code[i] = f.code;
+          msg[i] = f.msg;
+        } catch (const std::exception& e) {
+          code[i] = SC_ERR_INTERNAL;
+          msg[i] = e.what();
+        }
+      });
+    for (auto& t : th) t.join();
+    for (int i = 0; i < n; ++i) {
+      HIPCHK(hipEventRecord(b->ev_done[i], b->br[i]));
+      HIPCHK(hipStreamWaitEvent(s, b->ev_done[i], 0));
+    }
+    for (int i = 0; i < n; ++i)
+      if (code[i] != SC_OK) throw Fail{code[i], "plan " + std::to_string(i) + ": " + msg[i]};
+  });
+}
+
 }  // extern "C"

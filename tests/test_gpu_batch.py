@@ -95,3 +95,58 @@ def test_batch_errors(sc):
     b.jvp(vs, ys, 1)
     torch.cuda.synchronize()
     b.close()
+
+
+def _manufactured(p, shell):
+    """R_F(X) = R(X) - R(X*) with the exact root X* (drift speed C* through the phase slot), and a
+    start 1e-3 |X*| away from it."""
+    from oracle.solver import Problem
+    L, M, m0, N, Ek, Ra, seed = shell
+    lay = si.Layout(L, M, m0, N)
+    ora = Problem(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=200.0)
+    Xs = ora.clean(si.random_state(lay, seed, amp=(0.1, 0.1, 0.1), p=2) + ora.conductive_state())
+    J = si.default_phase_slot(lay, Xs)
+    Cs = 0.5
+    F = torch.empty(p.n_real, dtype=torch.float64, device="cuda")
+    p.newton_residual(torch.from_numpy(Xs).cuda(), Cs, F)
+    F.neg_()
+    d = ora.clean(si.random_state(lay, seed + 1, p=2))
+    d[J] = 0.0
+    X0 = Xs + 1e-3 * np.linalg.norm(Xs) * d / np.linalg.norm(d)
+    return Xs, Cs, J, F, X0
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_batch_newton_matches_per_plan(sc, prec):
+    """sc_batch_newton runs every plan's Newton-GMRES on its own branch; each plan must end where
+    sc_newton on that plan alone ends (same kernels, same order: bit-identical) and at its root."""
+    plans, probs = [], []
+    for shell in SHELLS[:2]:
+        L, M, m0, N, Ek, Ra, seed = shell
+        print(f"plan L={L} N={N}", flush=True)
+        p = sc.Plan(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=200.0, nvec_max=1)
+        p.factor()
+        plans.append(p)
+        probs.append(_manufactured(p, shell))
+    kw = dict(tol=1e-10, gmres_tol=1e-10 if prec == 0 else 1e-6, restart=40, max_newton=10, max_matvec=200, prec=prec)
+    ref = []
+    for i, (p, (Xs, Cs, J, F, X0)) in enumerate(zip(plans, probs)):
+        print(f"per-plan newton {i}", flush=True)
+        x = torch.from_numpy(X0).cuda()
+        C, rep = p.newton(x, Cs + 1e-3, J, forcing=F, **kw)
+        ref.append((x.cpu().numpy(), C, rep))
+    b = sc.Batch(plans)
+    xs = [torch.from_numpy(X0).cuda() for (_, _, _, _, X0) in probs]
+    print("batch newton", flush=True)
+    out = b.newton(xs, [Cs + 1e-3 for (_, Cs, _, _, _) in probs], [J for (_, _, J, _, _) in probs],
+                   forcings=[F for (_, _, _, F, _) in probs], **kw)
+    torch.cuda.synchronize()
+    for i, ((C, rep), x, (Xr, Cr, repr_), (Xs, Cs, J, F, X0)) in enumerate(zip(out, xs, ref, probs)):
+        X = x.cpu().numpy()
+        print(f"plan {i}: batch {rep} per-plan {repr_}", flush=True)
+        assert rep["converged"] and rep["rnorm"][-1] <= 1e-10
+        assert np.array_equal(X, Xr) and C == Cr and rep == repr_
+        assert np.linalg.norm(X - Xs) <= 1e-8 * np.linalg.norm(Xs)
+    b.close()
+    for p in plans:
+        p.close()
