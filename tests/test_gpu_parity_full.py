@@ -164,3 +164,48 @@ def test_wide_theta_fallback_paths(sc):
         print(f"L={L} N_theta={plan.layout['ntheta']} vec {i}: fp64 {e64:.2e} mixed {e32:.2e}", flush=True)
         assert e64 < 1e-11
         assert e32 < 1e-6
+
+
+# the throughput-stress shell: Ra = 1.2 * 6.5 Ek^(-1/3)
+SHELL_C5 = (255, 255, 12, 64, 3e-6, 541.0, 501, (8.0, 8.0, 0.1))
+
+
+def test_stress_shell_linearization(sc):
+    """L = M = 255, m0 = 12, N = 64 (N_theta = 384: batched-GEMM analysis; N_phi = 64: LDS ring
+    kernel), beyond the oracle's reach: the FP64 Jacobian action equals central differences of
+    the library's FP64 residual R(X, C), which is exactly quadratic in (X, C), for two step
+    sizes; the mixed path agrees with the FP64 one within 1e-6 on 16 vectors."""
+    L, M, m0, N, Ek, Ra, seed, amp = SHELL_C5
+    print(f"plan L={L} N={N}", flush=True)
+    plan = sc.Plan(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=200.0, nvec_max=16)
+    plan.factor()
+    lay = si.Layout(L, M, m0, N)
+    assert lay.n_real == plan.n_real
+    ri, ro = 0.35 / 0.65, 1.0 / 0.65
+    X = si.random_state(lay, seed, amp=amp, p=3.0, t_offset=lambda x: ro * ri / ((x + ri + ro) / 2) - ri)
+    J = si.default_phase_slot(lay, X)
+    C = 0.5
+    Xd = _dev(X)
+    plan.set_base(Xd, C, J)
+    V = _dev(si.random_vectors(lay, range(seed * 10, seed * 10 + 16)))
+    Y64, Ym = torch.empty_like(V), torch.empty_like(V)
+    plan.jvp(V, Y64, sc.SC_FP64)
+    plan.jvp(V, Ym, sc.SC_MIXED)
+    y64, ym = Y64.cpu().numpy(), Ym.cpu().numpy()
+    worst = max(_rel(ym[i], y64[i]) for i in range(16))
+    print(f"L={L} N={N} max mixed-vs-fp64 over 16 vectors {worst:.2e}", flush=True)
+    assert worst <= 1e-6
+    Rp, Rm = torch.empty_like(Xd), torch.empty_like(Xd)
+    for i in (0, 15):
+        v = V[i]
+        c = float(v[J])
+        u = v.clone()
+        u[J] = 0.0
+        for eps in (1.0, 1e-2):
+            plan.newton_residual(Xd + eps * u, C + eps * c, Rp, norm=False)
+            plan.newton_residual(Xd - eps * u, C - eps * c, Rm, norm=False)
+            cd = ((Rp - Rm) / (2 * eps)).cpu().numpy()
+            e = _rel(cd, y64[i])
+            print(f"vector {i} eps {eps:g}: central difference vs FP64 jvp {e:.2e}", flush=True)
+            assert e <= 1e-10
+    plan.close()
