@@ -23,7 +23,13 @@ import time
 
 import numpy as np
 
-WORKLOAD = dict(L=128, M=128, m0=10, N=48, Ek=1e-5, Pr=1.0, Ra=362.0, dt=200.0)
+WORKLOADS = {
+    # the shell the metric is quoted on
+    "c3": dict(L=128, M=128, m0=10, N=48, Ek=1e-5, Pr=1.0, Ra=362.0, dt=200.0),
+    # the throughput-stress shell (context only: no oracle baseline, no Newton run)
+    "stress": dict(L=255, M=255, m0=12, N=64, Ek=3e-6, Pr=1.0, Ra=541.0, dt=200.0),
+}
+WORKLOAD = WORKLOADS["c3"]
 RI_RO = (0.35 / 0.65, 1.0 / 0.65)   # inner and outer radius, gap 1
 BASE_AMP = (8.0, 8.0, 0.1)   # e, f amplitudes give kinetic-energy density ~25 at this shell
 PEAK = {"hbm": 8000.0, "fp32": 157.3, "fp64": 78.6}   # GB/s, TFLOP/s (MI355X published)
@@ -39,9 +45,12 @@ SINGLE_KERNEL_STAGES = {
 }
 
 
-def stage_kernels(tuning):
+def stage_kernels(tuning, N=48):
     """The kernel of each single-kernel stage under the autotuner's choices (FP32 transforms)."""
     k = dict(SINGLE_KERNEL_STAGES)
+    rt = (N + 15) // 16
+    k["radial_prep"] = f"sc::k_radial_prep<float, {rt}>"
+    k["project_rhs"] = f"sc::k_project_rhs<float, false, {rt}>"
     if tuning is not None:
         if tuning["ring_fp32"] >= 0:
             k["ring"] = "sc::k_ring<float, 0>"
@@ -74,7 +83,7 @@ def measured_traffic(kernel):
     return t["kernels"][kernel]["bytes"]
 
 
-def stage_work(lay, nvec, prec_bytes, factor_bytes, nblocks, refine):
+def stage_work(lay, nvec, prec_bytes, factor_bytes, nblocks, refine, dp_only=True):
     """Algorithmic flops and bytes per launch of each stage (measurement)."""
     L, N, Np, nth, nphi, K1, S = (lay["L"], lay["N"], lay["Np"], lay["ntheta"], lay["nphi"],
                                   lay["K"] + 1, lay["S"])
@@ -91,13 +100,14 @@ def stage_work(lay, nvec, prec_bytes, factor_bytes, nblocks, refine):
     # counted with the mirror folding (each degree parity contracts over the northern half); the
     # vector inputs are read once (their m P/sin half is derived from the dP half)
     fl = sum(2.0 * Np * nvec * n * (4 * nth + 4 * 2 * nth) for n in nl) / 2
-    by = prec_bytes * (K1 * Np * nvec * (4 * nth + 4 * nth) + Np * nvec * 8 * S + 3 * nth * S // 2)
+    by = prec_bytes * (K1 * Np * nvec * (4 * nth + (4 if dp_only else 8) * nth) + Np * nvec * 8 * S + 3 * nth * S // 2)
     w["legendre_anal"] = (fl, by)
     rings = Np * nth * nvec
-    # ring: reads 18 rows (6 scalar sums, 12 vector fields) and writes 8 rows (4 scalar, 4 vector)
-    # per (ring, harmonic), plus the 9 base fields per (r_p, node, point) in the linear mode
+    # ring: reads 18 rows (6 scalar sums, 12 vector fields) and writes 8 rows (4 scalar, 4 vector;
+    # 12 when the batched-GEMM analysis needs both halves of the vector rows) per (ring,
+    # harmonic), plus the 9 base fields per (r_p, node, point) in the linear mode
     w["ring"] = (rings * (2.0 * 13 * K1 * nphi * 2 + 60 * nphi),
-                 prec_bytes * (rings * (18 + 8) * K1 + Np * nth * 9 * nphi))
+                 prec_bytes * (rings * (18 + (8 if dp_only else 12)) * K1 + Np * nth * 9 * nphi))
     nreal = 6 * N * S
     w["radial_prep"] = (nvec * Np * S * 7 * N * 4.0, 8.0 * nvec * nreal + prec_bytes * nvec * Np * 16 * S)
     w["project_rhs"] = (nvec * S * 2 * (Np * Np + 3 * N * Np + N * N) * 2.0,
@@ -205,11 +215,12 @@ def run(args):
     N = W["N"]
     nblocks = sum(W["L"] - max(k * W["m0"], 1) + 1 for k in range(lay_d["K"] + 1)) * 2
     fbytes = 3 * nblocks * N * N * (8 if args.mixed_solve == "fp32" else 16)
-    work = stage_work(lay_d, nvec, 4, fbytes, nblocks, refine=args.refine_mixed if args.mixed_solve == "fp32" else 0)
+    work = stage_work(lay_d, nvec, 4, fbytes, nblocks, refine=args.refine_mixed if args.mixed_solve == "fp32" else 0,
+                      dp_only=tuning is None or bool(tuning["anal_folded"]))
     prof = mixed["prof"]
     # the dominant single-kernel stage of the mixed path (the chain solve is seven kernels and
     # the temperature solve runs beside it on a second stream)
-    kernels = stage_kernels(tuning)
+    kernels = stage_kernels(tuning, W["N"])
     dom = max((k for k in kernels if k in prof and prof[k][1]), key=lambda k: prof[k][0])
     ms, cnt = prof[dom]
     avg_s = ms / 1e3 / max(cnt, 1)
@@ -219,7 +230,7 @@ def run(args):
     fl /= max(per_call, 1)
     by /= max(per_call, 1)
     kname = kernels[dom]
-    traffic = measured_traffic(kname)
+    traffic = measured_traffic(kname) if args.workload == "c3" else None   # counters taken on that shell
     if dom in ("legendre_synth", "legendre_anal"):
         roof = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": PEAK["fp32"], "unit": "TFLOP/s"}
     else:
@@ -233,7 +244,8 @@ def run(args):
     stages = {k: {"ms_per_step": v[0] / max(args.steps, 1), "launches_per_step": v[1] / max(args.steps, 1)}
               for k, v in prof.items() if v[1]}
     out = {
-        "metric": "Jacobian-vector products/s at L=128,N=48; mixed vs FP64 at 1e-10 residual",
+        "metric": "Jacobian-vector products/s at L=128,N=48; mixed vs FP64 at 1e-10 residual"
+                  if args.workload == "c3" else f"Jacobian-vector products/s at L={W['L']},N={W['N']} (stress shell)",
         "value": value,
         "unit": "jvp/s",
         "n_gpus": 1,
@@ -245,7 +257,8 @@ def run(args):
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "rotating-shell jvp L=M=128 m0=10 N=48 Ek=1e-5 Ra=362 dt=200",
+        "config": {"workload": f"rotating-shell jvp L=M={W['L']} m0={W['m0']} N={W['N']} Ek={W['Ek']:g} "
+                               f"Ra={W['Ra']:g} dt={W['dt']:g}",
                    "nvec": nvec, "mixed_solve": args.mixed_solve,
                    "refine_mixed": args.refine_mixed if args.mixed_solve == "fp32" else 0, "N_p": lay_d["Np"], "N_theta": lay_d["ntheta"], "N_phi": lay_d["nphi"],
                    "n_real": plan.n_real},
@@ -347,6 +360,8 @@ def main():
     ap.add_argument("--no-alt-solve", action="store_true", help="do not time the other mixed-path solve")
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default kernel choices")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c3",
+                    help="c3: the metric's shell; stress: L=M=255, N=64 (no oracle baseline, no Newton run)")
     ap.add_argument("--restart", type=int, default=100)
     ap.add_argument("--max-matvec", type=int, default=300)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -363,6 +378,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 5}), flush=True)
         return
+    global WORKLOAD
+    WORKLOAD = WORKLOADS[args.workload]
+    if args.workload != "c3":   # the oracle and the Newton problem are sized for the metric's shell
+        args.no_cpu_baseline = True
+        args.no_newton = True
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no multi-GPU path.",
               file=sys.stderr)
