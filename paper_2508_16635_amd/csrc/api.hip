@@ -446,8 +446,9 @@ int ring_rt_log2(const sc::HostGrid& g) {
 }
 
 // Whether the register-transform ring kernel serves this N_phi and K: N_phi = N1 N2 with an
-// instantiation below, and N_phi >= 3K + 1 (the LDS copy of the sums, 26 (K+1) values per ring,
-// fits the field buffer of 10 (N_phi + 1)).
+// instantiation below, and N_phi >= 3K + 1 (its loops over harmonics have the compile-time
+// bound (N_phi - 1)/3 + 1, and the LDS copy of the sums, 18 (K+1) values per ring, fits the
+// field buffer of 10 (N_phi + 1)).
 static bool ring_reg_available(int nphi, int K) {
   if (3 * K + 1 > nphi) return false;
   switch (nphi) {

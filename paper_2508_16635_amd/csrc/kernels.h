@@ -3,9 +3,12 @@
 //
 // Data layouts (nv = vectors in the batch, q = field component, ri = Re/Im):
 //   canonical state  v[vec][field e,f,T][lm][j][ri]          (FP64; lm packs (m, l))
-//   synthesis input  Gs[k][(vec, q<3, ri, rp)][l-m]  Gv[k][(vec, q<5, ri, rp)][l-m]  (operand order)
-//   synthesis output Cs[k][(vec, q<3, ri, rp)][theta]  Cv[k][(vec, q<5, ri, rp)][2 nth]
-//   analysis input   Fs[k][(vec, rp, q<2, ri)][theta]  Fv[k][(vec, rp, q<2, ri)][2 nth]
+//   synthesis input  Gs[k][(vec, q<3, ri, rp)][l-m]  Gv[k][groups of four rows, syn_vec_row][l-m]
+//                    (operand order)
+//   synthesis output Cs[k][(vec, q<3, ri, rp)][theta]  Cv[k][(vec, f<12, rp)][theta] (the six
+//                    vector fields U_th, U_ph, w_th, w_ph, dT/dth, dT/dph, Re and Im)
+//   analysis input   Fs[k][(vec, rp, q<2, ri)][theta]  Fv[k][(vec, rp, q<2, ri)][2 nth] (dP half,
+//                    m P/sin half; only the dP half is written while the folded analysis runs)
 //   analysis output  As[k][(l-m)/8][(vec, rp, q<2, ri)][(l-m)%8]  (likewise Av; the GEMM
 //                    fallback writes As[k][(vec, rp, q<2, ri)][l-m])
 //   base fields      base[rp][field<9][phi][theta]
@@ -829,7 +832,7 @@ __global__ void __launch_bounds__(256) k_gemm_batched(const GemmProb* __restrict
 }
 
 // ------------------------------------------------------------------------------------------
-// K3/K4/K5: per ring (vec, r_p, theta): combine the synthesized Legendre sums into the
+// K3/K4/K5: per ring (vec, r_p, theta): take the synthesized Legendre sums as the
 // Fourier coefficients of the 9 physical fields (U, omega, grad T), inverse real FFT along
 // phi, pointwise products, forward real FFT of (W_r, W_theta, W_phi, Q), and write the
 // analysis inputs.  The FFTs are mixed-radix Stockham passes (radix 4, 2, 3, 5) between two
@@ -1267,7 +1270,7 @@ __global__ void __launch_bounds__(ring_reg_threads<T>()) k_ring_reg(DevGrid g, i
   constexpr int NT = ring_reg_threads<T>();                         // threads per workgroup
   static_assert(5 * RR <= NT && NT % 64 == 0, "a thread per inverse transform");
   constexpr int NPT = (RR * N + NT - 1) / NT;                       // product points per thread
-  // the fields of the transforms; first the copy of the Legendre sums [26 rows][K1][RR rings]
+  // the fields of the transforms; first the copy of the Legendre sums [18 rows][K1][RR rings]
   __shared__ cz<T> X[5 * RR * LS];
   T* Gl = reinterpret_cast<T*>(X);
   const int K1 = g.K + 1, nth = g.nth, Np = g.Np;
