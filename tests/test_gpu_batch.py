@@ -81,7 +81,7 @@ def test_batch_matches_eager(sc, prec):
 
 
 def test_batch_errors(sc):
-    plans, vs, _ = _setup(sc, [1, 1, 0])
+    plans, vs, bases = _setup(sc, [1, 1, 0])
     with pytest.raises(sc.ShellConvError) as ei:
         sc.Batch([plans[0], plans[0]])
     assert ei.value.code == 1
@@ -94,6 +94,33 @@ def test_batch_errors(sc):
     plans[0].profile(False)
     b.jvp(vs, ys, 1)
     torch.cuda.synchronize()
+    # batched Newton: a bad phase slot (an Re entry) and a bad restart are argument errors, a
+    # plan with the stage profiler on a state error; nothing runs in either case
+    xs = [torch.from_numpy(X).cuda() for (_, X, _) in bases]
+    Js = [J for (_, _, J) in bases]
+    with pytest.raises(sc.ShellConvError) as ei:
+        b.newton(xs, [0.3] * 3, [Js[0] - 1] + Js[1:], max_newton=1)
+    assert ei.value.code == 1
+    with pytest.raises(sc.ShellConvError) as ei:
+        b.newton(xs, [0.3] * 3, Js, restart=0, max_newton=1)
+    assert ei.value.code == 1
+    plans[1].profile(True)
+    with pytest.raises(sc.ShellConvError) as ei:
+        b.newton(xs, [0.3] * 3, Js, max_newton=1)
+    assert ei.value.code == 2
+    plans[1].profile(False)
+    # autotune: sizes and the profiler are checked first
+    with pytest.raises(sc.ShellConvError) as ei:
+        plans[0].autotune(nvec=plans[0].layout["nvec_max"] + 1)
+    assert ei.value.code == 1
+    with pytest.raises(sc.ShellConvError) as ei:
+        plans[0].autotune(nvec=1, reps=0)
+    assert ei.value.code == 1
+    plans[0].profile(True)
+    with pytest.raises(sc.ShellConvError) as ei:
+        plans[0].autotune(nvec=1)
+    assert ei.value.code == 2
+    plans[0].profile(False)
     b.close()
 
 
