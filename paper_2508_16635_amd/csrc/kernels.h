@@ -362,12 +362,14 @@ __global__ void __launch_bounds__(256) k_radial_prep(DevGrid g, const double* __
 // m P/sin have the parity (-1)^(l-m) under the mirror, dP/dtheta the opposite one.  For the
 // northern nodes the sums over even l - m (S_e) and over odd l - m (S_o) are two products
 // C_e = A_e B_e, C_o = A_o B_o with half the columns and half the depth; the outputs are then
-// S_e + S_o at the node and S_e - S_o (P, m P/sin) or S_o - S_e (dP/dtheta) at its mirror,
-// written in the natural layout C[row][theta] (vector rows: [dP part | m P/sin part]).
-// A (spectral profiles, rows (vec, r_p, q), depth [even l | odd l]) and B (tables, northern
-// columns) are stored in MFMA operand order, so every wavefront streams its operands from L2
-// into registers with unit-stride loads, one k-step ahead, with no LDS.  A workgroup owns
-// kSynTM row tiles and 4 kSynTN column tiles, wavefront w the column tiles w, w+4, ...
+// S_e + S_o at the node and S_e - S_o (P, m P/sin) or S_o - S_e (dP/dtheta) at its mirror.
+// A (spectral profiles, depth [even l | odd l]; scalar rows (vec, q, r_p), vector rows in groups,
+// syn_vec_row) and B (tables, northern columns) are stored in MFMA operand order, so every
+// wavefront streams its operands from L2 into registers with unit-stride loads, one k-step
+// ahead, with no LDS.  A workgroup owns kSynTM row tiles and 4 kSynTN column tiles: for the
+// scalar problem wavefront w takes the column tiles w, w+4 and writes C[row][theta]; for the
+// vector problem it takes the dP and the m P/sin tile of the same nodes and writes the six
+// fields C[(vec, field row, r_p)][theta].
 constexpr int kSynTM = 4;
 constexpr int kSynTN = 2;
 
