@@ -100,6 +100,16 @@ int sc_step(sc_plan* plan, const double* x, double C, double* x_next, void* stre
 /* r = B_C(x) - x (Sec. 3.3, eq:finalrhs).  If rnorm_host is non-NULL the stream is
  * synchronized and ||r||_2 is stored there; SC_ERR_NONFINITE if it is not finite. */
 int sc_newton_residual(sc_plan* plan, const double* x, double C, double* r, double* rnorm_host, void* stream);
+/* For callers that cannot allocate or synchronize (code under HIP stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): r = B_C(x) - x as sc_newton_residual, and ||r||_2
+ * written to the caller's device scalar *rnorm_dev on the stream (no host synchronization, no
+ * finiteness check: a NaN or Inf is written as computed).  Calls no allocating routine.  The
+ * norm's partial sums live in a fixed device array of the library (1024 doubles per GPU, held
+ * until the process ends), so n_real is limited to 1024 * 8192 = 8388608 values (SC_ERR_ARG
+ * beyond).  Every call on one GPU shares that array: calls that overlap on one GPU race.
+ * x, r, rnorm_dev: device memory owned by the caller.  Errors as sc_newton_residual. */
+int sc_newton_residual_noalloc(sc_plan* plan, const double* x, double C, double* r, double* rnorm_dev,
+                               void* stream);
 /* Base state of the Jacobian: caches the physical U, omega, grad T of x (FP64 and FP32) and
  * M x.  J is the phase slot (index of an Im entry with m > 0) or -1 for no drift unknown. */
 int sc_set_base(sc_plan* plan, const double* x, double C, long long J, void* stream);

@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH):
         "sc_factor": [vp, vp],
         "sc_step": [vp, vp, d, vp, vp],
         "sc_newton_residual": [vp, vp, d, vp, ctypes.POINTER(d), vp],
+        "sc_newton_residual_noalloc": [vp, vp, d, vp, vp, vp],
         "sc_set_base": [vp, vp, d, ll, vp],
         "sc_jvp": [vp, i, vp, ll, vp, ll, i, vp],
         "sc_newton": [vp, vp, ctypes.POINTER(d), ctypes.POINTER(_NewtonOpts), ctypes.POINTER(_NewtonReport), vp],
@@ -110,7 +111,7 @@ def exported_symbols():
     return ["sc_plan_create", "sc_plan_destroy", "sc_layout", "sc_set_params", "sc_factor", "sc_step",
             "sc_newton_residual", "sc_set_base", "sc_jvp", "sc_newton", "sc_profile", "sc_profile_read",
             "sc_last_error", "sc_batch_create", "sc_batch_destroy", "sc_batch_jvp", "sc_autotune",
-            "sc_batch_newton"]
+            "sc_batch_newton", "sc_newton_residual_noalloc"]
 
 
 def _check(rc):
@@ -178,6 +179,13 @@ class Plan:
         _check(_lib.sc_newton_residual(self._h, _ptr(x, self.n_real), C, _ptr(out, self.n_real),
                                        ctypes.byref(rn) if norm else None, _stream(stream)))
         return rn.value if norm else None
+
+    def newton_residual_noalloc(self, x, C, out, rnorm, stream=None):
+        """out = B_C(x) - x and rnorm[0] = ||out|| on the device, with no allocation and no
+        synchronization (sc_newton_residual_noalloc); rnorm: a float64 CUDA tensor."""
+        _check(_lib.sc_newton_residual_noalloc(self._h, _ptr(x, self.n_real), C, _ptr(out, self.n_real),
+                                               _ptr(rnorm, 1), _stream(stream)))
+        return out
 
     def set_base(self, x, C=0.0, J=-1, stream=None):
         _check(_lib.sc_set_base(self._h, _ptr(x, self.n_real), C, int(J), _stream(stream)))

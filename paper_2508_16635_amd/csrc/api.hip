@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <thread>
@@ -225,6 +226,33 @@ int guarded(F&& f) {
 }
 
 inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Scratch of the allocation-free residual (sc_newton_residual_noalloc): partial sums of squares,
+// one per chunk of kNoAllocChunk elements, in a file-scope device array that every GPU the
+// library runs on holds until the process ends.  Host code never passes the array's name to a
+// kernel: its device address on each device is looked up once, with that device current, when
+// the first plan is created there, and kept in g_scratch_dev.
+constexpr int kNoAllocParts = 1024;
+constexpr long long kNoAllocChunk = 8192;
+static __device__ __align__(256) double scratch[kNoAllocParts];
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_dev;   // indexed by device ordinal
+
+void resolve_scratch(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+  if (g_scratch_dev[dev]) return;
+  void* p = nullptr;
+  HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw Fail{SC_ERR_HIP, "hipGetSymbolAddress returned a null address for the scratch array"};
+  g_scratch_dev[dev] = static_cast<double*>(p);
+}
+
+double* scratch_on(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return dev >= 0 && dev < (int)g_scratch_dev.size() ? g_scratch_dev[dev] : nullptr;
+}
+
 
 // Stage profiler: brackets one launch with events on its stream (no effect when disabled).
 struct Prof {
@@ -966,6 +994,7 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     HIPCHK(hipGetDeviceCount(&ndev));
     if (p.device < 0 || p.device >= ndev) throw Fail{SC_ERR_ARG, "bad device ordinal"};
     HIPCHK(hipSetDevice(p.device));
+    resolve_scratch(p.device);
     HIPCHK(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
@@ -1325,6 +1354,35 @@ int sc_newton_residual(sc_plan* P, const double* x, double C, double* r, double*
       *rnorm_host = std::sqrt(ss);
       if (!std::isfinite(*rnorm_host)) throw Fail{SC_ERR_NONFINITE, "residual norm is not finite"};
     }
+  });
+}
+
+int sc_newton_residual_noalloc(sc_plan* P, const double* x, double C, double* r, double* rnorm_dev, void* stream) {
+  return guarded([&] {
+    check_plan(P);
+    if (!x || !r || !rnorm_dev) throw Fail{SC_ERR_ARG, "null vector"};
+    if (!P->factored) throw Fail{SC_ERR_STATE, "sc_factor has not run for the current (Ek, dt)"};
+    const long long n = P->n_real;
+    const long long nparts = (n + kNoAllocChunk - 1) / kNoAllocChunk;
+    if (nparts > kNoAllocParts)
+      throw Fail{SC_ERR_ARG, "n_real = " + std::to_string(n) + " exceeds the allocation-free limit of " +
+                                 std::to_string((long long)kNoAllocParts * kNoAllocChunk) + " values"};
+    double* parts = scratch_on(P->prm.device);
+    if (!parts) throw Fail{SC_ERR_INTERNAL, "scratch address of the device was not resolved"};
+    hipStream_t s = (hipStream_t)stream;
+    step_into_xbuf(P, x, C, s);
+    {
+      Prof _p(P, SC_STAGE_FINALIZE, s);
+      hipLaunchKernelGGL(sc::k_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, P->dg(), 1, P->xbuf.as<const double>(), x, n,
+                         (long long)-1, r, n, 1);
+    }
+    HIPCHK(hipGetLastError());
+    // every partial is written before it is read: nothing needs clearing
+    hipLaunchKernelGGL(sc::k_sumsq_parts, dim3((unsigned)nparts), dim3(256), 0, s, n, (const double*)r, kNoAllocChunk,
+                       parts);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(sc::k_sqrt_sum, dim3(1), dim3(256), 0, s, (int)nparts, (const double*)parts, rnorm_dev);
+    HIPCHK(hipGetLastError());
   });
 }
 

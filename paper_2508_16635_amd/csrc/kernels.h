@@ -2263,4 +2263,37 @@ __global__ void k_sumsq(long long n, const double* __restrict__ x, long long ld,
   if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+// Partial sums of squares: parts[b] = sum of x[i]^2 over chunk b = [b chunk, (b + 1) chunk) of
+// [0, n), one workgroup per chunk, fixed summation order.
+__global__ void __launch_bounds__(256) k_sumsq_parts(long long n, const double* __restrict__ x, long long chunk,
+                                                     double* __restrict__ parts) {
+  __shared__ double red[256];
+  const long long b0 = (long long)blockIdx.x * chunk;
+  const long long b1 = b0 + chunk < n ? b0 + chunk : n;
+  double s = 0.0;
+  for (long long i = b0 + threadIdx.x; i < b1; i += blockDim.x) s += x[i] * x[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) parts[blockIdx.x] = red[0];
+}
+
+// out[0] = sqrt(sum of parts[0..nparts)), one workgroup, fixed summation order.
+__global__ void __launch_bounds__(256) k_sqrt_sum(int nparts, const double* __restrict__ parts,
+                                                  double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += parts[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sqrt(red[0]);
+}
+
 }  // namespace sc
