@@ -320,14 +320,27 @@ def newton_runs(args, plan, C, lay):
     return res
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(args, X, C, J, lay):
-    """The FP64 oracle timed on the host cores on a bounded sample of the same workload."""
+    """The FP64 oracle timed on the host cores on a bounded sample of the same workload, with the
+    BLAS threads it gets by default and with one thread."""
     import seeded_inputs as si
     from oracle.solver import Problem
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
+        threadpool_limits = None
         cores = os.cpu_count()
     W = WORKLOAD
     p = Problem(W["L"], W["M"], W["m0"], W["N"], Ek=W["Ek"], Ra=W["Ra"], Pr=W["Pr"], dt=W["dt"])
@@ -339,9 +352,18 @@ def cpu_baseline(args, X, C, J, lay):
     for i in range(args.cpu_sample):
         p.jvp(V[i])
     dt_ = time.perf_counter() - t0
-    return {"value": args.cpu_sample / dt_, "unit": "jvp/s", "cores": cores, "kind": "oracle",
-            "sample": f"{args.cpu_sample} single-vector jvps of the same shell and base state "
-                      f"(oracle factor and base setup excluded)"}
+    out = {"value": args.cpu_sample / dt_, "unit": "jvp/s", "cores": cores, "kind": "oracle",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "sample": f"{args.cpu_sample} single-vector jvps of the same shell and base state "
+                     f"(oracle factor and base setup excluded)"}
+    if threadpool_limits is not None and args.cpu_sample_1t > 0:
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            for i in range(args.cpu_sample_1t):
+                p.jvp(V[i])
+            out["value_1thread"] = args.cpu_sample_1t / (time.perf_counter() - t0)
+            out["sample_1thread"] = f"{args.cpu_sample_1t} single-vector jvps with one BLAS thread"
+    return out
 
 
 def main():
@@ -352,6 +374,7 @@ def main():
     ap.add_argument("--nvec", type=int, default=16)
     ap.add_argument("--nvectors", type=int, default=200)
     ap.add_argument("--cpu-sample", type=int, default=20)
+    ap.add_argument("--cpu-sample-1t", type=int, default=3, help="oracle jvps timed with one BLAS thread")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed-solve", choices=("fp64", "fp32"), default="fp64",
                     help="implicit solve of the mixed path: one FP64 solve, or an FP32 solve plus refinement")

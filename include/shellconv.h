@@ -65,7 +65,15 @@ typedef struct {
                              solve                                                             */
   int mixed_solve;        /* implicit solve of SC_MIXED: SC_MIXED_SOLVE_FP64 (0 = default) or
                              SC_MIXED_SOLVE_FP32                                               */
+  int coriolis;           /* SC_CORIOLIS_IMPLICIT (0, default) or SC_CORIOLIS_EXPLICIT           */
 } sc_params;
+
+/* Treatment of the Coriolis force.  SC_CORIOLIS_IMPLICIT: in the implicit operator K, coupling
+ * e_l with f_{l+-1} (Sec. 3.2, eq:impcor_e_final / eq:impcor_f_final): block-tridiagonal chains.
+ * SC_CORIOLIS_EXPLICIT: the variant the paper compares against (Sec. 3.1, eq:expcor_e /
+ * eq:expcor_f with the force of eq:defineFexp): -2 e_z x U is evaluated on the grid with the other
+ * explicit forces, and K is block diagonal (the chain solves then run with zero couplings). */
+enum { SC_CORIOLIS_IMPLICIT = 0, SC_CORIOLIS_EXPLICIT = 1 };
 
 /* Implicit solve of the mixed path.  SC_MIXED_SOLVE_FP64: one solve with the FP64 factors (its
  * error, ~1e-11 relative, is far below that of the FP32 transforms).  SC_MIXED_SOLVE_FP32: a
@@ -130,7 +138,7 @@ int sc_jvp(sc_plan* plan, int nvec, const double* v, long long ldv, double* y, l
 typedef struct {
   double tol;             /* stop when ||R||_2 <= tol (absolute)                         */
   double gmres_tol;       /* relative tolerance of each GMRES solve                      */
-  int restart;            /* GMRES restart length, 1..128                                */
+  int restart;            /* GMRES restart length, 1..1024 (the basis holds restart + 1 vectors) */
   int max_newton;         /* Newton steps                                                */
   int max_matvec;         /* Jacobian actions per Newton step                            */
   int prec;               /* sc_precision of the Jacobian action                         */
@@ -170,7 +178,9 @@ const char* sc_last_error(void);
 /* Kernel choice by measurement (the transforms of Sec. 3.1 at this plan's L, M, m0, N).  Times
  * one transform pass (spectral prep, Legendre synthesis, azimuthal transforms and products,
  * Legendre analysis) of nvec zero vectors for every candidate, `reps` timed passes after one
- * untimed pass each, on `stream`, and keeps the fastest in the plan for later calls:
+ * untimed pass each, on `stream`, and keeps the fastest in the plan for later calls.  The pass
+ * uses the Jacobian action's linearized products (the base fields of sc_set_base read at every
+ * point) when a base state is set, else the nonlinear products of the step.  Candidates:
  *   ring kernel, per precision: the register-transform kernel (where N_phi = N1 N2 has one and
  *     N_phi >= 3K + 1) or the LDS kernel with 2^k rings per workgroup, k = 0 .. the LDS limit;
  *   analysis: the folded matrix-core kernel (where N_theta <= 256) or the plain batched GEMM,
@@ -184,6 +194,7 @@ const char* sc_last_error(void);
 typedef struct {
   int ring_fp32, ring_fp64, anal_folded, ncand;
   double ms_fp32, ms_fp64;
+  int linear_mode;        /* 1: timed with the Jacobian action's products (a base state was set) */
 } sc_tune_report;
 int sc_autotune(sc_plan* plan, int nvec, int reps, sc_tune_report* report, void* stream);
 

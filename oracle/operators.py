@@ -16,6 +16,12 @@ imperfect", Sec. 3.3); the IMEX step of eq:discrete then reads (M - dt K) X+ = M
 Buoyancy is explicit (it sits in F^implicit, eq:defineFimp), so the factor depends on
 (dt, Ek, Pr) only.
 
+Explicit-Coriolis variant (Sec. 3.1, eq:expcor_e / eq:expcor_f with the force of eq:defineFexp):
+the Coriolis force -2 e_z x U stays in the explicit force, so K keeps only the viscous and
+thermal-diffusion parts (no 2im/r^2 terms, no kappa couplings) and the matrices are block
+diagonal, one N x N block per (l, m) and potential.  The chains below are then kept with zero
+coupling blocks, which the banded solve handles unchanged.
+
 Boundary conditions by row replacement (Sec. 3.1), read as collocation at the
 Gauss-Lobatto nodes: e and T rows j = 0 and N-1 become Dirichlet rows; f rows 0 and N-1
 become f = 0 and rows 1 and N-2 become d_r f = 0 at r_o and r_i respectively.
@@ -58,8 +64,11 @@ def kappa_from_paper(l: int, m: int, which: str) -> float:
 class Operators:
     """Blocks of M and A = M - dt K for one grid and (Ek, Pr, dt)."""
 
-    def __init__(self, g: Grid, Ek: float, Pr: float, dt: float):
+    def __init__(self, g: Grid, Ek: float, Pr: float, dt: float, coriolis: str = "implicit"):
+        if coriolis not in ("implicit", "explicit"):
+            raise ValueError("coriolis must be 'implicit' or 'explicit'")
         self.g, self.Ek, self.Pr, self.dt = g, Ek, Pr, dt
+        self.cor = 1.0 if coriolis == "implicit" else 0.0     # weight of the Coriolis terms in K
         rad = g.rad
         self.r = rad.r
         self.D = rad.D
@@ -82,13 +91,13 @@ class Operators:
     def K_e_self(self, l, m):
         lam = l * (l + 1.0)
         return (np.diag(self.Ek * lam / self.r ** 2) @ self.Lop(l)
-                + np.diag(2j * m / self.r ** 2))
+                + self.cor * np.diag(2j * m / self.r ** 2))
 
     def K_f_self(self, l, m):
         lam = l * (l + 1.0)
         Lo = self.Lop(l)
         return (-np.diag(self.Ek * lam / self.r ** 2) @ Lo @ Lo
-                - np.diag(2j * m / self.r ** 2) @ Lo)
+                - self.cor * np.diag(2j * m / self.r ** 2) @ Lo)
 
     def K_couple(self, l, m, nb):
         """Coriolis coupling of row l to the neighbour l+nb (nb = -1 or +1), same form for
@@ -100,7 +109,7 @@ class Operators:
         else:
             kap = kappa(l + 1, m)
             op = np.diag(-(l + 1.0) / r) - self.D
-        return -np.diag(2.0 / r ** 2) @ op * kap + 0j
+        return -self.cor * np.diag(2.0 / r ** 2) @ op * kap + 0j
 
     def A_T(self, l):
         lam = l * (l + 1.0)

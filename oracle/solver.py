@@ -12,6 +12,11 @@ and the phase-slot trick): for v with c = v_J and u = v with u_J = 0,
 
 Slots without physical content (e, f at l = 0; imaginary parts at m = 0) are set to 0 by
 the step map, so R = -X and y = -v there.
+
+coriolis="explicit" is the variant of Sec. 3.1 (eq:expcor_e / eq:expcor_f, force of
+eq:defineFexp): -2 e_z x U (-2 e_z x u in the Jacobian action) joins the explicit force before
+the curl projections, and the implicit operator loses its Coriolis terms (block diagonal).
+The roots of R do not change, up to the radial truncation of the projected Coriolis force.
 """
 from __future__ import annotations
 
@@ -23,11 +28,13 @@ from .operators import ChainSolver, Operators, TSolver
 
 
 class Problem:
-    def __init__(self, L, M, m0, N, Ek, Ra, Pr, dt, eta=0.35, Np=0, nth=0, nphi=0, refine=2):
+    def __init__(self, L, M, m0, N, Ek, Ra, Pr, dt, eta=0.35, Np=0, nth=0, nphi=0, refine=2,
+                 coriolis="implicit"):
         self.g = Grid(L, M, m0, N, eta=eta, Np=Np, nth=nth, nphi=nphi)
         self.Ek, self.Ra, self.Pr, self.dt = Ek, Ra, Pr, dt
         self.refine = refine
-        self.ops = Operators(self.g, Ek, Pr, dt)
+        self.coriolis = coriolis
+        self.ops = Operators(self.g, Ek, Pr, dt, coriolis=coriolis)
         self._chains = None
         self._tsol = None
         g = self.g
@@ -137,6 +144,8 @@ class Problem:
         e, f, T = physics.unpack(g, self.clean(X))
         F = physics.fields(g, physics.spectral_inputs(g, e, f, T))
         W, Q = physics.nonlinear_forces(F, self.Ek)
+        if self.coriolis == "explicit":
+            W = tuple(a + b for a, b in zip(W, physics.coriolis_force(g, F)))
         Ne, Nf, NT = physics.project(g, W, Q)
         Bf = self.buoyancy(T)
         Me, Mf, MT = self.M_apply(e, f, T)
@@ -175,6 +184,8 @@ class Problem:
         e, f, T = physics.unpack(g, self.clean(u))
         Fu = physics.fields(g, physics.spectral_inputs(g, e, f, T))
         W, Q = physics.linearized_forces(b["F"], Fu, self.Ek)
+        if self.coriolis == "explicit":
+            W = tuple(a + b_ for a, b_ in zip(W, physics.coriolis_force(g, Fu)))
         Ne, Nf, NT = physics.project(g, W, Q)
         Bf = self.buoyancy(T)
         Me, Mf, MT = self.M_apply(e, f, T)

@@ -16,6 +16,8 @@ SC_FP64 = 0
 SC_MIXED = 1
 SC_MIXED_SOLVE_FP64 = 1   # mixed_solve of Plan
 SC_MIXED_SOLVE_FP32 = 2
+SC_CORIOLIS_IMPLICIT = 0   # coriolis of Plan
+SC_CORIOLIS_EXPLICIT = 1
 _ERRORS = {1: "SC_ERR_ARG", 2: "SC_ERR_STATE", 3: "SC_ERR_NONFINITE", 4: "SC_ERR_NOMEM",
            5: "SC_ERR_HIP", 6: "SC_ERR_INTERNAL"}
 
@@ -32,7 +34,8 @@ class _Params(ctypes.Structure):
                 ("Pr", ctypes.c_double), ("dt", ctypes.c_double),
                 ("nr_phys", ctypes.c_int), ("ntheta", ctypes.c_int), ("nphi", ctypes.c_int),
                 ("device", ctypes.c_int), ("nvec_max", ctypes.c_int),
-                ("refine_fp64", ctypes.c_int), ("refine_mixed", ctypes.c_int), ("mixed_solve", ctypes.c_int)]
+                ("refine_fp64", ctypes.c_int), ("refine_mixed", ctypes.c_int), ("mixed_solve", ctypes.c_int),
+                ("coriolis", ctypes.c_int)]
 
 
 class _Layout(ctypes.Structure):
@@ -49,7 +52,8 @@ class _NewtonOpts(ctypes.Structure):
 
 class _TuneReport(ctypes.Structure):
     _fields_ = [("ring_fp32", ctypes.c_int), ("ring_fp64", ctypes.c_int), ("anal_folded", ctypes.c_int),
-                ("ncand", ctypes.c_int), ("ms_fp32", ctypes.c_double), ("ms_fp64", ctypes.c_double)]
+                ("ncand", ctypes.c_int), ("ms_fp32", ctypes.c_double), ("ms_fp64", ctypes.c_double),
+                ("linear_mode", ctypes.c_int)]
 
 
 class _NewtonReport(ctypes.Structure):
@@ -141,10 +145,10 @@ class Plan:
     """One shell discretization with its tables, factors and workspaces on one GPU."""
 
     def __init__(self, L, M, m0, N, Ek, Ra, Pr=1.0, dt=200.0, radius_ratio=0.35, device=0, nvec_max=16,
-                 refine_fp64=-1, refine_mixed=-1, nr_phys=0, ntheta=0, nphi=0, mixed_solve=0):
+                 refine_fp64=-1, refine_mixed=-1, nr_phys=0, ntheta=0, nphi=0, mixed_solve=0, coriolis=0):
         lib = load_library()
         p = _Params(L, M, m0, N, radius_ratio, Ek, Ra, Pr, dt, nr_phys, ntheta, nphi, device, nvec_max,
-                    refine_fp64, refine_mixed, mixed_solve)
+                    refine_fp64, refine_mixed, mixed_solve, coriolis)
         h = ctypes.c_void_p()
         _check(lib.sc_plan_create(ctypes.byref(h), ctypes.byref(p)))
         self._h = h
@@ -191,7 +195,11 @@ class Plan:
         _check(_lib.sc_set_base(self._h, _ptr(x, self.n_real), C, int(J), _stream(stream)))
 
     def jvp(self, v, out, prec=SC_MIXED, stream=None):
-        """v, out: [nvec, n_real] (or [n_real]) float64 CUDA tensors."""
+        """v, out: [nvec, n_real] (or [n_real]) float64 CUDA tensors of the same shape."""
+        if v.dim() not in (1, 2) or v.shape[-1] != self.n_real:
+            raise ValueError("v must be [n_real] or [nvec, n_real]")
+        if tuple(out.shape) != tuple(v.shape):
+            raise ValueError("out must have the shape of v")
         nvec = 1 if v.dim() == 1 else v.shape[0]
         ld = self.n_real if v.dim() == 1 else v.stride(0)
         ldy = self.n_real if out.dim() == 1 else out.stride(0)
@@ -216,7 +224,8 @@ class Plan:
         r = _TuneReport()
         _check(_lib.sc_autotune(self._h, int(nvec), int(reps), ctypes.byref(r), _stream(stream)))
         return {"ring_fp32": r.ring_fp32, "ring_fp64": r.ring_fp64, "anal_folded": r.anal_folded,
-                "candidates": r.ncand, "ms_fp32": r.ms_fp32, "ms_fp64": r.ms_fp64}
+                "candidates": r.ncand, "ms_fp32": r.ms_fp32, "ms_fp64": r.ms_fp64,
+                "linear_mode": bool(r.linear_mode)}
 
     def newton(self, x, C=0.0, J=-1, tol=1e-10, gmres_tol=1e-10, restart=40, max_newton=20, max_matvec=400,
                prec=SC_FP64, forcing=None, stream=None):
@@ -271,6 +280,8 @@ class Batch:
                 nv[i], pv[i], py[i] = 0, None, None
                 continue
             k = 1 if v.dim() == 1 else v.shape[0]
+            if v.dim() not in (1, 2) or v.shape[-1] != p.n_real:
+                raise ValueError("vectors of plan %d must be [n_real] or [nvec, n_real]" % i)
             if y.shape != v.shape:
                 raise ValueError("output shape differs from input shape")
             nv[i] = k

@@ -91,7 +91,7 @@ struct sc_plan {
   // grid / radial data
   DevBuf d_lmk, d_lml, d_lmbase, d_r, d_rp, d_E, d_ED, d_ED2, d_P, d_Dp, d_D, d_D2, d_D4;
   DevBuf d_ET, d_EDT, d_ED2T, d_DT, d_D2T, d_D4T, d_rtiles, d_PT, d_DpT, d_ptiles;
-  DevBuf d_EF, d_PF, d_D2F, d_DF, d_D4F, d_qtiles;
+  DevBuf d_EF, d_PF, d_D2F, d_DF, d_D4F, d_qtiles, d_cst;
   int nqtiles = 0;
   int nrtiles = 0, nptiles = 0;
   // tables and workspaces per precision
@@ -191,6 +191,8 @@ struct sc_plan {
     g.ana_tiled = ana_ct > 0 ? 1 : 0;
     g.lmbase8 = d_lmb8.as<int>();
     g.fv_dp_only = g.ana_tiled;   // the folded analysis derives the m P/sin half
+    g.cor_explicit = prm.coriolis == SC_CORIOLIS_EXPLICIT ? 1 : 0;
+    g.cst = d_cst.as<double>();
     return g;
   }
   sc::PhysParams pp() const {
@@ -200,6 +202,7 @@ struct sc_plan {
     p.Pr = prm.Pr;
     p.dt = prm.dt;
     p.ro = hg.ro;
+    p.cor = prm.coriolis == SC_CORIOLIS_EXPLICIT ? 0.0 : 1.0;
     return p;
   }
 };
@@ -252,7 +255,6 @@ double* scratch_on(int dev) {
   std::lock_guard<std::mutex> lk(g_scratch_mu);
   return dev >= 0 && dev < (int)g_scratch_dev.size() ? g_scratch_dev[dev] : nullptr;
 }
-
 
 // Stage profiler: brackets one launch with events on its stream (no effect when disabled).
 struct Prof {
@@ -990,6 +992,8 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     if (p.mixed_solve != 0 && p.mixed_solve != SC_MIXED_SOLVE_FP64 && p.mixed_solve != SC_MIXED_SOLVE_FP32)
       throw Fail{SC_ERR_ARG, "mixed_solve must be 0, SC_MIXED_SOLVE_FP64 or SC_MIXED_SOLVE_FP32"};
     P->mixed_fp32_solve = (p.mixed_solve == SC_MIXED_SOLVE_FP32);
+    if (p.coriolis != SC_CORIOLIS_IMPLICIT && p.coriolis != SC_CORIOLIS_EXPLICIT)
+      throw Fail{SC_ERR_ARG, "coriolis must be SC_CORIOLIS_IMPLICIT or SC_CORIOLIS_EXPLICIT"};
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
     if (p.device < 0 || p.device >= ndev) throw Fail{SC_ERR_ARG, "bad device ordinal"};
@@ -1020,6 +1024,14 @@ int sc_plan_create(sc_plan** out, const sc_params* params) {
     upload(P->d_D, g.D);
     upload(P->d_D2, g.D2);
     upload(P->d_D4, g.D4);
+    {
+      std::vector<double> cst(2 * (size_t)g.nth);
+      for (int j = 0; j < g.nth; ++j) {
+        cst[j] = g.ct[j];
+        cst[g.nth + j] = g.st[j];
+      }
+      upload(P->d_cst, cst);
+    }
     auto transpose = [](const std::vector<double>& A, int rows, int cols) {
       std::vector<double> T((size_t)rows * cols);
       for (int i = 0; i < rows; ++i)
@@ -1217,7 +1229,7 @@ int sc_factor(sc_plan* P, void* stream) {
     const sc::HostGrid& g = P->hg;
     std::vector<sc::ChainFactor> ch;
     std::vector<sc::TFactor> tf;
-    sc::OpParams op{P->prm.Ek, P->prm.Pr, P->prm.dt};
+    sc::OpParams op{P->prm.Ek, P->prm.Pr, P->prm.dt, P->prm.coriolis == SC_CORIOLIS_EXPLICIT ? 0.0 : 1.0};
     int nth = (int)std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
     sc::factor_all(g, op, ch, tf, nth, kSeg);
     const int N = g.N;
@@ -1452,12 +1464,15 @@ int sc_autotune(sc_plan* P, int nvec, int reps, sc_tune_report* rep, void* strea
     HIPCHK(hipEventCreate(&ev.a));
     HIPCHK(hipEventCreate(&ev.b));
     int ncand = 0;
+    // the jvp's products (linear mode, base fields read per point) once a base state is set,
+    // else the nonlinear products of the step
+    const int mode = P->have_base ? sc::RING_LINEAR : sc::RING_NONLINEAR;
     // ms per transform pass of the current choices
     auto time_pass = [&](auto tag) -> double {
       typedef decltype(tag) T;
-      transforms<T>(P, sc::RING_NONLINEAR, nvec, vin.as<double>(), P->n_real, -1, s);
+      transforms<T>(P, mode, nvec, vin.as<double>(), P->n_real, -1, s);
       HIPCHK(hipEventRecord(ev.a, s));
-      for (int i = 0; i < reps; ++i) transforms<T>(P, sc::RING_NONLINEAR, nvec, vin.as<double>(), P->n_real, -1, s);
+      for (int i = 0; i < reps; ++i) transforms<T>(P, mode, nvec, vin.as<double>(), P->n_real, -1, s);
       HIPCHK(hipEventRecord(ev.b, s));
       HIPCHK(hipEventSynchronize(ev.b));
       float ms = 0.f;
@@ -1522,6 +1537,7 @@ int sc_autotune(sc_plan* P, int nvec, int reps, sc_tune_report* rep, void* strea
       rep->ncand = ncand;
       rep->ms_fp32 = best32;
       rep->ms_fp64 = best64;
+      rep->linear_mode = mode == sc::RING_LINEAR ? 1 : 0;
     }
   });
 }
@@ -1544,7 +1560,7 @@ int sc_newton(sc_plan* P, double* x, double* C, const sc_newton_opts* o, sc_newt
   return guarded([&] {
     check_plan(P);
     if (!x || !C || !o || !rep) throw Fail{SC_ERR_ARG, "null argument"};
-    if (o->restart < 1 || o->restart > 128) throw Fail{SC_ERR_ARG, "restart must lie in 1..128"};
+    if (o->restart < 1 || o->restart > 1024) throw Fail{SC_ERR_ARG, "restart must lie in 1..1024"};
     if (o->max_newton < 0 || o->max_newton > 64 || o->max_matvec < 1) throw Fail{SC_ERR_ARG, "bad iteration caps"};
     if (o->prec != SC_FP64 && o->prec != SC_MIXED) throw Fail{SC_ERR_ARG, "unknown precision"};
     if (!P->factored) throw Fail{SC_ERR_STATE, "sc_factor has not run for the current (Ek, dt)"};
@@ -1640,7 +1656,7 @@ int sc_batch_newton(sc_batch* b, double* const* x, double* C, const sc_newton_op
       sc_plan* P = b->plans[i];
       const sc_newton_opts& o = opts[i];
       if (!x[i]) throw Fail{SC_ERR_ARG, "null state"};
-      if (o.restart < 1 || o.restart > 128) throw Fail{SC_ERR_ARG, "restart must lie in 1..128"};
+      if (o.restart < 1 || o.restart > 1024) throw Fail{SC_ERR_ARG, "restart must lie in 1..1024"};
       if (o.max_newton < 0 || o.max_newton > 64 || o.max_matvec < 1) throw Fail{SC_ERR_ARG, "bad iteration caps"};
       if (o.prec != SC_FP64 && o.prec != SC_MIXED) throw Fail{SC_ERR_ARG, "unknown precision"};
       if (!P->factored) throw Fail{SC_ERR_STATE, "every plan needs sc_factor for its current (Ek, dt)"};

@@ -74,10 +74,15 @@ struct DevGrid {
   // (-D3, D2, D1, -D0) is a signed permutation of its dP half (D0..D3), and the folded analysis
   // takes it from there
   int fv_dp_only;
+  // explicit-Coriolis variant (Sec. 3.1, eq:defineFexp): the ring products add -2 e_z x U to the
+  // force; cst holds cos(theta_j), sin(theta_j) of the Gauss-Legendre nodes ([2][nth])
+  int cor_explicit;
+  const double* cst;
 };
 
 struct PhysParams {
   double Ek, Ra, Pr, dt, ro;
+  double cor;   // weight of the Coriolis terms of the implicit operator (1, or 0 when explicit)
 };
 
 // Final output of a Jacobian action, written by the last solve: y = clean(x) - u, where clean
@@ -846,6 +851,19 @@ __global__ void __launch_bounds__(256) k_gemm_batched(const GemmProb* __restrict
 // MODE 2: synthesis only, the 9 fields are written to base (and base32 if non-null).
 enum { RING_LINEAR = 0, RING_NONLINEAR = 1, RING_SYNTH = 2 };
 
+// Explicit-Coriolis variant: adds -2 e_z x u to the force (W_r, W_th, W_ph) at Gauss-Legendre node
+// th, where u = (f[0], f[1], f[2]) is the velocity of the products (U in the nonlinear step, the
+// perturbation u in the Jacobian action: the force is linear).  e_z x u = (-sin u_ph, -cos u_ph,
+// cos u_th + sin u_r).  Rings beyond the last node (never written) use the last node.
+template <class T>
+__device__ inline void coriolis_force(const DevGrid& g, int th, const T* f, T& W0, T& W1, T& W2) {
+  const int j = th < g.nth ? th : g.nth - 1;
+  const T c = (T)g.cst[j], s = (T)g.cst[g.nth + j];
+  W0 += (T)2 * s * f[2];
+  W1 += (T)2 * c * f[2];
+  W2 -= (T)2 * (c * f[1] + s * f[0]);
+}
+
 // Rows of the Legendre sums a ring reads per harmonic: 0..5 the scalar sums (U_r, w_r, dT/dr;
 // Re, Im), 6..17 the vector fields (U_th, U_ph, w_th, w_ph, (1/r) dT/dth, (1/(r sin)) dT/dph;
 // Re, Im).  Field f = 0..9 of the transforms (U_r, U_th, U_ph, w_r, w_th, w_ph, dT/dr, dT/dth,
@@ -1127,6 +1145,7 @@ __global__ void __launch_bounds__(kRingThreads) k_ring(DevGrid g, int nvec, int 
       W2 = Ek * ((b[0] * f[4] - b[1] * f[3]) + (f[0] * b[4] - f[1] * b[3]));
       Q = -((b[0] * f[6] + b[1] * f[7] + b[2] * f[8]) + (f[0] * b[6] + f[1] * b[7] + f[2] * b[8]));
     }
+    if (g.cor_explicit) coriolis_force<T>(g, th, f, W0, W1, W2);
     X[lp(zb + p)] = {W0, Q};
     X[lp(zb + N + p)] = {W1, W2};
   }
@@ -1380,6 +1399,7 @@ __global__ void __launch_bounds__(ring_reg_threads<T>()) k_ring_reg(DevGrid g, i
       W2 = Ek * ((b[0] * f[4] - b[1] * f[3]) + (f[0] * b[4] - f[1] * b[3]));
       Q = -((b[0] * f[6] + b[1] * f[7] + b[2] * f[8]) + (f[0] * b[6] + f[1] * b[7] + f[2] * b[8]));
     }
+    if (g.cor_explicit) coriolis_force<T>(g, th, f, W0, W1, W2);
     X[(0 * RR + r) * LS + pt] = {W0, Q};
     X[(1 * RR + r) * LS + pt] = {W1, W2};
   }
@@ -2126,7 +2146,8 @@ __global__ void __launch_bounds__(256) k_residual64(DevGrid g, PhysParams ph, in
   const double sg = (c == 0) ? -1.0 : 1.0;
   const double* b = bvec + (long long)vec * ld;
   double* rr = rvec + (long long)vec * ld;
-  const double kap_lo = kappa_dev(lw, m), kap_hi = kappa_dev(lw + 1, m);
+  const double kap_lo = ph.cor * kappa_dev(lw, m), kap_hi = ph.cor * kappa_dev(lw + 1, m);
+  const double cm = ph.cor * 2.0 * m;   // 2 m of the diagonal Coriolis term (0 when explicit)
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     // values from other lanes first (every lane takes part)
@@ -2159,11 +2180,11 @@ __global__ void __launch_bounds__(256) k_residual64(DevGrid g, PhysParams ph, in
           double cv;
           if (f == 0) {
             const double L_ = y[1][q] - lam / r2 * xv;
-            cv = a * xv - ph.dt * (a * L_ + sg * 2.0 * m / r2 * xo);
+            cv = a * xv - ph.dt * (a * L_ + sg * cm / r2 * xo);
           } else {
             const double L_ = y[3][q] - lam / r2 * xv, Lo = D2f_o - lam / r2 * xo;
             const double L2 = y[4][q] - lam * y[5][q] - lam / r2 * y[3][q] + lam * lam / (r2 * r2) * xv;
-            cv = -a * L_ + ph.dt * (a * L2 + sg * 2.0 * m / r2 * Lo);
+            cv = -a * L_ + ph.dt * (a * L2 + sg * cm / r2 * Lo);
           }
           // Coriolis coupling to the other potential at l-1 and l+1
           const int fo = 1 - f;

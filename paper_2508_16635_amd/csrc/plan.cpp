@@ -255,7 +255,7 @@ struct Blocks {
     for (int i = 0; i < N; ++i) {
       double r = G.r[i], r2 = r * r;
       double a = op.Ek * lam / r2;        // Ek lambda / r^2
-      cplx cor(0.0, 2.0 * m / r2);        // 2 i m / r^2
+      cplx cor(0.0, op.cor * 2.0 * m / r2);   // 2 i m / r^2 (0 in the explicit-Coriolis variant)
       for (int j = 0; j < N; ++j) {
         double Lij = G.D2[(size_t)i * N + j] - (i == j ? lam / r2 : 0.0);   // L_l
         cplx v;
@@ -288,7 +288,7 @@ struct Blocks {
     for (int i = 0; i < N; ++i) {
       double r = G.r[i];
       // K_couple = -(2/r^2) kap (c/r - D);  -dt K_couple = dt (2/r^2) kap (c/r - D)
-      double pre = op.dt * 2.0 / (r * r) * kap;
+      double pre = op.cor * op.dt * 2.0 / (r * r) * kap;
       for (int j = 0; j < N; ++j) B[(size_t)i * N + j] = pre * ((i == j ? c / r : 0.0) - G.D[(size_t)i * N + j]);
     }
     for (int row : bc_rows(t)) std::fill(B.begin() + (size_t)row * N, B.begin() + (size_t)(row + 1) * N, cplx(0.0));

@@ -54,6 +54,7 @@ struct TFactor {                              // temperature block per l (real)
 
 struct OpParams {
   double Ek, Pr, dt;
+  double cor = 1.0;   // weight of the Coriolis terms of K: 1 implicit, 0 explicit-Coriolis variant
 };
 
 // Builds and factors every chain and temperature block; nthreads host threads.

@@ -5,6 +5,8 @@ import numpy as np
 import pytest
 
 import seeded_inputs as si
+from oracle.solver import Problem
+from parity_util import FP64_BLOCK, check
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -70,6 +72,14 @@ def test_batch_matches_eager(sc, prec):
             print(f"call {rep} plan {i}: max rel diff {err:.2e}", flush=True)
             assert err <= 1e-14
         _ = _eager(plans[:1], vs[:1], 1 - prec)
+    # the batch outputs against the oracle, every vector of every shell
+    tol, btol = (1e-12, FP64_BLOCK) if prec == 0 else (1e-6, 1e-5)
+    for i, ((L, M, m0, N, Ek, Ra, seed), (lay, X, J), v, y) in enumerate(zip(SHELLS, bases, vs, ys)):
+        ora = Problem(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=200.0)
+        ora.set_base(X, 0.3, J)
+        vh, yh = v.cpu().numpy(), y.cpu().numpy()
+        for j in range(vh.shape[0]):
+            check(lay, yh[j], ora.jvp(vh[j]), tol, btol, f"batch plan {i} vec {j} prec {prec}")
     lay, X, J = bases[1]
     plans[1].set_base(torch.from_numpy(0.5 * X).cuda(), 0.1, J)
     ref2 = _eager(plans, vs, prec)

@@ -70,3 +70,31 @@ def test_newton_matches_oracle_trajectory(sc):
     assert abs(rep["rnorm"][0] - hist[0]) <= 1e-12 * hist[0]
     assert np.linalg.norm(X - Xo) <= 1e-9 * np.linalg.norm(X0 - Xo)
     assert abs(C - Co) <= 1e-9 * max(1.0, abs(0.2 - Co))
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_newton_converges_to_the_rw4_of_the_oracle(sc, prec):
+    """The converged rotating wave RW4 of the tiny shell (L = M = 16, m0 = 4, N = 16, Ek = 1e-3,
+    Ra = 78; tests/golden/rw4_L16_m4_N16.npz, computed by the oracle): the device Newton-GMRES,
+    started 1e-2 |X*| away with the drift speed off by 0.05, returns to the same X* and C*."""
+    import os
+    d = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rw4_L16_m4_N16.npz"),
+                allow_pickle=False)
+    Xs, Cs, J = d["X"], float(d["C"]), int(d["J"])
+    L, M, m0, N = (int(v) for v in d["shell"])
+    Ek, Pr, Ra = (float(v) for v in d["params"])
+    plan = sc.Plan(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=Pr, dt=200.0, nvec_max=1)
+    plan.factor()
+    ora = Problem(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=Pr, dt=200.0)
+    lay = si.Layout(L, M, m0, N)
+    dd = ora.clean(si.random_state(lay, 4001, p=2))
+    dd[J] = 0.0
+    X0 = Xs + 1e-2 * np.linalg.norm(Xs) * dd / np.linalg.norm(dd)
+    xd = _dev(X0)
+    C, rep = plan.newton(xd, Cs + 0.05, J, tol=1e-12, gmres_tol=1e-12 if prec == 0 else 1e-6, restart=40,
+                         max_newton=12, max_matvec=400, prec=prec)
+    X = xd.cpu().numpy()
+    ex, ec = np.linalg.norm(X - Xs) / np.linalg.norm(Xs), abs(C - Cs) / abs(Cs)
+    print(f"RW4 prec={prec}: {rep}; |X - X*|/|X*| {ex:.2e}, |C - C*|/|C*| {ec:.2e}", flush=True)
+    assert rep["converged"] and rep["rnorm"][-1] <= 1e-12
+    assert ex <= 1e-10 and ec <= 1e-10

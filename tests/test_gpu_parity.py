@@ -4,6 +4,7 @@ import pytest
 
 import seeded_inputs as si
 from oracle.solver import Problem
+from parity_util import FP64_BLOCK, check
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -59,8 +60,8 @@ def test_step_and_residual_fp64(lib, cfg):
     e2 = _rel(_host(out), R)
     print(f"cfg={cfg} step rel err {e1:.2e} residual rel err {e2:.2e} |R| {rn:.6e} vs {np.linalg.norm(R):.6e}", flush=True)
     assert e1 < 1e-12
-    assert e2 < 1e-10
-    assert abs(rn - np.linalg.norm(R)) <= 1e-10 * np.linalg.norm(R)
+    assert e2 < 1e-12
+    assert abs(rn - np.linalg.norm(R)) <= 1e-12 * np.linalg.norm(R)
 
 
 def test_conductive_fixed_point(lib):
@@ -73,9 +74,9 @@ def test_conductive_fixed_point(lib):
 
 
 @pytest.mark.parametrize("cfg", SMALL)
-@pytest.mark.parametrize("prec,solve,tol", [(0, 0, 1e-11), (1, 1, 1e-6), (1, 2, 1e-6)],
+@pytest.mark.parametrize("prec,solve,tol,btol", [(0, 0, 1e-12, FP64_BLOCK), (1, 1, 1e-6, 1e-5), (1, 2, 1e-6, 1e-5)],
                          ids=["fp64", "mixed-fp64solve", "mixed-fp32solve-refined"])
-def test_jvp(lib, cfg, prec, solve, tol):
+def test_jvp(lib, cfg, prec, solve, tol, btol):
     plan, ora, lay = _setup(lib, cfg, mixed_solve=solve)
     X = si.random_state(lay, 101, amp=(1e-2, 1e-2, 1e-2), p=2) + ora.conductive_state()
     J = si.default_phase_slot(lay, X)
@@ -87,9 +88,8 @@ def test_jvp(lib, cfg, prec, solve, tol):
     yd = torch.empty_like(vd)
     plan.jvp(vd, yd, prec)
     Y = _host(yd)
-    errs = [_rel(Y[i], ora.jvp(V[i])) for i in range(len(V))]
-    print(f"cfg={cfg} prec={prec} solve={solve} jvp rel errs", ["%.2e" % e for e in errs], flush=True)
-    assert max(errs) < tol
+    for i in range(len(V)):
+        check(lay, Y[i], ora.jvp(V[i]), tol, btol, f"cfg={cfg} prec={prec} solve={solve} vec {i}")
 
 
 @pytest.mark.parametrize("cfg", SMALL)
@@ -107,13 +107,12 @@ def test_autotune_then_jvp(lib, cfg):
     ora.set_base(X, 0.3, J)
     V = si.random_vectors(lay, [1001, 1002, 1003, 1004])
     vd = _dev(V)
-    for prec, tol in ((0, 1e-11), (1, 1e-6)):
+    for prec, tol, btol in ((0, 1e-12, FP64_BLOCK), (1, 1e-6, 1e-5)):
         yd = torch.empty_like(vd)
         plan.jvp(vd, yd, prec)
         Y = _host(yd)
-        errs = [_rel(Y[i], ora.jvp(V[i])) for i in range(len(V))]
-        print(f"cfg={cfg} tuned prec={prec} jvp rel errs", ["%.2e" % e for e in errs], flush=True)
-        assert max(errs) < tol
+        for i in range(len(V)):
+            check(lay, Y[i], ora.jvp(V[i]), tol, btol, f"cfg={cfg} tuned prec={prec} vec {i}")
     with pytest.raises(lib.ShellConvError) as ei:
         plan.autotune(nvec=0)
     assert ei.value.code == 1
@@ -128,3 +127,51 @@ def test_state_errors(lib):
     with pytest.raises(lib.ShellConvError) as ei:
         plan.set_base(v[0], 0.0, 2)   # an Re slot
     assert ei.value.code == 1
+
+
+# the tiny shell: L = M = 16, m0 = 1, N = 16, Ek = 1e-3, Pr = 1, Ra = 1.2 x 6.5 Ek^(-1/3) = 78
+C1 = (16, 16, 1, 16, 1e-3, 78.0)
+
+
+@pytest.mark.parametrize("dt", [1e-4, 200.0])
+def test_c1_step_and_ten_jvps(lib, dt):
+    """The tiny shell's state (conductive state plus a seeded perturbation of amplitude 1e-3,
+    coefficients decaying as (l+1)^-2): one IMEX step and ten Jacobian actions (vectors
+    1001..1010) at the small timestep 1e-4 and at the Newton pseudo-timestep 200."""
+    L, M, m0, N, Ek, Ra = C1
+    plan, ora, lay = _setup(lib, (L, M, m0, N, Ek, Ra, dt), nvec=10)
+    X = si.random_state(lay, 101, amp=(1e-3, 1e-3, 1e-3), p=2) + ora.conductive_state()
+    xd = _dev(X)
+    out = torch.empty_like(xd)
+    plan.step(xd, 0.0, out)
+    check(lay, _host(out), ora.step(X, 0.0), 1e-12, FP64_BLOCK, f"C1 dt={dt} step")
+    J = si.default_phase_slot(lay, X)
+    plan.set_base(xd, 0.0, J)
+    ora.set_base(X, 0.0, J)
+    V = si.random_vectors(lay, range(1001, 1011))
+    vd = _dev(V)
+    for prec, tol, btol in ((0, 1e-12, FP64_BLOCK), (1, 1e-6, 1e-5)):
+        yd = torch.empty_like(vd)
+        plan.jvp(vd, yd, prec)
+        Y = _host(yd)
+        for i in range(len(V)):
+            check(lay, Y[i], ora.jvp(V[i]), tol, btol, f"C1 dt={dt} prec={prec} vec {1001 + i}")
+
+
+@pytest.mark.parametrize("cfg", SMALL)
+def test_jvp_of_the_drift_unknown_alone(lib, cfg):
+    """v = c e_J (only the phase slot set): the action is the c im M X column of Sec. 3.4,
+    which is far smaller than the rest of a jvp and would hide in a mixed vector."""
+    plan, ora, lay = _setup(lib, cfg)
+    X = si.random_state(lay, 101, amp=(1e-1, 1e-1, 1e-1), p=2) + ora.conductive_state()
+    J = si.default_phase_slot(lay, X)
+    plan.set_base(_dev(X), 0.3, J)
+    ora.set_base(X, 0.3, J)
+    v = np.zeros((1, plan.n_real))
+    v[0, J] = 0.7
+    ref = ora.jvp(v[0])
+    vd = _dev(v)
+    for prec, tol, btol in ((0, 1e-12, FP64_BLOCK), (1, 1e-6, 1e-5)):
+        yd = torch.empty_like(vd)
+        plan.jvp(vd, yd, prec)
+        check(lay, _host(yd)[0], ref, tol, btol, f"cfg={cfg} drift column prec={prec}")

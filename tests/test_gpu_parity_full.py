@@ -5,6 +5,7 @@ import pytest
 
 import seeded_inputs as si
 from oracle.solver import Problem
+from parity_util import FP64_BLOCK, check
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -36,10 +37,10 @@ def _base(lay, ora, seed, amp):
 
 @pytest.mark.parametrize("shell", [SHELL_C2, SHELL_C3], ids=["L64N32", "L128N48"])
 def test_full_shell_jvp_batched(sc, shell):
-    """nvec = 17 (a full group of 16 plus a ragged tail of 1); vectors 0, 15 and 16 are
-    compared with the oracle one by one; every vector's mixed result against its FP64 one.
-    Both implicit solves of the mixed path: one FP64 solve (default) and the FP32 solve with
-    one FP64 refinement pass (a plan of its own)."""
+    """nvec = 17 (a full group of 16 plus a ragged tail of 1); every vector is compared with the
+    oracle one by one (global and per-(field, m) block errors), in both implicit solves of the
+    mixed path (one FP64 solve, the default; the FP32 solve with one FP64 refinement pass, a
+    plan of its own) and in FP64."""
     L, M, m0, N, Ek, Ra, seed, amp = shell
     nvec = 17
     plan = sc.Plan(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=200.0, nvec_max=nvec)
@@ -66,17 +67,15 @@ def test_full_shell_jvp_batched(sc, shell):
     torch.cuda.synchronize()
     y64, y32, y32r = Y64.cpu().numpy(), Y32.cpu().numpy(), Y32r.cpu().numpy()
     plan2.close()
-    for i in (0, 15, 16):
+    worst = {"fp64": 0.0, "mixed": 0.0, "mixed_fp32solve": 0.0}
+    for i in range(nvec):
         ref = ora.jvp(V[i])
-        e64, e32, e32r = _rel(y64[i], ref), _rel(y32[i], ref), _rel(y32r[i], ref)
-        print(f"L={L} N={N} vec {i}: fp64 rel err {e64:.2e}  mixed rel err {e32:.2e}  "
-              f"mixed (FP32 solve + refinement) {e32r:.2e}", flush=True)
-        assert e64 < 1e-11
-        assert e32 < 1e-6
-        assert e32r < 1e-6
-    worst = max(max(_rel(y32[i], y64[i]), _rel(y32r[i], y64[i])) for i in range(nvec))
-    print(f"L={L} N={N} max mixed-vs-fp64 over {nvec} vectors {worst:.2e}", flush=True)
-    assert worst < 1e-6
+        tag = f"L={L} N={N} vec {seed * 10 + 1 + i}"
+        worst["fp64"] = max(worst["fp64"], check(lay, y64[i], ref, 1e-12, FP64_BLOCK, tag + " fp64")[0])
+        worst["mixed"] = max(worst["mixed"], check(lay, y32[i], ref, 1e-6, 1e-5, tag + " mixed")[0])
+        worst["mixed_fp32solve"] = max(worst["mixed_fp32solve"],
+                                       check(lay, y32r[i], ref, 1e-6, 1e-5, tag + " mixed fp32 solve")[0])
+    print(f"L={L} N={N} worst relative error over {nvec} vectors vs the oracle: {worst}", flush=True)
 
 
 @pytest.mark.parametrize("shell", [SHELL_C2, SHELL_C3], ids=["L64N32", "L128N48"])
@@ -93,7 +92,8 @@ def test_full_shell_residual(sc, shell):
     ref = ora.residual(X, 0.5)
     e = _rel(R.cpu().numpy(), ref)
     print(f"L={L} N={N} residual rel err {e:.2e}, |R| {rn:.6e} vs {np.linalg.norm(ref):.6e}", flush=True)
-    assert e < 1e-11
+    assert e < 1e-12
+    check(lay, R.cpu().numpy(), ref, 1e-12, FP64_BLOCK, f"L={L} N={N} residual")
 
 
 def test_axisymmetric_and_odd_sizes(sc):
@@ -111,10 +111,10 @@ def test_axisymmetric_and_odd_sizes(sc):
     plan.jvp(_dev(V), Y, sc.SC_FP64)
     y = Y.cpu().numpy()
     for i in range(3):
-        assert _rel(y[i], ora.jvp(V[i])) < 1e-11
+        check(lay, y[i], ora.jvp(V[i]), 1e-12, FP64_BLOCK, f"axisymmetric odd N vec {i}")
     out = torch.empty(plan.n_real, dtype=torch.float64, device="cuda")
     plan.step(_dev(X), 0.0, out)
-    assert _rel(out.cpu().numpy(), ora.step(X, 0.0)) < 1e-12
+    check(lay, out.cpu().numpy(), ora.step(X, 0.0), 1e-12, FP64_BLOCK, "axisymmetric odd N step")
 
 
 def test_jvp_batch_limits(sc):
@@ -160,10 +160,10 @@ def test_wide_theta_fallback_paths(sc):
     y64, y32 = Y64.cpu().numpy(), Y32.cpu().numpy()
     for i in range(3):
         ref = ora.jvp(V[i])
-        e64, e32 = _rel(y64[i], ref), _rel(y32[i], ref)
-        print(f"L={L} N_theta={plan.layout['ntheta']} vec {i}: fp64 {e64:.2e} mixed {e32:.2e}", flush=True)
-        assert e64 < 1e-11
-        assert e32 < 1e-6
+        # N = 10 radial nodes and dt = 5: the global error of this shell sits at 1.4e-12, carried by
+        # the temperature m = 0 block (the open discrepancy described with FP64_BLOCK)
+        check(lay, y64[i], ref, 3e-12, FP64_BLOCK, f"L={L} N_theta={plan.layout['ntheta']} vec {i} fp64")
+        check(lay, y32[i], ref, 1e-6, 1e-5, f"L={L} N_theta={plan.layout['ntheta']} vec {i} mixed")
 
 
 # the throughput-stress shell: Ra = 1.2 * 6.5 Ek^(-1/3)
@@ -208,4 +208,29 @@ def test_stress_shell_linearization(sc):
             e = _rel(cd, y64[i])
             print(f"vector {i} eps {eps:g}: central difference vs FP64 jvp {e:.2e}", flush=True)
             assert e <= 1e-10
+    plan.close()
+
+
+@pytest.mark.timeout(900)
+def test_stress_shell_vs_oracle(sc):
+    """The stress shell against the oracle itself on one vector (the oracle's factor and one
+    Jacobian action take about a minute of host time at this size)."""
+    L, M, m0, N, Ek, Ra, seed, amp = SHELL_C5
+    plan = sc.Plan(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=200.0, nvec_max=1)
+    plan.factor()
+    lay = si.Layout(L, M, m0, N)
+    print("oracle factor at L=255, N=64", flush=True)
+    ora = Problem(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=200.0)
+    ora.factor()
+    X = _base(lay, ora, seed, amp)
+    J = si.default_phase_slot(lay, X)
+    plan.set_base(_dev(X), 0.5, J)
+    ora.set_base(X, 0.5, J)
+    V = si.random_vectors(lay, [seed * 10])
+    Vd = _dev(V)
+    ref = ora.jvp(V[0])
+    for prec, tol, btol in ((sc.SC_FP64, 1e-12, FP64_BLOCK), (sc.SC_MIXED, 1e-6, 1e-5)):
+        Y = torch.empty_like(Vd)
+        plan.jvp(Vd, Y, prec)
+        check(lay, Y.cpu().numpy()[0], ref, tol, btol, f"L={L} N={N} vec {seed * 10} prec={prec}")
     plan.close()
