@@ -118,8 +118,11 @@ int sc_newton_residual(sc_plan* plan, const double* x, double C, double* r, doub
  * x, r, rnorm_dev: device memory owned by the caller.  Errors as sc_newton_residual. */
 int sc_newton_residual_noalloc(sc_plan* plan, const double* x, double C, double* r, double* rnorm_dev,
                                void* stream);
-/* Base state of the Jacobian: caches the physical U, omega, grad T of x (FP64 and FP32) and
- * M x.  J is the phase slot (index of an Im entry with m > 0) or -1 for no drift unknown. */
+/* Base state of the Jacobian (Sec. 3.3, eq:precond: the linearized step B_U about U = x, with the
+ * replacement rules of its linearization): caches the physical U, omega, grad T of x (FP64 and
+ * FP32) and M x, the factor of the drift column c im M X.  J is the phase slot of Sec. 3.4 (the
+ * index of the Im entry of one m > 0 coefficient, where the Krylov vectors carry the drift-speed
+ * increment c) or -1 for no drift unknown. */
 int sc_set_base(sc_plan* plan, const double* x, double C, long long J, void* stream);
 /* Jacobian action y_i = (B_X - I)(u_i, c_i) on nvec vectors (Sec. 3.3 eq:precond, Sec. 3.4):
  * c_i = v_i[J], u_i = v_i with slot J zeroed; homogeneous boundary rows.
@@ -225,6 +228,68 @@ int sc_batch_jvp(sc_batch* batch, const int* nvec, const double* const* v, doubl
  * with the stage profiler on.  Calls that overlap on one batch, or that share a plan, race. */
 int sc_batch_newton(sc_batch* batch, double* const* x, double* C, const sc_newton_opts* opts,
                     sc_newton_report* reports, void* stream);
+
+/* Grid refinement (Sec. 4.2): y = x carried from the layout of `from` to that of `to` (same m0):
+ * every (field, l, m) present in both is its interpolating Chebyshev polynomial evaluated at the
+ * new Gauss-Lobatto nodes (the series padded with zeros); new degrees and orders are zero.
+ * x: device, n_real of `from`; y: device, n_real of `to`.  Synchronizes the stream. */
+int sc_interpolate(sc_plan* from, const double* x, sc_plan* to, double* y, void* stream);
+/* Resolution check (Sec. 4.2): cheb_ratio = max |a_{N-1}| / max |a_n| over the Chebyshev
+ * coefficients of every radial profile, sh_ratio = max |x at l = L| / max |x| (complex moduli).
+ * A ratio above the threshold (1e-6 in the paper) means under-resolution.  Synchronizes. */
+int sc_tail_ratios(sc_plan* plan, const double* x, double* cheb_ratio, double* sh_ratio, void* stream);
+
+/* Continuation of a branch of rotating waves (Sec. 3.5, 3.6, 4.2), a session on one device:
+ *   step size: p_new = p_i + alpha (p_i - p_{i-1}), alpha = (n_opt + 1)/(N_i + 1) with N_i the
+ *     Newton steps of the last point (eq:new_Ra, eq:alpha_cont; a point that needed none counts
+ *     as one); the first step from a single point is p_0 + dp_first from that point;
+ *   prediction: the quadratic Lagrange weights of the last three parameter values at p_new,
+ *     applied to the kept states and drift speeds (eq:lagrange);
+ *   turning points (eq:tp_detection_Ra): with J the index of the largest |x| of the last point,
+ *     if |dx_J/x_J| > gamma |dp/p| the component x_J is the independent variable instead
+ *     (eq:quad_extra_Ra): p_new and the state come from the Lagrange weights in x_J;
+ *   every point is a Newton-GMRES solve (sc_newton) at fixed p; if it fails, the step is taken
+ *     again with alpha and gamma halved, up to max_retries times.
+ * SC_CONT_RA: p = Ra.  SC_CONT_EK: p = log10 Ek with Ra = ra_coef Ek^(-1/3) (Sec. 4.2; 6.5 there);
+ *   every new Ek re-factors the plan, and with refine_tol > 0 a converged point whose Chebyshev
+ *   (or spherical-harmonic) tail ratio exceeds refine_tol grows N (or L and M) by refine_growth
+ *   (N at most 64): a new plan is made, the kept points are carried over by sc_interpolate, the
+ *   phase slot is chosen again (largest |Re| of an m = m0 entry of f or T) and the point is
+ *   recomputed on the new grid.  The session owns the plans it makes; the caller's plan is not
+ *   destroyed but its parameters change (Ra, Ek, factor) as the branch moves.
+ * sc_cont_create: the plan must be factored; x0 (device) is converged first by Newton at the
+ *   plan's parameters (SC_CONT_EK: at Ra = ra_coef Ek^(-1/3)); `first` (may be NULL) reports it.
+ *   newton.J is the phase slot in the plan's layout; newton.forcing must be NULL.
+ * sc_cont_step: one step; pt reports the point (converged = 0 if every retry failed; the branch
+ *   is then unchanged).  sc_cont_layout / sc_cont_state: the layout of the current resolution
+ *   and a copy of the newest state (device, n = its n_real) with its drift speed.
+ * Errors: SC_ERR_ARG (options, sizes), SC_ERR_STATE (no factor, profiler on, no convergence at
+ * the first point or after a refinement).  Every call synchronizes the stream. */
+enum { SC_CONT_RA = 0, SC_CONT_EK = 1 };
+typedef struct {
+  int param;              /* SC_CONT_RA or SC_CONT_EK                                        */
+  int n_opt;              /* target Newton steps per point (4..6 for Ra, 3 for Ek in the paper) */
+  double gamma;           /* turning-point factor (10..100 for Ra, 400..500 for Ek)            */
+  double ra_coef;         /* SC_CONT_EK: Ra = ra_coef Ek^(-1/3)                                */
+  double refine_tol;      /* SC_CONT_EK: under-resolution threshold (<= 0: no refinement)      */
+  double refine_growth;   /* resolution factor of a refinement (1.2 in the paper)              */
+  int max_retries;        /* halvings of a failed step, 0..16                                  */
+  sc_newton_opts newton;  /* Newton-GMRES of every point                                       */
+} sc_cont_opts;
+typedef struct {
+  double param, Ra, Ek, C; /* the point: p, Rayleigh and Ekman numbers, drift speed            */
+  double unorm;            /* ||x||_2                                                           */
+  double cheb_ratio, sh_ratio; /* tail ratios (SC_CONT_EK with refinement)                     */
+  int newton_steps, matvecs, converged, state_mode, refined, retries;
+  int L, N;                /* resolution of the point                                           */
+} sc_cont_point;
+typedef struct sc_cont sc_cont;
+int sc_cont_create(sc_cont** out, sc_plan* plan, const double* x0, double C0, const sc_cont_opts* opts,
+                   sc_cont_point* first, void* stream);
+int sc_cont_step(sc_cont* cont, double dp_first, sc_cont_point* pt, void* stream);
+int sc_cont_layout(const sc_cont* cont, sc_layout_info* out);
+int sc_cont_state(sc_cont* cont, double* x, long long n, double* C, void* stream);
+int sc_cont_destroy(sc_cont* cont);
 
 #ifdef __cplusplus
 }

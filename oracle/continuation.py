@@ -12,8 +12,13 @@ Sec. 3.5 (continuation) and Sec. 3.6 (turning points); Sec. 4.2 for the Ekman va
     three previous U_J values at U_J,new, and the parameter is extrapolated with them like every
     other component (eq:quad_extra_Ra).  Newton then runs at that fixed parameter with every
     component free.  The switch back happens when the test reverses.
-With one previous point the prediction is that point (zeroth order), with two it is linear.
+With one point on the branch the first step is p_0 + dp_first from that point (zeroth order),
+with two the prediction is linear.  A point that needed no Newton step counts as one in alpha.
 The drift speed C is carried with the state and extrapolated with the same weights.
+
+If Newton fails at the predicted point, the step is taken again from the last converged point
+with alpha and gamma halved (Sec. 3.6 restarts a failed continuation with a reduced gamma), up
+to max_retries times.
 
 The driver is generic: `solve(param, X, C) -> (X, C, newton_steps, converged)` runs Newton at a
 fixed parameter, so the same logic serves Ra (p = Ra) and Ek (p = log10 Ek, Sec. 4.2).
@@ -45,9 +50,9 @@ def lagrange_weights(t_new, ts):
 class Continuation:
     """Branch of converged points (param, X, C), newest last."""
 
-    def __init__(self, solve, n_opt=5, gamma=50.0, dp_min=0.0):
+    def __init__(self, solve, n_opt=5, gamma=50.0, max_retries=3):
         self.solve = solve
-        self.n_opt, self.gamma, self.dp_min = n_opt, gamma, dp_min
+        self.n_opt, self.gamma, self.max_retries = n_opt, gamma, max_retries
         self.params, self.states, self.Cs, self.iters = [], [], [], []
         self.state_mode = []          # per point: True if it was predicted with U_J as the variable
 
@@ -58,24 +63,25 @@ class Continuation:
         self.iters.append(int(iters))
         self.state_mode.append(False)
 
-    def turning(self):
+    def turning(self, gamma):
         """eq:tp_detection_Ra on the last two points: (switch to U_J, J)."""
         X1, X0 = self.states[-1], self.states[-2]
         J = int(np.argmax(np.abs(X1)))
         dU = abs((X1[J] - X0[J]) / X1[J])
         p1, p0 = self.params[-1], self.params[-2]
         dp = abs((p1 - p0) / p1)
-        return dU > self.gamma * dp, J
+        return dU > gamma * dp, J
 
-    def predict(self):
-        """(param, X, C) estimate of the next point and whether U_J was the variable."""
+    def predict(self, scale=1.0):
+        """(param, X, C) estimate of the next point and whether U_J was the variable; scale
+        multiplies alpha and gamma (1 on a first attempt)."""
         n = len(self.params)
         if n < 2:
             raise ValueError("continuation needs two converged points to set its step")
-        alpha = step_factor(self.n_opt, self.iters[-1])
+        alpha = scale * step_factor(self.n_opt, max(self.iters[-1], 1))
         k = min(n, 3)
         Xs, Cs, ps = self.states[-k:], self.Cs[-k:], self.params[-k:]
-        switch, J = self.turning()
+        switch, J = self.turning(scale * self.gamma)
         if not switch:
             p_new = ps[-1] + alpha * (ps[-1] - ps[-2])
             w = lagrange_weights(p_new, ps)
@@ -88,11 +94,17 @@ class Continuation:
         C = sum(wq * Cq for wq, Cq in zip(w, Cs))
         return p_new, X, C, switch
 
-    def step(self):
-        """One continuation step; returns (param, converged)."""
-        p, X, C, switch = self.predict()
-        Xn, Cn, its, ok = self.solve(p, X, C)
-        if ok:
-            self.add_point(p, Xn, Cn, its)
-            self.state_mode[-1] = switch
-        return p, ok
+    def step(self, dp_first=None):
+        """One continuation step; returns (param, converged, retries).  dp_first: the first
+        parameter step when the branch holds a single point (halved on a retry)."""
+        for r in range(self.max_retries + 1):
+            if len(self.params) == 1:
+                p, X, C, switch = self.params[0] + dp_first * 0.5 ** r, self.states[0], self.Cs[0], False
+            else:
+                p, X, C, switch = self.predict(0.5 ** r)
+            Xn, Cn, its, ok = self.solve(p, X, C)
+            if ok:
+                self.add_point(p, Xn, Cn, its)
+                self.state_mode[-1] = switch
+                return p, True, r
+        return p, False, r

@@ -16,6 +16,8 @@ SC_FP64 = 0
 SC_MIXED = 1
 SC_MIXED_SOLVE_FP64 = 1   # mixed_solve of Plan
 SC_MIXED_SOLVE_FP32 = 2
+SC_CONT_RA = 0             # param of Continuation
+SC_CONT_EK = 1
 SC_CORIOLIS_IMPLICIT = 0   # coriolis of Plan
 SC_CORIOLIS_EXPLICIT = 1
 _ERRORS = {1: "SC_ERR_ARG", 2: "SC_ERR_STATE", 3: "SC_ERR_NONFINITE", 4: "SC_ERR_NOMEM",
@@ -54,6 +56,20 @@ class _TuneReport(ctypes.Structure):
     _fields_ = [("ring_fp32", ctypes.c_int), ("ring_fp64", ctypes.c_int), ("anal_folded", ctypes.c_int),
                 ("ncand", ctypes.c_int), ("ms_fp32", ctypes.c_double), ("ms_fp64", ctypes.c_double),
                 ("linear_mode", ctypes.c_int)]
+
+
+class _ContOpts(ctypes.Structure):
+    _fields_ = [("param", ctypes.c_int), ("n_opt", ctypes.c_int), ("gamma", ctypes.c_double),
+                ("ra_coef", ctypes.c_double), ("refine_tol", ctypes.c_double), ("refine_growth", ctypes.c_double),
+                ("max_retries", ctypes.c_int), ("newton", _NewtonOpts)]
+
+
+class _ContPoint(ctypes.Structure):
+    _fields_ = [("param", ctypes.c_double), ("Ra", ctypes.c_double), ("Ek", ctypes.c_double), ("C", ctypes.c_double),
+                ("unorm", ctypes.c_double), ("cheb_ratio", ctypes.c_double), ("sh_ratio", ctypes.c_double),
+                ("newton_steps", ctypes.c_int), ("matvecs", ctypes.c_int), ("converged", ctypes.c_int),
+                ("state_mode", ctypes.c_int), ("refined", ctypes.c_int), ("retries", ctypes.c_int),
+                ("L", ctypes.c_int), ("N", ctypes.c_int)]
 
 
 class _NewtonReport(ctypes.Structure):
@@ -96,6 +112,13 @@ def load_library(path: str = LIB_PATH):
         "sc_batch_jvp": [vp, ctypes.POINTER(i), ctypes.POINTER(vp), ctypes.POINTER(vp), i, vp],
         "sc_batch_newton": [vp, ctypes.POINTER(vp), ctypes.POINTER(d), ctypes.POINTER(_NewtonOpts),
                             ctypes.POINTER(_NewtonReport), vp],
+        "sc_interpolate": [vp, vp, vp, vp, vp],
+        "sc_tail_ratios": [vp, vp, ctypes.POINTER(d), ctypes.POINTER(d), vp],
+        "sc_cont_create": [ctypes.POINTER(vp), vp, vp, d, ctypes.POINTER(_ContOpts), ctypes.POINTER(_ContPoint), vp],
+        "sc_cont_step": [vp, d, ctypes.POINTER(_ContPoint), vp],
+        "sc_cont_layout": [vp, ctypes.POINTER(_Layout)],
+        "sc_cont_state": [vp, vp, ll, ctypes.POINTER(d), vp],
+        "sc_cont_destroy": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -115,7 +138,8 @@ def exported_symbols():
     return ["sc_plan_create", "sc_plan_destroy", "sc_layout", "sc_set_params", "sc_factor", "sc_step",
             "sc_newton_residual", "sc_set_base", "sc_jvp", "sc_newton", "sc_profile", "sc_profile_read",
             "sc_last_error", "sc_batch_create", "sc_batch_destroy", "sc_batch_jvp", "sc_autotune",
-            "sc_batch_newton", "sc_newton_residual_noalloc"]
+            "sc_batch_newton", "sc_newton_residual_noalloc", "sc_interpolate", "sc_tail_ratios",
+            "sc_cont_create", "sc_cont_step", "sc_cont_layout", "sc_cont_state", "sc_cont_destroy"]
 
 
 def _check(rc):
@@ -190,6 +214,12 @@ class Plan:
         _check(_lib.sc_newton_residual_noalloc(self._h, _ptr(x, self.n_real), C, _ptr(out, self.n_real),
                                                _ptr(rnorm, 1), _stream(stream)))
         return out
+
+    def tail_ratios(self, x, stream=None):
+        """(Chebyshev, spherical-harmonic) tail ratios of a state (sc_tail_ratios)."""
+        rc, rl = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        _check(_lib.sc_tail_ratios(self._h, _ptr(x, self.n_real), ctypes.byref(rc), ctypes.byref(rl), _stream(stream)))
+        return rc.value, rl.value
 
     def set_base(self, x, C=0.0, J=-1, stream=None):
         _check(_lib.sc_set_base(self._h, _ptr(x, self.n_real), C, int(J), _stream(stream)))
@@ -305,3 +335,64 @@ class Batch:
             opts[i] = _NewtonOpts(tol, gmres_tol, restart, max_newton, max_matvec, int(prec), int(Js[i]), f)
         _check(_lib.sc_batch_newton(self._h, px, cs, opts, reps, _stream(stream)))
         return [(cs[i], _report_dict(reps[i])) for i in range(n)]
+
+
+def _point_dict(pt):
+    return {f: getattr(pt, f) for f, _ in _ContPoint._fields_}
+
+
+def interpolate(src, x, dst, y, stream=None):
+    """y (layout of plan dst) = x (layout of plan src) carried to the new grid (sc_interpolate)."""
+    _check(_lib.sc_interpolate(src._h, _ptr(x, src.n_real), dst._h, _ptr(y, dst.n_real), _stream(stream)))
+    return y
+
+
+class Continuation:
+    """A continuation session (sc_cont_*): Ra (param=SC_CONT_RA) or log10 Ek (SC_CONT_EK) along a
+    branch of rotating waves from a converged point of `plan`.  The session may replace the plan
+    by finer ones (refinement); state() returns a copy of the newest state."""
+
+    def __init__(self, plan, x0, C0, J, param=SC_CONT_RA, n_opt=4, gamma=50.0, ra_coef=6.5, refine_tol=0.0,
+                 refine_growth=1.2, max_retries=3, tol=1e-10, gmres_tol=1e-10, restart=40, max_newton=10,
+                 max_matvec=400, prec=SC_FP64, stream=None):
+        lib = load_library()
+        self.plan = plan
+        o = _ContOpts(int(param), int(n_opt), float(gamma), float(ra_coef), float(refine_tol), float(refine_growth),
+                      int(max_retries), _NewtonOpts(tol, gmres_tol, restart, max_newton, max_matvec, int(prec),
+                                                    int(J), None))
+        first = _ContPoint()
+        h = ctypes.c_void_p()
+        _check(lib.sc_cont_create(ctypes.byref(h), plan._h, _ptr(x0, plan.n_real), float(C0), ctypes.byref(o),
+                                  ctypes.byref(first), _stream(stream)))
+        self._h = h
+        self.first = _point_dict(first)
+
+    def step(self, dp_first=0.0, stream=None):
+        pt = _ContPoint()
+        _check(_lib.sc_cont_step(self._h, float(dp_first), ctypes.byref(pt), _stream(stream)))
+        return _point_dict(pt)
+
+    def layout(self):
+        lay = _Layout()
+        _check(_lib.sc_cont_layout(self._h, ctypes.byref(lay)))
+        return {f: getattr(lay, f) for f, _ in _Layout._fields_}
+
+    def state(self, stream=None):
+        """(x, C): a new float64 CUDA tensor with the newest state, and its drift speed."""
+        import torch
+        n = self.layout()["n_real"]
+        x = torch.empty(n, dtype=torch.float64, device="cuda")
+        c = ctypes.c_double(0.0)
+        _check(_lib.sc_cont_state(self._h, _ptr(x, n), n, ctypes.byref(c), _stream(stream)))
+        return x, c.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.sc_cont_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1694,3 +1694,429 @@ int sc_batch_newton(sc_batch* b, double* const* x, double* C, const sc_newton_op
 }
 
 }  // extern "C"
+
+// ==========================================================================================
+// Grid refinement and continuation (Sec. 3.5, 3.6, 4.2).
+namespace {
+
+constexpr double kPiD = 3.14159265358979323846;
+
+// Interpolation matrix [N_new][N_old]: the interpolating polynomial of N_old Gauss-Lobatto values
+// (its discrete Chebyshev series) evaluated at the N_new Gauss-Lobatto nodes.
+std::vector<double> cheb_interp_matrix(int No, int Nn) {
+  std::vector<double> Cm((size_t)No * No);   // [k][j]: Chebyshev coefficient k of nodal value j
+  for (int k = 0; k < No; ++k)
+    for (int j = 0; j < No; ++j) {
+      const double ck = (k == 0 || k == No - 1) ? 2.0 : 1.0, cj = (j == 0 || j == No - 1) ? 2.0 : 1.0;
+      Cm[(size_t)k * No + j] = 2.0 / ((No - 1) * ck * cj) * std::cos(kPiD * k * j / (No - 1));
+    }
+  std::vector<double> Ip((size_t)Nn * No, 0.0);
+  for (int i = 0; i < Nn; ++i)
+    for (int k = 0; k < No; ++k) {
+      const double Tk = std::cos(k * kPiD * i / (Nn - 1));   // T_k at x_i = cos(pi i/(Nn - 1))
+      for (int j = 0; j < No; ++j) Ip[(size_t)i * No + j] += Tk * Cm[(size_t)k * No + j];
+    }
+  return Ip;
+}
+
+void interp_device(sc_plan* from, const double* x, sc_plan* to, double* y, hipStream_t s) {
+  if (from->hg.m0 != to->hg.m0) throw Fail{SC_ERR_ARG, "interpolation keeps the sector: m0 must match"};
+  if (from->prm.device != to->prm.device) throw Fail{SC_ERR_ARG, "plans on different devices"};
+  DevBuf Ip;
+  upload(Ip, cheb_interp_matrix(from->hg.N, to->hg.N));
+  sc::InterpMap im;
+  im.N_old = from->hg.N;
+  im.N_new = to->hg.N;
+  im.S_old = from->hg.S;
+  im.S_new = to->hg.S;
+  im.L_old = from->hg.L;
+  im.K_old = from->hg.K;
+  im.m0 = from->hg.m0;
+  im.lmbase_old = from->d_lmbase.as<int>();
+  im.lm_k_new = to->d_lmk.as<int>();
+  im.lm_l_new = to->d_lml.as<int>();
+  im.Ip = Ip.as<double>();
+  hipLaunchKernelGGL(sc::k_interp, dim3(nblk(to->n_real, 256)), dim3(256), 0, s, im, x, y);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));   // Ip is freed on return
+}
+
+// Tail ratios of a host copy of a packed state: max |a_{N-1}| / max |a_n| over the Chebyshev
+// coefficients of every radial profile, and max |X at l = L| / max |X| (complex magnitudes).
+void tail_ratios_host(const sc_plan* P, const std::vector<double>& X, double& rc, double& rl) {
+  const sc::HostGrid& g = P->hg;
+  const int N = g.N;
+  std::vector<double> Cm((size_t)N * N);
+  for (int k = 0; k < N; ++k)
+    for (int j = 0; j < N; ++j) {
+      const double ck = (k == 0 || k == N - 1) ? 2.0 : 1.0, cj = (j == 0 || j == N - 1) ? 2.0 : 1.0;
+      Cm[(size_t)k * N + j] = 2.0 / ((N - 1) * ck * cj) * std::cos(kPiD * k * j / (N - 1));
+    }
+  double amax = 0.0, atail = 0.0, xmax = 0.0, xl = 0.0;
+  for (int f = 0; f < 3; ++f)
+    for (int lm = 0; lm < g.S; ++lm) {
+      const double* v = X.data() + 2LL * ((long long)N * ((long long)f * g.S + lm));
+      const bool top = g.lm_l[lm] == g.L;
+      for (int j = 0; j < N; ++j) {
+        const double a = std::hypot(v[2 * j], v[2 * j + 1]);
+        xmax = std::max(xmax, a);
+        if (top) xl = std::max(xl, a);
+      }
+      for (int k = 0; k < N; ++k) {
+        double re = 0.0, im = 0.0;
+        for (int j = 0; j < N; ++j) {
+          re += Cm[(size_t)k * N + j] * v[2 * j];
+          im += Cm[(size_t)k * N + j] * v[2 * j + 1];
+        }
+        const double a = std::hypot(re, im);
+        amax = std::max(amax, a);
+        if (k == N - 1) atail = std::max(atail, a);
+      }
+    }
+  rc = amax > 0 ? atail / amax : 0.0;
+  rl = xmax > 0 ? xl / xmax : 0.0;
+}
+
+// Phase slot on a host copy: the Im entry of an m = m0 coefficient of f or T whose real part is
+// largest in magnitude (-1 if the plan has no m > 0).
+long long phase_slot_host(const sc_plan* P, const std::vector<double>& X) {
+  const sc::HostGrid& g = P->hg;
+  if (g.K < 1) return -1;
+  long long best = -1;
+  double bv = -1.0;
+  for (int f = 1; f <= 2; ++f)
+    for (int l = g.ms[1]; l <= g.L; ++l) {
+      const int lm = g.lmbase[1] + (l - g.ms[1]);
+      for (int j = 0; j < g.N; ++j) {
+        const long long o = 2LL * ((long long)g.N * ((long long)f * g.S + lm) + j);
+        if (std::fabs(X[o]) > bv) {
+          bv = std::fabs(X[o]);
+          best = o + 1;
+        }
+      }
+    }
+  return best;
+}
+
+std::vector<double> to_host(const double* x, long long n, hipStream_t s) {
+  std::vector<double> h((size_t)n);
+  HIPCHK(hipMemcpyAsync(h.data(), x, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return h;
+}
+
+double read1(const double* x, long long i, hipStream_t s) {
+  double v = 0.0;
+  HIPCHK(hipMemcpyAsync(&v, x + i, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return v;
+}
+
+// Index of the largest |x| (device reduction in fixed chunks, ties to the lower index).
+long long argmax_abs(const double* x, long long n, hipStream_t s) {
+  const long long chunk = 8192, nparts = (n + chunk - 1) / chunk;
+  DevBuf pv, pi;
+  pv.alloc(nparts * sizeof(double));
+  pi.alloc(nparts * sizeof(long long));
+  hipLaunchKernelGGL(sc::k_absmax_parts, dim3((unsigned)nparts), dim3(256), 0, s, n, x, chunk, pv.as<double>(),
+                     pi.as<long long>());
+  HIPCHK(hipGetLastError());
+  std::vector<double> hv(nparts);
+  std::vector<long long> hi(nparts);
+  HIPCHK(hipMemcpyAsync(hv.data(), pv.p, nparts * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hi.data(), pi.p, nparts * sizeof(long long), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  long long best = 0;
+  double bv = -1.0;
+  for (long long b = 0; b < nparts; ++b)
+    if (hv[b] > bv) {
+      bv = hv[b];
+      best = hi[b];
+    }
+  return best;
+}
+
+double lagrange_w(double t, const double* ts, int n, int q) {
+  double v = 1.0;
+  for (int r = 0; r < n; ++r)
+    if (r != q) v *= (t - ts[r]) / (ts[q] - ts[r]);
+  return v;
+}
+
+}  // namespace
+
+struct sc_cont {
+  sc_plan* plan = nullptr;      // the plan of the current resolution
+  sc_plan* owned = nullptr;     // a plan made by a refinement (owned by the session)
+  sc_cont_opts o{};
+  long long J = -1;             // phase slot in the current layout
+  int n = 0;                    // converged points kept (<= 3), oldest first
+  DevBuf X[3];
+  double p[3] = {0, 0, 0}, C[3] = {0, 0, 0};
+  int its[3] = {0, 0, 0};
+  DevBuf trial;
+
+  ~sc_cont() {
+    if (owned) {
+      (void)hipSetDevice(owned->prm.device);
+      (void)hipDeviceSynchronize();
+      delete owned;
+    }
+  }
+  // parameters of the plan at continuation parameter value q (a new Ek re-factors: Sec. 4.2)
+  void apply(double q, hipStream_t s) {
+    if (o.param == SC_CONT_RA) {
+      if (sc_set_params(plan, q, plan->prm.Ek, plan->prm.dt) != SC_OK) throw Fail{SC_ERR_ARG, g_last_error};
+    } else {
+      const double Ek = std::pow(10.0, q), Ra = o.ra_coef * std::pow(Ek, -1.0 / 3.0);
+      if (sc_set_params(plan, Ra, Ek, plan->prm.dt) != SC_OK) throw Fail{SC_ERR_ARG, g_last_error};
+      if (!plan->factored) {
+        HIPCHK(hipStreamSynchronize(s));   // the factor buffers are replaced
+        if (sc_factor(plan, s) != SC_OK) throw Fail{SC_ERR_HIP, g_last_error};
+      }
+    }
+  }
+  double param_of_plan() const {
+    return o.param == SC_CONT_RA ? plan->prm.Ra : std::log10(plan->prm.Ek);
+  }
+  // Newton at parameter q from the iterate in x (in place); false if it did not converge
+  bool solve(double q, double* x, double& Cq, sc_newton_report& rep, hipStream_t s) {
+    apply(q, s);
+    sc_newton_opts no = o.newton;
+    no.J = J;
+    try {
+      newton_impl(plan, x, &Cq, no, J, &rep, s);
+    } catch (const Fail& f) {
+      if (f.code != SC_ERR_NONFINITE) throw;
+      return false;
+    }
+    return rep.converged != 0;
+  }
+  void push(double q, const double* x, double Cq, int nits, hipStream_t s) {
+    if (n == 3) {
+      std::swap(X[0].p, X[1].p);
+      std::swap(X[1].p, X[2].p);
+      p[0] = p[1]; p[1] = p[2];
+      C[0] = C[1]; C[1] = C[2];
+      its[0] = its[1]; its[1] = its[2];
+      n = 2;
+    }
+    HIPCHK(hipMemcpyAsync(X[n].p, x, plan->n_real * sizeof(double), hipMemcpyDeviceToDevice, s));
+    p[n] = q;
+    C[n] = Cq;
+    its[n] = nits;
+    ++n;
+  }
+};
+
+extern "C" {
+
+int sc_interpolate(sc_plan* from, const double* x, sc_plan* to, double* y, void* stream) {
+  return guarded([&] {
+    check_plan(from);
+    if (!to || !x || !y) throw Fail{SC_ERR_ARG, "null argument"};
+    interp_device(from, x, to, y, (hipStream_t)stream);
+  });
+}
+
+int sc_tail_ratios(sc_plan* P, const double* x, double* cheb_ratio, double* sh_ratio, void* stream) {
+  return guarded([&] {
+    check_plan(P);
+    if (!x || !cheb_ratio || !sh_ratio) throw Fail{SC_ERR_ARG, "null argument"};
+    const std::vector<double> h = to_host(x, P->n_real, (hipStream_t)stream);
+    tail_ratios_host(P, h, *cheb_ratio, *sh_ratio);
+  });
+}
+
+int sc_cont_create(sc_cont** out, sc_plan* plan, const double* x0, double C0, const sc_cont_opts* opts,
+                   sc_cont_point* first, void* stream) {
+  if (!out || !plan || !x0 || !opts) return fail(SC_ERR_ARG, "null argument");
+  *out = nullptr;
+  return guarded([&] {
+    check_plan(plan);
+    const sc_cont_opts& o = *opts;
+    if (o.param != SC_CONT_RA && o.param != SC_CONT_EK) throw Fail{SC_ERR_ARG, "param must be SC_CONT_RA or SC_CONT_EK"};
+    if (o.n_opt < 1 || !(o.gamma > 0) || o.max_retries < 0 || o.max_retries > 16)
+      throw Fail{SC_ERR_ARG, "need n_opt >= 1, gamma > 0, 0 <= max_retries <= 16"};
+    if (o.param == SC_CONT_EK && !(o.ra_coef > 0)) throw Fail{SC_ERR_ARG, "SC_CONT_EK needs ra_coef > 0"};
+    if (o.refine_tol > 0 && !(o.refine_growth > 1.0)) throw Fail{SC_ERR_ARG, "refine_growth must exceed 1"};
+    if (o.newton.restart < 1 || o.newton.restart > 1024 || o.newton.max_newton < 0 || o.newton.max_newton > 64 ||
+        o.newton.max_matvec < 1 || (o.newton.prec != SC_FP64 && o.newton.prec != SC_MIXED))
+      throw Fail{SC_ERR_ARG, "bad Newton options"};
+    if (o.newton.forcing) throw Fail{SC_ERR_ARG, "a continuation takes no forcing"};
+    if (!plan->factored) throw Fail{SC_ERR_STATE, "sc_factor has not run for the current (Ek, dt)"};
+    if (plan->prof_on) throw Fail{SC_ERR_STATE, "turn the stage profiler off before a continuation"};
+    hipStream_t s = (hipStream_t)stream;
+    std::unique_ptr<sc_cont> c(new sc_cont());
+    c->plan = plan;
+    c->o = o;
+    c->J = check_slot(plan, o.newton.J);
+    for (auto& b : c->X) b.alloc(plan->n_real * sizeof(double));
+    c->trial.alloc(plan->n_real * sizeof(double));
+    HIPCHK(hipMemcpyAsync(c->trial.p, x0, plan->n_real * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // the first point: converged at the plan's current parameters (Newton from x0)
+    const double q0 = c->param_of_plan();
+    double Cq = C0;
+    sc_newton_report rep;
+    const bool ok = c->solve(q0, c->trial.as<double>(), Cq, rep, s);
+    if (!ok) throw Fail{SC_ERR_STATE, "Newton did not converge at the first point"};
+    c->push(q0, c->trial.as<double>(), Cq, rep.newton_steps, s);
+    HIPCHK(hipStreamSynchronize(s));
+    if (first) {
+      std::memset(first, 0, sizeof(*first));
+      first->param = q0;
+      first->Ra = plan->prm.Ra;
+      first->Ek = plan->prm.Ek;
+      first->C = Cq;
+      first->unorm = norm2(plan, c->X[0].as<double>(), s);
+      first->newton_steps = rep.newton_steps;
+      first->matvecs = rep.matvecs;
+      first->converged = 1;
+      first->L = plan->hg.L;
+      first->N = plan->hg.N;
+    }
+    *out = c.release();
+  });
+}
+
+int sc_cont_step(sc_cont* c, double dp_first, sc_cont_point* pt, void* stream) {
+  return guarded([&] {
+    if (!c || !pt) throw Fail{SC_ERR_ARG, "null argument"};
+    check_plan(c->plan);
+    if (c->n == 1 && !(dp_first != 0.0 && std::isfinite(dp_first)))
+      throw Fail{SC_ERR_ARG, "the first step needs a nonzero dp_first"};
+    hipStream_t s = (hipStream_t)stream;
+    const long long n = c->plan->n_real;
+    std::memset(pt, 0, sizeof(*pt));
+    double* xt = c->trial.as<double>();
+    for (int r = 0; r <= c->o.max_retries; ++r) {
+      const double scale = std::ldexp(1.0, -r);
+      double q, Cq, w[3] = {0, 0, 0};
+      bool state_mode = false;
+      const int k = c->n;                       // points used by the prediction (1..3)
+      if (k == 1) {
+        q = c->p[0] + scale * dp_first;
+        w[0] = 1.0;
+      } else {
+        const double alpha = scale * (c->o.n_opt + 1.0) / (std::max(c->its[k - 1], 1) + 1.0);
+        // turning-point test on the last two points (eq:tp_detection_Ra)
+        const long long Jt = argmax_abs(c->X[k - 1].as<double>(), n, s);
+        double u[3];
+        for (int i = 0; i < k; ++i) u[i] = read1(c->X[i].as<double>(), Jt, s);
+        const double dU = std::fabs((u[k - 1] - u[k - 2]) / u[k - 1]);
+        const double dP = std::fabs((c->p[k - 1] - c->p[k - 2]) / c->p[k - 1]);
+        state_mode = dU > scale * c->o.gamma * dP;
+        if (!state_mode) {
+          q = c->p[k - 1] + alpha * (c->p[k - 1] - c->p[k - 2]);
+          for (int i = 0; i < k; ++i) w[i] = lagrange_w(q, c->p, k, i);
+        } else {
+          const double un = u[k - 1] + alpha * (u[k - 1] - u[k - 2]);
+          q = 0.0;
+          for (int i = 0; i < k; ++i) {
+            w[i] = lagrange_w(un, u, k, i);
+            q += w[i] * c->p[i];
+          }
+        }
+      }
+      Cq = 0.0;
+      for (int i = 0; i < k; ++i) Cq += w[i] * c->C[i];
+      const double* x1 = c->X[k > 1 ? 1 : 0].as<double>();
+      const double* x2 = c->X[k > 2 ? 2 : 0].as<double>();
+      hipLaunchKernelGGL(sc::k_lincomb3, dim3(nblk(n, 256)), dim3(256), 0, s, n, w[0], c->X[0].as<const double>(),
+                         w[1], x1, w[2], x2, xt);
+      HIPCHK(hipGetLastError());
+      sc_newton_report rep;
+      const bool ok = c->solve(q, xt, Cq, rep, s);
+      pt->retries = r;
+      pt->newton_steps = rep.newton_steps;
+      pt->matvecs += rep.matvecs;
+      pt->param = q;
+      if (!ok) continue;
+      c->push(q, xt, Cq, rep.newton_steps, s);
+      pt->converged = 1;
+      pt->state_mode = state_mode ? 1 : 0;
+      break;
+    }
+    if (pt->converged && c->o.param == SC_CONT_EK && c->o.refine_tol > 0) {
+      // under-resolution check on the new point (Sec. 4.2): grow N and/or L, M by refine_growth
+      const std::vector<double> h = to_host(c->X[c->n - 1].as<double>(), n, s);
+      double rc = 0, rl = 0;
+      tail_ratios_host(c->plan, h, rc, rl);
+      pt->cheb_ratio = rc;
+      pt->sh_ratio = rl;
+      const sc::HostGrid& g = c->plan->hg;
+      sc_params np = c->plan->prm;
+      np.nr_phys = np.ntheta = np.nphi = 0;
+      if (rc > c->o.refine_tol) np.N = std::min(64, (int)std::ceil(c->o.refine_growth * g.N));
+      if (rl > c->o.refine_tol) {
+        np.L = (int)std::ceil(c->o.refine_growth * g.L);
+        np.M = (int)std::ceil(c->o.refine_growth * g.M);
+      }
+      if (np.N != g.N || np.L != g.L) {
+        sc_plan* fine = nullptr;
+        if (sc_plan_create(&fine, &np) != SC_OK) throw Fail{SC_ERR_ARG, "refinement: " + g_last_error};
+        std::unique_ptr<sc_plan> guard(fine);
+        if (sc_factor(fine, s) != SC_OK) throw Fail{SC_ERR_HIP, "refinement: " + g_last_error};
+        // carry the kept points to the new grid
+        DevBuf Xn[3], tn;
+        for (int i = 0; i < 3; ++i) Xn[i].alloc(fine->n_real * sizeof(double));
+        tn.alloc(fine->n_real * sizeof(double));
+        for (int i = 0; i < c->n; ++i) interp_device(c->plan, c->X[i].as<double>(), fine, Xn[i].as<double>(), s);
+        sc_plan* coarse = c->plan;
+        c->plan = fine;
+        for (int i = 0; i < 3; ++i) {
+          std::swap(c->X[i].p, Xn[i].p);
+          std::swap(c->X[i].bytes, Xn[i].bytes);
+        }
+        std::swap(c->trial.p, tn.p);
+        std::swap(c->trial.bytes, tn.bytes);
+        c->J = phase_slot_host(fine, to_host(c->X[c->n - 1].as<double>(), fine->n_real, s));
+        // recompute the newest point on the new grid
+        HIPCHK(hipMemcpyAsync(c->trial.p, c->X[c->n - 1].p, fine->n_real * sizeof(double), hipMemcpyDeviceToDevice, s));
+        double Cq = c->C[c->n - 1];
+        sc_newton_report rep;
+        if (!c->solve(c->p[c->n - 1], c->trial.as<double>(), Cq, rep, s))
+          throw Fail{SC_ERR_STATE, "refinement: Newton did not converge on the refined grid"};
+        HIPCHK(hipMemcpyAsync(c->X[c->n - 1].p, c->trial.p, fine->n_real * sizeof(double), hipMemcpyDeviceToDevice, s));
+        c->C[c->n - 1] = Cq;
+        pt->matvecs += rep.matvecs;
+        pt->refined = 1;
+        HIPCHK(hipStreamSynchronize(s));
+        guard.release();
+        if (c->owned) delete c->owned;   // the previous refined plan (never the caller's)
+        c->owned = fine;
+        (void)coarse;
+      }
+    }
+    if (pt->converged) {
+      pt->C = c->C[c->n - 1];
+      pt->Ra = c->plan->prm.Ra;
+      pt->Ek = c->plan->prm.Ek;
+      pt->unorm = norm2(c->plan, c->X[c->n - 1].as<double>(), s);
+      pt->L = c->plan->hg.L;
+      pt->N = c->plan->hg.N;
+    }
+  });
+}
+
+int sc_cont_layout(const sc_cont* c, sc_layout_info* out) {
+  if (!c) return fail(SC_ERR_ARG, "null session");
+  return sc_layout(c->plan, out);
+}
+
+int sc_cont_state(sc_cont* c, double* x, long long n, double* C, void* stream) {
+  return guarded([&] {
+    if (!c || !x || !C) throw Fail{SC_ERR_ARG, "null argument"};
+    check_plan(c->plan);
+    if (n != c->plan->n_real) throw Fail{SC_ERR_ARG, "n must equal the current n_real (sc_cont_layout)"};
+    HIPCHK(hipMemcpyAsync(x, c->X[c->n - 1].p, n * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    *C = c->C[c->n - 1];
+  });
+}
+
+int sc_cont_destroy(sc_cont* c) {
+  delete c;
+  return SC_OK;
+}
+
+}  // extern "C"

@@ -2317,4 +2317,84 @@ __global__ void __launch_bounds__(256) k_sqrt_sum(int nparts, const double* __re
   if (threadIdx.x == 0) out[0] = sqrt(red[0]);
 }
 
+// ------------------------------------------------------------------------------------------
+// Continuation and grid refinement (Sec. 3.5, 4.2).
+// out = w0 x0 + w1 x1 + w2 x2 (the quadratic Lagrange prediction; unused terms have weight 0
+// and may repeat a valid pointer).
+__global__ void k_lincomb3(long long n, double w0, const double* __restrict__ x0, double w1,
+                           const double* __restrict__ x1, double w2, const double* __restrict__ x2,
+                           double* __restrict__ out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = w0 * x0[t] + w1 * x1[t] + w2 * x2[t];
+}
+
+// Index and magnitude of the largest |x| over chunk b of `chunk` elements: one workgroup per
+// chunk, ties to the lower index.
+__global__ void __launch_bounds__(256) k_absmax_parts(long long n, const double* __restrict__ x, long long chunk,
+                                                      double* __restrict__ pval, long long* __restrict__ pidx) {
+  __shared__ double sv[256];
+  __shared__ long long si[256];
+  const long long b0 = (long long)blockIdx.x * chunk;
+  const long long b1 = b0 + chunk < n ? b0 + chunk : n;
+  double bv = -1.0;
+  long long bi = b0;
+  for (long long i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+    const double a = fabs(x[i]);
+    if (a > bv) {
+      bv = a;
+      bi = i;
+    }
+  }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double ov = sv[threadIdx.x + w];
+      const long long oi = si[threadIdx.x + w];
+      if (ov > sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+        sv[threadIdx.x] = ov;
+        si[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    pval[blockIdx.x] = sv[0];
+    pidx[blockIdx.x] = si[0];
+  }
+}
+
+// Refinement: y (new layout) from x (old layout) with the same m0.  Every (field, l, m) profile
+// present in both layouts is carried by the interpolation matrix Ip (N_new x N_old, row-major:
+// the old interpolating polynomial evaluated at the new nodes); new degrees and orders are zero.
+// One thread per (field, packed lm of the new layout, new node, Re/Im).
+struct InterpMap {
+  int N_old, N_new, S_old, S_new, L_old, K_old, m0;
+  const int* lmbase_old;   // [K_old + 1]
+  const int* lm_k_new;     // [S_new]
+  const int* lm_l_new;     // [S_new]
+  const double* Ip;        // [N_new][N_old]
+};
+
+__global__ void k_interp(InterpMap im, const double* __restrict__ x, double* __restrict__ y) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = 3LL * im.S_new * im.N_new * 2;
+  if (t >= total) return;
+  const int c = (int)(t & 1);
+  const long long q = t >> 1;
+  const int jn = (int)(q % im.N_new);
+  const long long fl = q / im.N_new;
+  const int lm = (int)(fl % im.S_new), f = (int)(fl / im.S_new);
+  const int k = im.lm_k_new[lm], l = im.lm_l_new[lm];
+  double acc = 0.0;
+  if (k <= im.K_old && l <= im.L_old) {
+    const int lmo = im.lmbase_old[k] + (l - k * im.m0);
+    const double* src = x + 2LL * ((long long)im.N_old * ((long long)f * im.S_old + lmo)) + c;
+    const double* row = im.Ip + (long long)jn * im.N_old;
+    for (int j = 0; j < im.N_old; ++j) acc += row[j] * src[2LL * j];
+  }
+  y[t] = acc;
+}
+
 }  // namespace sc
