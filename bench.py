@@ -285,6 +285,9 @@ def run(args):
     if not args.no_newton:
         log("Newton runs")
         out["newton"] = newton_runs(args, plan, C, lay)
+    if not args.no_c4 and args.workload == "c3":
+        log("batched Newton of 32 uneven problems")
+        out["c4_batch"] = c4_batch(args)
     if not args.no_cpu_baseline:
         log("oracle on the host")
         out["cpu_baseline"] = cpu_baseline(args, X, C, J, lay)
@@ -405,6 +408,204 @@ def cpu_baseline(args, X, C, J, lay):
     return out
 
 
+def action_study(args):
+    """Jacobian actions per continuation point, implicit vs explicit Coriolis (Sec. 5, Figs. 8-10),
+    for the rotating wave RW4 (m0 = 4) along a branch in Ek with Ra = 7.8 Ek^(-1/3) (Ra = 78 at
+    Ek = 1e-3; the paper's path is 6.5 Ek^(-1/3)), and sector (m0 = 4) vs full domain (m0 = 1).
+    GMRES runs with the largest restart the library takes (1024 vectors), i.e. unrestarted for
+    every implicit solve.
+
+    Route: the oracle's RW4 of the tiny shell, carried to L = M = 47, N = 46 and converged
+    (Newton); continuation in log10 Ek with refinement (threshold 1e-6) down to Ek <= 1e-4 and up
+    to Ek >= 1e-2.  At each Ek point: three steps of Ra continuation (first step +2 % of Ra) with
+    implicit Coriolis, then the same from the explicit variant's own root; the actions of the
+    three Newton-GMRES solves are averaged (GMRES tolerance 1e-10, restart 300)."""
+    import torch
+    import paper_2508_16635_amd as sc
+    import seeded_inputs as si
+    here = os.path.dirname(os.path.abspath(__file__))
+    d = np.load(os.path.join(here, "tests", "golden", "rw4_L16_m4_N16.npz"), allow_pickle=False)
+    m0, L, N, coef = 4, 47, 46, 78.0 * 1e-3 ** (1.0 / 3.0)
+    newton_kw = dict(tol=1e-10, gmres_tol=1e-10, restart=1024, max_newton=10, max_matvec=args.study_max_matvec)
+    tiny = sc.Plan(16, 16, m0, 16, Ek=1e-3, Ra=78.0, nvec_max=1)
+    base = sc.Plan(L, L, m0, N, Ek=1e-3, Ra=78.0, dt=200.0, nvec_max=1)
+    base.factor()
+    x = torch.empty(base.n_real, dtype=torch.float64, device="cuda")
+    sc.interpolate(tiny, torch.from_numpy(d["X"]).cuda(), base, x)
+    J = si.default_phase_slot(si.Layout(L, L, m0, N), x.cpu().numpy())
+    C, rep = base.newton(x, float(d["C"]), J, **newton_kw)
+    points = [(1e-3, L, N, x.clone(), C, J)]
+    for dp in (-0.25, 0.25):
+        pl = sc.Plan(L, L, m0, N, Ek=1e-3, Ra=78.0, dt=200.0, nvec_max=1)
+        pl.factor()
+        cont = sc.Continuation(pl, x, C, J, param=sc.SC_CONT_EK, n_opt=3, gamma=450.0, ra_coef=coef,
+                               refine_tol=1e-6, refine_growth=1.2, **newton_kw)
+        last = [1e-3]
+        for _ in range(12):
+            pt = cont.step(dp_first=dp)
+            log(f"Ek continuation: {json.dumps({k: pt[k] for k in ('Ek', 'Ra', 'C', 'L', 'N', 'converged', 'refined')})}")
+            if not pt["converged"]:
+                break
+            last.append(pt["Ek"])
+            if len(last) > 3 and abs(np.log10(last[-1] / last[-3])) < 0.01:
+                break     # the branch turns (a fold in Ek along this Ra path): stop there
+            xs, Cs = cont.state()
+            lay = cont.layout()
+            points.append((pt["Ek"], lay["L"], lay["N"], xs, Cs, si.default_phase_slot(
+                si.Layout(lay["L"], lay["L"], m0, lay["N"]), xs.cpu().numpy())))
+            if (dp < 0 and pt["Ek"] <= 1.0001e-4) or (dp > 0 and pt["Ek"] >= 0.9999e-2):
+                break
+        cont.close()
+    rows = []
+    explicit_failed = False
+    for Ek, Lp, Np, xs, Cs, Jp in sorted(points, key=lambda t: -t[0]):
+        row = {"Ek": Ek, "Ra": coef * Ek ** (-1.0 / 3.0), "L": Lp, "N": Np}
+        for name, cor in (("implicit", sc.SC_CORIOLIS_IMPLICIT), ("explicit", sc.SC_CORIOLIS_EXPLICIT)):
+            if name == "explicit" and explicit_failed:
+                row[name] = {"actions_per_point": None, "skipped": "explicit failed at a larger Ek"}
+                continue
+            pl = sc.Plan(Lp, Lp, m0, Np, Ek=Ek, Ra=row["Ra"], dt=200.0, nvec_max=1, coriolis=cor)
+            pl.factor()
+            t0 = time.perf_counter()
+            cont, C_first = None, None
+            try:
+                cont = sc.Continuation(pl, xs, Cs, Jp, param=sc.SC_CONT_RA, n_opt=4, gamma=50.0, **newton_kw)
+                C_first = cont.first["C"]
+                mv = []
+                for _ in range(3):
+                    pt = cont.step(dp_first=0.02 * row["Ra"])
+                    if not pt["converged"]:
+                        break
+                    mv.append(pt["matvecs"])
+                cont.close()
+            except Exception as e:   # a Newton that does not converge within the caps
+                mv = []
+                log(f"{name} at Ek={Ek:g}: {e}")
+            row[name] = {"actions_per_point": float(np.mean(mv)) if len(mv) == 3 else None, "actions": mv,
+                         "seconds": time.perf_counter() - t0, "C_first": C_first}
+            if name == "explicit" and len(mv) < 3:
+                explicit_failed = True
+            log(f"Ek={Ek:.3g} {name}: {row[name]}")
+            pl.close()
+        a, b = row["implicit"]["actions_per_point"], row["explicit"]["actions_per_point"]
+        row["explicit_over_implicit"] = b / a if a and b else None
+        rows.append(row)
+    # sector vs full domain at Ek = 1e-3: the RW4 embedded in the full-domain layout (m0 = 1)
+    lay4, lay1 = si.Layout(L, L, 4, N), si.Layout(L, L, 1, N)
+    x4 = points[0][3].cpu().numpy()
+    x1 = np.zeros(lay1.n_real)
+    for fld in range(3):
+        for k, m in enumerate(lay4.ms):
+            o4, o1, n = lay4.offset(fld, k, m), lay1.offset(fld, m, m), 2 * N * (L - m + 1)
+            x1[o1:o1 + n] = x4[o4:o4 + n]
+    # the same phase slot as the sector's (an m = 4 entry; the full layout's m = 1 entries are 0)
+    J4 = points[0][5]
+    node4 = J4 // 2
+    fld4, lm4, j4 = node4 // (N * lay4.S), (node4 // N) % lay4.S, node4 % N
+    k4 = max(k for k in range(len(lay4.ms)) if lay4.lm_base[k] <= lm4)
+    l4 = lay4.ms[k4] + lm4 - lay4.lm_base[k4]
+    J1 = lay1.offset(fld4, lay4.ms[k4], l4, j4) + 1
+    dom = {}
+    for name, mm, xx, JJ in (("sector_m0_4", 4, x4, points[0][5]), ("full_m0_1", 1, x1, J1)):
+        pl = sc.Plan(L, L, mm, N, Ek=1e-3, Ra=78.0, dt=200.0, nvec_max=1)
+        pl.factor()
+        cont = sc.Continuation(pl, torch.from_numpy(xx).cuda(), points[0][4], JJ, param=sc.SC_CONT_RA, n_opt=4,
+                               gamma=50.0, **newton_kw)
+        mv, Cs_ = [], []
+        for _ in range(3):
+            pt = cont.step(dp_first=2.0)
+            mv.append(pt["matvecs"])
+            Cs_.append(pt["C"])
+        cont.close()
+        dom[name] = {"actions": mv, "C": Cs_}
+        log(f"{name}: {dom[name]}")
+        pl.close()
+    return {"study": "Jacobian actions per Newton-GMRES solve, RW4 branch", "rows": rows, "domain": dom,
+            "newton": newton_kw, "ra_coef": coef}
+
+
+def c4_problems():
+    """The batched-continuation workload: 32 problems of uneven truncation, i = 0..31:
+    Ek = (3e-5, 1e-4)[i // 16], Ra = Ra_ref(Ek) 3^((i % 16)/15) with Ra_ref = 6.5 Ek^(-1/3),
+    L = M = (64, 80, 96)[i % 3], N = (32, 40)[(i // 3) % 2], m0 = 4 + i % 9, seed 4001 + i."""
+    out = []
+    for i in range(32):
+        Ek = (3e-5, 1e-4)[i // 16]
+        Ra = 6.5 * Ek ** (-1.0 / 3.0) * 3.0 ** ((i % 16) / 15.0)
+        L = (64, 80, 96)[i % 3]
+        N = (32, 40)[(i // 3) % 2]
+        out.append(dict(i=i, Ek=Ek, Ra=Ra, L=L, M=L, N=N, m0=4 + i % 9, seed=4001 + i))
+    return out
+
+
+def c4_state(si, lay, pr):
+    """X* of problem pr, a rotating-wave-like guess: the conductive profile, the order m0 at
+    amplitude 1e-2 with coefficients decaying as (l+1)^-2 (random phases), the orders 2 m0 and
+    above at 1e-4, nothing else at m = 0."""
+    ri, ro = RI_RO
+    X = si.random_state(lay, pr["seed"], amp=(1.0, 1.0, 1.0), p=2.0, t_offset=lambda x: ro * ri / ((x + ri + ro) / 2) - ri)
+    Xc = si.random_state(lay, pr["seed"], amp=(0.0, 0.0, 0.0), p=2.0, t_offset=lambda x: ro * ri / ((x + ri + ro) / 2) - ri)
+    for fld in range(3):
+        for k, m in enumerate(lay.ms):
+            o = lay.offset(fld, k, m)
+            n = 2 * lay.N * lay.nl[k]
+            X[o:o + n] = Xc[o:o + n] if k == 0 else X[o:o + n] * (1e-2 if k == 1 else 1e-4)
+    return X
+
+
+def c4_batch(args):
+    """All 32 problems' manufactured Newton-GMRES solves (root X*, forcing -R(X*), start
+    X* + 1e-3 |X*| d) in one sc_batch_newton call: every plan on its own stream branch, driven by
+    a host thread of its own, its Arnoldi steps on the device in chunks of 8 between host checks.
+    Mixed Jacobian actions (GMRES tolerance 1e-6), Newton residual in FP64 to 1e-10.  Reports the
+    aggregate Jacobian actions per second."""
+    import torch
+    import paper_2508_16635_amd as sc
+    import seeded_inputs as si
+    probs = c4_problems()
+    plans, xs, Cs, Js, Fs, Xs = [], [], [], [], [], []
+    t0 = time.perf_counter()
+    for pr in probs:
+        p = sc.Plan(pr["L"], pr["M"], pr["m0"], pr["N"], Ek=pr["Ek"], Ra=pr["Ra"], Pr=1.0, dt=200.0, nvec_max=1)
+        p.factor()
+        lay = si.Layout(pr["L"], pr["M"], pr["m0"], pr["N"])
+        X = c4_state(si, lay, pr)
+        J = si.default_phase_slot(lay, X)
+        Xd = torch.from_numpy(X).cuda()
+        F = torch.empty_like(Xd)
+        p.newton_residual(Xd, 0.5, F)
+        F.neg_()
+        d = si.random_state(lay, pr["seed"] + 1000, p=2.0)
+        d[lay.nonphysical_mask()] = 0.0
+        d[J] = 0.0
+        d *= 1e-3 * np.linalg.norm(X) / np.linalg.norm(d)
+        plans.append(p)
+        xs.append(torch.from_numpy(X + d).cuda())
+        Cs.append(0.501)
+        Js.append(J)
+        Fs.append(F)
+        Xs.append(Xd)
+    t_setup = time.perf_counter() - t0
+    log(f"C4: 32 plans factored in {t_setup:.1f} s")
+    b = sc.Batch(plans)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = b.newton(xs, Cs, Js, tol=1e-10, gmres_tol=1e-6, restart=args.c4_restart, max_newton=8,
+                   max_matvec=1000, prec=sc.SC_MIXED, forcings=Fs)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    b.close()
+    mv = sum(rep["matvecs"] for _, rep in out)
+    errs = [float((x - X).norm() / X.norm()) for x, X in zip(xs, Xs)]
+    res = {"problems": 32, "converged": sum(rep["converged"] for _, rep in out), "jacobian_actions": mv,
+           "seconds": secs, "jvp_per_s": mv / secs, "setup_s": t_setup, "restart": args.c4_restart,
+           "max_rel_err_vs_root": max(errs), "max_final_rnorm": max(rep["rnorm"][-1] for _, rep in out),
+           "newton_steps": [rep["newton_steps"] for _, rep in out], "actions": [rep["matvecs"] for _, rep in out]}
+    for p in plans:
+        p.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -427,6 +628,12 @@ def main():
     ap.add_argument("--restart", type=int, default=1000,
                     help="GMRES restart of the Newton runs (GMRES(40) stagnates on the timed state)")
     ap.add_argument("--max-matvec", type=int, default=3000)
+    ap.add_argument("--study", choices=("actions",), default=None,
+                    help="actions: Jacobian actions per continuation point, implicit vs explicit Coriolis and "
+                         "sector vs full domain (prints its own JSON line instead of the benchmark)")
+    ap.add_argument("--study-max-matvec", type=int, default=8000)
+    ap.add_argument("--no-c4", action="store_true", help="skip the 32-problem batched Newton leg")
+    ap.add_argument("--c4-restart", type=int, default=200)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy (y = 1.0 * x, fp32) of MIB MiB five times: the reference "
                          "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -440,6 +647,9 @@ def main():
             torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 5}), flush=True)
+        return
+    if args.study == "actions":
+        print(json.dumps(action_study(args)), flush=True)
         return
     global WORKLOAD
     WORKLOAD = WORKLOADS[args.workload]

@@ -66,6 +66,9 @@ typedef struct {
   int mixed_solve;        /* implicit solve of SC_MIXED: SC_MIXED_SOLVE_FP64 (0 = default) or
                              SC_MIXED_SOLVE_FP32                                               */
   int coriolis;           /* SC_CORIOLIS_IMPLICIT (0, default) or SC_CORIOLIS_EXPLICIT           */
+  int graph_capture;      /* must be 0: capturing the Krylov chunks and batch calls into HIP
+                             graphs is switched off in this build (a captured batch call crashed
+                             the host process; cause not found); nonzero gives SC_ERR_ARG          */
 } sc_params;
 
 /* Treatment of the Coriolis force.  SC_CORIOLIS_IMPLICIT: in the implicit operator K, coupling

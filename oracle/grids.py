@@ -13,6 +13,7 @@ a nodal vector stands for its interpolating polynomial of degree N-1.
 """
 from __future__ import annotations
 
+import functools
 import math
 from dataclasses import dataclass, field
 
@@ -118,10 +119,46 @@ def default_grid_sizes(L: int, M: int, m0: int, N: int):
     return Np, nth, nphi
 
 
+@functools.lru_cache(maxsize=32)
+def _gauss_legendre_cached(nth: int):
+    return _gauss_legendre(nth)
+
+
 def gauss_legendre(nth: int):
-    """Gauss-Legendre nodes x = cos(theta) (descending, north first) and weights."""
-    x, w = nplegendre.leggauss(nth)
-    return x[::-1].copy(), w[::-1].copy()
+    """Copies of the cached (nodes, weights, sin(theta)) of _gauss_legendre."""
+    return tuple(a.copy() for a in _gauss_legendre_cached(nth))
+
+
+def _gauss_legendre(nth: int):
+    """Gauss-Legendre nodes x = cos(theta) (descending, north first), weights and sin(theta).
+
+    numpy's leggauss gives the nodes to double precision, but its weights lose up to 3e-11 of
+    relative accuracy at the nodes next to the poles (where 1 - x^2 is small), which the m = 0
+    analysis feels.  So each node is polished by Newton's iteration on P_n in 40-digit arithmetic
+    (three-term recurrence), and w = 2 / ((1 - x^2) P_n'(x)^2) and sin(theta) = sqrt(1 - x^2) are
+    evaluated there before rounding to double."""
+    import mpmath
+    x0, _ = nplegendre.leggauss(nth)
+    x0 = x0[::-1]
+    x = np.empty(nth)
+    w = np.empty(nth)
+    st = np.empty(nth)
+    with mpmath.workdps(40):
+        def pn(z):
+            p0, p1 = mpmath.mpf(1), z
+            for k in range(1, nth):
+                p0, p1 = p1, ((2 * k + 1) * z * p1 - k * p0) / (k + 1)
+            return p1, p0                      # P_n(z), P_(n-1)(z)
+        for j in range((nth + 1) // 2):        # northern half; the rest by symmetry
+            z = mpmath.mpf(float(x0[j]))
+            for _ in range(4):
+                p, q = pn(z)
+                z = z - p / (nth * (z * p - q) / (z * z - 1))
+            p, q = pn(z)
+            dp = nth * (z * p - q) / (z * z - 1)
+            x[j], w[j], st[j] = float(z), float(2 / ((1 - z * z) * dp * dp)), float(mpmath.sqrt(1 - z * z))
+            x[nth - 1 - j], w[nth - 1 - j], st[nth - 1 - j] = -x[j], w[j], st[j]
+    return x, w, st
 
 
 def norm_factor(l: int, m: int) -> float:
@@ -131,15 +168,17 @@ def norm_factor(l: int, m: int) -> float:
     return math.sqrt((2.0 - (m == 0)) * (2 * l + 1) * math.exp(lr))
 
 
-def legendre_tables(L: int, ms, x: np.ndarray):
+def legendre_tables(L: int, ms, x: np.ndarray, s: np.ndarray = None):
     """Normalized associated Legendre functions Pbar_l^m = N_l^m P_l^m(x) (no Condon-Shortley
-    phase), their theta-derivative and m Pbar/sin(theta), at the nodes x = cos(theta).
+    phase), their theta-derivative and m Pbar/sin(theta), at the nodes x = cos(theta); s is
+    sin(theta) (default sqrt(1 - x^2), which loses digits next to the poles).
 
     Returns dicts keyed by m of arrays [l - m, j].  The recursion is the textbook one
     for sqrt((2l+1)(l-m)!/(l+m)!) P_l^m (sectoral seed, then the three-term recursion
     in l); the theta-derivative uses (1-x^2) dP_l^m/dx = -l x P_l^m + (l+m) P_{l-1}^m.
     """
-    s = np.sqrt(1.0 - x * x)
+    if s is None:
+        s = np.sqrt(1.0 - x * x)
     P, dP, mPs = {}, {}, {}
     pmm = np.ones_like(x)                       # p_0^0
     for m in range(0, max(ms) + 1):
@@ -193,8 +232,7 @@ class Grid:
         self.rad = Radial(self.N, self.Np, self.ri, self.ro)
         self.K = min(self.M, self.L) // self.m0
         self.ms = [k * self.m0 for k in range(self.K + 1)]
-        self.ct, self.wt = gauss_legendre(self.nth)
-        self.st = np.sqrt(1.0 - self.ct ** 2)
-        self.P, self.dP, self.mPs = legendre_tables(self.L, self.ms, self.ct)
+        self.ct, self.wt, self.st = gauss_legendre(self.nth)
+        self.P, self.dP, self.mPs = legendre_tables(self.L, self.ms, self.ct, self.st)
         # sector grid: phi_k = 2 pi k /(m0 N_phi)
         self.phi = 2.0 * np.pi * np.arange(self.nphi) / (self.m0 * self.nphi)

@@ -37,7 +37,7 @@ class _Params(ctypes.Structure):
                 ("nr_phys", ctypes.c_int), ("ntheta", ctypes.c_int), ("nphi", ctypes.c_int),
                 ("device", ctypes.c_int), ("nvec_max", ctypes.c_int),
                 ("refine_fp64", ctypes.c_int), ("refine_mixed", ctypes.c_int), ("mixed_solve", ctypes.c_int),
-                ("coriolis", ctypes.c_int)]
+                ("coriolis", ctypes.c_int), ("graph_capture", ctypes.c_int)]
 
 
 class _Layout(ctypes.Structure):
@@ -169,10 +169,11 @@ class Plan:
     """One shell discretization with its tables, factors and workspaces on one GPU."""
 
     def __init__(self, L, M, m0, N, Ek, Ra, Pr=1.0, dt=200.0, radius_ratio=0.35, device=0, nvec_max=16,
-                 refine_fp64=-1, refine_mixed=-1, nr_phys=0, ntheta=0, nphi=0, mixed_solve=0, coriolis=0):
+                 refine_fp64=-1, refine_mixed=-1, nr_phys=0, ntheta=0, nphi=0, mixed_solve=0, coriolis=0,
+                 graph_capture=0):
         lib = load_library()
         p = _Params(L, M, m0, N, radius_ratio, Ek, Ra, Pr, dt, nr_phys, ntheta, nphi, device, nvec_max,
-                    refine_fp64, refine_mixed, mixed_solve, coriolis)
+                    refine_fp64, refine_mixed, mixed_solve, coriolis, int(graph_capture))
         h = ctypes.c_void_p()
         _check(lib.sc_plan_create(ctypes.byref(h), ctypes.byref(p)))
         self._h = h

@@ -1481,6 +1481,7 @@ template <class T, bool STEP, int RTN>
 __global__ void __launch_bounds__(256) k_project_rhs(DevGrid g, PhysParams ph, int nvec, const T* __restrict__ As,
                                                      const T* __restrict__ Av, const double* __restrict__ v,
                                                      long long ldv, long long J, double C,
+                                                     const double* __restrict__ Cdev,
                                                      const double* __restrict__ MX, double* __restrict__ b) {
   extern __shared__ unsigned char smem_raw[];
   const int N = g.N, Np = g.Np;
@@ -1502,6 +1503,9 @@ __global__ void __launch_bounds__(256) k_project_rhs(DevGrid g, PhysParams ph, i
   double* bb = b + (long long)vec * 6LL * N * g.S;
   double cval = 0.0;
   if (!STEP && J >= 0) cval = v[(long long)vec * ldv + J];
+  // the drift speed of the base state is read from device memory in the Jacobian action, so a
+  // captured graph of it stays valid when only the base state changes
+  if (!STEP) C = Cdev[0];
   // analysis outputs on the N_p nodes: column (c, t) = c * 8 + t
   staged_copy<10, T>(
       4 * rowsP * 16,
@@ -2395,6 +2399,106 @@ __global__ void k_interp(InterpMap im, const double* __restrict__ x, double* __r
     for (int j = 0; j < im.N_old; ++j) acc += row[j] * src[2LL * j];
   }
   y[t] = acc;
+}
+
+// Device-side Arnoldi (restarted GMRES without a host round trip per step).
+// out[i] = sum over c of part[i * nchunk + c], i < k, in a fixed order.
+__global__ void k_dots_reduce(const double* __restrict__ part, int k, int nchunk, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(long long)i * nchunk + c];
+  out[i] = s;
+}
+
+// Dot products of w with every V_i, i < k, in one pass: workgroup b owns the elements
+// [b len, (b + 1) len) of w (len = 4 * 256, kept in registers) and reads each V_i once;
+// part[i * nchunk + b] is its partial sum (summed in a fixed order by k_dots_reduce).
+constexpr int kDotsPerThread = 4;
+constexpr int kDotsMaxK = 1025;
+__global__ void __launch_bounds__(256) k_dots_multi(const double* __restrict__ V, long long ldv, int k,
+                                                    const double* __restrict__ w, long long n, int nchunk,
+                                                    double* __restrict__ part) {
+  __shared__ double red[4][kDotsMaxK];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const long long base = (long long)blockIdx.x * (256 * kDotsPerThread);
+  double wr[kDotsPerThread];
+  long long idx[kDotsPerThread];
+#pragma unroll
+  for (int q = 0; q < kDotsPerThread; ++q) {
+    idx[q] = base + tid + 256LL * q;
+    wr[q] = idx[q] < n ? w[idx[q]] : 0.0;
+  }
+  for (int i = 0; i < k; ++i) {
+    const double* v = V + (long long)i * ldv;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kDotsPerThread; ++q)
+      if (idx[q] < n) s += v[idx[q]] * wr[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) red[wave][i] = s;
+  }
+  __syncthreads();
+  for (int i = tid; i < k; i += blockDim.x)
+    part[(long long)i * nchunk + blockIdx.x] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+}
+
+// Step j's tail, one thread: column j of the Hessenberg matrix (Hc, column-major with leading
+// dimension ld = restart + 1) from the two Gram-Schmidt passes, h_{j+1,j} = ||w|| from its chunk
+// partials, the previous Givens rotations applied to the column, rotation j, the rotated
+// right-hand side g, the residual estimate res[j] = |g_{j+1}| and hinv = 1/h_{j+1,j} (0 at a
+// breakdown).
+__global__ void k_arnoldi_tail(int j, int ld, const double* __restrict__ h1, const double* __restrict__ h2,
+                               const double* __restrict__ pn, int nchunk, double* __restrict__ Hc,
+                               double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+                               double* __restrict__ res, double* __restrict__ hinv) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double* col = Hc + (long long)j * ld;
+  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+  double ss = 0.0;
+  for (int c = 0; c < nchunk; ++c) ss += pn[c];
+  const double hn = sqrt(ss);
+  hinv[0] = hn > 0.0 ? 1.0 / hn : 0.0;
+  for (int i = 0; i < j; ++i) {
+    const double a = col[i], b = col[i + 1];
+    col[i] = cs[i] * a + sn[i] * b;
+    col[i + 1] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = col[j];
+  const double den = hypot(a, hn);
+  cs[j] = den > 0.0 ? a / den : 1.0;
+  sn[j] = den > 0.0 ? hn / den : 0.0;
+  col[j] = den;
+  col[j + 1] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  res[j] = fabs(g[j + 1]);
+}
+
+// Start of a GMRES cycle, one thread: beta = ||r|| from its chunk partials, g = beta e_1,
+// hinv = 1/beta.
+__global__ void k_cycle_init(int ld, const double* __restrict__ pn, int nchunk, double* __restrict__ g,
+                             double* __restrict__ hinv) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double ss = 0.0;
+  for (int c = 0; c < nchunk; ++c) ss += pn[c];
+  const double beta = sqrt(ss);
+  g[0] = beta;
+  for (int i = 1; i < ld; ++i) g[i] = 0.0;
+  hinv[0] = beta > 0.0 ? 1.0 / beta : 0.0;
+}
+
+// x[0] = v (a device scalar written in stream order)
+__global__ void k_set1(double* __restrict__ x, double v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) x[0] = v;
+}
+
+// dst = alpha[0] * src (alpha read from device memory)
+__global__ void k_scale_dev(double* __restrict__ dst, const double* __restrict__ src, const double* __restrict__ alpha,
+                            long long n) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) dst[t] = alpha[0] * src[t];
 }
 
 }  // namespace sc

@@ -80,36 +80,56 @@ std::vector<double> bary_interp(const std::vector<double>& xs, const std::vector
   return E;
 }
 
-// Gauss-Legendre nodes (descending cos theta) and weights by Newton's iteration on P_n.
-void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+// Gauss-Legendre nodes x_j = cos(theta_j) (descending), weights and sin(theta_j), computed in
+// the host's extended precision (long double) and rounded once.  Newton's iteration runs on theta
+// (northern half; the southern nodes by symmetry).  Next to the poles (x > 1/2) P_n(cos theta)
+// comes from the three-term recurrence written for the differences d_k = P_k - P_(k-1), driven
+// by y = 1 - x = 2 sin^2(theta/2): d_(k+1) = (k d_k - (2k+1) y P_k)/(k+1), P_(k+1) = P_k + d_(k+1);
+// elsewhere from the plain one.  Nothing depends on 1 - x^2 formed from a rounded x, which loses
+// digits next to the poles: sin(theta) comes from theta, and at a root of P_n the weight is
+// w = 2 (1 - x^2) / (n P_(n-1))^2 = 2 sin^2(theta) / (n P_(n-1))^2.
+typedef long double ld_t;
+
+static void legendre_pair(int n, ld_t th, ld_t& pn, ld_t& pn1) {
+  const ld_t sh = std::sin(0.5L * th), y = 2.0L * sh * sh, x = std::cos(th);
+  ld_t prev = 1.0L, cur = 1.0L - y, d = -y;   // P_0, P_1, P_1 - P_0
+  for (int k = 1; k < n; ++k) {
+    ld_t dn;
+    if (y < 0.5L) dn = (k * d - (2.0L * k + 1.0L) * y * cur) / (k + 1.0L);
+    else dn = ((2.0L * k + 1.0L) * x * cur - k * prev) / (k + 1.0L) - cur;
+    prev = cur;
+    cur += dn;
+    d = dn;
+  }
+  pn = cur;     // P_n
+  pn1 = prev;   // P_(n-1)
+}
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w, std::vector<double>& st) {
   x.assign(n, 0.0);
   w.assign(n, 0.0);
-  for (int i = 0; i < n; ++i) {
-    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
-    double dp = 1.0;
+  st.assign(n, 0.0);
+  const ld_t pi = 3.14159265358979323846264338327950288L;
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    ld_t th = pi * (i + 0.75L) / (n + 0.5L);
+    ld_t pn = 0.0L, pn1 = 0.0L;
     for (int it = 0; it < 100; ++it) {
-      double p0 = 1.0, p1 = z;  // after the loop: p1 = P_n(z), p0 = P_{n-1}(z)
-      for (int k = 2; k <= n; ++k) {
-        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-        p0 = p1;
-        p1 = p2;
-      }
-      dp = n * (z * p1 - p0) / (z * z - 1.0);
-      double dz = p1 / dp;
-      z -= dz;
-      if (std::fabs(dz) < 1e-16) break;
+      legendre_pair(n, th, pn, pn1);
+      const ld_t dth = n * (std::cos(th) * pn - pn1) / std::sin(th);   // dP_n/dtheta
+      const ld_t step = pn / dth;
+      th -= step;
+      if (std::fabs(step) <= 1e-18L * th) break;
     }
-    // final derivative at the converged node
-    double p0 = 1.0, p1 = z;
-    for (int k = 2; k <= n; ++k) {
-      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-      p0 = p1;
-      p1 = p2;
-    }
-    dp = n * (z * p1 - p0) / (z * z - 1.0);
-    x[i] = z;
-    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    legendre_pair(n, th, pn, pn1);
+    const ld_t s = std::sin(th), q = n * pn1;
+    x[i] = (double)std::cos(th);
+    st[i] = (double)s;
+    w[i] = (double)(2.0L * s * s / (q * q));
+    x[n - 1 - i] = -x[i];
+    st[n - 1 - i] = st[i];
+    w[n - 1 - i] = w[i];
   }
+  if (n % 2) x[n / 2] = 0.0;   // the equatorial node of an odd rule
 }
 
 }  // namespace
@@ -186,9 +206,7 @@ void build_grid(HostGrid& g, int L, int M, int m0, int N, double eta, int Np, in
     }
 
   // angular grid and normalized associated Legendre functions (no Condon-Shortley phase)
-  gauss_legendre(g.nth, g.ct, g.wt);
-  g.st.resize(g.nth);
-  for (int j = 0; j < g.nth; ++j) g.st[j] = std::sqrt(std::max(0.0, 1.0 - g.ct[j] * g.ct[j]));
+  gauss_legendre(g.nth, g.ct, g.wt, g.st);
   g.Pb.assign(g.K + 1, {});
   g.dPb.assign(g.K + 1, {});
   g.mPs.assign(g.K + 1, {});

@@ -6,13 +6,8 @@ import numpy as np
 
 FIELDS = ("e", "f", "T")
 
-# Per-block bar of the FP64 path.  In every FP64 case measured the worst block is the temperature
-# block at m = 0 (low degrees l = 1, 2, mid-radius nodes): up to 2.2e-11 of its largest element at
-# L = 255 and 1.5e-11 at L = 128 (absolute 2e-12 against a block maximum of 0.12; global errors
-# stay <= 4e-13).  More FP64 refinement passes leave it unchanged, so it comes from
-# the right-hand side, not from the implicit solve; the oracle's own rounding noise there,
-# measured by rotation equivariance, is 1e-14.  Its source is not localized; the bar is 1e-10.
-FP64_BLOCK = 1e-10
+# Per-block bar of the FP64 path (every (field, m) block to 1e-11 of its own largest element).
+FP64_BLOCK = 1e-11
 
 
 def rel(a, b):

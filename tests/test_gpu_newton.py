@@ -98,3 +98,35 @@ def test_newton_converges_to_the_rw4_of_the_oracle(sc, prec):
     print(f"RW4 prec={prec}: {rep}; |X - X*|/|X*| {ex:.2e}, |C - C*|/|C*| {ec:.2e}", flush=True)
     assert rep["converged"] and rep["rnorm"][-1] <= 1e-12
     assert ex <= 1e-10 and ec <= 1e-10
+
+
+@pytest.mark.skip(reason="HIP graph capture is switched off (a captured batch call crashed the host process; "
+                         "cause not found); this case uses the same capture path")
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_newton_with_graph_capture_equals_eager(sc, prec):
+    """graph_capture: the Arnoldi chunks of GMRES are captured into HIP graphs and replayed (the
+    same graphs across restart cycles and Newton steps: the drift speed is read from device
+    memory); the Newton history, state and drift speed are identical to the eager launches."""
+    L, M, m0, N, Ek, Ra = 12, 12, 4, 14, 1e-3, 78.0
+    out = []
+    for gc in (0, 1):
+        plan = sc.Plan(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=200.0, nvec_max=1, graph_capture=gc)
+        plan.factor()
+        ora = Problem(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=200.0)
+        lay = si.Layout(L, M, m0, N)
+        Xs = ora.clean(si.random_state(lay, 3999, amp=(0.1, 0.1, 0.1), p=2) + ora.conductive_state())
+        J = si.default_phase_slot(lay, Xs)
+        Fd = torch.empty(plan.n_real, dtype=torch.float64, device="cuda")
+        plan.newton_residual(_dev(Xs), 0.5, Fd)
+        Fd.neg_()
+        d = ora.clean(si.random_state(lay, 77, p=2))
+        d[J] = 0.0
+        xd = _dev(Xs + 1e-3 * np.linalg.norm(Xs) * d / np.linalg.norm(d))
+        C, rep = plan.newton(xd, 0.501, J, tol=1e-10, gmres_tol=1e-10 if prec == 0 else 1e-6, restart=20,
+                             max_newton=10, max_matvec=400, prec=prec, forcing=Fd)
+        print(f"graph_capture={gc}: {rep}", flush=True)
+        assert rep["converged"]
+        out.append((xd.cpu().numpy(), C, rep))
+        plan.close()
+    (X0, C0, r0), (X1, C1, r1) = out
+    assert r0 == r1 and C0 == C1 and np.array_equal(X0, X1)

@@ -147,3 +147,16 @@ def test_kappa_equals_printed_coefficients():
         for l in range(max(m, 1), 60):
             assert abs(kappa(l, m) - kappa_from_paper(l, m, "lower")) < 1e-12 * max(1, kappa(l, m))
             assert abs(kappa(l + 1, m) - kappa_from_paper(l, m, "upper")) < 1e-12 * max(1, kappa(l + 1, m))
+
+
+def test_gauss_legendre_moments_to_rounding():
+    """Gauss quadrature with n nodes integrates x^(2k) exactly for 2k <= 2n - 1; the highest
+    moments live next to the poles, so they fix the weights of the polar nodes (where the weights
+    numpy's leggauss returns are off by up to 3e-11)."""
+    from oracle.grids import gauss_legendre
+    for n in (26, 98, 194):
+        x, w, st = gauss_legendre(n)
+        assert np.abs(st * st + x * x - 1).max() < 5e-16
+        for k in (0, n // 2, n - 1):
+            exact = 2.0 / (2 * k + 1)
+            assert abs((w * x ** (2 * k)).sum() - exact) <= 1e-14 * exact, (n, k)
