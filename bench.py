@@ -282,6 +282,9 @@ def run(args):
     }
     log("single-vector rates")
     out["nvec1_jvp_per_s"] = single_vector_rates(args, plan, batch, sc)
+    if args.batch_scaling and args.workload == "c3":
+        log("larger batches")
+        out["batch_scaling_jvp_per_s"] = batch_scaling(args, W, Xd, C, J, V, sc)
     if not args.no_newton:
         log("Newton runs")
         out["newton"] = newton_runs(args, plan, C, lay)
@@ -335,6 +338,31 @@ def newton_runs(args, plan, C, lay):
                      "gmres_tol": gtol}
     res["mixed_speedup_vs_fp64"] = res["fp64"]["seconds"] / res["mixed"]["seconds"]
     return res
+
+
+def batch_scaling(args, W, Xd, C, J, V, sc):
+    """jvp/s of both paths with 32 and 64 vectors per call (a plan sized for 64, the plan's
+    default kernels), context for the 16-vector headline."""
+    import torch
+    plan = sc.Plan(W["L"], W["M"], W["m0"], W["N"], Ek=W["Ek"], Ra=W["Ra"], Pr=W["Pr"], dt=W["dt"], nvec_max=64)
+    plan.factor()
+    plan.set_base(Xd, C, J)
+    out = {}
+    for nv in (32, 64):
+        v = V[:nv]
+        y = torch.empty_like(v)
+        for name, prec in (("mixed", sc.SC_MIXED), ("fp64", sc.SC_FP64)):
+            for _ in range(2):
+                plan.jvp(v, y, prec)
+            torch.cuda.synchronize()
+            reps = max(args.steps // 2, 3)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                plan.jvp(v, y, prec)
+            torch.cuda.synchronize()
+            out[f"{name}_nvec{nv}"] = reps * nv / (time.perf_counter() - t0)
+    plan.close()
+    return out
 
 
 def single_vector_rates(args, plan, batch, sc):
@@ -456,40 +484,6 @@ def action_study(args):
             if (dp < 0 and pt["Ek"] <= 1.0001e-4) or (dp > 0 and pt["Ek"] >= 0.9999e-2):
                 break
         cont.close()
-    rows = []
-    explicit_failed = False
-    for Ek, Lp, Np, xs, Cs, Jp in sorted(points, key=lambda t: -t[0]):
-        row = {"Ek": Ek, "Ra": coef * Ek ** (-1.0 / 3.0), "L": Lp, "N": Np}
-        for name, cor in (("implicit", sc.SC_CORIOLIS_IMPLICIT), ("explicit", sc.SC_CORIOLIS_EXPLICIT)):
-            if name == "explicit" and explicit_failed:
-                row[name] = {"actions_per_point": None, "skipped": "explicit failed at a larger Ek"}
-                continue
-            pl = sc.Plan(Lp, Lp, m0, Np, Ek=Ek, Ra=row["Ra"], dt=200.0, nvec_max=1, coriolis=cor)
-            pl.factor()
-            t0 = time.perf_counter()
-            cont, C_first = None, None
-            try:
-                cont = sc.Continuation(pl, xs, Cs, Jp, param=sc.SC_CONT_RA, n_opt=4, gamma=50.0, **newton_kw)
-                C_first = cont.first["C"]
-                mv = []
-                for _ in range(3):
-                    pt = cont.step(dp_first=0.02 * row["Ra"])
-                    if not pt["converged"]:
-                        break
-                    mv.append(pt["matvecs"])
-                cont.close()
-            except Exception as e:   # a Newton that does not converge within the caps
-                mv = []
-                log(f"{name} at Ek={Ek:g}: {e}")
-            row[name] = {"actions_per_point": float(np.mean(mv)) if len(mv) == 3 else None, "actions": mv,
-                         "seconds": time.perf_counter() - t0, "C_first": C_first}
-            if name == "explicit" and len(mv) < 3:
-                explicit_failed = True
-            log(f"Ek={Ek:.3g} {name}: {row[name]}")
-            pl.close()
-        a, b = row["implicit"]["actions_per_point"], row["explicit"]["actions_per_point"]
-        row["explicit_over_implicit"] = b / a if a and b else None
-        rows.append(row)
     # sector vs full domain at Ek = 1e-3: the RW4 embedded in the full-domain layout (m0 = 1)
     lay4, lay1 = si.Layout(L, L, 4, N), si.Layout(L, L, 1, N)
     x4 = points[0][3].cpu().numpy()
@@ -506,7 +500,7 @@ def action_study(args):
     l4 = lay4.ms[k4] + lm4 - lay4.lm_base[k4]
     J1 = lay1.offset(fld4, lay4.ms[k4], l4, j4) + 1
     dom = {}
-    for name, mm, xx, JJ in (("sector_m0_4", 4, x4, points[0][5]), ("full_m0_1", 1, x1, J1)):
+    for name, mm, xx, JJ in (("sector_m0_4", 4, x4, J4), ("full_m0_1", 1, x1, J1)):
         pl = sc.Plan(L, L, mm, N, Ek=1e-3, Ra=78.0, dt=200.0, nvec_max=1)
         pl.factor()
         cont = sc.Continuation(pl, torch.from_numpy(xx).cuda(), points[0][4], JJ, param=sc.SC_CONT_RA, n_opt=4,
@@ -516,10 +510,40 @@ def action_study(args):
             pt = cont.step(dp_first=2.0)
             mv.append(pt["matvecs"])
             Cs_.append(pt["C"])
+            log(f"{name}: Ra {pt['Ra']:.3f} C {pt['C']:.6f} actions {pt['matvecs']} converged {pt['converged']}")
         cont.close()
         dom[name] = {"actions": mv, "C": Cs_}
-        log(f"{name}: {dom[name]}")
         pl.close()
+    rows = []
+    for Ek, Lp, Np, xs, Cs, Jp in sorted(points, key=lambda t: -t[0]):
+        row = {"Ek": Ek, "Ra": coef * Ek ** (-1.0 / 3.0), "L": Lp, "N": Np}
+        for name, cor in (("implicit", sc.SC_CORIOLIS_IMPLICIT), ("explicit", sc.SC_CORIOLIS_EXPLICIT)):
+            if name == "explicit" and Ek < args.study_explicit_min_ek:
+                row[name] = {"actions_per_point": None,
+                             "skipped": f"below Ek = {args.study_explicit_min_ek:g} (tens of thousands of actions per point)"}
+                continue
+            pl = sc.Plan(Lp, Lp, m0, Np, Ek=Ek, Ra=row["Ra"], dt=200.0, nvec_max=1, coriolis=cor)
+            pl.factor()
+            t0 = time.perf_counter()
+            mv, C_first = [], None
+            try:
+                cont = sc.Continuation(pl, xs, Cs, Jp, param=sc.SC_CONT_RA, n_opt=4, gamma=50.0, **newton_kw)
+                C_first = cont.first["C"]
+                for _ in range(3):
+                    pt = cont.step(dp_first=0.02 * row["Ra"])
+                    log(f"Ek={Ek:.3g} {name}: Ra {pt['Ra']:.3f} actions {pt['matvecs']} converged {pt['converged']}")
+                    if not pt["converged"]:
+                        break
+                    mv.append(pt["matvecs"])
+                cont.close()
+            except Exception as e:   # a Newton that does not converge within the caps
+                log(f"{name} at Ek={Ek:g}: {e}")
+            row[name] = {"actions_per_point": float(np.mean(mv)) if len(mv) == 3 else None, "actions": mv,
+                         "seconds": time.perf_counter() - t0, "C_first": C_first}
+            pl.close()
+        a, b = row["implicit"]["actions_per_point"], row["explicit"]["actions_per_point"]
+        row["explicit_over_implicit"] = b / a if a and b else None
+        rows.append(row)
     return {"study": "Jacobian actions per Newton-GMRES solve, RW4 branch", "rows": rows, "domain": dom,
             "newton": newton_kw, "ra_coef": coef}
 
@@ -591,7 +615,7 @@ def c4_batch(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = b.newton(xs, Cs, Js, tol=1e-10, gmres_tol=1e-6, restart=args.c4_restart, max_newton=8,
-                   max_matvec=1000, prec=sc.SC_MIXED, forcings=Fs)
+                   max_matvec=2000, prec=sc.SC_MIXED, forcings=Fs)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     b.close()
@@ -632,8 +656,10 @@ def main():
                     help="actions: Jacobian actions per continuation point, implicit vs explicit Coriolis and "
                          "sector vs full domain (prints its own JSON line instead of the benchmark)")
     ap.add_argument("--study-max-matvec", type=int, default=8000)
+    ap.add_argument("--study-explicit-min-ek", type=float, default=1.1e-4)
     ap.add_argument("--no-c4", action="store_true", help="skip the 32-problem batched Newton leg")
-    ap.add_argument("--c4-restart", type=int, default=200)
+    ap.add_argument("--batch-scaling", type=int, default=1, help="also time 32 and 64 vectors per call (0: skip)")
+    ap.add_argument("--c4-restart", type=int, default=1000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy (y = 1.0 * x, fp32) of MIB MiB five times: the reference "
                          "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters")

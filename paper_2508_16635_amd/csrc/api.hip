@@ -123,8 +123,8 @@ struct sc_plan {
   DevBuf Tinv64, tr64, tc64, Tinv32, tr32, tc32;
   // Newton-GMRES workspace (allocated by the first sc_newton call)
   DevBuf kV, kW, kR, kDu, kPart, kH;
-  DevBuf kHc, kGiv, kRes;  // device Arnoldi: Hessenberg columns, Givens (cs, sn, g), residual estimates
-                           // kGiv also holds the two Gram-Schmidt columns, norm partials and 1/h
+  DevBuf kHc, kGiv, kRes;  // device Arnoldi: Hessenberg columns; the two Gram-Schmidt columns and 1/h;
+                           // norm partials
   int krylov_cap = 0;
   // stage profiler: pairs of events recorded around launches while enabled
   bool prof_on = false;
@@ -891,62 +891,10 @@ void ensure_krylov(sc_plan* P, int restart) {
   P->kPart.alloc((size_t)(restart + 1) * std::max<long long>(kDotChunks, dots_chunks(n)) * sizeof(double));
   P->kH.alloc((size_t)(restart + 1) * sizeof(double));
   P->kHc.alloc((size_t)(restart + 1) * restart * sizeof(double));
-  P->kGiv.alloc((size_t)(6 * (restart + 1) + kDotChunks + 1) * sizeof(double));
-  P->kRes.alloc((size_t)restart * sizeof(double));
+  P->kGiv.alloc((size_t)(3 * (restart + 1)) * sizeof(double));
+  P->kRes.alloc((size_t)std::max<long long>(kDotChunks, dots_chunks(n)) * sizeof(double));
   P->krylov_cap = restart;
   ++P->graph_epoch;
-}
-
-// Device Arnoldi workspace views (capacity krylov_cap).
-struct ArnoldiWs {
-  double *Hc, *cs, *sn, *g, *h1, *h2, *pn, *hinv, *res;
-  int ld;
-};
-ArnoldiWs arnoldi_ws(sc_plan* P) {
-  const int R = P->krylov_cap;
-  double* b = P->kGiv.as<double>();
-  ArnoldiWs a;
-  a.ld = R + 1;
-  a.Hc = P->kHc.as<double>();
-  a.cs = b;
-  a.sn = b + (R + 1);
-  a.g = b + 2 * (R + 1);
-  a.h1 = b + 3 * (R + 1);
-  a.h2 = b + 4 * (R + 1);
-  a.hinv = b + 5 * (R + 1);
-  a.pn = b + 6 * (R + 1);
-  a.res = P->kRes.as<double>();
-  return a;
-}
-
-constexpr int kArnoldiChunk = 8;   // Arnoldi steps enqueued between two host checks
-
-// One Arnoldi step j on the device, no host synchronization: w = J V_j, classical Gram-Schmidt
-// twice against V_0..V_j, h_{j+1,j} = ||w||, Givens update of column j, V_{j+1} = w / h_{j+1,j}.
-void arnoldi_step(sc_plan* P, int j, int prec, hipStream_t s) {
-  const long long n = P->n_real;
-  double* V = P->kV.as<double>();
-  double* w = P->kW.as<double>();
-  double* part = P->kPart.as<double>();
-  const ArnoldiWs a = arnoldi_ws(P);
-  jvp_impl(P, 1, V + (long long)j * n, n, w, n, prec, s);
-  const int nch = (int)dots_chunks(n);
-  for (int pass = 0; pass < 2; ++pass) {
-    double* h = pass == 0 ? a.h1 : a.h2;
-    hipLaunchKernelGGL(sc::k_dots_multi, dim3(nch), dim3(256), 0, s, (const double*)V, n, j + 1, (const double*)w, n,
-                       nch, part);
-    hipLaunchKernelGGL(sc::k_dots_reduce, dim3(nblk(j + 1, 256)), dim3(256), 0, s, (const double*)part, j + 1, nch,
-                       h);
-    hipLaunchKernelGGL(sc::k_combine, dim3(nblk(n, 256)), dim3(256), 0, s, w, 1.0, (const double*)V, n, j + 1,
-                       (const double*)h, n);
-  }
-  hipLaunchKernelGGL(sc::k_dots_partial, dim3(kDotChunks, 1), dim3(256), 0, s, (const double*)w, n, 1,
-                     (const double*)w, n, kDotChunks, a.pn);
-  hipLaunchKernelGGL(sc::k_arnoldi_tail, dim3(1), dim3(64), 0, s, j, a.ld, (const double*)a.h1, (const double*)a.h2,
-                     (const double*)a.pn, kDotChunks, a.Hc, a.cs, a.sn, a.g, a.res, a.hinv);
-  hipLaunchKernelGGL(sc::k_scale_dev, dim3(nblk(n, 256)), dim3(256), 0, s, V + (long long)(j + 1) * n,
-                     (const double*)w, (const double*)a.hinv, n);
-  HIPCHK(hipGetLastError());
 }
 
 // h[i] = <V_i, w> for i < k (device vectors, fixed-order host summation of fixed chunks)
@@ -978,15 +926,71 @@ void combine(sc_plan* P, double* w, double alpha, const double* V, long long ldv
   HIPCHK(hipGetLastError());
 }
 
+// Device Arnoldi workspace views (capacity krylov_cap).
+struct ArnoldiWs {
+  double *Hc, *h1, *h2, *pn, *hinv;
+  int ld;
+};
+ArnoldiWs arnoldi_ws(sc_plan* P) {
+  const int R = P->krylov_cap;
+  double* b = P->kGiv.as<double>();
+  ArnoldiWs a;
+  a.ld = R + 1;
+  a.Hc = P->kHc.as<double>();
+  a.h1 = b;
+  a.h2 = b + (R + 1);
+  a.hinv = b + 2 * (R + 1);
+  a.pn = P->kRes.as<double>();   // norm partials (capacity max(restart, chunks of n))
+  return a;
+}
+
+constexpr int kArnoldiChunk = 8;   // Arnoldi steps enqueued between two host checks
+
+// ||x||^2 partials of x into pn (one pass, dots_chunks(n) workgroups)
+void norm_parts(sc_plan* P, const double* x, double* pn, hipStream_t s) {
+  const long long n = P->n_real;
+  const int nch = (int)dots_chunks(n);
+  hipLaunchKernelGGL(sc::k_dots_multi, dim3(nch, 1), dim3(256), 0, s, x, n, 1, x, n, nch, pn);
+}
+
+// One Arnoldi step j on the device, no host synchronization: w = J V_j, classical Gram-Schmidt
+// twice against V_0..V_j, column j of the Hessenberg matrix with h_{j+1,j} = ||w||, and
+// V_{j+1} = w / h_{j+1,j}.
+void arnoldi_step(sc_plan* P, int j, int prec, hipStream_t s) {
+  const long long n = P->n_real;
+  double* V = P->kV.as<double>();
+  double* w = P->kW.as<double>();
+  double* part = P->kPart.as<double>();
+  const ArnoldiWs a = arnoldi_ws(P);
+  jvp_impl(P, 1, V + (long long)j * n, n, w, n, prec, s);
+  const int nch = (int)dots_chunks(n);
+  for (int pass = 0; pass < 2; ++pass) {
+    double* h = pass == 0 ? a.h1 : a.h2;
+    hipLaunchKernelGGL(sc::k_dots_multi, dim3(nch, (j + 1 + sc::kDotsGroup - 1) / sc::kDotsGroup), dim3(256), 0, s,
+                       (const double*)V, n, j + 1, (const double*)w, n, nch, part);
+    hipLaunchKernelGGL(sc::k_dots_reduce, dim3(nblk(j + 1, 4)), dim3(256), 0, s, (const double*)part, j + 1, nch, h);
+    hipLaunchKernelGGL(sc::k_combine, dim3(nblk(n, 256)), dim3(256), 0, s, w, 1.0, (const double*)V, n, j + 1,
+                       (const double*)h, n);
+  }
+  norm_parts(P, w, a.pn, s);
+  hipLaunchKernelGGL(sc::k_arnoldi_col, dim3(1), dim3(256), 0, s, j, a.ld, (const double*)a.h1, (const double*)a.h2,
+                     (const double*)a.pn, nch, a.Hc, a.hinv);
+  hipLaunchKernelGGL(sc::k_scale_dev, dim3(nblk(n, 256)), dim3(256), 0, s, V + (long long)(j + 1) * n,
+                     (const double*)w, (const double*)a.hinv, n);
+  HIPCHK(hipGetLastError());
+}
+
 // Restarted GMRES for (B_X - I) du = b with the current base; returns the number of jvps.
-// The Arnoldi steps run on the device in chunks of kArnoldiChunk with one host check of the
-// residual estimates per chunk, so up to kArnoldiChunk - 1 steps beyond convergence may be
-// computed (and counted); the solution uses the steps up to the first converged one.
+// The Arnoldi steps run on the device in chunks of kArnoldiChunk; after each chunk the host reads
+// the new Hessenberg columns, applies the Givens rotations and checks the residual estimates, so
+// up to kArnoldiChunk - 1 steps beyond convergence may be computed (and counted); the solution
+// uses the steps up to the first converged one.
 int gmres(sc_plan* P, const double* b, double* du, double rtol, int restart, int maxmv, int prec, hipStream_t s) {
   const long long n = P->n_real;
   double* V = P->kV.as<double>();
   double* w = P->kW.as<double>();
   const ArnoldiWs a = arnoldi_ws(P);
+  const int nch = (int)dots_chunks(n);
   const double bn = norm2(P, b, s);
   hipLaunchKernelGGL(sc::k_scale, dim3(nblk(n, 256)), dim3(256), 0, s, du, b, 0.0, n);
   HIPCHK(hipGetLastError());
@@ -996,16 +1000,16 @@ int gmres(sc_plan* P, const double* b, double* du, double rtol, int restart, int
   HIPCHK(hipGetLastError());
   int mv = 0;
   double beta = bn;
-  std::vector<double> res(restart), Hh, gh(restart + 1);
+  std::vector<double> H((size_t)a.ld * restart), cs(restart), sn(restart), g(restart + 1);
   while (true) {
     if (beta <= rtol * bn || mv >= maxmv) break;
-    hipLaunchKernelGGL(sc::k_dots_partial, dim3(kDotChunks, 1), dim3(256), 0, s, (const double*)V, n, 1,
-                       (const double*)V, n, kDotChunks, a.pn);
-    hipLaunchKernelGGL(sc::k_cycle_init, dim3(1), dim3(64), 0, s, a.ld, (const double*)a.pn, kDotChunks, a.g,
-                       a.hinv);
+    norm_parts(P, V, a.pn, s);
+    hipLaunchKernelGGL(sc::k_inv_norm, dim3(1), dim3(64), 0, s, (const double*)a.pn, nch, a.hinv);
     hipLaunchKernelGGL(sc::k_scale_dev, dim3(nblk(n, 256)), dim3(256), 0, s, V, (const double*)V,
                        (const double*)a.hinv, n);
     HIPCHK(hipGetLastError());
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
     int j = 0, jend = 0;
     bool done = false;
     while (j < restart && !done) {
@@ -1014,24 +1018,33 @@ int gmres(sc_plan* P, const double* b, double* du, double rtol, int restart, int
         done = true;
         break;
       }
-      if (P->prm.graph_capture && !P->prof_on) {
-        const hipGraphExec_t ex = plan_graph(P, {1, j, cnt, prec}, [&](hipStream_t cs) {
-          for (int q = 0; q < cnt; ++q) arnoldi_step(P, j + q, prec, cs);
-        });
-        launch_graph(ex, P->cap, P->ev_gin, P->ev_gout, s);
-      } else {
-        for (int q = 0; q < cnt; ++q) arnoldi_step(P, j + q, prec, s);
-      }
+      for (int q = 0; q < cnt; ++q) arnoldi_step(P, j + q, prec, s);
       mv += cnt;
-      HIPCHK(hipMemcpyAsync(res.data() + j, a.res + j, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(H.data() + (size_t)j * a.ld, a.Hc + (size_t)j * a.ld, (size_t)cnt * a.ld * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      for (int q = 0; q < cnt; ++q)
-        if (!std::isfinite(res[j + q])) throw Fail{SC_ERR_NONFINITE, "GMRES residual estimate is not finite"};
-      for (int q = 0; q < cnt && !done; ++q)
-        if (res[j + q] <= rtol * bn) {
-          jend = j + q + 1;
+      for (int q = 0; q < cnt && !done; ++q) {
+        const int jj = j + q;
+        double* col = H.data() + (size_t)jj * a.ld;
+        const double hn = col[jj + 1];
+        if (!std::isfinite(hn)) throw Fail{SC_ERR_NONFINITE, "GMRES: non-finite Hessenberg entry"};
+        for (int i = 0; i < jj; ++i) {
+          const double x0 = col[i], x1 = col[i + 1];
+          col[i] = cs[i] * x0 + sn[i] * x1;
+          col[i + 1] = -sn[i] * x0 + cs[i] * x1;
+        }
+        const double x0 = col[jj], den = std::hypot(x0, hn);
+        cs[jj] = den > 0 ? x0 / den : 1.0;
+        sn[jj] = den > 0 ? hn / den : 0.0;
+        col[jj] = den;
+        col[jj + 1] = 0.0;
+        g[jj + 1] = -sn[jj] * g[jj];
+        g[jj] = cs[jj] * g[jj];
+        if (std::fabs(g[jj + 1]) <= rtol * bn || hn == 0.0) {
+          jend = jj + 1;
           done = true;
         }
+      }
       if (!done) {
         j += cnt;
         jend = j;
@@ -1039,17 +1052,12 @@ int gmres(sc_plan* P, const double* b, double* du, double rtol, int restart, int
       }
     }
     if (jend == 0) break;
-    // y = R^{-1} g from the first jend columns (host), du -= V y
-    // columns have the workspace's leading dimension a.ld (the capacity may exceed restart)
-    Hh.resize((size_t)jend * a.ld);
-    HIPCHK(hipMemcpyAsync(Hh.data(), a.Hc, Hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(gh.data(), a.g, jend * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    // y = R^{-1} g from the first jend rotated columns, du -= V y
     std::vector<double> y(jend, 0.0);
     for (int i = jend - 1; i >= 0; --i) {
-      double acc = gh[i];
-      for (int q = i + 1; q < jend; ++q) acc -= Hh[(size_t)q * a.ld + i] * y[q];
-      y[i] = acc / Hh[(size_t)i * a.ld + i];
+      double acc = g[i];
+      for (int q = i + 1; q < jend; ++q) acc -= H[(size_t)q * a.ld + i] * y[q];
+      y[i] = acc / H[(size_t)i * a.ld + i];
     }
     for (auto& v : y) v = -v;
     combine(P, du, 1.0, V, n, jend, y, s);

@@ -2402,91 +2402,94 @@ __global__ void k_interp(InterpMap im, const double* __restrict__ x, double* __r
 }
 
 // Device-side Arnoldi (restarted GMRES without a host round trip per step).
-// out[i] = sum over c of part[i * nchunk + c], i < k, in a fixed order.
-__global__ void k_dots_reduce(const double* __restrict__ part, int k, int nchunk, double* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= k) return;
-  double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[(long long)i * nchunk + c];
-  out[i] = s;
+// out[i] = sum over c of part[i * nchunk + c], i < k: one wavefront per i, lane l adds the
+// entries c = l, l + 64, ... in order, then a fixed shuffle tree (reproducible results).
+__device__ inline double wave_sum_fixed(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
 }
 
-// Dot products of w with every V_i, i < k, in one pass: workgroup b owns the elements
-// [b len, (b + 1) len) of w (len = 4 * 256, kept in registers) and reads each V_i once;
-// part[i * nchunk + b] is its partial sum (summed in a fixed order by k_dots_reduce).
+__global__ void __launch_bounds__(256) k_dots_reduce(const double* __restrict__ part, int k, int nchunk,
+                                                     double* __restrict__ out) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= k) return;
+  double s = 0.0;
+  for (int c = lane; c < nchunk; c += 64) s += part[(long long)i * nchunk + c];
+  s = wave_sum_fixed(s);
+  if (lane == 0) out[i] = s;
+}
+
+// Column j of the Hessenberg matrix (Hc: column-major, leading dimension ld) from the two
+// Gram-Schmidt passes, h_{j+1,j} = ||w|| from its chunk partials pn, and hinv = 1/h_{j+1,j}
+// (0 at a breakdown).  The Givens rotations are applied on the host, once per chunk of steps.
+__global__ void __launch_bounds__(256) k_arnoldi_col(int j, int ld, const double* __restrict__ h1,
+                                                     const double* __restrict__ h2, const double* __restrict__ pn,
+                                                     int nchunk, double* __restrict__ Hc, double* __restrict__ hinv) {
+  double* col = Hc + (long long)j * ld;
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = h1[i] + h2[i];
+  if (threadIdx.x < 64) {
+    double ss = 0.0;
+    for (int c = threadIdx.x; c < nchunk; c += 64) ss += pn[c];
+    ss = wave_sum_fixed(ss);
+    if (threadIdx.x == 0) {
+      const double hn = sqrt(ss);
+      col[j + 1] = hn;
+      hinv[0] = hn > 0.0 ? 1.0 / hn : 0.0;
+    }
+  }
+}
+
+// 1 / ||r|| from its chunk partials (0 if r = 0), one wavefront.
+__global__ void k_inv_norm(const double* __restrict__ pn, int nchunk, double* __restrict__ hinv) {
+  double ss = 0.0;
+  for (int c = threadIdx.x; c < nchunk; c += 64) ss += pn[c];
+  ss = wave_sum_fixed(ss);
+  if (threadIdx.x == 0) hinv[0] = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+}
+
+// Dot products of w with V_i, i < k: workgroup (b, c) owns the elements [b len, (b + 1) len) of
+// w (len = 4 * 256, in registers) and the vectors i = 8 c .. 8 c + 7, all of whose loads are
+// issued together; part[i * nchunk + b] is its partial sum (summed in a fixed order by
+// k_dots_reduce).
 constexpr int kDotsPerThread = 4;
-constexpr int kDotsMaxK = 1025;
+constexpr int kDotsGroup = 8;
 __global__ void __launch_bounds__(256) k_dots_multi(const double* __restrict__ V, long long ldv, int k,
                                                     const double* __restrict__ w, long long n, int nchunk,
                                                     double* __restrict__ part) {
-  __shared__ double red[4][kDotsMaxK];
+  __shared__ double red[4][kDotsGroup];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const long long base = (long long)blockIdx.x * (256 * kDotsPerThread);
-  double wr[kDotsPerThread];
+  const int i0 = blockIdx.y * kDotsGroup;
+  double wr[kDotsPerThread], s[kDotsGroup];
   long long idx[kDotsPerThread];
 #pragma unroll
   for (int q = 0; q < kDotsPerThread; ++q) {
     idx[q] = base + tid + 256LL * q;
     wr[q] = idx[q] < n ? w[idx[q]] : 0.0;
   }
-  for (int i = 0; i < k; ++i) {
+#pragma unroll
+  for (int g = 0; g < kDotsGroup; ++g) {
+    const int i = min(i0 + g, k - 1);   // rows beyond k repeat the last one and are not stored
     const double* v = V + (long long)i * ldv;
-    double s = 0.0;
+    double a = 0.0;
 #pragma unroll
     for (int q = 0; q < kDotsPerThread; ++q)
-      if (idx[q] < n) s += v[idx[q]] * wr[q];
+      if (idx[q] < n) a += v[idx[q]] * wr[q];
+    s[g] = a;
+  }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) red[wave][i] = s;
+  for (int g = 0; g < kDotsGroup; ++g) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s[g] += __shfl_xor(s[g], off);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int g = 0; g < kDotsGroup; ++g) red[wave][g] = s[g];
   }
   __syncthreads();
-  for (int i = tid; i < k; i += blockDim.x)
-    part[(long long)i * nchunk + blockIdx.x] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
-}
-
-// Step j's tail, one thread: column j of the Hessenberg matrix (Hc, column-major with leading
-// dimension ld = restart + 1) from the two Gram-Schmidt passes, h_{j+1,j} = ||w|| from its chunk
-// partials, the previous Givens rotations applied to the column, rotation j, the rotated
-// right-hand side g, the residual estimate res[j] = |g_{j+1}| and hinv = 1/h_{j+1,j} (0 at a
-// breakdown).
-__global__ void k_arnoldi_tail(int j, int ld, const double* __restrict__ h1, const double* __restrict__ h2,
-                               const double* __restrict__ pn, int nchunk, double* __restrict__ Hc,
-                               double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
-                               double* __restrict__ res, double* __restrict__ hinv) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  double* col = Hc + (long long)j * ld;
-  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-  double ss = 0.0;
-  for (int c = 0; c < nchunk; ++c) ss += pn[c];
-  const double hn = sqrt(ss);
-  hinv[0] = hn > 0.0 ? 1.0 / hn : 0.0;
-  for (int i = 0; i < j; ++i) {
-    const double a = col[i], b = col[i + 1];
-    col[i] = cs[i] * a + sn[i] * b;
-    col[i + 1] = -sn[i] * a + cs[i] * b;
-  }
-  const double a = col[j];
-  const double den = hypot(a, hn);
-  cs[j] = den > 0.0 ? a / den : 1.0;
-  sn[j] = den > 0.0 ? hn / den : 0.0;
-  col[j] = den;
-  col[j + 1] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  res[j] = fabs(g[j + 1]);
-}
-
-// Start of a GMRES cycle, one thread: beta = ||r|| from its chunk partials, g = beta e_1,
-// hinv = 1/beta.
-__global__ void k_cycle_init(int ld, const double* __restrict__ pn, int nchunk, double* __restrict__ g,
-                             double* __restrict__ hinv) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  double ss = 0.0;
-  for (int c = 0; c < nchunk; ++c) ss += pn[c];
-  const double beta = sqrt(ss);
-  g[0] = beta;
-  for (int i = 1; i < ld; ++i) g[i] = 0.0;
-  hinv[0] = beta > 0.0 ? 1.0 / beta : 0.0;
+  if (tid < kDotsGroup && i0 + tid < k)
+    part[(long long)(i0 + tid) * nchunk + blockIdx.x] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
 }
 
 // x[0] = v (a device scalar written in stream order)
