@@ -281,7 +281,8 @@ def run(args):
         "stages_fp64": {k: {"ms_per_step": v[0] / max(args.steps, 1)} for k, v in fp64["prof"].items() if v[1]},
     }
     log("single-vector rates")
-    out["nvec1_jvp_per_s"] = single_vector_rates(args, plan, batch, sc)
+    if not args.no_single_vector:
+        out["nvec1_jvp_per_s"] = single_vector_rates(args, plan, batch, sc)
     if args.batch_scaling and args.workload == "c3":
         log("larger batches")
         out["batch_scaling_jvp_per_s"] = batch_scaling(args, W, Xd, C, J, V, sc)
@@ -630,6 +631,134 @@ def c4_batch(args):
     return res
 
 
+def _csv_rows(d, suffix):
+    """Rows of every rocprofv3 CSV under directory d whose name ends with suffix."""
+    import csv
+    rows = []
+    for root, _, files in os.walk(d):
+        for f in sorted(files):
+            if f.endswith(suffix):
+                with open(os.path.join(root, f), newline="") as fh:
+                    rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _kname(s):
+    """Kernel name without the return type and the argument list."""
+    s = s.strip()
+    if s.startswith("void "):
+        s = s[5:]
+    depth = 0
+    for i, ch in enumerate(s):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return s[:i]
+    return s
+
+
+def _counters(d):
+    """{kernel: {"launches": n, counter: mean per dispatch, "vgpr", "lds"}} from counter CSVs."""
+    per = {}
+    for r in _csv_rows(d, "counter_collection.csv"):
+        k, c = _kname(r["Kernel_Name"]), r["Counter_Name"]
+        disp = per.setdefault(k, {})
+        e = disp.setdefault(r["Dispatch_Id"], {"vgpr": r.get("VGPR_Count"), "agpr": r.get("Accum_VGPR_Count"),
+                                                "lds": r.get("LDS_Block_Size"), "wg": r.get("Workgroup_Size")})
+        e[c] = e.get(c, 0.0) + float(r["Counter_Value"])
+    out = {}
+    for k, disp in per.items():
+        names = {c for e in disp.values() for c in e if c not in ("vgpr", "agpr", "lds", "wg")}
+        first = next(iter(disp.values()))
+        out[k] = {"launches": len(disp), "vgpr": first["vgpr"], "agpr": first["agpr"], "lds": first["lds"],
+                  "wg": first["wg"]}
+        for c in names:
+            out[k][c] = sum(e.get(c, 0.0) for e in disp.values()) / len(disp)
+    return out
+
+
+def summarize_profiles(d):
+    """Turns the rocprofv3 runs under d (stats/, fetch/, write/, probe_fetch/, probe_write/,
+    sq_mfma/, sq_lds/, any of them may be missing) into the committed traffic file and prints
+    Markdown tables.  FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled by the
+    ratio of the bytes a plain copy moves to what the same counter reads for it."""
+    md = []
+    stats = {}
+    for r in _csv_rows(os.path.join(d, "stats"), "kernel_stats.csv"):
+        stats[_kname(r["Name"])] = {"calls": int(r["Calls"]), "total_us": float(r["TotalDurationNs"]) / 1e3,
+                            "avg_us": float(r["AverageNs"]) / 1e3, "pct": float(r["Percentage"])}
+    if stats:
+        md += ["kernel | calls | total us | avg us | % of GPU time", "---|---|---|---|---"]
+        for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["total_us"]):
+            md.append(f"{k} | {v['calls']} | {v['total_us']:.1f} | {v['avg_us']:.1f} | {v['pct']:.2f}")
+        md.append("")
+    fetch, write = _counters(os.path.join(d, "fetch")), _counters(os.path.join(d, "write"))
+    pf, pw = _counters(os.path.join(d, "probe_fetch")), _counters(os.path.join(d, "probe_write"))
+    if fetch and write and pf and pw:
+        probe = lambda t, c: next(v[c] for k, v in t.items() if "Mul" in k)
+        nbytes = 256 * (1 << 20)
+        kib = {"FETCH_SIZE": probe(pf, "FETCH_SIZE"), "WRITE_SIZE": probe(pw, "WRITE_SIZE")}
+        scale = {c: nbytes / (kib[c] * 1024.0) for c in kib}
+        ker = {}
+        for k in set(fetch) & set(write):
+            fb = fetch[k]["FETCH_SIZE"] * 1024.0 * scale["FETCH_SIZE"]
+            wb = write[k]["WRITE_SIZE"] * 1024.0 * scale["WRITE_SIZE"]
+            ker[k] = {"launches": fetch[k]["launches"], "fetch_bytes": fb, "write_bytes": wb, "bytes": fb + wb}
+        traffic = {"copy_probe_kib_per_launch": kib, "scale": scale, "kernels": ker,
+                   "sources_sha256": sources_sha256()}
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(traffic, fh, indent=1, sort_keys=True)
+        md += [f"Calibration: the plain copy (256 MiB read, 256 MiB written) reads FETCH_SIZE = "
+               f"{kib['FETCH_SIZE']:.0f} KiB and WRITE_SIZE = {kib['WRITE_SIZE']:.0f} KiB per launch: scale "
+               f"{scale['FETCH_SIZE']:.3f} and {scale['WRITE_SIZE']:.3f}.", "",
+               "kernel | launches | read MB/launch | written MB/launch | total MB/launch", "---|---|---|---|---"]
+        for k, v in sorted(ker.items(), key=lambda kv: -kv[1]["bytes"]):
+            md.append(f"{k} | {v['launches']} | {v['fetch_bytes'] / 1e6:.1f} | {v['write_bytes'] / 1e6:.1f} | "
+                      f"{v['bytes'] / 1e6:.1f}")
+        md.append("")
+    mf = _counters(os.path.join(d, "sq_mfma"))
+    if mf:
+        # SQ_BUSY_CYCLES sums the cycles of the 32 shader engines (4 per XCD), the MFMA busy
+        # cycles those of the 1024 SIMDs
+        md += ["kernel | launches | MFMA FLOP/launch | MFMA TFLOP/s (trace avg) | of peak | MFMA busy per SIMD-cycle | "
+               "VALU insts/wave | waves/launch",
+               "---|---|---|---|---|---|---|---"]
+        for k, v in sorted(mf.items(), key=lambda kv: -stats.get(kv[0], {}).get("total_us", 0.0)):
+            if not k.startswith("sc::"):
+                continue
+            f32 = v.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) * 512
+            f64 = v.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512
+            fl, peak = (f64, PEAK["fp64"]) if f64 > f32 else (f32, PEAK["fp32"])
+            avg = stats.get(k, {}).get("avg_us")
+            rate = fl / (avg * 1e-6) / 1e12 if avg and fl else 0.0
+            busy = v.get("SQ_BUSY_CYCLES", 0.0)
+            mb = v.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (busy / 32.0 * 1024.0) if busy else 0.0
+            waves = v.get("SQ_WAVES", 0.0)
+            vi = v.get("SQ_INSTS_VALU", 0.0) / waves if waves else 0.0
+            md.append(f"{k} | {v['launches']} | {fl:.3e} | {rate:.1f} | {rate / peak:.3f} | {mb:.3f} | {vi:.0f} | "
+                      f"{waves:.0f}")
+        md.append("")
+    ld = _counters(os.path.join(d, "sq_lds"))
+    if ld:
+        md += ["kernel | LDS insts/wave | bank-conflict cycles / LDS active cycles | LDS wait / LDS active | "
+               "VMEM rd insts/wave",
+               "---|---|---|---|---"]
+        for k, v in sorted(ld.items(), key=lambda kv: -stats.get(kv[0], {}).get("total_us", 0.0)):
+            if not k.startswith("sc::"):
+                continue
+            waves = v.get("SQ_WAVES", 0.0) or 1.0
+            act = v.get("SQ_LDS_IDX_ACTIVE", 0.0)
+            bc = v.get("SQ_LDS_BANK_CONFLICT", 0.0) / act if act else 0.0
+            aw = v.get("SQ_ACTIVE_INST_LDS", 0.0)
+            wt = v.get("SQ_WAIT_INST_LDS", 0.0) / aw if aw else 0.0
+            md.append(f"{k} | {v.get('SQ_INSTS_LDS', 0.0) / waves:.0f} | {bc:.3f} | {wt:.2f} | "
+                      f"{v.get('SQ_INSTS_VMEM_RD', 0.0) / waves:.0f}")
+        md.append("")
+    print("\n".join(md), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -657,13 +786,20 @@ def main():
                          "sector vs full domain (prints its own JSON line instead of the benchmark)")
     ap.add_argument("--study-max-matvec", type=int, default=8000)
     ap.add_argument("--study-explicit-min-ek", type=float, default=1.1e-4)
+    ap.add_argument("--no-single-vector", action="store_true", help="skip the one-vector-per-call rates")
     ap.add_argument("--no-c4", action="store_true", help="skip the 32-problem batched Newton leg")
     ap.add_argument("--batch-scaling", type=int, default=1, help="also time 32 and 64 vectors per call (0: skip)")
     ap.add_argument("--c4-restart", type=int, default=1000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy (y = 1.0 * x, fp32) of MIB MiB five times: the reference "
                          "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
+                    help="only summarize the rocprofv3 runs under DIR (stats/, fetch/, write/, probe_fetch/, "
+                         "probe_write/, sq_mfma/, sq_lds/): rewrite the traffic file, print Markdown tables")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     if args.copy_probe:
         import torch
         n = args.copy_probe * (1 << 20) // 4

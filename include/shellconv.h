@@ -204,6 +204,16 @@ typedef struct {
 } sc_tune_report;
 int sc_autotune(sc_plan* plan, int nvec, int reps, sc_tune_report* report, void* stream);
 
+/* Kernel choices of a plan, set by hand (as sc_autotune sets them): ring_fp32 / ring_fp64 = -1
+ * for the register-transform ring kernel (where sc_autotune lists it as a candidate), k >= 0 for
+ * the LDS ring kernel with 2^k rings per workgroup up to the LDS limit; anal_folded = 1 for the
+ * folded analysis kernel (where N_theta <= 256), 0 for the batched GEMM.  Every choice computes
+ * the same sums (Sec. 3.2, the transforms of the explicit forces); the choice only changes the
+ * time.  Errors: SC_ERR_ARG (null plan, a choice this grid does not have; the plan is then
+ * unchanged).  sc_get_kernels writes the choices in effect (any pointer may be NULL). */
+int sc_set_kernels(sc_plan* plan, int ring_fp32, int ring_fp64, int anal_folded);
+int sc_get_kernels(const sc_plan* plan, int* ring_fp32, int* ring_fp64, int* anal_folded);
+
 /* Ragged batches of problems (plans of different L, M, m0, N, Ek, Ra, ...) on one device, e.g.
  * the points of a continuation in (Ra, Ek) (Sec. 4).  sc_batch_jvp applies the Jacobian of every
  * plan to its own vectors, each plan on a stream branch of its own forked from `stream` and

@@ -107,6 +107,8 @@ def load_library(path: str = LIB_PATH):
         "sc_profile": [vp, i],
         "sc_profile_read": [vp, ctypes.POINTER(d), ctypes.POINTER(ll), i],
         "sc_autotune": [vp, i, i, ctypes.POINTER(_TuneReport), vp],
+        "sc_set_kernels": [vp, i, i, i],
+        "sc_get_kernels": [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)],
         "sc_batch_create": [ctypes.POINTER(vp), ctypes.POINTER(vp), i],
         "sc_batch_destroy": [vp],
         "sc_batch_jvp": [vp, ctypes.POINTER(i), ctypes.POINTER(vp), ctypes.POINTER(vp), i, vp],
@@ -139,7 +141,8 @@ def exported_symbols():
             "sc_newton_residual", "sc_set_base", "sc_jvp", "sc_newton", "sc_profile", "sc_profile_read",
             "sc_last_error", "sc_batch_create", "sc_batch_destroy", "sc_batch_jvp", "sc_autotune",
             "sc_batch_newton", "sc_newton_residual_noalloc", "sc_interpolate", "sc_tail_ratios",
-            "sc_cont_create", "sc_cont_step", "sc_cont_layout", "sc_cont_state", "sc_cont_destroy"]
+            "sc_cont_create", "sc_cont_step", "sc_cont_layout", "sc_cont_state", "sc_cont_destroy",
+            "sc_set_kernels", "sc_get_kernels"]
 
 
 def _check(rc):
@@ -257,6 +260,17 @@ class Plan:
         return {"ring_fp32": r.ring_fp32, "ring_fp64": r.ring_fp64, "anal_folded": r.anal_folded,
                 "candidates": r.ncand, "ms_fp32": r.ms_fp32, "ms_fp64": r.ms_fp64,
                 "linear_mode": bool(r.linear_mode)}
+
+    def set_kernels(self, ring_fp32, ring_fp64, anal_folded):
+        """Sets the kernel choices by hand (sc_set_kernels): ring -1 register kernel, k >= 0 LDS
+        kernel with 2^k rings; anal_folded 1 or 0."""
+        _check(_lib.sc_set_kernels(self._h, int(ring_fp32), int(ring_fp64), int(anal_folded)))
+
+    def kernels(self):
+        """The kernel choices in effect (sc_get_kernels)."""
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(_lib.sc_get_kernels(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"ring_fp32": a.value, "ring_fp64": b.value, "anal_folded": c.value}
 
     def newton(self, x, C=0.0, J=-1, tol=1e-10, gmres_tol=1e-10, restart=40, max_newton=20, max_matvec=400,
                prec=SC_FP64, forcing=None, stream=None):

@@ -1704,6 +1704,38 @@ int sc_autotune(sc_plan* P, int nvec, int reps, sc_tune_report* rep, void* strea
   });
 }
 
+int sc_set_kernels(sc_plan* P, int ring_fp32, int ring_fp64, int anal_folded) {
+  return guarded([&] {
+    check_plan(P);
+    const sc::HostGrid& g = P->hg;
+    auto ok = [&](int c, int lim) { return c == -1 ? ring_reg_available(g.nphi, g.K) : (c >= 0 && c <= lim); };
+    if (!ok(ring_fp32, ring_rt_log2<float>(g)) || !ok(ring_fp64, ring_rt_log2<double>(g)))
+      throw Fail{SC_ERR_ARG, "ring kernel choice not available on this grid"};
+    if ((anal_folded != 0 && anal_folded != 1) || (anal_folded == 1 && P->ana_ct_fold == 0))
+      throw Fail{SC_ERR_ARG, "analysis kernel choice not available on this grid"};
+    P->ring_reg32 = ring_fp32 < 0;
+    P->ring_rtl32 = ring_fp32;
+    P->ring_reg64 = ring_fp64 < 0;
+    P->ring_rtl64 = ring_fp64;
+    P->ana_ct = anal_folded ? P->ana_ct_fold : 0;
+    ++P->graph_epoch;
+  });
+}
+
+int sc_get_kernels(const sc_plan* P, int* ring_fp32, int* ring_fp64, int* anal_folded) {
+  return guarded([&] {
+    if (!P) throw Fail{SC_ERR_ARG, "null plan"};
+    const sc::HostGrid& g = P->hg;
+    auto cur = [&](bool reg, int rtl, int lim) {
+      if (reg && ring_reg_available(g.nphi, g.K)) return -1;
+      return rtl >= 0 ? std::min(rtl, lim) : lim;
+    };
+    if (ring_fp32) *ring_fp32 = cur(P->ring_reg32, P->ring_rtl32, ring_rt_log2<float>(g));
+    if (ring_fp64) *ring_fp64 = cur(P->ring_reg64, P->ring_rtl64, ring_rt_log2<double>(g));
+    if (anal_folded) *anal_folded = P->ana_ct > 0 ? 1 : 0;
+  });
+}
+
 int sc_jvp(sc_plan* P, int nvec, const double* v, long long ldv, double* y, long long ldy, sc_precision prec,
            void* stream) {
   return guarded([&] {

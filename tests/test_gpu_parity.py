@@ -118,6 +118,57 @@ def test_autotune_then_jvp(lib, cfg):
     assert ei.value.code == 1
 
 
+@pytest.mark.parametrize("cfg", SMALL)
+def test_every_kernel_candidate_matches_the_oracle(lib, cfg):
+    """Each ring kernel (the register-transform kernel where the grid has one, the LDS kernel at
+    every 2^k rings per workgroup) in both precisions, with each analysis kernel, forced with
+    sc_set_kernels: every Jacobian action of a batch of 6 vectors matches the oracle; unavailable
+    choices are refused."""
+    plan, ora, lay = _setup(lib, cfg, nvec=6)
+    X = si.random_state(lay, 101, amp=(1e-2, 1e-2, 1e-2), p=2) + ora.conductive_state()
+    J = si.default_phase_slot(lay, X)
+    plan.set_base(_dev(X), 0.3, J)
+    ora.set_base(X, 0.3, J)
+    V = si.random_vectors(lay, [1001, 1002, 1003, 1004, 1005, 1006])
+    vd = _dev(V)
+    refs = [ora.jvp(V[i]) for i in range(len(V))]
+    default = plan.kernels()
+    d32, d64, df = default["ring_fp32"], default["ring_fp64"], default["anal_folded"]
+
+    def available(args):
+        before = plan.kernels()
+        try:
+            plan.set_kernels(*args)
+            return True
+        except lib.ShellConvError as e:
+            assert e.code == 1 and plan.kernels() == before      # a refused choice changes nothing
+            return False
+
+    c32 = [c for c in range(-2, 6) if available((c, d64, df))]
+    c64 = [c for c in range(-2, 6) if available((d32, c, df))]
+    folds = [f for f in (0, 1) if available((d32, d64, f))]
+    print(f"cfg={cfg} default {default}, ring candidates fp32 {c32} fp64 {c64}, analysis {folds}", flush=True)
+    assert 0 in c32 and 0 in c64 and len(c32) >= 3 and len(c64) >= 2 and 0 in folds
+    ran = 0
+    for f in folds:
+        for prec, cands, tol, btol in ((1, c32, 1e-6, 1e-5), (0, c64, 1e-12, FP64_BLOCK)):
+            for c in cands:
+                args = (c, d64, f) if prec == 1 else (d32, c, f)
+                plan.set_kernels(*args)
+                assert plan.kernels() == dict(zip(("ring_fp32", "ring_fp64", "anal_folded"), args))
+                yd = torch.empty_like(vd)
+                plan.jvp(vd, yd, prec)
+                Y = _host(yd)
+                for i in range(len(V)):
+                    check(lay, Y[i], refs[i], tol, btol, f"cfg={cfg} kernels={args} prec={prec} vec {i}")
+                ran += 1
+    print(f"cfg={cfg} {ran} forced (kernel, precision) combinations match the oracle", flush=True)
+    with pytest.raises(lib.ShellConvError):
+        plan.set_kernels(99, 0, 0)
+    with pytest.raises(lib.ShellConvError):
+        plan.set_kernels(0, 0, 2)
+
+
 def test_state_errors(lib):
     plan, ora, lay = _setup(lib, SMALL[1])
     v = torch.zeros((1, plan.n_real), dtype=torch.float64, device="cuda")
