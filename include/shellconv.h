@@ -188,13 +188,15 @@ const char* sc_last_error(void);
  * uses the Jacobian action's linearized products (the base fields of sc_set_base read at every
  * point) when a base state is set, else the nonlinear products of the step.  Candidates:
  *   ring kernel, per precision: the register-transform kernel (where N_phi = N1 N2 has one and
- *     N_phi >= 3K + 1) or the LDS kernel with 2^k rings per workgroup, k = 0 .. the LDS limit;
+ *     N_phi >= 3K + 1) in each of its workgroup shapes (FP32: 32, 24 or 16 rings; FP64: 16 or 8;
+ *     eight threads per ring) or the LDS kernel with 2^k rings per workgroup, k = 0 .. the LDS
+ *     limit;
  *   analysis: the folded matrix-core kernel (where N_theta <= 256) or the plain batched GEMM,
  *     timed in FP32 and used by both precisions.
  * Results are unchanged in value (every candidate computes the same sums).  Allocates a
  * scratch vector block (nvec * n_real doubles) for the call.  nvec: 1 .. nvec_max; reps >= 1.
- * report (may be NULL): the choices (ring_fp32/ring_fp64: -1 register kernel, k >= 0 LDS kernel
- * with 2^k rings; anal_folded: 1 or 0), the best times in ms per pass and the number of
+ * report (may be NULL): the choices (ring_fp32/ring_fp64: -1 - v register kernel of shape v,
+ * k >= 0 LDS kernel with 2^k rings; anal_folded: 1 or 0), the best times in ms per pass and the number of
  * candidates timed.  Errors: SC_ERR_ARG (sizes), SC_ERR_STATE (the stage profiler is on).
  * Calls that overlap with other calls on the plan race. */
 typedef struct {
@@ -204,9 +206,11 @@ typedef struct {
 } sc_tune_report;
 int sc_autotune(sc_plan* plan, int nvec, int reps, sc_tune_report* report, void* stream);
 
-/* Kernel choices of a plan, set by hand (as sc_autotune sets them): ring_fp32 / ring_fp64 = -1
- * for the register-transform ring kernel (where sc_autotune lists it as a candidate), k >= 0 for
- * the LDS ring kernel with 2^k rings per workgroup up to the LDS limit; anal_folded = 1 for the
+/* Kernel choices of a plan, set by hand (as sc_autotune sets them): ring_fp32 / ring_fp64 =
+ * -1 - v for the register-transform ring kernel of shape v (where sc_autotune lists it as a
+ * candidate; FP32: v = 0, 1, 2 for 32, 24, 16 rings per workgroup; FP64: v = 0, 1 for 16, 8),
+ * k >= 0 for the LDS ring kernel with 2^k rings per workgroup up to the LDS limit;
+ * anal_folded = 1 for the
  * folded analysis kernel (where N_theta <= 256), 0 for the batched GEMM.  Every choice computes
  * the same sums (Sec. 3.2, the transforms of the explicit forces); the choice only changes the
  * time.  Errors: SC_ERR_ARG (null plan, a choice this grid does not have; the plan is then

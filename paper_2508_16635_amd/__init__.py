@@ -262,8 +262,9 @@ class Plan:
                 "linear_mode": bool(r.linear_mode)}
 
     def set_kernels(self, ring_fp32, ring_fp64, anal_folded):
-        """Sets the kernel choices by hand (sc_set_kernels): ring -1 register kernel, k >= 0 LDS
-        kernel with 2^k rings; anal_folded 1 or 0."""
+        """Sets the kernel choices by hand (sc_set_kernels): ring -1 - v register kernel of shape v
+        (FP32: 32, 24, 16 rings per workgroup; FP64: 16, 8), k >= 0 LDS kernel with 2^k rings;
+        anal_folded 1 or 0."""
         _check(_lib.sc_set_kernels(self._h, int(ring_fp32), int(ring_fp64), int(anal_folded)))
 
     def kernels(self):

@@ -83,6 +83,7 @@ struct sc_plan {
   bool mixed_fp32_solve = false;  // SC_MIXED_SOLVE_FP32
   bool ring_reg32 = true, ring_reg64 = false;  // register-transform ring kernel where N_phi has one
   int ring_rtl32 = -1, ring_rtl64 = -1;         // LDS ring kernel: log2 rings per workgroup (-1: the LDS limit)
+  int ring_rv32 = 0, ring_rv64 = 0;             // register ring kernel: shape variant (rings per workgroup)
   int fft_nr = 0, fft_r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   long long n_real = 0;
   bool factored = false, have_base = false;
@@ -556,26 +557,51 @@ static bool ring_reg_available(int nphi, int K) {
   }
 }
 
-// Register-transform ring kernel for N_phi = N1 N2, if this N_phi has one and N_phi >= 3K + 1.
-// Returns false if not.
+// Arguments of a register-transform ring launch.
+template <class T>
+struct RingRegArgs {
+  hipStream_t s;
+  sc::DevGrid dg;
+  int nvec;
+  const T *Cs, *Cv, *base, *fw;
+  T Ek;
+  T *Fs, *Fv;
+  double* b64;
+  float* b32;
+};
+
+template <class T, int MODE, int N1, int N2, int V>
+void launch_ring_reg_v(const RingRegArgs<T>& a) {
+  constexpr int RR = sc::ring_reg_rings<T>(V);
+  const dim3 grid((unsigned)((long long)a.nvec * a.dg.Np * ((a.dg.nth + RR - 1) / RR)));
+  hipLaunchKernelGGL((sc::k_ring_reg<T, MODE, N1, N2, RR>), grid, dim3(sc::ring_reg_threads(RR)), 0, a.s, a.dg,
+                     a.nvec, a.Cs, a.Cv, a.base, a.fw, a.Ek, a.Fs, a.Fv, a.b64, a.b32);
+}
+
+template <class T, int MODE, int N1, int N2>
+void launch_ring_reg_n(int variant, const RingRegArgs<T>& a) {
+  if (variant == 1) launch_ring_reg_v<T, MODE, N1, N2, 1>(a);
+  else if constexpr (sc::ring_reg_variants<T>() > 2) {
+    if (variant == 2) launch_ring_reg_v<T, MODE, N1, N2, 2>(a);
+    else launch_ring_reg_v<T, MODE, N1, N2, 0>(a);
+  } else {
+    launch_ring_reg_v<T, MODE, N1, N2, 0>(a);
+  }
+}
+
+// Register-transform ring kernel (shape `variant`, see ring_reg_rings) for N_phi = N1 N2, if this
+// N_phi has one and N_phi >= 3K + 1.  Returns false if not.
 template <class T, int MODE>
-bool launch_ring_reg(int nphi, dim3 grid, hipStream_t s, const sc::DevGrid& dg, int nvec, const T* Cs, const T* Cv,
-                     const T* base, const T* fw, T Ek, T* Fs, T* Fv, double* b64, float* b32) {
-  if (!ring_reg_available(nphi, dg.K)) return false;
-#define SC_RING_REG(N1, N2)                                                                                   \
-  hipLaunchKernelGGL((sc::k_ring_reg<T, MODE, N1, N2>), grid, dim3(sc::ring_reg_threads<T>()), 0, s, dg, nvec, Cs, Cv, \
-                     base, fw, Ek, Fs, \
-                     Fv, b64, b32);                                                                           \
-  return true
+bool launch_ring_reg(int nphi, int variant, const RingRegArgs<T>& a) {
+  if (!ring_reg_available(nphi, a.dg.K)) return false;
   switch (nphi) {
-    case 10: SC_RING_REG(2, 5);
-    case 15: SC_RING_REG(3, 5);
-    case 20: SC_RING_REG(4, 5);
-    case 32: SC_RING_REG(8, 4);
-    case 40: SC_RING_REG(8, 5);
+    case 10: launch_ring_reg_n<T, MODE, 2, 5>(variant, a); return true;
+    case 15: launch_ring_reg_n<T, MODE, 3, 5>(variant, a); return true;
+    case 20: launch_ring_reg_n<T, MODE, 4, 5>(variant, a); return true;
+    case 32: launch_ring_reg_n<T, MODE, 8, 4>(variant, a); return true;
+    case 40: launch_ring_reg_n<T, MODE, 8, 5>(variant, a); return true;
     default: return false;
   }
-#undef SC_RING_REG
 }
 
 // Spectral state -> analysed forces (As, Av) in precision T.  mode: linear/nonlinear/synth.
@@ -614,21 +640,21 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
   const T* fw = tab + P->tl.fw;
   T Ek = (T)P->prm.Ek;
   const bool use_reg = std::is_same<T, float>::value ? P->ring_reg32 : P->ring_reg64;
-  const int RRg = sc::ring_reg_rings<T>();
-  const dim3 grid_reg((unsigned)((long long)nvec * g.Np * ((g.nth + RRg - 1) / RRg)));
+  const int rvar = std::is_same<T, float>::value ? P->ring_rv32 : P->ring_rv64;
   {
     Prof _p(P, SC_STAGE_RING, s);
     bool done = false;
     if (use_reg) {
-      if (mode == sc::RING_LINEAR)
-        done = launch_ring_reg<T, sc::RING_LINEAR>(g.nphi, grid_reg, s, dg, nvec, ws + w.Cs, ws + w.Cv, base, fw, Ek,
-                                                    ws + w.Fs, ws + w.Fv, (double*)nullptr, (float*)nullptr);
-      else if (mode == sc::RING_NONLINEAR)
-        done = launch_ring_reg<T, sc::RING_NONLINEAR>(g.nphi, grid_reg, s, dg, nvec, ws + w.Cs, ws + w.Cv, base, fw, Ek,
-                                                       ws + w.Fs, ws + w.Fv, (double*)nullptr, (float*)nullptr);
-      else
-        done = launch_ring_reg<T, sc::RING_SYNTH>(g.nphi, grid_reg, s, dg, nvec, ws + w.Cs, ws + w.Cv, base, fw, Ek,
-                                                   ws + w.Fs, ws + w.Fv, P->base64.as<double>(), P->base32.as<float>());
+      RingRegArgs<T> a = {s, dg, nvec, ws + w.Cs, ws + w.Cv, base, fw, Ek, ws + w.Fs, ws + w.Fv, nullptr, nullptr};
+      if (mode == sc::RING_LINEAR) {
+        done = launch_ring_reg<T, sc::RING_LINEAR>(g.nphi, rvar, a);
+      } else if (mode == sc::RING_NONLINEAR) {
+        done = launch_ring_reg<T, sc::RING_NONLINEAR>(g.nphi, rvar, a);
+      } else {
+        a.b64 = P->base64.as<double>();
+        a.b32 = P->base32.as<float>();
+        done = launch_ring_reg<T, sc::RING_SYNTH>(g.nphi, rvar, a);
+      }
     }
     if (done) {
     } else if (mode == sc::RING_LINEAR)
@@ -1605,6 +1631,27 @@ int sc_profile_read(sc_plan* P, double* ms_total, long long* count, int nstages)
   });
 }
 
+}  // extern "C"
+
+// Ring kernel choice c of precision T: -1 - v the register kernel of shape v, k >= 0 the LDS
+// kernel with 2^k rings per workgroup (validated by the callers).
+template <class T>
+static void set_ring_choice(sc_plan* P, int c) {
+  const bool reg = c < 0;
+  const int rv = reg ? -1 - c : 0;
+  if (std::is_same<T, float>::value) {
+    P->ring_reg32 = reg;
+    P->ring_rtl32 = c;
+    P->ring_rv32 = rv;
+  } else {
+    P->ring_reg64 = reg;
+    P->ring_rtl64 = c;
+    P->ring_rv64 = rv;
+  }
+}
+
+extern "C" {
+
 int sc_autotune(sc_plan* P, int nvec, int reps, sc_tune_report* rep, void* stream) {
   return guarded([&] {
     check_plan(P);
@@ -1641,24 +1688,16 @@ int sc_autotune(sc_plan* P, int nvec, int reps, sc_tune_report* rep, void* strea
       ++ncand;
       return (double)ms / reps;
     };
-    // ring candidates: -1 register kernel, k >= 0 LDS kernel with 2^k rings
+    // ring candidates: -1 - v register kernel of shape v, k >= 0 LDS kernel with 2^k rings
     auto ring_cands = [&](auto tag) {
       typedef decltype(tag) T;
       std::vector<int> c;
-      if (ring_reg_available(g.nphi, g.K)) c.push_back(-1);
+      if (ring_reg_available(g.nphi, g.K))
+        for (int v = 0; v < sc::ring_reg_variants<T>(); ++v) c.push_back(-1 - v);
       for (int k = 0; k <= ring_rt_log2<T>(g); ++k) c.push_back(k);
       return c;
     };
-    auto set_ring = [&](auto tag, int c) {
-      typedef decltype(tag) T;
-      if (std::is_same<T, float>::value) {
-        P->ring_reg32 = c < 0;
-        P->ring_rtl32 = c;
-      } else {
-        P->ring_reg64 = c < 0;
-        P->ring_rtl64 = c;
-      }
-    };
+    auto set_ring = [&](auto tag, int c) { set_ring_choice<decltype(tag)>(P, c); };
     auto tune_ring = [&](auto tag, double& best, int& choice) {
       best = 1e300;
       for (int c : ring_cands(tag)) {
@@ -1708,15 +1747,16 @@ int sc_set_kernels(sc_plan* P, int ring_fp32, int ring_fp64, int anal_folded) {
   return guarded([&] {
     check_plan(P);
     const sc::HostGrid& g = P->hg;
-    auto ok = [&](int c, int lim) { return c == -1 ? ring_reg_available(g.nphi, g.K) : (c >= 0 && c <= lim); };
-    if (!ok(ring_fp32, ring_rt_log2<float>(g)) || !ok(ring_fp64, ring_rt_log2<double>(g)))
+    auto ok = [&](int c, int lim, int nvar) {
+      return c < 0 ? (ring_reg_available(g.nphi, g.K) && -1 - c < nvar) : c <= lim;
+    };
+    if (!ok(ring_fp32, ring_rt_log2<float>(g), sc::ring_reg_variants<float>()) ||
+        !ok(ring_fp64, ring_rt_log2<double>(g), sc::ring_reg_variants<double>()))
       throw Fail{SC_ERR_ARG, "ring kernel choice not available on this grid"};
     if ((anal_folded != 0 && anal_folded != 1) || (anal_folded == 1 && P->ana_ct_fold == 0))
       throw Fail{SC_ERR_ARG, "analysis kernel choice not available on this grid"};
-    P->ring_reg32 = ring_fp32 < 0;
-    P->ring_rtl32 = ring_fp32;
-    P->ring_reg64 = ring_fp64 < 0;
-    P->ring_rtl64 = ring_fp64;
+    set_ring_choice<float>(P, ring_fp32);
+    set_ring_choice<double>(P, ring_fp64);
     P->ana_ct = anal_folded ? P->ana_ct_fold : 0;
     ++P->graph_epoch;
   });
@@ -1726,12 +1766,12 @@ int sc_get_kernels(const sc_plan* P, int* ring_fp32, int* ring_fp64, int* anal_f
   return guarded([&] {
     if (!P) throw Fail{SC_ERR_ARG, "null plan"};
     const sc::HostGrid& g = P->hg;
-    auto cur = [&](bool reg, int rtl, int lim) {
-      if (reg && ring_reg_available(g.nphi, g.K)) return -1;
+    auto cur = [&](bool reg, int rv, int rtl, int lim) {
+      if (reg && ring_reg_available(g.nphi, g.K)) return -1 - rv;
       return rtl >= 0 ? std::min(rtl, lim) : lim;
     };
-    if (ring_fp32) *ring_fp32 = cur(P->ring_reg32, P->ring_rtl32, ring_rt_log2<float>(g));
-    if (ring_fp64) *ring_fp64 = cur(P->ring_reg64, P->ring_rtl64, ring_rt_log2<double>(g));
+    if (ring_fp32) *ring_fp32 = cur(P->ring_reg32, P->ring_rv32, P->ring_rtl32, ring_rt_log2<float>(g));
+    if (ring_fp64) *ring_fp64 = cur(P->ring_reg64, P->ring_rv64, P->ring_rtl64, ring_rt_log2<double>(g));
     if (anal_folded) *anal_folded = P->ana_ct > 0 ? 1 : 0;
   });
 }

@@ -1272,23 +1272,28 @@ __device__ inline void ring_spectrum(cz<T> (&z)[N], const T* g, int rs, int ks, 
   }
 }
 
-// Rings and threads per workgroup of k_ring_reg.
+// Rings per workgroup of k_ring_reg: the variants a plan may choose, per precision (the first
+// is the default), and the threads of a workgroup of RR rings: eight per ring (five hold the
+// inverse transforms, two the forward ones; 8 RR is a whole number of wavefronts).  Fewer rings
+// give smaller workgroups (less LDS each, more of them per compute unit) at the same number of
+// waves per compute unit, and fewer rings past the last node in the last tile.
 template <class T>
-__host__ __device__ constexpr int ring_reg_rings() {
-  return sizeof(T) == 4 ? 32 : 16;
+__host__ __device__ constexpr int ring_reg_variants() {
+  return sizeof(T) == 4 ? 3 : 2;
 }
 template <class T>
-__host__ __device__ constexpr int ring_reg_threads() {
-  return 256;
+__host__ __device__ constexpr int ring_reg_rings(int variant) {
+  return sizeof(T) == 4 ? (variant == 0 ? 32 : variant == 1 ? 24 : 16) : (variant == 0 ? 16 : 8);
 }
+__host__ __device__ constexpr int ring_reg_threads(int rr) { return 8 * rr; }
 
-template <class T, int MODE, int N1, int N2>
-__global__ void __launch_bounds__(ring_reg_threads<T>()) k_ring_reg(DevGrid g, int nvec, const T* __restrict__ Cs, const T* __restrict__ Cv,
+template <class T, int MODE, int N1, int N2, int RR>
+__global__ void __launch_bounds__(ring_reg_threads(RR)) k_ring_reg(DevGrid g, int nvec, const T* __restrict__ Cs, const T* __restrict__ Cv,
                                                   const T* __restrict__ base, const T* __restrict__ fw, T Ek,
                                                   T* __restrict__ Fs, T* __restrict__ Fv, double* __restrict__ base_out64,
                                                   float* __restrict__ base_out32) {
-  constexpr int N = N1 * N2, RR = ring_reg_rings<T>(), LS = N + 1;  // LS: LDS stride of one (slot, ring)
-  constexpr int NT = ring_reg_threads<T>();                         // threads per workgroup
+  constexpr int N = N1 * N2, LS = N + 1;  // LS: LDS stride of one (slot, ring)
+  constexpr int NT = ring_reg_threads(RR);  // threads per workgroup
   static_assert(5 * RR <= NT && NT % 64 == 0, "a thread per inverse transform");
   constexpr int NPT = (RR * N + NT - 1) / NT;                       // product points per thread
   // the fields of the transforms; first the copy of the Legendre sums [18 rows][K1][RR rings]
