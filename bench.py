@@ -681,7 +681,7 @@ def _counters(d):
 
 def summarize_profiles(d):
     """Turns the rocprofv3 runs under d (stats/, fetch/, write/, probe_fetch/, probe_write/,
-    sq_mfma/, sq_lds/, any of them may be missing) into the committed traffic file and prints
+    sq_mfma/, sq_lds/, sq_time/, any of them may be missing) into the committed traffic file and prints
     Markdown tables.  FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled by the
     ratio of the bytes a plain copy moves to what the same counter reads for it."""
     md = []
@@ -756,6 +756,20 @@ def summarize_profiles(d):
             md.append(f"{k} | {v.get('SQ_INSTS_LDS', 0.0) / waves:.0f} | {bc:.3f} | {wt:.2f} | "
                       f"{v.get('SQ_INSTS_VMEM_RD', 0.0) / waves:.0f}")
         md.append("")
+    tm = _counters(os.path.join(d, "sq_time"))
+    if tm:
+        # per-wave time split (wave-cycles, quad-cycle units cancel in the ratios)
+        md += ["kernel | waiting on anything / wave time | issuing any / wave time | VALU issue / wave time | "
+               "LDS issue / wave time | VMEM issue / wave time",
+               "---|---|---|---|---|---"]
+        for k, v in sorted(tm.items(), key=lambda kv: -stats.get(kv[0], {}).get("total_us", 0.0)):
+            if not k.startswith("sc::"):
+                continue
+            wc = v.get("SQ_WAVE_CYCLES", 0.0) or 1.0
+            md.append(f"{k} | {v.get('SQ_WAIT_ANY', 0.0) / wc:.2f} | {v.get('SQ_ACTIVE_INST_ANY', 0.0) / wc:.2f} | "
+                      f"{v.get('SQ_ACTIVE_INST_VALU', 0.0) / wc:.2f} | {v.get('SQ_ACTIVE_INST_LDS', 0.0) / wc:.2f} | "
+                      f"{v.get('SQ_ACTIVE_INST_VMEM', 0.0) / wc:.2f}")
+        md.append("")
     print("\n".join(md), flush=True)
 
 
@@ -795,7 +809,7 @@ def main():
                          "kernel for scaling the FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="only summarize the rocprofv3 runs under DIR (stats/, fetch/, write/, probe_fetch/, "
-                         "probe_write/, sq_mfma/, sq_lds/): rewrite the traffic file, print Markdown tables")
+                         "probe_write/, sq_mfma/, sq_lds/, sq_time/): rewrite the traffic file, print Markdown tables")
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles)

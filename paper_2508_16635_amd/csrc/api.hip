@@ -545,12 +545,18 @@ int ring_rt_log2(const sc::HostGrid& g) {
   return lg;
 }
 
-// Whether the register-transform ring kernel serves this N_phi and K: N_phi = N1 N2 with an
-// instantiation below, and N_phi >= 3K + 1 (its loops over harmonics have the compile-time
-// bound (N_phi - 1)/3 + 1, and the LDS copy of the sums, 18 (K+1) values per ring, fits the
-// field buffer of 10 (N_phi + 1)).
-static bool ring_reg_available(int nphi, int K) {
+// Whether the register-transform ring kernel serves this grid: N_phi = N1 N2 with an
+// instantiation below, N_phi >= 3K + 1 (its loops over harmonics have the compile-time bound
+// (N_phi - 1)/3 + 1, and the LDS copy of the sums, 18 (K+1) values per ring, fits the field
+// buffer of 10 (N_phi + 1)), and its buffer loads and stores reach every sum, base field and
+// output with 32-bit byte offsets (each range below 2^31 bytes in FP64).
+static bool ring_reg_available(const sc::DevGrid& d) {
+  const int nphi = d.nphi, K = d.K;
   if (3 * K + 1 > nphi) return false;
+  const long long lim = 1LL << 31;
+  if (18LL * (K + 1) * d.Np * d.vcap * d.nth * 8 >= lim || 9LL * d.N * d.nth * d.Np * 8 >= lim ||
+      12LL * (K + 1) * d.Np * d.vcap * d.nth * 8 >= lim)
+    return false;
   switch (nphi) {
     case 10: case 15: case 20: case 32: case 40: return true;
     default: return false;
@@ -593,7 +599,7 @@ void launch_ring_reg_n(int variant, const RingRegArgs<T>& a) {
 // N_phi has one and N_phi >= 3K + 1.  Returns false if not.
 template <class T, int MODE>
 bool launch_ring_reg(int nphi, int variant, const RingRegArgs<T>& a) {
-  if (!ring_reg_available(nphi, a.dg.K)) return false;
+  if (!ring_reg_available(a.dg)) return false;
   switch (nphi) {
     case 10: launch_ring_reg_n<T, MODE, 2, 5>(variant, a); return true;
     case 15: launch_ring_reg_n<T, MODE, 3, 5>(variant, a); return true;
@@ -1692,7 +1698,7 @@ int sc_autotune(sc_plan* P, int nvec, int reps, sc_tune_report* rep, void* strea
     auto ring_cands = [&](auto tag) {
       typedef decltype(tag) T;
       std::vector<int> c;
-      if (ring_reg_available(g.nphi, g.K))
+      if (ring_reg_available(P->dg()))
         for (int v = 0; v < sc::ring_reg_variants<T>(); ++v) c.push_back(-1 - v);
       for (int k = 0; k <= ring_rt_log2<T>(g); ++k) c.push_back(k);
       return c;
@@ -1748,7 +1754,7 @@ int sc_set_kernels(sc_plan* P, int ring_fp32, int ring_fp64, int anal_folded) {
     check_plan(P);
     const sc::HostGrid& g = P->hg;
     auto ok = [&](int c, int lim, int nvar) {
-      return c < 0 ? (ring_reg_available(g.nphi, g.K) && -1 - c < nvar) : c <= lim;
+      return c < 0 ? (ring_reg_available(P->dg()) && -1 - c < nvar) : c <= lim;
     };
     if (!ok(ring_fp32, ring_rt_log2<float>(g), sc::ring_reg_variants<float>()) ||
         !ok(ring_fp64, ring_rt_log2<double>(g), sc::ring_reg_variants<double>()))
@@ -1767,7 +1773,7 @@ int sc_get_kernels(const sc_plan* P, int* ring_fp32, int* ring_fp64, int* anal_f
     if (!P) throw Fail{SC_ERR_ARG, "null plan"};
     const sc::HostGrid& g = P->hg;
     auto cur = [&](bool reg, int rv, int rtl, int lim) {
-      if (reg && ring_reg_available(g.nphi, g.K)) return -1 - rv;
+      if (reg && ring_reg_available(P->dg())) return -1 - rv;
       return rtl >= 0 ? std::min(rtl, lim) : lim;
     };
     if (ring_fp32) *ring_fp32 = cur(P->ring_reg32, P->ring_rv32, P->ring_rtl32, ring_rt_log2<float>(g));

@@ -1272,6 +1272,37 @@ __device__ inline void ring_spectrum(cz<T> (&z)[N], const T* g, int rs, int ks, 
   }
 }
 
+// Buffer loads (raw, byte offsets: per-lane vo plus wave-uniform so).  The third descriptor word
+// selects 32-bit data with bounds checking, so a load past num_records returns zero.
+constexpr int kBufferDword3 = 0x00020000;
+
+template <class T>
+__device__ __forceinline__ T buffer_load1(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so);
+template <>
+__device__ __forceinline__ float buffer_load1<float>(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+template <>
+__device__ __forceinline__ double buffer_load1<double>(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+template <class T>
+__device__ __forceinline__ void buffer_store1(T x, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so);
+template <>
+__device__ __forceinline__ void buffer_store1<float>(float x, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, vo, so, 0);
+}
+template <>
+__device__ __forceinline__ void buffer_store1<double>(double x, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, x), r, vo, so,
+                                        0);
+}
+template <class V>
+__device__ __forceinline__ V buffer_load8(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  static_assert(sizeof(V) == 8, "an 8-byte piece");
+  return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+
 // Rings per workgroup of k_ring_reg: the variants a plan may choose, per precision (the first
 // is the default), and the threads of a workgroup of RR rings: eight per ring (five hold the
 // inverse transforms, two the forward ones; 8 RR is a whole number of wavefronts).  Fewer rings
@@ -1304,16 +1335,24 @@ __global__ void __launch_bounds__(ring_reg_threads(RR)) k_ring_reg(DevGrid g, in
   const int lid = xcd_linear_id();
   const int tile = lid % ntile, rv = lid / ntile, rp = rv / nvec, vq = rv - rp * nvec;
   const int th0 = tile * RR, tid = threadIdx.x;
+  // The loads go through buffer resources with 32-bit byte offsets (the launch checks that the
+  // sums of every vector, 18 (K+1) N_p vcap N_theta values from Cs on, and the base fields fit
+  // in 2^31 bytes): one add per load instead of 64-bit address arithmetic, and a load past a
+  // resource returns zero.
+  const unsigned szT = sizeof(T);
   // base fields of this thread's product points, loaded first so they arrive during the FFTs;
   // points of rings beyond the last node read that node (their results are never written)
   T bpre[NPT][9];
   if (MODE == RING_LINEAR) {
+    const __amdgpu_buffer_rsrc_t rb =
+        __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(9u * N * nth * Np * szT), kBufferDword3);
+    const unsigned qs = (unsigned)N * nth * szT;   // byte stride of the nine fields
 #pragma unroll
     for (int u = 0; u < NPT; ++u) {
       const int idx = tid + NT * u, r = idx % RR, pt = min(idx / RR, N - 1), th = min(th0 + r, nth - 1);
-      const T* bp = base + ((long long)rp * 9 * N + pt) * nth + th;
+      const unsigned vo = ((unsigned)(rp * 9 * N + pt) * nth + th) * szT;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) bpre[u][q] = bp[(long long)q * N * nth];
+      for (int q = 0; q < 9; ++q) bpre[u][q] = buffer_load1<T>(rb, vo, q * qs);
     }
   }
   // copy of the sums of this workgroup's rings into LDS, [18 rows][K1][RR rings]: every (row, k)
@@ -1325,23 +1364,26 @@ __global__ void __launch_bounds__(ring_reg_threads(RR)) k_ring_reg(DevGrid g, in
     constexpr int EPL = 8 / sizeof(T), PPR = RR / EPL, NG = NT / PPR;   // elements per piece, pieces per run, groups
     constexpr int KM = (N - 1) / 3 + 1, NRW = (kRingRows + NG - 1) / NG; // rows per group
     typedef T pT __attribute__((ext_vector_type(EPL)));
-    const long long kS = (long long)6 * Np * g.vcap * nth, kV = (long long)12 * Np * g.vcap * nth;
-    const long long sR = (long long)Np * nth;
-    // unconditional loads at clamped positions: a piece beyond the last node reads the last
-    // one (that ring's results are never written), k >= K1 repeats a valid one and is not
-    // stored; rows beyond the last are skipped (whole wavefronts but one)
+    const unsigned kS = 6u * Np * g.vcap * nth * szT, kV = 2 * kS;        // bytes per harmonic
+    const unsigned sR = (unsigned)Np * nth * szT;                          // bytes per row
+    const unsigned offV = (unsigned)(Cv - Cs) * szT;                       // Cv follows Cs
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)Cs, (short)0, (int)(3u * K1 * kS), kBufferDword3);
+    // a piece beyond the last node reads the last one (that ring's results are never written),
+    // k >= K1 reads past the rows of K1 harmonics (not stored); rows beyond the last are
+    // skipped (whole wavefronts but one)
     const int e = tid % PPR, grp = tid / PPR, th = min(th0 + e * EPL, nth - EPL);
-    const T* cs = Cs + ((long long)vq * 6 * Np + rp) * nth + th;
-    const T* cv = Cv + ((long long)vq * 12 * Np + rp) * nth + th;
+    const unsigned vs = ((unsigned)(vq * 6 * Np + rp) * nth + th) * szT;
+    const unsigned vv = offV + ((unsigned)(vq * 12 * Np + rp) * nth + th) * szT;
     pT val[NRW][KM];
 #pragma unroll
     for (int i = 0; i < NRW; ++i) {
       const int row = grp + i * NG;
       if (i > 0 && row >= kRingRows) continue;
-      const T* src = row < 6 ? cs + row * sR : cv + (row - 6) * sR;
-      const long long kst = row < 6 ? kS : kV;
+      unsigned o = row < 6 ? vs + row * sR : vv + (row - 6) * sR;
+      const unsigned kst = row < 6 ? kS : kV;
 #pragma unroll
-      for (int k = 0; k < KM; ++k) val[i][k] = *reinterpret_cast<const pT*>(src + min(k, K1 - 1) * kst);
+      for (int k = 0; k < KM; ++k, o += kst) val[i][k] = buffer_load8<pT>(rs, o, 0);
     }
 #pragma unroll
     for (int i = 0; i < NRW; ++i) {
@@ -1421,13 +1463,17 @@ __global__ void __launch_bounds__(ring_reg_threads(RR)) k_ring_reg(DevGrid g, in
     fft_reg<T, N1, N2, -1>(z, fw);
     if (th < nth) {
       const int vr = vq * Np + rp;  // row (vec, r_p) of the analysis inputs
-      const long long Ma = (long long)4 * Np * g.vcap;
-      // output rows of harmonic k: running pointers, advanced by one harmonic block per k
-      T* os = Fs + ((long long)vr * 4) * nth + th;
-      T* ov = Fv + ((long long)vr * 4) * 2 * nth + th;
-      const long long dS = Ma * nth, dV = Ma * 2 * nth;
+      // buffer stores from Fs (Fv follows it; 3 (K+1) 4 N_p vcap N_theta values in all): per
+      // lane the byte offset of its first output row, per (harmonic, row) a wave-uniform offset
+      const unsigned Ma = 4u * Np * g.vcap, ns = (unsigned)nth * szT;
+      const __amdgpu_buffer_rsrc_t rf =
+          __builtin_amdgcn_make_buffer_rsrc((void*)Fs, (short)0, (int)(3u * K1 * Ma * ns), kBufferDword3);
+      const unsigned vsb = ((unsigned)vr * 4 * nth + th) * szT;
+      const unsigned vvb = (unsigned)(Fv - Fs) * szT + ((unsigned)vr * 4 * 2 * nth + th) * szT;
+      const unsigned dS = Ma * ns, dV = 2 * Ma * ns;
+      auto st = [&](unsigned vo, unsigned so, T x) { buffer_store1<T>(x, rf, vo, so); };
 #pragma unroll
-      for (int k = 0; k < (N - 1) / 3 + 1; ++k, os += dS, ov += dV) {
+      for (int k = 0; k < (N - 1) / 3 + 1; ++k) {
         if (k >= K1) continue;
         const T sc = (k == 0 ? (T)1 : (T)2) / (T)N;
         T ar, ai, br, bi;
@@ -1443,20 +1489,22 @@ __global__ void __launch_bounds__(ring_reg_threads(RR)) k_ring_reg(DevGrid g, in
         }
         ar *= sc; ai *= sc; br *= sc; bi *= sc;
         if (o == 0) {  // (W_r, Q)
-          os[0 * nth] = ar;
-          os[1 * nth] = ai;
-          os[2 * nth] = br;
-          os[3 * nth] = bi;
+          const unsigned so = k * dS;
+          st(vsb, so, ar);
+          st(vsb, so + ns, ai);
+          st(vsb, so + 2 * ns, br);
+          st(vsb, so + 3 * ns, bi);
         } else {       // (W_th, W_ph): dP rows (W_th, -W_ph); mPs rows (-i W_ph, -i W_th)
-          ov[0 * 2 * nth] = ar;
-          ov[1 * 2 * nth] = ai;
-          ov[2 * 2 * nth] = -br;
-          ov[3 * 2 * nth] = -bi;
+          const unsigned so = k * dV;
+          st(vvb, so, ar);
+          st(vvb, so + 2 * ns, ai);
+          st(vvb, so + 4 * ns, -br);
+          st(vvb, so + 6 * ns, -bi);
           if (!g.fv_dp_only) {
-            ov[0 * 2 * nth + nth] = bi;
-            ov[1 * 2 * nth + nth] = -br;
-            ov[2 * 2 * nth + nth] = ai;
-            ov[3 * 2 * nth + nth] = -ar;
+            st(vvb, so + ns, bi);
+            st(vvb, so + 3 * ns, -br);
+            st(vvb, so + 5 * ns, ai);
+            st(vvb, so + 7 * ns, -ar);
           }
         }
       }
