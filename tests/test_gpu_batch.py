@@ -189,6 +189,64 @@ def test_batch_newton_matches_per_plan(sc, prec):
         p.close()
 
 
+# three problems of uneven truncation in the pattern of the 32-problem continuation batch (order
+# m0 at 1e-2, higher orders at 1e-4, conductive profile), small enough for the oracle
+C4_SAMPLES = [(16, 16, 4, 16, 1e-3, 70.0, 4101), (20, 20, 3, 20, 3e-4, 110.0, 4102), (24, 24, 5, 18, 1e-3, 90.0, 4103)]
+
+
+def test_batch_newton_solves_the_oracle_problems(sc):
+    """sc_batch_newton on three uneven problems whose forcing is the oracle's residual at the
+    chosen root, F = -R_oracle(X*, C*), in the mixed precision of the continuation batch (GMRES
+    tolerance 1e-6, restart 1000): every plan converges to ||R + F|| <= 1e-10 and lands on X*, C*
+    (so the library's Newton solves the oracle's equations), and the oracle's own residual at the
+    converged point equals its residual at X*."""
+    ri, ro = 0.35 / 0.65, 1.0 / 0.65
+    plans, probs = [], []
+    for (L, M, m0, N, Ek, Ra, seed) in C4_SAMPLES:
+        print(f"plan L={L} m0={m0} N={N} Ek={Ek}", flush=True)
+        p = sc.Plan(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=200.0, nvec_max=1)
+        p.factor()
+        lay = si.Layout(L, M, m0, N)
+        ora = Problem(L, M, m0, N, Ek=Ek, Ra=Ra, Pr=1.0, dt=200.0)
+        X = si.random_state(lay, seed, amp=(1.0, 1.0, 1.0), p=2.0, t_offset=lambda x: ro * ri / ((x + ri + ro) / 2) - ri)
+        Xc = si.random_state(lay, seed, amp=(0.0, 0.0, 0.0), p=2.0, t_offset=lambda x: ro * ri / ((x + ri + ro) / 2) - ri)
+        for fld in range(3):
+            for k, m in enumerate(lay.ms):
+                o = lay.offset(fld, k, m)
+                n = 2 * lay.N * lay.nl[k]
+                X[o:o + n] = Xc[o:o + n] if k == 0 else X[o:o + n] * (1e-2 if k == 1 else 1e-4)
+        Xs = ora.clean(X)
+        J = si.default_phase_slot(lay, Xs)
+        Cs = 0.5
+        R0 = ora.residual(Xs, Cs)
+        d = ora.clean(si.random_state(lay, seed + 1, p=2))
+        d[J] = 0.0
+        X0 = Xs + 1e-3 * np.linalg.norm(Xs) * d / np.linalg.norm(d)
+        plans.append(p)
+        probs.append((ora, Xs, Cs, J, R0, X0))
+    b = sc.Batch(plans)
+    xs = [torch.from_numpy(X0).cuda() for (_, _, _, _, _, X0) in probs]
+    Fs = [torch.from_numpy(-R0).cuda() for (_, _, _, _, R0, _) in probs]
+    print("batch newton", flush=True)
+    out = b.newton(xs, [Cs + 1e-3 for (_, _, Cs, _, _, _) in probs], [J for (_, _, _, J, _, _) in probs],
+                   forcings=Fs, tol=1e-10, gmres_tol=1e-6, restart=1000, max_newton=10, max_matvec=2000, prec=1)
+    torch.cuda.synchronize()
+    b.close()
+    for i, ((C, rep), x, (ora, Xs, Cs, J, R0, X0)) in enumerate(zip(out, xs, probs)):
+        X = x.cpu().numpy()
+        ex = np.linalg.norm(X - Xs) / np.linalg.norm(Xs)
+        dR = np.linalg.norm(ora.residual(X, C) - R0)
+        print(f"problem {i}: {rep['newton_steps']} Newton steps, {rep['matvecs']} actions, |R+F| {rep['rnorm'][-1]:.2e}, "
+              f"|X - X*|/|X*| {ex:.2e}, C - C* {C - Cs:.2e}, oracle |R(X) - R(X*)| {dR:.2e}", flush=True)
+        assert rep["converged"] and rep["rnorm"][-1] <= 1e-10
+        # the drift speed is fixed only to ||R + F|| / |dR/dC|, and |dR/dC| ~ 1e-3 here (the
+        # non-axisymmetric part of these states is 1e-2 of the profile)
+        assert ex <= 1e-9 and abs(C - Cs) <= 1e-6
+        assert dR <= 1e-9
+    for p in plans:
+        p.close()
+
+
 GRAPH_OFF = ("HIP graph capture is switched off: the first captured batch call ended the process with a host "
              "segmentation fault inside the HIP runtime (twice, on the caller's stream and on a library stream); "
              "cause not found, so the captured path raises SC_ERR_ARG and stays off the GPU")
