@@ -37,7 +37,7 @@ PEAK = {"hbm": 8000.0, "fp32": 157.3, "fp64": 78.6}   # GB/s, TFLOP/s (MI355X pu
 
 # single-kernel stages of the mixed path at this workload and the kernel each one launches
 SINGLE_KERNEL_STAGES = {
-    "ring": "sc::k_ring_reg<float, 0, 8, 5>",          # N_phi = 40 = 8 x 5
+    "ring": "sc::k_ring_reg<float, 0, 8, 5, 32>",      # N_phi = 40 = 8 x 5, 32 rings per workgroup
     "legendre_synth": "sc::k_synth<float>",
     "legendre_anal": "sc::k_anal<float, 5>",           # up to 5 column tiles per degree parity
     "radial_prep": "sc::k_radial_prep<float, 3>",
@@ -54,6 +54,8 @@ def stage_kernels(tuning, N=48):
     if tuning is not None:
         if tuning["ring_fp32"] >= 0:
             k["ring"] = "sc::k_ring<float, 0>"
+        else:   # register ring of shape -1 - v: 32, 24 or 16 rings per workgroup
+            k["ring"] = f"sc::k_ring_reg<float, 0, 8, 5, {(32, 24, 16)[-1 - tuning['ring_fp32']]}>"
         if not tuning["anal_folded"]:
             k["legendre_anal"] = "sc::k_gemm_batched<float>"
     return k
@@ -156,7 +158,8 @@ def run(args):
     t_base = time.time() - t0
     # kernel choice by measurement at this shell and batch (sc_autotune, timing the Jacobian
     # action's linear products on this base state), before any timing
-    tuning = None if args.no_autotune else plan.autotune(nvec, reps=5)
+    # 20 timed passes per candidate: the register ring's shapes differ by a few per cent
+    tuning = None if args.no_autotune else plan.autotune(nvec, reps=20)
     nv_total = max(args.nvectors, nvec)
     V = torch.from_numpy(si.random_vectors(lay, range(3001, 3001 + nv_total))).to(dev)
     Y = torch.empty((nvec, plan.n_real), dtype=torch.float64, device=dev)
@@ -198,7 +201,7 @@ def run(args):
         plan2.factor()
         plan2.set_base(Xd, C, J)
         if not args.no_autotune:
-            plan2.autotune(nvec, reps=5)
+            plan2.autotune(nvec, reps=20)
         r2 = timed(plan2, sc.SC_MIXED)
         Y2 = torch.empty_like(Y)
         plan2.jvp(batch(0), Y2, sc.SC_MIXED)
