@@ -184,7 +184,8 @@ const char* sc_last_error(void);
 /* Kernel choice by measurement (the transforms of Sec. 3.1 at this plan's L, M, m0, N).  Times
  * one transform pass (spectral prep, Legendre synthesis, azimuthal transforms and products,
  * Legendre analysis) of nvec zero vectors for every candidate, `reps` timed passes after one
- * untimed pass each, on `stream`, and keeps the fastest in the plan for later calls.  The pass
+ * untimed pass each, on `stream`, in three interleaved rounds over the ring candidates (each
+ * kept at its fastest round), and keeps the fastest in the plan for later calls.  The pass
  * uses the Jacobian action's linearized products (the base fields of sc_set_base read at every
  * point) when a base state is set, else the nonlinear products of the step.  Candidates:
  *   ring kernel, per precision: the register-transform kernel (where N_phi = N1 N2 has one and

@@ -1691,7 +1691,6 @@ int sc_autotune(sc_plan* P, int nvec, int reps, sc_tune_report* rep, void* strea
       HIPCHK(hipEventSynchronize(ev.b));
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, ev.a, ev.b));
-      ++ncand;
       return (double)ms / reps;
     };
     // ring candidates: -1 - v register kernel of shape v, k >= 0 LDS kernel with 2^k rings
@@ -1704,16 +1703,24 @@ int sc_autotune(sc_plan* P, int nvec, int reps, sc_tune_report* rep, void* strea
       return c;
     };
     auto set_ring = [&](auto tag, int c) { set_ring_choice<decltype(tag)>(P, c); };
+    // three interleaved rounds over the candidates, each kept at its fastest round: drifts of
+    // the device (clocks, caches) then touch every candidate alike, and the register ring's
+    // shapes differ by only a few per cent
     auto tune_ring = [&](auto tag, double& best, int& choice) {
-      best = 1e300;
-      for (int c : ring_cands(tag)) {
-        set_ring(tag, c);
-        const double t = time_pass(tag);
-        if (t < best) {
-          best = t;
-          choice = c;
+      const std::vector<int> cands = ring_cands(tag);
+      ncand += (int)cands.size();
+      std::vector<double> t(cands.size(), 1e300);
+      for (int round = 0; round < 3; ++round)
+        for (size_t i = 0; i < cands.size(); ++i) {
+          set_ring(tag, cands[i]);
+          t[i] = std::min(t[i], time_pass(tag));
         }
-      }
+      best = 1e300;
+      for (size_t i = 0; i < cands.size(); ++i)
+        if (t[i] < best) {
+          best = t[i];
+          choice = cands[i];
+        }
       set_ring(tag, choice);
     };
     // FP32: ring choice for each analysis path; the analysis path serves both precisions
