@@ -229,7 +229,7 @@ def run(args):
     work = stage_work(lay_d, nvec, 4, fbytes, nblocks, refine=args.refine_mixed if args.mixed_solve == "fp32" else 0,
                       dp_only=tuning is None or bool(tuning["anal_folded"]))
     prof = mixed["prof"]
-    # the dominant single-kernel stage of the mixed path (the chain solve is seven kernels and
+    # the dominant single-kernel stage of the mixed path (the chain solve is five kernels and
     # the temperature solve runs beside it on a second stream)
     kernels = stage_kernels(tuning, W["N"])
     dom = max((k for k in kernels if k in prof and prof[k][1]), key=lambda k: prof[k][0])

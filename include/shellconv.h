@@ -173,7 +173,8 @@ enum {
   SC_STAGE_CHAIN_SOLVE = 5,     /* block-tridiagonal e/f solves                            */
   SC_STAGE_T_SOLVE = 6,         /* temperature solves                                      */
   SC_STAGE_RESIDUAL = 7,        /* FP64 residual of the implicit operator                  */
-  SC_STAGE_AXPY = 8,            /* refinement update (now folded into the correction solve) */
+  SC_STAGE_AXPY = 8,            /* refinement update: folded into the correction solve, so no
+                                   launch is recorded here; the index is kept stable     */
   SC_STAGE_FINALIZE = 9,        /* output assembly                                         */
   SC_NSTAGES = 10
 };

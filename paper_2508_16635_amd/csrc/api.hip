@@ -116,10 +116,10 @@ struct sc_plan {
   // base state (dC: its drift speed, read by the Jacobian action's right-hand side)
   DevBuf base64, base32, MX, dC;
   // factors
-  DevBuf chains, segs, blk_field, blk_lm, blk_next, blk_fsrc;
+  DevBuf chains, segs, blk_field, blk_lm, blk_next;
   int nchains = 0, nblocks = 0, nsegs = 0;
-  DevBuf Sinv64, G64, H64, Phi64, Psi64, sr64, sc64, Rg64, Cg64;
-  DevBuf Sinv32, G32, H32, Phi32, Psi32, sr32, sc32, Rg32, Cg32;
+  DevBuf D64, G64, H64, Phi64, Psi64, Cg64;
+  DevBuf D32, G32, H32, Phi32, Psi32, Cg32;
   DevBuf wscan;  // scan work vectors, capacity vcap x nblocks x N complex doubles
   DevBuf Tinv64, tr64, tc64, Tinv32, tr32, tc32;
   // Newton-GMRES workspace (allocated by the first sc_newton call)
@@ -742,29 +742,22 @@ void chain_solve_rt(sc_plan* P, int nvec, const double* b, double* x, const sc::
   const int nvg = (nvec + kVG - 1) / kVG;
   const bool d = std::is_same<F, double>::value;
   typedef sc::cpx<F> C;
-  const C* Sinv = (const C*)(d ? P->Sinv64.p : P->Sinv32.p);
+  const C* Dm = (const C*)(d ? P->D64.p : P->D32.p);
   const C* Gm = (const C*)(d ? P->G64.p : P->G32.p);
   const C* H = (const C*)(d ? P->H64.p : P->H32.p);
   const C* Phi = (const C*)(d ? P->Phi64.p : P->Phi32.p);
   const C* Psi = (const C*)(d ? P->Psi64.p : P->Psi32.p);
-  const F* sr = (const F*)(d ? P->sr64.p : P->sr32.p);
-  const F* scl = (const F*)(d ? P->sc64.p : P->sc32.p);
-  const F* Rg = (const F*)(d ? P->Rg64.p : P->Rg32.p);
   const F* Cg = (const F*)(d ? P->Cg64.p : P->Cg32.p);
   C* W = (C*)P->wscan.p;
   const sc::ChainMeta* ch = P->chains.as<sc::ChainMeta>();
   const sc::SegMeta* sg = P->segs.as<sc::SegMeta>();
   const dim3 blk(sc::kSolveThreads);
-  hipLaunchKernelGGL((sc::k_cs_rhs<F, RT>), dim3(P->nblocks, nvg), blk, 0, s, dg, nvec, P->blk_field.as<int>(),
-                     P->blk_lm.as<int>(), Sinv, sr, scl, Rg, b, W);
-  HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL((sc::k_cs_fwd_local<F, RT>), dim3(P->nsegs, nvg), blk, 0, s, dg, nvec, sg, Gm, W);
+  hipLaunchKernelGGL((sc::k_cs_fwd_rhs<F, RT>), dim3(P->nsegs, nvg), blk, 0, s, dg, nvec, sg, P->blk_field.as<int>(),
+                     P->blk_lm.as<int>(), Dm, Gm, b, W);
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL((sc::k_cs_fwd_bound<F, RT>), dim3(P->nchains, nvg), blk, 0, s, dg, nvec, ch, kSeg, Phi, W);
   HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL((sc::k_cs_fix<F, RT>), dim3(P->nblocks, nvg), blk, 0, s, dg, nvec, P->blk_fsrc.as<int>(), Phi, W);
-  HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL((sc::k_cs_bwd_local<F, RT>), dim3(P->nsegs, nvg), blk, 0, s, dg, nvec, sg, H, W);
+  hipLaunchKernelGGL((sc::k_cs_bwd_fix<F, RT>), dim3(P->nsegs, nvg), blk, 0, s, dg, nvec, sg, Phi, H, W);
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL((sc::k_cs_bwd_bound<F, RT>), dim3(P->nchains, nvg), blk, 0, s, dg, nvec, ch, kSeg, Psi, W);
   HIPCHK(hipGetLastError());
@@ -1435,10 +1428,10 @@ int sc_factor(sc_plan* P, void* stream) {
     // lane l of (t, s) holds M[16 t + l % 16][4 s + l / 16], zero outside N x N
     const int RT = (N + 15) / 16, KS = 4 * RT;
     const long long FB = sc::frag_block_size(RT);
-    std::vector<double> Sinv(2 * nb * FB, 0.0), Gm(2 * nb * FB, 0.0), H(2 * nb * FB, 0.0), Phi(2 * nb * FB, 0.0),
+    std::vector<double> Dm(2 * nb * FB, 0.0), Gm(2 * nb * FB, 0.0), H(2 * nb * FB, 0.0), Phi(2 * nb * FB, 0.0),
         Psi(2 * nb * FB, 0.0);
-    std::vector<int> bfsrc;
-    std::vector<double> sr(nb * N), scv(nb * N), Rg(nb * N), Cg(nb * N);
+    std::vector<double> Cg(nb * N);
+    std::vector<sc::cplx> Dblk((size_t)NN);
     long long b = 0;
     auto put = [&](std::vector<double>& dst, const std::vector<sc::cplx>& src, long long bb, int i) {
       for (int t = 0; t < RT; ++t)
@@ -1463,19 +1456,18 @@ int sc_factor(sc_plan* P, void* stream) {
         int p = i / kSeg;
         bool fixup = (p < nseg - 1) && (i % kSeg != 0);
         bnext.push_back(fixup ? (int)(meta.back().start + (p + 1) * kSeg) : -1);
-        bool ffix = (p > 0) && (i != std::min((p + 1) * kSeg, c.n) - 1);
-        bfsrc.push_back(ffix ? (int)(meta.back().start + p * kSeg - 1) : -1);
-        put(Sinv, c.Sinv, b, i);
+        // D_i = diag(sc_i) Shat_i^{-1} diag(sr_i) diag(Rg_i): the right-hand side's scalings
+        // folded into the pivot block's inverse, so that c_i = D_i b_i
+        for (int r = 0; r < N; ++r)
+          for (int q = 0; q < N; ++q)
+            Dblk[(size_t)r * N + q] = c.Sinv[(size_t)i * NN + (size_t)r * N + q] *
+                                      (c.sc[(size_t)i * N + r] * c.sr[(size_t)i * N + q] * c.Rg[(size_t)i * N + q]);
+        put(Dm, Dblk, b, 0);
         put(Gm, c.G, b, i);
         put(H, c.H, b, i);
         put(Phi, c.Phi, b, i);
         put(Psi, c.Psi, b, i);
-        for (int j = 0; j < N; ++j) {
-          sr[b * N + j] = c.sr[(size_t)i * N + j];
-          scv[b * N + j] = c.sc[(size_t)i * N + j];
-          Rg[b * N + j] = c.Rg[(size_t)i * N + j];
-          Cg[b * N + j] = c.Cg[(size_t)i * N + j];
-        }
+        for (int j = 0; j < N; ++j) Cg[b * N + j] = c.Cg[(size_t)i * N + j];
       }
     }
     std::vector<double> Tinv((size_t)(g.L + 1) * N * N), tr((size_t)(g.L + 1) * N), tc((size_t)(g.L + 1) * N);
@@ -1494,17 +1486,13 @@ int sc_factor(sc_plan* P, void* stream) {
     upload(P->blk_field, bf);
     upload(P->blk_lm, blm);
     upload(P->blk_next, bnext);
-    upload(P->blk_fsrc, bfsrc);
-    up2(P->Sinv64, P->Sinv32, Sinv);
+    up2(P->D64, P->D32, Dm);
     up2(P->G64, P->G32, Gm);
     up2(P->H64, P->H32, H);
     up2(P->Phi64, P->Phi32, Phi);
     up2(P->Psi64, P->Psi32, Psi);
     P->wscan.alloc((size_t)P->wcap * nb * N * 2 * sizeof(double));
     HIPCHK(hipMemset(P->wscan.p, 0, (size_t)P->wcap * nb * N * 2 * sizeof(double)));
-    up2(P->sr64, P->sr32, sr);
-    up2(P->sc64, P->sc32, scv);
-    up2(P->Rg64, P->Rg32, Rg);
     up2(P->Cg64, P->Cg32, Cg);
     up2(P->Tinv64, P->Tinv32, Tinv);
     up2(P->tr64, P->tr32, tr);

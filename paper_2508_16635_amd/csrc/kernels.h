@@ -1686,13 +1686,13 @@ __global__ void k_apply_M(DevGrid g, PhysParams ph, const double* __restrict__ X
 //   forward  z_i = c_i - G_i z_{i-1},   c_i = D_i t_i,  G_i = D_i Lo_i
 //   backward x_i = z_i - H_i x_{i+1}
 // Inside a segment [a, e]: z_i = zeta_i + Phi_i z_{a-1}, x_i = xi_i + Psi_i x_{e+1}, with zeta
-// and xi the local recurrences started from zero.  Launches: c (all blocks), local forward
-// (per segment), forward boundary pass (per chain), forward fix-up (all blocks), local
-// backward (per segment), backward boundary pass (per chain), backward fix-up and output
-// (all blocks).
+// and xi the local recurrences started from zero.  Launches: local forward with c (per
+// segment), forward boundary pass (per chain), forward fix-up with the local backward (per
+// segment), backward boundary pass (per chain), backward fix-up and output (all blocks).
 //
-// Every step is y = w + sign M x for one complex N x N block M and 16 right-hand sides, done
-// as four real 16x16x4 MFMA products per k-step (Re/Im split).  The blocks are stored in the
+// Every step is y = w + sign M x for one complex N x N block M (or the sum of two such
+// products) and 16 right-hand sides, done as three real 16x16x4 MFMA products per k-step
+// (Gauss's form of the complex product).  The blocks are stored in the
 // MFMA operand order: with RT = ceil(N/16) row tiles and 4 RT k-steps, lane l of
 // (row tile t, k-step s) holds M[16t + l%16][4s + l/16] (zero outside N x N), so wave t of
 // the workgroup streams its operands with fully coalesced loads straight into registers,
@@ -1776,6 +1776,38 @@ struct ChainOps {
       yi[q] = p3[q] - p1[q] - p2[q];
     }
   }
+  // The Gauss sums of M x added into (p1, p2, p3), x = sgn * (LDS buffer), or x in registers in
+  // the B-operand layout (xv[ks] = x[4 ks + l/16][l % 16]); several products summed this way
+  // share one set of sums, finished by yr = p1 - p2, yi = p3 - p1 - p2.
+  __device__ inline void acc_lds(const F (&ar)[KS], const F (&ai)[KS], const cpx<F>* x, F sgn, acc_t& p1, acc_t& p2,
+                                 acc_t& p3) const {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const cpx<F> xv = x[(4 * ks + (l >> 4)) * kVG + col];
+      const F c = sgn * xv.re, d = sgn * xv.im;
+      p1 = Mfma<F>::step(ar[ks], c, p1);
+      p2 = Mfma<F>::step(ai[ks], d, p2);
+      p3 = Mfma<F>::step(ar[ks] + ai[ks], c + d, p3);
+    }
+  }
+  __device__ inline void acc_reg(const F (&ar)[KS], const F (&ai)[KS], const cpx<F> (&xv)[KS], acc_t& p1, acc_t& p2,
+                                 acc_t& p3) const {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      p1 = Mfma<F>::step(ar[ks], xv[ks].re, p1);
+      p2 = Mfma<F>::step(ai[ks], xv[ks].im, p2);
+      p3 = Mfma<F>::step(ar[ks] + ai[ks], xv[ks].re + xv[ks].im, p3);
+    }
+  }
+  __device__ inline void load_ops(const cpx<F>* __restrict__ frags, long long blk, F (&ar)[KS], F (&ai)[KS]) const {
+    const cpx<F>* p = frags + blk * FB + (long long)w * KS * 64 + l;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const cpx<F> v = p[ks * 64];
+      ar[ks] = v.re;
+      ai[ks] = v.im;
+    }
+  }
 };
 
 // x block of W (or zero) into a 64 x 16 LDS buffer; the second buffer (if any) is zeroed.
@@ -1842,57 +1874,81 @@ __device__ inline void chain_walk(int N, int wcap, const cpx<F>* __restrict__ fr
   }
 }
 
-// c_i = diag(sc_i) Shat_i^{-1} diag(Rg_i sr_i) b_i for every block; zero columns beyond nvec.
+// Forward pass of one segment [a, e] with its right-hand side: c_i = D_i b_i for every block
+// of the segment (D_i = diag(sc_i) Shat_i^{-1} diag(sr_i) diag(Rg_i), the scalings folded into
+// the stored blocks) and the local recurrence zeta_a = c_a, zeta_i = c_i - G_i zeta_{i-1},
+// stored in W (zero columns beyond nvec).  Each step sums both products in one set of Gauss
+// sums; b is read from the FP64 input straight into the B-operand layout, and the operands of
+// step t+1 (D, G fragments and b) load while step t multiplies.
 template <class F, int RT>
-__global__ void __launch_bounds__(kSolveThreads) k_cs_rhs(DevGrid g, int nvec, const int* __restrict__ blk_field,
-                                                         const int* __restrict__ blk_lm, const cpx<F>* __restrict__ Sinv,
-                                                         const F* __restrict__ sr, const F* __restrict__ scl,
-                                                         const F* __restrict__ Rg, const double* __restrict__ bvec,
-                                                         cpx<F>* __restrict__ W) {
-  __shared__ cpx<F> xs[64 * kVG];
+__global__ void __launch_bounds__(kSolveThreads, 1) k_cs_fwd_rhs(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
+                                                                const int* __restrict__ blk_field,
+                                                                const int* __restrict__ blk_lm,
+                                                                const cpx<F>* __restrict__ Dm,
+                                                                const cpx<F>* __restrict__ Gm,
+                                                                const double* __restrict__ bvec,
+                                                                cpx<F>* __restrict__ W) {
+  __shared__ cpx<F> xb[2 * 64 * kVG];
   typedef ChainOps<F, RT> Ops;
-  const int N = g.N;
+  constexpr int KS = Ops::KS;
+  const SegMeta sg = segs[blockIdx.x];
+  const int N = g.N, a = sg.first_block, len = sg.len, v0 = blockIdx.y * kVG, nv = min(kVG, nvec - v0);
   Ops op(N, g.wcap);
-  const int blk = blockIdx.x, v0 = blockIdx.y * kVG, nv = min(kVG, nvec - v0);
-  typename Ops::Set S;
-  if (op.active()) op.load_frag(Sinv, blk, S);
+  // rows N..63 of both buffers are read as zero operands and never written by the steps
+  for (int idx = N * kVG + threadIdx.x; idx < 64 * kVG; idx += kSolveThreads) {
+    xb[idx] = cpx<F>{0, 0};
+    xb[64 * kVG + idx] = cpx<F>{0, 0};
+  }
+  struct Set {
+    F dr[KS], di[KS], gr[KS], gi[KS];
+    cpx<F> b[KS];
+  };
   const long long ld = 6LL * N * g.S;
-  const long long o = 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + blk_lm[blk]));
-  staged_copy<64 * kVG / kSolveThreads, cpx<F>>(
-      64 * kVG,
-      [&](int idx) -> cpx<F> {
-        const int r = idx / kVG, c = idx % kVG;
-        if (r >= N || c >= nv) return cpx<F>{0, 0};
-        const double* bp = bvec + (long long)(v0 + c) * ld + o + 2 * r;
-        const F sc = Rg[(long long)blk * N + r] * sr[(long long)blk * N + r];
-        return cpx<F>{sc * (F)bp[0], sc * (F)bp[1]};
-      },
-      [&](int idx, cpx<F> v) { xs[idx] = v; });
-  __syncthreads();
-  if (op.active()) {
-    typename Ops::acc_t yr, yi;
-    op.apply(S, xs, yr, yi);
+  auto load = [&](int t, Set& S) {
+    const long long blk = a + (t < len ? t : len - 1);
+    op.load_ops(Dm, blk, S.dr, S.di);
+    op.load_ops(Gm, blk, S.gr, S.gi);
+    const double* bp = bvec + (long long)(v0 + op.col) * ld + 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + blk_lm[blk]));
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = op.row(q);
-      if (r < N) {
-        const F c = scl[(long long)blk * N + r];
-        W[((long long)blk * N + r) * g.wcap + v0 + op.col] = cpx<F>{c * yr[q], c * yi[q]};
+    for (int ks = 0; ks < KS; ++ks) {
+      const int r = 4 * ks + (op.l >> 4);
+      S.b[ks] = cpx<F>{0, 0};
+      if (r < N && op.col < nv) S.b[ks] = cpx<F>{(F)bp[2 * r], (F)bp[2 * r + 1]};
+    }
+  };
+  Set S0, S1;
+  if (op.active()) load(0, S0);
+  __syncthreads();
+  auto body = [&](int t, Set& cur, Set& nxt, int pb) {
+    if (op.active()) {
+      load(t + 1, nxt);
+      __builtin_amdgcn_sched_barrier(0);
+      typename Ops::acc_t p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+      op.acc_reg(cur.dr, cur.di, cur.b, p1, p2, p3);
+      if (t > 0) op.acc_lds(cur.gr, cur.gi, xb + pb * 64 * kVG, (F)-1, p1, p2, p3);
+      cpx<F>* xo = xb + (pb ^ 1) * 64 * kVG;
+      const long long blk = a + t;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = op.row(q);
+        if (r < N) {
+          const cpx<F> y = {p1[q] - p2[q], p3[q] - p1[q] - p2[q]};
+          xo[r * kVG + op.col] = y;
+          W[(blk * N + r) * g.wcap + v0 + op.col] = y;
+        }
       }
     }
+    __syncthreads();
+  };
+  int pb = 0;
+  for (int t = 0; t < len; t += 2) {
+    body(t, S0, S1, pb);
+    pb ^= 1;
+    if (t + 1 < len) {
+      body(t + 1, S1, S0, pb);
+      pb ^= 1;
+    }
   }
-}
-
-// Local forward recurrence per segment: zeta_a = c_a, zeta_i = c_i - G_i zeta_{i-1}.
-template <class F, int RT>
-__global__ void __launch_bounds__(kSolveThreads, 1) k_cs_fwd_local(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
-                                                                  const cpx<F>* __restrict__ Gm, cpx<F>* __restrict__ W) {
-  __shared__ cpx<F> xb[2 * 64 * kVG];
-  const SegMeta sg = segs[blockIdx.x];
-  if (sg.len <= 1) return;
-  const int a = sg.first_block;
-  chain_walk<F, RT>(g.N, g.wcap, Gm, W, blockIdx.y * kVG, sg.len - 1, [&](int t) { return (long long)(a + t); },
-                    (F)-1, xb);
 }
 
 // Boundary pass of the forward recurrence: z_e(p) = zeta_e(p) + Phi_e(p) z_e(p-1).
@@ -1908,16 +1964,76 @@ __global__ void __launch_bounds__(kSolveThreads, 1) k_cs_fwd_bound(DevGrid g, in
                     [&](int p) { return (long long)(st + min((p + 1) * seg, n) - 1); }, (F)1, xb);
 }
 
-// Local backward recurrence per segment: xi_e = z_e, xi_i = z_i - H_i xi_{i+1}.
+// Backward pass of one segment [a, e] with the forward fix-up: the forward values of a segment
+// p > 0 are completed on the way, z_i = zeta_i + Phi_i z_{a-1} (z_{a-1}, the previous segment's
+// last value, and z_e are final after the forward boundary pass), and the local backward
+// recurrence xi_e = z_e, xi_i = z_i - H_i xi_{i+1} runs from e down to a, stored in W.  Each
+// step sums both products in one set of Gauss sums; z_{a-1} is held in registers in the
+// B-operand layout, and the operands of step t+1 load while step t multiplies.
 template <class F, int RT>
-__global__ void __launch_bounds__(kSolveThreads, 1) k_cs_bwd_local(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
-                                                                  const cpx<F>* __restrict__ H, cpx<F>* __restrict__ W) {
+__global__ void __launch_bounds__(kSolveThreads, 1) k_cs_bwd_fix(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
+                                                                const cpx<F>* __restrict__ Phi,
+                                                                const cpx<F>* __restrict__ H, cpx<F>* __restrict__ W) {
   __shared__ cpx<F> xb[2 * 64 * kVG];
+  typedef ChainOps<F, RT> Ops;
+  constexpr int KS = Ops::KS;
   const SegMeta sg = segs[blockIdx.x];
   if (sg.len <= 1) return;
-  const int e = sg.first_block + sg.len - 1;
-  chain_walk<F, RT>(g.N, g.wcap, H, W, blockIdx.y * kVG, sg.len - 1, [&](int t) { return (long long)(e - t); },
-                    (F)-1, xb);
+  const int N = g.N, a = sg.first_block, len = sg.len, e = a + len - 1, v0 = blockIdx.y * kVG;
+  const bool fix = sg.pidx > 0;
+  Ops op(N, g.wcap);
+  stage_x<F>(W, N, g.wcap, e, v0, xb, xb + 64 * kVG);
+  cpx<F> zs[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int r = 4 * ks + (op.l >> 4);
+    zs[ks] = cpx<F>{0, 0};
+    if (fix && r < N) zs[ks] = W[((long long)(a - 1) * N + r) * g.wcap + v0 + op.col];
+  }
+  struct Set {
+    F hr[KS], hi[KS], pr[KS], pi[KS];
+    cpx<F> w[4];
+  };
+  auto load = [&](int t, Set& S) {
+    const long long blk = e - (t < len ? t : len - 1);
+    op.load_ops(H, blk, S.hr, S.hi);
+    if (fix) op.load_ops(Phi, blk, S.pr, S.pi);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) S.w[q] = W[(blk * N + op.rowc[q]) * g.wcap + v0 + op.col];
+  };
+  Set S0, S1;
+  if (op.active()) load(1, S0);
+  __syncthreads();
+  auto body = [&](int t, Set& cur, Set& nxt, int pb) {
+    if (op.active()) {
+      load(t + 1, nxt);
+      __builtin_amdgcn_sched_barrier(0);
+      typename Ops::acc_t p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+      if (fix) op.acc_reg(cur.pr, cur.pi, zs, p1, p2, p3);
+      op.acc_lds(cur.hr, cur.hi, xb + pb * 64 * kVG, (F)-1, p1, p2, p3);
+      cpx<F>* xo = xb + (pb ^ 1) * 64 * kVG;
+      const long long blk = e - t;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = op.row(q);
+        if (r < N) {
+          const cpx<F> y = {cur.w[q].re + p1[q] - p2[q], cur.w[q].im + p3[q] - p1[q] - p2[q]};
+          xo[r * kVG + op.col] = y;
+          W[(blk * N + r) * g.wcap + v0 + op.col] = y;
+        }
+      }
+    }
+    __syncthreads();
+  };
+  int pb = 0;
+  for (int t = 1; t < len; t += 2) {
+    body(t, S0, S1, pb);
+    pb ^= 1;
+    if (t + 1 < len) {
+      body(t + 1, S1, S0, pb);
+      pb ^= 1;
+    }
+  }
 }
 
 // Boundary pass of the backward recurrence: x_a(p) = xi_a(p) + Psi_a(p) x_a(p+1).
@@ -1931,35 +2047,6 @@ __global__ void __launch_bounds__(kSolveThreads, 1) k_cs_bwd_bound(DevGrid g, in
   const int st = ch.start, last = ch.nseg - 1;
   chain_walk<F, RT>(g.N, g.wcap, Psi, W, blockIdx.y * kVG, ch.nseg - 1,
                     [&](int t) { return (long long)(st + (last - t) * seg); }, (F)1, xb);
-}
-
-// One fix-up step for every block with src[b] >= 0: W[b] = W[b] + M_b W[src[b]].
-template <class F, int RT>
-__global__ void __launch_bounds__(kSolveThreads) k_cs_fix(DevGrid g, int nvec, const int* __restrict__ src,
-                                                         const cpx<F>* __restrict__ M, cpx<F>* __restrict__ W) {
-  __shared__ cpx<F> xs[64 * kVG];
-  typedef ChainOps<F, RT> Ops;
-  const int blk = blockIdx.x;
-  const int sb = src[blk];
-  if (sb < 0) return;
-  const int N = g.N, v0 = blockIdx.y * kVG;
-  Ops op(N, g.wcap);
-  typename Ops::Set S;
-  if (op.active()) {
-    op.load_frag(M, blk, S);
-    op.load_w(W, blk, v0, S);
-  }
-  stage_x<F>(W, N, g.wcap, sb, v0, xs, nullptr);
-  __syncthreads();
-  if (op.active()) {
-    typename Ops::acc_t yr, yi;
-    op.apply(S, xs, yr, yi);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = op.row(q);
-      if (r < N) W[((long long)blk * N + r) * g.wcap + v0 + op.col] = cpx<F>{S.w[q].re + yr[q], S.w[q].im + yi[q]};
-    }
-  }
 }
 
 // x_i = xi_i + Psi_i x_{a(p+1)} for the blocks not yet final, then x = Cg x~ into the
