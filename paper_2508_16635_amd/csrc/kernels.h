@@ -1452,19 +1452,63 @@ __global__ void __launch_bounds__(ring_reg_threads(RR)) k_ring_reg(DevGrid g, in
   }
   if (MODE == RING_SYNTH) return;
   __syncthreads();
-  // forward transforms of slots 0 and 1: thread (o, r); split the packed pair, scale by
-  // (2 - delta_k0)/N_phi and write the analysis inputs
-  if (tid < 2 * RR) {
-    const int o = tid / RR, r = tid % RR, th = th0 + r;
-    cz<T> z[N];
-    const cz<T>* xi = X + (o * RR + r) * LS;
+  // forward transforms of slots 0 and 1, spread over the eight threads (j, r) of every ring as
+  // a four-step FFT through LDS: the 2 N2 column DFTs of length N1 (inputs n = N2 n1 + n2),
+  // written to slot 2 + o at N2 k1 + n2; then the 2 N1 row DFTs of length N2, their inputs
+  // twiddled by w^(n2 k1), output k = k1 + N1 k2 written to slot o at k; then the 2 KM
+  // harmonics (o, k): split the packed pair, scale by (2 - delta_k0)/N_phi and write the
+  // analysis inputs.  Slots 2..4 are free after the products.
+  {
+    const int r = tid % RR, j = tid / RR, th = th0 + r;
 #pragma unroll
-    for (int p = 0; p < N; ++p) z[p] = xi[p];
-    fft_reg<T, N1, N2, -1>(z, fw);
+    for (int i = 0; i < (2 * N2 + 7) / 8; ++i) {
+      const int c = j + 8 * i;
+      if (c < 2 * N2) {
+        const int o = c / N2, n2 = c - o * N2;
+        const cz<T>* xi = X + (o * RR + r) * LS + n2;
+        cz<T> v[N1];
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) v[n1] = xi[N2 * n1];
+        small_dft<T, N1>(v, (T)-1);
+        cz<T>* xo = X + ((2 + o) * RR + r) * LS + n2;
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) xo[N2 * k1] = v[k1];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < (2 * N1 + 7) / 8; ++i) {
+      const int c = j + 8 * i;
+      if (c < 2 * N1) {
+        const int o = c / N1, k1 = c - o * N1;
+        const cz<T>* xi = X + ((2 + o) * RR + r) * LS + N2 * k1;
+        cz<T> u[N2];
+        T tc[N2], ts[N2];
+#pragma unroll
+        for (int n2 = 1; n2 < N2; ++n2) {
+          const int e = (n2 * k1) % N;   // fw[2e], fw[2e+1] = cos, -sin(2 pi e / N)
+          tc[n2] = fw[2 * e];
+          ts[n2] = fw[2 * e + 1];
+        }
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) u[n2] = xi[n2];
+#pragma unroll
+        for (int n2 = 1; n2 < N2; ++n2) {
+          const cz<T> a = u[n2];
+          u[n2] = {a.re * tc[n2] - a.im * ts[n2], a.re * ts[n2] + a.im * tc[n2]};
+        }
+        small_dft<T, N2>(u, (T)-1);
+        cz<T>* xo = X + (o * RR + r) * LS + k1;
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) xo[N1 * k2] = u[k2];
+      }
+    }
+    __syncthreads();
     if (th < nth) {
+      constexpr int KM = (N - 1) / 3 + 1;
       const int vr = vq * Np + rp;  // row (vec, r_p) of the analysis inputs
       // buffer stores from Fs (Fv follows it; 3 (K+1) 4 N_p vcap N_theta values in all): per
-      // lane the byte offset of its first output row, per (harmonic, row) a wave-uniform offset
+      // lane the byte offset of its output row and harmonic, per row a wave-uniform offset
       const unsigned Ma = 4u * Np * g.vcap, ns = (unsigned)nth * szT;
       const __amdgpu_buffer_rsrc_t rf =
           __builtin_amdgcn_make_buffer_rsrc((void*)Fs, (short)0, (int)(3u * K1 * Ma * ns), kBufferDword3);
@@ -1473,38 +1517,38 @@ __global__ void __launch_bounds__(ring_reg_threads(RR)) k_ring_reg(DevGrid g, in
       const unsigned dS = Ma * ns, dV = 2 * Ma * ns;
       auto st = [&](unsigned vo, unsigned so, T x) { buffer_store1<T>(x, rf, vo, so); };
 #pragma unroll
-      for (int k = 0; k < (N - 1) / 3 + 1; ++k) {
-        if (k >= K1) continue;
-        const T sc = (k == 0 ? (T)1 : (T)2) / (T)N;
+      for (int i = 0; i < (2 * KM + 7) / 8; ++i) {
+        const int c = j + 8 * i, o = c / KM, k = c - o * KM;
+        if (c >= 2 * KM || k >= K1) continue;
+        const cz<T>* z = X + (o * RR + r) * LS;
+        const cz<T> zk = z[k], zm = z[k == 0 ? 0 : N - k];
+        const T sc = (T)1 / (T)N;   // (2 - delta_k0)/N_phi with the 1/2 of the unpacking
         T ar, ai, br, bi;
         if (k == 0) {
-          const cz<T> z0 = z[fft_pos<N1, N2>(0)];
-          ar = z0.re; ai = 0; br = z0.im; bi = 0;
+          ar = zk.re * sc; ai = 0; br = zk.im * sc; bi = 0;
         } else {
-          const cz<T> zk = z[fft_pos<N1, N2>(k)], zm = z[fft_pos<N1, N2>(N - k)];
-          ar = (T)0.5 * (zk.re + zm.re);
-          ai = (T)0.5 * (zk.im - zm.im);
-          br = (T)0.5 * (zk.im + zm.im);
-          bi = (T)0.5 * (zm.re - zk.re);
+          ar = (zk.re + zm.re) * sc;
+          ai = (zk.im - zm.im) * sc;
+          br = (zk.im + zm.im) * sc;
+          bi = (zm.re - zk.re) * sc;
         }
-        ar *= sc; ai *= sc; br *= sc; bi *= sc;
         if (o == 0) {  // (W_r, Q)
-          const unsigned so = k * dS;
-          st(vsb, so, ar);
-          st(vsb, so + ns, ai);
-          st(vsb, so + 2 * ns, br);
-          st(vsb, so + 3 * ns, bi);
+          const unsigned vo = vsb + k * dS;
+          st(vo, 0, ar);
+          st(vo, ns, ai);
+          st(vo, 2 * ns, br);
+          st(vo, 3 * ns, bi);
         } else {       // (W_th, W_ph): dP rows (W_th, -W_ph); mPs rows (-i W_ph, -i W_th)
-          const unsigned so = k * dV;
-          st(vvb, so, ar);
-          st(vvb, so + 2 * ns, ai);
-          st(vvb, so + 4 * ns, -br);
-          st(vvb, so + 6 * ns, -bi);
+          const unsigned vo = vvb + k * dV;
+          st(vo, 0, ar);
+          st(vo, 2 * ns, ai);
+          st(vo, 4 * ns, -br);
+          st(vo, 6 * ns, -bi);
           if (!g.fv_dp_only) {
-            st(vvb, so + ns, bi);
-            st(vvb, so + 3 * ns, -br);
-            st(vvb, so + 5 * ns, ai);
-            st(vvb, so + 7 * ns, -ar);
+            st(vo, ns, bi);
+            st(vo, 3 * ns, -br);
+            st(vo, 5 * ns, ai);
+            st(vo, 7 * ns, -ar);
           }
         }
       }
