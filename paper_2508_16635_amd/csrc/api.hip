@@ -752,15 +752,31 @@ void chain_solve_rt(sc_plan* P, int nvec, const double* b, double* x, const sc::
   const sc::ChainMeta* ch = P->chains.as<sc::ChainMeta>();
   const sc::SegMeta* sg = P->segs.as<sc::SegMeta>();
   const dim3 blk(sc::kSolveThreads);
-  hipLaunchKernelGGL((sc::k_cs_fwd_rhs<F, RT>), dim3(P->nsegs, nvg), blk, 0, s, dg, nvec, sg, P->blk_field.as<int>(),
-                     P->blk_lm.as<int>(), Dm, Gm, b, W);
-  HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL((sc::k_cs_fwd_bound<F, RT>), dim3(P->nchains, nvg), blk, 0, s, dg, nvec, ch, kSeg, Phi, W);
-  HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL((sc::k_cs_bwd_fix<F, RT>), dim3(P->nsegs, nvg), blk, 0, s, dg, nvec, sg, Phi, H, W);
-  HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL((sc::k_cs_bwd_bound<F, RT>), dim3(P->nchains, nvg), blk, 0, s, dg, nvec, ch, kSeg, Psi, W);
-  HIPCHK(hipGetLastError());
+  if (nvec == 1) {
+    // one right-hand side: the walks on the vector units with deeper operand prefetch (a
+    // 16-column matrix-core step would carry 15 columns of padding)
+    hipLaunchKernelGGL((sc::k_cs1_fwd_rhs<F, RT>), dim3(P->nsegs), blk, 0, s, dg, sg, P->blk_field.as<int>(),
+                       P->blk_lm.as<int>(), Dm, Gm, b, W);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL((sc::k_cs1_fwd_bound<F, RT>), dim3(P->nchains), blk, 0, s, dg, ch, kSeg, Phi, W);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL((sc::k_cs1_bwd_fix<F, RT>), dim3(P->nsegs), blk, 0, s, dg, sg, Phi, H, W);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL((sc::k_cs1_bwd_bound<F, RT>), dim3(P->nchains), blk, 0, s, dg, ch, kSeg, Psi, W);
+    HIPCHK(hipGetLastError());
+  } else {
+    hipLaunchKernelGGL((sc::k_cs_fwd_rhs<F, RT>), dim3(P->nsegs, nvg), blk, 0, s, dg, nvec, sg, P->blk_field.as<int>(),
+                       P->blk_lm.as<int>(), Dm, Gm, b, W);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL((sc::k_cs_fwd_bound<F, RT>), dim3(P->nchains, nvg), blk, 0, s, dg, nvec, ch, kSeg, Phi, W);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL((sc::k_cs_bwd_fix<F, RT>), dim3(P->nsegs, nvg), blk, 0, s, dg, nvec, sg, Phi, H, W);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL((sc::k_cs_bwd_bound<F, RT>), dim3(P->nchains, nvg), blk, 0, s, dg, nvec, ch, kSeg, Psi, W);
+    HIPCHK(hipGetLastError());
+  }
+  // the output kernel's product columns are independent: at nvec = 1 the columns 1..15 of W
+  // (not written by the one-vector walks) only reach output columns that are not stored
   hipLaunchKernelGGL((sc::k_cs_out<F, RT, ACC, FIN>), dim3(P->nblocks, nvg), blk, 0, s, dg, nvec,
                      P->blk_field.as<int>(), P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const C*)W, x, fo);
   HIPCHK(hipGetLastError());

@@ -1995,6 +1995,261 @@ __global__ void __launch_bounds__(kSolveThreads, 1) k_cs_fwd_rhs(DevGrid g, int 
   }
 }
 
+// Block products for one right-hand side (nvec = 1) on the vector units.  A 16-column
+// matrix-core product would spend 15 of its columns on padding, and a walk step would wait on
+// it.  Lane l of wave w (w < RT) holds the operands it would feed to the matrix cores,
+// M[16 w + l%16][4 s + l/16] for the k-steps s, forms that row's partial sum over the columns
+// = l/16 (mod 4), and the four partial sums of a row meet by lane exchanges (rowsum4).  Waves
+// beyond the row tiles load the last tile's operands and write nothing, and no load sits under
+// a branch: the compiler then keeps every register set of a prefetch ring in place and waits
+// only for the set in use (a conditional load is copied into the ring and waited for at once).
+template <class F, int RT>
+struct Lane1 {
+  static constexpr int KS = 4 * RT, FB = 256 * RT * RT;
+  int w, l, c0, row, rowc;
+  bool writer;
+  __device__ Lane1(int N) {
+    w = min((int)(threadIdx.x >> 6), RT - 1);
+    l = threadIdx.x & 63;
+    c0 = l >> 4;
+    row = 16 * w + (l & 15);
+    rowc = row < N ? row : N - 1;
+    writer = (int)(threadIdx.x >> 6) < RT && c0 == 0 && row < N;
+  }
+  __device__ inline void load(const cpx<F>* __restrict__ frags, long long blk, F (&ar)[KS], F (&ai)[KS]) const {
+    const cpx<F>* p = frags + blk * FB + (long long)w * KS * 64 + l;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const cpx<F> v = p[ks * 64];
+      ar[ks] = v.re;
+      ai[ks] = v.im;
+    }
+  }
+  // (re, im) += sgn * row part of M x, x in LDS (64 entries)
+  __device__ inline void dot_lds(const F (&ar)[KS], const F (&ai)[KS], const cpx<F>* x, F sgn, F& re, F& im) const {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const cpx<F> xv = x[4 * ks + c0];
+      const F xr = sgn * xv.re, xi = sgn * xv.im;
+      re += ar[ks] * xr - ai[ks] * xi;
+      im += ar[ks] * xi + ai[ks] * xr;
+    }
+  }
+  // (re, im) += row part of M x, x in registers (xv[ks] = x[4 ks + l/16])
+  __device__ inline void dot_reg(const F (&ar)[KS], const F (&ai)[KS], const cpx<F> (&xv)[KS], F& re, F& im) const {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      re += ar[ks] * xv[ks].re - ai[ks] * xv[ks].im;
+      im += ar[ks] * xv[ks].im + ai[ks] * xv[ks].re;
+    }
+  }
+  __device__ static inline void rowsum4(F& re, F& im) {
+    re += __shfl_xor(re, 16);
+    im += __shfl_xor(im, 16);
+    re += __shfl_xor(re, 32);
+    im += __shfl_xor(im, 32);
+  }
+};
+
+// Sequential walk for one right-hand side: x_0 = W[blk(0)], then W[blk(t)] = W[blk(t)] +
+// sign M_{blk(t)} x_{t-1}, x_t = that result, for t = 1..nsteps.  The operands of PD steps are in
+// flight (a ring of register sets); steps past nsteps (padding to a multiple of PD) write
+// nothing.  x sits in LDS (64 entries, rows >= N zero).
+template <class F, int RT, int PD, class BlockOf>
+__device__ inline void chain_walk1(int N, int wcap, const cpx<F>* __restrict__ frags, cpx<F>* __restrict__ W,
+                                   int nsteps, BlockOf blk_of, F sign, cpx<F>* xbuf) {
+  typedef Lane1<F, RT> Ln;
+  constexpr int KS = Ln::KS;
+  const Ln ln(N);
+  struct Set {
+    F ar[KS], ai[KS];
+    cpx<F> wv;
+  };
+  {
+    const long long b0 = blk_of(0);
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+      const cpx<F> v = i < N ? W[(b0 * N + i) * wcap] : cpx<F>{0, 0};
+      xbuf[i] = v;
+      xbuf[64 + i] = cpx<F>{0, 0};
+    }
+  }
+  auto load = [&](int t, Set& S) {
+    const long long b = blk_of(t < nsteps ? t : nsteps);
+    ln.load(frags, b, S.ar, S.ai);
+    S.wv = W[(b * N + ln.rowc) * wcap];
+  };
+  Set S[PD];
+#pragma unroll
+  for (int d = 0; d < PD; ++d) load(1 + d, S[d]);
+  __syncthreads();
+  int pb = 0;
+  auto body = [&](int t, Set& cur) {
+    F re = 0, im = 0;
+    ln.dot_lds(cur.ar, cur.ai, xbuf + pb * 64, sign, re, im);
+    Ln::rowsum4(re, im);
+    if (ln.writer && t <= nsteps) {
+      const cpx<F> y = {cur.wv.re + re, cur.wv.im + im};
+      xbuf[(pb ^ 1) * 64 + ln.row] = y;
+      W[((long long)blk_of(t) * N + ln.row) * wcap] = y;
+    }
+    load(t + PD, cur);
+    __syncthreads();
+    pb ^= 1;
+  };
+  for (int t = 1; t <= nsteps; t += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) body(t + d, S[d]);
+  }
+}
+
+// Boundary passes for one right-hand side (see chain_walk1).
+constexpr int kWalk1Depth = 3;
+template <class F, int RT>
+__global__ void __launch_bounds__(kSolveThreads, 1) k_cs1_fwd_bound(DevGrid g, const ChainMeta* __restrict__ chains,
+                                                                   int seg, const cpx<F>* __restrict__ Phi,
+                                                                   cpx<F>* __restrict__ W) {
+  __shared__ cpx<F> xb[2 * 64];
+  const ChainMeta ch = chains[blockIdx.x];
+  if (ch.nseg <= 1) return;
+  const int st = ch.start, n = ch.n;
+  chain_walk1<F, RT, kWalk1Depth>(g.N, g.wcap, Phi, W, ch.nseg - 1,
+                                  [&](int p) { return (long long)(st + min((p + 1) * seg, n) - 1); }, (F)1, xb);
+}
+
+template <class F, int RT>
+__global__ void __launch_bounds__(kSolveThreads, 1) k_cs1_bwd_bound(DevGrid g, const ChainMeta* __restrict__ chains,
+                                                                   int seg, const cpx<F>* __restrict__ Psi,
+                                                                   cpx<F>* __restrict__ W) {
+  __shared__ cpx<F> xb[2 * 64];
+  const ChainMeta ch = chains[blockIdx.x];
+  if (ch.nseg <= 1) return;
+  const int st = ch.start, last = ch.nseg - 1;
+  chain_walk1<F, RT, kWalk1Depth>(g.N, g.wcap, Psi, W, ch.nseg - 1,
+                                  [&](int t) { return (long long)(st + (last - t) * seg); }, (F)1, xb);
+}
+
+// Local walks for one right-hand side (as k_cs_fwd_rhs and k_cs_bwd_fix, on the vector units;
+// see Lane1).  The operands of kLocal1Depth steps are in flight; the step before the first one
+// multiplies a zero buffer instead of branching around its product.
+constexpr int kLocal1Depth = 2;
+template <class F, int RT>
+__global__ void __launch_bounds__(kSolveThreads, 1) k_cs1_fwd_rhs(DevGrid g, const SegMeta* __restrict__ segs,
+                                                                 const int* __restrict__ blk_field,
+                                                                 const int* __restrict__ blk_lm,
+                                                                 const cpx<F>* __restrict__ Dm,
+                                                                 const cpx<F>* __restrict__ Gm,
+                                                                 const double* __restrict__ bvec,
+                                                                 cpx<F>* __restrict__ W) {
+  typedef Lane1<F, RT> Ln;
+  constexpr int KS = Ln::KS, PD = kLocal1Depth;
+  __shared__ cpx<F> xb[2 * 64];
+  const SegMeta sg = segs[blockIdx.x];
+  const int N = g.N, a = sg.first_block, len = sg.len, wcap = g.wcap;
+  const Ln ln(N);
+  for (int i = threadIdx.x; i < 2 * 64; i += blockDim.x) xb[i] = cpx<F>{0, 0};
+  struct Set {
+    F dr[KS], di[KS], gr[KS], gi[KS];
+    cpx<F> b[KS];
+  };
+  auto load = [&](int t, Set& S) {
+    const long long blk = a + (t < len ? t : len - 1);
+    ln.load(Dm, blk, S.dr, S.di);
+    ln.load(Gm, blk, S.gr, S.gi);
+    const double* bp = bvec + 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + blk_lm[blk]));
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int r = 4 * ks + ln.c0, rr = r < N ? r : N - 1;
+      const double br = bp[2 * rr], bi = bp[2 * rr + 1];
+      S.b[ks] = r < N ? cpx<F>{(F)br, (F)bi} : cpx<F>{0, 0};
+    }
+  };
+  Set S[PD];
+#pragma unroll
+  for (int d = 0; d < PD; ++d) load(d, S[d]);
+  __syncthreads();
+  int pb = 0;
+  auto body = [&](int t, Set& cur) {
+    F re = 0, im = 0;
+    ln.dot_reg(cur.dr, cur.di, cur.b, re, im);
+    ln.dot_lds(cur.gr, cur.gi, xb + pb * 64, (F)-1, re, im);
+    Ln::rowsum4(re, im);
+    if (ln.writer && t < len) {
+      const cpx<F> y = {re, im};
+      xb[(pb ^ 1) * 64 + ln.row] = y;
+      W[((long long)(a + t) * N + ln.row) * wcap] = y;
+    }
+    load(t + PD, cur);
+    __syncthreads();
+    pb ^= 1;
+  };
+  for (int t = 0; t < len; t += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) body(t + d, S[d]);
+  }
+}
+
+template <class F, int RT>
+__global__ void __launch_bounds__(kSolveThreads, 1) k_cs1_bwd_fix(DevGrid g, const SegMeta* __restrict__ segs,
+                                                                 const cpx<F>* __restrict__ Phi,
+                                                                 const cpx<F>* __restrict__ H, cpx<F>* __restrict__ W) {
+  typedef Lane1<F, RT> Ln;
+  constexpr int KS = Ln::KS, PD = kLocal1Depth;
+  __shared__ cpx<F> xb[2 * 64];
+  const SegMeta sg = segs[blockIdx.x];
+  if (sg.len <= 1) return;
+  const int N = g.N, a = sg.first_block, len = sg.len, e = a + len - 1, wcap = g.wcap;
+  const bool fix = sg.pidx > 0;
+  const Ln ln(N);
+  for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+    xb[i] = i < N ? W[((long long)e * N + i) * wcap] : cpx<F>{0, 0};
+    xb[64 + i] = cpx<F>{0, 0};
+  }
+  // z_{a-1} in the B-operand layout (zero in the first segment)
+  cpx<F> zs[KS];
+  {
+    const long long bz = fix ? a - 1 : a;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int r = 4 * ks + ln.c0, rr = r < N ? r : N - 1;
+      const cpx<F> v = W[(bz * N + rr) * wcap];
+      zs[ks] = (fix && r < N) ? v : cpx<F>{0, 0};
+    }
+  }
+  struct Set {
+    F hr[KS], hi[KS], pr[KS], pi[KS];
+    cpx<F> wv;
+  };
+  auto load = [&](int t, Set& S) {
+    const long long blk = e - (t < len ? t : len - 1);
+    ln.load(H, blk, S.hr, S.hi);
+    ln.load(Phi, blk, S.pr, S.pi);
+    S.wv = W[(blk * N + ln.rowc) * wcap];
+  };
+  Set S[PD];
+#pragma unroll
+  for (int d = 0; d < PD; ++d) load(1 + d, S[d]);
+  __syncthreads();
+  int pb = 0;
+  auto body = [&](int t, Set& cur) {
+    F re = 0, im = 0;
+    ln.dot_reg(cur.pr, cur.pi, zs, re, im);
+    ln.dot_lds(cur.hr, cur.hi, xb + pb * 64, (F)-1, re, im);
+    Ln::rowsum4(re, im);
+    if (ln.writer && t < len) {
+      const cpx<F> y = {cur.wv.re + re, cur.wv.im + im};
+      xb[(pb ^ 1) * 64 + ln.row] = y;
+      W[((long long)(e - t) * N + ln.row) * wcap] = y;
+    }
+    load(t + PD, cur);
+    __syncthreads();
+    pb ^= 1;
+  };
+  for (int t = 1; t < len; t += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) body(t + d, S[d]);
+  }
+}
+
 // Boundary pass of the forward recurrence: z_e(p) = zeta_e(p) + Phi_e(p) z_e(p-1).
 template <class F, int RT>
 __global__ void __launch_bounds__(kSolveThreads, 1) k_cs_fwd_bound(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
