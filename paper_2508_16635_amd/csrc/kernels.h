@@ -448,7 +448,12 @@ __global__ void __launch_bounds__(256) k_synth(const SynProb* __restrict__ probs
         ce[i][j][q] = (T)0;
         co[i][j][q] = (T)0;
       }
-  // one pipelined pass over a part: A k-steps [k0, k0 + n), tables B
+  // one pipelined pass over a part: A k-steps [k0, k0 + n), tables B.  The loop takes the
+  // k-steps in pairs with no branch on the k-step inside (a load used only in a conditional
+  // block is sunk into it, behind the products it should overlap, and a select on a loaded value
+  // waits for it); an odd last k-step runs after the loop.  In FP32 the column tiles beyond ncol
+  // multiply clamped table operands into sums that are never stored (cheaper than the branch,
+  // measured); in FP64, where a product costs twice as much, they are skipped.
   auto pass = [&](int k0, int n, const T* const* B, acc_t (&acc)[kSynTM][kSynTN]) {
     if (n <= 0) return;
     T a0[kSynTM], b0[kSynTN], a1[kSynTM], b1[kSynTN];
@@ -462,22 +467,22 @@ __global__ void __launch_bounds__(256) k_synth(const SynProb* __restrict__ probs
     auto run = [&](const T* a, const T* b) {
 #pragma unroll
       for (int j = 0; j < kSynTN; ++j)
-        if (j < ncol) {
+        if (sizeof(T) == 4 || j < ncol) {
 #pragma unroll
           for (int i = 0; i < kSynTM; ++i) acc[i][j] = Mfma<T>::step(a[i], b[j], acc[i][j]);
         }
     };
     load(0, a0, b0);
-    for (int st = 0; st < n; st += 2) {
+    int st = 0;
+    for (; st + 1 < n; st += 2) {
       load(st + 1, a1, b1);
       __builtin_amdgcn_sched_barrier(0);
       run(a0, b0);
-      if (st + 1 < n) {
-        load(st + 2, a0, b0);
-        __builtin_amdgcn_sched_barrier(0);
-        run(a1, b1);
-      }
+      load(st + 2, a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      run(a1, b1);
     }
+    if (st < n) run(a0, b0);
   };
   pass(0, pr.kse, Be, ce);
   pass(pr.kse, pr.kso, Bo, co);
@@ -681,14 +686,17 @@ __global__ void __launch_bounds__(256) k_anal(const AnaProb* __restrict__ probs,
       const T asg = (derived && (q4 == 0 || q4 == 3)) ? (T)-1 : (T)1;
       const T* Bb = tab + pr.t_off + (long long)(part * (pr.cte + pr.cto) + (par ? pr.cte : 0)) * KSa * 64 + l;
       // operands of PD k-steps are in flight: slot u holds k-step s + u while it is multiplied
-      // and is then refilled with k-step s + u + PD
+      // and is then refilled with k-step s + u + PD.  Nothing touches a table operand between
+      // its load and its product, and no product sits under a branch (either makes the compiler
+      // wait for every load in flight): the sign and the zero of a padded k-step past KSa are
+      // applied to the LDS operand at its use.
       constexpr int PD = sizeof(T) == 4 ? 2 : 4;
       with_count<CT>(nct, [&](auto ncc) {
         constexpr int NC = decltype(ncc)::value;
         T aq[PD], bq[PD][NC];
         auto load = [&](int s, T& a, T (&b)[NC]) {
           s = s < KSa ? s : KSa - 1;
-          a = asg * Ab[4 * s];
+          a = Ab[4 * s];
 #pragma unroll
           for (int c = 0; c < NC; ++c) b[c] = Bb[((long long)c * KSa + s) * 64];
         };
@@ -698,10 +706,9 @@ __global__ void __launch_bounds__(256) k_anal(const AnaProb* __restrict__ probs,
 #pragma unroll
           for (int u = 0; u < PD; ++u) {
             __builtin_amdgcn_sched_barrier(0);
-            if (s + u < KSa) {
+            const T a = (s + u < KSa) ? asg * aq[u] : (T)0;
 #pragma unroll
-              for (int c = 0; c < NC; ++c) acc[c] = Mfma<T>::step(aq[u], bq[u][c], acc[c]);
-            }
+            for (int c = 0; c < NC; ++c) acc[c] = Mfma<T>::step(a, bq[u][c], acc[c]);
             load(s + u + PD, aq[u], bq[u]);
           }
         }
