@@ -1256,9 +1256,13 @@ __device__ inline void fft_reg(cz<T> (&x)[N1 * N2], const T* __restrict__ fw) {
 template <class T, int N>
 __device__ inline void ring_spectrum(cz<T> (&z)[N], const T* g, int rs, int ks, int K1, int q) {
   constexpr int KM = (N - 1) / 3 + 1;   // K1 <= KM (N_phi >= 3K + 1)
-  const int fa = 2 * q, fb = 2 * q + 1;
-  const T* a = g + kRingFieldRow[fa] * rs;
-  const T* b = g + kRingFieldRow[fb] * rs;
+  const int fb = 2 * q + 1;
+  // kRingFieldRow[2q] and [2q+1] by selects: a lookup in the table would be a memory load, and
+  // waiting for it would wait for every load issued before it (the base fields in flight)
+  const int ra = q == 0 ? 0 : q == 1 ? 8 : q == 2 ? 10 : q == 3 ? 4 : 16;
+  const int rb = q == 0 ? 6 : q == 1 ? 2 : q == 2 ? 12 : q == 3 ? 14 : 0;
+  const T* a = g + ra * rs;
+  const T* b = g + rb * rs;
   const T bon = fb == 9 ? (T)0 : (T)1;
 #pragma unroll
   for (int k = 0; k < KM; ++k) {
@@ -1347,10 +1351,12 @@ __global__ void __launch_bounds__(ring_reg_threads(RR)) k_ring_reg(DevGrid g, in
   // in 2^31 bytes): one add per load instead of 64-bit address arithmetic, and a load past a
   // resource returns zero.
   const unsigned szT = sizeof(T);
-  // base fields of this thread's product points, loaded first so they arrive during the FFTs;
-  // points of rings beyond the last node read that node (their results are never written)
+  // base fields of this thread's product points; points of rings beyond the last node read that
+  // node (their results are never written).  They are loaded right after the sums: the memory
+  // counter completes in issue order, so loads issued before the sums would be waited for with
+  // them, while loads issued after them stay in flight through the FFTs
   T bpre[NPT][9];
-  if (MODE == RING_LINEAR) {
+  auto load_base = [&] {
     const __amdgpu_buffer_rsrc_t rb =
         __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(9u * N * nth * Np * szT), kBufferDword3);
     const unsigned qs = (unsigned)N * nth * szT;   // byte stride of the nine fields
@@ -1361,7 +1367,7 @@ __global__ void __launch_bounds__(ring_reg_threads(RR)) k_ring_reg(DevGrid g, in
 #pragma unroll
       for (int q = 0; q < 9; ++q) bpre[u][q] = buffer_load1<T>(rb, vo, q * qs);
     }
-  }
+  };
   // copy of the sums of this workgroup's rings into LDS, [18 rows][K1][RR rings]: every (row, k)
   // is a run of RR consecutive theta, read as 8-byte pieces (nth and th0 are even, so a piece
   // lies wholly inside or wholly beyond the last node).  Thread (group, piece) owns rows group,
@@ -1391,6 +1397,11 @@ __global__ void __launch_bounds__(ring_reg_threads(RR)) k_ring_reg(DevGrid g, in
       const unsigned kst = row < 6 ? kS : kV;
 #pragma unroll
       for (int k = 0; k < KM; ++k, o += kst) val[i][k] = buffer_load8<pT>(rs, o, 0);
+    }
+    if (MODE == RING_LINEAR) {
+      __builtin_amdgcn_sched_barrier(0);
+      load_base();
+      __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int i = 0; i < NRW; ++i) {
