@@ -191,17 +191,19 @@ __device__ inline void mfma_f64_products(const double* const (&Mp)[NPR], const T
       for (int p = 0; p < NPR; ++p) acc[p] = Mfma<double>::step(a[p][st], (double)Xp[p][row * ldx], acc[p]);
     }
   };
+  // k blocks in pairs with no branch inside (a load used only in a conditional block is sunk
+  // into it, behind the products it should overlap); an odd last block runs after the loop
   load(0, a0);
-  for (int kb = 0; kb < KB; kb += 2) {
+  int kb = 0;
+  for (; kb + 1 < KB; kb += 2) {
     load(kb + 1, a1);
     __builtin_amdgcn_sched_barrier(0);
     run(kb, a0);
-    if (kb + 1 < KB) {
-      load(kb + 2, a0);
-      __builtin_amdgcn_sched_barrier(0);
-      run(kb + 1, a1);
-    }
+    load(kb + 2, a0);
+    __builtin_amdgcn_sched_barrier(0);
+    run(kb + 1, a1);
   }
+  if (kb < KB) run(kb, a0);
 }
 
 // ------------------------------------------------------------------------------------------
