@@ -775,10 +775,13 @@ void chain_solve_rt(sc_plan* P, int nvec, const double* b, double* x, const sc::
     hipLaunchKernelGGL((sc::k_cs_bwd_bound<F, RT>), dim3(P->nchains, nvg), blk, 0, s, dg, nvec, ch, kSeg, Psi, W);
     HIPCHK(hipGetLastError());
   }
-  // the output kernel's product columns are independent: at nvec = 1 the columns 1..15 of W
-  // (not written by the one-vector walks) only reach output columns that are not stored
-  hipLaunchKernelGGL((sc::k_cs_out<F, RT, ACC, FIN>), dim3(P->nblocks, nvg), blk, 0, s, dg, nvec,
-                     P->blk_field.as<int>(), P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const C*)W, x, fo);
+  if (nvec == 1)
+    hipLaunchKernelGGL((sc::k_cs1_out<F, RT, ACC, FIN>), dim3(P->nblocks), blk, 0, s, dg, P->blk_field.as<int>(),
+                       P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const C*)W, x, fo);
+  else
+    hipLaunchKernelGGL((sc::k_cs_out<F, RT, ACC, FIN>), dim3(P->nblocks, nvg), blk, 0, s, dg, nvec,
+                       P->blk_field.as<int>(), P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const C*)W, x,
+                       fo);
   HIPCHK(hipGetLastError());
 }
 

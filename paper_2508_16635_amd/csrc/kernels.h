@@ -2441,6 +2441,68 @@ __global__ void __launch_bounds__(kSolveThreads) k_cs_out(DevGrid g, int nvec, c
   }
 }
 
+// Backward fix-up and output for one right-hand side (as k_cs_out, on the vector units; see
+// Lane1): the 16-column kernel would also stage the 15 unused columns of W.  One workgroup per
+// block; the operands of the product, and x_{a(p+1)}, are read in the B-operand layout and
+// masked at their use.
+template <class F, int RT, bool ACC, bool FIN>
+__global__ void __launch_bounds__(kSolveThreads) k_cs1_out(DevGrid g, const int* __restrict__ blk_field,
+                                                          const int* __restrict__ blk_lm,
+                                                          const int* __restrict__ blk_next,
+                                                          const cpx<F>* __restrict__ Psi, const F* __restrict__ Cg,
+                                                          const cpx<F>* __restrict__ W, double* __restrict__ xvec,
+                                                          FinalOut fo) {
+  typedef Lane1<F, RT> Ln;
+  constexpr int KS = Ln::KS;
+  const int N = g.N, wcap = g.wcap, blk = blockIdx.x, nx = blk_next[blk];
+  const Ln ln(N);
+  F ar[KS], ai[KS];
+  ln.load(Psi, blk, ar, ai);
+  cpx<F> xv[KS];
+  {
+    const long long bx = nx >= 0 ? nx : blk;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int r = 4 * ks + ln.c0, rr = r < N ? r : N - 1;
+      xv[ks] = W[(bx * N + rr) * wcap];
+    }
+  }
+  const cpx<F> wv = W[((long long)blk * N + ln.rowc) * wcap];
+  const long long ld = 6LL * N * g.S;
+  const int lm = blk_lm[blk];
+  const long long oo = 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + lm)) + 2 * ln.rowc;
+  const double cq = (double)Cg[(long long)blk * N + ln.rowc];
+  double xa0 = 0.0, xa1 = 0.0, ua0 = 0.0, ua1 = 0.0;
+  if (ACC) {
+    xa0 = xvec[oo];
+    xa1 = xvec[oo + 1];
+  }
+  if (FIN) {
+    ua0 = fo.v[oo];
+    ua1 = fo.v[oo + 1];
+  }
+  F re = 0, im = 0;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const bool ok = nx >= 0 && 4 * ks + ln.c0 < N;
+    const F xr = ok ? xv[ks].re : (F)0, xi = ok ? xv[ks].im : (F)0;
+    re += ar[ks] * xr - ai[ks] * xi;
+    im += ar[ks] * xi + ai[ks] * xr;
+  }
+  Ln::rowsum4(re, im);
+  if (ln.writer) {
+    const double x0 = cq * (double)(wv.re + re) + xa0, x1 = cq * (double)(wv.im + im) + xa1;
+    if (FIN) {
+      const bool mzero = (g.lm_k[lm] == 0);
+      fo.y[oo] = x0 - (oo == fo.J ? 0.0 : ua0);
+      fo.y[oo + 1] = (mzero ? 0.0 : x1) - (oo + 1 == fo.J ? 0.0 : ua1);
+    } else {
+      xvec[oo] = x0;
+      xvec[oo + 1] = x1;
+    }
+  }
+}
+
 // Temperature blocks: x = tc * Tinv (tr * b) per l, for every (vec, k, l), both Re and Im
 // (ACC: added to x; FIN: y = clean(x) - u is written instead of x, and the workgroups of l = 0
 // also write y = -u on the e, f slots at l = 0, which no chain covers).  One workgroup per

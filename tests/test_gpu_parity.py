@@ -93,6 +93,33 @@ def test_jvp(lib, cfg, prec, solve, tol, btol):
 
 
 @pytest.mark.parametrize("cfg", SMALL)
+@pytest.mark.parametrize("prec,solve,tol,btol", [(0, 0, 1e-12, FP64_BLOCK), (1, 1, 1e-6, 1e-5), (1, 2, 1e-6, 1e-5)],
+                         ids=["fp64", "mixed-fp64solve", "mixed-fp32solve-refined"])
+def test_single_vector_jvp(lib, cfg, prec, solve, tol, btol):
+    """One vector per call takes the one-right-hand-side chain solve (vector-unit walks and
+    output): each action matches the oracle, and the same vectors in one batched call (the
+    matrix-core walks) give the same actions up to rounding."""
+    plan, ora, lay = _setup(lib, cfg, mixed_solve=solve)
+    X = si.random_state(lay, 101, amp=(1e-2, 1e-2, 1e-2), p=2) + ora.conductive_state()
+    J = si.default_phase_slot(lay, X)
+    plan.set_base(_dev(X), 0.3, J)
+    ora.set_base(X, 0.3, J)
+    V = si.random_vectors(lay, [1101, 1102, 1103])
+    vd = _dev(V)
+    yb = torch.empty_like(vd)
+    plan.jvp(vd, yb, prec)
+    Yb = _host(yb)
+    for i in range(len(V)):
+        y1 = torch.empty_like(vd[i])
+        plan.jvp(vd[i].contiguous(), y1, prec)
+        Y1 = _host(y1)
+        check(lay, Y1, ora.jvp(V[i]), tol, btol, f"cfg={cfg} prec={prec} solve={solve} single vec {i}")
+        d = float(np.abs(Y1 - Yb[i]).max() / np.abs(Yb[i]).max())
+        print(f"cfg={cfg} prec={prec} solve={solve} vec {i}: one-vector vs batched max rel {d:.2e}", flush=True)
+        assert d <= 2 * tol    # both are within tol of the oracle
+
+
+@pytest.mark.parametrize("cfg", SMALL)
 def test_autotune_then_jvp(lib, cfg):
     """sc_autotune times every ring and analysis candidate of the shell and keeps the fastest;
     the Jacobian actions with the chosen kernels still match the oracle in both precisions."""
