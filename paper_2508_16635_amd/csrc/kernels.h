@@ -2778,14 +2778,42 @@ __global__ void __launch_bounds__(256) k_dots_partial(const double* __restrict__
   if (threadIdx.x == 0) part[(long long)i * nchunk + chunk] = red[0];
 }
 
-// w = alpha * w - sum_i h_i V_i   (alpha = 1: Gram-Schmidt update; the sum runs over i < k)
-__global__ void k_combine(double* __restrict__ w, double alpha, const double* __restrict__ V, long long ldv, int k,
-                          const double* __restrict__ h, long long n) {
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  double acc = alpha * w[t];
-  for (int i = 0; i < k; ++i) acc -= h[i] * V[(long long)i * ldv + t];
-  w[t] = acc;
+// w = alpha * w - sum_i h_i V_i   (alpha = 1: Gram-Schmidt update; the sum runs over i < k, in
+// order).  The vectors go in groups of kCombineGroup, the loads of the next group in flight while
+// the current one is summed (a bandwidth-bound stream needs many loads in flight per wave); the
+// loop takes groups in pairs with an odd last group after it, and no load sits under a branch
+// (the compiler would wait for it at once).  Lanes past n load the last element and store
+// nothing.
+constexpr int kCombineGroup = 8;
+__global__ void __launch_bounds__(256) k_combine(double* __restrict__ w, double alpha, const double* __restrict__ V,
+                                                 long long ldv, int k, const double* __restrict__ h, long long n) {
+  constexpr int G = kCombineGroup;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x, tc = t < n ? t : n - 1;
+  const int ng = k / G;
+  double acc = alpha * w[tc];
+  double va[G], vb[G];
+  auto load = [&](int gi, double (&v)[G]) {
+    gi = gi < ng ? gi : ng - 1;
+#pragma unroll
+    for (int g = 0; g < G; ++g) v[g] = V[(long long)(gi * G + g) * ldv + tc];
+  };
+  auto use = [&](int gi, const double (&v)[G]) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc -= h[gi * G + g] * v[g];
+  };
+  if (ng > 0) {
+    load(0, va);
+    int gi = 0;
+    for (; gi + 1 < ng; gi += 2) {
+      load(gi + 1, vb);
+      use(gi, va);
+      load(gi + 2, va);
+      use(gi + 1, vb);
+    }
+    if (gi < ng) use(gi, va);
+  }
+  for (int i = ng * G; i < k; ++i) acc -= h[i] * V[(long long)i * ldv + tc];
+  if (t < n) w[t] = acc;
 }
 
 // dst = alpha * src
@@ -2970,33 +2998,44 @@ __global__ void k_inv_norm(const double* __restrict__ pn, int nchunk, double* __
 }
 
 // Dot products of w with V_i, i < k: workgroup (b, c) owns the elements [b len, (b + 1) len) of
-// w (len = 4 * 256, in registers) and the vectors i = 8 c .. 8 c + 7, all of whose loads are
-// issued together; part[i * nchunk + b] is its partial sum (summed in a fixed order by
-// k_dots_reduce).
-constexpr int kDotsPerThread = 4;
+// w (len = 256 kDotsPerThread; thread t the pairs 2 (t + 256 q), q < kDotsPerThread / 2, read as
+// 16-byte loads; n is even) and the vectors i = 8 c .. 8 c + 7, all of whose loads are issued
+// together; part[i * nchunk + b] is its partial sum (summed in a fixed order by k_dots_reduce).
+// Pairs past n read the last pair (clamped, no load under a branch) and are masked at use.
+constexpr int kDotsPerThread = 8;
 constexpr int kDotsGroup = 8;
 __global__ void __launch_bounds__(256) k_dots_multi(const double* __restrict__ V, long long ldv, int k,
                                                     const double* __restrict__ w, long long n, int nchunk,
                                                     double* __restrict__ part) {
+  constexpr int NP = kDotsPerThread / 2;
   __shared__ double red[4][kDotsGroup];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const long long base = (long long)blockIdx.x * (256 * kDotsPerThread);
   const int i0 = blockIdx.y * kDotsGroup;
-  double wr[kDotsPerThread], s[kDotsGroup];
-  long long idx[kDotsPerThread];
+  double2 wr[NP];
+  double msk[NP];
+  long long idx[NP];
 #pragma unroll
-  for (int q = 0; q < kDotsPerThread; ++q) {
-    idx[q] = base + tid + 256LL * q;
-    wr[q] = idx[q] < n ? w[idx[q]] : 0.0;
+  for (int q = 0; q < NP; ++q) {
+    const long long e = base + 2 * (tid + 256LL * q);
+    idx[q] = e < n ? e : n - 2;
+    msk[q] = e < n ? 1.0 : 0.0;
+    wr[q] = *reinterpret_cast<const double2*>(w + idx[q]);
   }
+  double2 vv[kDotsGroup][NP];
 #pragma unroll
   for (int g = 0; g < kDotsGroup; ++g) {
     const int i = min(i0 + g, k - 1);   // rows beyond k repeat the last one and are not stored
     const double* v = V + (long long)i * ldv;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) vv[g][q] = *reinterpret_cast<const double2*>(v + idx[q]);
+  }
+  double s[kDotsGroup];
+#pragma unroll
+  for (int g = 0; g < kDotsGroup; ++g) {
     double a = 0.0;
 #pragma unroll
-    for (int q = 0; q < kDotsPerThread; ++q)
-      if (idx[q] < n) a += v[idx[q]] * wr[q];
+    for (int q = 0; q < NP; ++q) a += msk[q] * (vv[g][q].x * wr[q].x + vv[g][q].y * wr[q].y);
     s[g] = a;
   }
 #pragma unroll
