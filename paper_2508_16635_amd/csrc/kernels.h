@@ -2468,7 +2468,6 @@ __global__ void __launch_bounds__(kSolveThreads) k_cs1_out(DevGrid g, const int*
     }
   }
   const cpx<F> wv = W[((long long)blk * N + ln.rowc) * wcap];
-  const long long ld = 6LL * N * g.S;
   const int lm = blk_lm[blk];
   const long long oo = 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + lm)) + 2 * ln.rowc;
   const double cq = (double)Cg[(long long)blk * N + ln.rowc];
