@@ -764,6 +764,8 @@ void chain_solve_rt(sc_plan* P, int nvec, const double* b, double* x, const sc::
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL((sc::k_cs1_bwd_bound<F, RT>), dim3(P->nchains), blk, 0, s, dg, ch, kSeg, Psi, W);
     HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL((sc::k_cs1_out<F, RT, ACC, FIN>), dim3(P->nblocks), blk, 0, s, dg, P->blk_field.as<int>(),
+                       P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const C*)W, x, fo);
   } else {
     hipLaunchKernelGGL((sc::k_cs_fwd_rhs<F, RT>), dim3(P->nsegs, nvg), blk, 0, s, dg, nvec, sg, P->blk_field.as<int>(),
                        P->blk_lm.as<int>(), Dm, Gm, b, W);
@@ -774,14 +776,10 @@ void chain_solve_rt(sc_plan* P, int nvec, const double* b, double* x, const sc::
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL((sc::k_cs_bwd_bound<F, RT>), dim3(P->nchains, nvg), blk, 0, s, dg, nvec, ch, kSeg, Psi, W);
     HIPCHK(hipGetLastError());
-  }
-  if (nvec == 1)
-    hipLaunchKernelGGL((sc::k_cs1_out<F, RT, ACC, FIN>), dim3(P->nblocks), blk, 0, s, dg, P->blk_field.as<int>(),
-                       P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const C*)W, x, fo);
-  else
     hipLaunchKernelGGL((sc::k_cs_out<F, RT, ACC, FIN>), dim3(P->nblocks, nvg), blk, 0, s, dg, nvec,
                        P->blk_field.as<int>(), P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const C*)W, x,
                        fo);
+  }
   HIPCHK(hipGetLastError());
 }
 
