@@ -692,7 +692,7 @@ __global__ void __launch_bounds__(256) k_anal(const AnaProb* __restrict__ probs,
       // its load and its product, and no product sits under a branch (either makes the compiler
       // wait for every load in flight): the sign and the zero of a padded k-step past KSa are
       // applied to the LDS operand at its use.
-      constexpr int PD = sizeof(T) == 4 ? 2 : 4;
+      constexpr int PD = 4;
       with_count<CT>(nct, [&](auto ncc) {
         constexpr int NC = decltype(ncc)::value;
         T aq[PD], bq[PD][NC];
