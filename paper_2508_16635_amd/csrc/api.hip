@@ -930,10 +930,10 @@ void ensure_krylov(sc_plan* P, int restart) {
   P->kW.alloc(n * sizeof(double));
   P->kR.alloc(n * sizeof(double));
   P->kDu.alloc(n * sizeof(double));
-  P->kPart.alloc((size_t)(restart + 1) * std::max<long long>(kDotChunks, dots_chunks(n)) * sizeof(double));
+  P->kPart.alloc((size_t)2 * (restart + 1) * std::max<long long>(kDotChunks, dots_chunks(n)) * sizeof(double));
   P->kH.alloc((size_t)(restart + 1) * sizeof(double));
   P->kHc.alloc((size_t)(restart + 1) * restart * sizeof(double));
-  P->kGiv.alloc((size_t)(3 * (restart + 1)) * sizeof(double));
+  P->kGiv.alloc((size_t)(5 * (restart + 1) + 4) * sizeof(double));
   P->kRes.alloc((size_t)std::max<long long>(kDotChunks, dots_chunks(n)) * sizeof(double));
   P->krylov_cap = restart;
   ++P->graph_epoch;
@@ -970,7 +970,7 @@ void combine(sc_plan* P, double* w, double alpha, const double* V, long long ldv
 
 // Device Arnoldi workspace views (capacity krylov_cap).
 struct ArnoldiWs {
-  double *Hc, *h1, *h2, *pn, *hinv;
+  double *Hc, *h1, *h2, *pn, *hinv, *coef;   // h1, h2 contiguous: the 2 (R + 1) reduced dot products
   int ld;
 };
 ArnoldiWs arnoldi_ws(sc_plan* P) {
@@ -982,6 +982,7 @@ ArnoldiWs arnoldi_ws(sc_plan* P) {
   a.h1 = b;
   a.h2 = b + (R + 1);
   a.hinv = b + 2 * (R + 1);
+  a.coef = b + 2 * (R + 1) + 2;   // 2 + 2 R coefficients of the delayed step
   a.pn = P->kRes.as<double>();   // norm partials (capacity max(restart, chunks of n))
   return a;
 }
@@ -995,30 +996,44 @@ void norm_parts(sc_plan* P, const double* x, double* pn, hipStream_t s) {
   hipLaunchKernelGGL(sc::k_dots_multi, dim3(nch, 1), dim3(256), 0, s, x, n, 1, x, n, nch, pn);
 }
 
-// One Arnoldi step j on the device, no host synchronization: w = J V_j, classical Gram-Schmidt
-// twice against V_0..V_j, column j of the Hessenberg matrix with h_{j+1,j} = ||w||, and
-// V_{j+1} = w / h_{j+1,j}.
+// One Arnoldi step j on the device, no host synchronization, with the second Gram-Schmidt pass
+// delayed to the next step (k_dcgs_coef): w = J u with u = V_j (orthogonalized once); one pass of
+// dot products of V_0..V_j with u and w; the coefficients, column j - 1 finished and column j
+// written; one update pass giving the final V_j and w1; H[j+1, j] = ||w1||, V_{j+1} = w1 / ||w1||.
 void arnoldi_step(sc_plan* P, int j, int prec, hipStream_t s) {
   const long long n = P->n_real;
   double* V = P->kV.as<double>();
   double* w = P->kW.as<double>();
   double* part = P->kPart.as<double>();
   const ArnoldiWs a = arnoldi_ws(P);
-  jvp_impl(P, 1, V + (long long)j * n, n, w, n, prec, s);
+  double* u = V + (long long)j * n;
+  jvp_impl(P, 1, u, n, w, n, prec, s);
   const int nch = (int)dots_chunks(n);
-  for (int pass = 0; pass < 2; ++pass) {
-    double* h = pass == 0 ? a.h1 : a.h2;
-    hipLaunchKernelGGL(sc::k_dots_multi, dim3(nch, (j + 1 + sc::kDotsGroup - 1) / sc::kDotsGroup), dim3(256), 0, s,
-                       (const double*)V, n, j + 1, (const double*)w, n, nch, part);
-    hipLaunchKernelGGL(sc::k_dots_reduce, dim3(nblk(j + 1, 4)), dim3(256), 0, s, (const double*)part, j + 1, nch, h);
-    hipLaunchKernelGGL(sc::k_combine, dim3(nblk(n, 256)), dim3(256), 0, s, w, 1.0, (const double*)V, n, j + 1,
-                       (const double*)h, n);
-  }
+  hipLaunchKernelGGL(sc::k_dots_multi2, dim3(nch, (j + 1 + sc::kDotsGroup - 1) / sc::kDotsGroup), dim3(256), 0, s,
+                     (const double*)V, n, j + 1, (const double*)u, (const double*)w, n, nch, part);
+  hipLaunchKernelGGL(sc::k_dots_reduce, dim3(nblk(2 * (j + 1), 4)), dim3(256), 0, s, (const double*)part, 2 * (j + 1),
+                     nch, a.h1);
+  hipLaunchKernelGGL(sc::k_dcgs_coef, dim3(1), dim3(256), 0, s, j, a.ld, (const double*)a.h1, 0, a.Hc, a.coef);
+  hipLaunchKernelGGL(sc::k_combine2, dim3(nblk(n, 256)), dim3(256), 0, s, w, V, n, j, (const double*)a.coef, n);
   norm_parts(P, w, a.pn, s);
-  hipLaunchKernelGGL(sc::k_arnoldi_col, dim3(1), dim3(256), 0, s, j, a.ld, (const double*)a.h1, (const double*)a.h2,
-                     (const double*)a.pn, nch, a.Hc, a.hinv);
+  hipLaunchKernelGGL(sc::k_colnorm, dim3(1), dim3(64), 0, s, j, a.ld, (const double*)a.pn, nch, a.Hc, a.hinv);
   hipLaunchKernelGGL(sc::k_scale_dev, dim3(nblk(n, 256)), dim3(256), 0, s, V + (long long)(j + 1) * n,
                      (const double*)w, (const double*)a.hinv, n);
+  HIPCHK(hipGetLastError());
+}
+
+// Finishes column k - 1 after the last step of a cycle: the dot products of V_k (orthogonalized
+// once) with V_0..V_k give the second pass's coefficients (no new Jacobian action).
+void arnoldi_finish(sc_plan* P, int k, hipStream_t s) {
+  const long long n = P->n_real;
+  double* V = P->kV.as<double>();
+  double* part = P->kPart.as<double>();
+  const ArnoldiWs a = arnoldi_ws(P);
+  const int nch = (int)dots_chunks(n);
+  hipLaunchKernelGGL(sc::k_dots_multi, dim3(nch, (k + 1 + sc::kDotsGroup - 1) / sc::kDotsGroup), dim3(256), 0, s,
+                     (const double*)V, n, k + 1, (const double*)(V + (long long)k * n), n, nch, part);
+  hipLaunchKernelGGL(sc::k_dots_reduce, dim3(nblk(k + 1, 4)), dim3(256), 0, s, (const double*)part, k + 1, nch, a.h1);
+  hipLaunchKernelGGL(sc::k_dcgs_coef, dim3(1), dim3(256), 0, s, k, a.ld, (const double*)a.h1, 1, a.Hc, a.coef);
   HIPCHK(hipGetLastError());
 }
 
@@ -1052,45 +1067,54 @@ int gmres(sc_plan* P, const double* b, double* du, double rtol, int restart, int
     HIPCHK(hipGetLastError());
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
-    int j = 0, jend = 0;
-    bool done = false;
-    while (j < restart && !done) {
+    // column j - 1 of the Hessenberg matrix is finished by step j (the delayed second
+    // Gram-Schmidt pass), so the host takes the columns one step behind the device and the last
+    // column of a cycle is finished by arnoldi_finish
+    int j = 0, jend = 0, jq = 0;
+    bool done = false, cycle = true;   // done: converged, broken down or out of actions
+    while (cycle) {
       const int cnt = std::min(std::min(kArnoldiChunk, restart - j), maxmv - mv);
-      if (cnt <= 0) {
-        done = true;
-        break;
-      }
-      for (int q = 0; q < cnt; ++q) arnoldi_step(P, j + q, prec, s);
-      mv += cnt;
-      HIPCHK(hipMemcpyAsync(H.data() + (size_t)j * a.ld, a.Hc + (size_t)j * a.ld, (size_t)cnt * a.ld * sizeof(double),
-                            hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      for (int q = 0; q < cnt && !done; ++q) {
-        const int jj = j + q;
-        double* col = H.data() + (size_t)jj * a.ld;
-        const double hn = col[jj + 1];
-        if (!std::isfinite(hn)) throw Fail{SC_ERR_NONFINITE, "GMRES: non-finite Hessenberg entry"};
-        for (int i = 0; i < jj; ++i) {
-          const double x0 = col[i], x1 = col[i + 1];
-          col[i] = cs[i] * x0 + sn[i] * x1;
-          col[i + 1] = -sn[i] * x0 + cs[i] * x1;
-        }
-        const double x0 = col[jj], den = std::hypot(x0, hn);
-        cs[jj] = den > 0 ? x0 / den : 1.0;
-        sn[jj] = den > 0 ? hn / den : 0.0;
-        col[jj] = den;
-        col[jj + 1] = 0.0;
-        g[jj + 1] = -sn[jj] * g[jj];
-        g[jj] = cs[jj] * g[jj];
-        if (std::fabs(g[jj + 1]) <= rtol * bn || hn == 0.0) {
-          jend = jj + 1;
-          done = true;
-        }
-      }
-      if (!done) {
+      if (cnt > 0) {
+        for (int q = 0; q < cnt; ++q) arnoldi_step(P, j + q, prec, s);
+        mv += cnt;
         j += cnt;
+      }
+      const bool last = cnt <= 0 || j >= restart || mv >= maxmv;
+      if (last && j > jq) arnoldi_finish(P, j, s);
+      const int jfin = last ? j : j - 1;   // columns [jq, jfin) are final
+      if (jfin > jq) {
+        HIPCHK(hipMemcpyAsync(H.data() + (size_t)jq * a.ld, a.Hc + (size_t)jq * a.ld,
+                              (size_t)(jfin - jq) * a.ld * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int jj = jq; jj < jfin && !done; ++jj) {
+          double* col = H.data() + (size_t)jj * a.ld;
+          const double hn = col[jj + 1];
+          if (!std::isfinite(hn)) throw Fail{SC_ERR_NONFINITE, "GMRES: non-finite Hessenberg entry"};
+          for (int i = 0; i < jj; ++i) {
+            const double x0 = col[i], x1 = col[i + 1];
+            col[i] = cs[i] * x0 + sn[i] * x1;
+            col[i + 1] = -sn[i] * x0 + cs[i] * x1;
+          }
+          const double x0 = col[jj], den = std::hypot(x0, hn);
+          cs[jj] = den > 0 ? x0 / den : 1.0;
+          sn[jj] = den > 0 ? hn / den : 0.0;
+          col[jj] = den;
+          col[jj + 1] = 0.0;
+          g[jj + 1] = -sn[jj] * g[jj];
+          g[jj] = cs[jj] * g[jj];
+          if (std::fabs(g[jj + 1]) <= rtol * bn || hn == 0.0) {
+            jend = jj + 1;
+            done = true;
+          }
+        }
+        jq = jfin;
+      }
+      if (done) {
+        cycle = false;
+      } else if (last) {
         jend = j;
-        if (mv >= maxmv) done = true;
+        cycle = false;
+        if (cnt <= 0 || mv >= maxmv) done = true;
       }
     }
     if (jend == 0) break;

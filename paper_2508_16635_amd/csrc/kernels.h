@@ -2815,6 +2815,130 @@ __global__ void __launch_bounds__(256) k_combine(double* __restrict__ w, double 
   if (t < n) w[t] = acc;
 }
 
+// Arnoldi step with delayed reorthogonalization (classical Gram-Schmidt applied twice, the second
+// pass of step j done at step j + 1 together with the first pass of step j + 1: one pass over the
+// basis for the dot products and one for the update per step, instead of two each; the method
+// of the low-synchronization Gram-Schmidt variants for GMRES, restated here from its algebra).
+// At step j the basis vectors V_0..V_{j-1} are final and V_j holds u, orthogonalized once against
+// them and normalized once; w = A u.  With s = V^T u, alpha = u.u, p = V^T w, q = u.w (one pass):
+//   rho = sqrt(alpha - s.s),  v_j = (u - V s) / rho                  (u orthogonalized again)
+//   H[0:j, j-1] += H[j, j-1] s,  H[j, j-1] *= rho                      (column j-1 final)
+//   A v_j = (w - [V, v_j] t) / rho with t = H[0:j+1, 0:j] s          (the Arnoldi relation)
+//   c = v_j.w = (q - s.p) / rho
+//   column j: h_r = (p_r - t_r) / rho (r < j), h_j = (c - t_j) / rho
+//   w1 = A v_j - [V, v_j] h = (w - (c/rho) u - V (p - (c/rho) s)) / rho    (one pass)
+// then H[j+1, j] = ||w1|| and V_{j+1} = w1 / ||w1||, orthogonalized once (finished at step j + 1).
+// k_dcgs_coef (one workgroup): sp = the reduced dot products (s_0..s_{j-1}, alpha, then
+// p_0..p_{j-1}, q); corrects column j-1 and writes column j (rows 0..j) of Hc and
+// coef = (1/rho, c/rho, s_0..s_{j-1}, g_0..g_{j-1}), g = p - (c/rho) s.  With fin it only
+// finishes column j-1 (sp = s, alpha of V_j against V_0..V_{j-1}: the end of a cycle).  The
+// sums are taken in a fixed order; rho = 0 (u in the span of V: a breakdown) gives zero
+// coefficients.
+__global__ void __launch_bounds__(256) k_dcgs_coef(int j, int ld, const double* __restrict__ sp, int fin,
+                                                   double* __restrict__ Hc, double* __restrict__ coef) {
+  __shared__ double red[2][256];
+  __shared__ double sh[2];
+  const int tid = threadIdx.x;
+  const double* sv = sp;
+  const double* pv = sp + (j + 1);
+  double a1 = 0.0, a2 = 0.0;
+  for (int i = tid; i < j; i += 256) {
+    a1 += sv[i] * sv[i];
+    if (!fin) a2 += sv[i] * pv[i];
+  }
+  red[0][tid] = a1;
+  red[1][tid] = a2;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      red[0][tid] += red[0][tid + h];
+      red[1][tid] += red[1][tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double r2 = sv[j] - red[0][0];
+    const double rho = r2 > 0.0 ? sqrt(r2) : 0.0;
+    sh[0] = rho;
+    sh[1] = (!fin && rho > 0.0) ? (pv[j] - red[1][0]) / rho : 0.0;
+  }
+  __syncthreads();
+  const double rho = sh[0], c = sh[1], ir = rho > 0.0 ? 1.0 / rho : 0.0;
+  if (j >= 1) {
+    double* col = Hc + (long long)(j - 1) * ld;
+    const double hj = col[j];
+    for (int i = tid; i < j; i += 256) col[i] += hj * sv[i];
+    __syncthreads();
+    if (tid == 0) col[j] = hj * rho;
+    __syncthreads();
+  }
+  if (fin) return;
+  double* colj = Hc + (long long)j * ld;
+  for (int r = tid; r <= j; r += 256) {
+    double t = 0.0;
+    for (int cl = r > 0 ? r - 1 : 0; cl < j; ++cl) t += Hc[r + (long long)cl * ld] * sv[cl];
+    colj[r] = (r < j ? pv[r] - t : c - t) * ir;
+  }
+  const double cu = c * ir;
+  for (int i = tid; i < j; i += 256) {
+    coef[2 + i] = sv[i];
+    coef[2 + j + i] = pv[i] - cu * sv[i];
+  }
+  if (tid == 0) {
+    coef[0] = ir;
+    coef[1] = cu;
+  }
+}
+
+// The update pass of the delayed step (see k_dcgs_coef), reading V_0..V_{j-1} once for both
+// outputs: V_j <- (u - V s) / rho and w <- (w - cu u - V g) / rho, u = V_j, coef = (1/rho, cu, s,
+// g).  Basis loads in groups of kCombineGroup with the next group in flight (as in k_combine).
+__global__ void __launch_bounds__(256) k_combine2(double* __restrict__ w, double* __restrict__ V, long long ldv, int j,
+                                                  const double* __restrict__ coef, long long n) {
+  constexpr int G = kCombineGroup;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x, tc = t < n ? t : n - 1;
+  const int ng = j / G;
+  const double ir = coef[0], cu = coef[1];
+  const double* sv = coef + 2;
+  const double* gv = coef + 2 + j;
+  double* u = V + (long long)j * ldv;
+  const double uu = u[tc];
+  double av = uu, aw = w[tc] - cu * uu;
+  double va[G], vb[G];
+  auto load = [&](int gi, double (&v)[G]) {
+    gi = gi < ng ? gi : ng - 1;
+#pragma unroll
+    for (int g = 0; g < G; ++g) v[g] = V[(long long)(gi * G + g) * ldv + tc];
+  };
+  auto use = [&](int gi, const double (&v)[G]) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      av -= sv[gi * G + g] * v[g];
+      aw -= gv[gi * G + g] * v[g];
+    }
+  };
+  if (ng > 0) {
+    load(0, va);
+    int gi = 0;
+    for (; gi + 1 < ng; gi += 2) {
+      load(gi + 1, vb);
+      use(gi, va);
+      load(gi + 2, va);
+      use(gi + 1, vb);
+    }
+    if (gi < ng) use(gi, va);
+  }
+  for (int i = ng * G; i < j; ++i) {
+    const double v = V[(long long)i * ldv + tc];
+    av -= sv[i] * v;
+    aw -= gv[i] * v;
+  }
+  if (t < n) {
+    u[t] = av * ir;
+    w[t] = aw * ir;
+  }
+}
+
 // dst = alpha * src
 __global__ void k_scale(double* __restrict__ dst, const double* __restrict__ src, double alpha, long long n) {
   long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2968,26 +3092,6 @@ __global__ void __launch_bounds__(256) k_dots_reduce(const double* __restrict__ 
   if (lane == 0) out[i] = s;
 }
 
-// Column j of the Hessenberg matrix (Hc: column-major, leading dimension ld) from the two
-// Gram-Schmidt passes, h_{j+1,j} = ||w|| from its chunk partials pn, and hinv = 1/h_{j+1,j}
-// (0 at a breakdown).  The Givens rotations are applied on the host, once per chunk of steps.
-__global__ void __launch_bounds__(256) k_arnoldi_col(int j, int ld, const double* __restrict__ h1,
-                                                     const double* __restrict__ h2, const double* __restrict__ pn,
-                                                     int nchunk, double* __restrict__ Hc, double* __restrict__ hinv) {
-  double* col = Hc + (long long)j * ld;
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = h1[i] + h2[i];
-  if (threadIdx.x < 64) {
-    double ss = 0.0;
-    for (int c = threadIdx.x; c < nchunk; c += 64) ss += pn[c];
-    ss = wave_sum_fixed(ss);
-    if (threadIdx.x == 0) {
-      const double hn = sqrt(ss);
-      col[j + 1] = hn;
-      hinv[0] = hn > 0.0 ? 1.0 / hn : 0.0;
-    }
-  }
-}
-
 // 1 / ||r|| from its chunk partials (0 if r = 0), one wavefront.
 __global__ void k_inv_norm(const double* __restrict__ pn, int nchunk, double* __restrict__ hinv) {
   double ss = 0.0;
@@ -2996,22 +3100,37 @@ __global__ void k_inv_norm(const double* __restrict__ pn, int nchunk, double* __
   if (threadIdx.x == 0) hinv[0] = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
 }
 
-// Dot products of w with V_i, i < k: workgroup (b, c) owns the elements [b len, (b + 1) len) of
-// w (len = 256 kDotsPerThread; thread t the pairs 2 (t + 256 q), q < kDotsPerThread / 2, read as
-// 16-byte loads; n is even) and the vectors i = 8 c .. 8 c + 7, all of whose loads are issued
-// together; part[i * nchunk + b] is its partial sum (summed in a fixed order by k_dots_reduce).
-// Pairs past n read the last pair (clamped, no load under a branch) and are masked at use.
+// H[j+1, j] = ||w|| from its chunk partials pn, hinv = 1/||w|| (0 at a breakdown), one wavefront.
+__global__ void k_colnorm(int j, int ld, const double* __restrict__ pn, int nchunk, double* __restrict__ Hc,
+                          double* __restrict__ hinv) {
+  double ss = 0.0;
+  for (int c = threadIdx.x; c < nchunk; c += 64) ss += pn[c];
+  ss = wave_sum_fixed(ss);
+  if (threadIdx.x == 0) {
+    const double hn = sqrt(ss);
+    Hc[(j + 1) + (long long)j * ld] = hn;
+    hinv[0] = hn > 0.0 ? 1.0 / hn : 0.0;
+  }
+}
+
+// Dot products of x_r (r < NX right vectors) with V_i, i < k: workgroup (b, c) owns the elements
+// [b len, (b + 1) len) (len = 256 kDotsPerThread; thread t the pairs 2 (t + 256 q),
+// q < kDotsPerThread / 2, read as 16-byte loads; n is even) and the vectors i = 8 c .. 8 c + 7,
+// all of whose loads are issued together; part[(r k + i) * nchunk + b] is the partial sum of
+// <V_i, x_r> (summed in a fixed order by k_dots_reduce).  Pairs past n read the last pair
+// (clamped, no load under a branch) and are masked at use.
 constexpr int kDotsPerThread = 8;
 constexpr int kDotsGroup = 8;
-__global__ void __launch_bounds__(256) k_dots_multi(const double* __restrict__ V, long long ldv, int k,
-                                                    const double* __restrict__ w, long long n, int nchunk,
-                                                    double* __restrict__ part) {
+template <int NX>
+__device__ __forceinline__ void dots_multi_dev(const double* __restrict__ V, long long ldv, int k,
+                                               const double* __restrict__ x0, const double* __restrict__ x1,
+                                               long long n, int nchunk, double* __restrict__ part) {
   constexpr int NP = kDotsPerThread / 2;
-  __shared__ double red[4][kDotsGroup];
+  __shared__ double red[4][NX][kDotsGroup];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const long long base = (long long)blockIdx.x * (256 * kDotsPerThread);
   const int i0 = blockIdx.y * kDotsGroup;
-  double2 wr[NP];
+  double2 xr[NX][NP];
   double msk[NP];
   long long idx[NP];
 #pragma unroll
@@ -3019,7 +3138,8 @@ __global__ void __launch_bounds__(256) k_dots_multi(const double* __restrict__ V
     const long long e = base + 2 * (tid + 256LL * q);
     idx[q] = e < n ? e : n - 2;
     msk[q] = e < n ? 1.0 : 0.0;
-    wr[q] = *reinterpret_cast<const double2*>(w + idx[q]);
+    xr[0][q] = *reinterpret_cast<const double2*>(x0 + idx[q]);
+    if (NX > 1) xr[NX - 1][q] = *reinterpret_cast<const double2*>(x1 + idx[q]);
   }
   double2 vv[kDotsGroup][NP];
 #pragma unroll
@@ -3029,26 +3149,48 @@ __global__ void __launch_bounds__(256) k_dots_multi(const double* __restrict__ V
 #pragma unroll
     for (int q = 0; q < NP; ++q) vv[g][q] = *reinterpret_cast<const double2*>(v + idx[q]);
   }
-  double s[kDotsGroup];
+  double s[NX][kDotsGroup];
 #pragma unroll
-  for (int g = 0; g < kDotsGroup; ++g) {
-    double a = 0.0;
+  for (int r = 0; r < NX; ++r)
 #pragma unroll
-    for (int q = 0; q < NP; ++q) a += msk[q] * (vv[g][q].x * wr[q].x + vv[g][q].y * wr[q].y);
-    s[g] = a;
-  }
+    for (int g = 0; g < kDotsGroup; ++g) {
+      double a = 0.0;
 #pragma unroll
-  for (int g = 0; g < kDotsGroup; ++g) {
+      for (int q = 0; q < NP; ++q) a += msk[q] * (vv[g][q].x * xr[r][q].x + vv[g][q].y * xr[r][q].y);
+      s[r][g] = a;
+    }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s[g] += __shfl_xor(s[g], off);
-  }
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int g = 0; g < kDotsGroup; ++g) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s[r][g] += __shfl_xor(s[r][g], off);
+    }
   if (lane == 0) {
 #pragma unroll
-    for (int g = 0; g < kDotsGroup; ++g) red[wave][g] = s[g];
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int g = 0; g < kDotsGroup; ++g) red[wave][r][g] = s[r][g];
   }
   __syncthreads();
-  if (tid < kDotsGroup && i0 + tid < k)
-    part[(long long)(i0 + tid) * nchunk + blockIdx.x] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+  if (tid < NX * kDotsGroup) {
+    const int r = tid / kDotsGroup, g = tid % kDotsGroup;
+    if (i0 + g < k)
+      part[((long long)r * k + i0 + g) * nchunk + blockIdx.x] =
+          ((red[0][r][g] + red[1][r][g]) + red[2][r][g]) + red[3][r][g];
+  }
+}
+
+// One right vector (norms, Gram-Schmidt dot products) and two (the delayed reorthogonalization).
+__global__ void __launch_bounds__(256) k_dots_multi(const double* __restrict__ V, long long ldv, int k,
+                                                    const double* __restrict__ w, long long n, int nchunk,
+                                                    double* __restrict__ part) {
+  dots_multi_dev<1>(V, ldv, k, w, w, n, nchunk, part);
+}
+__global__ void __launch_bounds__(256) k_dots_multi2(const double* __restrict__ V, long long ldv, int k,
+                                                     const double* __restrict__ x0, const double* __restrict__ x1,
+                                                     long long n, int nchunk, double* __restrict__ part) {
+  dots_multi_dev<2>(V, ldv, k, x0, x1, n, nchunk, part);
 }
 
 // x[0] = v (a device scalar written in stream order)
