@@ -934,7 +934,8 @@ void ensure_krylov(sc_plan* P, int restart) {
   P->kH.alloc((size_t)(restart + 1) * sizeof(double));
   P->kHc.alloc((size_t)(restart + 1) * restart * sizeof(double));
   P->kGiv.alloc((size_t)(5 * (restart + 1) + 4) * sizeof(double));
-  P->kRes.alloc((size_t)std::max<long long>(kDotChunks, dots_chunks(n)) * sizeof(double));
+  P->kRes.alloc((size_t)std::max<long long>(std::max<long long>(kDotChunks, dots_chunks(n)), nblk(n, 256)) *
+                sizeof(double));
   P->krylov_cap = restart;
   ++P->graph_epoch;
 }
@@ -983,7 +984,7 @@ ArnoldiWs arnoldi_ws(sc_plan* P) {
   a.h2 = b + (R + 1);
   a.hinv = b + 2 * (R + 1);
   a.coef = b + 2 * (R + 1) + 2;   // 2 + 2 R coefficients of the delayed step
-  a.pn = P->kRes.as<double>();   // norm partials (capacity max(restart, chunks of n))
+  a.pn = P->kRes.as<double>();   // norm partials (capacity: chunks of n, workgroups of the update)
   return a;
 }
 
@@ -998,8 +999,9 @@ void norm_parts(sc_plan* P, const double* x, double* pn, hipStream_t s) {
 
 // One Arnoldi step j on the device, no host synchronization, with the second Gram-Schmidt pass
 // delayed to the next step (k_dcgs_coef): w = J u with u = V_j (orthogonalized once); one pass of
-// dot products of V_0..V_j with u and w; the coefficients, column j - 1 finished and column j
-// written; one update pass giving the final V_j and w1; H[j+1, j] = ||w1||, V_{j+1} = w1 / ||w1||.
+// dot products of V_0..V_j with u and w; the coefficients and column j - 1 finished; one update
+// pass giving the final V_j, w1 and the parts of ||w1||^2; column j; H[j+1, j] = ||w1||,
+// V_{j+1} = w1 / ||w1||.
 void arnoldi_step(sc_plan* P, int j, int prec, hipStream_t s) {
   const long long n = P->n_real;
   double* V = P->kV.as<double>();
@@ -1014,9 +1016,11 @@ void arnoldi_step(sc_plan* P, int j, int prec, hipStream_t s) {
   hipLaunchKernelGGL(sc::k_dots_reduce, dim3(nblk(2 * (j + 1), 4)), dim3(256), 0, s, (const double*)part, 2 * (j + 1),
                      nch, a.h1);
   hipLaunchKernelGGL(sc::k_dcgs_coef, dim3(1), dim3(256), 0, s, j, a.ld, (const double*)a.h1, 0, a.Hc, a.coef);
-  hipLaunchKernelGGL(sc::k_combine2, dim3(nblk(n, 256)), dim3(256), 0, s, w, V, n, j, (const double*)a.coef, n);
-  norm_parts(P, w, a.pn, s);
-  hipLaunchKernelGGL(sc::k_colnorm, dim3(1), dim3(64), 0, s, j, a.ld, (const double*)a.pn, nch, a.Hc, a.hinv);
+  const int nwg = (int)nblk(n, 256);
+  hipLaunchKernelGGL(sc::k_combine2, dim3(nwg), dim3(256), 0, s, w, V, n, j, (const double*)a.coef, n, a.pn);
+  hipLaunchKernelGGL(sc::k_hess_col, dim3((j + 1 + 63) / 64), dim3(256), 0, s, j, a.ld, (const double*)a.h1,
+                     (const double*)a.coef, a.Hc);
+  hipLaunchKernelGGL(sc::k_colnorm, dim3(1), dim3(64), 0, s, j, a.ld, (const double*)a.pn, nwg, a.Hc, a.hinv);
   hipLaunchKernelGGL(sc::k_scale_dev, dim3(nblk(n, 256)), dim3(256), 0, s, V + (long long)(j + 1) * n,
                      (const double*)w, (const double*)a.hinv, n);
   HIPCHK(hipGetLastError());

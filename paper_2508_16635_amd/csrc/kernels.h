@@ -2755,6 +2755,13 @@ __global__ void k_finalize(DevGrid g, int nvec, const double* __restrict__ x, co
   y[(long long)vec * ldy + i] = xv - u;
 }
 
+// Sum over the 64 lanes of a wavefront by a fixed shuffle tree (reproducible results).
+__device__ inline double wave_sum_fixed(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
 // ------------------------------------------------------------------------------------------
 // K13: Krylov helpers (FP64).  Partial dot products part[i * nchunk + chunk] of V_i with w over
 // fixed chunks (summed on the host in a fixed order, so results are reproducible).
@@ -2829,11 +2836,11 @@ __global__ void __launch_bounds__(256) k_combine(double* __restrict__ w, double 
 //   w1 = A v_j - [V, v_j] h = (w - (c/rho) u - V (p - (c/rho) s)) / rho    (one pass)
 // then H[j+1, j] = ||w1|| and V_{j+1} = w1 / ||w1||, orthogonalized once (finished at step j + 1).
 // k_dcgs_coef (one workgroup): sp = the reduced dot products (s_0..s_{j-1}, alpha, then
-// p_0..p_{j-1}, q); corrects column j-1 and writes column j (rows 0..j) of Hc and
-// coef = (1/rho, c/rho, s_0..s_{j-1}, g_0..g_{j-1}), g = p - (c/rho) s.  With fin it only
-// finishes column j-1 (sp = s, alpha of V_j against V_0..V_{j-1}: the end of a cycle).  The
-// sums are taken in a fixed order; rho = 0 (u in the span of V: a breakdown) gives zero
-// coefficients.
+// p_0..p_{j-1}, q); finishes column j-1 of Hc and writes coef = (1/rho, c/rho, s_0..s_{j-1},
+// g_0..g_{j-1}, c), g = p - (c/rho) s, for the update pass; column j (the product with H) is
+// k_hess_col's.  With fin it only finishes column j-1 (sp = s, alpha of V_j against
+// V_0..V_{j-1}: the end of a cycle).  The sums are taken in a fixed order; rho = 0 (u in the span
+// of V: a breakdown) gives zero coefficients.
 __global__ void __launch_bounds__(256) k_dcgs_coef(int j, int ld, const double* __restrict__ sp, int fin,
                                                    double* __restrict__ Hc, double* __restrict__ coef) {
   __shared__ double red[2][256];
@@ -2870,15 +2877,8 @@ __global__ void __launch_bounds__(256) k_dcgs_coef(int j, int ld, const double* 
     for (int i = tid; i < j; i += 256) col[i] += hj * sv[i];
     __syncthreads();
     if (tid == 0) col[j] = hj * rho;
-    __syncthreads();
   }
   if (fin) return;
-  double* colj = Hc + (long long)j * ld;
-  for (int r = tid; r <= j; r += 256) {
-    double t = 0.0;
-    for (int cl = r > 0 ? r - 1 : 0; cl < j; ++cl) t += Hc[r + (long long)cl * ld] * sv[cl];
-    colj[r] = (r < j ? pv[r] - t : c - t) * ir;
-  }
   const double cu = c * ir;
   for (int i = tid; i < j; i += 256) {
     coef[2 + i] = sv[i];
@@ -2887,14 +2887,49 @@ __global__ void __launch_bounds__(256) k_dcgs_coef(int j, int ld, const double* 
   if (tid == 0) {
     coef[0] = ir;
     coef[1] = cu;
+    coef[2 + 2 * j] = c;
+  }
+}
+
+// Column j of the delayed step (after k_dcgs_coef): h_r = (p_r - t_r) / rho for r < j,
+// h_j = (c - t_j) / rho, t = H[0:j+1, 0:j] s (H upper Hessenberg: row r from column r - 1 on).
+// Workgroup b owns rows 64 b .. 64 b + 63; wave q of it the columns = q (mod 4) of each row, with
+// the loads of eight columns issued together; the four partial sums meet in LDS in a fixed order.
+__global__ void __launch_bounds__(256) k_hess_col(int j, int ld, const double* __restrict__ sp,
+                                                  const double* __restrict__ coef, double* __restrict__ Hc) {
+  __shared__ double red[4][64];
+  const int tid = threadIdx.x, q = tid >> 6, r = blockIdx.x * 64 + (tid & 63);
+  const double* sv = sp;
+  const double* pv = sp + (j + 1);
+  double t = 0.0;
+  if (r <= j) {
+    int cl = (r > 0 ? r - 1 : 0);
+    cl += (q - cl % 4 + 4) % 4;   // the first column = q (mod 4) from r - 1 on
+    for (; cl + 28 < j; cl += 32) {
+      double hv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) hv[u] = Hc[r + (long long)(cl + 4 * u) * ld];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t += hv[u] * sv[cl + 4 * u];
+    }
+    for (; cl < j; cl += 4) t += Hc[r + (long long)cl * ld] * sv[cl];
+  }
+  red[q][tid & 63] = t;
+  __syncthreads();
+  if (q == 0 && r <= j) {
+    const int i = tid & 63;
+    const double tt = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+    const double ir = coef[0], c = coef[2 + 2 * j];
+    Hc[r + (long long)j * ld] = (r < j ? pv[r] - tt : c - tt) * ir;
   }
 }
 
 // The update pass of the delayed step (see k_dcgs_coef), reading V_0..V_{j-1} once for both
 // outputs: V_j <- (u - V s) / rho and w <- (w - cu u - V g) / rho, u = V_j, coef = (1/rho, cu, s,
-// g).  Basis loads in groups of kCombineGroup with the next group in flight (as in k_combine).
+// g); pn[b] = the part of ||w||^2 of workgroup b.  Basis loads in groups of kCombineGroup with the
+// next group in flight (as in k_combine).
 __global__ void __launch_bounds__(256) k_combine2(double* __restrict__ w, double* __restrict__ V, long long ldv, int j,
-                                                  const double* __restrict__ coef, long long n) {
+                                                  const double* __restrict__ coef, long long n, double* __restrict__ pn) {
   constexpr int G = kCombineGroup;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x, tc = t < n ? t : n - 1;
   const int ng = j / G;
@@ -2933,10 +2968,18 @@ __global__ void __launch_bounds__(256) k_combine2(double* __restrict__ w, double
     av -= sv[i] * v;
     aw -= gv[i] * v;
   }
+  const double w1 = aw * ir;
   if (t < n) {
     u[t] = av * ir;
-    w[t] = aw * ir;
+    w[t] = w1;
   }
+  // ||w1||^2 partial of this workgroup (fixed order), for k_colnorm
+  __shared__ double red[4];
+  double ss = t < n ? w1 * w1 : 0.0;
+  ss = wave_sum_fixed(ss);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
+  __syncthreads();
+  if (threadIdx.x == 0) pn[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // dst = alpha * src
@@ -3076,12 +3119,6 @@ __global__ void k_interp(InterpMap im, const double* __restrict__ x, double* __r
 // Device-side Arnoldi (restarted GMRES without a host round trip per step).
 // out[i] = sum over c of part[i * nchunk + c], i < k: one wavefront per i, lane l adds the
 // entries c = l, l + 64, ... in order, then a fixed shuffle tree (reproducible results).
-__device__ inline double wave_sum_fixed(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
 __global__ void __launch_bounds__(256) k_dots_reduce(const double* __restrict__ part, int k, int nchunk,
                                                      double* __restrict__ out) {
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
