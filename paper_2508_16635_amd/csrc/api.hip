@@ -1000,8 +1000,8 @@ void norm_parts(sc_plan* P, const double* x, double* pn, hipStream_t s) {
 // One Arnoldi step j on the device, no host synchronization, with the second Gram-Schmidt pass
 // delayed to the next step (k_dcgs_coef): w = J u with u = V_j (orthogonalized once); one pass of
 // dot products of V_0..V_j with u and w; the coefficients and column j - 1 finished; one update
-// pass giving the final V_j, w1 and the parts of ||w1||^2; column j; H[j+1, j] = ||w1||,
-// V_{j+1} = w1 / ||w1||.
+// pass giving the final V_j, w1 and the parts of ||w1||^2; column j; H[j+1, j] = ||w1|| and
+// V_{j+1} = w1 / ||w1|| in one pass.
 void arnoldi_step(sc_plan* P, int j, int prec, hipStream_t s) {
   const long long n = P->n_real;
   double* V = P->kV.as<double>();
@@ -1020,9 +1020,8 @@ void arnoldi_step(sc_plan* P, int j, int prec, hipStream_t s) {
   hipLaunchKernelGGL(sc::k_combine2, dim3(nwg), dim3(256), 0, s, w, V, n, j, (const double*)a.coef, n, a.pn);
   hipLaunchKernelGGL(sc::k_hess_col, dim3((j + 1 + 63) / 64), dim3(256), 0, s, j, a.ld, (const double*)a.h1,
                      (const double*)a.coef, a.Hc);
-  hipLaunchKernelGGL(sc::k_colnorm, dim3(1), dim3(64), 0, s, j, a.ld, (const double*)a.pn, nwg, a.Hc, a.hinv);
-  hipLaunchKernelGGL(sc::k_scale_dev, dim3(nblk(n, 256)), dim3(256), 0, s, V + (long long)(j + 1) * n,
-                     (const double*)w, (const double*)a.hinv, n);
+  hipLaunchKernelGGL(sc::k_scale_norm, dim3(nwg), dim3(256), 0, s, j, a.ld, (const double*)a.pn, nwg, (const double*)w,
+                     V + (long long)(j + 1) * n, n, a.Hc);
   HIPCHK(hipGetLastError());
 }
 

@@ -2973,7 +2973,7 @@ __global__ void __launch_bounds__(256) k_combine2(double* __restrict__ w, double
     u[t] = av * ir;
     w[t] = w1;
   }
-  // ||w1||^2 partial of this workgroup (fixed order), for k_colnorm
+  // ||w1||^2 partial of this workgroup (fixed order), for k_scale_norm
   __shared__ double red[4];
   double ss = t < n ? w1 * w1 : 0.0;
   ss = wave_sum_fixed(ss);
@@ -3137,17 +3137,26 @@ __global__ void k_inv_norm(const double* __restrict__ pn, int nchunk, double* __
   if (threadIdx.x == 0) hinv[0] = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
 }
 
-// H[j+1, j] = ||w|| from its chunk partials pn, hinv = 1/||w|| (0 at a breakdown), one wavefront.
-__global__ void k_colnorm(int j, int ld, const double* __restrict__ pn, int nchunk, double* __restrict__ Hc,
-                          double* __restrict__ hinv) {
-  double ss = 0.0;
-  for (int c = threadIdx.x; c < nchunk; c += 64) ss += pn[c];
-  ss = wave_sum_fixed(ss);
-  if (threadIdx.x == 0) {
-    const double hn = sqrt(ss);
-    Hc[(j + 1) + (long long)j * ld] = hn;
-    hinv[0] = hn > 0.0 ? 1.0 / hn : 0.0;
+// V_{j+1} = w / ||w|| with ||w||^2 the sum of the nchunk parts pn (every workgroup sums them in
+// the same fixed order, so all use the same norm); workgroup 0 also writes H[j+1, j] = ||w||.
+// ||w|| = 0 (a breakdown) gives V_{j+1} = 0.
+__global__ void __launch_bounds__(256) k_scale_norm(int j, int ld, const double* __restrict__ pn, int nchunk,
+                                                    const double* __restrict__ w, double* __restrict__ vout,
+                                                    long long n, double* __restrict__ Hc) {
+  __shared__ double sh;
+  if (threadIdx.x < 64) {
+    double ss = 0.0;
+    for (int c = threadIdx.x; c < nchunk; c += 64) ss += pn[c];
+    ss = wave_sum_fixed(ss);
+    if (threadIdx.x == 0) {
+      const double hn = sqrt(ss);
+      sh = hn > 0.0 ? 1.0 / hn : 0.0;
+      if (blockIdx.x == 0) Hc[(j + 1) + (long long)j * ld] = hn;
+    }
   }
+  __syncthreads();
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) vout[t] = sh * w[t];
 }
 
 // Dot products of x_r (r < NX right vectors) with V_i, i < k: workgroup (b, c) owns the elements
