@@ -135,12 +135,16 @@ int sc_set_base(sc_plan* plan, const double* x, double C, long long J, void* str
 int sc_jvp(sc_plan* plan, int nvec, const double* v, long long ldv, double* y, long long ldy,
            sc_precision prec, void* stream);
 /* Newton-GMRES on R_C(X) = B_C(X) - X (+ forcing), Sec. 3.3 and 3.4: each Newton step solves
- * (B_X - I)(u, c) = R with restarted GMRES (Saad-Schultz, classical Gram-Schmidt applied twice,
- * dot products and updates on the device, Hessenberg and Givens rotations on the host) using
- * sc_jvp in the chosen precision, then X <- X - u, C <- C - c with c carried in slot J.
+ * (B_X - I)(u, c) = R with restarted GMRES (Saad-Schultz) using sc_jvp in the chosen precision,
+ * then X <- X - u, C <- C - c with c carried in slot J.  The Arnoldi steps run on the device:
+ * classical Gram-Schmidt applied twice, the second pass of each basis vector delayed to the
+ * next step and merged with that step's first pass (one pass over the basis for the dot
+ * products and one for the update per step); the Hessenberg columns are finished there too.
+ * The host reads them once per chunk of 8 steps, applies the Givens rotations and checks the
+ * residual estimate, and solves the small triangular system once per cycle.
  * x: device state, updated in place; C: host drift speed, updated in place.  Synchronizes the
- * stream once per Krylov step.  The Krylov basis is allocated by the first call (or a call
- * with a longer restart) and kept by the plan. */
+ * stream once per chunk of Krylov steps.  The Krylov basis is allocated by the first call (or a
+ * call with a longer restart) and kept by the plan. */
 typedef struct {
   double tol;             /* stop when ||R||_2 <= tol (absolute)                         */
   double gmres_tol;       /* relative tolerance of each GMRES solve                      */
