@@ -735,7 +735,7 @@ size_t tsolve_smem(const sc::HostGrid& g) {
   return sizeof(F) * ((size_t)g.N * (g.N + 1) + (size_t)sc::kTV * (g.K + 1) * 2 * (g.N + 1));
 }
 
-// The seven chain-solve launches for RT = ceil(N/16) row tiles.
+// The five chain-solve launches for RT = ceil(N/16) row tiles.
 template <class F, int RT, bool ACC, bool FIN>
 void chain_solve_rt(sc_plan* P, int nvec, const double* b, double* x, const sc::FinalOut& fo, hipStream_t s) {
   sc::DevGrid dg = P->dg();
@@ -767,14 +767,14 @@ void chain_solve_rt(sc_plan* P, int nvec, const double* b, double* x, const sc::
     hipLaunchKernelGGL((sc::k_cs1_out<F, RT, ACC, FIN>), dim3(P->nblocks), blk, 0, s, dg, P->blk_field.as<int>(),
                        P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const C*)W, x, fo);
   } else {
-    hipLaunchKernelGGL((sc::k_cs_fwd_rhs<F, RT>), dim3(P->nsegs, nvg), blk, 0, s, dg, nvec, sg, P->blk_field.as<int>(),
+    hipLaunchKernelGGL((sc::k_cs_fwd_rhs<F, RT>), dim3(P->nsegs, nvg), dim3(sc::walk_threads(RT)), 0, s, dg, nvec, sg, P->blk_field.as<int>(),
                        P->blk_lm.as<int>(), Dm, Gm, b, W);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_cs_fwd_bound<F, RT>), dim3(P->nchains, nvg), blk, 0, s, dg, nvec, ch, kSeg, Phi, W);
+    hipLaunchKernelGGL((sc::k_cs_fwd_bound<F, RT>), dim3(P->nchains, nvg), dim3(sc::walk_threads(RT)), 0, s, dg, nvec, ch, kSeg, Phi, W);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_cs_bwd_fix<F, RT>), dim3(P->nsegs, nvg), blk, 0, s, dg, nvec, sg, Phi, H, W);
+    hipLaunchKernelGGL((sc::k_cs_bwd_fix<F, RT>), dim3(P->nsegs, nvg), dim3(sc::walk_threads(RT)), 0, s, dg, nvec, sg, Phi, H, W);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_cs_bwd_bound<F, RT>), dim3(P->nchains, nvg), blk, 0, s, dg, nvec, ch, kSeg, Psi, W);
+    hipLaunchKernelGGL((sc::k_cs_bwd_bound<F, RT>), dim3(P->nchains, nvg), dim3(sc::walk_threads(RT)), 0, s, dg, nvec, ch, kSeg, Psi, W);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL((sc::k_cs_out<F, RT, ACC, FIN>), dim3(P->nblocks, nvg), blk, 0, s, dg, nvec,
                        P->blk_field.as<int>(), P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const C*)W, x,

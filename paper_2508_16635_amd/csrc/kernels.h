@@ -1890,51 +1890,138 @@ __device__ inline void stage_x(const cpx<F>* __restrict__ W, int N, int wcap, lo
       });
 }
 
-// Sequential walk: x_0 = W[blk(0)], then for t = 1..nsteps: W[blk(t)] = W[blk(t)] +
-// sign M_{blk(t)} x_{t-1}, x_t = that result.  Two register sets alternate so that the operands
-// of step t+1 load while step t computes.
-template <class F, int RT, class BlockOf>
-__device__ inline void chain_walk(int N, int wcap, const cpx<F>* __restrict__ frags, cpx<F>* __restrict__ W, int v0,
-                                  int nsteps, BlockOf blk_of, F sign, cpx<F>* xbuf) {
-  typedef ChainOps<F, RT> Ops;
-  Ops op(N, wcap);
-  typename Ops::Set S0, S1;
-  stage_x<F>(W, N, wcap, blk_of(0), v0, xbuf, xbuf + 64 * kVG);
-  auto load = [&](int t, typename Ops::Set& S) {
-    const long long b = blk_of(t < nsteps ? t : nsteps);
-    op.load_frag(frags, b, S);
-    op.load_w(W, b, v0, S);
-  };
-  if (op.active()) load(1, S0);
-  __syncthreads();
-  auto body = [&](int t, typename Ops::Set& cur, typename Ops::Set& nxt, int pb) {
-    if (op.active()) {
-      load(t + 1, nxt);
-      __builtin_amdgcn_sched_barrier(0);
-      typename Ops::acc_t yr, yi;
-      op.apply(cur, xbuf + pb * 64 * kVG, yr, yi);
-      cpx<F>* xo = xbuf + (pb ^ 1) * 64 * kVG;
-      const long long b = blk_of(t);
+// Walks with the k-steps of each row tile split over four waves.  One CU's matrix cores bound a
+// walk step (a complex N x N by N x 16 product per chain or segment), so the step's products
+// are spread over all four SIMDs: the 4 RT k-steps of each row tile are split into KQ groups
+// (four, two at four row tiles, whose 8 waves then keep 256 VGPRs each), wave (rt, kq) of the
+// RT KQ waves multiplies the KW = 4 RT / KQ k-steps of group kq of row tile rt (the Gauss sums
+// of 3 KW matrix-core products instead of 12 RT), writes its partial product to LDS, and after
+// one barrier every wave sums the KQ partials of the x rows its own k-steps read next,
+// x[4 s + l/16][l % 16], straight into registers in the B-operand layout (xrow[j] for its
+// k-step j); the waves of row tile 0 store the result.  The partials are double-buffered, so one barrier per step suffices: a buffer is
+// written again only after the barrier that every reader of its previous contents has passed.
+// Operands are loaded PD steps ahead into a ring of register sets, unconditionally (indices
+// clamped), and steps past the end (padding to a multiple of PD) store nothing.
+__host__ __device__ constexpr int walk_kq(int rt) { return rt >= 4 ? 2 : 4; }
+__host__ __device__ constexpr int walk_threads(int rt) { return 64 * rt * walk_kq(rt); }
+template <int RT>
+constexpr int walk_part_entries() {  // two buffers of [kq][row][column] partials
+  return 2 * walk_kq(RT) * 16 * RT * kVG;
+}
+// operand sets in flight in a boundary walk: three, two at four row tiles (eight k-steps per wave)
+template <int RT>
+constexpr int walk_depth() {
+  return RT >= 4 ? 2 : 3;
+}
+
+template <class F, int RT>
+struct KqWave {
+  static constexpr int KQ = walk_kq(RT), KW = 4 * RT / KQ, KS = 4 * RT, FB = 256 * RT * RT,
+                       PBUF = KQ * 16 * RT * kVG;
+  typedef typename Mfma<F>::acc_t acc_t;
+  int rt, kq, l, col;
+  int xrow[KW], xrowc[KW];  // x rows of this lane's B operands (clamped into [0, N))
+  __device__ explicit KqWave(int N) {
+    const int wv = threadIdx.x >> 6;
+    rt = wv / KQ;
+    kq = wv % KQ;
+    l = threadIdx.x & 63;
+    col = l & 15;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = op.row(q);
-        if (r < N) {
-          const cpx<F> y = {cur.w[q].re + sign * yr[q], cur.w[q].im + sign * yi[q]};
-          xo[r * kVG + op.col] = y;
-          W[(b * N + r) * wcap + v0 + op.col] = y;
-        }
-      }
+    for (int j = 0; j < KW; ++j) {
+      xrow[j] = 4 * (kq * KW + j) + (l >> 4);
+      xrowc[j] = xrow[j] < N ? xrow[j] : N - 1;
     }
-    __syncthreads();
+  }
+  __device__ inline void load(const cpx<F>* __restrict__ frags, long long blk, F (&ar)[KW], F (&ai)[KW]) const {
+    const cpx<F>* p = frags + blk * FB + (long long)(rt * KS + kq * KW) * 64 + l;
+#pragma unroll
+    for (int j = 0; j < KW; ++j) {
+      const cpx<F> v = p[j * 64];
+      ar[j] = v.re;
+      ai[j] = v.im;
+    }
+  }
+  // Gauss sums of M x over this wave's k-steps added into (p1, p2, p3)
+  __device__ inline void gauss(const F (&ar)[KW], const F (&ai)[KW], const cpx<F> (&x)[KW], acc_t& p1, acc_t& p2,
+                               acc_t& p3) const {
+#pragma unroll
+    for (int j = 0; j < KW; ++j) {
+      p1 = Mfma<F>::step(ar[j], x[j].re, p1);
+      p2 = Mfma<F>::step(ai[j], x[j].im, p2);
+      p3 = Mfma<F>::step(ar[j] + ai[j], x[j].re + x[j].im, p3);
+    }
+  }
+  __device__ inline void put(cpx<F>* buf, const acc_t& p1, const acc_t& p2, const acc_t& p3) const {
+    cpx<F>* pw = buf + kq * (16 * RT * kVG);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 16 * rt + Mfma<F>::out_row(l, q);
+      pw[r * kVG + col] = cpx<F>{p1[q] - p2[q], p3[q] - p1[q] - p2[q]};
+    }
+  }
+  __device__ inline cpx<F> sum(const cpx<F>* buf, int j) const {
+    const int o = xrow[j] * kVG + col;
+    constexpr int S = 16 * RT * kVG;
+    if (KQ == 2) {
+      const cpx<F> s0 = buf[o], s1 = buf[S + o];
+      return cpx<F>{s0.re + s1.re, s0.im + s1.im};
+    }
+    const cpx<F> s0 = buf[o], s1 = buf[S + o], s2 = buf[2 * S + o], s3 = buf[3 * S + o];
+    return cpx<F>{(s0.re + s1.re) + (s2.re + s3.re), (s0.im + s1.im) + (s2.im + s3.im)};
+  }
+};
+
+// Boundary walk: x_0 = W[blk(0)]; for t = 1..nsteps: W[blk(t)] = W[blk(t)] + sign M_blk(t) x_{t-1},
+// x_t = that result.
+template <class F, int RT, int PD, class BlockOf>
+__device__ inline void chain_walk_kq(int N, int wcap, const cpx<F>* __restrict__ frags, cpx<F>* __restrict__ W, int v0,
+                                     int nsteps, BlockOf blk_of, F sign, cpx<F>* part) {
+  typedef KqWave<F, RT> Kw;
+  typedef typename Kw::acc_t acc_t;
+  const Kw kw(N);
+  struct Set {
+    F ar[Kw::KW], ai[Kw::KW];
+    cpx<F> wx[Kw::KW];
   };
-  int pb = 0;
-  for (int t = 1; t <= nsteps; t += 2) {
-    body(t, S0, S1, pb);
-    pb ^= 1;
-    if (t + 1 <= nsteps) {
-      body(t + 1, S1, S0, pb);
-      pb ^= 1;
+  auto load = [&](int t, Set& S) {
+    const long long b = blk_of(t < nsteps ? t : nsteps);
+    kw.load(frags, b, S.ar, S.ai);
+#pragma unroll
+    for (int j = 0; j < Kw::KW; ++j) S.wx[j] = W[(b * N + kw.xrowc[j]) * wcap + v0 + kw.col];
+  };
+  cpx<F> x[Kw::KW];
+  {
+    const long long b0 = blk_of(0);
+#pragma unroll
+    for (int j = 0; j < Kw::KW; ++j) {
+      const cpx<F> v = W[(b0 * N + kw.xrowc[j]) * wcap + v0 + kw.col];
+      x[j] = kw.xrow[j] < N ? v : cpx<F>{0, 0};
     }
+  }
+  Set S[PD];
+#pragma unroll
+  for (int d = 0; d < PD; ++d) load(1 + d, S[d]);
+  int pb = 0;
+  auto body = [&](int t, Set& cur) {
+    acc_t p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+    kw.gauss(cur.ar, cur.ai, x, p1, p2, p3);
+    kw.put(part + pb * Kw::PBUF, p1, p2, p3);
+    __syncthreads();
+    const long long b = blk_of(t <= nsteps ? t : nsteps);
+#pragma unroll
+    for (int j = 0; j < Kw::KW; ++j) {
+      const cpx<F> sm = kw.sum(part + pb * Kw::PBUF, j);
+      const cpx<F> y = {cur.wx[j].re + sign * sm.re, cur.wx[j].im + sign * sm.im};
+      x[j] = kw.xrow[j] < N ? y : cpx<F>{0, 0};
+      if (kw.rt == 0 && kw.xrow[j] < N && t <= nsteps) W[(b * N + kw.xrow[j]) * wcap + v0 + kw.col] = y;
+    }
+    load(t + PD, cur);
+    pb ^= 1;
+  };
+  for (int t = 1; t <= nsteps; t += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) body(t + d, S[d]);
   }
 }
 
@@ -1942,76 +2029,83 @@ __device__ inline void chain_walk(int N, int wcap, const cpx<F>* __restrict__ fr
 // of the segment (D_i = diag(sc_i) Shat_i^{-1} diag(sr_i) diag(Rg_i), the scalings folded into
 // the stored blocks) and the local recurrence zeta_a = c_a, zeta_i = c_i - G_i zeta_{i-1},
 // stored in W (zero columns beyond nvec).  Each step sums both products in one set of Gauss
-// sums; b is read from the FP64 input straight into the B-operand layout, and the operands of
-// step t+1 (D, G fragments and b) load while step t multiplies.
+// sums on the k-split waves (see KqWave); b is read from the FP64 input straight into the
+// B-operand layout (rows and vectors clamped, masked at use), and the operands of the next two
+// steps are in flight (local_sets).  One workgroup of RT KQ waves per (segment, vector group).
+// Operand sets of a local walk: the loads of step t + NS - 1 are issued (behind a scheduling
+// barrier, so that the compiler keeps them there) before the products of step t; two sets at
+// three row tiles (three would spill there), one at four (eight k-steps of two blocks per wave).
+template <int RT>
+constexpr int local_sets() {
+  return RT >= 4 ? 1 : RT >= 3 ? 2 : 3;
+}
 template <class F, int RT>
-__global__ void __launch_bounds__(kSolveThreads, 1) k_cs_fwd_rhs(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
-                                                                const int* __restrict__ blk_field,
-                                                                const int* __restrict__ blk_lm,
-                                                                const cpx<F>* __restrict__ Dm,
-                                                                const cpx<F>* __restrict__ Gm,
-                                                                const double* __restrict__ bvec,
-                                                                cpx<F>* __restrict__ W) {
-  __shared__ cpx<F> xb[2 * 64 * kVG];
-  typedef ChainOps<F, RT> Ops;
-  constexpr int KS = Ops::KS;
+__global__ void __launch_bounds__(walk_threads(RT), 1) k_cs_fwd_rhs(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
+                                                                     const int* __restrict__ blk_field,
+                                                                     const int* __restrict__ blk_lm,
+                                                                     const cpx<F>* __restrict__ Dm,
+                                                                     const cpx<F>* __restrict__ Gm,
+                                                                     const double* __restrict__ bvec,
+                                                                     cpx<F>* __restrict__ W) {
+  __shared__ cpx<F> part[walk_part_entries<RT>()];
+  typedef KqWave<F, RT> Kw;
+  typedef typename Kw::acc_t acc_t;
   const SegMeta sg = segs[blockIdx.x];
   const int N = g.N, a = sg.first_block, len = sg.len, v0 = blockIdx.y * kVG, nv = min(kVG, nvec - v0);
-  Ops op(N, g.wcap);
-  // rows N..63 of both buffers are read as zero operands and never written by the steps
-  for (int idx = N * kVG + threadIdx.x; idx < 64 * kVG; idx += kSolveThreads) {
-    xb[idx] = cpx<F>{0, 0};
-    xb[64 * kVG + idx] = cpx<F>{0, 0};
-  }
-  struct Set {
-    F dr[KS], di[KS], gr[KS], gi[KS];
-    cpx<F> b[KS];
-  };
+  const Kw kw(N);
   const long long ld = 6LL * N * g.S;
+  const long long vrow = (long long)(v0 + min(kw.col, nv - 1)) * ld;  // this lane's vector, clamped
+  bool bok[Kw::KW];
+#pragma unroll
+  for (int j = 0; j < Kw::KW; ++j) bok[j] = kw.xrow[j] < N && kw.col < nv;
+  struct Set {
+    F dr[Kw::KW], di[Kw::KW], gr[Kw::KW], gi[Kw::KW];
+    double2 b[Kw::KW];
+  };
   auto load = [&](int t, Set& S) {
     const long long blk = a + (t < len ? t : len - 1);
-    op.load_ops(Dm, blk, S.dr, S.di);
-    op.load_ops(Gm, blk, S.gr, S.gi);
-    const double* bp = bvec + (long long)(v0 + op.col) * ld + 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + blk_lm[blk]));
+    kw.load(Dm, blk, S.dr, S.di);
+    kw.load(Gm, blk, S.gr, S.gi);
+    const double* bp = bvec + vrow + 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + blk_lm[blk]));
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int r = 4 * ks + (op.l >> 4);
-      S.b[ks] = cpx<F>{0, 0};
-      if (r < N && op.col < nv) S.b[ks] = cpx<F>{(F)bp[2 * r], (F)bp[2 * r + 1]};
-    }
+    for (int j = 0; j < Kw::KW; ++j) S.b[j] = *reinterpret_cast<const double2*>(bp + 2 * kw.xrowc[j]);
   };
-  Set S0, S1;
-  if (op.active()) load(0, S0);
-  __syncthreads();
-  auto body = [&](int t, Set& cur, Set& nxt, int pb) {
-    if (op.active()) {
-      load(t + 1, nxt);
-      __builtin_amdgcn_sched_barrier(0);
-      typename Ops::acc_t p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
-      op.acc_reg(cur.dr, cur.di, cur.b, p1, p2, p3);
-      if (t > 0) op.acc_lds(cur.gr, cur.gi, xb + pb * 64 * kVG, (F)-1, p1, p2, p3);
-      cpx<F>* xo = xb + (pb ^ 1) * 64 * kVG;
-      const long long blk = a + t;
+  cpx<F> x[Kw::KW];  // -zeta_{i-1} in the B-operand layout (zero before the first step)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = op.row(q);
-        if (r < N) {
-          const cpx<F> y = {p1[q] - p2[q], p3[q] - p1[q] - p2[q]};
-          xo[r * kVG + op.col] = y;
-          W[(blk * N + r) * g.wcap + v0 + op.col] = y;
-        }
-      }
+  for (int j = 0; j < Kw::KW; ++j) x[j] = cpx<F>{0, 0};
+  constexpr int NS = local_sets<RT>();
+  Set S[NS];
+#pragma unroll
+  for (int d = 0; d + 1 < NS; ++d) load(d, S[d]);
+  int pb = 0;
+  // steps past the segment (padding to a multiple of NS) skip the products and store nothing
+  auto body = [&](int t, Set& cur, Set& ahead) {
+    load(t + NS - 1, ahead);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t < len) {
+      acc_t p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+      cpx<F> bv[Kw::KW];
+#pragma unroll
+      for (int j = 0; j < Kw::KW; ++j) bv[j] = bok[j] ? cpx<F>{(F)cur.b[j].x, (F)cur.b[j].y} : cpx<F>{0, 0};
+      kw.gauss(cur.dr, cur.di, bv, p1, p2, p3);
+      kw.gauss(cur.gr, cur.gi, x, p1, p2, p3);
+      kw.put(part + pb * Kw::PBUF, p1, p2, p3);
     }
     __syncthreads();
-  };
-  int pb = 0;
-  for (int t = 0; t < len; t += 2) {
-    body(t, S0, S1, pb);
-    pb ^= 1;
-    if (t + 1 < len) {
-      body(t + 1, S1, S0, pb);
-      pb ^= 1;
+    if (t < len) {
+      const long long blk = a + t;
+#pragma unroll
+      for (int j = 0; j < Kw::KW; ++j) {
+        const cpx<F> y = kw.sum(part + pb * Kw::PBUF, j);
+        x[j] = kw.xrow[j] < N ? cpx<F>{-y.re, -y.im} : cpx<F>{0, 0};
+        if (kw.rt == 0 && kw.xrow[j] < N) W[(blk * N + kw.xrow[j]) * g.wcap + v0 + kw.col] = y;
+      }
     }
+    pb ^= 1;
+  };
+  for (int t = 0; t < len; t += NS) {
+#pragma unroll
+    for (int d = 0; d < NS; ++d) body(t + d, S[d], S[(d + NS - 1) % NS]);
   }
 }
 
@@ -2271,101 +2365,102 @@ __global__ void __launch_bounds__(kSolveThreads, 1) k_cs1_bwd_fix(DevGrid g, con
 }
 
 // Boundary pass of the forward recurrence: z_e(p) = zeta_e(p) + Phi_e(p) z_e(p-1).
+// One workgroup of RT KQ waves per (chain, vector group).
 template <class F, int RT>
-__global__ void __launch_bounds__(kSolveThreads, 1) k_cs_fwd_bound(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
-                                                                  int seg, const cpx<F>* __restrict__ Phi,
-                                                                  cpx<F>* __restrict__ W) {
-  __shared__ cpx<F> xb[2 * 64 * kVG];
+__global__ void __launch_bounds__(walk_threads(RT), 1) k_cs_fwd_bound(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
+                                                                       int seg, const cpx<F>* __restrict__ Phi,
+                                                                       cpx<F>* __restrict__ W) {
+  __shared__ cpx<F> part[walk_part_entries<RT>()];
   const ChainMeta ch = chains[blockIdx.x];
   if (ch.nseg <= 1) return;
   const int st = ch.start, n = ch.n;
-  chain_walk<F, RT>(g.N, g.wcap, Phi, W, blockIdx.y * kVG, ch.nseg - 1,
-                    [&](int p) { return (long long)(st + min((p + 1) * seg, n) - 1); }, (F)1, xb);
+  chain_walk_kq<F, RT, walk_depth<RT>()>(g.N, g.wcap, Phi, W, blockIdx.y * kVG, ch.nseg - 1,
+                                   [&](int p) { return (long long)(st + min((p + 1) * seg, n) - 1); }, (F)1, part);
 }
 
 // Backward pass of one segment [a, e] with the forward fix-up: the forward values of a segment
 // p > 0 are completed on the way, z_i = zeta_i + Phi_i z_{a-1} (z_{a-1}, the previous segment's
 // last value, and z_e are final after the forward boundary pass), and the local backward
 // recurrence xi_e = z_e, xi_i = z_i - H_i xi_{i+1} runs from e down to a, stored in W.  Each
-// step sums both products in one set of Gauss sums; z_{a-1} is held in registers in the
-// B-operand layout, and the operands of step t+1 load while step t multiplies.
+// step sums both products in one set of Gauss sums on the k-split waves (see KqWave); z_{a-1}
+// is held in registers in the B-operand layout (zero in a chain's first segment, whose Phi
+// blocks are then multiplied by zero), and the operands of the next two steps are in flight.
 template <class F, int RT>
-__global__ void __launch_bounds__(kSolveThreads, 1) k_cs_bwd_fix(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
-                                                                const cpx<F>* __restrict__ Phi,
-                                                                const cpx<F>* __restrict__ H, cpx<F>* __restrict__ W) {
-  __shared__ cpx<F> xb[2 * 64 * kVG];
-  typedef ChainOps<F, RT> Ops;
-  constexpr int KS = Ops::KS;
+__global__ void __launch_bounds__(walk_threads(RT), 1) k_cs_bwd_fix(DevGrid g, int nvec, const SegMeta* __restrict__ segs,
+                                                                     const cpx<F>* __restrict__ Phi,
+                                                                     const cpx<F>* __restrict__ H, cpx<F>* __restrict__ W) {
+  __shared__ cpx<F> part[walk_part_entries<RT>()];
+  typedef KqWave<F, RT> Kw;
+  typedef typename Kw::acc_t acc_t;
   const SegMeta sg = segs[blockIdx.x];
   if (sg.len <= 1) return;
   const int N = g.N, a = sg.first_block, len = sg.len, e = a + len - 1, v0 = blockIdx.y * kVG;
   const bool fix = sg.pidx > 0;
-  Ops op(N, g.wcap);
-  stage_x<F>(W, N, g.wcap, e, v0, xb, xb + 64 * kVG);
-  cpx<F> zs[KS];
+  const Kw kw(N);
+  const long long ap = a > 0 ? a - 1 : 0;
+  cpx<F> x[Kw::KW], zs[Kw::KW];  // -xi_{i+1} and z_{a-1}
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    const int r = 4 * ks + (op.l >> 4);
-    zs[ks] = cpx<F>{0, 0};
-    if (fix && r < N) zs[ks] = W[((long long)(a - 1) * N + r) * g.wcap + v0 + op.col];
+  for (int j = 0; j < Kw::KW; ++j) {
+    const cpx<F> v = W[((long long)e * N + kw.xrowc[j]) * g.wcap + v0 + kw.col];
+    const cpx<F> z = W[(ap * N + kw.xrowc[j]) * g.wcap + v0 + kw.col];
+    x[j] = kw.xrow[j] < N ? cpx<F>{-v.re, -v.im} : cpx<F>{0, 0};
+    zs[j] = (fix && kw.xrow[j] < N) ? z : cpx<F>{0, 0};
   }
   struct Set {
-    F hr[KS], hi[KS], pr[KS], pi[KS];
-    cpx<F> w[4];
+    F hr[Kw::KW], hi[Kw::KW], pr[Kw::KW], pi[Kw::KW];
+    cpx<F> w[Kw::KW];
   };
   auto load = [&](int t, Set& S) {
     const long long blk = e - (t < len ? t : len - 1);
-    op.load_ops(H, blk, S.hr, S.hi);
-    if (fix) op.load_ops(Phi, blk, S.pr, S.pi);
+    kw.load(H, blk, S.hr, S.hi);
+    kw.load(Phi, blk, S.pr, S.pi);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) S.w[q] = W[(blk * N + op.rowc[q]) * g.wcap + v0 + op.col];
+    for (int j = 0; j < Kw::KW; ++j) S.w[j] = W[(blk * N + kw.xrowc[j]) * g.wcap + v0 + kw.col];
   };
-  Set S0, S1;
-  if (op.active()) load(1, S0);
-  __syncthreads();
-  auto body = [&](int t, Set& cur, Set& nxt, int pb) {
-    if (op.active()) {
-      load(t + 1, nxt);
-      __builtin_amdgcn_sched_barrier(0);
-      typename Ops::acc_t p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
-      if (fix) op.acc_reg(cur.pr, cur.pi, zs, p1, p2, p3);
-      op.acc_lds(cur.hr, cur.hi, xb + pb * 64 * kVG, (F)-1, p1, p2, p3);
-      cpx<F>* xo = xb + (pb ^ 1) * 64 * kVG;
-      const long long blk = e - t;
+  constexpr int NS = local_sets<RT>();
+  Set S[NS];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = op.row(q);
-        if (r < N) {
-          const cpx<F> y = {cur.w[q].re + p1[q] - p2[q], cur.w[q].im + p3[q] - p1[q] - p2[q]};
-          xo[r * kVG + op.col] = y;
-          W[(blk * N + r) * g.wcap + v0 + op.col] = y;
-        }
-      }
+  for (int d = 0; d + 1 < NS; ++d) load(1 + d, S[d]);
+  int pb = 0;
+  auto body = [&](int t, Set& cur, Set& ahead) {
+    load(t + NS - 1, ahead);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t < len) {
+      acc_t p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+      kw.gauss(cur.pr, cur.pi, zs, p1, p2, p3);
+      kw.gauss(cur.hr, cur.hi, x, p1, p2, p3);
+      kw.put(part + pb * Kw::PBUF, p1, p2, p3);
     }
     __syncthreads();
-  };
-  int pb = 0;
-  for (int t = 1; t < len; t += 2) {
-    body(t, S0, S1, pb);
-    pb ^= 1;
-    if (t + 1 < len) {
-      body(t + 1, S1, S0, pb);
-      pb ^= 1;
+    if (t < len) {
+      const long long blk = e - t;
+#pragma unroll
+      for (int j = 0; j < Kw::KW; ++j) {
+        const cpx<F> sm = kw.sum(part + pb * Kw::PBUF, j);
+        const cpx<F> y = {cur.w[j].re + sm.re, cur.w[j].im + sm.im};
+        x[j] = kw.xrow[j] < N ? cpx<F>{-y.re, -y.im} : cpx<F>{0, 0};
+        if (kw.rt == 0 && kw.xrow[j] < N) W[(blk * N + kw.xrow[j]) * g.wcap + v0 + kw.col] = y;
+      }
     }
+    pb ^= 1;
+  };
+  for (int t = 1; t < len; t += NS) {
+#pragma unroll
+    for (int d = 0; d < NS; ++d) body(t + d, S[d], S[(d + NS - 1) % NS]);
   }
 }
 
 // Boundary pass of the backward recurrence: x_a(p) = xi_a(p) + Psi_a(p) x_a(p+1).
 template <class F, int RT>
-__global__ void __launch_bounds__(kSolveThreads, 1) k_cs_bwd_bound(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
-                                                                  int seg, const cpx<F>* __restrict__ Psi,
-                                                                  cpx<F>* __restrict__ W) {
-  __shared__ cpx<F> xb[2 * 64 * kVG];
+__global__ void __launch_bounds__(walk_threads(RT), 1) k_cs_bwd_bound(DevGrid g, int nvec, const ChainMeta* __restrict__ chains,
+                                                                       int seg, const cpx<F>* __restrict__ Psi,
+                                                                       cpx<F>* __restrict__ W) {
+  __shared__ cpx<F> part[walk_part_entries<RT>()];
   const ChainMeta ch = chains[blockIdx.x];
   if (ch.nseg <= 1) return;
   const int st = ch.start, last = ch.nseg - 1;
-  chain_walk<F, RT>(g.N, g.wcap, Psi, W, blockIdx.y * kVG, ch.nseg - 1,
-                    [&](int t) { return (long long)(st + (last - t) * seg); }, (F)1, xb);
+  chain_walk_kq<F, RT, walk_depth<RT>()>(g.N, g.wcap, Psi, W, blockIdx.y * kVG, ch.nseg - 1,
+                                   [&](int t) { return (long long)(st + (last - t) * seg); }, (F)1, part);
 }
 
 // x_i = xi_i + Psi_i x_{a(p+1)} for the blocks not yet final, then x = Cg x~ into the

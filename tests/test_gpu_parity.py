@@ -92,6 +92,31 @@ def test_jvp(lib, cfg, prec, solve, tol, btol):
         check(lay, Y[i], ora.jvp(V[i]), tol, btol, f"cfg={cfg} prec={prec} solve={solve} vec {i}")
 
 
+# N = 52: every block spans four 16-row tiles (the largest chain-solve shape, 16 waves per
+# boundary-walk workgroup); at L = 24 the chains hold 2-4 segments, so the boundary walks take
+# several steps
+FOUR_TILES = (24, 24, 4, 52, 1e-3, 78.0, 200.0)
+
+
+@pytest.mark.parametrize("prec,solve,tol,btol", [(0, 0, 1e-12, FP64_BLOCK), (1, 1, 1e-6, 1e-5), (1, 2, 1e-6, 1e-5)],
+                         ids=["fp64", "mixed-fp64solve", "mixed-fp32solve-refined"])
+def test_jvp_four_row_tiles(lib, prec, solve, tol, btol):
+    """17 vectors in one call (a full vector group and a one-column one) at N = 52; sampled
+    actions of both groups against the oracle."""
+    plan, ora, lay = _setup(lib, FOUR_TILES, nvec=17, mixed_solve=solve)
+    X = si.random_state(lay, 111, amp=(1e-2, 1e-2, 1e-2), p=2) + ora.conductive_state()
+    J = si.default_phase_slot(lay, X)
+    plan.set_base(_dev(X), 0.3, J)
+    ora.set_base(X, 0.3, J)
+    V = si.random_vectors(lay, range(1201, 1218))
+    vd = _dev(V)
+    yd = torch.empty_like(vd)
+    plan.jvp(vd, yd, prec)
+    Y = _host(yd)
+    for i in (0, 9, 16):
+        check(lay, Y[i], ora.jvp(V[i]), tol, btol, f"N=52 prec={prec} solve={solve} vec {i}")
+
+
 @pytest.mark.parametrize("cfg", SMALL)
 @pytest.mark.parametrize("prec,solve,tol,btol", [(0, 0, 1e-12, FP64_BLOCK), (1, 1, 1e-6, 1e-5), (1, 2, 1e-6, 1e-5)],
                          ids=["fp64", "mixed-fp64solve", "mixed-fp32solve-refined"])
