@@ -703,7 +703,7 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
   HIPCHK(hipGetLastError());
 }
 
-constexpr int kSeg = 8;   // blocks per scan segment
+constexpr int kSeg = 10;  // blocks per scan segment
 using sc::kVG;            // vectors per workgroup in the chain solves
 
 // Projection launch for RT = ceil(N/16) output row tiles.
