@@ -704,6 +704,7 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
 }
 
 constexpr int kSeg = 10;  // blocks per scan segment
+static_assert(kSeg <= sc::kSegMax, "the one-vector local walks hold a segment in LDS");
 using sc::kVG;            // vectors per workgroup in the chain solves
 
 // Projection launch for RT = ceil(N/16) output row tiles.
@@ -755,14 +756,15 @@ void chain_solve_rt(sc_plan* P, int nvec, const double* b, double* x, const sc::
   if (nvec == 1) {
     // one right-hand side: the walks on the vector units with deeper operand prefetch (a
     // 16-column matrix-core step would carry 15 columns of padding)
-    hipLaunchKernelGGL((sc::k_cs1_fwd_rhs<F, RT>), dim3(P->nsegs), blk, 0, s, dg, sg, P->blk_field.as<int>(),
+    const dim3 wblk(sc::walk_threads(RT));
+    hipLaunchKernelGGL((sc::k_cs1_fwd_rhs<F, RT>), dim3(P->nsegs), wblk, 0, s, dg, sg, P->blk_field.as<int>(),
                        P->blk_lm.as<int>(), Dm, Gm, b, W);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_cs1_fwd_bound<F, RT>), dim3(P->nchains), blk, 0, s, dg, ch, kSeg, Phi, W);
+    hipLaunchKernelGGL((sc::k_cs1_fwd_bound<F, RT>), dim3(P->nchains), wblk, 0, s, dg, ch, kSeg, Phi, W);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_cs1_bwd_fix<F, RT>), dim3(P->nsegs), blk, 0, s, dg, sg, Phi, H, W);
+    hipLaunchKernelGGL((sc::k_cs1_bwd_fix<F, RT>), dim3(P->nsegs), wblk, 0, s, dg, sg, Phi, H, W);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((sc::k_cs1_bwd_bound<F, RT>), dim3(P->nchains), blk, 0, s, dg, ch, kSeg, Psi, W);
+    hipLaunchKernelGGL((sc::k_cs1_bwd_bound<F, RT>), dim3(P->nchains), wblk, 0, s, dg, ch, kSeg, Psi, W);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL((sc::k_cs1_out<F, RT, ACC, FIN>), dim3(P->nblocks), blk, 0, s, dg, P->blk_field.as<int>(),
                        P->blk_lm.as<int>(), P->blk_next.as<int>(), Psi, Cg, (const C*)W, x, fo);

@@ -2076,7 +2076,10 @@ __global__ void __launch_bounds__(walk_threads(RT), 1) k_cs_fwd_rhs(DevGrid g, i
   constexpr int NS = local_sets<RT>();
   Set S[NS];
 #pragma unroll
-  for (int d = 0; d + 1 < NS; ++d) load(d, S[d]);
+  for (int d = 0; d + 1 < NS; ++d) {
+    load(d, S[d]);
+    __builtin_amdgcn_sched_barrier(0);  // the sets in issue order (the waits count in order)
+  }
   int pb = 0;
   // steps past the segment (padding to a multiple of NS) skip the products and store nothing
   auto body = [&](int t, Set& cur, Set& ahead) {
@@ -2109,14 +2112,11 @@ __global__ void __launch_bounds__(walk_threads(RT), 1) k_cs_fwd_rhs(DevGrid g, i
   }
 }
 
-// Block products for one right-hand side (nvec = 1) on the vector units.  A 16-column
-// matrix-core product would spend 15 of its columns on padding, and a walk step would wait on
-// it.  Lane l of wave w (w < RT) holds the operands it would feed to the matrix cores,
-// M[16 w + l%16][4 s + l/16] for the k-steps s, forms that row's partial sum over the columns
-// = l/16 (mod 4), and the four partial sums of a row meet by lane exchanges (rowsum4).  Waves
-// beyond the row tiles load the last tile's operands and write nothing, and no load sits under
-// a branch: the compiler then keeps every register set of a prefetch ring in place and waits
-// only for the set in use (a conditional load is copied into the ring and waited for at once).
+// Block product for one right-hand side (nvec = 1) on the vector units, the output kernel's
+// layout: lane l of wave w (w < RT) holds M[16 w + l%16][4 s + l/16] for every k-step s, forms
+// that row's partial sum over the columns = l/16 (mod 4), and the four partial sums of a row
+// meet by lane exchanges (rowsum4).  Waves beyond the row tiles load the last tile's operands
+// and write nothing.
 template <class F, int RT>
 struct Lane1 {
   static constexpr int KS = 4 * RT, FB = 256 * RT * RT;
@@ -2139,24 +2139,6 @@ struct Lane1 {
       ai[ks] = v.im;
     }
   }
-  // (re, im) += sgn * row part of M x, x in LDS (64 entries)
-  __device__ inline void dot_lds(const F (&ar)[KS], const F (&ai)[KS], const cpx<F>* x, F sgn, F& re, F& im) const {
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const cpx<F> xv = x[4 * ks + c0];
-      const F xr = sgn * xv.re, xi = sgn * xv.im;
-      re += ar[ks] * xr - ai[ks] * xi;
-      im += ar[ks] * xi + ai[ks] * xr;
-    }
-  }
-  // (re, im) += row part of M x, x in registers (xv[ks] = x[4 ks + l/16])
-  __device__ inline void dot_reg(const F (&ar)[KS], const F (&ai)[KS], const cpx<F> (&xv)[KS], F& re, F& im) const {
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      re += ar[ks] * xv[ks].re - ai[ks] * xv[ks].im;
-      im += ar[ks] * xv[ks].im + ai[ks] * xv[ks].re;
-    }
-  }
   __device__ static inline void rowsum4(F& re, F& im) {
     re += __shfl_xor(re, 16);
     im += __shfl_xor(im, 16);
@@ -2165,202 +2147,307 @@ struct Lane1 {
   }
 };
 
-// Sequential walk for one right-hand side: x_0 = W[blk(0)], then W[blk(t)] = W[blk(t)] +
-// sign M_{blk(t)} x_{t-1}, x_t = that result, for t = 1..nsteps.  The operands of PD steps are in
-// flight (a ring of register sets); steps past nsteps (padding to a multiple of PD) write
-// nothing.  x sits in LDS (64 entries, rows >= N zero).
-template <class F, int RT, int PD, class BlockOf>
-__device__ inline void chain_walk1(int N, int wcap, const cpx<F>* __restrict__ frags, cpx<F>* __restrict__ W,
-                                   int nsteps, BlockOf blk_of, F sign, cpx<F>* xbuf) {
-  typedef Lane1<F, RT> Ln;
-  constexpr int KS = Ln::KS;
-  const Ln ln(N);
-  struct Set {
-    F ar[KS], ai[KS];
-    cpx<F> wv;
-  };
-  {
-    const long long b0 = blk_of(0);
-    for (int i = threadIdx.x; i < 64; i += blockDim.x) {
-      const cpx<F> v = i < N ? W[(b0 * N + i) * wcap] : cpx<F>{0, 0};
-      xbuf[i] = v;
-      xbuf[64 + i] = cpx<F>{0, 0};
+// Walks for one right-hand side (nvec = 1) on the vector units, with the waves of KqWave: lane l
+// of wave (rt, kq) holds the operands M[16 rt + l%16][4 s + l/16] of its group's k-steps s
+// (the stored MFMA operand order) and the entries x[4 s + l/16] they multiply, forms its part
+// of row 16 rt + l%16, and the four parts of a row meet by lane exchanges; the groups' sums meet
+// through LDS (double-buffered, one barrier per step), and every lane then sums the x entries
+// its own k-steps read next straight into registers.  A 16-column matrix-core product would
+// spend 15 of its columns on padding.  A lane's operand set is KW fragments per block plus KW
+// right-hand-side or w entries, so the sets of several steps stay within the 63 loads the
+// memory counter tracks.
+template <class F, int RT>
+struct Kq1 {
+  static constexpr int KQ = walk_kq(RT), KW = 4 * RT / KQ, KS = 4 * RT, FB = 256 * RT * RT, PBUF = KQ * 64;
+  int rt, kq, l, c0, row;
+  int xrow[KW], xrowc[KW];
+  bool writer;  // column-0 lanes of row tile 0 store the x entries they hold
+  __device__ explicit Kq1(int N) {
+    const int wv = threadIdx.x >> 6;
+    rt = wv / KQ;
+    kq = wv % KQ;
+    l = threadIdx.x & 63;
+    c0 = l >> 4;
+    row = 16 * rt + (l & 15);
+#pragma unroll
+    for (int j = 0; j < KW; ++j) {
+      xrow[j] = 4 * (kq * KW + j) + c0;
+      xrowc[j] = xrow[j] < N ? xrow[j] : N - 1;
+    }
+    writer = rt == 0 && (l & 15) == 0;
+  }
+  __device__ inline void load(const cpx<F>* __restrict__ frags, long long blk, F (&ar)[KW], F (&ai)[KW]) const {
+    const cpx<F>* p = frags + blk * FB + (long long)(rt * KS + kq * KW) * 64 + l;
+#pragma unroll
+    for (int j = 0; j < KW; ++j) {
+      const cpx<F> v = p[j * 64];
+      ar[j] = v.re;
+      ai[j] = v.im;
     }
   }
+  // (re, im) += this lane's part of row M x
+  __device__ static inline void dot(const F (&ar)[KW], const F (&ai)[KW], const cpx<F> (&x)[KW], F& re, F& im) {
+#pragma unroll
+    for (int j = 0; j < KW; ++j) {
+      re += ar[j] * x[j].re - ai[j] * x[j].im;
+      im += ar[j] * x[j].im + ai[j] * x[j].re;
+    }
+  }
+  // the row's sum over this group's k-steps into buf[kq][row]
+  __device__ inline void put(cpx<F>* buf, F re, F im) const {
+    re += __shfl_xor(re, 16);
+    im += __shfl_xor(im, 16);
+    re += __shfl_xor(re, 32);
+    im += __shfl_xor(im, 32);
+    if (c0 == 0) buf[kq * 64 + row] = cpx<F>{re, im};
+  }
+  __device__ inline cpx<F> sum(const cpx<F>* buf, int j) const {
+    const int o = xrow[j];
+    if (KQ == 2) return cpx<F>{buf[o].re + buf[64 + o].re, buf[o].im + buf[64 + o].im};
+    const cpx<F> s0 = buf[o], s1 = buf[64 + o], s2 = buf[128 + o], s3 = buf[192 + o];
+    return cpx<F>{(s0.re + s1.re) + (s2.re + s3.re), (s0.im + s1.im) + (s2.im + s3.im)};
+  }
+};
+
+// Operand sets of the one-vector walks: the loads of step t + NS - 1 are issued (behind a
+// scheduling barrier) before the products of step t; steps past the end skip the products.
+// One set at four row tiles (eight k-steps of two blocks per lane: two sets would spill).
+template <int RT>
+constexpr int walk1_sets() {
+  return RT >= 4 ? 1 : 3;
+}
+
+// Boundary walk for one right-hand side: x_0 = W[blk(0)]; for t = 1..nsteps:
+// W[blk(t)] = W[blk(t)] + M_blk(t) x_{t-1}, x_t = that result.
+template <class F, int RT, class BlockOf>
+__device__ inline void chain_walk1(int N, int wcap, const cpx<F>* __restrict__ frags, cpx<F>* __restrict__ W,
+                                   int nsteps, BlockOf blk_of, cpx<F>* part) {
+  typedef Kq1<F, RT> Kw;
+  constexpr int KW = Kw::KW, NS = walk1_sets<RT>();
+  const Kw kw(N);
+  struct Set {
+    F ar[KW], ai[KW];
+    cpx<F> w[KW];
+  };
   auto load = [&](int t, Set& S) {
     const long long b = blk_of(t < nsteps ? t : nsteps);
-    ln.load(frags, b, S.ar, S.ai);
-    S.wv = W[(b * N + ln.rowc) * wcap];
-  };
-  Set S[PD];
+    kw.load(frags, b, S.ar, S.ai);
 #pragma unroll
-  for (int d = 0; d < PD; ++d) load(1 + d, S[d]);
-  __syncthreads();
-  int pb = 0;
-  auto body = [&](int t, Set& cur) {
-    F re = 0, im = 0;
-    ln.dot_lds(cur.ar, cur.ai, xbuf + pb * 64, sign, re, im);
-    Ln::rowsum4(re, im);
-    if (ln.writer && t <= nsteps) {
-      const cpx<F> y = {cur.wv.re + re, cur.wv.im + im};
-      xbuf[(pb ^ 1) * 64 + ln.row] = y;
-      W[((long long)blk_of(t) * N + ln.row) * wcap] = y;
+    for (int j = 0; j < KW; ++j) S.w[j] = W[(b * N + kw.xrowc[j]) * wcap];
+  };
+  cpx<F> x[KW];
+  {
+    const long long b0 = blk_of(0);
+#pragma unroll
+    for (int j = 0; j < KW; ++j) {
+      const cpx<F> v = W[(b0 * N + kw.xrowc[j]) * wcap];
+      x[j] = kw.xrow[j] < N ? v : cpx<F>{0, 0};
     }
-    load(t + PD, cur);
+  }
+  Set S[NS];
+#pragma unroll
+  for (int d = 0; d + 1 < NS; ++d) {
+    load(1 + d, S[d]);
+    __builtin_amdgcn_sched_barrier(0);  // the sets in issue order (the waits count in order)
+  }
+  int pb = 0;
+  auto body = [&](int t, Set& cur, Set& ahead) {
+    load(t + NS - 1, ahead);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t <= nsteps) {
+      F re = 0, im = 0;
+      Kw::dot(cur.ar, cur.ai, x, re, im);
+      kw.put(part + pb * Kw::PBUF, re, im);
+    }
     __syncthreads();
+    if (t <= nsteps) {
+      const long long b = blk_of(t);
+#pragma unroll
+      for (int j = 0; j < KW; ++j) {
+        const cpx<F> sm = kw.sum(part + pb * Kw::PBUF, j);
+        const cpx<F> y = {cur.w[j].re + sm.re, cur.w[j].im + sm.im};
+        x[j] = kw.xrow[j] < N ? y : cpx<F>{0, 0};
+        if (kw.writer && kw.xrow[j] < N) W[(b * N + kw.xrow[j]) * wcap] = y;
+      }
+    }
     pb ^= 1;
   };
-  for (int t = 1; t <= nsteps; t += PD) {
+  for (int t = 1; t <= nsteps; t += NS) {
 #pragma unroll
-    for (int d = 0; d < PD; ++d) body(t + d, S[d]);
+    for (int d = 0; d < NS; ++d) body(t + d, S[d], S[(d + NS - 1) % NS]);
   }
 }
 
-// Boundary passes for one right-hand side (see chain_walk1).
-constexpr int kWalk1Depth = 3;
+// Boundary passes for one right-hand side: one workgroup of RT KQ waves per chain.
 template <class F, int RT>
-__global__ void __launch_bounds__(kSolveThreads, 1) k_cs1_fwd_bound(DevGrid g, const ChainMeta* __restrict__ chains,
-                                                                   int seg, const cpx<F>* __restrict__ Phi,
-                                                                   cpx<F>* __restrict__ W) {
-  __shared__ cpx<F> xb[2 * 64];
+__global__ void __launch_bounds__(walk_threads(RT), 1) k_cs1_fwd_bound(DevGrid g, const ChainMeta* __restrict__ chains,
+                                                                      int seg, const cpx<F>* __restrict__ Phi,
+                                                                      cpx<F>* __restrict__ W) {
+  __shared__ cpx<F> part[2 * Kq1<F, RT>::PBUF];
   const ChainMeta ch = chains[blockIdx.x];
   if (ch.nseg <= 1) return;
   const int st = ch.start, n = ch.n;
-  chain_walk1<F, RT, kWalk1Depth>(g.N, g.wcap, Phi, W, ch.nseg - 1,
-                                  [&](int p) { return (long long)(st + min((p + 1) * seg, n) - 1); }, (F)1, xb);
+  chain_walk1<F, RT>(g.N, g.wcap, Phi, W, ch.nseg - 1,
+                     [&](int p) { return (long long)(st + min((p + 1) * seg, n) - 1); }, part);
 }
 
 template <class F, int RT>
-__global__ void __launch_bounds__(kSolveThreads, 1) k_cs1_bwd_bound(DevGrid g, const ChainMeta* __restrict__ chains,
-                                                                   int seg, const cpx<F>* __restrict__ Psi,
-                                                                   cpx<F>* __restrict__ W) {
-  __shared__ cpx<F> xb[2 * 64];
+__global__ void __launch_bounds__(walk_threads(RT), 1) k_cs1_bwd_bound(DevGrid g, const ChainMeta* __restrict__ chains,
+                                                                      int seg, const cpx<F>* __restrict__ Psi,
+                                                                      cpx<F>* __restrict__ W) {
+  __shared__ cpx<F> part[2 * Kq1<F, RT>::PBUF];
   const ChainMeta ch = chains[blockIdx.x];
   if (ch.nseg <= 1) return;
   const int st = ch.start, last = ch.nseg - 1;
-  chain_walk1<F, RT, kWalk1Depth>(g.N, g.wcap, Psi, W, ch.nseg - 1,
-                                  [&](int t) { return (long long)(st + (last - t) * seg); }, (F)1, xb);
+  chain_walk1<F, RT>(g.N, g.wcap, Psi, W, ch.nseg - 1, [&](int t) { return (long long)(st + (last - t) * seg); },
+                     part);
 }
 
-// Local walks for one right-hand side (as k_cs_fwd_rhs and k_cs_bwd_fix, on the vector units;
-// see Lane1).  The operands of kLocal1Depth steps are in flight; the step before the first one
-// multiplies a zero buffer instead of branching around its product.
-constexpr int kLocal1Depth = 2;
+// Local walks for one right-hand side (as k_cs_fwd_rhs and k_cs_bwd_fix): one workgroup of
+// RT KQ waves per segment.  The results stay in LDS until the walk ends (no store inside the
+// loop, whose conditional form would make the compiler wait on the prefetched operands) and are
+// then written out together.
+constexpr int kSegMax = 16;  // longest scan segment the one-vector local walks hold in LDS
 template <class F, int RT>
-__global__ void __launch_bounds__(kSolveThreads, 1) k_cs1_fwd_rhs(DevGrid g, const SegMeta* __restrict__ segs,
-                                                                 const int* __restrict__ blk_field,
-                                                                 const int* __restrict__ blk_lm,
-                                                                 const cpx<F>* __restrict__ Dm,
-                                                                 const cpx<F>* __restrict__ Gm,
-                                                                 const double* __restrict__ bvec,
-                                                                 cpx<F>* __restrict__ W) {
-  typedef Lane1<F, RT> Ln;
-  constexpr int KS = Ln::KS, PD = kLocal1Depth;
-  __shared__ cpx<F> xb[2 * 64];
+__global__ void __launch_bounds__(walk_threads(RT), 1) k_cs1_fwd_rhs(DevGrid g, const SegMeta* __restrict__ segs,
+                                                                    const int* __restrict__ blk_field,
+                                                                    const int* __restrict__ blk_lm,
+                                                                    const cpx<F>* __restrict__ Dm,
+                                                                    const cpx<F>* __restrict__ Gm,
+                                                                    const double* __restrict__ bvec,
+                                                                    cpx<F>* __restrict__ W) {
+  typedef Kq1<F, RT> Kw;
+  constexpr int KW = Kw::KW, NS = walk1_sets<RT>();
+  __shared__ cpx<F> part[2 * Kw::PBUF];
+  __shared__ cpx<F> ys[kSegMax * 64];  // the segment's results, stored after the walk
   const SegMeta sg = segs[blockIdx.x];
   const int N = g.N, a = sg.first_block, len = sg.len, wcap = g.wcap;
-  const Ln ln(N);
-  for (int i = threadIdx.x; i < 2 * 64; i += blockDim.x) xb[i] = cpx<F>{0, 0};
+  const Kw kw(N);
   struct Set {
-    F dr[KS], di[KS], gr[KS], gi[KS];
-    cpx<F> b[KS];
+    F dr[KW], di[KW], gr[KW], gi[KW];
+    double2 b[KW];
   };
   auto load = [&](int t, Set& S) {
     const long long blk = a + (t < len ? t : len - 1);
-    ln.load(Dm, blk, S.dr, S.di);
-    ln.load(Gm, blk, S.gr, S.gi);
+    kw.load(Dm, blk, S.dr, S.di);
+    kw.load(Gm, blk, S.gr, S.gi);
     const double* bp = bvec + 2LL * ((long long)N * ((long long)blk_field[blk] * g.S + blk_lm[blk]));
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int r = 4 * ks + ln.c0, rr = r < N ? r : N - 1;
-      const double br = bp[2 * rr], bi = bp[2 * rr + 1];
-      S.b[ks] = r < N ? cpx<F>{(F)br, (F)bi} : cpx<F>{0, 0};
-    }
+    for (int j = 0; j < KW; ++j) S.b[j] = *reinterpret_cast<const double2*>(bp + 2 * kw.xrowc[j]);
   };
-  Set S[PD];
+  cpx<F> x[KW];  // -zeta_{i-1} (zero before the first step)
 #pragma unroll
-  for (int d = 0; d < PD; ++d) load(d, S[d]);
-  __syncthreads();
+  for (int j = 0; j < KW; ++j) x[j] = cpx<F>{0, 0};
+  Set S[NS];
+#pragma unroll
+  for (int d = 0; d + 1 < NS; ++d) {
+    load(d, S[d]);
+    __builtin_amdgcn_sched_barrier(0);  // the sets in issue order (the waits count in order)
+  }
   int pb = 0;
-  auto body = [&](int t, Set& cur) {
-    F re = 0, im = 0;
-    ln.dot_reg(cur.dr, cur.di, cur.b, re, im);
-    ln.dot_lds(cur.gr, cur.gi, xb + pb * 64, (F)-1, re, im);
-    Ln::rowsum4(re, im);
-    if (ln.writer && t < len) {
-      const cpx<F> y = {re, im};
-      xb[(pb ^ 1) * 64 + ln.row] = y;
-      W[((long long)(a + t) * N + ln.row) * wcap] = y;
+  auto body = [&](int t, Set& cur, Set& ahead) {
+    load(t + NS - 1, ahead);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t < len) {
+      cpx<F> bv[KW];
+#pragma unroll
+      for (int j = 0; j < KW; ++j) bv[j] = kw.xrow[j] < N ? cpx<F>{(F)cur.b[j].x, (F)cur.b[j].y} : cpx<F>{0, 0};
+      F re = 0, im = 0;
+      Kw::dot(cur.dr, cur.di, bv, re, im);
+      Kw::dot(cur.gr, cur.gi, x, re, im);
+      kw.put(part + pb * Kw::PBUF, re, im);
     }
-    load(t + PD, cur);
     __syncthreads();
+    if (t < len) {
+#pragma unroll
+      for (int j = 0; j < KW; ++j) {
+        const cpx<F> y = kw.sum(part + pb * Kw::PBUF, j);
+        x[j] = kw.xrow[j] < N ? cpx<F>{-y.re, -y.im} : cpx<F>{0, 0};
+        if (kw.writer) ys[t * 64 + kw.xrow[j]] = y;
+      }
+    }
     pb ^= 1;
   };
-  for (int t = 0; t < len; t += PD) {
+  for (int t = 0; t < len; t += NS) {
 #pragma unroll
-    for (int d = 0; d < PD; ++d) body(t + d, S[d]);
+    for (int d = 0; d < NS; ++d) body(t + d, S[d], S[(d + NS - 1) % NS]);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < len * N; i += blockDim.x) {
+    const int t = i / N, r = i - t * N;
+    W[((long long)(a + t) * N + r) * wcap] = ys[t * 64 + r];
   }
 }
 
 template <class F, int RT>
-__global__ void __launch_bounds__(kSolveThreads, 1) k_cs1_bwd_fix(DevGrid g, const SegMeta* __restrict__ segs,
-                                                                 const cpx<F>* __restrict__ Phi,
-                                                                 const cpx<F>* __restrict__ H, cpx<F>* __restrict__ W) {
-  typedef Lane1<F, RT> Ln;
-  constexpr int KS = Ln::KS, PD = kLocal1Depth;
-  __shared__ cpx<F> xb[2 * 64];
+__global__ void __launch_bounds__(walk_threads(RT), 1) k_cs1_bwd_fix(DevGrid g, const SegMeta* __restrict__ segs,
+                                                                    const cpx<F>* __restrict__ Phi,
+                                                                    const cpx<F>* __restrict__ H, cpx<F>* __restrict__ W) {
+  typedef Kq1<F, RT> Kw;
+  constexpr int KW = Kw::KW, NS = walk1_sets<RT>();
+  __shared__ cpx<F> part[2 * Kw::PBUF];
+  __shared__ cpx<F> ys[kSegMax * 64];  // the segment's results, stored after the walk
   const SegMeta sg = segs[blockIdx.x];
   if (sg.len <= 1) return;
   const int N = g.N, a = sg.first_block, len = sg.len, e = a + len - 1, wcap = g.wcap;
   const bool fix = sg.pidx > 0;
-  const Ln ln(N);
-  for (int i = threadIdx.x; i < 64; i += blockDim.x) {
-    xb[i] = i < N ? W[((long long)e * N + i) * wcap] : cpx<F>{0, 0};
-    xb[64 + i] = cpx<F>{0, 0};
-  }
-  // z_{a-1} in the B-operand layout (zero in the first segment)
-  cpx<F> zs[KS];
-  {
-    const long long bz = fix ? a - 1 : a;
+  const Kw kw(N);
+  const long long ap = a > 0 ? a - 1 : 0;
+  cpx<F> x[KW], zs[KW];  // -xi_{i+1} and z_{a-1} (zero in a chain's first segment)
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int r = 4 * ks + ln.c0, rr = r < N ? r : N - 1;
-      const cpx<F> v = W[(bz * N + rr) * wcap];
-      zs[ks] = (fix && r < N) ? v : cpx<F>{0, 0};
-    }
+  for (int j = 0; j < KW; ++j) {
+    const cpx<F> v = W[((long long)e * N + kw.xrowc[j]) * wcap];
+    const cpx<F> z = W[(ap * N + kw.xrowc[j]) * wcap];
+    x[j] = kw.xrow[j] < N ? cpx<F>{-v.re, -v.im} : cpx<F>{0, 0};
+    zs[j] = (fix && kw.xrow[j] < N) ? z : cpx<F>{0, 0};
   }
   struct Set {
-    F hr[KS], hi[KS], pr[KS], pi[KS];
-    cpx<F> wv;
+    F hr[KW], hi[KW], pr[KW], pi[KW];
+    cpx<F> w[KW];
   };
   auto load = [&](int t, Set& S) {
     const long long blk = e - (t < len ? t : len - 1);
-    ln.load(H, blk, S.hr, S.hi);
-    ln.load(Phi, blk, S.pr, S.pi);
-    S.wv = W[(blk * N + ln.rowc) * wcap];
-  };
-  Set S[PD];
+    kw.load(H, blk, S.hr, S.hi);
+    kw.load(Phi, blk, S.pr, S.pi);
 #pragma unroll
-  for (int d = 0; d < PD; ++d) load(1 + d, S[d]);
-  __syncthreads();
+    for (int j = 0; j < KW; ++j) S.w[j] = W[(blk * N + kw.xrowc[j]) * wcap];
+  };
+  Set S[NS];
+#pragma unroll
+  for (int d = 0; d + 1 < NS; ++d) {
+    load(1 + d, S[d]);
+    __builtin_amdgcn_sched_barrier(0);  // the sets in issue order (the waits count in order)
+  }
   int pb = 0;
-  auto body = [&](int t, Set& cur) {
-    F re = 0, im = 0;
-    ln.dot_reg(cur.pr, cur.pi, zs, re, im);
-    ln.dot_lds(cur.hr, cur.hi, xb + pb * 64, (F)-1, re, im);
-    Ln::rowsum4(re, im);
-    if (ln.writer && t < len) {
-      const cpx<F> y = {cur.wv.re + re, cur.wv.im + im};
-      xb[(pb ^ 1) * 64 + ln.row] = y;
-      W[((long long)(e - t) * N + ln.row) * wcap] = y;
+  auto body = [&](int t, Set& cur, Set& ahead) {
+    load(t + NS - 1, ahead);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t < len) {
+      F re = 0, im = 0;
+      Kw::dot(cur.pr, cur.pi, zs, re, im);
+      Kw::dot(cur.hr, cur.hi, x, re, im);
+      kw.put(part + pb * Kw::PBUF, re, im);
     }
-    load(t + PD, cur);
     __syncthreads();
+    if (t < len) {
+#pragma unroll
+      for (int j = 0; j < KW; ++j) {
+        const cpx<F> sm = kw.sum(part + pb * Kw::PBUF, j);
+        const cpx<F> y = {cur.w[j].re + sm.re, cur.w[j].im + sm.im};
+        x[j] = kw.xrow[j] < N ? cpx<F>{-y.re, -y.im} : cpx<F>{0, 0};
+        if (kw.writer) ys[t * 64 + kw.xrow[j]] = y;
+      }
+    }
     pb ^= 1;
   };
-  for (int t = 1; t < len; t += PD) {
+  for (int t = 1; t < len; t += NS) {
 #pragma unroll
-    for (int d = 0; d < PD; ++d) body(t + d, S[d]);
+    for (int d = 0; d < NS; ++d) body(t + d, S[d], S[(d + NS - 1) % NS]);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < (len - 1) * N; i += blockDim.x) {
+    const int t = 1 + i / N, r = i - (t - 1) * N;
+    W[((long long)(e - t) * N + r) * wcap] = ys[t * 64 + r];
   }
 }
 
@@ -2420,7 +2507,10 @@ __global__ void __launch_bounds__(walk_threads(RT), 1) k_cs_bwd_fix(DevGrid g, i
   constexpr int NS = local_sets<RT>();
   Set S[NS];
 #pragma unroll
-  for (int d = 0; d + 1 < NS; ++d) load(1 + d, S[d]);
+  for (int d = 0; d + 1 < NS; ++d) {
+    load(1 + d, S[d]);
+    __builtin_amdgcn_sched_barrier(0);  // the sets in issue order (the waits count in order)
+  }
   int pb = 0;
   auto body = [&](int t, Set& cur, Set& ahead) {
     load(t + NS - 1, ahead);

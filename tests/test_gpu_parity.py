@@ -102,7 +102,7 @@ FOUR_TILES = (24, 24, 4, 52, 1e-3, 78.0, 200.0)
                          ids=["fp64", "mixed-fp64solve", "mixed-fp32solve-refined"])
 def test_jvp_four_row_tiles(lib, prec, solve, tol, btol):
     """17 vectors in one call (a full vector group and a one-column one) at N = 52; sampled
-    actions of both groups against the oracle."""
+    actions of both groups, and one of them applied alone, against the oracle."""
     plan, ora, lay = _setup(lib, FOUR_TILES, nvec=17, mixed_solve=solve)
     X = si.random_state(lay, 111, amp=(1e-2, 1e-2, 1e-2), p=2) + ora.conductive_state()
     J = si.default_phase_slot(lay, X)
@@ -114,7 +114,12 @@ def test_jvp_four_row_tiles(lib, prec, solve, tol, btol):
     plan.jvp(vd, yd, prec)
     Y = _host(yd)
     for i in (0, 9, 16):
-        check(lay, Y[i], ora.jvp(V[i]), tol, btol, f"N=52 prec={prec} solve={solve} vec {i}")
+        ref = ora.jvp(V[i])
+        check(lay, Y[i], ref, tol, btol, f"N=52 prec={prec} solve={solve} vec {i}")
+        if i == 9:    # one vector per call: the vector-unit walks at four row tiles
+            y1 = torch.empty_like(vd[i])
+            plan.jvp(vd[i].contiguous(), y1, prec)
+            check(lay, _host(y1), ref, tol, btol, f"N=52 prec={prec} solve={solve} single vec {i}")
 
 
 @pytest.mark.parametrize("cfg", SMALL)
