@@ -2001,7 +2001,10 @@ __device__ inline void chain_walk_kq(int N, int wcap, const cpx<F>* __restrict__
   }
   Set S[PD];
 #pragma unroll
-  for (int d = 0; d < PD; ++d) load(1 + d, S[d]);
+  for (int d = 0; d < PD; ++d) {
+    load(1 + d, S[d]);
+    __builtin_amdgcn_sched_barrier(0);  // the sets in issue order (the waits count in order)
+  }
   int pb = 0;
   auto body = [&](int t, Set& cur) {
     acc_t p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
