@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -63,11 +64,16 @@ TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profile
 
 
 def sources_sha256():
+    """Hash of the kernel sources' code: comments and runs of white space are dropped first, so
+    that an edited comment does not discard counters taken on the same code."""
     here = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
     for f in ("paper_2508_16635_amd/csrc/kernels.h", "paper_2508_16635_amd/csrc/api.hip"):
-        with open(os.path.join(here, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(here, f), encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)   # block comments
+        src = re.sub(r"//[^\n]*", " ", src)                  # line comments
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()
 
 
@@ -86,7 +92,8 @@ def measured_traffic(kernel):
 
 
 def stage_work(lay, nvec, prec_bytes, factor_bytes, nblocks, refine, dp_only=True):
-    """Algorithmic flops and bytes per launch of each stage (measurement)."""
+    """Algorithmic flops and bytes per launch of each stage: the work the method defines (each
+    operand read once, each result written once), not what a kernel happens to move."""
     L, N, Np, nth, nphi, K1, S = (lay["L"], lay["N"], lay["Np"], lay["ntheta"], lay["nphi"],
                                   lay["K"] + 1, lay["S"])
     m0 = lay["m0"]

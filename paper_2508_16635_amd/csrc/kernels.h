@@ -1756,13 +1756,14 @@ __global__ void k_apply_M(DevGrid g, PhysParams ph, const double* __restrict__ X
 //
 // Every step is y = w + sign M x for one complex N x N block M (or the sum of two such
 // products) and 16 right-hand sides, done as three real 16x16x4 MFMA products per k-step
-// (Gauss's form of the complex product).  The blocks are stored in the
-// MFMA operand order: with RT = ceil(N/16) row tiles and 4 RT k-steps, lane l of
-// (row tile t, k-step s) holds M[16t + l%16][4s + l/16] (zero outside N x N), so wave t of
-// the workgroup streams its operands with fully coalesced loads straight into registers,
-// one step ahead of their use.  x sits in LDS (64 rows x 16 columns, rows >= N zero).
-// Work vectors live in W[(block*N + j)*wcap + vec] (complex, precision F, scaled space);
-// wcap is a multiple of 16 and the columns beyond nvec carry zeros.
+// (Gauss's form of the complex product).  The blocks are stored in the MFMA operand order:
+// with RT = ceil(N/16) row tiles and 4 RT k-steps, lane l of (row tile t, k-step s) holds
+// M[16t + l%16][4s + l/16] (zero outside N x N), so a wave streams the operands of its k-steps
+// with fully coalesced loads straight into registers, ahead of their use (the walks split the
+// k-steps of a row tile over several waves; see KqWave).  The output kernel stages x in LDS
+// (64 rows x 16 columns, rows >= N zero).  Work vectors live in W[(block*N + j)*wcap + vec]
+// (complex, precision F, scaled space); wcap is a multiple of 16 and the columns beyond nvec
+// carry zeros.
 struct ChainMeta {
   int start, n, k, first_seg, nseg, pad0, pad1, pad2;
 };
