@@ -21,6 +21,10 @@ FLAGS = [
     "-Wno-unused-result",
     # packed FP32 instructions stay off: ordinary float code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in ordinary VGPRs: with the default heuristic the k-loops of the
+    # Legendre, radial and chain products kept them in AGPRs and copied them between the two
+    # register files around every product (waiting on each product's result)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(HERE, os.pardir, "include"),
 ]
 SOURCES = [os.path.join(CSRC, "api.hip"), os.path.join(CSRC, "plan.cpp")]
