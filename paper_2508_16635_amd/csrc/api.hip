@@ -63,6 +63,34 @@ void upload(DevBuf& b, const std::vector<T>& h) {
   if (!h.empty()) HIPCHK(hipMemcpy(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
 }
 
+// Rows of (problem, tile within the problem) for every workgroup of a grouped launch, one row per
+// vector count nv = 1..vcap (row nv starts at off[nv]), so that a workgroup finds its problem
+// with one load instead of walking the problem list.  Left empty (off all -1) beyond 4M entries.
+template <class Prob, class TilesOf>
+void build_tile_lut(const std::vector<Prob>& probs, int vcap, TilesOf tiles_of, DevBuf& buf,
+                    std::vector<long long>& off) {
+  off.assign(vcap + 1, -1);
+  long long total = 0;
+  for (int nv = 1; nv <= vcap; ++nv)
+    for (const Prob& q : probs) total += tiles_of(q, nv);
+  if (total > (4LL << 20)) return;
+  std::vector<int2> h;
+  h.reserve((size_t)total);
+  for (int nv = 1; nv <= vcap; ++nv) {
+    off[nv] = (long long)h.size();
+    for (int p = 0; p < (int)probs.size(); ++p) {
+      const int nt = tiles_of(probs[p], nv);
+      for (int t = 0; t < nt; ++t) {
+        int2 e;
+        e.x = p;
+        e.y = t;
+        h.push_back(e);
+      }
+    }
+  }
+  upload(buf, h);
+}
+
 // Workspace offsets (elements) of one precision.
 struct WsLayout {
   long long Gs, Gv, Cs, Cv, Fs, Fv, As, Av, total;
@@ -108,6 +136,11 @@ struct sc_plan {
   int ana_ct_fold = 0;                     // the folded kernel's column tiles where it can run (0: it cannot)
   std::vector<sc::AnaProb> h_anf;
   std::vector<sc::SynProb> h_syn;
+  // tile -> (problem, tile within it) of the synthesis and folded-analysis launches, one row per
+  // vector count 1..vcap starting at lut_*_off[nvec] (empty when the rows would be too large:
+  // the kernels then search the problem list themselves)
+  DevBuf lut_syn, lut_anf;
+  std::vector<long long> lut_syn_off, lut_anf_off;
   std::vector<sc::GemmProb> h_ana;
   std::vector<long long> h_gsoff;         // per m: operand-order offsets of Gs, Gv
   int rtcS = 0, rtcV = 0;
@@ -489,6 +522,10 @@ void build_workspaces(sc_plan* P) {
   P->nprob_syn = (int)P->h_syn.size();
   P->nprob_ana = (int)P->h_ana.size();
   P->nprob_anf = (int)P->h_anf.size();
+  build_tile_lut(P->h_syn, P->vcap, [](const sc::SynProb& q, int nv) { return sc::syn_tiles(q, nv); }, P->lut_syn,
+                 P->lut_syn_off);
+  build_tile_lut(P->h_anf, P->vcap, [](const sc::AnaProb& q, int nv) { return sc::ana_tiles(q, nv); }, P->lut_anf,
+                 P->lut_anf_off);
   {
     // the smallest instantiated column-tile count that covers every m (0: keep the GEMM path)
     int ct = 0;
@@ -633,8 +670,9 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
   for (const auto& pr : P->h_syn) nt += sc::syn_tiles(pr, nvec);
   {
     Prof _p(P, SC_STAGE_LEGENDRE_SYNTH, s);
+    const int2* lut = P->lut_syn_off[nvec] >= 0 ? P->lut_syn.as<int2>() + P->lut_syn_off[nvec] : nullptr;
     hipLaunchKernelGGL(sc::k_synth<T>, dim3((unsigned)nt), dim3(256), 0, s, P->probs_syn.as<sc::SynProb>(),
-                       P->nprob_syn, nvec, (const T*)ws, tab, ws);
+                       P->nprob_syn, lut, nvec, (const T*)ws, tab, ws);
   }
   HIPCHK(hipGetLastError());
   const int rtl_set = std::is_same<T, float>::value ? P->ring_rtl32 : P->ring_rtl64;
@@ -682,10 +720,11 @@ void transforms(sc_plan* P, int mode, int nvec, const double* v, long long ldv, 
     long long na = 0;
     for (const auto& a : P->h_anf) na += sc::ana_tiles(a, nvec);
     const size_t lds = sc::ana_lds_bytes<T>(g.nth, g.L + 1);
+    const int2* lut = P->lut_anf_off[nvec] >= 0 ? P->lut_anf.as<int2>() + P->lut_anf_off[nvec] : nullptr;
     Prof _p(P, SC_STAGE_LEGENDRE_ANAL, s);
 #define SC_ANAL(CT)                                                                                              \
   hipLaunchKernelGGL((sc::k_anal<T, CT>), dim3((unsigned)na), dim3(256), lds, s, P->probs_anf.as<sc::AnaProb>(), \
-                     P->nprob_anf, nvec, g.nth, (const T*)ws, tab, ws)
+                     P->nprob_anf, lut, nvec, g.nth, (const T*)ws, tab, ws)
     switch (P->ana_ct) {
       case 1: SC_ANAL(1); break;
       case 2: SC_ANAL(2); break;

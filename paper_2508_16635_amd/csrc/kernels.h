@@ -400,17 +400,24 @@ __host__ __device__ inline int syn_tiles(const SynProb& p, int nvec) {
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_synth(const SynProb* __restrict__ probs, int nprob, int nvec,
+__global__ void __launch_bounds__(256) k_synth(const SynProb* __restrict__ probs, int nprob,
+                                               const int2* __restrict__ lut, int nvec,
                                                const T* __restrict__ ws_in, const T* __restrict__ tab,
                                                T* __restrict__ ws_out) {
   typedef typename Mfma<T>::acc_t acc_t;
   int tile = blockIdx.x, p = 0;
-  for (; p < nprob; ++p) {
-    const int nt = syn_tiles(probs[p], nvec);
-    if (tile < nt) break;
-    tile -= nt;
+  if (lut) {   // (problem, tile) of this workgroup, one load
+    const int2 pt = lut[blockIdx.x];
+    p = pt.x;
+    tile = pt.y;
+  } else {
+    for (; p < nprob; ++p) {
+      const int nt = syn_tiles(probs[p], nvec);
+      if (tile < nt) break;
+      tile -= nt;
+    }
+    if (p >= nprob) return;
   }
-  if (p >= nprob) return;
   const SynProb pr = probs[p];
   const int ct = pr.parts * pr.cth, ks = pr.kse + pr.kso;
   const int ncg = (ct + 4 * kSynTN - 1) / (4 * kSynTN);
@@ -616,19 +623,26 @@ __host__ __device__ inline size_t ana_lds_bytes(int nth, int nlmax) {
 }
 
 template <class T, int CT>
-__global__ void __launch_bounds__(256) k_anal(const AnaProb* __restrict__ probs, int nprob, int nvec, int nth,
+__global__ void __launch_bounds__(256) k_anal(const AnaProb* __restrict__ probs, int nprob,
+                                              const int2* __restrict__ lut, int nvec, int nth,
                                               const T* __restrict__ ws_in, const T* __restrict__ tab,
                                               T* __restrict__ ws_out) {
   typedef typename Mfma<T>::acc_t acc_t;
   extern __shared__ unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   int tile = blockIdx.x, p = 0;
-  for (; p < nprob; ++p) {
-    const int nt = ana_tiles(probs[p], nvec);
-    if (tile < nt) break;
-    tile -= nt;
+  if (lut) {   // (problem, tile) of this workgroup, one load
+    const int2 pt = lut[blockIdx.x];
+    p = pt.x;
+    tile = pt.y;
+  } else {
+    for (; p < nprob; ++p) {
+      const int nt = ana_tiles(probs[p], nvec);
+      if (tile < nt) break;
+      tile -= nt;
+    }
+    if (p >= nprob) return;
   }
-  if (p >= nprob) return;
   const AnaProb pr = probs[p];
   const int nh = nth / 2, KSa = (nh + 3) >> 2, pitch = 4 * KSa + 1;
   const int rows = pr.rper * nvec, r0 = tile * kAnaRows;
